@@ -1,0 +1,213 @@
+"""Seeded synthetic lattice models (inputs only).
+
+This module builds the inputs of a GW calculation -- the one-body Hamiltonian
+H0(R) and the pair interaction V(R) on a periodic mesh -- for the model
+families of the paper (graphene with on-site and Ohno-type interactions,
+validation section; the degenerate five-orbital extended Hund-Hubbard model,
+benchmark section) and for the seeded variants the benchmark uses.  It holds
+none of the method's arithmetic: no transforms, no Dyson solves, no bubble.
+Both the HIP path and the test oracle consume its arrays.
+
+Array conventions
+-----------------
+* ``H_R[a, b, R1, R2]`` is the matrix element of H0 between orbital a in cell
+  R = R1 a1 + R2 a2 and orbital b in cell 0 (eV), indices taken mod the mesh.
+* ``V_R[alpha, beta, R1, R2]`` is the interaction between pair alpha = (p; i, l)
+  in cell R and pair beta = (q; j, k) in cell 0, i.e. V_{ijkl}^{pq}(R) of the
+  paper's Hamiltonian with c+_i c_l at p and c+_j c_k at q.  Pairs are ordered
+  site-major, then i, then l.
+"""
+import math
+
+import numpy as np
+
+#: Coulomb constant e^2 / (4 pi eps0) in eV * Angstrom (Ohno potential scale).
+COULOMB_EV_ANGSTROM = 14.397
+#: Carbon-carbon distance in graphene (Angstrom); the paper gives no geometry.
+GRAPHENE_ACC = 1.42
+
+
+def pair_count(site_norb):
+    return int(sum(n * n for n in site_norb))
+
+
+def _kanamori_block(norb, U, J):
+    """On-site rotationally invariant Kanamori tensor in the pair basis.
+
+    U' = U - 2J; V_(ii),(ii) = U; V_(ii),(jj) = U'; V_(ij),(ji) = J (exchange,
+    spin flip); V_(ij),(ij) = J (pair hopping), i != j.
+    """
+    nb = norb * norb
+    v = np.zeros((nb, nb), dtype=np.complex128)
+    up = U - 2.0 * J
+    for i in range(norb):
+        for j in range(norb):
+            a_ii = i * norb + i
+            a_jj = j * norb + j
+            if i == j:
+                v[a_ii, a_ii] = U
+            else:
+                v[a_ii, a_jj] = up
+                v[i * norb + j, j * norb + i] = J
+                v[i * norb + j, i * norb + j] = J
+    return v
+
+
+def _hopping_bandwidth(hops, norb, n):
+    """max_k eps_max - min_k eps_min of H0(k) = sum_R t(R) e^{-ik.R} on an n x n mesh."""
+    ks = 2.0 * np.pi * np.arange(n) / n
+    lo, hi = np.inf, -np.inf
+    for k1 in ks:
+        for k2 in ks:
+            h = np.zeros((norb, norb), dtype=np.complex128)
+            for (r1, r2), t in hops.items():
+                h += t * np.exp(-1j * (k1 * r1 + k2 * r2))
+            ev = np.linalg.eigvalsh(0.5 * (h + h.conj().T))
+            lo = min(lo, ev[0])
+            hi = max(hi, ev[-1])
+    return hi - lo
+
+
+def five_orbital(n=24, seed=22223, bandwidth=4.0, U=4.0, J=0.7, Vnn=1.0,
+                 beta=50.0, omega_max=25.0, eps=1e-10, n_target=6.0,
+                 norb=5, scale_mesh=24):
+    """Extended Hund-Hubbard model on a square lattice, one site, ``norb`` orbitals.
+
+    Hopping: i.i.d. complex Gaussian norb x norb matrices on the bonds
+    x, y, x+y, x-y (seeded), t(-R) = t(R)^dagger, no on-site term, scaled so
+    that the band width over a ``scale_mesh`` x ``scale_mesh`` mesh equals
+    ``bandwidth``.  Interaction: on-site Kanamori (U, J) plus a
+    nearest-neighbour density-density V_(ii),(jj)(+-x, +-y) = Vnn.
+    """
+    rng = np.random.default_rng(seed)
+    hops = {}
+    for r in [(1, 0), (0, 1), (1, 1), (1, -1)]:
+        t = (rng.standard_normal((norb, norb)) + 1j * rng.standard_normal((norb, norb))) / math.sqrt(2.0)
+        hops[r] = t
+        hops[(-r[0], -r[1])] = t.conj().T
+    scale = bandwidth / _hopping_bandwidth(hops, norb, scale_mesh)
+    H_R = np.zeros((norb, norb, n, n), dtype=np.complex128)
+    for (r1, r2), t in hops.items():
+        H_R[:, :, r1 % n, r2 % n] += scale * t
+    nb = norb * norb
+    V_R = np.zeros((nb, nb, n, n), dtype=np.complex128)
+    V_R[:, :, 0, 0] = _kanamori_block(norb, U, J)
+    for (r1, r2) in [(1, 0), (-1, 0), (0, 1), (0, -1)]:
+        for i in range(norb):
+            for j in range(norb):
+                V_R[i * norb + i, j * norb + j, r1 % n, r2 % n] += Vnn
+    return {"name": "five_orbital_%dx%d" % (n, n), "mesh": (n, n), "site_norb": [norb],
+            "H_R": H_R, "V_R": V_R, "beta": float(beta), "omega_max": float(omega_max),
+            "eps": float(eps), "n_target": float(n_target), "seed": seed}
+
+
+def graphene(n=12, t=-2.7, U=3.0, ohno=False, beta=10.0, omega_max=100.0, eps=1e-8,
+             n_target=2.0, shells=5):
+    """Graphene honeycomb, sites A and B with one p_z orbital each.
+
+    Geometry: a = sqrt(3) a_cc, a1 = a (1, 0), a2 = a (1/2, sqrt(3)/2),
+    tau_A = 0, tau_B = (a1 + a2) / 3.  Nearest-neighbour hopping t on the
+    three A-B bonds.  Interaction: on-site U, and with ``ohno`` the Ohno
+    potential V(d) = U / sqrt(1 + (U d / 14.397 eV A)^2) between sites at
+    distance d up to the ``shells``-th neighbour shell.
+    """
+    acc = GRAPHENE_ACC
+    a = math.sqrt(3.0) * acc
+    a1 = np.array([a, 0.0])
+    a2 = np.array([0.5 * a, 0.5 * math.sqrt(3.0) * a])
+    tau = [np.zeros(2), (a1 + a2) / 3.0]
+    H_R = np.zeros((2, 2, n, n), dtype=np.complex128)
+    for (r1, r2) in [(0, 0), (-1, 0), (0, -1)]:
+        H_R[0, 1, r1 % n, r2 % n] += t
+        H_R[1, 0, (-r1) % n, (-r2) % n] += t
+    V_R = np.zeros((2, 2, n, n), dtype=np.complex128)
+    V_R[0, 0, 0, 0] = U
+    V_R[1, 1, 0, 0] = U
+    if ohno:
+        shell_d = acc * np.array([1.0, math.sqrt(3.0), 2.0, math.sqrt(7.0), 3.0])[:shells]
+        dmax = shell_d[-1] * (1.0 + 1e-9)
+        reach = int(math.ceil(dmax / a)) + 2
+        for p in range(2):
+            for q in range(2):
+                for r1 in range(-reach, reach + 1):
+                    for r2 in range(-reach, reach + 1):
+                        d = np.linalg.norm(r1 * a1 + r2 * a2 + tau[p] - tau[q])
+                        if 1e-9 < d <= dmax:
+                            V_R[p, q, r1 % n, r2 % n] += U / math.sqrt(1.0 + (U * d / COULOMB_EV_ANGSTROM) ** 2)
+    name = "graphene_%s_%dx%d" % ("ohno" if ohno else "onsite", n, n)
+    return {"name": name, "mesh": (n, n), "site_norb": [1, 1], "H_R": H_R, "V_R": V_R,
+            "beta": float(beta), "omega_max": float(omega_max), "eps": float(eps),
+            "n_target": float(n_target)}
+
+
+def local_model(mesh, site_norb, levels, V_local, beta, omega_max, eps, n_target=None):
+    """Flat-band (atomic-limit) model: no hopping, on-site levels and interaction."""
+    n1, n2 = mesh
+    n_o = int(sum(site_norb))
+    H_R = np.zeros((n_o, n_o, n1, n2), dtype=np.complex128)
+    H_R[:, :, 0, 0] = np.diag(np.asarray(levels, dtype=np.float64))
+    nb = pair_count(site_norb)
+    V_R = np.zeros((nb, nb, n1, n2), dtype=np.complex128)
+    V_R[:, :, 0, 0] = V_local
+    return {"name": "local", "mesh": (n1, n2), "site_norb": list(site_norb), "H_R": H_R,
+            "V_R": V_R, "beta": float(beta), "omega_max": float(omega_max), "eps": float(eps),
+            "n_target": n_target}
+
+
+def kanamori(norb, U, J):
+    """The on-site Kanamori pair tensor for one site with ``norb`` orbitals."""
+    return _kanamori_block(norb, U, J)
+
+
+def random_model(mesh, site_norb, seed, bandwidth=3.0, U=2.0, J=0.3, Vnn=0.4,
+                 beta=10.0, omega_max=20.0, eps=1e-8, n_target=None):
+    """Small seeded model with every site coupled, for parity tests.
+
+    Random complex hoppings between all orbitals on the bonds x, y, x+y
+    (and their Hermitian partners), random on-site levels, Kanamori on every
+    site, and density-density V between every site pair on the x, y bonds.
+    """
+    rng = np.random.default_rng(seed)
+    n1, n2 = mesh
+    n_o = int(sum(site_norb))
+    hops = {}
+    onsite = rng.standard_normal((n_o, n_o)) + 1j * rng.standard_normal((n_o, n_o))
+    hops[(0, 0)] = 0.25 * (onsite + onsite.conj().T)
+    for r in [(1, 0), (0, 1), (1, 1)]:
+        t = (rng.standard_normal((n_o, n_o)) + 1j * rng.standard_normal((n_o, n_o))) / math.sqrt(2.0)
+        hops[r] = t
+        hops[(-r[0], -r[1])] = t.conj().T
+    scale = bandwidth / max(_hopping_bandwidth(hops, n_o, 8), 1e-12)
+    H_R = np.zeros((n_o, n_o, n1, n2), dtype=np.complex128)
+    for (r1, r2), t in hops.items():
+        H_R[:, :, r1 % n1, r2 % n2] += scale * t
+    nb = pair_count(site_norb)
+    V_R = np.zeros((nb, nb, n1, n2), dtype=np.complex128)
+    offs = np.cumsum([0] + [n * n for n in site_norb])
+    for p, n in enumerate(site_norb):
+        V_R[offs[p]:offs[p + 1], offs[p]:offs[p + 1], 0, 0] = _kanamori_block(n, U, J)
+    for p, npp in enumerate(site_norb):
+        for q, nq in enumerate(site_norb):
+            for (r1, r2) in [(1, 0), (-1, 0), (0, 1), (0, -1)]:
+                for i in range(npp):
+                    for j in range(nq):
+                        V_R[offs[p] + i * npp + i, offs[q] + j * nq + j, r1 % n1, r2 % n2] += Vnn
+    if n_target is None:
+        n_target = float(n_o)
+    return {"name": "random_%s_%dx%d_s%d" % ("-".join(map(str, site_norb)), n1, n2, seed),
+            "mesh": (n1, n2), "site_norb": list(site_norb), "H_R": H_R, "V_R": V_R,
+            "beta": float(beta), "omega_max": float(omega_max), "eps": float(eps),
+            "n_target": float(n_target)}
+
+
+# The benchmark workloads, by name.
+def workload(name):
+    if name == "graphene_g0w0_12":
+        return graphene(n=12, U=3.0, ohno=False, beta=10.0, omega_max=100.0, eps=1e-8)
+    if name == "graphene_ohno_36":
+        return graphene(n=36, U=3.0, ohno=True, beta=40.0, omega_max=100.0, eps=1e-10)
+    if name == "five_orbital_24":
+        return five_orbital(n=24, beta=50.0, omega_max=25.0, eps=1e-10)
+    if name == "five_orbital_48":
+        return five_orbital(n=48, beta=100.0, omega_max=25.0, eps=1e-10)
+    raise KeyError(name)

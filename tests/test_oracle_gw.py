@@ -1,0 +1,339 @@
+"""Pins of the oracle's GW iteration against closed forms, invariants and
+brute-force Matsubara sums (not GPU).
+
+Every expected value here is derived independently of the oracle's code:
+eigen-decompositions of H0(k) (numpy.linalg.eigh), Lindhard sums written out
+over k and bands, Matsubara sums, and atomic-limit formulas derived by hand
+(their derivations are in the docstrings).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gw, lattice
+from oracle.dlr import DLR
+from paper_2604_22223_amd import workloads as wl
+
+
+def fermi(x):
+    x = np.asarray(x, dtype=float)
+    return 0.5 * (1.0 - np.tanh(0.5 * x))
+
+
+def model_of(w, n_target="keep"):
+    nt = w["n_target"] if n_target == "keep" else n_target
+    return gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], nt)
+
+
+def eig_k(H_k):
+    """eigen-decomposition of H0(k) for every k: (xi[n1, n2, b], U[n1, n2, a, b])."""
+    h = np.moveaxis(H_k, (0, 1), (-2, -1))
+    return np.linalg.eigh(h)
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = wl.random_model((4, 4), [2, 1], seed=3, beta=10.0, omega_max=20.0, eps=1e-10)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    m = model_of(w)
+    st0 = gw.initial_state(m, d)
+    st1 = gw.gw_iteration(m, d, st0, keep=True)
+    return w, d, m, st0, st1
+
+
+# ----------------------------------------------------------------------------
+# P3: G0, density, chemical potential
+# ----------------------------------------------------------------------------
+
+def test_g0_closed_form(small):
+    """G0(k, tau) = -U diag(e^{-xi tau} (1 - f(xi))) U^dagger, xi = eps - mu;
+    n(k) = U f(xi) U^dagger; N_e = n_target; G(0+) + G(beta-) = -1."""
+    w, d, m, st0, st1 = small
+    mu = st0["mu"]
+    ev, U = eig_k(m.H_k)
+    xi = ev - mu
+    tau = d.tau_t * d.beta
+    f = fermi(d.beta * xi)
+    g_exact = -np.einsum("xyan,txyn,xybn->tabxy", U, np.exp(-xi[None] * tau[:, None, None, None]) * (1 - f)[None],
+                         U.conj())
+    g_tau = st1["intermediates"]["G_tau"]
+    assert np.abs(g_tau - g_exact).max() < 1e-6
+    n_exact = np.einsum("xyan,xyn,xybn->abxy", U, f, U.conj())
+    n_k = gw.density_k(st0["G_iw"], d)
+    assert np.abs(n_k - n_exact).max() < 1e-6
+    assert abs(gw.electron_count(n_k) - m.n_target) < 1e-10
+    coeff = d.coeffs_from_iw_f(st0["G_iw"])
+    eye = np.eye(m.n_o)[:, :, None, None]
+    assert np.abs(coeff.sum(axis=0) - eye).max() < 1e-5
+
+
+# ----------------------------------------------------------------------------
+# P4: Lindhard bubble
+# ----------------------------------------------------------------------------
+
+def test_bubble_lindhard(small):
+    """For G = G0 (derivation in the design notes):
+    P_{(il),(jk)}(q, i nu) = -(2/N_k) sum_k sum_{n,m} U_ln(k) U*_jn(k) U_km(k-q) U*_im(k-q)
+                              (f_n(k) - f_m(k-q)) / (i nu + xi_m(k-q) - xi_n(k)),
+    with the degenerate limit beta f (1 - f)."""
+    w, d, m, st0, st1 = small
+    mu = st0["mu"]
+    ev, U = eig_k(m.H_k)
+    xi = ev - mu
+    f = fermi(d.beta * xi)
+    n1, n2 = m.mesh
+    nu = 1j * 2 * np.pi * d.n_b / d.beta
+    P = np.zeros((d.r, m.n_b, m.n_b, n1, n2), dtype=complex)
+    for q1 in range(n1):
+        for q2 in range(n2):
+            acc = np.zeros((d.r, m.n_b, m.n_b), dtype=complex)
+            for k1 in range(n1):
+                for k2 in range(n2):
+                    kq = ((k1 - q1) % n1, (k2 - q2) % n2)
+                    Ua, Ub = U[k1, k2], U[kq]
+                    xa, xb = xi[k1, k2], xi[kq]
+                    fa, fb = f[k1, k2], f[kq]
+                    den = nu[:, None, None] + xb[None, None, :] - xa[None, :, None]     # [t, n, m]
+                    num = (fa[:, None] - fb[None, :])[None]
+                    with np.errstate(divide="ignore", invalid="ignore"):
+                        ratio = num / den
+                    degen = np.abs(den) < 1e-12
+                    lim = (d.beta * fa * (1 - fa))[None, :, None] * np.ones_like(den)
+                    ratio = np.where(degen, lim, ratio)
+                    for al, (i, l) in enumerate(m.pairs):
+                        for be, (j, k) in enumerate(m.pairs):
+                            amp = (Ua[l, :, None] * Ua[j, :, None].conj() * Ub[k, None, :] * Ub[i, None, :].conj())
+                            acc[:, al, be] += np.sum(amp[None] * ratio, axis=(1, 2))
+            P[..., q1, q2] = -2.0 / m.n_k * acc
+    p_oracle = st1["intermediates"]["P_nu_q"]
+    assert np.abs(p_oracle - P).max() / np.abs(P).max() < 2e-6
+
+
+# ----------------------------------------------------------------------------
+# P5: Dyson equation for W
+# ----------------------------------------------------------------------------
+
+def test_dyson_w_scalar_and_residual():
+    rng = np.random.default_rng(11)
+    # 1 x 1: W - V = U^2 P / (1 - U P)
+    U = 2.5
+    P = rng.standard_normal((3, 1, 1, 2, 2)) + 1j * rng.standard_normal((3, 1, 1, 2, 2))
+    V = np.full((1, 1, 2, 2), U, dtype=complex)
+    wc = gw.dyson_W(V, P)
+    assert np.abs(wc - U * U * P / (1 - U * P)).max() < 1e-13
+    # matrix: residual of W = V + V P W with W = W^C + V
+    nb = 5
+    P = 0.1 * (rng.standard_normal((2, nb, nb, 3, 3)) + 1j * rng.standard_normal((2, nb, nb, 3, 3)))
+    V = rng.standard_normal((nb, nb, 3, 3)) + 1j * rng.standard_normal((nb, nb, 3, 3))
+    W = gw.dyson_W(V, P) + V[None]
+    for t in range(2):
+        for x in range(3):
+            for y in range(3):
+                v, p, ww = V[..., x, y], P[t, ..., x, y], W[t, ..., x, y]
+                assert np.abs(ww - v - v @ p @ ww).max() < 1e-12 * np.abs(ww).max()
+
+
+# ----------------------------------------------------------------------------
+# P6 / P7: atomic limit
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("norb,U,J", [(1, 2.0, 0.0), (3, 2.0, 0.4), (2, 3.0, 0.5)])
+def test_atomic_limit_kanamori(norb, U, J):
+    """Flat band (no hopping), level xi relative to mu, Kanamori U, U' = U - 2J, J.
+
+    G(tau) = -(1 - f) e^{-xi tau} diagonal, so the bubble is constant in tau and
+    only connects a pair to its swap: P_{ab}(tau) = -2 f (1 - f) S_{ab}.  Hence
+    P(i nu) = p S delta_{nu,0} with p = -2 beta f (1 - f), and W^C(tau) =
+    W^C(i nu = 0) / beta is constant.  The density pairs (ii) decouple from the
+    (ij),(ji) pairs: on (ii) V has eigenvalues U + (N-1) U' (uniform, weight
+    1/N) and U - U' (weight (N-1)/N); each (ij),(ji) block is J [[1,1],[1,1]]
+    with S the swap, whose only non-zero mode has eigenvalue 2J.  Summing
+    the modes with a = 2 f (1 - f):
+        Sigma^C(i w) = A / (i w - xi),
+        A = sum_modes w_mode lam^2 a / (1 + beta a lam) + (N-1) 2 a J^2 / (1 + 2 beta a J).
+    Hartree-Fock per spin-orbital: n [U + (N-1)(2U' - J)], n = f."""
+    beta, level, mu = 8.0, 0.3, 0.0
+    w = wl.local_model((2, 2), [norb], [level] * norb, wl.kanamori(norb, U, J), beta, 20.0, 1e-12)
+    d = DLR(beta, 20.0, 1e-12)
+    m = model_of(w, n_target=None)
+    st = gw.gw_iteration(m, d, gw.g0_fixed_mu(m, d, mu))
+    xi = level - mu
+    f = float(fermi(beta * xi))
+    a = 2 * f * (1 - f)
+    Up = U - 2 * J
+    modes = [(U + (norb - 1) * Up, 1.0 / norb), (U - Up, (norb - 1) / norb)]
+    A = sum(wt * lam * lam * a / (1 + beta * a * lam) for lam, wt in modes)
+    A += (norb - 1) * 2 * a * J * J / (1 + 2 * beta * a * J)
+    sig_exact = A / (d.iw - xi)
+    for i in range(norb):
+        assert np.abs(st["sig_iw"][:, i, i, 1, 0] - sig_exact).max() < 1e-11
+    off = st["sig_iw"] - np.einsum("ab,t...->tab...", np.eye(norb), st["sig_iw"][:, 0, 0])
+    assert np.abs(off).max() < 1e-11
+    hf = f * (U + (norb - 1) * (2 * Up - J))
+    assert np.abs(st["sig_hf_k"] - hf * np.eye(norb)[:, :, None, None]).max() < 1e-9
+
+
+def test_graphene_half_filling_mu():
+    """Particle-hole symmetric graphene at half filling (on-site U, A-B
+    nearest-neighbour V1 and same-sublattice next-nearest V2): the correlation
+    self-energy shifts nothing, the same-sublattice density vanishes off-site,
+    the Fock term on a site is -U n = -U/2 and the Hartree term is
+    2 (V_AA(q=0) + V_AB(q=0)) / 2.  So mu = V_AA(q=0) + V_AB(q=0) - U/2."""
+    U, n = 3.0, 8
+    w = wl.graphene(n=n, U=U, ohno=False, beta=5.0, omega_max=100.0, eps=1e-10)
+    V = w["V_R"].copy()
+    for (r1, r2) in [(0, 0), (-1, 0), (0, -1)]:
+        V[0, 1, r1 % n, r2 % n] += 1.0
+        V[1, 0, (-r1) % n, (-r2) % n] += 1.0
+    for (r1, r2) in [(1, 0), (-1, 0), (0, 1), (0, -1), (1, -1), (-1, 1)]:
+        V[0, 0, r1 % n, r2 % n] += 0.5
+        V[1, 1, r1 % n, r2 % n] += 0.5
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], V, w["beta"], 2.0)
+    st = gw.gw_iteration(m, d, gw.initial_state(m, d))
+    vq0 = V.sum(axis=(-2, -1)).real
+    assert abs(st["mu"] - (vq0[0, 0] + vq0[0, 1] - U / 2)) < 1e-6
+
+
+# ----------------------------------------------------------------------------
+# P8: symmetries
+# ----------------------------------------------------------------------------
+
+def _herm_err(x):
+    return np.abs(x - np.conj(np.swapaxes(x, 1, 2))).max() / np.abs(x).max()
+
+
+def test_hermiticity_and_bubble_symmetry(small):
+    w, d, m, st0, st1 = small
+    inter = st1["intermediates"]
+    assert _herm_err(inter["G_tau"]) < 1e-8
+    assert _herm_err(inter["sig_tau_k"]) < 1e-6
+    hf = st1["sig_hf_k"]
+    assert np.abs(hf - np.conj(np.swapaxes(hf, 0, 1))).max() < 1e-8
+    # P_{alpha beta}(R, tau) = P_{beta alpha}(-R, beta - tau) from its definition:
+    # evaluate P at beta - tau_k through its DLR expansion
+    from oracle.dlr import kernel_tau
+    P = inter["P_tau_R"]
+    coef = d.coeffs_from_tau(P)
+    Pr = np.tensordot(kernel_tau(d.tau_t, d.omega, d.beta, reflect=True), coef, axes=(1, 0))
+    assert np.abs(P - lattice.reflect(np.swapaxes(Pr, 1, 2))).max() / np.abs(P).max() < 1e-7
+
+
+def _rotated_pair(U):
+    """T_{(a d),(i l)} = U_{a i} U*_{d l}: V~ = T V T^T when c~ = U c."""
+    n = U.shape[0]
+    return np.einsum("ai,dl->adil", U, U.conj()).reshape(n * n, n * n)
+
+
+def _covariance_case(sigma_fn=None):
+    """One GW iteration of a single-site 3-orbital model with complex hopping
+    and of the same model in a rotated orbital basis c~ = U c (U random
+    unitary).  Physics requires Sigma~ = U Sigma U^dagger, mu~ = mu."""
+    w = wl.random_model((3, 3), [3], seed=5, beta=6.0, omega_max=20.0, eps=1e-10)
+    rng = np.random.default_rng(9)
+    U, _ = np.linalg.qr(rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3)))
+    T = _rotated_pair(U)
+    H2 = np.einsum("ab,bcxy,cd->adxy", U, w["H_R"], U.conj().T)
+    V2 = np.einsum("AB,BCxy,CD->ADxy", T, w["V_R"], T.T)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    m1 = model_of(w)
+    m2 = gw.Model(w["mesh"], w["site_norb"], H2, V2, w["beta"], w["n_target"])
+    s1 = gw.gw_iteration(m1, d, gw.initial_state(m1, d))
+    s2 = gw.gw_iteration(m2, d, gw.initial_state(m2, d))
+    rot = np.einsum("ab,tbc...,cd->tad...", U, s1["sig_iw"], U.conj().T)
+    return abs(s1["mu"] - s2["mu"]), np.abs(s2["sig_iw"] - rot).max() / np.abs(rot).max(), s1, s2, U
+
+
+def test_orbital_basis_covariance():
+    dmu, dsig, s1, s2, U = _covariance_case()
+    assert dmu < 1e-9
+    assert dsig < 1e-8
+    hf_rot = U @ np.moveaxis(s1["sig_hf_k"], (0, 1), (-2, -1)) @ U.conj().T
+    assert np.abs(np.moveaxis(s2["sig_hf_k"], (0, 1), (-2, -1)) - hf_rot).max() < 1e-9
+
+
+def test_planted_transpose_breaks_covariance(monkeypatch):
+    """A transposed contraction in the self-energy (G_{jl} for G_{lj}), a
+    plausible index slip that Hermiticity does not see, must fail the
+    covariance pin."""
+    def wrong_sigma(G_tau_R, Wc_tau_R, pairs, n_o):
+        r = G_tau_R.shape[0]
+        sig = np.zeros((r, n_o, n_o) + G_tau_R.shape[-2:], dtype=complex)
+        for al, (i, l) in enumerate(pairs):
+            for be, (j, k) in enumerate(pairs):
+                sig[:, i, k] -= Wc_tau_R[:, al, be] * G_tau_R[:, j, l]
+        return sig
+
+    monkeypatch.setattr(gw, "sigma", wrong_sigma)
+    _, dsig, _, _, _ = _covariance_case()
+    assert dsig > 1e-3
+
+
+# ----------------------------------------------------------------------------
+# P9: brute-force Matsubara sums (exact G0W0 on a tiny mesh)
+# ----------------------------------------------------------------------------
+
+def test_g0w0_brute_force_matsubara():
+    """One band on a 3 x 3 mesh, on-site U, fixed mu:
+    P(q, i nu_m) = -(2/N) sum_k (f(xi_k) - f(xi_{k-q})) / (i nu_m + xi_{k-q} - xi_k),
+    W^C = U^2 P / (1 - U P),
+    Sigma^C(k, i w_n) = -(1/(beta N)) sum_{q, m} W^C(q, i nu_m) G0(k - q, i w_n - i nu_m),
+    summed over |m| <= M (the odd 1/nu^3 tail cancels between +-m)."""
+    n, beta, U, mu = 3, 4.0, 1.0, 0.2
+    H_R = np.zeros((1, 1, n, n), dtype=complex)
+    for (r1, r2) in [(1, 0), (-1, 0), (0, 1), (0, -1)]:
+        H_R[0, 0, r1 % n, r2 % n] += -0.5
+    V_R = np.zeros((1, 1, n, n), dtype=complex)
+    V_R[0, 0, 0, 0] = U
+    d = DLR(beta, 30.0, 1e-12)
+    m = gw.Model((n, n), [1], H_R, V_R, beta, None)
+    st = gw.gw_iteration(m, d, gw.g0_fixed_mu(m, d, mu))
+    ks = 2 * np.pi * np.arange(n) / n
+    xi = np.array([[-0.5 * (2 * np.cos(a) + 2 * np.cos(b)) - mu for b in ks] for a in ks])
+    f = fermi(beta * xi)
+    M = 200000
+    mm = np.arange(-M, M + 1)
+    nu = 1j * 2 * np.pi * mm / beta
+    Pq = np.zeros((n, n, len(mm)), dtype=complex)
+    for q1 in range(n):
+        for q2 in range(n):
+            for k1 in range(n):
+                for k2 in range(n):
+                    a, b = xi[k1, k2], xi[(k1 - q1) % n, (k2 - q2) % n]
+                    fa, fb = f[k1, k2], f[(k1 - q1) % n, (k2 - q2) % n]
+                    den = nu + b - a
+                    with np.errstate(divide="ignore", invalid="ignore"):
+                        term = np.where(np.abs(den) < 1e-14, beta * fa * (1 - fa), (fa - fb) / den)
+                    Pq[q1, q2] -= 2.0 / (n * n) * term
+    Wc = U * U * Pq / (1 - U * Pq)
+    worst = 0.0
+    for t, nf in enumerate(d.n_f):
+        if abs(nf) > 40:
+            continue
+        iw = 1j * (2 * nf + 1) * np.pi / beta
+        for k1 in range(n):
+            for k2 in range(n):
+                s = 0.0
+                for q1 in range(n):
+                    for q2 in range(n):
+                        g0 = 1.0 / (iw - nu - xi[(k1 - q1) % n, (k2 - q2) % n])
+                        s = s + np.sum(Wc[q1, q2] * g0)
+                s = -s / (beta * n * n)
+                worst = max(worst, abs(s - st["sig_iw"][t, 0, 0, k1, k2]))
+    assert worst < 1e-7
+
+
+def test_scf_converges_and_keeps_filling():
+    """The self-consistent loop reaches |Delta Sigma| <= 1e-8 on a small
+    multi-orbital model without mixing; every iterate keeps the filling."""
+    w = wl.five_orbital(n=6, norb=3, U=1.0, J=0.1, Vnn=0.2, beta=20.0, omega_max=20.0, eps=1e-10,
+                        n_target=3.6, scale_mesh=6)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    m = model_of(w)
+    seen = []
+    st, hist = gw.scf(m, d, tol=1e-8, max_iter=40,
+                      callback=lambda s: seen.append(gw.electron_count(gw.density_k(s["G_iw"], d))))
+    assert hist[-1][0] <= 1e-8
+    assert len(hist) < 40
+    assert max(abs(x - 3.6) for x in seen) < 1e-10

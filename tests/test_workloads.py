@@ -1,0 +1,44 @@
+"""Input generators: shapes and the symmetries of a physical Hamiltonian (not GPU)."""
+import numpy as np
+
+from paper_2604_22223_amd import workloads as wl
+from oracle import lattice
+
+
+def _reflect_swap(x):
+    return np.conj(lattice.reflect(np.swapaxes(x, 0, 1)))
+
+
+def test_five_orbital_model():
+    w = wl.five_orbital(n=24)
+    assert w["H_R"].shape == (5, 5, 24, 24) and w["V_R"].shape == (25, 25, 24, 24)
+    # Hermitian H0: H(-R) = H(R)^dagger
+    assert np.abs(w["H_R"] - _reflect_swap(w["H_R"])).max() < 1e-15
+    # band width over the 24 x 24 mesh is 4 eV
+    hk = np.moveaxis(np.fft.fft2(w["H_R"], axes=(-2, -1)), (0, 1), (-2, -1))
+    ev = np.linalg.eigvalsh(hk)
+    assert abs((ev.max() - ev.min()) - 4.0) < 1e-12
+    # interaction symmetric under exchange of the two pairs: V_ab(R) = V_ba(-R)
+    assert np.abs(w["V_R"] - lattice.reflect(np.swapaxes(w["V_R"], 0, 1))).max() == 0.0
+    v0 = w["V_R"][:, :, 0, 0].real
+    assert v0[0, 0] == 4.0 and v0[0, 6] == 4.0 - 2 * 0.7 and v0[1, 5] == 0.7 and v0[1, 1] == 0.7
+
+
+def test_graphene_model():
+    w = wl.graphene(n=12, ohno=True)
+    assert np.abs(w["H_R"] - _reflect_swap(w["H_R"])).max() < 1e-15
+    assert np.abs(w["V_R"] - lattice.reflect(np.swapaxes(w["V_R"], 0, 1))).max() < 1e-15
+    hk = np.moveaxis(np.fft.fft2(w["H_R"], axes=(-2, -1)), (0, 1), (-2, -1))
+    ev = np.linalg.eigvalsh(hk)
+    assert abs(ev.max() - 3 * 2.7) < 1e-12            # |3t| at Gamma
+    assert abs(w["V_R"][0, 0, 0, 0] - 3.0) < 1e-15
+    # three A-B bonds at a_cc, each U / sqrt(1 + (U a_cc / 14.397)^2)
+    v1 = 3.0 / np.sqrt(1 + (3.0 * 1.42 / 14.397) ** 2)
+    assert abs(w["V_R"][0, 1, 0, 0] - v1) < 1e-14
+
+
+def test_random_model_seeded():
+    a = wl.random_model((4, 4), [2, 1], seed=3)
+    b = wl.random_model((4, 4), [2, 1], seed=3)
+    assert np.array_equal(a["H_R"], b["H_R"]) and np.array_equal(a["V_R"], b["V_R"])
+    assert a["V_R"].shape == (5, 5, 4, 4)
