@@ -1,0 +1,242 @@
+/*
+ * libqgw -- one GW iteration on a tight-binding lattice, HIP kernels for gfx950.
+ *
+ * C ABI.  Every function returns a qgw_status; qgw_last_error() gives a
+ * thread-local message for the last failing call on that thread.  No C++
+ * exception crosses this boundary.
+ *
+ * Physics (arXiv:2604.22223, method section):
+ *   H0(k)         Eq. eq:fourier-transform-kr applied to H0(R) (cell-periodic gauge)
+ *   G(k, i w)     Eq. full-green-freq with G0^{-1} = (i w + mu) - H0(k)
+ *   P(q, i nu)    Eq. eq-polarizability (spin sum 2, fermionic antiperiodicity)
+ *   W(q, i nu)    Eq. eq-screened-coulomb, W^C = W - V
+ *   Sigma^C       Eq. eq-gw-self-energy
+ *   Sigma^H, ^F   Eqs. eq-hartree-self-energy, eq-fock-self-energy
+ *   density       n = -G(beta^-), mu adjusted to the target filling
+ *                 (G class paragraph of Fig. fig-self (b))
+ *   time/frequency axes in the discrete Lehmann representation (DLR; the
+ *   sentence after Eq. eq:bare-green-freq)
+ *
+ * Index conventions.  Orbitals a = 0 .. n_o-1 are numbered site by site.
+ * Pair ("product") indices alpha = (p; i, l), i and l orbitals of site p,
+ * numbered site-major then i then l; N_b = sum_p n_p^2.  A pair array
+ * X[alpha][beta] holds the paper's X_{ijkl} with alpha = (i, l) and
+ * beta = (j, k); with that labelling W = V + V P W is a matrix product.
+ *
+ * Data.  All device arrays are complex, interleaved (re, im), C-contiguous,
+ * 16-byte aligned for double precision and 8-byte aligned for single, and
+ * owned by the caller.  The mesh is square, n x n, N_k = n * n, with the
+ * flat index k = k1 * n + k2 (fastest); k.R = 2 pi (k1 R1 + k2 R2) / n.
+ * Layouts (r = DLR rank):
+ *   orbital array  [r][n_o][n_o][N_k]      ("G layout")
+ *   pair slab      [r][N_b][N_b][N_k]      (mesh fastest; transforms over R/q)
+ *   pair matrix    [r][N_k][N_b][N_b]      (one N_b x N_b matrix per (node, q))
+ *   static orbital [n_o][n_o][N_k], static pair [N_b][N_b][N_k]
+ *
+ * Streams.  ``stream`` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Compute calls only enqueue work, allocate nothing and return
+ * once the work is queued, except qgw_dyson_G, which also returns the
+ * chemical potential on the host and therefore waits for its stream.
+ */
+#ifndef QGW_H
+#define QGW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qgw_status;
+
+enum {
+  QGW_OK = 0,
+  QGW_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad enum            */
+  QGW_ERR_SHAPE = 2,         /* sizes inconsistent with the plan                 */
+  QGW_ERR_UNSUPPORTED = 3,   /* mesh side, N_b or rank outside the built set    */
+  QGW_ERR_DEVICE = 4,        /* HIP error, or no GPU                             */
+  QGW_ERR_NOT_CONVERGED = 5, /* chemical potential search did not converge      */
+  QGW_ERR_NONFINITE = 6,     /* NaN / Inf met (inputs or a singular solve)       */
+  QGW_ERR_ALLOC = 7          /* device or host allocation failed (plan set-up)  */
+};
+
+/* Arithmetic of the bulk arrays. */
+enum { QGW_F64 = 0, QGW_F32 = 1 };
+
+/* DLR maps (qgw_dlr_transform).  Each maps the r node values of a function
+ * to r node values of the same function elsewhere (construction of Kaye,
+ * Chen & Parcollet, PRB 105, 235115 (2022), cited by the paper for the DLR):
+ *   QGW_F_IW2TAU   fermionic Matsubara nodes -> tau_k
+ *   QGW_F_IW2TAUR  fermionic Matsubara nodes -> beta - tau_k
+ *   QGW_F_TAU2IW   tau_k -> fermionic Matsubara nodes
+ *   QGW_B_TAU2IW   tau_k -> bosonic Matsubara nodes
+ *   QGW_B_IW2TAU   bosonic Matsubara nodes -> tau_k
+ *   QGW_F_IW2BETA  fermionic Matsubara nodes -> beta^- (one output row)   */
+enum {
+  QGW_F_IW2TAU = 0,
+  QGW_F_IW2TAUR = 1,
+  QGW_F_TAU2IW = 2,
+  QGW_B_TAU2IW = 3,
+  QGW_B_IW2TAU = 4,
+  QGW_F_IW2BETA = 5
+};
+
+/* Pair-array layouts. */
+enum { QGW_LAYOUT_SLAB = 0, QGW_LAYOUT_MATRIX = 1 };
+
+/* Transform directions for qgw_lattice_fft (Eq. eq:fourier-transform-kr). */
+enum {
+  QGW_R_TO_K = -1,  /* X(k) = sum_R X(R) e^{-i k.R}                 */
+  QGW_K_TO_R = +1   /* X(R) = (1/N_k) sum_k X(k) e^{+i k.R}         */
+};
+
+typedef struct qgw_plan_s *qgw_plan;
+
+/* Plan description.  The DLR nodes are data: pass the node set produced by
+ * qgw_dlr_build (or any other node set of the same rank).  All host arrays
+ * are read during qgw_plan_create only. */
+typedef struct {
+  int32_t n;                 /* mesh side: N_k = n * n                             */
+  int32_t n_sites;           /* basis sites per cell                               */
+  const int32_t *site_norb;  /* [n_sites] orbitals per site                        */
+  double beta;               /* inverse temperature (1/eV)                         */
+  int32_t rank;              /* DLR rank r                                         */
+  const double *omega;       /* [r] DLR real frequencies (eV)                      */
+  const double *tau_t;       /* [r] DLR times as tau / beta in (0, 1)              */
+  const int64_t *n_f;        /* [r] fermionic nodes: w = (2 n + 1) pi / beta       */
+  const int64_t *n_b;        /* [r] bosonic nodes:   nu = 2 n pi / beta            */
+  int32_t precision;         /* QGW_F64 or QGW_F32                                 */
+  int32_t device;            /* HIP device ordinal                                 */
+} qgw_plan_desc;
+
+/* ------------------------------------------------------------------ set-up */
+
+/* DLR node selection on the host in FP64 (DLR paragraph of the method
+ * section; Kaye, Chen & Parcollet 2022): pivoted QR of the Lehmann kernel
+ * K(t, x) = exp(-t x) / (1 + exp(-x)) on composite Chebyshev grids, with
+ * dimensionless cutoff lambda = beta * omega_max and tolerance eps.
+ * Outputs (caller-owned, capacity max_rank each): x = beta * omega_l,
+ * tau_t, n_f, n_b, all sorted ascending; *rank receives r.  Returns
+ * QGW_ERR_SHAPE if r would exceed max_rank. */
+qgw_status qgw_dlr_build(double lambda, double eps, int32_t max_rank,
+                         double *x, double *tau_t, int64_t *n_f, int64_t *n_b,
+                         int32_t *rank);
+
+/* Creates a plan: validates the description, forms the r x r DLR maps in
+ * FP64 on the host by LU solves (never an explicit inverse), uploads them,
+ * builds FFT twiddles and allocates the plan's private device scratch.
+ * Supported: n in {1,2,3,4,5,6,8,9,10,12,15,16,18,20,24,25,27,30,32,36,40,
+ * 45,48}; N_b in {1,2,4,5,8,9,16,25}; 1 <= r <= 96. */
+qgw_status qgw_plan_create(const qgw_plan_desc *desc, qgw_plan *plan);
+qgw_status qgw_plan_destroy(qgw_plan plan);
+
+/* Copies the FP64 r x r map (row-major, interleaved complex, r*r*2 doubles;
+ * r*2 for QGW_F_IW2BETA) of ``map`` to host memory ``out``. */
+qgw_status qgw_plan_get_map(qgw_plan plan, int32_t map, double *out);
+
+/* Sizes of the plan: any output pointer may be NULL. */
+qgw_status qgw_plan_sizes(qgw_plan plan, int32_t *rank, int32_t *n_o,
+                          int32_t *n_b, int32_t *n_k);
+
+/* ------------------------------------------------------------ step calls */
+
+/* a1, a11, density row: out[m][c] = scale * sum_t T_map[m][t] in[t][c] for
+ * c < ncols (orbital arrays: ncols = n_o^2 N_k).  in and out must not
+ * overlap.  QGW_F_IW2BETA writes one row out[c].
+ * hermitian = 1 maps the Hermitian part (X + X^dagger) / 2 of the input,
+ * taken over the orbital indices at every (node, k); hermitian = 2 returns
+ * the Hermitian part of the output.  Both need ncols = n_o^2 N_k.  The exact
+ * Sigma^C(k, tau) and density matrix are Hermitian; the loop keeps only
+ * their Hermitian parts. */
+qgw_status qgw_dlr_transform(qgw_plan plan, int32_t map, int64_t ncols,
+                             double scale_re, double scale_im, int32_t hermitian,
+                             const void *in, void *out, void *stream);
+
+/* a5, a7: the same map on pair arrays [r] x (N_b^2 N_k) with a layout
+ * change: in_layout / out_layout are QGW_LAYOUT_SLAB or QGW_LAYOUT_MATRIX. */
+qgw_status qgw_dlr_transform_pairs(qgw_plan plan, int32_t map,
+                                   int32_t in_layout, int32_t out_layout,
+                                   const void *in, void *out, void *stream);
+
+/* a2, a4, a8, a10: ``batch`` 2-D transforms over the trailing N_k axis,
+ * direction QGW_R_TO_K or QGW_K_TO_R (with 1/N_k).  in == out allowed. */
+qgw_status qgw_lattice_fft(qgw_plan plan, int32_t dir, int64_t batch,
+                           const void *in, void *out, void *stream);
+
+/* a3 (+ a4): P_{(il),(jk)}(R, tau) = -2 G_{lj}(R, tau) G_{ki}(-R, beta - tau).
+ * G_tau_R = G(R, tau_k) and G_reflt_R = G(R, beta - tau_k), orbital layout.
+ * With out_q = 0 writes P(R, tau); with out_q = 1 writes P(q, tau) (the
+ * R -> q transform fused).  Output: pair slab. */
+qgw_status qgw_bubble(qgw_plan plan, const void *G_tau_R, const void *G_reflt_R,
+                      int32_t out_q, void *P, void *stream);
+
+/* a6: W^C = (I - V P)^{-1} V - V for every (q, bosonic node), Gauss-Jordan
+ * with partial pivoting.  V_q: [N_k][N_b][N_b]; P_nu, Wc_nu: pair matrix
+ * layout.  A zero pivot yields non-finite output (see qgw_check_finite). */
+qgw_status qgw_dyson_W(qgw_plan plan, const void *V_q, const void *P_nu,
+                       void *Wc_nu, void *stream);
+
+/* a9 (+ a8, a10): Sigma^C_{ik}(R, tau) = -sum W^C_{(il),(jk)}(R, tau) G_{lj}(R, tau).
+ * Wc: pair slab, in q (in_q = 1, the q -> R transform fused) or R (in_q = 0).
+ * G_tau_R: orbital layout.  Output Sigma in k (out_k = 1, R -> k fused) or R. */
+qgw_status qgw_sigma(qgw_plan plan, const void *G_tau_R, const void *Wc,
+                     int32_t in_q, int32_t out_k, void *Sig, void *stream);
+
+/* a12: Sigma_HF(R) = Sigma_F(R) + delta_{R,0} Sigma_H from the density n(R)
+ * (static orbital layout) and V(R) (static pair layout), both in R.  Output
+ * static orbital layout, in R. */
+qgw_status qgw_hartree_fock(qgw_plan plan, const void *V_R, const void *n_R,
+                            void *SigHF_R, void *stream);
+
+/* a13: G(k, i w_m) = [(i w_m + mu) - H(k) - Sigma(k, i w_m)]^{-1} with H =
+ * H0 + Sigma_HF (static orbital layout) and Sigma (orbital layout, or NULL
+ * for Sigma = 0).  If n_target is finite, mu is first solved so that
+ * N_e(mu) = 2/N_k sum_k Re Tr n(k) = n_target, n = -G(beta^-), by a
+ * bracketing search (bisection safeguarded, |d mu| <= 1e-13 eV); *mu is the
+ * output (its input value is ignored).  If n_target is NaN, *mu is used as
+ * given.  Waits for ``stream``.  QGW_ERR_NOT_CONVERGED if no bracket or no
+ * convergence within the step limit. */
+qgw_status qgw_dyson_G(qgw_plan plan, const void *H_k, const void *Sig_iw,
+                       double n_target, double *mu, void *G_iw, void *stream);
+
+/* ------------------------------------------------------- whole iteration */
+
+typedef struct qgw_state_s *qgw_state;
+
+/* A self-consistent GW state bound to a plan: holds H0(k), V(q) and every
+ * intermediate array on the device.  H0_R: [n_o][n_o][N_k] and V_R:
+ * [N_b][N_b][N_k] are device arrays in R (FP64).  mixing in (0, 1] is the
+ * linear mixing weight of the total self-energy (1 = none). */
+qgw_status qgw_state_create(qgw_plan plan, const void *H0_R, const void *V_R,
+                            double n_target, double mixing, qgw_state *state);
+qgw_status qgw_state_destroy(qgw_state state);
+
+/* Sets G = G0 at the chemical potential for the target filling (or at *mu
+ * if n_target is NaN). */
+qgw_status qgw_state_init_g0(qgw_state state, double *mu, void *stream);
+
+/* Runs up to n_iter GW iterations (Fig. fig-self (b): a1 .. a14), stopping
+ * early once max |Delta Sigma| <= tol.  Outputs (any may be NULL): the
+ * number of iterations done, the last max |Delta Sigma| and mu. */
+qgw_status qgw_gw_iteration(qgw_state state, int32_t n_iter, double tol,
+                            int32_t *iters_done, double *d_sigma, double *mu,
+                            void *stream);
+
+/* Copies a state array (FP64) into the caller's device buffer ``dst`` on
+ * ``stream``: which = 0 G(k, i w) [orbital], 1 Sigma^C(k, i w) [orbital],
+ * 2 Sigma_HF(k) [static orbital], 3 P(q, i nu) [pair matrix],
+ * 4 W^C(q, i nu) [pair matrix].  *bytes (if not NULL) receives the size. */
+qgw_status qgw_state_copy(qgw_state state, int32_t which, void *dst, int64_t *bytes,
+                          void *stream);
+
+/* Checks ``count`` complex values (precision of the plan) for NaN/Inf;
+ * waits for the stream.  QGW_ERR_NONFINITE if any is found. */
+qgw_status qgw_check_finite(qgw_plan plan, const void *x, int64_t count, void *stream);
+
+const char *qgw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QGW_H */

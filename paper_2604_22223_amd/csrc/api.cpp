@@ -1,0 +1,646 @@
+// C ABI of libqgw: argument validation, plans, the step calls and the
+// self-consistent GW state.  Every compute step runs in the HIP kernels of
+// this library; the host side only validates, sequences launches and builds
+// the FP64 DLR maps once per plan.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qgw.h"
+#include "qgw_internal.h"
+
+namespace qgw {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace qgw
+
+using namespace qgw;
+
+struct qgw_plan_s {
+  Plan p;
+};
+
+struct qgw_state_s {
+  qgw_plan plan = nullptr;
+  double n_target = 0.0, mixing = 1.0, mu = 0.0;
+  // static arrays
+  void *H_k = nullptr, *V_R = nullptr, *V_q = nullptr, *V_qm = nullptr, *V_q0 = nullptr;
+  // fermionic
+  void *G_iw = nullptr, *Sig_iw = nullptr, *Sig_iw_old = nullptr, *SigHF_k = nullptr, *SigHF_old = nullptr;
+  void *n_k = nullptr, *n_R = nullptr, *SigHF_R = nullptr, *Hs_k = nullptr;
+  void *G_tau = nullptr, *G_reflt = nullptr, *Sig_tau_k = nullptr;
+  // pair
+  void *Pq = nullptr, *P_nu = nullptr, *Wc_nu = nullptr;
+  double* d_dsig = nullptr;
+  double* d_blockmax = nullptr;
+  bool have_old = false;
+};
+
+#define QGW_CHECK_HIP(expr, what)                                             \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      set_error(std::string(what) + ": " + hipGetErrorString(e_));            \
+      return QGW_ERR_DEVICE;                                                  \
+    }                                                                         \
+  } while (0)
+
+#define QGW_REQUIRE(cond, code, msg) \
+  do {                               \
+    if (!(cond)) {                   \
+      set_error(msg);                \
+      return code;                   \
+    }                                \
+  } while (0)
+
+static bool mesh_supported(int n) {
+  switch (n) {
+#define QGW_CASE(NN) case NN:
+    QGW_FOR_EACH_MESH(QGW_CASE)
+#undef QGW_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+static bool nb_supported(int nb) {
+  switch (nb) {
+#define QGW_CASE(NN) case NN:
+    QGW_FOR_EACH_NB(QGW_CASE)
+#undef QGW_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+static size_t csize(const Plan& p) { return p.prec == 0 ? 16 : 8; }
+
+static void free_plan_device(Plan& p) {
+  for (int m = 0; m < kNumMaps; ++m) {
+    if (p.dmaps64.m[m]) (void)hipFree(p.dmaps64.m[m]);
+    if (p.dmaps32.m[m]) (void)hipFree(p.dmaps32.m[m]);
+    p.dmaps64.m[m] = p.dmaps32.m[m] = nullptr;
+  }
+  void* ptrs[] = {p.d_tw64, p.d_tw32, p.d_pairs, p.terms.d_terms, p.terms.d_off,
+                  p.d_wn, p.d_partials, p.d_status, p.d_scalars};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  p.d_tw64 = nullptr;
+  p.d_tw32 = nullptr;
+  p.d_pairs = nullptr;
+  p.terms.d_terms = p.terms.d_off = nullptr;
+  p.d_wn = nullptr;
+  p.d_partials = nullptr;
+  p.d_status = nullptr;
+  p.d_scalars = nullptr;
+}
+
+template <typename V>
+static hipError_t upload(void** dst, const V* src, size_t bytes) {
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+}
+
+extern "C" {
+
+const char* qgw_last_error(void) { return g_err.c_str(); }
+
+qgw_status qgw_dlr_build(double lambda, double eps, int32_t max_rank, double* x, double* tau_t,
+                         int64_t* n_f, int64_t* n_b, int32_t* rank) {
+  QGW_REQUIRE(x && tau_t && n_f && n_b && rank, QGW_ERR_INVALID_ARG, "qgw_dlr_build: null output");
+  QGW_REQUIRE(max_rank > 0, QGW_ERR_INVALID_ARG, "qgw_dlr_build: max_rank must be positive");
+  std::vector<double> xs, ts;
+  std::vector<int64_t> nf, nb;
+  std::string err;
+  int r;
+  try {
+    r = dlr_build_host(lambda, eps, max_rank, xs, ts, nf, nb, err);
+  } catch (const std::bad_alloc&) {
+    set_error("qgw_dlr_build: out of host memory");
+    return QGW_ERR_ALLOC;
+  }
+  if (r == -1) {
+    set_error(err);
+    return QGW_ERR_INVALID_ARG;
+  }
+  if (r < 0) {
+    set_error(err);
+    return QGW_ERR_SHAPE;
+  }
+  for (int i = 0; i < r; ++i) {
+    x[i] = xs[i];
+    tau_t[i] = ts[i];
+    n_f[i] = nf[i];
+    n_b[i] = nb[i];
+  }
+  *rank = r;
+  return QGW_OK;
+}
+
+qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
+  QGW_REQUIRE(d && out, QGW_ERR_INVALID_ARG, "qgw_plan_create: null argument");
+  *out = nullptr;
+  QGW_REQUIRE(d->n >= 1, QGW_ERR_INVALID_ARG, "qgw_plan_create: mesh side must be >= 1");
+  QGW_REQUIRE(mesh_supported(d->n), QGW_ERR_UNSUPPORTED,
+              "qgw_plan_create: mesh side " + std::to_string(d->n) + " has no compiled transform");
+  QGW_REQUIRE(d->n_sites >= 1 && d->site_norb, QGW_ERR_INVALID_ARG, "qgw_plan_create: need n_sites >= 1 and site_norb");
+  QGW_REQUIRE(d->beta > 0.0 && std::isfinite(d->beta), QGW_ERR_INVALID_ARG, "qgw_plan_create: beta must be positive");
+  QGW_REQUIRE(d->rank >= 1 && d->rank <= kMaxRank, QGW_ERR_UNSUPPORTED, "qgw_plan_create: DLR rank must be in [1, 96]");
+  QGW_REQUIRE(d->omega && d->tau_t && d->n_f && d->n_b, QGW_ERR_INVALID_ARG, "qgw_plan_create: null DLR node array");
+  QGW_REQUIRE(d->precision == QGW_F64 || d->precision == QGW_F32, QGW_ERR_INVALID_ARG, "qgw_plan_create: bad precision");
+  int no = 0, nb = 0;
+  for (int s = 0; s < d->n_sites; ++s) {
+    QGW_REQUIRE(d->site_norb[s] >= 1, QGW_ERR_INVALID_ARG, "qgw_plan_create: site with no orbitals");
+    no += d->site_norb[s];
+    nb += d->site_norb[s] * d->site_norb[s];
+  }
+  QGW_REQUIRE(no <= 8, QGW_ERR_UNSUPPORTED, "qgw_plan_create: at most 8 orbitals per cell");
+  QGW_REQUIRE(nb_supported(nb), QGW_ERR_UNSUPPORTED,
+              "qgw_plan_create: pair basis size " + std::to_string(nb) + " has no compiled Dyson-W solver");
+  for (int i = 0; i < d->rank; ++i) {
+    QGW_REQUIRE(d->tau_t[i] > 0.0 && d->tau_t[i] < 1.0, QGW_ERR_INVALID_ARG, "qgw_plan_create: tau_t must lie in (0, 1)");
+    QGW_REQUIRE(std::isfinite(d->omega[i]), QGW_ERR_INVALID_ARG, "qgw_plan_create: non-finite omega");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    set_error("qgw_plan_create: no HIP device");
+    return QGW_ERR_DEVICE;
+  }
+  QGW_REQUIRE(d->device >= 0 && d->device < ndev, QGW_ERR_INVALID_ARG, "qgw_plan_create: bad device ordinal");
+  QGW_CHECK_HIP(hipSetDevice(d->device), "hipSetDevice");
+
+  qgw_plan h = new (std::nothrow) qgw_plan_s;
+  QGW_REQUIRE(h, QGW_ERR_ALLOC, "qgw_plan_create: out of host memory");
+  Plan& p = h->p;
+  p.device = d->device;
+  p.n = d->n;
+  p.nk = d->n * d->n;
+  p.no = no;
+  p.nb = nb;
+  p.r = d->rank;
+  p.prec = d->precision;
+  p.beta = d->beta;
+  p.site_norb.assign(d->site_norb, d->site_norb + d->n_sites);
+  p.omega.assign(d->omega, d->omega + p.r);
+  p.tau_t.assign(d->tau_t, d->tau_t + p.r);
+  p.n_f.assign(d->n_f, d->n_f + p.r);
+  p.n_b.assign(d->n_b, d->n_b + p.r);
+  // orbital / pair bookkeeping
+  p.pair_of.assign(size_t(no) * no, -1);
+  int off = 0, al = 0;
+  for (int s = 0; s < d->n_sites; ++s) {
+    const int ns = d->site_norb[s];
+    for (int i = 0; i < ns; ++i) p.orb_site.push_back(s);
+    for (int i = 0; i < ns; ++i)
+      for (int l = 0; l < ns; ++l) {
+        p.pair_first.push_back(off + i);
+        p.pair_second.push_back(off + l);
+        p.pair_of[size_t(off + i) * no + off + l] = al++;
+      }
+    off += ns;
+  }
+  // term table: for output (i, k): alpha = (i, l), beta = (j, k)
+  std::vector<int> terms, toff(size_t(no) * no + 1, 0);
+  int max_terms = 0;
+  for (int i = 0; i < no; ++i)
+    for (int k = 0; k < no; ++k) {
+      int cnt = 0;
+      for (int a = 0; a < nb; ++a) {
+        if (p.pair_first[a] != i) continue;
+        for (int b = 0; b < nb; ++b) {
+          if (p.pair_second[b] != k) continue;
+          terms.push_back(a);
+          terms.push_back(b);
+          terms.push_back(p.pair_second[a]);
+          terms.push_back(p.pair_first[b]);
+          ++cnt;
+        }
+      }
+      toff[size_t(i) * no + k + 1] = toff[size_t(i) * no + k] + cnt;
+      if (cnt > max_terms) max_terms = cnt;
+    }
+  p.terms.max_terms = max_terms;
+  // DLR maps (FP64, host)
+  std::string err;
+  if (!dlr_maps_host(p.beta, p.omega, p.tau_t, p.n_f, p.n_b, p.maps, err)) {
+    delete h;
+    set_error("qgw_plan_create: " + err);
+    return QGW_ERR_INVALID_ARG;
+  }
+  // rows per chunk: minimise padded rows, then the number of chunks
+  {
+    const int cand[] = {8, 16, 20, 24, 28, 32};
+    int best_mt = 32, best_cost = 1 << 30;
+    for (int mt : cand) {
+      const int chunks = (p.r + mt - 1) / mt;
+      const int cost = chunks * mt * 4 + chunks;
+      if (cost < best_cost) {
+        best_cost = cost;
+        best_mt = mt;
+      }
+    }
+    p.dmaps64.mt = p.dmaps32.mt = best_mt;
+    p.dmaps64.rows_padded = p.dmaps32.rows_padded = ((p.r + best_mt - 1) / best_mt) * best_mt;
+  }
+  hipError_t e = hipSuccess;
+  {
+    const int rp = p.dmaps64.rows_padded;
+    for (int m = 0; m < kNumMaps && e == hipSuccess; ++m) {
+      const int rows = (m == 5) ? 1 : p.r;
+      std::vector<zd> h64(size_t(rp) * p.r, mk(0.0, 0.0));
+      std::vector<zf> h32(size_t(rp) * p.r, mk(0.0f, 0.0f));
+      for (int i = 0; i < rows; ++i)
+        for (int j = 0; j < p.r; ++j) {
+          const std::complex<double> v = p.maps[m][size_t(i) * p.r + j];
+          h64[size_t(i) * p.r + j] = mk(v.real(), v.imag());
+          h32[size_t(i) * p.r + j] = mk(float(v.real()), float(v.imag()));
+        }
+      e = upload(&p.dmaps64.m[m], h64.data(), h64.size() * sizeof(zd));
+      if (e == hipSuccess) e = upload(&p.dmaps32.m[m], h32.data(), h32.size() * sizeof(zf));
+    }
+  }
+  if (e == hipSuccess) {
+    std::vector<zd> t64(p.n);
+    std::vector<zf> t32(p.n);
+    for (int j = 0; j < p.n; ++j) {
+      const long double a = -2.0L * 3.141592653589793238462643383279502884L * j / p.n;
+      t64[j] = mk(double(cosl(a)), double(sinl(a)));
+      t32[j] = mk(float(cosl(a)), float(sinl(a)));
+    }
+    e = upload((void**)&p.d_tw64, t64.data(), t64.size() * sizeof(zd));
+    if (e == hipSuccess) e = upload((void**)&p.d_tw32, t32.data(), t32.size() * sizeof(zf));
+  }
+  if (e == hipSuccess) {
+    std::vector<int> pt(2 * nb + no * no);
+    for (int a = 0; a < nb; ++a) {
+      pt[a] = p.pair_first[a];
+      pt[nb + a] = p.pair_second[a];
+    }
+    for (int i = 0; i < no * no; ++i) pt[2 * nb + i] = p.pair_of[i];
+    e = upload((void**)&p.d_pairs, pt.data(), pt.size() * sizeof(int));
+  }
+  if (e == hipSuccess) e = upload((void**)&p.terms.d_terms, terms.data(), terms.size() * sizeof(int));
+  if (e == hipSuccess) e = upload((void**)&p.terms.d_off, toff.data(), toff.size() * sizeof(int));
+  if (e == hipSuccess) {
+    std::vector<double> wn(p.r);
+    for (int m = 0; m < p.r; ++m) wn[m] = (2.0 * double(p.n_f[m]) + 1.0) * 3.14159265358979323846 / p.beta;
+    e = upload((void**)&p.d_wn, wn.data(), wn.size() * sizeof(double));
+  }
+  if (e == hipSuccess) {
+    p.max_blocks = 8192;
+    e = hipMalloc((void**)&p.d_partials, size_t(2) * 4 * p.max_blocks * sizeof(double));
+  }
+  if (e == hipSuccess) e = hipMalloc((void**)&p.d_status, 16 * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&p.d_scalars, 16 * sizeof(double));
+  if (e != hipSuccess) {
+    set_error(std::string("qgw_plan_create: ") + hipGetErrorString(e));
+    free_plan_device(p);
+    delete h;
+    return QGW_ERR_ALLOC;
+  }
+  *out = h;
+  return QGW_OK;
+}
+
+qgw_status qgw_plan_destroy(qgw_plan h) {
+  if (!h) return QGW_OK;
+  (void)hipSetDevice(h->p.device);
+  free_plan_device(h->p);
+  delete h;
+  return QGW_OK;
+}
+
+qgw_status qgw_plan_get_map(qgw_plan h, int32_t map, double* out) {
+  QGW_REQUIRE(h && out, QGW_ERR_INVALID_ARG, "qgw_plan_get_map: null argument");
+  QGW_REQUIRE(map >= 0 && map < kNumMaps, QGW_ERR_INVALID_ARG, "qgw_plan_get_map: bad map");
+  const auto& v = h->p.maps[map];
+  for (size_t i = 0; i < v.size(); ++i) {
+    out[2 * i] = v[i].real();
+    out[2 * i + 1] = v[i].imag();
+  }
+  return QGW_OK;
+}
+
+qgw_status qgw_plan_sizes(qgw_plan h, int32_t* rank, int32_t* n_o, int32_t* n_b, int32_t* n_k) {
+  QGW_REQUIRE(h, QGW_ERR_INVALID_ARG, "qgw_plan_sizes: null plan");
+  if (rank) *rank = h->p.r;
+  if (n_o) *n_o = h->p.no;
+  if (n_b) *n_b = h->p.nb;
+  if (n_k) *n_k = h->p.nk;
+  return QGW_OK;
+}
+
+// ------------------------------------------------------------------ steps
+
+#define QGW_PLAN(h, name)                                                   \
+  QGW_REQUIRE(h, QGW_ERR_INVALID_ARG, std::string(name) + ": null plan"); \
+  const Plan& p = h->p;                                                     \
+  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice")
+
+qgw_status qgw_dlr_transform(qgw_plan h, int32_t map, int64_t ncols, double sre, double sim,
+                             int32_t hermitian, const void* in, void* out, void* stream) {
+  QGW_PLAN(h, "qgw_dlr_transform");
+  QGW_REQUIRE(map >= 0 && map < kNumMaps, QGW_ERR_INVALID_ARG, "qgw_dlr_transform: bad map");
+  QGW_REQUIRE(ncols >= 0, QGW_ERR_INVALID_ARG, "qgw_dlr_transform: negative ncols");
+  if (ncols == 0) return QGW_OK;
+  QGW_REQUIRE(in && out, QGW_ERR_INVALID_ARG, "qgw_dlr_transform: null array");
+  QGW_REQUIRE(in != out, QGW_ERR_INVALID_ARG, "qgw_dlr_transform: in and out must differ");
+  QGW_REQUIRE(hermitian >= 0 && hermitian <= 2, QGW_ERR_INVALID_ARG, "qgw_dlr_transform: bad hermitian mode");
+  QGW_REQUIRE(hermitian == 0 || ncols == int64_t(p.no) * p.no * p.nk, QGW_ERR_SHAPE,
+              "qgw_dlr_transform: the Hermitian modes need ncols = n_o^2 N_k");
+  QGW_CHECK_HIP(launch_dlr(p, map, ncols, sre, sim, in, out, (hipStream_t)stream, hermitian), "qgw_dlr_transform");
+  return QGW_OK;
+}
+
+qgw_status qgw_dlr_transform_pairs(qgw_plan h, int32_t map, int32_t in_layout, int32_t out_layout,
+                                   const void* in, void* out, void* stream) {
+  QGW_PLAN(h, "qgw_dlr_transform_pairs");
+  QGW_REQUIRE(map >= 0 && map < 5, QGW_ERR_INVALID_ARG, "qgw_dlr_transform_pairs: bad map");
+  QGW_REQUIRE((in_layout == 0 || in_layout == 1) && (out_layout == 0 || out_layout == 1), QGW_ERR_INVALID_ARG,
+              "qgw_dlr_transform_pairs: bad layout");
+  QGW_REQUIRE(in && out && in != out, QGW_ERR_INVALID_ARG, "qgw_dlr_transform_pairs: need distinct arrays");
+  QGW_CHECK_HIP(launch_dlr_pairs(p, map, in_layout, out_layout, in, out, (hipStream_t)stream),
+                "qgw_dlr_transform_pairs");
+  return QGW_OK;
+}
+
+qgw_status qgw_lattice_fft(qgw_plan h, int32_t dir, int64_t batch, const void* in, void* out, void* stream) {
+  QGW_PLAN(h, "qgw_lattice_fft");
+  QGW_REQUIRE(dir == QGW_R_TO_K || dir == QGW_K_TO_R, QGW_ERR_INVALID_ARG, "qgw_lattice_fft: bad direction");
+  QGW_REQUIRE(batch >= 0, QGW_ERR_INVALID_ARG, "qgw_lattice_fft: negative batch");
+  if (batch == 0) return QGW_OK;
+  QGW_REQUIRE(in && out, QGW_ERR_INVALID_ARG, "qgw_lattice_fft: null array");
+  QGW_CHECK_HIP(launch_lattice_fft(p, dir, batch, in, out, (hipStream_t)stream), "qgw_lattice_fft");
+  return QGW_OK;
+}
+
+qgw_status qgw_bubble(qgw_plan h, const void* gt, const void* gr, int32_t out_q, void* P, void* stream) {
+  QGW_PLAN(h, "qgw_bubble");
+  QGW_REQUIRE(gt && gr && P, QGW_ERR_INVALID_ARG, "qgw_bubble: null array");
+  QGW_REQUIRE(P != gt && P != gr, QGW_ERR_INVALID_ARG, "qgw_bubble: output aliases an input");
+  QGW_CHECK_HIP(launch_bubble(p, gt, gr, out_q ? 1 : 0, P, (hipStream_t)stream), "qgw_bubble");
+  return QGW_OK;
+}
+
+qgw_status qgw_dyson_W(qgw_plan h, const void* V_q, const void* P_nu, void* Wc_nu, void* stream) {
+  QGW_PLAN(h, "qgw_dyson_W");
+  QGW_REQUIRE(V_q && P_nu && Wc_nu, QGW_ERR_INVALID_ARG, "qgw_dyson_W: null array");
+  QGW_CHECK_HIP(launch_dyson_w(p, V_q, P_nu, Wc_nu, (hipStream_t)stream), "qgw_dyson_W");
+  return QGW_OK;
+}
+
+qgw_status qgw_sigma(qgw_plan h, const void* gt, const void* wc, int32_t in_q, int32_t out_k, void* sig,
+                     void* stream) {
+  QGW_PLAN(h, "qgw_sigma");
+  QGW_REQUIRE(gt && wc && sig, QGW_ERR_INVALID_ARG, "qgw_sigma: null array");
+  QGW_REQUIRE(sig != gt && sig != wc, QGW_ERR_INVALID_ARG, "qgw_sigma: output aliases an input");
+  QGW_CHECK_HIP(launch_sigma(p, gt, wc, in_q ? 1 : 0, out_k ? 1 : 0, sig, (hipStream_t)stream), "qgw_sigma");
+  return QGW_OK;
+}
+
+qgw_status qgw_hartree_fock(qgw_plan h, const void* V_R, const void* n_R, void* SigHF_R, void* stream) {
+  QGW_PLAN(h, "qgw_hartree_fock");
+  QGW_REQUIRE(V_R && n_R && SigHF_R, QGW_ERR_INVALID_ARG, "qgw_hartree_fock: null array");
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_hartree_fock: FP64 plans only");
+  // V(q = 0) in the plan's status scratch is too small: use the partials buffer
+  const size_t need = size_t(p.nb) * p.nb * sizeof(zd);
+  QGW_REQUIRE(need <= size_t(2) * 4 * p.max_blocks * sizeof(double), QGW_ERR_UNSUPPORTED, "qgw_hartree_fock: pair basis too large");
+  hipStream_t s = (hipStream_t)stream;
+  QGW_CHECK_HIP(launch_pair_sum_r(p, V_R, p.d_partials, s), "qgw_hartree_fock");
+  QGW_CHECK_HIP(launch_hartree_fock(p, V_R, p.d_partials, n_R, SigHF_R, s), "qgw_hartree_fock");
+  return QGW_OK;
+}
+
+static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw, double n_target,
+                              double* mu, void* G_iw, hipStream_t s, double* evals) {
+  const int mode = std::isnan(n_target) ? 0 : 1;
+  double sc[2] = {*mu, n_target};
+  QGW_CHECK_HIP(hipMemcpyAsync(p.d_scalars, sc, sizeof(sc), hipMemcpyHostToDevice, s), "qgw_dyson_G");
+  QGW_CHECK_HIP(launch_dyson_g(p, H_k, Sig_iw, mode, G_iw, s), "qgw_dyson_G launch");
+  double res[4];
+  int st = 0;
+  QGW_CHECK_HIP(hipMemcpyAsync(res, p.d_scalars, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
+  QGW_CHECK_HIP(hipMemcpyAsync(&st, p.d_status, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
+  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_dyson_G");
+  if (mode == 1) {
+    *mu = res[0];
+    if (evals) *evals = res[2];
+    if (st == 1) {
+      set_error("qgw_dyson_G: no bracket for the chemical potential");
+      return QGW_ERR_NOT_CONVERGED;
+    }
+    if (st == 2) {
+      set_error("qgw_dyson_G: chemical potential search did not converge");
+      return QGW_ERR_NOT_CONVERGED;
+    }
+    if (!std::isfinite(res[0])) {
+      set_error("qgw_dyson_G: non-finite chemical potential");
+      return QGW_ERR_NONFINITE;
+    }
+  }
+  return QGW_OK;
+}
+
+qgw_status qgw_dyson_G(qgw_plan h, const void* H_k, const void* Sig_iw, double n_target, double* mu,
+                       void* G_iw, void* stream) {
+  QGW_PLAN(h, "qgw_dyson_G");
+  QGW_REQUIRE(H_k && G_iw && mu, QGW_ERR_INVALID_ARG, "qgw_dyson_G: null argument");
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_dyson_G: the Dyson G solve is FP64");
+  if (!std::isnan(n_target))
+    QGW_REQUIRE(n_target > 0.0 && n_target < 2.0 * p.no, QGW_ERR_INVALID_ARG,
+                "qgw_dyson_G: target filling must lie in (0, 2 n_o)");
+  else
+    QGW_REQUIRE(std::isfinite(*mu), QGW_ERR_INVALID_ARG, "qgw_dyson_G: fixed mu must be finite");
+  return run_dyson_g(p, H_k, Sig_iw, n_target, mu, G_iw, (hipStream_t)stream, nullptr);
+}
+
+qgw_status qgw_check_finite(qgw_plan h, const void* x, int64_t count, void* stream) {
+  QGW_PLAN(h, "qgw_check_finite");
+  QGW_REQUIRE(x || count == 0, QGW_ERR_INVALID_ARG, "qgw_check_finite: null array");
+  QGW_REQUIRE(count >= 0, QGW_ERR_INVALID_ARG, "qgw_check_finite: negative count");
+  hipStream_t s = (hipStream_t)stream;
+  int zero = 0, cnt = 0;
+  QGW_CHECK_HIP(hipMemcpyAsync(p.d_status + 8, &zero, sizeof(int), hipMemcpyHostToDevice, s), "qgw_check_finite");
+  QGW_CHECK_HIP(launch_count_nonfinite(p, x, count, p.d_status + 8, s), "qgw_check_finite");
+  QGW_CHECK_HIP(hipMemcpyAsync(&cnt, p.d_status + 8, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_check_finite");
+  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_check_finite");
+  if (cnt) {
+    set_error("qgw_check_finite: " + std::to_string(cnt) + " non-finite values");
+    return QGW_ERR_NONFINITE;
+  }
+  return QGW_OK;
+}
+
+// ------------------------------------------------------------------ state
+
+static void free_state(qgw_state st) {
+  void* ptrs[] = {st->H_k, st->V_R, st->V_q, st->V_qm, st->V_q0, st->G_iw, st->Sig_iw, st->Sig_iw_old,
+                  st->SigHF_k, st->SigHF_old, st->n_k, st->n_R, st->SigHF_R, st->Hs_k, st->G_tau,
+                  st->G_reflt, st->Sig_tau_k, st->Pq, st->P_nu, st->Wc_nu, st->d_dsig, st->d_blockmax};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, double n_target, double mixing,
+                            qgw_state* out) {
+  QGW_PLAN(h, "qgw_state_create");
+  QGW_REQUIRE(out && H0_R && V_R, QGW_ERR_INVALID_ARG, "qgw_state_create: null argument");
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_state_create: FP64 plans only");
+  QGW_REQUIRE(mixing > 0.0 && mixing <= 1.0, QGW_ERR_INVALID_ARG, "qgw_state_create: mixing must be in (0, 1]");
+  if (!std::isnan(n_target))
+    QGW_REQUIRE(n_target > 0.0 && n_target < 2.0 * p.no, QGW_ERR_INVALID_ARG,
+                "qgw_state_create: target filling must lie in (0, 2 n_o)");
+  *out = nullptr;
+  qgw_state st = new (std::nothrow) qgw_state_s;
+  QGW_REQUIRE(st, QGW_ERR_ALLOC, "qgw_state_create: out of host memory");
+  st->plan = h;
+  st->n_target = n_target;
+  st->mixing = mixing;
+  const size_t so = size_t(p.no) * p.no * p.nk * 16;         // static orbital
+  const size_t sp = size_t(p.nb) * p.nb * p.nk * 16;         // static pair
+  const size_t fo = so * p.r;                                // fermionic orbital
+  const size_t fp = sp * p.r;                                // pair with nodes
+  hipError_t e = hipSuccess;
+  struct {
+    void** ptr;
+    size_t bytes;
+  } allocs[] = {{&st->H_k, so},       {&st->V_R, sp},     {&st->V_q, sp},        {&st->V_qm, sp},
+                {&st->V_q0, size_t(p.nb) * p.nb * 16},    {&st->G_iw, fo},       {&st->Sig_iw, fo},
+                {&st->Sig_iw_old, fo}, {&st->SigHF_k, so}, {&st->SigHF_old, so},  {&st->n_k, so},
+                {&st->n_R, so},       {&st->SigHF_R, so}, {&st->Hs_k, so},       {&st->G_tau, fo},
+                {&st->G_reflt, fo},   {&st->Sig_tau_k, fo}, {&st->Pq, fp},       {&st->P_nu, fp},
+                {&st->Wc_nu, fp},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096}};
+  for (auto& a : allocs) {
+    if (e != hipSuccess) break;
+    e = hipMalloc(a.ptr, a.bytes);
+  }
+  hipStream_t s = nullptr;
+  if (e == hipSuccess) e = hipMemcpyAsync(st->V_R, V_R, sp, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = launch_lattice_fft(p, QGW_R_TO_K, int64_t(p.no) * p.no, H0_R, st->H_k, s);
+  if (e == hipSuccess) e = launch_lattice_fft(p, QGW_R_TO_K, int64_t(p.nb) * p.nb, V_R, st->V_q, s);
+  if (e == hipSuccess) e = launch_slab_to_matrix_static(p, st->V_q, st->V_qm, s);
+  if (e == hipSuccess) e = launch_pair_sum_r(p, V_R, st->V_q0, s);
+  if (e == hipSuccess) e = hipMemsetAsync(st->Sig_iw, 0, fo, s);
+  if (e == hipSuccess) e = hipMemsetAsync(st->Sig_iw_old, 0, fo, s);
+  if (e == hipSuccess) e = hipMemsetAsync(st->SigHF_k, 0, so, s);
+  if (e == hipSuccess) e = hipMemsetAsync(st->SigHF_old, 0, so, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    set_error(std::string("qgw_state_create: ") + hipGetErrorString(e));
+    free_state(st);
+    delete st;
+    return QGW_ERR_DEVICE;
+  }
+  *out = st;
+  return QGW_OK;
+}
+
+qgw_status qgw_state_destroy(qgw_state st) {
+  if (!st) return QGW_OK;
+  (void)hipSetDevice(st->plan->p.device);
+  free_state(st);
+  delete st;
+  return QGW_OK;
+}
+
+qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
+  QGW_REQUIRE(st && mu, QGW_ERR_INVALID_ARG, "qgw_state_init_g0: null argument");
+  const Plan& p = st->plan->p;
+  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t so = size_t(p.no) * p.no * p.nk * 16;
+  const size_t fo = so * p.r;
+  QGW_CHECK_HIP(hipMemsetAsync(st->Sig_iw_old, 0, fo, s), "qgw_state_init_g0");
+  QGW_CHECK_HIP(hipMemsetAsync(st->SigHF_old, 0, so, s), "qgw_state_init_g0");
+  double m = *mu;
+  qgw_status rc = run_dyson_g(p, st->H_k, nullptr, st->n_target, &m, st->G_iw, s, nullptr);
+  if (rc != QGW_OK) return rc;
+  st->mu = m;
+  *mu = m;
+  return QGW_OK;
+}
+
+qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* iters_done, double* d_sigma,
+                            double* mu_out, void* stream) {
+  QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_gw_iteration: null state");
+  QGW_REQUIRE(n_iter >= 0, QGW_ERR_INVALID_ARG, "qgw_gw_iteration: negative n_iter");
+  const Plan& p = st->plan->p;
+  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t no2 = int64_t(p.no) * p.no, nb2 = int64_t(p.nb) * p.nb;
+  const int64_t ncol_g = no2 * p.nk;
+  double dsig = NAN;
+  int done = 0;
+  for (int it = 0; it < n_iter; ++it) {
+    // a12: density of the incoming G, Hartree-Fock
+    QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2BETA, ncol_g, -1.0, 0.0, st->G_iw, st->n_k, s, 2), "a12 density");
+    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2, st->n_k, st->n_R, s), "a12 fft");
+    QGW_CHECK_HIP(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, s), "a12 hf");
+    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, s), "a12 fft");
+    // a1, a2
+    QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G_iw, st->G_tau, s), "a1");
+    QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s), "a1");
+    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, s), "a2");
+    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_reflt, st->G_reflt, s), "a2");
+    // a3 + a4, a5, a6, a7
+    QGW_CHECK_HIP(launch_bubble(p, st->G_tau, st->G_reflt, 1, st->Pq, s), "a3");
+    QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq, st->P_nu, s), "a5");
+    QGW_CHECK_HIP(launch_dyson_w(p, st->V_qm, st->P_nu, st->Wc_nu, s), "a6");
+    QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc_nu, st->Pq, s), "a7");
+    // a8 + a9 + a10, a11
+    QGW_CHECK_HIP(launch_sigma(p, st->G_tau, st->Pq, 1, 1, st->Sig_tau_k, s), "a9");
+    QGW_CHECK_HIP(launch_dlr(p, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->Sig_tau_k, st->Sig_iw, s, 1), "a11");
+    // a14: change of the total self-energy, mixing
+    QGW_CHECK_HIP(launch_delta_and_mix(p, st->SigHF_k, st->Sig_iw, st->SigHF_old, st->Sig_iw_old, st->mixing,
+                                       st->d_dsig, st->d_blockmax, s),
+                  "a14");
+    (void)nb2;
+    // a13: Dyson G with the chemical potential
+    QGW_CHECK_HIP(launch_add(p, ncol_g, st->H_k, st->SigHF_k, st->Hs_k, s), "a13");
+    double m = st->mu;
+    qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, nullptr);
+    if (rc != QGW_OK) return rc;
+    st->mu = m;
+    QGW_CHECK_HIP(hipMemcpy(&dsig, st->d_dsig, sizeof(double), hipMemcpyDeviceToHost), "a14");
+    ++done;
+    if (dsig <= tol) break;
+  }
+  if (iters_done) *iters_done = done;
+  if (d_sigma) *d_sigma = dsig;
+  if (mu_out) *mu_out = st->mu;
+  return QGW_OK;
+}
+
+qgw_status qgw_state_copy(qgw_state st, int32_t which, void* dst, int64_t* bytes, void* stream) {
+  QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_copy: null state");
+  const Plan& p = st->plan->p;
+  const size_t so = size_t(p.no) * p.no * p.nk * 16;
+  const size_t fp = size_t(p.nb) * p.nb * p.nk * 16 * p.r;
+  const void* src = nullptr;
+  size_t n = 0;
+  switch (which) {
+    case 0: src = st->G_iw; n = so * p.r; break;
+    case 1: src = st->Sig_iw; n = so * p.r; break;
+    case 2: src = st->SigHF_k; n = so; break;
+    case 3: src = st->P_nu; n = fp; break;
+    case 4: src = st->Wc_nu; n = fp; break;
+    default:
+      set_error("qgw_state_copy: bad selector");
+      return QGW_ERR_INVALID_ARG;
+  }
+  if (bytes) *bytes = int64_t(n);
+  if (!dst) return QGW_OK;
+  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
+  QGW_CHECK_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, (hipStream_t)stream), "qgw_state_copy");
+  return QGW_OK;
+}
+
+}  // extern "C"

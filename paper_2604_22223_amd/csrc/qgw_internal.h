@@ -1,0 +1,104 @@
+// Internal declarations shared by the libqgw translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qgw_complex.h"
+
+namespace qgw {
+
+// Mesh sides with a compiled transform (radix 2, 3, 5; at most 48).
+#define QGW_FOR_EACH_MESH(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48)
+
+// Pair-basis sizes with a compiled Dyson-W solver.
+#define QGW_FOR_EACH_NB(X) X(1) X(2) X(4) X(5) X(8) X(9) X(16) X(25)
+
+// Orbital counts with a compiled Dyson-G solver.
+#define QGW_FOR_EACH_NO(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+
+constexpr int kMaxRank = 96;
+constexpr int kNumMaps = 6;
+
+struct DeviceMaps {
+  void* m[kNumMaps] = {nullptr};  // rows padded to a multiple of mt, zero-filled
+  int mt = 32;                    // output rows per thread block chunk
+  int rows_padded = 0;
+};
+
+// Term lists of the Fock / self-energy contraction: for output (i, k),
+// every (alpha, beta) with first(alpha) = i, second(beta) = k, stored as
+// (alpha, beta, l = second(alpha), j = first(beta)).
+struct TermTable {
+  int* d_terms = nullptr;  // int4 per term
+  int* d_off = nullptr;    // [n_o * n_o + 1] offsets into terms
+  int max_terms = 0;
+};
+
+struct Plan {
+  int device = 0;
+  int n = 0, nk = 0, no = 0, nb = 0, r = 0, prec = 0;
+  double beta = 0.0;
+  std::vector<int> site_norb, pair_first, pair_second, orb_site, pair_of;  // pair_of[a*no+b] or -1
+  std::vector<double> omega, tau_t;
+  std::vector<int64_t> n_f, n_b;
+  std::vector<std::complex<double>> maps[kNumMaps];  // host FP64, r x r (IW2BETA: 1 x r)
+  DeviceMaps dmaps64, dmaps32;
+  zd* d_tw64 = nullptr;
+  zf* d_tw32 = nullptr;
+  int* d_pairs = nullptr;  // [2 * nb]: first, second
+  TermTable terms;
+  double* d_wn = nullptr;  // fermionic Matsubara frequencies (r)
+  // Dyson-G scratch: partial sums (2 x max blocks x 4), status word
+  double* d_partials = nullptr;
+  int* d_status = nullptr;
+  double* d_scalars = nullptr;  // [8]: mu, n_target, d_sigma, ...
+  int max_blocks = 0;
+};
+
+void set_error(const std::string& msg);
+
+// ---- kernels (each returns hipSuccess or the launch error) ----------------
+hipError_t launch_lattice_fft(const Plan& p, int dir, int64_t batch, const void* in, void* out,
+                              hipStream_t s);
+hipError_t launch_bubble(const Plan& p, const void* g_tau_r, const void* g_reflt_r, int out_q,
+                         void* out, hipStream_t s);
+hipError_t launch_sigma(const Plan& p, const void* g_tau_r, const void* wc, int in_q, int out_k,
+                        void* sig, hipStream_t s);
+// herm: 0 plain, 1 Hermitian part of the input, 2 of the output (orbital arrays)
+hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double sim, const void* in,
+                      void* out, hipStream_t s, int herm = 0);
+hipError_t launch_dlr_pairs(const Plan& p, int map, int in_layout, int out_layout, const void* in,
+                            void* out, hipStream_t s);
+hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void* wc_nu,
+                          hipStream_t s);
+hipError_t launch_hartree_fock(const Plan& p, const void* v_r, const void* v_q0, const void* n_r,
+                               void* sig_hf_r, hipStream_t s);
+hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStream_t s);
+// Dyson G.  mode 0: fixed mu (scalars[0]); mode 1: solve mu for scalars[1].
+hipError_t launch_dyson_g(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
+                          hipStream_t s);
+hipError_t launch_slab_to_matrix_static(const Plan& p, const void* in, void* out, hipStream_t s);
+hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b, void* out,
+                      hipStream_t s);
+// d_sigma = max |(hf_new + c_new) - (hf_old + c_old)|; then optional mixing
+// new <- old + alpha (new - old), and old <- new.
+hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* hf_old,
+                                void* c_old, double alpha, double* d_out, double* block_scratch,
+                                hipStream_t s);
+hipError_t launch_count_nonfinite(const Plan& p, const void* x, int64_t count, int* d_count,
+                                  hipStream_t s);
+
+// ---- host DLR -------------------------------------------------------------
+int dlr_build_host(double lambda, double eps, int max_rank, std::vector<double>& x,
+                   std::vector<double>& tau_t, std::vector<int64_t>& n_f,
+                   std::vector<int64_t>& n_b, std::string& err);
+bool dlr_maps_host(double beta, const std::vector<double>& omega, const std::vector<double>& tau_t,
+                   const std::vector<int64_t>& n_f, const std::vector<int64_t>& n_b,
+                   std::vector<std::complex<double>> maps[kNumMaps], std::string& err);
+
+}  // namespace qgw

@@ -1,0 +1,265 @@
+"""Thin ctypes binding of libqgw (argument marshalling only).
+
+Every function mirrors a C entry point of ``include/qgw.h`` with the same
+name minus the ``qgw_`` prefix.  Device arrays are torch tensors
+(complex128 for FP64 plans, complex64 for FP32 plans) on the plan's device;
+the work is queued on torch's current stream.  Nothing here computes: if the
+shared library is missing, every call raises.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqgw.so")
+
+QGW_OK = 0
+STATUS_NAMES = {0: "QGW_OK", 1: "QGW_ERR_INVALID_ARG", 2: "QGW_ERR_SHAPE", 3: "QGW_ERR_UNSUPPORTED",
+                4: "QGW_ERR_DEVICE", 5: "QGW_ERR_NOT_CONVERGED", 6: "QGW_ERR_NONFINITE",
+                7: "QGW_ERR_ALLOC"}
+F64, F32 = 0, 1
+F_IW2TAU, F_IW2TAUR, F_TAU2IW, B_TAU2IW, B_IW2TAU, F_IW2BETA = range(6)
+LAYOUT_SLAB, LAYOUT_MATRIX = 0, 1
+R_TO_K, K_TO_R = -1, +1
+
+#: Every C entry point the header declares.
+EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get_map", "qgw_plan_sizes",
+           "qgw_dlr_transform", "qgw_dlr_transform_pairs", "qgw_lattice_fft", "qgw_bubble", "qgw_dyson_W",
+           "qgw_sigma", "qgw_hartree_fock", "qgw_dyson_G", "qgw_state_create", "qgw_state_destroy",
+           "qgw_state_init_g0", "qgw_gw_iteration", "qgw_state_copy", "qgw_check_finite",
+           "qgw_last_error"]
+
+
+class QGWError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_sites", ctypes.c_int32),
+                ("site_norb", ctypes.POINTER(ctypes.c_int32)), ("beta", ctypes.c_double),
+                ("rank", ctypes.c_int32), ("omega", ctypes.POINTER(ctypes.c_double)),
+                ("tau_t", ctypes.POINTER(ctypes.c_double)), ("n_f", ctypes.POINTER(ctypes.c_int64)),
+                ("n_b", ctypes.POINTER(ctypes.c_int64)), ("precision", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libqgw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libqgw.so is not built: run `python -m paper_2604_22223_amd.build`")
+        # torch first: the library's libamdhip64.so.7 dependency then binds to
+        # the HIP runtime torch already loaded, so device pointers and streams
+        # from torch are valid in the library
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        pd, pi32, pi64 = ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i64)
+        sig = {
+            "qgw_dlr_build": [dbl, dbl, i32, pd, pd, pi64, pi64, pi32],
+            "qgw_plan_create": [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)],
+            "qgw_plan_destroy": [vp],
+            "qgw_plan_get_map": [vp, i32, pd],
+            "qgw_plan_sizes": [vp, pi32, pi32, pi32, pi32],
+            "qgw_dlr_transform": [vp, i32, i64, dbl, dbl, i32, vp, vp, vp],
+            "qgw_dlr_transform_pairs": [vp, i32, i32, i32, vp, vp, vp],
+            "qgw_lattice_fft": [vp, i32, i64, vp, vp, vp],
+            "qgw_bubble": [vp, vp, vp, i32, vp, vp],
+            "qgw_dyson_W": [vp, vp, vp, vp, vp],
+            "qgw_sigma": [vp, vp, vp, i32, i32, vp, vp],
+            "qgw_hartree_fock": [vp, vp, vp, vp, vp],
+            "qgw_dyson_G": [vp, vp, vp, dbl, pd, vp, vp],
+            "qgw_state_create": [vp, vp, vp, dbl, dbl, ctypes.POINTER(vp)],
+            "qgw_state_destroy": [vp],
+            "qgw_state_init_g0": [vp, pd, vp],
+            "qgw_gw_iteration": [vp, i32, dbl, pi32, pd, pd, vp],
+            "qgw_state_copy": [vp, i32, vp, pi64, vp],
+            "qgw_check_finite": [vp, vp, i64, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = i32
+        L.qgw_last_error.argtypes = []
+        L.qgw_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != QGW_OK:
+        raise QGWError(status, lib().qgw_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def dlr_build(lam, eps, max_rank=96):
+    """Host FP64 DLR node selection; returns dict(x=beta*omega, tau_t, n_f, n_b)."""
+    x = np.zeros(max_rank)
+    t = np.zeros(max_rank)
+    nf = np.zeros(max_rank, dtype=np.int64)
+    nb = np.zeros(max_rank, dtype=np.int64)
+    r = ctypes.c_int32(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().qgw_dlr_build(float(lam), float(eps), int(max_rank), x.ctypes.data_as(dp),
+                               t.ctypes.data_as(dp), nf.ctypes.data_as(ip), nb.ctypes.data_as(ip),
+                               ctypes.byref(r)))
+    r = r.value
+    return {"x": x[:r].copy(), "tau_t": t[:r].copy(), "n_f": nf[:r].copy(), "n_b": nb[:r].copy()}
+
+
+class Plan:
+    """A libqgw plan: mesh n x n, sites/orbitals, DLR nodes, precision."""
+
+    def __init__(self, n, site_norb, beta, omega, tau_t, n_f, n_b, precision=F64, device=0):
+        self._keep = [np.ascontiguousarray(site_norb, dtype=np.int32),
+                      np.ascontiguousarray(omega, dtype=np.float64),
+                      np.ascontiguousarray(tau_t, dtype=np.float64),
+                      np.ascontiguousarray(n_f, dtype=np.int64),
+                      np.ascontiguousarray(n_b, dtype=np.int64)]
+        so, om, tt, nf, nb = self._keep
+        d = PlanDesc(int(n), len(so), so.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(beta),
+                     len(om), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     tt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     nf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                     nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(precision), int(device))
+        h = ctypes.c_void_p()
+        _check(lib().qgw_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        r, no, nbp, nk = (ctypes.c_int32() for _ in range(4))
+        _check(lib().qgw_plan_sizes(h, ctypes.byref(r), ctypes.byref(no), ctypes.byref(nbp), ctypes.byref(nk)))
+        self.r, self.n_o, self.n_b, self.n_k = r.value, no.value, nbp.value, nk.value
+        self.n = int(n)
+        self.beta = float(beta)
+        self.precision = int(precision)
+        self.device = int(device)
+
+    @classmethod
+    def from_nodes(cls, n, site_norb, beta, nodes, precision=F64, device=0):
+        """``nodes``: dict with omega (eV), tau_t, n_f, n_b."""
+        return cls(n, site_norb, beta, nodes["omega"], nodes["tau_t"], nodes["n_f"], nodes["n_b"],
+                   precision, device)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().qgw_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_map(self, which):
+        rows = 1 if which == F_IW2BETA else self.r
+        out = np.zeros(rows * self.r * 2)
+        _check(lib().qgw_plan_get_map(self.handle, int(which), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return (out[0::2] + 1j * out[1::2]).reshape(rows, self.r)
+
+    # ---- step calls ------------------------------------------------------
+    def dlr_transform(self, which, x, out, scale=1.0, hermitian=0):
+        ncols = x.numel() // self.r
+        s = complex(scale)
+        _check(lib().qgw_dlr_transform(self.handle, int(which), int(ncols), s.real, s.imag, int(hermitian),
+                                       _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def dlr_transform_pairs(self, which, in_layout, out_layout, x, out):
+        _check(lib().qgw_dlr_transform_pairs(self.handle, int(which), int(in_layout), int(out_layout),
+                                             _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def lattice_fft(self, direction, x, out):
+        batch = x.numel() // self.n_k
+        _check(lib().qgw_lattice_fft(self.handle, int(direction), int(batch), _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def bubble(self, g_tau_r, g_reflt_r, out, out_q=True):
+        _check(lib().qgw_bubble(self.handle, _ptr(g_tau_r), _ptr(g_reflt_r), int(bool(out_q)), _ptr(out), _stream()))
+        return out
+
+    def dyson_W(self, v_q, p_nu, out):
+        _check(lib().qgw_dyson_W(self.handle, _ptr(v_q), _ptr(p_nu), _ptr(out), _stream()))
+        return out
+
+    def sigma(self, g_tau_r, wc, out, in_q=True, out_k=True):
+        _check(lib().qgw_sigma(self.handle, _ptr(g_tau_r), _ptr(wc), int(bool(in_q)), int(bool(out_k)), _ptr(out), _stream()))
+        return out
+
+    def hartree_fock(self, v_r, n_r, out):
+        _check(lib().qgw_hartree_fock(self.handle, _ptr(v_r), _ptr(n_r), _ptr(out), _stream()))
+        return out
+
+    def dyson_G(self, h_k, sig_iw, out, n_target=None, mu=0.0):
+        m = ctypes.c_double(float(mu))
+        nt = float("nan") if n_target is None else float(n_target)
+        _check(lib().qgw_dyson_G(self.handle, _ptr(h_k), _ptr(sig_iw), nt, ctypes.byref(m), _ptr(out), _stream()))
+        return m.value
+
+    def check_finite(self, x):
+        _check(lib().qgw_check_finite(self.handle, _ptr(x), int(x.numel()), _stream()))
+
+
+class State:
+    """Self-consistent GW state on the device (FP64 plans)."""
+
+    def __init__(self, plan, H0_R, V_R, n_target=None, mixing=1.0):
+        self.plan = plan
+        self._H0_R, self._V_R = H0_R, V_R
+        h = ctypes.c_void_p()
+        nt = float("nan") if n_target is None else float(n_target)
+        _check(lib().qgw_state_create(plan.handle, _ptr(H0_R), _ptr(V_R), nt, float(mixing), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().qgw_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_g0(self, mu=0.0):
+        m = ctypes.c_double(float(mu))
+        _check(lib().qgw_state_init_g0(self.handle, ctypes.byref(m), _stream()))
+        return m.value
+
+    def iterate(self, n_iter=1, tol=0.0):
+        done = ctypes.c_int32(0)
+        ds = ctypes.c_double(math.nan)
+        mu = ctypes.c_double(math.nan)
+        _check(lib().qgw_gw_iteration(self.handle, int(n_iter), float(tol), ctypes.byref(done), ctypes.byref(ds),
+                                      ctypes.byref(mu), _stream()))
+        return done.value, ds.value, mu.value
+
+    def array(self, which):
+        """Copy of a state array as a torch tensor (0 G, 1 Sigma_C, 2 Sigma_HF, 3 P, 4 W^C)."""
+        import torch
+        p = self.plan
+        shapes = {0: (p.r, p.n_o, p.n_o, p.n_k), 1: (p.r, p.n_o, p.n_o, p.n_k), 2: (p.n_o, p.n_o, p.n_k),
+                  3: (p.r, p.n_k, p.n_b, p.n_b), 4: (p.r, p.n_k, p.n_b, p.n_b)}
+        out = torch.empty(shapes[which], dtype=torch.complex128, device="cuda:%d" % p.device)
+        nbytes = ctypes.c_int64(0)
+        _check(lib().qgw_state_copy(self.handle, int(which), _ptr(out), ctypes.byref(nbytes), _stream()))
+        assert nbytes.value == out.numel() * 16
+        return out

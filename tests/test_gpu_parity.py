@@ -1,0 +1,249 @@
+"""Parity of every HIP step, and of whole GW iterations, with the oracle.
+
+All inputs are seeded synthetic models; the library gets the oracle's DLR
+node set (the nodes are a discretisation choice, passed as data) and builds
+its own maps.  Each step of the library gets the oracle's input of that step
+and is compared element by element with the oracle's output at the FP64
+tolerance: max |gpu - oracle| / max |oracle| <= 1e-10.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import rel_err
+from oracle import gw, lattice
+from oracle.dlr import DLR
+from paper_2604_22223_amd import qgw
+from paper_2604_22223_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def dev(x):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+class Case:
+    """One model: oracle state before and after one iteration, and a plan."""
+
+    def __init__(self, name, w, steps_from_g0=True):
+        self.name = name
+        self.w = w
+        self.d = DLR(w["beta"], w["omega_max"], w["eps"])
+        self.m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
+        self.st0 = gw.initial_state(self.m, self.d)
+        self.st1 = gw.gw_iteration(self.m, self.d, self.st0, keep=True)
+        self.inter = self.st1["intermediates"]
+        self.n = w["mesh"][0]
+        self.plan = qgw.Plan.from_nodes(self.n, w["site_norb"], w["beta"], self.d.nodes())
+
+    def flat(self, x):
+        """oracle [..., n1, n2] -> library [..., N_k]"""
+        return np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))
+
+
+CASE_SPECS = {
+    # 3 orbitals on two sites (N_b = 5), complex hopping, 6 x 6 mesh
+    "random_2+1_6x6": lambda: wl.random_model((6, 6), [2, 1], seed=3, beta=10.0, omega_max=20.0, eps=1e-10),
+    # five orbitals (N_b = 25) on a 10 x 10 mesh: N_k = 100 leaves ragged tiles
+    "five_orbital_10x10": lambda: wl.five_orbital(n=10, U=1.0, J=0.1, Vnn=0.2, beta=20.0, omega_max=25.0,
+                                                  eps=1e-10, scale_mesh=10),
+    # graphene G0W0 workload at its full size (12 x 12, r = 43)
+    "graphene_g0w0_12": lambda: wl.workload("graphene_g0w0_12"),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASE_SPECS))
+def case(request):
+    print("\n[parity case] %s" % request.param, flush=True)
+    return Case(request.param, CASE_SPECS[request.param]())
+
+
+def test_dlr_maps_match_oracle(case):
+    names = ["F_iw2tau", "F_iw2taur", "F_tau2iw", "B_tau2iw", "B_iw2tau"]
+    for which, name in enumerate(names):
+        lib_map = case.plan.get_map(which)
+        # applied to representable data the maps agree to rounding; the
+        # matrices themselves to what their conditioning allows
+        assert rel_err(lib_map, getattr(case.d, name)) < 1e-5
+    assert rel_err(case.plan.get_map(qgw.F_IW2BETA)[0], case.d.F_iw2beta) < 1e-5
+
+
+def test_a1_dlr_transform(case):
+    torch = _torch()
+    g = dev(case.flat(case.st0["G_iw"]))
+    out = torch.empty_like(g)
+    case.plan.dlr_transform(qgw.F_IW2TAU, g, out)
+    assert rel_err(host(out), case.flat(case.inter["G_tau"])) < TOL
+    case.plan.dlr_transform(qgw.F_IW2TAUR, g, out)
+    assert rel_err(host(out), case.flat(case.inter["G_reflt"])) < TOL
+    # density row with the Hermitian part of the output
+    n_out = torch.empty_like(g[0])
+    case.plan.dlr_transform(qgw.F_IW2BETA, g, n_out, scale=-1.0, hermitian=2)
+    assert rel_err(host(n_out), case.flat(case.inter["n_k"])) < TOL
+
+
+def test_a2_lattice_fft(case):
+    torch = _torch()
+    x = dev(case.flat(case.inter["G_tau"]))
+    out = torch.empty_like(x)
+    case.plan.lattice_fft(qgw.K_TO_R, x, out)
+    assert rel_err(host(out), case.flat(case.inter["G_tau_R"])) < TOL
+    back = torch.empty_like(x)
+    case.plan.lattice_fft(qgw.R_TO_K, out, back)
+    assert rel_err(host(back), case.flat(case.inter["G_tau"])) < TOL
+    # in place
+    y = x.clone()
+    case.plan.lattice_fft(qgw.K_TO_R, y, y)
+    assert rel_err(host(y), case.flat(case.inter["G_tau_R"])) < TOL
+
+
+def test_a3_a4_bubble(case):
+    torch = _torch()
+    gt = dev(case.flat(case.inter["G_tau_R"]))
+    gr = dev(case.flat(case.inter["G_reflt_R"]))
+    r, nb, nk = case.d.r, case.m.n_b, case.m.n_k
+    out = torch.empty((r, nb, nb, nk), dtype=torch.complex128, device="cuda:0")
+    case.plan.bubble(gt, gr, out, out_q=False)
+    assert rel_err(host(out), case.flat(case.inter["P_tau_R"])) < TOL
+    case.plan.bubble(gt, gr, out, out_q=True)
+    assert rel_err(host(out), case.flat(case.inter["P_tau_q"])) < TOL
+
+
+def _matrix_layout(x_slab):
+    """[t][A][B][k] -> [t][k][A][B]"""
+    return np.ascontiguousarray(np.moveaxis(x_slab, -1, 1))
+
+
+def test_a5_a6_a7_screened_interaction(case):
+    torch = _torch()
+    r, nb, nk = case.d.r, case.m.n_b, case.m.n_k
+    pq = dev(case.flat(case.inter["P_tau_q"]))
+    p_nu = torch.empty((r, nk, nb, nb), dtype=torch.complex128, device="cuda:0")
+    case.plan.dlr_transform_pairs(qgw.B_TAU2IW, qgw.LAYOUT_SLAB, qgw.LAYOUT_MATRIX, pq, p_nu)
+    p_ref = _matrix_layout(case.flat(case.inter["P_nu_q"]))
+    assert rel_err(host(p_nu), p_ref) < TOL
+    # slab -> slab layout gives the same numbers
+    p_slab = torch.empty_like(pq)
+    case.plan.dlr_transform_pairs(qgw.B_TAU2IW, qgw.LAYOUT_SLAB, qgw.LAYOUT_SLAB, pq, p_slab)
+    assert rel_err(host(p_slab), case.flat(case.inter["P_nu_q"])) < TOL
+    # Dyson W from the oracle's P
+    vq = dev(np.moveaxis(case.flat(case.m.V_q), -1, 0))
+    wc = torch.empty_like(p_nu)
+    case.plan.dyson_W(vq, dev(p_ref), wc)
+    wc_ref = _matrix_layout(case.flat(case.inter["Wc_nu_q"]))
+    assert rel_err(host(wc), wc_ref) < TOL
+    # bosonic i nu -> tau with the layout change back
+    wt = torch.empty_like(pq)
+    case.plan.dlr_transform_pairs(qgw.B_IW2TAU, qgw.LAYOUT_MATRIX, qgw.LAYOUT_SLAB, dev(wc_ref), wt)
+    assert rel_err(host(wt), case.flat(case.inter["Wc_tau_q"])) < TOL
+
+
+def test_a8_a9_a10_a11_self_energy(case):
+    torch = _torch()
+    r, no, nk = case.d.r, case.m.n_o, case.m.n_k
+    gt = dev(case.flat(case.inter["G_tau_R"]))
+    sig = torch.empty((r, no, no, nk), dtype=torch.complex128, device="cuda:0")
+    raw_k = case.flat(lattice.k_from_R(case.inter["sig_tau_R"]))
+    for in_q, win in [(True, case.inter["Wc_tau_q"]), (False, case.inter["Wc_tau_R"])]:
+        w = dev(case.flat(win))
+        case.plan.sigma(gt, w, sig, in_q=in_q, out_k=False)
+        assert rel_err(host(sig), case.flat(case.inter["sig_tau_R"])) < TOL
+        case.plan.sigma(gt, w, sig, in_q=in_q, out_k=True)
+        assert rel_err(host(sig), raw_k) < TOL
+    # tau -> i omega of the Hermitian part
+    out = torch.empty_like(sig)
+    case.plan.dlr_transform(qgw.F_TAU2IW, sig, out, hermitian=1)
+    assert rel_err(host(out), case.flat(case.st1["sig_iw"])) < TOL
+
+
+def test_a12_hartree_fock(case):
+    torch = _torch()
+    no, nk = case.m.n_o, case.m.n_k
+    out = torch.empty((no, no, nk), dtype=torch.complex128, device="cuda:0")
+    case.plan.hartree_fock(dev(case.flat(case.m.V_R)), dev(case.flat(case.inter["n_R"])), out)
+    assert rel_err(host(out), case.flat(case.inter["sig_hf_R"])) < TOL
+
+
+def test_a13_dyson_g(case):
+    torch = _torch()
+    h = dev(case.flat(case.m.H_k + case.st1["sig_hf_k"]))
+    s = dev(case.flat(case.st1["sig_iw"]))
+    out = torch.empty_like(s)
+    # fixed chemical potential
+    mu0 = case.st1["mu"]
+    case.plan.dyson_G(h, s, out, n_target=None, mu=mu0)
+    ref = case.flat(gw.dyson_G(case.m.H_k, case.st1["sig_hf_k"], case.st1["sig_iw"], case.d.iw, mu0))
+    assert rel_err(host(out), ref) < TOL
+    # target filling: mu by the bracketing search
+    mu = case.plan.dyson_G(h, s, out, n_target=case.m.n_target)
+    assert abs(mu - case.st1["mu"]) <= 1e-10 * max(1.0, abs(case.st1["mu"]))
+    assert rel_err(host(out), case.flat(case.st1["G_iw"])) < TOL
+    # G0 (no self-energy)
+    h0 = dev(case.flat(case.m.H_k))
+    mu = case.plan.dyson_G(h0, None, out, n_target=case.m.n_target)
+    assert abs(mu - case.st0["mu"]) <= 1e-10 * max(1.0, abs(case.st0["mu"]))
+    assert rel_err(host(out), case.flat(case.st0["G_iw"])) < TOL
+
+
+def test_whole_iterations(case):
+    """init G0, then three GW iterations through the composite entry point."""
+    p = case.plan
+    st = qgw.State(p, dev(case.flat(case.m.H_R)), dev(case.flat(case.m.V_R)), n_target=case.m.n_target)
+    mu0 = st.init_g0()
+    assert abs(mu0 - case.st0["mu"]) <= 1e-10 * max(1.0, abs(case.st0["mu"]))
+    ref = case.st0
+    for it in range(3):
+        ref = gw.gw_iteration(case.m, case.d, ref)
+        done, dsig, mu = st.iterate(1)
+        assert done == 1
+        assert abs(mu - ref["mu"]) <= 1e-10 * max(1.0, abs(ref["mu"])), (it, mu, ref["mu"])
+        assert abs(dsig - ref["d_sigma"]) <= 1e-10 * max(1.0, ref["d_sigma"]), (it, dsig, ref["d_sigma"])
+        assert rel_err(host(st.array(0)), case.flat(ref["G_iw"])) < TOL
+        assert rel_err(host(st.array(1)), case.flat(ref["sig_iw"])) < TOL
+        assert rel_err(host(st.array(2)), case.flat(ref["sig_hf_k"])) < TOL
+    st.close()
+
+
+def test_nonfinite_detection():
+    torch = _torch()
+    w = wl.random_model((4, 4), [1], seed=1, beta=5.0, omega_max=10.0, eps=1e-8)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    p = qgw.Plan.from_nodes(4, [1], w["beta"], d.nodes())
+    x = torch.zeros(100, dtype=torch.complex128, device="cuda:0")
+    p.check_finite(x)
+    x[37] = complex(float("nan"), 0.0)
+    with pytest.raises(qgw.QGWError) as e:
+        p.check_finite(x)
+    assert e.value.status == 6
+
+
+def test_empty_and_bad_arguments():
+    torch = _torch()
+    w = wl.random_model((4, 4), [1], seed=1, beta=5.0, omega_max=10.0, eps=1e-8)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    p = qgw.Plan.from_nodes(4, [1], w["beta"], d.nodes())
+    x = torch.zeros((d.r, 1, 1, 16), dtype=torch.complex128, device="cuda:0")
+    # empty batch is a no-op
+    assert qgw.lib().qgw_lattice_fft(p.handle, qgw.K_TO_R, 0, None, None, None) == 0
+    # bad enum, aliasing
+    with pytest.raises(qgw.QGWError):
+        p.dlr_transform(9, x, x.clone())
+    with pytest.raises(qgw.QGWError):
+        p.dlr_transform(qgw.F_IW2TAU, x, x)
+    with pytest.raises(qgw.QGWError):
+        p.dyson_G(x[0], x, x.clone(), n_target=5.0)      # filling outside (0, 2 n_o)
