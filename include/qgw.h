@@ -229,6 +229,20 @@ qgw_status qgw_gw_iteration(qgw_state state, int32_t n_iter, double tol,
 qgw_status qgw_state_copy(qgw_state state, int32_t which, void *dst, int64_t *bytes,
                           void *stream);
 
+/* Per-step timing of qgw_gw_iteration with HIP events on the caller's
+ * stream.  mode 1 resets the accumulators and enables timing, mode 0
+ * disables it, mode 2 only reads.  ms[QGW_NUM_STEPS] (may be NULL) receives
+ * the accumulated milliseconds per step and *iters the number of timed
+ * iterations.  Steps, in launch order:
+ *   0 a12  density n = -G(beta^-), Hartree-Fock      1 a1  G(tau), G(beta - tau)
+ *   2 a2   k -> R of both                             3 a3+a4 bubble, R -> q
+ *   4 a5   P: tau -> i nu (to the matrix layout)      5 a6  Dyson W
+ *   6 a7   W^C: i nu -> tau (to the slab layout)      7 a8-a10 self-energy
+ *   8 a11  Sigma^C: tau -> i w                        9 a14 Delta Sigma, mixing
+ *  10 a13  Dyson G with the chemical-potential search */
+#define QGW_NUM_STEPS 11
+qgw_status qgw_state_profile(qgw_state state, int32_t mode, double *ms, int32_t *iters);
+
 /* Checks ``count`` complex values (precision of the plan) for NaN/Inf;
  * waits for the stream.  QGW_ERR_NONFINITE if any is found. */
 qgw_status qgw_check_finite(qgw_plan plan, const void *x, int64_t count, void *stream);

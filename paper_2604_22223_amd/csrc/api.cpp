@@ -39,7 +39,11 @@ struct qgw_state_s {
   void *Pq = nullptr, *P_nu = nullptr, *Wc_nu = nullptr;
   double* d_dsig = nullptr;
   double* d_blockmax = nullptr;
-  bool have_old = false;
+  // per-step timing with HIP events on the caller's stream
+  bool prof = false;
+  hipEvent_t ev[QGW_NUM_STEPS + 1] = {};
+  double prof_ms[QGW_NUM_STEPS] = {};
+  int prof_iters = 0;
 };
 
 #define QGW_CHECK_HIP(expr, what)                                             \
@@ -482,6 +486,8 @@ qgw_status qgw_check_finite(qgw_plan h, const void* x, int64_t count, void* stre
 // ------------------------------------------------------------------ state
 
 static void free_state(qgw_state st) {
+  for (auto& e : st->ev)
+    if (e) (void)hipEventDestroy(e);
   void* ptrs[] = {st->H_k, st->V_R, st->V_q, st->V_qm, st->V_q0, st->G_iw, st->Sig_iw, st->Sig_iw_old,
                   st->SigHF_k, st->SigHF_old, st->n_k, st->n_R, st->SigHF_R, st->Hs_k, st->G_tau,
                   st->G_reflt, st->Sig_tau_k, st->Pq, st->P_nu, st->Wc_nu, st->d_dsig, st->d_blockmax};
@@ -575,41 +581,62 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
   const Plan& p = st->plan->p;
   QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t no2 = int64_t(p.no) * p.no, nb2 = int64_t(p.nb) * p.nb;
+  const int64_t no2 = int64_t(p.no) * p.no;
   const int64_t ncol_g = no2 * p.nk;
   double dsig = NAN;
   int done = 0;
+  auto mark = [&](int i) -> hipError_t { return st->prof ? hipEventRecord(st->ev[i], s) : hipSuccess; };
   for (int it = 0; it < n_iter; ++it) {
-    // a12: density of the incoming G, Hartree-Fock
+    // a12: density of the incoming G (Hermitian part), Hartree-Fock
+    QGW_CHECK_HIP(mark(0), "profile");
     QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2BETA, ncol_g, -1.0, 0.0, st->G_iw, st->n_k, s, 2), "a12 density");
     QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2, st->n_k, st->n_R, s), "a12 fft");
     QGW_CHECK_HIP(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, s), "a12 hf");
     QGW_CHECK_HIP(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, s), "a12 fft");
     // a1, a2
+    QGW_CHECK_HIP(mark(1), "profile");
     QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G_iw, st->G_tau, s), "a1");
     QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s), "a1");
+    QGW_CHECK_HIP(mark(2), "profile");
     QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, s), "a2");
     QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_reflt, st->G_reflt, s), "a2");
     // a3 + a4, a5, a6, a7
+    QGW_CHECK_HIP(mark(3), "profile");
     QGW_CHECK_HIP(launch_bubble(p, st->G_tau, st->G_reflt, 1, st->Pq, s), "a3");
+    QGW_CHECK_HIP(mark(4), "profile");
     QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq, st->P_nu, s), "a5");
+    QGW_CHECK_HIP(mark(5), "profile");
     QGW_CHECK_HIP(launch_dyson_w(p, st->V_qm, st->P_nu, st->Wc_nu, s), "a6");
+    QGW_CHECK_HIP(mark(6), "profile");
     QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc_nu, st->Pq, s), "a7");
-    // a8 + a9 + a10, a11
+    // a8 + a9 + a10, a11 (Hermitian part of Sigma^C(k, tau))
+    QGW_CHECK_HIP(mark(7), "profile");
     QGW_CHECK_HIP(launch_sigma(p, st->G_tau, st->Pq, 1, 1, st->Sig_tau_k, s), "a9");
+    QGW_CHECK_HIP(mark(8), "profile");
     QGW_CHECK_HIP(launch_dlr(p, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->Sig_tau_k, st->Sig_iw, s, 1), "a11");
     // a14: change of the total self-energy, mixing
+    QGW_CHECK_HIP(mark(9), "profile");
     QGW_CHECK_HIP(launch_delta_and_mix(p, st->SigHF_k, st->Sig_iw, st->SigHF_old, st->Sig_iw_old, st->mixing,
                                        st->d_dsig, st->d_blockmax, s),
                   "a14");
-    (void)nb2;
     // a13: Dyson G with the chemical potential
+    QGW_CHECK_HIP(mark(10), "profile");
     QGW_CHECK_HIP(launch_add(p, ncol_g, st->H_k, st->SigHF_k, st->Hs_k, s), "a13");
     double m = st->mu;
     qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, nullptr);
     if (rc != QGW_OK) return rc;
     st->mu = m;
-    QGW_CHECK_HIP(hipMemcpy(&dsig, st->d_dsig, sizeof(double), hipMemcpyDeviceToHost), "a14");
+    QGW_CHECK_HIP(mark(QGW_NUM_STEPS), "profile");
+    QGW_CHECK_HIP(hipMemcpyAsync(&dsig, st->d_dsig, sizeof(double), hipMemcpyDeviceToHost, s), "a14");
+    QGW_CHECK_HIP(hipStreamSynchronize(s), "a14");
+    if (st->prof) {
+      for (int i = 0; i < QGW_NUM_STEPS; ++i) {
+        float ms = 0.0f;
+        QGW_CHECK_HIP(hipEventElapsedTime(&ms, st->ev[i], st->ev[i + 1]), "profile");
+        st->prof_ms[i] += ms;
+      }
+      ++st->prof_iters;
+    }
     ++done;
     if (dsig <= tol) break;
   }
@@ -640,6 +667,25 @@ qgw_status qgw_state_copy(qgw_state st, int32_t which, void* dst, int64_t* bytes
   if (!dst) return QGW_OK;
   QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
   QGW_CHECK_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, (hipStream_t)stream), "qgw_state_copy");
+  return QGW_OK;
+}
+
+qgw_status qgw_state_profile(qgw_state st, int32_t mode, double* ms, int32_t* iters) {
+  QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_profile: null state");
+  QGW_REQUIRE(mode >= 0 && mode <= 2, QGW_ERR_INVALID_ARG, "qgw_state_profile: bad mode");
+  QGW_CHECK_HIP(hipSetDevice(st->plan->p.device), "hipSetDevice");
+  if (mode == 1) {
+    for (auto& e : st->ev)
+      if (!e) QGW_CHECK_HIP(hipEventCreate(&e), "qgw_state_profile");
+    for (double& v : st->prof_ms) v = 0.0;
+    st->prof_iters = 0;
+    st->prof = true;
+  } else if (mode == 0) {
+    st->prof = false;
+  }
+  if (ms)
+    for (int i = 0; i < QGW_NUM_STEPS; ++i) ms[i] = st->prof_ms[i];
+  if (iters) *iters = st->prof_iters;
   return QGW_OK;
 }
 

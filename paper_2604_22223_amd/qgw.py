@@ -28,7 +28,7 @@ R_TO_K, K_TO_R = -1, +1
 EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get_map", "qgw_plan_sizes",
            "qgw_dlr_transform", "qgw_dlr_transform_pairs", "qgw_lattice_fft", "qgw_bubble", "qgw_dyson_W",
            "qgw_sigma", "qgw_hartree_fock", "qgw_dyson_G", "qgw_state_create", "qgw_state_destroy",
-           "qgw_state_init_g0", "qgw_gw_iteration", "qgw_state_copy", "qgw_check_finite",
+           "qgw_state_init_g0", "qgw_gw_iteration", "qgw_state_copy", "qgw_state_profile", "qgw_check_finite",
            "qgw_last_error"]
 
 
@@ -82,6 +82,7 @@ def lib():
             "qgw_state_init_g0": [vp, pd, vp],
             "qgw_gw_iteration": [vp, i32, dbl, pi32, pd, pd, vp],
             "qgw_state_copy": [vp, i32, vp, pi64, vp],
+            "qgw_state_profile": [vp, i32, pd, pi32],
             "qgw_check_finite": [vp, vp, i64, vp],
         }
         for name, args in sig.items():
@@ -251,6 +252,17 @@ class State:
         _check(lib().qgw_gw_iteration(self.handle, int(n_iter), float(tol), ctypes.byref(done), ctypes.byref(ds),
                                       ctypes.byref(mu), _stream()))
         return done.value, ds.value, mu.value
+
+    STEP_NAMES = ["a12_density_hf", "a1_dlr_g", "a2_fft_g", "a3a4_bubble", "a5_dlr_p", "a6_dyson_w",
+                  "a7_dlr_w", "a8a9a10_sigma", "a11_dlr_sigma", "a14_delta_mix", "a13_dyson_g"]
+
+    def profile(self, mode=2):
+        """mode 1: reset + enable, 0: disable, 2: read.  Returns (ms per step dict, iterations)."""
+        ms = np.zeros(len(self.STEP_NAMES))
+        it = ctypes.c_int32(0)
+        _check(lib().qgw_state_profile(self.handle, int(mode), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.byref(it)))
+        return dict(zip(self.STEP_NAMES, ms.tolist())), it.value
 
     def array(self, which):
         """Copy of a state array as a torch tensor (0 G, 1 Sigma_C, 2 Sigma_HF, 3 P, 4 W^C)."""
