@@ -191,11 +191,14 @@ qgw_status qgw_hartree_fock(qgw_plan plan, const void *V_R, const void *n_R,
 /* a13: G(k, i w_m) = [(i w_m + mu) - H(k) - Sigma(k, i w_m)]^{-1} with H =
  * H0 + Sigma_HF (static orbital layout) and Sigma (orbital layout, or NULL
  * for Sigma = 0).  If n_target is finite, mu is first solved so that
- * N_e(mu) = 2/N_k sum_k Re Tr n(k) = n_target, n = -G(beta^-), by a
- * bracketing search (bisection safeguarded, |d mu| <= 1e-13 eV); *mu is the
- * output (its input value is ignored).  If n_target is NaN, *mu is used as
- * given.  Waits for ``stream``.  QGW_ERR_NOT_CONVERGED if no bracket or no
- * convergence within the step limit. */
+ * N_e(mu) = 2/N_k sum_k Re Tr n(k) = n_target, n = -G(beta^-), by Newton
+ * steps on N_e(mu) (dN_e/dmu from Tr G^2) kept inside the sign-change
+ * bracket by bisection once one is known, until |d mu| <= 1e-13 max(1, |mu|)
+ * eV or |N_e - n_target| <= 1e-13.  On input *mu is the starting point (NaN:
+ * the centre of the Gershgorin bounds of H); on output the chemical
+ * potential.  If n_target is NaN, *mu is used as given.  Waits for
+ * ``stream``.  QGW_ERR_NOT_CONVERGED if the search does not converge within
+ * 200 evaluations. */
 qgw_status qgw_dyson_G(qgw_plan plan, const void *H_k, const void *Sig_iw,
                        double n_target, double *mu, void *G_iw, void *stream);
 

@@ -252,7 +252,8 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
       }
     }
     p.dmaps64.mt = p.dmaps32.mt = best_mt;
-    p.dmaps64.rows_padded = p.dmaps32.rows_padded = ((p.r + best_mt - 1) / best_mt) * best_mt;
+    // zero rows past r so that every chunk size up to 32 reads inside the map
+    p.dmaps64.rows_padded = p.dmaps32.rows_padded = ((p.r + 31) / 32) * 32 + 32;
   }
   hipError_t e = hipSuccess;
   {

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_dlr(const cpx<T>* __restrict__ in, cpx<
   int64_t cin = 0, cout = 0, cswap = 0, plane = ncols;
   bool valid;
   if (MODE == kPlain) {
-    const int64_t c = int64_t(blockIdx.x) * 256 + tid;
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + tid;
     valid = c < ncols;
     cin = cout = c;
     if (HERM) {  // na = n_o, nq = N_k: column of the transposed element
@@ -121,18 +121,21 @@ hipError_t dlr_launch(const Plan& p, int map, int64_t ncols, int na, int nq, dou
                       const void* in, void* out, hipStream_t s) {
   const DeviceMaps& d = (sizeof(T) == 8) ? p.dmaps64 : p.dmaps32;
   const int rows_out = (map == 5) ? 1 : p.r;
-  const int mt = d.mt;
+  // small column counts: 64-thread blocks and 8-row chunks for enough blocks
+  const bool small = (MODE == kPlain) && ncols <= 65536;
+  const int mt = small ? 8 : d.mt;
+  const int bs = small ? 64 : 256;
   const unsigned chunks = unsigned((rows_out + mt - 1) / mt);
   unsigned bx;
   if (MODE == kPlain)
-    bx = unsigned((ncols + 255) / 256);
+    bx = unsigned((ncols + bs - 1) / bs);
   else
     bx = unsigned(((nq + 15) / 16) * ((na + 15) / 16));
   if (bx == 0) return hipSuccess;
   const dim3 grid(bx, chunks);
 #define QGW_DLR_MT(MTV)                                                                        \
   case MTV:                                                                                    \
-    hipLaunchKernelGGL((k_dlr<T, MTV, MODE, HERM>), grid, dim3(256), 0, s, (const cpx<T>*)in,  \
+    hipLaunchKernelGGL((k_dlr<T, MTV, MODE, HERM>), grid, dim3(bs), 0, s, (const cpx<T>*)in,   \
                        (cpx<T>*)out, map_ptr<T>(p, map), p.r, rows_out, ncols, na, nq, T(sre), \
                        T(sim));                                                                \
     break;

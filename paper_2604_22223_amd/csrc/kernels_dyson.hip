@@ -1,21 +1,28 @@
 // Dyson equations.
 //
 // Screened interaction (Eq. eq-screened-coulomb): for every (bosonic node,
-// q) solve (I - V P) W = V and return W^C = W - V.  One lane owns one row of
-// the augmented system [I - V P | V] in registers; the lanes of one matrix
-// form a power-of-two segment of the wavefront.  Gauss-Jordan elimination
-// with partial pivoting: the pivot row is found by a segmented arg-max over
-// the unused rows (ties go to the lower row), broadcast through LDS, and
-// eliminated from every other row, so each lane ends with the solution row
-// of the column it pivoted.
+// q) solve (I - V P) W = V and return W^C = W - V.  Gauss-Jordan elimination
+// with partial pivoting on the augmented system [I - V P | V], two lanes per
+// row: lane (row, half 0) holds the row of I - V P, lane (row, half 1) the row
+// of V, so a row costs 2 x N_b registers-worth of complex values spread over
+// two lanes.  Both halves run the same instruction stream on different
+// columns (no divergence): the pivot row is found by a segmented arg-max
+// over the unused rows (ties go to the lower row) and broadcast through LDS;
+// every row is updated as x <- x - f * pivot_row, with f = a_rs / a_ps for the
+// other rows and f = 1 - 1 / a_ps for the pivot row itself (which normalises
+// it).  At the end the half-1 lane of the row that pivoted column s holds row
+// s of W.
 //
 // Green's function (Eq. full-green-freq): one thread per (fermionic node, k)
 // inverts the n_o x n_o matrix (i w + mu) - H(k) - Sigma(k, i w) in registers
 // (in-place Gauss-Jordan with partial pivoting).  The chemical potential for
-// the target filling is found inside one cooperative launch: every
-// evaluation of N_e(mu) = -2/N_k sum_{k,m} Re rho_m Tr G(k, i w_m) ends in a
-// grid-wide barrier after which every block sums the same per-block partials
-// in the same order, so all blocks take identical root-finding steps.
+// the target filling is found inside one cooperative launch by a safeguarded
+// Newton iteration on N_e(mu) = -2/N_k sum_{k,m} Re rho_m Tr G(k, i w_m), with
+// dN_e/dmu = 2/N_k sum Re rho_m Tr G^2 (dG/dmu = -G^2): steps stay inside the
+// sign-change bracket once one is known (bisection otherwise) and are capped
+// before.  Each evaluation ends in a grid-wide barrier after which every block
+// sums the same per-block partials in the same order, so all blocks take
+// identical steps.
 #include <hip/hip_cooperative_groups.h>
 
 #include "qgw_internal.h"
@@ -33,92 +40,121 @@ constexpr int pow2_ceil(int n) {
 // ---------------------------------------------------------------------------
 // W^C = (I - V P)^{-1} V - V
 // ---------------------------------------------------------------------------
+template <int NB>
+struct DysonWShape {
+  static constexpr int SEG = pow2_ceil(NB);     // lanes per half
+  static constexpr int LPM = 2 * SEG;           // lanes per matrix
+  static constexpr int MPW = 64 / LPM;          // matrices per block (one wavefront)
+  static constexpr int NN = NB * NB;
+  static constexpr int SPLIT = (NB + 1) / 2;    // columns of I - V P formed by each half
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_cpx(cpx<T> v, int src, int width) {
+  return mk(__shfl(v.re, src, width), __shfl(v.im, src, width));
+}
+
 template <int NB, typename T>
 __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
                                                 const cpx<T>* __restrict__ pnu,
                                                 cpx<T>* __restrict__ wc, int64_t nmat, int nk) {
-  constexpr int SEG = pow2_ceil(NB);
-  constexpr int MPW = 64 / SEG;
-  constexpr int NN = NB * NB;
-  __shared__ cpx<T> sp[MPW * NN];
-  __shared__ cpx<T> piv[2][MPW][2 * NB];
+  using S = DysonWShape<NB>;
+  __shared__ cpx<T> sp[S::MPW * S::NN];
+  __shared__ cpx<T> piv[2][S::MPW][2 * NB];
   const int lane = threadIdx.x;
-  const int mw = lane / SEG, row = lane % SEG;
-  const int64_t mat0 = int64_t(blockIdx.x) * MPW;
+  const int mw = lane / S::LPM;
+  const int half = (lane / S::SEG) & 1;
+  const int row = lane % S::SEG;
+  const int64_t mat0 = int64_t(blockIdx.x) * S::MPW;
   const int64_t mat = mat0 + mw;
   const bool valid = (mat < nmat) && (row < NB);
   const int q = int(valid ? mat % nk : 0);
-  // stage the block's P matrices (contiguous in the matrix layout)
-  const int64_t nload = (nmat - mat0 < MPW ? nmat - mat0 : MPW) * NN;
-  for (int e = lane; e < MPW * NN; e += 64) sp[e] = e < nload ? pnu[mat0 * NN + e] : mk(T(0), T(0));
-  cpx<T> a[NB], b[NB];
+  const int64_t nload = (nmat - mat0 < S::MPW ? nmat - mat0 : S::MPW) * S::NN;
+  for (int e = lane; e < S::MPW * S::NN; e += 64) sp[e] = e < nload ? pnu[mat0 * S::NN + e] : mk(T(0), T(0));
+  __syncthreads();
+  const cpx<T>* vrow = vq + (int64_t(q) * NB + (row < NB ? row : 0)) * NB;
+  const cpx<T>* pm = sp + mw * S::NN;
+  // I - V P: half h forms columns [h * SPLIT, h * SPLIT + SPLIT) of its row
+  cpx<T> y[S::SPLIT];
+  const int coff = half * S::SPLIT;
+#pragma unroll
+  for (int c = 0; c < S::SPLIT; ++c) y[c] = mk(T(row == c + coff ? 1 : 0), T(0));
   if (valid) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) b[c] = vq[(int64_t(q) * NB + row) * NB + c];
+    for (int j = 0; j < NB; ++j) {
+      const cpx<T> v = vrow[j];
+#pragma unroll
+      for (int c = 0; c < S::SPLIT; ++c) {
+        const int col = c + coff < NB ? c + coff : NB - 1;
+        y[c] = fms(y[c], v, pm[j * NB + col]);
+      }
+    }
+  }
+  __syncthreads();  // P no longer needed: reuse its LDS for the hand-over
+  cpx<T>* xch = sp + mw * S::NN;
+  if (valid && half == 1) {
+#pragma unroll
+    for (int c = 0; c < NB - S::SPLIT; ++c) xch[row * S::SPLIT + c] = y[c];
   }
   __syncthreads();
+  cpx<T> x[NB];
   if (valid) {
-    const cpx<T>* pm = sp + mw * NN;
+    if (half == 0) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      cpx<T> s = mk(T(c == row ? 1 : 0), T(0));
+      for (int c = 0; c < S::SPLIT; ++c) x[c] = y[c];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) s = fms(s, b[j], pm[j * NB + c]);
-      a[c] = s;
+      for (int c = S::SPLIT; c < NB; ++c) x[c] = xch[row * S::SPLIT + c - S::SPLIT];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) x[c] = vrow[c];
     }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) x[c] = mk(T(0), T(0));
   }
   bool used = false;
   int my_step = 0;
+  const int partner = lane - half * S::SEG;  // the half-0 lane of this row
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
-    T val = (valid && !used) ? norm2(a[s]) : T(-1);
+    T val = (valid && half == 0 && !used) ? norm2(x[s]) : T(-1);
     int idx = row;
 #pragma unroll
-    for (int off = SEG / 2; off >= 1; off >>= 1) {
-      const T ov = __shfl_xor(val, off, SEG);
-      const int oi = __shfl_xor(idx, off, SEG);
+    for (int off = S::SEG; off >= 1; off >>= 1) {
+      const T ov = __shfl_xor(val, off, S::LPM);
+      const int oi = __shfl_xor(idx, off, S::LPM);
       if (ov > val || (ov == val && oi < idx)) {
         val = ov;
         idx = oi;
       }
     }
-    const bool me = valid && (row == idx);
-    if (me) {
-      used = true;
+    const bool is_p = valid && (row == idx);
+    if (is_p) {
+      if (half == 0) used = true;
       my_step = s;
 #pragma unroll
-      for (int c = s; c < NB; ++c) piv[s & 1][mw][c] = a[c];
-#pragma unroll
-      for (int c = 0; c < NB; ++c) piv[s & 1][mw][NB + c] = b[c];
+      for (int c = 0; c < NB; ++c) piv[s & 1][mw][half * NB + c] = x[c];
     }
     __syncthreads();
+    const cpx<T>* pr = piv[s & 1][mw] + half * NB;
+    const cpx<T> pinv = inv(piv[s & 1][mw][s]);
+    cpx<T> f = is_p ? mk(T(1), T(0)) - pinv : x[s] * pinv;  // meaningful on half 0
+    f = shfl_cpx(f, partner, 64);
     if (valid) {
-      const cpx<T>* pr = piv[s & 1][mw];
-      const cpx<T> pinv = inv(pr[s]);
-      if (me) {
 #pragma unroll
-        for (int c = s + 1; c < NB; ++c) a[c] = a[c] * pinv;
-        a[s] = mk(T(1), T(0));
-#pragma unroll
-        for (int c = 0; c < NB; ++c) b[c] = b[c] * pinv;
-      } else {
-        const cpx<T> f = a[s] * pinv;
-#pragma unroll
-        for (int c = s + 1; c < NB; ++c) a[c] = fms(a[c], f, pr[c]);
-        a[s] = mk(T(0), T(0));
-#pragma unroll
-        for (int c = 0; c < NB; ++c) b[c] = fms(b[c], f, pr[NB + c]);
-      }
+      for (int c = 0; c < NB; ++c) x[c] = fms(x[c], f, pr[c]);
+      if (half == 0) x[s] = mk(T(is_p ? 1 : 0), T(0));
     }
   }
-  // W^C row my_step = b - V row my_step; stage in LDS, store contiguously
-  if (valid) {
+  // W^C row my_step = (row of W) - (row of V); staged in LDS, stored contiguously
+  __syncthreads();
+  if (valid && half == 1) {
     const cpx<T>* vr = vq + (int64_t(q) * NB + my_step) * NB;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) sp[mw * NN + my_step * NB + c] = b[c] - vr[c];
+    for (int c = 0; c < NB; ++c) sp[mw * S::NN + my_step * NB + c] = x[c] - vr[c];
   }
   __syncthreads();
-  for (int e = lane; e < nload; e += 64) wc[mat0 * NN + e] = sp[e];
+  for (int e = lane; e < nload; e += 64) wc[mat0 * S::NN + e] = sp[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -140,14 +176,16 @@ __device__ __forceinline__ void invert_inplace(cpx<double> (&a)[NO][NO]) {
       }
     }
     perm[k] = p;
+    // row swap k <-> p as exact 0/1-weighted blends (w x + (1 - w) y is exact
+    // for w in {0, 1}); keeps the matrix in registers, unlike a select chain
 #pragma unroll
     for (int i = k + 1; i < NO; ++i) {
-      const bool sw = (p == i);
+      const double w = (p == i) ? 1.0 : 0.0, v = 1.0 - w;
 #pragma unroll
       for (int j = 0; j < NO; ++j) {
-        const cpx<double> t = a[k][j];
-        a[k][j] = sw ? a[i][j] : t;
-        a[i][j] = sw ? t : a[i][j];
+        const cpx<double> t = a[k][j], u = a[i][j];
+        a[k][j] = mk(w * u.re + v * t.re, w * u.im + v * t.im);
+        a[i][j] = mk(w * t.re + v * u.re, w * t.im + v * u.im);
       }
     }
     const cpx<double> pinv = inv(a[k][k]);
@@ -167,12 +205,12 @@ __device__ __forceinline__ void invert_inplace(cpx<double> (&a)[NO][NO]) {
   for (int k = NO - 1; k >= 0; --k) {
 #pragma unroll
     for (int c = k + 1; c < NO; ++c) {
-      const bool sw = (perm[k] == c);
+      const double w = (perm[k] == c) ? 1.0 : 0.0, v = 1.0 - w;
 #pragma unroll
       for (int i = 0; i < NO; ++i) {
-        const cpx<double> t = a[i][k];
-        a[i][k] = sw ? a[i][c] : t;
-        a[i][c] = sw ? t : a[i][c];
+        const cpx<double> t = a[i][k], u = a[i][c];
+        a[i][k] = mk(w * u.re + v * t.re, w * u.im + v * t.im);
+        a[i][c] = mk(w * t.re + v * u.re, w * t.im + v * u.im);
       }
     }
   }
@@ -184,9 +222,9 @@ struct DysonGArgs {
   const double* wn;   // [r]
   const zd* rho;      // [r]: G(beta^-) = sum_m rho_m G(i w_m)
   zd* g;              // [r][no][no][nk]
-  double* scal;       // [0] mu (in/out), [1] n_target, [2] evaluations, [3] final N_e
-  double* partials;   // [2][4][max_blocks]
-  int* status;        // 0 ok, 1 no bracket, 2 not converged
+  double* scal;       // [0] mu (in: start / fixed; out), [1] n_target, [2] evaluations, [3] final N_e
+  double* partials;   // [2][4][max blocks]
+  int* status;        // 0 ok, 2 not converged
   int r, nk, mode, max_evals;
   double beta, tol_mu, tol_n;
 };
@@ -210,7 +248,8 @@ __device__ __forceinline__ void load_base(const DysonGArgs& A, int64_t gi, cpx<d
     }
 }
 
-// block-level deterministic sum (one wavefront per block)
+// block-level deterministic reductions (one wavefront per block); the xor
+// butterfly leaves the same value in every lane
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -227,32 +266,47 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// N_e(mu) and dN_e/dmu; ends with a grid barrier
 template <int NO>
-__device__ double count_electrons(const DysonGArgs& A, double mu, cg::grid_group& grid, int buf) {
+__device__ __forceinline__ void count_electrons(const DysonGArgs& A, double mu, cg::grid_group& grid, int buf,
+                                             double& n_e, double& dn_e) {
   const int64_t total = int64_t(A.r) * A.nk;
   const int64_t stride = int64_t(gridDim.x) * 64;
-  double acc = 0.0;
+  double acc = 0.0, accd = 0.0;
   for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
     cpx<double> a[NO][NO];
     load_base<NO>(A, gi, a);
 #pragma unroll
     for (int i = 0; i < NO; ++i) a[i][i].re += mu;
     invert_inplace<NO>(a);
-    cpx<double> tr = mk(0.0, 0.0);
+    cpx<double> tr = mk(0.0, 0.0), tr2 = mk(0.0, 0.0);
 #pragma unroll
-    for (int i = 0; i < NO; ++i) tr = tr + a[i][i];
-    const int m = int(gi / A.nk);
-    const zd rh = A.rho[m];
+    for (int i = 0; i < NO; ++i) {
+      tr = tr + a[i][i];
+#pragma unroll
+      for (int j = 0; j < NO; ++j) tr2 = fma(tr2, a[i][j], a[j][i]);
+    }
+    const zd rh = A.rho[int(gi / A.nk)];
     acc += rh.re * tr.re - rh.im * tr.im;
+    accd += rh.re * tr2.re - rh.im * tr2.im;
   }
   acc = wave_sum(acc);
+  accd = wave_sum(accd);
   double* part = A.partials + int64_t(buf) * 4 * gridDim.x;
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = acc;
+    part[gridDim.x + blockIdx.x] = accd;
+  }
   grid.sync();
-  double s = 0.0;
-  for (int b = threadIdx.x; b < int(gridDim.x); b += 64) s += part[b];
+  double s = 0.0, sd = 0.0;
+  for (int b = threadIdx.x; b < int(gridDim.x); b += 64) {
+    s += part[b];
+    sd += part[gridDim.x + b];
+  }
   s = wave_sum(s);
-  return -2.0 * s / double(A.nk);
+  sd = wave_sum(sd);
+  n_e = -2.0 * s / double(A.nk);
+  dn_e = 2.0 * sd / double(A.nk);
 }
 
 template <int NO>
@@ -265,100 +319,67 @@ __global__ __launch_bounds__(64) void k_dyson_g(DysonGArgs A) {
   double n_final = 0.0;
   if (A.mode == 1) {
     const double nt = A.scal[1];
-    // Gershgorin bounds of H plus a bound on |Sigma|
-    double glo = 1e300, ghi = -1e300, smax = 0.0;
-    for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
-      const int m = int(gi / A.nk), k = int(gi - int64_t(m) * A.nk);
-      for (int i = 0; i < NO; ++i) {
-        double rad = 0.0;
-        for (int j = 0; j < NO; ++j) {
-          const zd h = A.hk[(int64_t(i) * NO + j) * A.nk + k];
-          if (j != i) rad += sqrt(norm2(h));
-          if (A.sig) smax = fmax(smax, sqrt(norm2(A.sig[((int64_t(m) * NO + i) * NO + j) * A.nk + k])));
+    if (!isfinite(mu)) {
+      // no starting point: the centre of the Gershgorin bounds of H
+      double glo = 1e300, ghi = -1e300;
+      for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
+        const int k = int(gi % A.nk);
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+          double rad = 0.0;
+#pragma unroll
+          for (int j = 0; j < NO; ++j)
+            if (j != i) rad += sqrt(norm2(A.hk[(int64_t(i) * NO + j) * A.nk + k]));
+          const double d = A.hk[(int64_t(i) * NO + i) * A.nk + k].re;
+          glo = fmin(glo, d - rad);
+          ghi = fmax(ghi, d + rad);
         }
-        const double d = A.hk[(int64_t(i) * NO + i) * A.nk + k].re;
-        glo = fmin(glo, d - rad);
-        ghi = fmax(ghi, d + rad);
       }
+      glo = wave_min(glo);
+      ghi = wave_max(ghi);
+      double* part = A.partials + int64_t(1) * 4 * gridDim.x;
+      if (threadIdx.x == 0) {
+        part[2 * gridDim.x + blockIdx.x] = glo;
+        part[3 * gridDim.x + blockIdx.x] = ghi;
+      }
+      grid.sync();
+      glo = 1e300;
+      ghi = -1e300;
+      for (int b = threadIdx.x; b < int(gridDim.x); b += 64) {
+        glo = fmin(glo, part[2 * gridDim.x + b]);
+        ghi = fmax(ghi, part[3 * gridDim.x + b]);
+      }
+      mu = 0.5 * (wave_min(glo) + wave_max(ghi));
     }
-    glo = wave_min(glo);
-    ghi = wave_max(ghi);
-    smax = wave_max(smax);
-    double* part = A.partials + int64_t(1) * 4 * gridDim.x;
-    if (threadIdx.x == 0) {
-      part[blockIdx.x] = glo;
-      part[gridDim.x + blockIdx.x] = ghi;
-      part[2 * gridDim.x + blockIdx.x] = smax;
-    }
-    grid.sync();
-    glo = 1e300;
-    ghi = -1e300;
-    smax = 0.0;
-    for (int b = threadIdx.x; b < int(gridDim.x); b += 64) {
-      glo = fmin(glo, part[b]);
-      ghi = fmax(ghi, part[gridDim.x + b]);
-      smax = fmax(smax, part[2 * gridDim.x + b]);
-    }
-    glo = wave_min(glo);
-    ghi = wave_max(ghi);
-    smax = wave_max(smax);
-    const double pad = 10.0 / A.beta + NO * smax + 1.0;
-    double lo = glo - pad, hi = ghi + pad;
+    double lo = -INFINITY, hi = INFINITY, cap = 1.0;
+    bool done = false;
     int buf = 0;
-    double flo = count_electrons<NO>(A, lo, grid, buf) - nt;
-    buf ^= 1;
-    double fhi = count_electrons<NO>(A, hi, grid, buf) - nt;
-    buf ^= 1;
-    evals = 2;
-    int widen = 0;
-    while (!(flo < 0.0 && fhi > 0.0) && widen < 60) {
-      const double w = hi - lo;
-      lo -= w;
-      hi += w;
-      flo = count_electrons<NO>(A, lo, grid, buf) - nt;
+    for (int it = 0; it < A.max_evals && !done; ++it) {
+      double ne, dne;
+      count_electrons<NO>(A, mu, grid, buf, ne, dne);
       buf ^= 1;
-      fhi = count_electrons<NO>(A, hi, grid, buf) - nt;
-      buf ^= 1;
-      evals += 2;
-      ++widen;
-    }
-    if (!(flo < 0.0 && fhi > 0.0)) {
-      status = 1;
-      mu = 0.5 * (lo + hi);
-    } else {
-      // Illinois false position, every third step a bisection
-      int side = 0;
-      double c = 0.5 * (lo + hi), fc = 0.0;
-      bool done = false;
-      for (int it = 0; it < A.max_evals && !done; ++it) {
-        if (it % 3 == 2) {
-          c = 0.5 * (lo + hi);
-        } else {
-          c = hi - fhi * (hi - lo) / (fhi - flo);
-          if (!(c > lo && c < hi)) c = 0.5 * (lo + hi);
+      ++evals;
+      const double f = ne - nt;
+      n_final = ne;
+      if (f < 0.0) lo = fmax(lo, mu);
+      if (f > 0.0) hi = fmin(hi, mu);
+      if (fabs(f) <= A.tol_n) break;
+      double nxt = (dne > 0.0) ? mu - f / dne : NAN;
+      const bool bracket = isfinite(lo) && isfinite(hi);
+      if (bracket) {
+        if (!(nxt > lo && nxt < hi)) nxt = 0.5 * (lo + hi);
+      } else {
+        if (!isfinite(nxt)) nxt = mu + (f < 0.0 ? cap : -cap);
+        if (fabs(nxt - mu) > cap) {
+          nxt = mu + (nxt > mu ? cap : -cap);
+          cap *= 4.0;
         }
-        fc = count_electrons<NO>(A, c, grid, buf) - nt;
-        buf ^= 1;
-        ++evals;
-        if (fc < 0.0) {
-          lo = c;
-          flo = fc;
-          if (side == -1) fhi *= 0.5;
-          side = -1;
-        } else if (fc > 0.0) {
-          hi = c;
-          fhi = fc;
-          if (side == +1) flo *= 0.5;
-          side = +1;
-        } else {
-          done = true;
-        }
-        if (hi - lo <= A.tol_mu || fabs(fc) <= A.tol_n) done = true;
       }
-      mu = (fabs(fc) <= A.tol_n || hi - lo > A.tol_mu) ? c : 0.5 * (lo + hi);
-      if (!done) status = 2;
-      n_final = fc + nt;
+      const double tol = A.tol_mu * fmax(1.0, fabs(mu));
+      if (fabs(nxt - mu) <= tol || (bracket && hi - lo <= tol)) done = true;
+      mu = nxt;
     }
+    if (!done && !(fabs(n_final - nt) <= A.tol_n)) status = 2;
   }
   // G at the final mu
   for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
@@ -388,7 +409,7 @@ namespace {
 
 template <int NB, typename T>
 hipError_t dyson_w_nb(const Plan& p, const void* v_q, const void* p_nu, void* wc_nu, hipStream_t s) {
-  constexpr int MPW = 64 / pow2_ceil(NB);
+  constexpr int MPW = DysonWShape<NB>::MPW;
   const int64_t nmat = int64_t(p.r) * p.nk;
   const unsigned blocks = unsigned((nmat + MPW - 1) / MPW);
   hipLaunchKernelGGL((k_dyson_w<NB, T>), dim3(blocks), dim3(64), 0, s, (const cpx<T>*)v_q,
