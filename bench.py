@@ -6,12 +6,18 @@ A step is one full GW iteration through libqgw (Fig. fig-self (b): density
 and Hartree-Fock, G(i w) -> G(tau), bubble, P(i nu), Dyson W, W^C(tau),
 self-energy, Sigma(i w), Delta Sigma, Dyson G with the chemical-potential
 search).  Inputs are seeded and synthetic and resident in HBM before timing.
-W untimed iterations run first, then exactly K iterations are timed between
-two device synchronisations; per-step durations come from HIP events the
-library records on the same stream inside that timed region.  A separate
-self-consistent run from G0 reports the iterations and the time to reach
-max |Delta Sigma| <= 1e-6.  The oracle is timed on the host for one
-iteration of the same workload (the CPU baseline).
+
+The timed work is back-to-back self-consistent solves from G0 to
+max |Delta Sigma| <= 1e-6 (a converged solve restarts from G0), under two
+precision schedules: plain FP64, and the chosen one (the bulk steps a1-a11
+in FP32 while |Delta Sigma| is large, FP64 to finish, so every solve ends on
+an FP64 fixed point).  For each, W untimed iterations run first, then exactly
+K iterations are timed between two device synchronisations; `value` is the
+chosen schedule's iterations/s.  Per-step durations come from HIP events the
+library records on the same stream inside the timed region.  One solve per
+schedule is also timed on its own (iterations and time to solution).  The
+oracle is timed on the host for one iteration of the same workload (the CPU
+baseline).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -29,6 +35,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix), TFLOP/s
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 (vector = matrix), TFLOP/s
+SWITCH_TOL = 1e-4              # |Delta Sigma| at which the mixed solve leaves FP32
 
 WORKLOAD = "five_orbital_24"
 METRIC = "GW iterations/sec (5-orb, 24^2 k), chosen vs plain FP64, at |dSigma|<=1e-6"
@@ -46,32 +54,52 @@ def make_workload():
     return wl.five_orbital(n=24, U=1.0, J=0.1, Vnn=0.2, beta=50.0, omega_max=25.0, eps=1e-10)
 
 
-def step_model(r, n_o, n_b, n_k, mesh_n):
-    """Algorithmic bytes (HBM) and flops of each timed step, FP64 complex."""
-    c = 16.0
-    s_g = r * n_o * n_o * n_k * c           # one fermionic orbital array
-    s_p = r * n_b * n_b * n_k * c           # one pair array
-    stat_o = n_o * n_o * n_k * c
+def step_model(r, n_o, n_b, n_k, prec="f64"):
+    """Algorithmic HBM bytes and flops of each timed step.
+
+    FP64 iterations hold complex128 arrays (16 bytes); the FP32 iterations run
+    a1-a11 on complex64 arrays (8 bytes) and start from / end in the FP64
+    G(i w) and Sigma(i w) of the solve; a12, a13 and a14 are FP64 in both."""
+    c = 16.0 if prec == "f64" else 8.0
+    ng = r * n_o * n_o * n_k                 # elements of one fermionic array
+    npair = r * n_b * n_b * n_k              # elements of one pair array
+    stat_o = n_o * n_o * n_k * 16.0
     fft_flops = 5.0 * n_k * math.log2(max(n_k, 2))   # per slab (complex 2-D FFT)
     return {
-        "a12_density_hf": {"bytes": s_g + 6 * stat_o + n_b * n_b * n_k * c, "flops": 8.0 * r * n_o * n_o * n_k},
-        "a1_dlr_g": {"bytes": 3 * s_g, "flops": 2 * 8.0 * r * r * n_o * n_o * n_k},
-        "a2_fft_g": {"bytes": 4 * s_g, "flops": 2 * r * n_o * n_o * fft_flops},
-        "a3a4_bubble": {"bytes": 2 * s_g + s_p, "flops": r * n_b * n_b * (fft_flops + 12.0 * n_k)},
-        "a5_dlr_p": {"bytes": 2 * s_p, "flops": 8.0 * r * r * n_b * n_b * n_k},
-        "a6_dyson_w": {"bytes": 2 * s_p + n_b * n_b * n_k * c, "flops": (8.0 + 8.0 / 3.0 + 8.0) * n_b ** 3 * r * n_k},
-        "a7_dlr_w": {"bytes": 2 * s_p, "flops": 8.0 * r * r * n_b * n_b * n_k},
-        "a8a9a10_sigma": {"bytes": s_p + 2 * s_g, "flops": r * n_b * n_b * (fft_flops + 8.0 * n_k) + r * n_o * n_o * fft_flops},
-        "a11_dlr_sigma": {"bytes": 3 * s_g, "flops": 8.0 * r * r * n_o * n_o * n_k},
-        "a14_delta_mix": {"bytes": 4 * s_g, "flops": 0.0},
-        "a13_dyson_g": {"bytes": 2 * s_g, "flops": 0.0},
+        "a12_density_hf": {"bytes": 16.0 * ng + 6 * stat_o + n_b * n_b * n_k * 16.0, "flops": 8.0 * r * n_o * n_o * n_k},
+        # read G(i w) once (FP64), write G(tau) and G(beta - tau)
+        "a1_dlr_g": {"bytes": 16.0 * ng + 2 * c * ng, "flops": 2 * 8.0 * r * r * n_o * n_o * n_k},
+        "a2_fft_g": {"bytes": 4 * c * ng, "flops": 2 * r * n_o * n_o * fft_flops},
+        "a3a4_bubble": {"bytes": 2 * c * ng + c * npair, "flops": r * n_b * n_b * (fft_flops + 12.0 * n_k)},
+        "a5_dlr_p": {"bytes": 2 * c * npair, "flops": 8.0 * r * r * n_b * n_b * n_k},
+        "a6_dyson_w": {"bytes": 2 * c * npair + n_b * n_b * n_k * c, "flops": (8.0 + 8.0 / 3.0 + 8.0) * n_b ** 3 * r * n_k},
+        "a7_dlr_w": {"bytes": 2 * c * npair, "flops": 8.0 * r * r * n_b * n_b * n_k},
+        "a8a9a10_sigma": {"bytes": c * npair + 2 * c * ng, "flops": r * n_b * n_b * (fft_flops + 8.0 * n_k) + r * n_o * n_o * fft_flops},
+        # read Sigma^C(k, tau), write the FP64 Sigma^C(k, i w)
+        "a11_dlr_sigma": {"bytes": c * ng + 16.0 * ng, "flops": 8.0 * r * r * n_o * n_o * n_k},
+        "a14_delta_mix": {"bytes": 4 * 16.0 * ng, "flops": 0.0},
+        "a13_dyson_g": {"bytes": 2 * 16.0 * ng, "flops": 0.0},
     }
 
 
-def bound_of(entry):
-    """HBM-bound if the arithmetic intensity is below the FP64 ridge point."""
-    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+PEAK_TFLOPS = {"f64": FP64_PEAK_TFLOPS, "f32": FP32_PEAK_TFLOPS}
+FP64_STEPS = ("a12_density_hf", "a14_delta_mix", "a13_dyson_g")
+
+
+def bound_of(entry, prec):
+    """HBM-bound if the arithmetic intensity is below the ridge point of the step's precision."""
+    ridge = PEAK_TFLOPS[prec] * 1e12 / (HBM_PEAK_GBS * 1e9)
     return "alu" if entry["flops"] / max(entry["bytes"], 1.0) > ridge else "hbm"
+
+
+def roof(entry, prec, ms):
+    b = bound_of(entry, prec)
+    if b == "hbm":
+        ach, peak, unit = entry["bytes"] / (ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        ach, peak, unit = entry["flops"] / (ms * 1e-3) / 1e12, PEAK_TFLOPS[prec], "TFLOP/s"
+    return {"ms": round(ms, 5), "bound": b, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+            "frac": round(ach / peak, 4)}
 
 
 def cpu_baseline(w):
@@ -90,11 +118,39 @@ def cpu_baseline(w):
                       "(NumPy FP64, %s BLAS threads, %d host CPUs visible), %.1f s" % (threads, os.cpu_count(), dt)}
 
 
+def solve(st, mode, tol, max_iter=60):
+    """One self-consistent solve from G0 under a precision schedule."""
+    st.set_precision(mode, SWITCH_TOL)
+    st.init_g0()
+    hist = []
+    for _ in range(max_iter):
+        _, dsig, mu = st.iterate(1)
+        hist.append((dsig, st.info()[0]))
+        if dsig <= tol and hist[-1][1] == 0:
+            break
+    return hist, mu
+
+
+def timed_solves(torch, st, mode, tol, steps):
+    """Exactly `steps` GW iterations of back-to-back solves from G0 (a converged
+    solve restarts from G0), between two device synchronisations."""
+    st.set_precision(mode, SWITCH_TOL)
+    st.init_g0()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, dsig, _ = st.iterate(1)
+        if dsig <= tol and st.info()[0] == 0:
+            st.init_g0()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
     a = ap.parse_args()
@@ -119,57 +175,62 @@ def main():
     H_R, V_R = flat(w["H_R"]), flat(w["V_R"])
     setup_s = time.perf_counter() - t0
     log("[bench] plan: r=%d n_o=%d N_b=%d N_k=%d (setup %.2fs)" % (plan.r, plan.n_o, plan.n_b, plan.n_k, setup_s))
-
-    # self-consistency from G0 to the tolerance: iterations and time to solution
     st = qgw.State(plan, H_R, V_R, n_target=w["n_target"])
-    st.init_g0()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters, hist = 0, []
-    while iters < 60:
-        done, dsig, mu = st.iterate(1)
-        iters += done
-        hist.append(dsig)
-        if dsig <= a.tol:
-            break
-    torch.cuda.synchronize()
-    tts = time.perf_counter() - t0
-    log("[bench] SCF from G0: %d iterations to |dSigma| = %.2e, %.4f s, mu = %.10f" % (iters, dsig, tts, mu))
-    converged = dsig <= a.tol
 
-    # warm-up, then exactly K timed iterations with per-step HIP events
-    for _ in range(a.warmup):
-        st.iterate(1)
-    st.profile(1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        st.iterate(1)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    steps_ms, nprof = st.profile(0)
-    ms_per_step = 1e3 * elapsed / a.steps
-    value = a.steps / elapsed
-    log("[bench] %d timed iterations: %.3f ms/iteration, %.1f iterations/s" % (a.steps, ms_per_step, value))
+    # self-consistent solves from G0 to the tolerance under both schedules
+    solves = {}
+    for name, mode in (("fp64", 0), ("mixed", 1)):
+        solve(st, mode, a.tol)                 # first solve: warm caches and code paths
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist, mu = solve(st, mode, a.tol)
+        torch.cuda.synchronize()
+        tts = time.perf_counter() - t0
+        sig = st.array(1).cpu().numpy()
+        n32 = sum(1 for _, p in hist if p == 1)
+        solves[name] = {"iterations": len(hist), "fp32_iterations": n32, "time_to_solution_s": round(tts, 6),
+                        "final_dsigma": hist[-1][0], "converged": bool(hist[-1][0] <= a.tol), "mu": mu, "sigma": sig}
+        log("[bench] %-5s solve from G0: %d iterations (%d FP32) to |dSigma| = %.2e in %.4f s, mu = %.10f"
+            % (name, len(hist), n32, hist[-1][0], tts, mu))
+    sig_diff = float(np.max(np.abs(solves["mixed"]["sigma"] - solves["fp64"]["sigma"])))
+    log("[bench] max |Sigma_mixed - Sigma_fp64| at convergence: %.2e" % sig_diff)
+    for v in solves.values():
+        del v["sigma"]
 
-    model = step_model(plan.r, plan.n_o, plan.n_b, plan.n_k, n)
-    steps = {}
-    for name, tot in steps_ms.items():
-        ms = tot / max(nprof, 1)
-        e = model[name]
-        b = bound_of(e)
-        if b == "hbm":
-            ach, peak, unit = e["bytes"] / (ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
-        else:
-            ach, peak, unit = e["flops"] / (ms * 1e-3) / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
-        steps[name] = {"ms": round(ms, 5), "bound": b, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-                       "frac": round(ach / peak, 4)}
-        log("[bench]   %-16s %8.4f ms  %-3s %9.2f %-7s (%.1f%% of peak)" % (name, ms, b, ach, unit, 100 * ach / peak))
-    dom = max(steps, key=lambda k: steps[k]["ms"])
+    # plain FP64 and chosen (mixed) schedules: W untimed, then exactly K timed iterations each
+    timed = {}
+    for name, mode in (("fp64", 0), ("mixed", 1)):
+        timed_solves(torch, st, mode, a.tol, a.warmup)
+        st.profile(1)
+        el = timed_solves(torch, st, mode, a.tol, a.steps)
+        timed[name] = {"elapsed": el, "prof": st.profile(0, per_precision=True)}
+        log("[bench] %-5s: %d timed iterations in %.4f s: %.3f ms/iteration, %.1f iterations/s"
+            % (name, a.steps, el, 1e3 * el / a.steps, a.steps / el))
+    value = a.steps / timed["mixed"]["elapsed"]
+    ms_per_step = 1e3 * timed["mixed"]["elapsed"] / a.steps
+    value64 = a.steps / timed["fp64"]["elapsed"]
+
+    # per-step roofline over the chosen schedule's timed region, by precision
+    steps, totals = {}, {}
+    for prec in ("f64", "f32"):
+        ms_tot, iters = timed["mixed"]["prof"][prec]
+        if iters == 0:
+            continue
+        model = step_model(plan.r, plan.n_o, plan.n_b, plan.n_k, prec)
+        for name, tot in ms_tot.items():
+            key = "%s:%s" % (name, prec)
+            kprec = "f64" if name in FP64_STEPS else prec
+            steps[key] = dict(roof(model[name], kprec, tot / iters), iterations=iters)
+            steps[key]["per_launch"] = {"bytes": model[name]["bytes"], "flops": model[name]["flops"]}
+            totals[key] = tot
+            log("[bench]   %-22s %8.4f ms x %3d  %-3s %9.2f %-7s (%.1f%% of peak)"
+                % (key, tot / iters, iters, steps[key]["bound"], steps[key]["achieved"], steps[key]["unit"],
+                   100 * steps[key]["frac"]))
+    dom = max(totals, key=totals.get)
     dd = steps[dom]
     roofline = {"bound": dd["bound"], "achieved": dd["achieved"], "peak": dd["peak"], "unit": dd["unit"],
                 "frac": dd["frac"], "traffic": None, "kernel": dom,
-                "per_launch": {"bytes": model[dom]["bytes"], "flops": model[dom]["flops"], "ms": dd["ms"]}}
+                "per_launch": dict(dd["per_launch"], ms=dd["ms"])}
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -180,13 +241,19 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GW iterations/sec", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic (seeded five-orbital model)",
         "config": {"workload": WORKLOAD, "mesh": "24x24", "n_orb": plan.n_o, "n_pair": plan.n_b,
                    "beta": w["beta"], "omega_max": w["omega_max"], "dlr_eps": w["eps"], "dlr_rank": plan.r,
-                   "U": 1.0, "J": 0.1, "V_nn": 0.2, "filling": w["n_target"], "path": "fp64",
-                   "scf_iterations_to_tol": iters, "scf_converged": bool(converged),
-                   "scf_time_to_tol_s": round(tts, 5), "tol": a.tol},
+                   "U": 1.0, "J": 0.1, "V_nn": 0.2, "filling": w["n_target"], "tol": a.tol,
+                   "path": "chosen: FP32 a1-a11 while |dSigma| > %g and falling, then FP64" % SWITCH_TOL,
+                   "timed_work": "back-to-back self-consistent solves from G0 to |dSigma| <= tol"},
+        "plain_fp64": {"value": round(value64, 3), "ms_per_step": round(1e3 * timed["fp64"]["elapsed"] / a.steps, 4)},
+        "chosen_vs_fp64": round(value / value64, 4),
+        "solves": solves,
+        "time_to_solution_fp64_over_chosen": round(solves["fp64"]["time_to_solution_s"]
+                                                   / solves["mixed"]["time_to_solution_s"], 4),
+        "sigma_diff_chosen_vs_fp64": sig_diff,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "steps_detail": steps,

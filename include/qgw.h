@@ -232,11 +232,26 @@ qgw_status qgw_gw_iteration(qgw_state state, int32_t n_iter, double tol,
 qgw_status qgw_state_copy(qgw_state state, int32_t which, void *dst, int64_t *bytes,
                           void *stream);
 
+/* Precision schedule of the solve.  mode 0: every iteration in FP64.  mode 1
+ * (mixed): iterations run the bulk steps a1-a11 in FP32 (complex64 arrays,
+ * FP32 matrix cores for the DLR maps, FP32 Dyson W) while max |Delta Sigma|
+ * is above switch_tol and still falling by at least half per iteration; the
+ * rest of the solve runs in FP64, so the converged result is an FP64 fixed
+ * point (defect correction).  Density, Hartree-Fock, the Dyson G solve and
+ * the chemical potential are FP64 in both modes.  qgw_state_init_g0 restarts
+ * the schedule. */
+qgw_status qgw_state_set_precision(qgw_state state, int32_t mode, double switch_tol);
+
+/* Precision used by the last iteration (0 FP64, 1 FP32) and the number of
+ * FP32 and FP64 iterations since qgw_state_init_g0. */
+qgw_status qgw_state_info(qgw_state state, int32_t *last_prec, int32_t *n_fp32, int32_t *n_fp64);
+
 /* Per-step timing of qgw_gw_iteration with HIP events on the caller's
  * stream.  mode 1 resets the accumulators and enables timing, mode 0
- * disables it, mode 2 only reads.  ms[QGW_NUM_STEPS] (may be NULL) receives
- * the accumulated milliseconds per step and *iters the number of timed
- * iterations.  Steps, in launch order:
+ * disables it, mode 2 only reads.  ms[2 * QGW_NUM_STEPS] (may be NULL)
+ * receives the accumulated milliseconds per step, first over the FP64
+ * iterations, then over the FP32 ones; iters[2] (may be NULL) the number of
+ * timed FP64 and FP32 iterations.  Steps, in launch order:
  *   0 a12  density n = -G(beta^-), Hartree-Fock      1 a1  G(tau), G(beta - tau)
  *   2 a2   k -> R of both                             3 a3+a4 bubble, R -> q
  *   4 a5   P: tau -> i nu (to the matrix layout)      5 a6  Dyson W

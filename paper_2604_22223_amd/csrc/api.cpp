@@ -39,11 +39,20 @@ struct qgw_state_s {
   void *Pq = nullptr, *P_nu = nullptr, *Wc_nu = nullptr;
   double* d_dsig = nullptr;
   double* d_blockmax = nullptr;
+  // single-precision copies for the FP32 phase of the solve
+  Plan p32;
+  void *G32 = nullptr, *Gt32 = nullptr, *Gr32 = nullptr, *St32 = nullptr, *Siw32 = nullptr;
+  void *Pq32 = nullptr, *Pnu32 = nullptr, *Wc32 = nullptr, *Vqm32 = nullptr;
+  int prec_mode = 0;          // 0: FP64 only; 1: FP32 until |dSigma| <= switch_tol, then FP64
+  double switch_tol = 1e-4;
+  bool in_fp32 = false;
+  int n_fp32 = 0, n_fp64 = 0, last_prec = 0;
+  double last_dsig = INFINITY;
   // per-step timing with HIP events on the caller's stream
   bool prof = false;
   hipEvent_t ev[QGW_NUM_STEPS + 1] = {};
-  double prof_ms[QGW_NUM_STEPS] = {};
-  int prof_iters = 0;
+  double prof_ms[2][QGW_NUM_STEPS] = {};  // [FP64, FP32 iterations][step]
+  int prof_iters[2] = {};
 };
 
 #define QGW_CHECK_HIP(expr, what)                                             \
@@ -491,7 +500,9 @@ static void free_state(qgw_state st) {
     if (e) (void)hipEventDestroy(e);
   void* ptrs[] = {st->H_k, st->V_R, st->V_q, st->V_qm, st->V_q0, st->G_iw, st->Sig_iw, st->Sig_iw_old,
                   st->SigHF_k, st->SigHF_old, st->n_k, st->n_R, st->SigHF_R, st->Hs_k, st->G_tau,
-                  st->G_reflt, st->Sig_tau_k, st->Pq, st->P_nu, st->Wc_nu, st->d_dsig, st->d_blockmax};
+                  st->G_reflt, st->Sig_tau_k, st->Pq, st->P_nu, st->Wc_nu, st->d_dsig, st->d_blockmax,
+                  st->G32, st->Gt32, st->Gr32, st->St32, st->Siw32, st->Pq32, st->Pnu32, st->Wc32,
+                  st->Vqm32};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -524,16 +535,22 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
                 {&st->Sig_iw_old, fo}, {&st->SigHF_k, so}, {&st->SigHF_old, so},  {&st->n_k, so},
                 {&st->n_R, so},       {&st->SigHF_R, so}, {&st->Hs_k, so},       {&st->G_tau, fo},
                 {&st->G_reflt, fo},   {&st->Sig_tau_k, fo}, {&st->Pq, fp},       {&st->P_nu, fp},
-                {&st->Wc_nu, fp},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096}};
+                {&st->Wc_nu, fp},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096},
+                {&st->G32, fo / 2},   {&st->Gt32, fo / 2}, {&st->Gr32, fo / 2},   {&st->St32, fo / 2},
+                {&st->Siw32, fo / 2}, {&st->Pq32, fp / 2}, {&st->Pnu32, fp / 2}, {&st->Wc32, fp / 2},
+                {&st->Vqm32, sp / 2}};
   for (auto& a : allocs) {
     if (e != hipSuccess) break;
     e = hipMalloc(a.ptr, a.bytes);
   }
+  st->p32 = p;
+  st->p32.prec = QGW_F32;
   hipStream_t s = nullptr;
   if (e == hipSuccess) e = hipMemcpyAsync(st->V_R, V_R, sp, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = launch_lattice_fft(p, QGW_R_TO_K, int64_t(p.no) * p.no, H0_R, st->H_k, s);
   if (e == hipSuccess) e = launch_lattice_fft(p, QGW_R_TO_K, int64_t(p.nb) * p.nb, V_R, st->V_q, s);
   if (e == hipSuccess) e = launch_slab_to_matrix_static(p, st->V_q, st->V_qm, s);
+  if (e == hipSuccess) e = launch_convert(int64_t(p.nb) * p.nb * p.nk, st->V_qm, st->Vqm32, 1, s);
   if (e == hipSuccess) e = launch_pair_sum_r(p, V_R, st->V_q0, s);
   if (e == hipSuccess) e = hipMemsetAsync(st->Sig_iw, 0, fo, s);
   if (e == hipSuccess) e = hipMemsetAsync(st->Sig_iw_old, 0, fo, s);
@@ -572,6 +589,28 @@ qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
   if (rc != QGW_OK) return rc;
   st->mu = m;
   *mu = m;
+  st->in_fp32 = st->prec_mode == 1;
+  st->n_fp32 = st->n_fp64 = 0;
+  st->last_dsig = INFINITY;
+  return QGW_OK;
+}
+
+qgw_status qgw_state_set_precision(qgw_state st, int32_t mode, double switch_tol) {
+  QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: null state");
+  QGW_REQUIRE(mode == 0 || mode == 1, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: mode must be 0 or 1");
+  QGW_REQUIRE(switch_tol > 0.0, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: switch_tol must be positive");
+  st->prec_mode = mode;
+  st->switch_tol = switch_tol;
+  st->in_fp32 = mode == 1;
+  st->last_dsig = INFINITY;
+  return QGW_OK;
+}
+
+qgw_status qgw_state_info(qgw_state st, int32_t* last_prec, int32_t* n_fp32, int32_t* n_fp64) {
+  QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_info: null state");
+  if (last_prec) *last_prec = st->last_prec;
+  if (n_fp32) *n_fp32 = st->n_fp32;
+  if (n_fp64) *n_fp64 = st->n_fp64;
   return QGW_OK;
 }
 
@@ -594,27 +633,53 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2, st->n_k, st->n_R, s), "a12 fft");
     QGW_CHECK_HIP(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, s), "a12 hf");
     QGW_CHECK_HIP(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, s), "a12 fft");
-    // a1, a2
-    QGW_CHECK_HIP(mark(1), "profile");
-    QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G_iw, st->G_tau, s), "a1");
-    QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s), "a1");
-    QGW_CHECK_HIP(mark(2), "profile");
-    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, s), "a2");
-    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_reflt, st->G_reflt, s), "a2");
-    // a3 + a4, a5, a6, a7
-    QGW_CHECK_HIP(mark(3), "profile");
-    QGW_CHECK_HIP(launch_bubble(p, st->G_tau, st->G_reflt, 1, st->Pq, s), "a3");
-    QGW_CHECK_HIP(mark(4), "profile");
-    QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq, st->P_nu, s), "a5");
-    QGW_CHECK_HIP(mark(5), "profile");
-    QGW_CHECK_HIP(launch_dyson_w(p, st->V_qm, st->P_nu, st->Wc_nu, s), "a6");
-    QGW_CHECK_HIP(mark(6), "profile");
-    QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc_nu, st->Pq, s), "a7");
-    // a8 + a9 + a10, a11 (Hermitian part of Sigma^C(k, tau))
-    QGW_CHECK_HIP(mark(7), "profile");
-    QGW_CHECK_HIP(launch_sigma(p, st->G_tau, st->Pq, 1, 1, st->Sig_tau_k, s), "a9");
-    QGW_CHECK_HIP(mark(8), "profile");
-    QGW_CHECK_HIP(launch_dlr(p, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->Sig_tau_k, st->Sig_iw, s, 1), "a11");
+    const bool f32 = st->prec_mode == 1 && st->in_fp32;
+    if (!f32) {
+      // a1, a2
+      QGW_CHECK_HIP(mark(1), "profile");
+      QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G_iw, st->G_tau, s), "a1");
+      QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s), "a1");
+      QGW_CHECK_HIP(mark(2), "profile");
+      QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, s), "a2");
+      QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_reflt, st->G_reflt, s), "a2");
+      // a3 + a4, a5, a6, a7
+      QGW_CHECK_HIP(mark(3), "profile");
+      QGW_CHECK_HIP(launch_bubble(p, st->G_tau, st->G_reflt, 1, st->Pq, s), "a3");
+      QGW_CHECK_HIP(mark(4), "profile");
+      QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq, st->P_nu, s), "a5");
+      QGW_CHECK_HIP(mark(5), "profile");
+      QGW_CHECK_HIP(launch_dyson_w(p, st->V_qm, st->P_nu, st->Wc_nu, s), "a6");
+      QGW_CHECK_HIP(mark(6), "profile");
+      QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc_nu, st->Pq, s), "a7");
+      // a8 + a9 + a10, a11 (Hermitian part of Sigma^C(k, tau))
+      QGW_CHECK_HIP(mark(7), "profile");
+      QGW_CHECK_HIP(launch_sigma(p, st->G_tau, st->Pq, 1, 1, st->Sig_tau_k, s), "a9");
+      QGW_CHECK_HIP(mark(8), "profile");
+      QGW_CHECK_HIP(launch_dlr(p, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->Sig_tau_k, st->Sig_iw, s, 1), "a11");
+    } else {
+      // the same steps in single precision (defect-correction phase of the solve)
+      const Plan& q = st->p32;
+      QGW_CHECK_HIP(mark(1), "profile");
+      QGW_CHECK_HIP(launch_convert(ncol_g * p.r, st->G_iw, st->G32, 1, s), "a1 f32");
+      QGW_CHECK_HIP(launch_dlr(q, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G32, st->Gt32, s), "a1 f32");
+      QGW_CHECK_HIP(launch_dlr(q, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G32, st->Gr32, s), "a1 f32");
+      QGW_CHECK_HIP(mark(2), "profile");
+      QGW_CHECK_HIP(launch_lattice_fft(q, QGW_K_TO_R, no2 * p.r, st->Gt32, st->Gt32, s), "a2 f32");
+      QGW_CHECK_HIP(launch_lattice_fft(q, QGW_K_TO_R, no2 * p.r, st->Gr32, st->Gr32, s), "a2 f32");
+      QGW_CHECK_HIP(mark(3), "profile");
+      QGW_CHECK_HIP(launch_bubble(q, st->Gt32, st->Gr32, 1, st->Pq32, s), "a3 f32");
+      QGW_CHECK_HIP(mark(4), "profile");
+      QGW_CHECK_HIP(launch_dlr_pairs(q, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq32, st->Pnu32, s), "a5 f32");
+      QGW_CHECK_HIP(mark(5), "profile");
+      QGW_CHECK_HIP(launch_dyson_w(q, st->Vqm32, st->Pnu32, st->Wc32, s), "a6 f32");
+      QGW_CHECK_HIP(mark(6), "profile");
+      QGW_CHECK_HIP(launch_dlr_pairs(q, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc32, st->Pq32, s), "a7 f32");
+      QGW_CHECK_HIP(mark(7), "profile");
+      QGW_CHECK_HIP(launch_sigma(q, st->Gt32, st->Pq32, 1, 1, st->St32, s), "a9 f32");
+      QGW_CHECK_HIP(mark(8), "profile");
+      QGW_CHECK_HIP(launch_dlr(q, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->St32, st->Siw32, s, 1), "a11 f32");
+      QGW_CHECK_HIP(launch_convert(ncol_g * p.r, st->Siw32, st->Sig_iw, 0, s), "a11 f32");
+    }
     // a14: change of the total self-energy, mixing
     QGW_CHECK_HIP(mark(9), "profile");
     QGW_CHECK_HIP(launch_delta_and_mix(p, st->SigHF_k, st->Sig_iw, st->SigHF_old, st->Sig_iw_old, st->mixing,
@@ -634,12 +699,21 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
       for (int i = 0; i < QGW_NUM_STEPS; ++i) {
         float ms = 0.0f;
         QGW_CHECK_HIP(hipEventElapsedTime(&ms, st->ev[i], st->ev[i + 1]), "profile");
-        st->prof_ms[i] += ms;
+        st->prof_ms[f32 ? 1 : 0][i] += ms;
       }
-      ++st->prof_iters;
+      ++st->prof_iters[f32 ? 1 : 0];
     }
     ++done;
-    if (dsig <= tol) break;
+    st->last_prec = f32 ? 1 : 0;
+    if (f32) {
+      ++st->n_fp32;
+      // leave the single-precision phase at its tolerance, or once it stalls
+      if (dsig <= st->switch_tol || dsig > 0.5 * st->last_dsig) st->in_fp32 = false;
+    } else {
+      ++st->n_fp64;
+    }
+    st->last_dsig = dsig;
+    if (dsig <= tol && !(st->prec_mode == 1 && f32)) break;
   }
   if (iters_done) *iters_done = done;
   if (d_sigma) *d_sigma = dsig;
@@ -678,15 +752,17 @@ qgw_status qgw_state_profile(qgw_state st, int32_t mode, double* ms, int32_t* it
   if (mode == 1) {
     for (auto& e : st->ev)
       if (!e) QGW_CHECK_HIP(hipEventCreate(&e), "qgw_state_profile");
-    for (double& v : st->prof_ms) v = 0.0;
-    st->prof_iters = 0;
+    for (auto& row : st->prof_ms)
+      for (double& v : row) v = 0.0;
+    st->prof_iters[0] = st->prof_iters[1] = 0;
     st->prof = true;
   } else if (mode == 0) {
     st->prof = false;
   }
   if (ms)
-    for (int i = 0; i < QGW_NUM_STEPS; ++i) ms[i] = st->prof_ms[i];
-  if (iters) *iters = st->prof_iters;
+    for (int k = 0; k < 2; ++k)
+      for (int i = 0; i < QGW_NUM_STEPS; ++i) ms[k * QGW_NUM_STEPS + i] = st->prof_ms[k][i];
+  if (iters) iters[0] = st->prof_iters[0], iters[1] = st->prof_iters[1];
   return QGW_OK;
 }
 

@@ -153,10 +153,185 @@ hipError_t dlr_launch(const Plan& p, int map, int64_t ncols, int na, int nq, dou
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// MFMA form for pair arrays (r <= 64): out = T in as a complex GEMM of an
+// r x r map with ~10^5-10^6 columns, done as four real products per 4-deep
+// slice on the 16x16x4 matrix cores (FP64 or FP32).  A block of 8 waves
+// keeps Re T and Im T in LDS ([16 MT][KP], zero padded); each wave computes a
+// strip of 16 columns for all rows.  Strips are ordered so that the 8 waves
+// of a block write 8 adjacent elements of every output run (128 bytes in
+// FP64), the input side reads 16 contiguous elements per 4-deep slice.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of D held in element v by lane l (column l % 16)
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+template <typename T, int MT, int MODE, bool HERM_IN>
+__global__ __launch_bounds__(512) void k_dlr_mfma(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                                  const cpx<T>* __restrict__ map, int r, int kp, int na,
+                                                  int nq, int64_t nstrips, int no, T sre, T sim) {
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  extern __shared__ unsigned char smem_raw[];
+  T* tre = reinterpret_cast<T*>(smem_raw);
+  T* tim = tre + MT * 16 * kp;
+  for (int e = threadIdx.x; e < MT * 16 * kp; e += blockDim.x) {
+    const int i = e / kp, k = e - i * kp;
+    const cpx<T> v = (i < r && k < r) ? map[int64_t(i) * r + k] : mk(T(0), T(0));
+    tre[e] = v.re;
+    tim[e] = v.im;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lc = lane & 15, lk = lane >> 4;
+  const int64_t plane = int64_t(na) * nq;
+  for (int64_t strip = int64_t(blockIdx.x) * 8 + wave; strip < nstrips; strip += int64_t(gridDim.x) * 8) {
+    int64_t cin, cout;
+    bool valid;
+    if (MODE == kSlabToMatrix) {
+      const int64_t qb = strip / na;
+      const int a = int(strip - qb * na);
+      const int q = int(qb) * 16 + lc;
+      valid = q < nq;
+      cin = int64_t(a) * nq + q;
+      cout = int64_t(q) * na + a;
+    } else if (MODE == kMatrixToSlab) {
+      const int64_t ab = strip / nq;
+      const int q = int(strip - ab * nq);
+      const int a = int(ab) * 16 + lc;
+      valid = a < na;
+      cin = int64_t(q) * na + a;
+      cout = int64_t(a) * nq + q;
+    } else {
+      cin = cout = strip * 16 + lc;
+      valid = cin < plane;
+    }
+    int64_t cswap = cin;
+    if (HERM_IN && valid) {  // orbital array: column (a n_o + b) N_k + k -> (b n_o + a) N_k + k
+      const int64_t k = cin % nq, ab = cin / nq;
+      const int a = int(ab / no), b = int(ab % no);
+      cswap = (int64_t(b) * no + a) * nq + k;
+    }
+    v4 accr[MT], acci[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      accr[mt] = v4{T(0), T(0), T(0), T(0)};
+      acci[mt] = v4{T(0), T(0), T(0), T(0)};
+    }
+    const cpx<T>* src = in + cin;
+    const cpx<T>* srcs = in + cswap;
+    auto load = [&](int t) -> cpx<T> {
+      if (!(valid && t < r)) return mk(T(0), T(0));
+      cpx<T> v = src[int64_t(t) * plane];
+      if (HERM_IN) v = scale(v + conj(srcs[int64_t(t) * plane]), T(0.5));
+      return v;
+    };
+    cpx<T> x = load(lk);
+    for (int kb = 0; kb < kp; kb += 4) {
+      const cpx<T> xn = load(kb + 4 + lk);
+      const int k = kb + lk;
+      T ar[MT], ai[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        ar[mt] = tre[(mt * 16 + lc) * kp + k];
+        ai[mt] = tim[(mt * 16 + lc) * kp + k];
+      }
+      // 2 MT independent accumulator chains per half-slice
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        accr[mt] = M::mac(ar[mt], x.re, accr[mt]);
+        acci[mt] = M::mac(ar[mt], x.im, acci[mt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        accr[mt] = M::mac(-ai[mt], x.im, accr[mt]);
+        acci[mt] = M::mac(ai[mt], x.re, acci[mt]);
+      }
+      x = xn;
+    }
+    if (valid) {
+      const cpx<T> sc = mk(sre, sim);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = mt * 16 + M::row(lane, v);
+          if (m < r) out[int64_t(m) * plane + cout] = sc * mk(accr[mt][v], acci[mt][v]);
+        }
+    }
+  }
+}
+
+// na x nq columns; HERM_IN: orbital arrays (na = n_o^2, nq = N_k)
+template <typename T, int MODE, bool HERM_IN>
+hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, double sim, const void* in,
+                           void* out, hipStream_t s) {
+  const int kp = (p.r + 3) / 4 * 4;
+  const int mt = (p.r + 15) / 16;
+  int64_t nstrips;
+  if (MODE == kSlabToMatrix)
+    nstrips = int64_t((nq + 15) / 16) * na;
+  else if (MODE == kMatrixToSlab)
+    nstrips = int64_t((na + 15) / 16) * nq;
+  else
+    nstrips = (int64_t(na) * nq + 15) / 16;
+  int dev = 0, ncu = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  int64_t blocks = (nstrips + 7) / 8;
+  if (blocks > 2 * ncu) blocks = 2 * ncu;
+  const size_t lds = size_t(2) * mt * 16 * kp * sizeof(T);
+  const cpx<T>* mp = map_ptr<T>(p, map);
+#define QGW_MFMA_MT(MTV)                                                                                 \
+  case MTV:                                                                                              \
+    hipLaunchKernelGGL((k_dlr_mfma<T, MTV, MODE, HERM_IN>), dim3(unsigned(blocks)), dim3(512), lds, s,  \
+                       (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, nstrips, p.no, T(sre),     \
+                       T(sim));                                                                         \
+    break;
+  switch (mt) {
+    QGW_MFMA_MT(1)
+    QGW_MFMA_MT(2)
+    QGW_MFMA_MT(3)
+    QGW_MFMA_MT(4)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef QGW_MFMA_MT
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double sim, const void* in,
                       void* out, hipStream_t s, int herm) {
+  const int64_t ng = int64_t(p.no) * p.no * p.nk;
+  if (p.r <= 64 && map != 5 && herm != 2 && (herm == 0 || ncols == ng)) {
+    const int na = herm ? p.no * p.no : 1;
+    const int nq = herm ? p.nk : int(ncols);
+    if (herm == 0 && ncols > (int64_t(1) << 30)) return hipErrorInvalidValue;
+    if (p.prec == 0) {
+      if (herm) return dlr_mfma_launch<double, kPlain, true>(p, map, na, nq, sre, sim, in, out, s);
+      return dlr_mfma_launch<double, kPlain, false>(p, map, na, nq, sre, sim, in, out, s);
+    }
+    if (herm) return dlr_mfma_launch<float, kPlain, true>(p, map, na, nq, sre, sim, in, out, s);
+    return dlr_mfma_launch<float, kPlain, false>(p, map, na, nq, sre, sim, in, out, s);
+  }
   if (herm) {
     if (ncols != int64_t(p.no) * p.no * p.nk) return hipErrorInvalidValue;
     if (p.prec == 0) {
@@ -177,6 +352,16 @@ hipError_t launch_dlr_pairs(const Plan& p, int map, int in_layout, int out_layou
   int mode = kPlain;
   if (in_layout == 0 && out_layout == 1) mode = kSlabToMatrix;
   if (in_layout == 1 && out_layout == 0) mode = kMatrixToSlab;
+  if (p.r <= 64) {  // matrix-core path
+    if (p.prec == 0) {
+      if (mode == kPlain) return dlr_mfma_launch<double, kPlain, false>(p, map, na, nq, 1, 0, in, out, s);
+      if (mode == kSlabToMatrix) return dlr_mfma_launch<double, kSlabToMatrix, false>(p, map, na, nq, 1, 0, in, out, s);
+      return dlr_mfma_launch<double, kMatrixToSlab, false>(p, map, na, nq, 1, 0, in, out, s);
+    }
+    if (mode == kPlain) return dlr_mfma_launch<float, kPlain, false>(p, map, na, nq, 1, 0, in, out, s);
+    if (mode == kSlabToMatrix) return dlr_mfma_launch<float, kSlabToMatrix, false>(p, map, na, nq, 1, 0, in, out, s);
+    return dlr_mfma_launch<float, kMatrixToSlab, false>(p, map, na, nq, 1, 0, in, out, s);
+  }
   if (p.prec == 0) {
     if (mode == kPlain) return dlr_launch<double, kPlain, 0>(p, map, ncols, na, nq, 1, 0, in, out, s);
     if (mode == kSlabToMatrix) return dlr_launch<double, kSlabToMatrix, 0>(p, map, ncols, na, nq, 1, 0, in, out, s);

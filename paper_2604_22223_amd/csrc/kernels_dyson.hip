@@ -73,37 +73,41 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
   for (int e = lane; e < S::MPW * S::NN; e += 64) sp[e] = e < nload ? pnu[mat0 * S::NN + e] : mk(T(0), T(0));
   __syncthreads();
   const cpx<T>* vrow = vq + (int64_t(q) * NB + (row < NB ? row : 0)) * NB;
-  const cpx<T>* pm = sp + mw * S::NN;
-  // I - V P: half h forms columns [h * SPLIT, h * SPLIT + SPLIT) of its row
-  cpx<T> y[S::SPLIT];
-  const int coff = half * S::SPLIT;
+  cpx<T>* pm = sp + mw * S::NN;
+  // I - V P, formed in place of P: in round g, half h forms columns
+  // [8 g + 4 h, 8 g + 4 h + 4) of its row; once every lane has read those
+  // columns of P they are overwritten by the columns of I - V P.
+  constexpr int CW = 4;
 #pragma unroll
-  for (int c = 0; c < S::SPLIT; ++c) y[c] = mk(T(row == c + coff ? 1 : 0), T(0));
-  if (valid) {
+  for (int g = 0; g < (NB + 2 * CW - 1) / (2 * CW); ++g) {
+    const int c0 = (2 * g + half) * CW;
+    cpx<T> acc[CW];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const cpx<T> v = vrow[j];
+    for (int c = 0; c < CW; ++c) acc[c] = mk(T(row == c0 + c ? 1 : 0), T(0));
+    if (valid && c0 < NB) {
 #pragma unroll
-      for (int c = 0; c < S::SPLIT; ++c) {
-        const int col = c + coff < NB ? c + coff : NB - 1;
-        y[c] = fms(y[c], v, pm[j * NB + col]);
+      for (int j = 0; j < NB; ++j) {
+        const cpx<T> v = vrow[j];
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+          const int col = c0 + c < NB ? c0 + c : NB - 1;
+          acc[c] = fms(acc[c], v, pm[j * NB + col]);
+        }
       }
     }
-  }
-  __syncthreads();  // P no longer needed: reuse its LDS for the hand-over
-  cpx<T>* xch = sp + mw * S::NN;
-  if (valid && half == 1) {
+    __syncthreads();
+    if (valid) {
 #pragma unroll
-    for (int c = 0; c < NB - S::SPLIT; ++c) xch[row * S::SPLIT + c] = y[c];
+      for (int c = 0; c < CW; ++c)
+        if (c0 + c < NB) pm[row * NB + c0 + c] = acc[c];
+    }
   }
   __syncthreads();
   cpx<T> x[NB];
   if (valid) {
     if (half == 0) {
 #pragma unroll
-      for (int c = 0; c < S::SPLIT; ++c) x[c] = y[c];
-#pragma unroll
-      for (int c = S::SPLIT; c < NB; ++c) x[c] = xch[row * S::SPLIT + c - S::SPLIT];
+      for (int c = 0; c < NB; ++c) x[c] = pm[row * NB + c];
     } else {
 #pragma unroll
       for (int c = 0; c < NB; ++c) x[c] = vrow[c];

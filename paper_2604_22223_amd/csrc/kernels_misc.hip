@@ -113,7 +113,26 @@ __global__ void k_count_nonfinite(const cpx<T>* __restrict__ x, int64_t n, int* 
   if (!isfinite(v.re) || !isfinite(v.im)) atomicAdd(count, 1);
 }
 
+// precision changes of complex arrays (round to nearest)
+__global__ void k_to_f32(const zd* __restrict__ in, zf* __restrict__ out, int64_t n) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi < n) out[gi] = cast<float>(in[gi]);
+}
+__global__ void k_to_f64(const zf* __restrict__ in, zd* __restrict__ out, int64_t n) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi < n) out[gi] = cast<double>(in[gi]);
+}
+
 static unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+hipError_t launch_convert(int64_t count, const void* in, void* out, int to_f32, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (to_f32)
+    hipLaunchKernelGGL(k_to_f32, dim3(nblk(count, 256)), dim3(256), 0, s, (const zd*)in, (zf*)out, count);
+  else
+    hipLaunchKernelGGL(k_to_f64, dim3(nblk(count, 256)), dim3(256), 0, s, (const zf*)in, (zd*)out, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_hartree_fock(const Plan& p, const void* v_r, const void* v_q0, const void* n_r,
                                void* sig_hf_r, hipStream_t s) {

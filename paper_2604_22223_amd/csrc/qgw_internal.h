@@ -90,6 +90,8 @@ hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b
 hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* hf_old,
                                 void* c_old, double alpha, double* d_out, double* block_scratch,
                                 hipStream_t s);
+// complex128 <-> complex64 copies (to_f32 = 1: double -> float)
+hipError_t launch_convert(int64_t count, const void* in, void* out, int to_f32, hipStream_t s);
 hipError_t launch_count_nonfinite(const Plan& p, const void* x, int64_t count, int* d_count,
                                   hipStream_t s);
 

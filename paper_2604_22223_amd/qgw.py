@@ -28,7 +28,8 @@ R_TO_K, K_TO_R = -1, +1
 EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get_map", "qgw_plan_sizes",
            "qgw_dlr_transform", "qgw_dlr_transform_pairs", "qgw_lattice_fft", "qgw_bubble", "qgw_dyson_W",
            "qgw_sigma", "qgw_hartree_fock", "qgw_dyson_G", "qgw_state_create", "qgw_state_destroy",
-           "qgw_state_init_g0", "qgw_gw_iteration", "qgw_state_copy", "qgw_state_profile", "qgw_check_finite",
+           "qgw_state_init_g0", "qgw_gw_iteration", "qgw_state_copy", "qgw_state_profile",
+           "qgw_state_set_precision", "qgw_state_info", "qgw_check_finite",
            "qgw_last_error"]
 
 
@@ -83,6 +84,8 @@ def lib():
             "qgw_gw_iteration": [vp, i32, dbl, pi32, pd, pd, vp],
             "qgw_state_copy": [vp, i32, vp, pi64, vp],
             "qgw_state_profile": [vp, i32, pd, pi32],
+            "qgw_state_set_precision": [vp, i32, dbl],
+            "qgw_state_info": [vp, pi32, pi32, pi32],
             "qgw_check_finite": [vp, vp, i64, vp],
         }
         for name, args in sig.items():
@@ -256,13 +259,30 @@ class State:
     STEP_NAMES = ["a12_density_hf", "a1_dlr_g", "a2_fft_g", "a3a4_bubble", "a5_dlr_p", "a6_dyson_w",
                   "a7_dlr_w", "a8a9a10_sigma", "a11_dlr_sigma", "a14_delta_mix", "a13_dyson_g"]
 
-    def profile(self, mode=2):
-        """mode 1: reset + enable, 0: disable, 2: read.  Returns (ms per step dict, iterations)."""
-        ms = np.zeros(len(self.STEP_NAMES))
-        it = ctypes.c_int32(0)
-        _check(lib().qgw_state_profile(self.handle, int(mode), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                       ctypes.byref(it)))
-        return dict(zip(self.STEP_NAMES, ms.tolist())), it.value
+    def profile(self, mode=2, per_precision=False):
+        """mode 1: reset + enable, 0: disable, 2: read.
+
+        Returns (ms per step dict, iterations) summed over both precisions, or
+        with per_precision a dict {"f64": (ms dict, iters), "f32": (ms dict, iters)}."""
+        ns = len(self.STEP_NAMES)
+        ms = np.zeros(2 * ns)
+        it = (ctypes.c_int32 * 2)()
+        _check(lib().qgw_state_profile(self.handle, int(mode), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), it))
+        rows = {"f64": (dict(zip(self.STEP_NAMES, ms[:ns].tolist())), it[0]),
+                "f32": (dict(zip(self.STEP_NAMES, ms[ns:].tolist())), it[1])}
+        if per_precision:
+            return rows
+        return dict(zip(self.STEP_NAMES, (ms[:ns] + ms[ns:]).tolist())), it[0] + it[1]
+
+    def set_precision(self, mode, switch_tol=1e-4):
+        """mode 0: FP64 throughout; 1: FP32 bulk steps until |dSigma| <= switch_tol, then FP64."""
+        _check(lib().qgw_state_set_precision(self.handle, int(mode), float(switch_tol)))
+
+    def info(self):
+        """(precision of the last iteration, FP32 iterations, FP64 iterations)."""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qgw_state_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def array(self, which):
         """Copy of a state array as a torch tensor (0 G, 1 Sigma_C, 2 Sigma_HF, 3 P, 4 W^C)."""

@@ -1,0 +1,132 @@
+"""Single precision steps and the mixed-precision solve against the oracle.
+
+The FP32 maps get an a-priori error bound: rounding the FP64 map and the
+input to FP32 and accumulating r complex products costs at most about
+(r + 4) u (|T| |x|)_i per output element (u = 2^-24, a factor 2 for complex
+arithmetic).  The mixed solve (FP32 bulk steps while max |Delta Sigma| is
+large, FP64 to finish) must land on the oracle's FP64 fixed point to within
+the solve's tolerance: |Sigma_mixed - Sigma_oracle| <= 1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import gw
+from oracle.dlr import DLR
+from paper_2604_22223_amd import qgw
+from paper_2604_22223_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def flat(x):
+    return np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))
+
+
+@pytest.fixture(scope="module")
+def five8():
+    """Five orbitals on an 8 x 8 mesh, beta = 20, converged by the oracle to 1e-10."""
+    print("\n[mixed case] five_orbital_8x8", flush=True)
+    w = wl.five_orbital(n=8, U=1.0, J=0.1, Vnn=0.2, beta=20.0, omega_max=25.0, eps=1e-10, scale_mesh=8)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
+    st0 = gw.initial_state(m, d)
+    conv, hist = gw.scf(m, d, tol=1e-10, max_iter=40, state=st0)
+    assert hist[-1][0] <= 1e-10
+    return {"w": w, "d": d, "m": m, "st0": st0, "conv": conv}
+
+
+@pytest.mark.parametrize("which,attr", [(qgw.F_IW2TAU, "F_iw2tau"), (qgw.F_IW2TAUR, "F_iw2taur"),
+                                        (qgw.F_TAU2IW, "F_tau2iw"), (qgw.B_TAU2IW, "B_tau2iw"),
+                                        (qgw.B_IW2TAU, "B_iw2tau")])
+def test_fp32_maps_within_rounding_bound(five8, which, attr):
+    torch = _torch()
+    d = five8["d"]
+    T = getattr(d, attr)
+    rng = np.random.default_rng(7)
+    ncols = 3 * 1000 + 17                     # several column tiles and a ragged tail
+    x = (rng.standard_normal((d.r, ncols)) + 1j * rng.standard_normal((d.r, ncols))).astype(np.complex64)
+    x64 = x.astype(np.complex128)
+    p32 = qgw.Plan.from_nodes(8, [5], d.beta, d.nodes(), precision=qgw.F32)
+    xin = torch.from_numpy(x).to("cuda:0")
+    out = torch.empty((T.shape[0], ncols), dtype=torch.complex64, device="cuda:0")
+    p32.dlr_transform(which, xin, out)
+    ref = T @ x64
+    bound = 2.0 * (d.r + 4) * U32 * (np.abs(T) @ np.abs(x64))
+    err = np.abs(out.cpu().numpy().astype(np.complex128) - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    p32.close()
+
+
+def _run(plan, m, mode, tol, max_iter=40):
+    torch = _torch()
+    st = qgw.State(plan, torch.from_numpy(flat(m.H_R)).to("cuda:0"), torch.from_numpy(flat(m.V_R)).to("cuda:0"),
+                   n_target=m.n_target)
+    st.set_precision(mode, 1e-4)
+    st.init_g0()
+    hist = []
+    for _ in range(max_iter):
+        done, dsig, mu = st.iterate(1)
+        prec = st.info()[0]
+        hist.append((dsig, prec))
+        if dsig <= tol and prec == 0:
+            break
+    return st, hist, mu
+
+
+def test_mixed_solve_reaches_oracle_fixed_point(five8):
+    m, d, conv = five8["m"], five8["d"], five8["conv"]
+    plan = qgw.Plan.from_nodes(8, [5], d.beta, d.nodes())
+    st, hist, mu = _run(plan, m, 1, 1e-9)
+    last_prec, n32, n64 = st.info()
+    print("[mixed] history", ["%.1e/%d" % h for h in hist], flush=True)
+    assert last_prec == 0 and n32 >= 2 and n64 >= 1
+    assert n32 + n64 == len(hist)
+    assert hist[-1][0] <= 1e-9
+    # the FP32 phase is a defect-correction start: the converged point is FP64
+    assert np.max(np.abs(st.array(1).cpu().numpy() - flat(conv["sig_iw"]))) <= 1e-6
+    assert np.max(np.abs(st.array(2).cpu().numpy() - flat(conv["sig_hf_k"]))) <= 1e-6
+    assert np.max(np.abs(st.array(0).cpu().numpy() - flat(conv["G_iw"]))) <= 1e-6
+    assert abs(mu - conv["mu"]) <= 1e-7
+    st.close()
+    plan.close()
+
+
+def test_mixed_and_fp64_solves_agree(five8):
+    """Both schedules reach the same fixed point; the FP32 phase only changes the start."""
+    m, d = five8["m"], five8["d"]
+    plan = qgw.Plan.from_nodes(8, [5], d.beta, d.nodes())
+    st64, h64, mu64 = _run(plan, m, 0, 1e-9)
+    st32, h32, mu32 = _run(plan, m, 1, 1e-9)
+    assert st64.info()[1] == 0 and all(p == 0 for _, p in h64)
+    a = st64.array(1).cpu().numpy()
+    b = st32.array(1).cpu().numpy()
+    assert np.max(np.abs(a - b)) <= 1e-6
+    assert abs(mu64 - mu32) <= 1e-7
+    st64.close()
+    st32.close()
+    plan.close()
+
+
+def test_first_fp32_iteration_tracks_oracle(five8):
+    """One FP32 iteration from G0 against the oracle's FP64 iteration."""
+    m, d, st0 = five8["m"], five8["d"], five8["st0"]
+    ref = gw.gw_iteration(m, d, st0)
+    plan = qgw.Plan.from_nodes(8, [5], d.beta, d.nodes())
+    st, hist, mu = _run(plan, m, 1, 0.0, max_iter=1)
+    assert hist[0][1] == 1
+    sig = st.array(1).cpu().numpy()
+    scale = np.max(np.abs(ref["sig_iw"]))
+    rel = np.max(np.abs(sig - flat(ref["sig_iw"]))) / scale
+    print("[mixed] first FP32 iteration: rel err of Sigma^C %.2e" % rel, flush=True)
+    assert rel <= 2e-4
+    assert abs(mu - ref["mu"]) <= 1e-4 * max(1.0, abs(ref["mu"]))
+    st.close()
+    plan.close()
