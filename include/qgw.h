@@ -36,7 +36,9 @@
  * Streams.  ``stream`` is a hipStream_t passed as void* (NULL = the default
  * stream).  Compute calls only enqueue work, allocate nothing and return
  * once the work is queued, except qgw_dyson_G, which also returns the
- * chemical potential on the host and therefore waits for its stream.
+ * chemical potential on the host and therefore waits for its stream, and
+ * the adjoint calls marked "workspace", which allocate a plan-owned buffer
+ * on their first use.
  */
 #ifndef QGW_H
 #define QGW_H
@@ -201,6 +203,96 @@ qgw_status qgw_hartree_fock(qgw_plan plan, const void *V_R, const void *n_R,
  * 200 evaluations. */
 qgw_status qgw_dyson_G(qgw_plan plan, const void *H_k, const void *Sig_iw,
                        double n_target, double *mu, void *G_iw, void *stream);
+
+/* ------------------------------------------------------------- adjoints
+ *
+ * Reverse-mode derivatives of the step calls (FP64 plans only; FP32 plans
+ * return QGW_ERR_UNSUPPORTED).  For a real loss L the cotangent of a complex
+ * array z is zbar = dL/dRe z + i dL/dIm z (the convention of PyTorch's
+ * complex autograd), so a complex-linear y = A x has xbar = A^H ybar.  Every
+ * call overwrites its outputs (callers add branches themselves); shapes and
+ * layouts are those of the forward call.  Calls marked "workspace" use a
+ * plan-owned device buffer that is allocated, or grown, on the first call
+ * that needs it: such calls are not graph-capturable the first time, and
+ * calls on one plan from several streams at once race on it. */
+
+/* a15: adjoint of qgw_dlr_transform with the same map, ncols, scale and
+ * hermitian mode: xbar = herm_in(conj(scale) T^H herm_out(ybar)).  For
+ * QGW_F_IW2BETA ybar has ncols entries and xbar r x ncols. */
+qgw_status qgw_dlr_transform_bwd(qgw_plan plan, int32_t map, int64_t ncols,
+                                 double scale_re, double scale_im, int32_t hermitian,
+                                 const void *ybar, void *xbar, void *stream);
+
+/* a15: adjoint of qgw_dlr_transform_pairs (same map and layouts): ybar is
+ * in out_layout, xbar in in_layout. */
+qgw_status qgw_dlr_transform_pairs_bwd(qgw_plan plan, int32_t map,
+                                       int32_t in_layout, int32_t out_layout,
+                                       const void *ybar, void *xbar, void *stream);
+
+/* a16: adjoint of qgw_lattice_fft in direction dir: for QGW_K_TO_R,
+ * xbar(k) = (1/N_k) sum_R ybar(R) e^{-ik.R}; for QGW_R_TO_K,
+ * xbar(R) = sum_k ybar(k) e^{+ik.R}.  ybar == xbar allowed. */
+qgw_status qgw_lattice_fft_bwd(qgw_plan plan, int32_t dir, int64_t batch,
+                               const void *ybar, void *xbar, void *stream);
+
+/* a17: adjoint of qgw_bubble with out_q = 1 (Eq. eq-polarizability):
+ *   Gbar_lj(R, tau)         = -2 sum_{ik} conj(G_ki(-R, beta - tau)) Pbar_{(il),(jk)}(R, tau)
+ *   Gbar_ki(-R, beta - tau) = -2 sum_{lj} conj(G_lj(R, tau)) Pbar_{(il),(jk)}(R, tau)
+ * with Pbar(R) = sum_q e^{iq.R} Pbar(q).  Pbar_q: pair slab in q; outputs:
+ * orbital layout in R, written whole. */
+qgw_status qgw_bubble_bwd(qgw_plan plan, const void *G_tau_R, const void *G_reflt_R,
+                          const void *Pbar_q, void *Gbar_tau_R, void *Gbar_reflt_R,
+                          void *stream);
+
+/* a19: adjoint of qgw_sigma with in_q = 1 and the given out_k (Eq.
+ * eq-gw-self-energy):
+ *   Wcbar_{(il),(jk)}(R) = -conj(G_lj(R)) Sbar_ik(R),  then to q
+ *   Gbar_lj(R)          = -sum_{ik} conj(W^C_{(il),(jk)}(R)) Sbar_ik(R)
+ * Sigbar in k (out_k = 1) or R; Wc_q and Wcbar_q pair slabs in q; Gbar_tau_R
+ * orbital layout in R.  Workspace (r n_o^2 N_k complex) when out_k = 1. */
+qgw_status qgw_sigma_bwd(qgw_plan plan, const void *G_tau_R, const void *Wc_q,
+                         int32_t out_k, const void *Sigbar, void *Gbar_tau_R,
+                         void *Wcbar_q, void *stream);
+
+/* a18: adjoint of qgw_dyson_W (Eq. eq-screened-coulomb).  With A = I - V P,
+ * W = A^{-1} V and Wbar the cotangent of W^C = W - V:
+ *   Pbar = W^H Wbar W^H,   Vbar = sum over nodes [A^{-H} Wbar (I + P W)^H - Wbar].
+ * V_q, Vbar_q: [N_k][N_b][N_b]; P_nu, Wcbar_nu, Pbar_nu: pair matrix
+ * layout.  The node sum runs in a fixed order (deterministic).  Workspace
+ * (min(r, 8) N_b^2 N_k complex). */
+qgw_status qgw_dyson_W_bwd(qgw_plan plan, const void *V_q, const void *P_nu,
+                           const void *Wcbar_nu, void *Pbar_nu, void *Vbar_q,
+                           void *stream);
+
+/* a12 adjoint: cotangents of n(R) and V(R) for a cotangent Sbar_R of the
+ * Hartree-Fock self-energy (Eqs. eq-hartree-self-energy,
+ * eq-fock-self-energy).  Either output may be NULL.  Workspace (N_b^2). */
+qgw_status qgw_hartree_fock_bwd(qgw_plan plan, const void *V_R, const void *n_R,
+                                const void *Sbar_R, void *nbar_R, void *Vbar_R,
+                                void *stream);
+
+/* a20: adjoint of qgw_dyson_G at the chemical potential mu it returned.
+ * With X = H + Sigma: Sigbar = G^H Gbar G^H at every (node, k).  If
+ * n_target is finite mu moves with X (N_e(mu, X) = n_target), which adds
+ * c conj(rho_m) (G^2)^H with c = 2/N_k (mubar - Re sum tr(G^H Gbar G^H)) /
+ * (dN_e/dmu); mubar is the cotangent of the returned mu.  If n_target is
+ * NaN mu is held fixed and mubar is ignored.  Sigbar: orbital layout
+ * (r n_o^2 N_k); Hbar (may be NULL) = sum over nodes of Sigbar, static
+ * orbital layout.  Sig_iw may be NULL (Sigma = 0). */
+qgw_status qgw_dyson_G_bwd(qgw_plan plan, const void *H_k, const void *Sig_iw,
+                           double mu, double n_target, double mubar,
+                           const void *Gbar, void *Sigbar, void *Hbar, void *stream);
+
+/* Layout change of ``nn`` pair arrays between QGW_LAYOUT_SLAB
+ * [nn][N_b][N_b][N_k] and QGW_LAYOUT_MATRIX [nn][N_k][N_b][N_b] (a
+ * permutation; its adjoint is the opposite change).  FP64 plans. */
+qgw_status qgw_pair_layout(qgw_plan plan, int32_t in_layout, int32_t out_layout,
+                           int64_t nn, const void *in, void *out, void *stream);
+
+/* out = a + b over ``count`` complex FP64 entries (the static H0(k) +
+ * Sigma_HF(k) of the Dyson equation for G); out may alias a or b. */
+qgw_status qgw_add(qgw_plan plan, int64_t count, const void *a, const void *b,
+                   void *out, void *stream);
 
 /* ------------------------------------------------------- whole iteration */
 

@@ -228,3 +228,30 @@ def one_iteration_grad(model, dlr, cot):
     c = iteration_vjp(model, dlr, st0, out, cot)
     hbar_k = c["H_k"] + g0_vjp(model, dlr, st0, c["G_iw"])
     return out, {"H_R": k_from_R_adj(hbar_k), "V_R": c["V_R"]}
+
+
+def n_iteration_grad(model, dlr, cot, n_iter):
+    """Gradient of L(state after n GW iterations from G0) with respect to H0(R) and V(R).
+
+    The forward keeps every iteration's input state (the checkpoints); the
+    backward runs the iterations' adjoints in reverse, passing the incoming-G
+    cotangent of one iteration to the G output of the one before, and adds
+    up the H and V cotangents of all of them and of G0.
+    """
+    from . import gw
+    states = [gw.initial_state(model, dlr)]
+    outs = []
+    for _ in range(n_iter):
+        o = gw.gw_iteration(model, dlr, states[-1], keep=True)
+        outs.append(o)
+        states.append(o)
+    hbar_k = np.zeros_like(model.H_k)
+    vbar_r = np.zeros_like(model.V_R)
+    c = dict(cot)
+    for it in range(n_iter - 1, -1, -1):
+        res = iteration_vjp(model, dlr, states[it], outs[it], c)
+        hbar_k = hbar_k + res["H_k"]
+        vbar_r = vbar_r + res["V_R"]
+        c = {"G_iw": res["G_iw"]}
+    hbar_k = hbar_k + g0_vjp(model, dlr, states[0], c["G_iw"])
+    return outs[-1], {"H_R": k_from_R_adj(hbar_k), "V_R": vbar_r}

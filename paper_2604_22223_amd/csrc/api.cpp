@@ -96,19 +96,22 @@ static bool nb_supported(int nb) {
 static size_t csize(const Plan& p) { return p.prec == 0 ? 16 : 8; }
 
 static void free_plan_device(Plan& p) {
-  for (int m = 0; m < kNumMaps; ++m) {
+  for (int m = 0; m < kNumDevMaps; ++m) {
     if (p.dmaps64.m[m]) (void)hipFree(p.dmaps64.m[m]);
     if (p.dmaps32.m[m]) (void)hipFree(p.dmaps32.m[m]);
     p.dmaps64.m[m] = p.dmaps32.m[m] = nullptr;
   }
-  void* ptrs[] = {p.d_tw64, p.d_tw32, p.d_pairs, p.terms.d_terms, p.terms.d_off,
-                  p.d_wn, p.d_partials, p.d_status, p.d_scalars};
+  void* ptrs[] = {p.d_tw64, p.d_tw32, p.d_pairs, p.terms.d_terms, p.terms.d_off, p.terms_lj.d_terms,
+                  p.terms_lj.d_off, p.d_wn, p.d_partials, p.d_status, p.d_scalars, p.d_ws};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   p.d_tw64 = nullptr;
   p.d_tw32 = nullptr;
   p.d_pairs = nullptr;
   p.terms.d_terms = p.terms.d_off = nullptr;
+  p.terms_lj.d_terms = p.terms_lj.d_off = nullptr;
+  p.d_ws = nullptr;
+  p.ws_bytes = 0;
   p.d_wn = nullptr;
   p.d_partials = nullptr;
   p.d_status = nullptr;
@@ -241,6 +244,27 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
       if (cnt > max_terms) max_terms = cnt;
     }
   p.terms.max_terms = max_terms;
+  // the same terms keyed by (l, j) = (second(alpha), first(beta)), entries (alpha, beta, i, k)
+  std::vector<int> terms_lj, toff_lj(size_t(no) * no + 1, 0);
+  int max_lj = 0;
+  for (int l = 0; l < no; ++l)
+    for (int j = 0; j < no; ++j) {
+      int cnt = 0;
+      for (int a = 0; a < nb; ++a) {
+        if (p.pair_second[a] != l) continue;
+        for (int b = 0; b < nb; ++b) {
+          if (p.pair_first[b] != j) continue;
+          terms_lj.push_back(a);
+          terms_lj.push_back(b);
+          terms_lj.push_back(p.pair_first[a]);
+          terms_lj.push_back(p.pair_second[b]);
+          ++cnt;
+        }
+      }
+      toff_lj[size_t(l) * no + j + 1] = toff_lj[size_t(l) * no + j] + cnt;
+      if (cnt > max_lj) max_lj = cnt;
+    }
+  p.terms_lj.max_terms = max_lj;
   // DLR maps (FP64, host)
   std::string err;
   if (!dlr_maps_host(p.beta, p.omega, p.tau_t, p.n_f, p.n_b, p.maps, err)) {
@@ -280,6 +304,16 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
       e = upload(&p.dmaps64.m[m], h64.data(), h64.size() * sizeof(zd));
       if (e == hipSuccess) e = upload(&p.dmaps32.m[m], h32.data(), h32.size() * sizeof(zf));
     }
+    // adjoint maps T^H of the square maps (FP64 only: the adjoint calls run in FP64)
+    for (int m = 0; m < 5 && e == hipSuccess; ++m) {
+      std::vector<zd> h64(size_t(rp) * p.r, mk(0.0, 0.0));
+      for (int i = 0; i < p.r; ++i)
+        for (int j = 0; j < p.r; ++j) {
+          const std::complex<double> v = std::conj(p.maps[m][size_t(j) * p.r + i]);
+          h64[size_t(i) * p.r + j] = mk(v.real(), v.imag());
+        }
+      e = upload(&p.dmaps64.m[kAdjMap0 + m], h64.data(), h64.size() * sizeof(zd));
+    }
   }
   if (e == hipSuccess) {
     std::vector<zd> t64(p.n);
@@ -303,6 +337,8 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
   }
   if (e == hipSuccess) e = upload((void**)&p.terms.d_terms, terms.data(), terms.size() * sizeof(int));
   if (e == hipSuccess) e = upload((void**)&p.terms.d_off, toff.data(), toff.size() * sizeof(int));
+  if (e == hipSuccess) e = upload((void**)&p.terms_lj.d_terms, terms_lj.data(), terms_lj.size() * sizeof(int));
+  if (e == hipSuccess) e = upload((void**)&p.terms_lj.d_off, toff_lj.data(), toff_lj.size() * sizeof(int));
   if (e == hipSuccess) {
     std::vector<double> wn(p.r);
     for (int m = 0; m < p.r; ++m) wn[m] = (2.0 * double(p.n_f[m]) + 1.0) * 3.14159265358979323846 / p.beta;
@@ -474,6 +510,168 @@ qgw_status qgw_dyson_G(qgw_plan h, const void* H_k, const void* Sig_iw, double n
   else
     QGW_REQUIRE(std::isfinite(*mu), QGW_ERR_INVALID_ARG, "qgw_dyson_G: fixed mu must be finite");
   return run_dyson_g(p, H_k, Sig_iw, n_target, mu, G_iw, (hipStream_t)stream, nullptr);
+}
+
+// ------------------------------------------------------------------ adjoints
+
+static hipError_t ensure_ws(Plan& p, size_t bytes) {
+  if (p.ws_bytes >= bytes) return hipSuccess;
+  if (p.d_ws) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    (void)hipFree(p.d_ws);
+    p.d_ws = nullptr;
+    p.ws_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&p.d_ws, bytes);
+  if (e == hipSuccess) p.ws_bytes = bytes;
+  return e;
+}
+
+#define QGW_BWD_PLAN(h, name)                                                                        \
+  QGW_PLAN(h, name);                                                                                 \
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, std::string(name) + ": adjoints need an FP64 plan")
+
+qgw_status qgw_dlr_transform_bwd(qgw_plan h, int32_t map, int64_t ncols, double sre, double sim,
+                                 int32_t hermitian, const void* ybar, void* xbar, void* stream) {
+  QGW_BWD_PLAN(h, "qgw_dlr_transform_bwd");
+  QGW_REQUIRE(map >= 0 && map < kNumMaps, QGW_ERR_INVALID_ARG, "qgw_dlr_transform_bwd: bad map");
+  QGW_REQUIRE(ncols >= 0, QGW_ERR_INVALID_ARG, "qgw_dlr_transform_bwd: negative ncols");
+  if (ncols == 0) return QGW_OK;
+  QGW_REQUIRE(ybar && xbar && ybar != xbar, QGW_ERR_INVALID_ARG, "qgw_dlr_transform_bwd: need distinct arrays");
+  QGW_REQUIRE(hermitian >= 0 && hermitian <= 2, QGW_ERR_INVALID_ARG, "qgw_dlr_transform_bwd: bad hermitian mode");
+  QGW_REQUIRE(hermitian == 0 || ncols == int64_t(p.no) * p.no * p.nk, QGW_ERR_SHAPE,
+              "qgw_dlr_transform_bwd: the Hermitian modes need ncols = n_o^2 N_k");
+  hipStream_t s = (hipStream_t)stream;
+  if (map == QGW_F_IW2BETA) {
+    QGW_CHECK_HIP(launch_row_map_bwd(p, ncols, sre, sim, hermitian, ybar, xbar, s), "qgw_dlr_transform_bwd");
+    return QGW_OK;
+  }
+  // y = herm_out(s T herm_in(x)): xbar = herm_in(conj(s) T^H herm_out(ybar))
+  const int hb = hermitian == 1 ? 2 : (hermitian == 2 ? 1 : 0);
+  QGW_CHECK_HIP(launch_dlr(p, kAdjMap0 + map, ncols, sre, -sim, ybar, xbar, s, hb), "qgw_dlr_transform_bwd");
+  return QGW_OK;
+}
+
+qgw_status qgw_dlr_transform_pairs_bwd(qgw_plan h, int32_t map, int32_t in_layout, int32_t out_layout,
+                                       const void* ybar, void* xbar, void* stream) {
+  QGW_BWD_PLAN(h, "qgw_dlr_transform_pairs_bwd");
+  QGW_REQUIRE(map >= 0 && map < 5, QGW_ERR_INVALID_ARG, "qgw_dlr_transform_pairs_bwd: bad map");
+  QGW_REQUIRE((in_layout == 0 || in_layout == 1) && (out_layout == 0 || out_layout == 1), QGW_ERR_INVALID_ARG,
+              "qgw_dlr_transform_pairs_bwd: bad layout");
+  QGW_REQUIRE(ybar && xbar && ybar != xbar, QGW_ERR_INVALID_ARG, "qgw_dlr_transform_pairs_bwd: need distinct arrays");
+  QGW_CHECK_HIP(launch_dlr_pairs(p, kAdjMap0 + map, out_layout, in_layout, ybar, xbar, (hipStream_t)stream),
+                "qgw_dlr_transform_pairs_bwd");
+  return QGW_OK;
+}
+
+qgw_status qgw_lattice_fft_bwd(qgw_plan h, int32_t dir, int64_t batch, const void* ybar, void* xbar,
+                               void* stream) {
+  QGW_BWD_PLAN(h, "qgw_lattice_fft_bwd");
+  QGW_REQUIRE(dir == QGW_R_TO_K || dir == QGW_K_TO_R, QGW_ERR_INVALID_ARG, "qgw_lattice_fft_bwd: bad direction");
+  QGW_REQUIRE(batch >= 0, QGW_ERR_INVALID_ARG, "qgw_lattice_fft_bwd: negative batch");
+  if (batch == 0) return QGW_OK;
+  QGW_REQUIRE(ybar && xbar, QGW_ERR_INVALID_ARG, "qgw_lattice_fft_bwd: null array");
+  // adjoint of k -> R (1/N_k, e^{+ik.R}) is e^{-ik.R} with 1/N_k; of R -> k it is e^{+ik.R} unscaled
+  const int sign = dir == QGW_K_TO_R ? -1 : +1;
+  const double sc = dir == QGW_K_TO_R ? 1.0 / double(p.nk) : 1.0;
+  QGW_CHECK_HIP(launch_lattice_fft_scaled(p, sign, sc, batch, ybar, xbar, (hipStream_t)stream),
+                "qgw_lattice_fft_bwd");
+  return QGW_OK;
+}
+
+qgw_status qgw_bubble_bwd(qgw_plan h, const void* gt, const void* gr, const void* Pbar_q, void* Gbar_tau,
+                          void* Gbar_reflt, void* stream) {
+  QGW_BWD_PLAN(h, "qgw_bubble_bwd");
+  QGW_REQUIRE(gt && gr && Pbar_q && Gbar_tau && Gbar_reflt, QGW_ERR_INVALID_ARG, "qgw_bubble_bwd: null array");
+  QGW_REQUIRE(Gbar_tau != Gbar_reflt && Gbar_tau != gt && Gbar_tau != gr && Gbar_reflt != gt && Gbar_reflt != gr,
+              QGW_ERR_INVALID_ARG, "qgw_bubble_bwd: outputs alias inputs");
+  hipStream_t s = (hipStream_t)stream;
+  QGW_CHECK_HIP(launch_contract_bwd(p, 1, Pbar_q, gr, Gbar_tau, s), "qgw_bubble_bwd");
+  QGW_CHECK_HIP(launch_contract_bwd(p, 2, Pbar_q, gt, Gbar_reflt, s), "qgw_bubble_bwd");
+  return QGW_OK;
+}
+
+qgw_status qgw_sigma_bwd(qgw_plan h, const void* gt, const void* wc_q, int32_t out_k, const void* Sigbar,
+                         void* Gbar_tau, void* Wcbar_q, void* stream) {
+  QGW_BWD_PLAN(h, "qgw_sigma_bwd");
+  QGW_REQUIRE(gt && wc_q && Sigbar && Gbar_tau && Wcbar_q, QGW_ERR_INVALID_ARG, "qgw_sigma_bwd: null array");
+  QGW_REQUIRE(Gbar_tau != gt && Wcbar_q != wc_q && Gbar_tau != Wcbar_q, QGW_ERR_INVALID_ARG,
+              "qgw_sigma_bwd: outputs alias inputs");
+  hipStream_t s = (hipStream_t)stream;
+  const void* sbar_r = Sigbar;
+  if (out_k) {
+    const size_t bytes = size_t(p.r) * p.no * p.no * p.nk * sizeof(zd);
+    QGW_CHECK_HIP(ensure_ws(h->p, bytes), "qgw_sigma_bwd: workspace");
+    QGW_CHECK_HIP(launch_lattice_fft_scaled(p, +1, 1.0, int64_t(p.r) * p.no * p.no, Sigbar, p.d_ws, s),
+                  "qgw_sigma_bwd");
+    sbar_r = p.d_ws;
+  }
+  QGW_CHECK_HIP(launch_contract_bwd(p, 0, wc_q, sbar_r, Gbar_tau, s), "qgw_sigma_bwd");
+  QGW_CHECK_HIP(launch_sigma_bwd_wc(p, gt, sbar_r, Wcbar_q, s), "qgw_sigma_bwd");
+  return QGW_OK;
+}
+
+qgw_status qgw_dyson_W_bwd(qgw_plan h, const void* V_q, const void* P_nu, const void* Wcbar_nu, void* Pbar_nu,
+                           void* Vbar_q, void* stream) {
+  QGW_BWD_PLAN(h, "qgw_dyson_W_bwd");
+  QGW_REQUIRE(V_q && P_nu && Wcbar_nu && Pbar_nu && Vbar_q, QGW_ERR_INVALID_ARG, "qgw_dyson_W_bwd: null array");
+  QGW_REQUIRE(Pbar_nu != P_nu && Pbar_nu != Wcbar_nu && Vbar_q != V_q, QGW_ERR_INVALID_ARG,
+              "qgw_dyson_W_bwd: outputs alias inputs");
+  const int chunks = p.r < 8 ? p.r : 8;
+  const int64_t nv = int64_t(p.nb) * p.nb * p.nk;
+  QGW_CHECK_HIP(ensure_ws(h->p, size_t(chunks) * nv * sizeof(zd)), "qgw_dyson_W_bwd: workspace");
+  hipStream_t s = (hipStream_t)stream;
+  QGW_CHECK_HIP(launch_dyson_w_bwd(p, V_q, P_nu, Wcbar_nu, Pbar_nu, p.d_ws, chunks, s), "qgw_dyson_W_bwd");
+  QGW_CHECK_HIP(launch_sum_chunks(nv, chunks, p.d_ws, Vbar_q, s), "qgw_dyson_W_bwd");
+  return QGW_OK;
+}
+
+qgw_status qgw_hartree_fock_bwd(qgw_plan h, const void* V_R, const void* n_R, const void* Sbar_R, void* nbar_R,
+                                void* Vbar_R, void* stream) {
+  QGW_BWD_PLAN(h, "qgw_hartree_fock_bwd");
+  QGW_REQUIRE(V_R && n_R && Sbar_R && (nbar_R || Vbar_R), QGW_ERR_INVALID_ARG, "qgw_hartree_fock_bwd: null array");
+  QGW_CHECK_HIP(ensure_ws(h->p, size_t(p.nb) * p.nb * sizeof(zd)), "qgw_hartree_fock_bwd: workspace");
+  hipStream_t s = (hipStream_t)stream;
+  QGW_CHECK_HIP(launch_pair_sum_r(p, V_R, p.d_ws, s), "qgw_hartree_fock_bwd");
+  QGW_CHECK_HIP(launch_hartree_fock_bwd(p, V_R, p.d_ws, n_R, Sbar_R, nbar_R, Vbar_R, s), "qgw_hartree_fock_bwd");
+  return QGW_OK;
+}
+
+qgw_status qgw_dyson_G_bwd(qgw_plan h, const void* H_k, const void* Sig_iw, double mu, double n_target,
+                           double mubar, const void* Gbar, void* Sigbar, void* Hbar, void* stream) {
+  QGW_BWD_PLAN(h, "qgw_dyson_G_bwd");
+  QGW_REQUIRE(H_k && Gbar && Sigbar, QGW_ERR_INVALID_ARG, "qgw_dyson_G_bwd: null array");
+  QGW_REQUIRE(std::isfinite(mu), QGW_ERR_INVALID_ARG, "qgw_dyson_G_bwd: mu must be finite");
+  QGW_REQUIRE(Sigbar != Gbar && Sigbar != H_k && Sigbar != Sig_iw, QGW_ERR_INVALID_ARG,
+              "qgw_dyson_G_bwd: Sigbar aliases an input");
+  hipStream_t s = (hipStream_t)stream;
+  QGW_CHECK_HIP(launch_dyson_g_bwd(p, H_k, Sig_iw, mu, n_target, mubar, Gbar, Sigbar, s), "qgw_dyson_G_bwd");
+  if (Hbar) QGW_CHECK_HIP(launch_sum_nodes(p, Sigbar, Hbar, s), "qgw_dyson_G_bwd");
+  return QGW_OK;
+}
+
+qgw_status qgw_add(qgw_plan h, int64_t count, const void* a, const void* b, void* out, void* stream) {
+  QGW_PLAN(h, "qgw_add");
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_add: FP64 plans only");
+  QGW_REQUIRE(count >= 0, QGW_ERR_INVALID_ARG, "qgw_add: negative count");
+  if (count == 0) return QGW_OK;
+  QGW_REQUIRE(a && b && out, QGW_ERR_INVALID_ARG, "qgw_add: null array");
+  QGW_CHECK_HIP(launch_add(p, count, a, b, out, (hipStream_t)stream), "qgw_add");
+  return QGW_OK;
+}
+
+qgw_status qgw_pair_layout(qgw_plan h, int32_t in_layout, int32_t out_layout, int64_t nn, const void* in, void* out,
+                           void* stream) {
+  QGW_PLAN(h, "qgw_pair_layout");
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_pair_layout: FP64 plans only");
+  QGW_REQUIRE((in_layout == 0 && out_layout == 1) || (in_layout == 1 && out_layout == 0), QGW_ERR_INVALID_ARG,
+              "qgw_pair_layout: layouts must differ");
+  QGW_REQUIRE(nn >= 0, QGW_ERR_INVALID_ARG, "qgw_pair_layout: negative count");
+  if (nn == 0) return QGW_OK;
+  QGW_REQUIRE(in && out && in != out, QGW_ERR_INVALID_ARG, "qgw_pair_layout: need distinct arrays");
+  QGW_CHECK_HIP(launch_pair_layout(p, out_layout == 1 ? 1 : 0, nn, in, out, (hipStream_t)stream), "qgw_pair_layout");
+  return QGW_OK;
 }
 
 qgw_status qgw_check_finite(qgw_plan h, const void* x, int64_t count, void* stream) {

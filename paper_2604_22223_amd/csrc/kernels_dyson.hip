@@ -25,6 +25,8 @@
 // identical steps.
 #include <hip/hip_cooperative_groups.h>
 
+#include <cmath>
+
 #include "qgw_internal.h"
 
 namespace cg = cooperative_groups;
@@ -407,6 +409,243 @@ __global__ __launch_bounds__(64) void k_dyson_g(DysonGArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// adjoint of Dyson W (FP64).  With A = I - V P and W = A^{-1} V,
+// dW = A^{-1} dV (I + P W) + W dP W.  For a cotangent Wbar of W^C = W - V:
+//   X = A^{-H} Wbar,  Y = X W^H,  Pbar = W^H Wbar W^H = V^H Y,
+//   Vbar = A^{-H} Wbar (I + P W)^H - Wbar = X + Y P^H - Wbar.
+// V(q) is static, so Vbar(q) sums over the bosonic nodes: block (q, chunk)
+// sums the nodes of its chunk in a fixed order and writes a partial.  The
+// matrices live in LDS; 256 threads share each product; the inverse is
+// Gauss-Jordan with partial pivoting on [A | I].
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256) void k_dyson_w_bwd(const zd* __restrict__ vq, const zd* __restrict__ pnu,
+                                                     const zd* __restrict__ wbar, zd* __restrict__ pbar,
+                                                     zd* __restrict__ vpart, int r, int nk, int chunks) {
+  constexpr int NN = NB * NB;
+  constexpr int LA = 2 * NB;
+  constexpr int PER = (NN + 255) / 256;
+  __shared__ cpx<double> sV[NN], sA[NB * LA], sP[NN], sX[NN], sW[NN], sf[NB];
+  __shared__ int spiv;
+  __shared__ cpx<double> spinv;
+  const int q = blockIdx.x, ch = blockIdx.y, tid = threadIdx.x;
+  const int m0 = int(int64_t(r) * ch / chunks), m1 = int(int64_t(r) * (ch + 1) / chunks);
+  for (int e = tid; e < NN; e += 256) sV[e] = vq[int64_t(q) * NN + e];
+  cpx<double> vacc[PER];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) vacc[s] = mk(0.0, 0.0);
+  for (int m = m0; m < m1; ++m) {
+    const int64_t base = (int64_t(m) * nk + q) * NN;
+    __syncthreads();
+    for (int e = tid; e < NN; e += 256) {
+      sP[e] = pnu[base + e];
+      sX[e] = wbar[base + e];
+    }
+    __syncthreads();
+    for (int e = tid; e < NN; e += 256) {
+      const int a = e / NB, b = e - (e / NB) * NB;
+      cpx<double> acc = mk(0.0, 0.0);
+      for (int c = 0; c < NB; ++c) acc = fma(acc, sV[a * NB + c], sP[c * NB + b]);
+      const double d = (a == b) ? 1.0 : 0.0;
+      sA[a * LA + b] = mk(d - acc.re, -acc.im);
+      sA[a * LA + NB + b] = mk(d, 0.0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < NB; ++kk) {
+      if (tid == 0) {
+        int pv = kk;
+        double best = norm2(sA[kk * LA + kk]);
+        for (int i = kk + 1; i < NB; ++i) {
+          const double v = norm2(sA[i * LA + kk]);
+          if (v > best) {
+            best = v;
+            pv = i;
+          }
+        }
+        spiv = pv;
+      }
+      __syncthreads();
+      const int pv = spiv;
+      if (pv != kk) {
+        for (int c = tid; c < LA; c += 256) {
+          const cpx<double> t = sA[kk * LA + c];
+          sA[kk * LA + c] = sA[pv * LA + c];
+          sA[pv * LA + c] = t;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) spinv = inv(sA[kk * LA + kk]);
+      for (int i = tid; i < NB; i += 256) sf[i] = sA[i * LA + kk];
+      __syncthreads();
+      const cpx<double> pinv = spinv;
+      for (int c = tid; c < LA; c += 256) sA[kk * LA + c] = sA[kk * LA + c] * pinv;
+      __syncthreads();
+      for (int e = tid; e < NB * LA; e += 256) {
+        const int i = e / LA, c = e - (e / LA) * LA;
+        if (i != kk) sA[e] = fms(sA[e], sf[i], sA[kk * LA + c]);
+      }
+      __syncthreads();
+    }
+    // W = A^{-1} V
+    for (int e = tid; e < NN; e += 256) {
+      const int a = e / NB, b = e - (e / NB) * NB;
+      cpx<double> acc = mk(0.0, 0.0);
+      for (int c = 0; c < NB; ++c) acc = fma(acc, sA[a * LA + NB + c], sV[c * NB + b]);
+      sW[e] = acc;
+    }
+    __syncthreads();
+    // X = A^{-H} Wbar; Vbar += X - Wbar
+    cpx<double> xr[PER];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int e = tid + 256 * s;
+      xr[s] = mk(0.0, 0.0);
+      if (e < NN) {
+        const int a = e / NB, b = e - (e / NB) * NB;
+        cpx<double> acc = mk(0.0, 0.0);
+        for (int c = 0; c < NB; ++c) acc = fma(acc, conj(sA[c * LA + NB + a]), sX[c * NB + b]);
+        xr[s] = acc;
+        vacc[s] = vacc[s] + (acc - sX[e]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int e = tid + 256 * s;
+      if (e < NN) sX[e] = xr[s];
+    }
+    __syncthreads();
+    // Y = X W^H into the first NN entries of sA
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int e = tid + 256 * s;
+      if (e < NN) {
+        const int a = e / NB, b = e - (e / NB) * NB;
+        cpx<double> acc = mk(0.0, 0.0);
+        for (int c = 0; c < NB; ++c) acc = fma(acc, sX[a * NB + c], conj(sW[b * NB + c]));
+        xr[s] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int e = tid + 256 * s;
+      if (e < NN) sA[e] = xr[s];
+    }
+    __syncthreads();
+    // Pbar = V^H Y; Vbar += Y P^H
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int e = tid + 256 * s;
+      if (e < NN) {
+        const int a = e / NB, b = e - (e / NB) * NB;
+        cpx<double> pb = mk(0.0, 0.0), vy = mk(0.0, 0.0);
+        for (int c = 0; c < NB; ++c) {
+          pb = fma(pb, conj(sV[c * NB + a]), sA[c * NB + b]);
+          vy = fma(vy, sA[a * NB + c], conj(sP[b * NB + c]));
+        }
+        pbar[base + e] = pb;
+        vacc[s] = vacc[s] + vy;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int e = tid + 256 * s;
+    if (e < NN) vpart[(int64_t(ch) * nk + q) * NN + e] = vacc[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of Dyson G with the chemical potential.  G = [(i w + mu) - X]^{-1}
+// with X = H + Sigma; dG = G (dX - dmu) G, so the direct cotangent of X is
+// S = G^H Gbar G^H and dL/dmu = mubar - Re sum tr S.  With the filling held,
+// N_e(mu, X) = N_target moves mu by -dN_X / N_mu, with
+// N_mu = 2/N_k Re sum rho_m tr G^2 and the X-cotangent of N_e equal to
+// -2/N_k conj(rho_m) (G^2)^H; the second pass adds that term.
+// ---------------------------------------------------------------------------
+template <int NO>
+__global__ __launch_bounds__(64) void k_dyson_g_bwd1(DysonGArgs A, double mu, const zd* __restrict__ gbar,
+                                                     zd* __restrict__ sbar, double* __restrict__ part) {
+  const int64_t total = int64_t(A.r) * A.nk;
+  const int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x;
+  double acc = 0.0, acc2 = 0.0;
+  if (gi < total) {
+    cpx<double> g[NO][NO];
+    load_base<NO>(A, gi, g);
+#pragma unroll
+    for (int i = 0; i < NO; ++i) g[i][i].re += mu;
+    invert_inplace<NO>(g);
+    const int m = int(gi / A.nk), k = int(gi - int64_t(m) * A.nk);
+    cpx<double> t1[NO][NO];
+#pragma unroll
+    for (int i = 0; i < NO; ++i)
+#pragma unroll
+      for (int j = 0; j < NO; ++j) {
+        cpx<double> s = mk(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < NO; ++c) s = fma(s, conj(g[c][i]), gbar[((int64_t(m) * NO + c) * NO + j) * A.nk + k]);
+        t1[i][j] = s;
+      }
+    cpx<double> tr2 = mk(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < NO; ++i)
+#pragma unroll
+      for (int j = 0; j < NO; ++j) {
+        cpx<double> s = mk(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < NO; ++c) s = fma(s, t1[i][c], conj(g[j][c]));
+        sbar[((int64_t(m) * NO + i) * NO + j) * A.nk + k] = s;
+        if (i == j) acc += s.re;
+        tr2 = fma(tr2, g[i][j], g[j][i]);
+      }
+    const zd rh = A.rho[m];
+    acc2 = rh.re * tr2.re - rh.im * tr2.im;
+  }
+  acc = wave_sum(acc);
+  acc2 = wave_sum(acc2);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = acc;
+    part[gridDim.x + blockIdx.x] = acc2;
+  }
+}
+
+template <int NO>
+__global__ __launch_bounds__(64) void k_dyson_g_bwd2(DysonGArgs A, double mu, double mubar,
+                                                     const double* __restrict__ part, int nblk,
+                                                     zd* __restrict__ sbar) {
+  double s = 0.0, s2 = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) {
+    s += part[b];
+    s2 += part[nblk + b];
+  }
+  s = wave_sum(s);
+  s2 = wave_sum(s2);
+  const double n_mu = 2.0 * s2 / double(A.nk);
+  const double coef = (mubar - s) / n_mu * 2.0 / double(A.nk);
+  const int64_t total = int64_t(A.r) * A.nk;
+  const int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x;
+  if (gi >= total) return;
+  cpx<double> g[NO][NO];
+  load_base<NO>(A, gi, g);
+#pragma unroll
+  for (int i = 0; i < NO; ++i) g[i][i].re += mu;
+  invert_inplace<NO>(g);
+  const int m = int(gi / A.nk), k = int(gi - int64_t(m) * A.nk);
+  const cpx<double> w = scale(conj(A.rho[m]), coef);
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      cpx<double> g2ji = mk(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < NO; ++c) g2ji = fma(g2ji, g[j][c], g[c][i]);
+      const int64_t o = ((int64_t(m) * NO + i) * NO + j) * A.nk + k;
+      sbar[o] = sbar[o] + w * conj(g2ji);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
@@ -455,7 +694,70 @@ hipError_t dyson_g_no(const Plan& p, const void* h_k, const void* sig_iw, int mo
   return hipLaunchCooperativeKernel((const void*)k_dyson_g<NO>, dim3(blocks), dim3(64), args, 0, s);
 }
 
+template <int NB>
+hipError_t dyson_w_bwd_nb(const Plan& p, const void* v_q, const void* p_nu, const void* wbar, void* pbar,
+                          void* vpart, int chunks, hipStream_t s) {
+  hipLaunchKernelGGL((k_dyson_w_bwd<NB>), dim3(unsigned(p.nk), unsigned(chunks)), dim3(256), 0, s,
+                     (const zd*)v_q, (const zd*)p_nu, (const zd*)wbar, (zd*)pbar, (zd*)vpart, p.r, p.nk, chunks);
+  return hipGetLastError();
+}
+
+template <int NO>
+hipError_t dyson_g_bwd_no(const Plan& p, const void* h_k, const void* sig_iw, double mu, double n_target,
+                          double mubar, const void* gbar, void* sbar, hipStream_t s) {
+  DysonGArgs A;
+  A.hk = (const zd*)h_k;
+  A.sig = (const zd*)sig_iw;
+  A.wn = p.d_wn;
+  A.rho = (const zd*)p.dmaps64.m[5];
+  A.g = nullptr;
+  A.scal = p.d_scalars;
+  A.partials = p.d_partials;
+  A.status = p.d_status;
+  A.r = p.r;
+  A.nk = p.nk;
+  A.mode = 0;
+  A.max_evals = 0;
+  A.beta = p.beta;
+  A.tol_mu = A.tol_n = 0.0;
+  const int64_t total = int64_t(p.r) * p.nk;
+  const int nblk = int((total + 63) / 64);
+  if (2 * int64_t(nblk) > 8 * int64_t(p.max_blocks)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_dyson_g_bwd1<NO>), dim3(unsigned(nblk)), dim3(64), 0, s, A, mu, (const zd*)gbar, (zd*)sbar,
+                     p.d_partials);
+  if (std::isfinite(n_target))
+    hipLaunchKernelGGL((k_dyson_g_bwd2<NO>), dim3(unsigned(nblk)), dim3(64), 0, s, A, mu, mubar,
+                       (const double*)p.d_partials, nblk, (zd*)sbar);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_dyson_w_bwd(const Plan& p, const void* v_q, const void* p_nu, const void* wbar, void* pbar,
+                              void* vpart, int chunks, hipStream_t s) {
+  switch (p.nb) {
+#define QGW_CASE(NBV) \
+  case NBV:           \
+    return dyson_w_bwd_nb<NBV>(p, v_q, p_nu, wbar, pbar, vpart, chunks, s);
+    QGW_FOR_EACH_NB(QGW_CASE)
+#undef QGW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_dyson_g_bwd(const Plan& p, const void* h_k, const void* sig_iw, double mu, double n_target,
+                              double mubar, const void* gbar, void* sbar, hipStream_t s) {
+  switch (p.no) {
+#define QGW_CASE(NOV) \
+  case NOV:           \
+    return dyson_g_bwd_no<NOV>(p, h_k, sig_iw, mu, n_target, mubar, gbar, sbar, s);
+    QGW_FOR_EACH_NO(QGW_CASE)
+#undef QGW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void* wc_nu,
                           hipStream_t s) {

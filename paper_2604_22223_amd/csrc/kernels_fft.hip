@@ -13,23 +13,6 @@
 
 namespace qgw {
 
-template <int N>
-struct MeshShape {
-  static constexpr int NN = N * N;
-  static constexpr int LD = N + 1;
-  static constexpr int SLAB = N * LD;  // LDS elements per slab
-};
-
-// Slab count per block: enough lines for a few waves, LDS-bounded.
-template <typename T>
-static int slabs_per_block(int n, int lds_budget) {
-  const int slab_bytes = n * (n + 1) * int(sizeof(cpx<T>));
-  int s = 256 / n;
-  if (s < 1) s = 1;
-  while (s > 1 && s * slab_bytes > lds_budget) --s;
-  return s;
-}
-
 // ---------------------------------------------------------------------------
 // plain batched 2-D transform
 // ---------------------------------------------------------------------------
@@ -276,19 +259,24 @@ const cpx<float>* twiddles<float>(const Plan& p) {
 }
 
 template <int N, typename T>
-hipError_t fft_n(const Plan& p, int dir, int64_t batch, const void* in, void* out, hipStream_t s) {
+hipError_t fft_signed(const Plan& p, int sign, T sc, int64_t batch, const void* in, void* out, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   const int spb = slabs_per_block<T>(N, kLdsBudget);
   const size_t lds = size_t(spb) * MeshShape<N>::SLAB * sizeof(cpx<T>);
   const int64_t blocks = (batch + spb - 1) / spb;
-  const T sc = dir > 0 ? T(1) / T(N * N) : T(1);
-  if (dir > 0)
+  if (sign > 0)
     hipLaunchKernelGGL((k_lattice_fft<N, +1, T>), dim3(unsigned(blocks)), dim3(spb * N), lds, s,
                        (const cpx<T>*)in, (cpx<T>*)out, batch, spb, twiddles<T>(p), sc);
   else
     hipLaunchKernelGGL((k_lattice_fft<N, -1, T>), dim3(unsigned(blocks)), dim3(spb * N), lds, s,
                        (const cpx<T>*)in, (cpx<T>*)out, batch, spb, twiddles<T>(p), sc);
   return hipGetLastError();
+}
+
+// X(R) = (1/N_k) sum_k X(k) e^{+ik.R} for dir > 0, X(k) = sum_R X(R) e^{-ik.R} for dir < 0
+template <int N, typename T>
+hipError_t fft_n(const Plan& p, int dir, int64_t batch, const void* in, void* out, hipStream_t s) {
+  return fft_signed<N, T>(p, dir > 0 ? +1 : -1, dir > 0 ? T(1) / T(N * N) : T(1), batch, in, out, s);
 }
 
 template <int N, typename T>
@@ -342,6 +330,20 @@ hipError_t launch_lattice_fft(const Plan& p, int dir, int64_t batch, const void*
 #define QGW_CASE(NN) \
   case NN:           \
     return p.prec == 0 ? fft_n<NN, double>(p, dir, batch, in, out, s) : fft_n<NN, float>(p, dir, batch, in, out, s);
+    QGW_FOR_EACH_MESH(QGW_CASE)
+#undef QGW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_lattice_fft_scaled(const Plan& p, int sign, double out_scale, int64_t batch,
+                                     const void* in, void* out, hipStream_t s) {
+  switch (p.n) {
+#define QGW_CASE(NN)                                                                                   \
+  case NN:                                                                                             \
+    return p.prec == 0 ? fft_signed<NN, double>(p, sign, out_scale, batch, in, out, s)                \
+                       : fft_signed<NN, float>(p, sign, float(out_scale), batch, in, out, s);
     QGW_FOR_EACH_MESH(QGW_CASE)
 #undef QGW_CASE
     default:

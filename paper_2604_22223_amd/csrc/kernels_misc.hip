@@ -123,6 +123,91 @@ __global__ void k_to_f64(const zf* __restrict__ in, zd* __restrict__ out, int64_
   if (gi < n) out[gi] = cast<double>(in[gi]);
 }
 
+
+// ---- adjoints -------------------------------------------------------------
+
+// out[e] = sum_c partial[c][e], chunks in a fixed order
+__global__ void k_sum_chunks(const zd* __restrict__ part, zd* __restrict__ out, int64_t n, int chunks) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi >= n) return;
+  cpx<double> s = part[gi];
+  for (int c = 1; c < chunks; ++c) s = s + part[int64_t(c) * n + gi];
+  out[gi] = s;
+}
+
+// out[ab][k] = sum_m x[m][ab][k]
+__global__ void k_sum_nodes(const zd* __restrict__ x, zd* __restrict__ out, int64_t n, int r) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi >= n) return;
+  cpx<double> s = mk(0.0, 0.0);
+  for (int m = 0; m < r; ++m) s = s + x[int64_t(m) * n + gi];
+  out[gi] = s;
+}
+
+// Adjoint of the Hartree-Fock self-energy in the density:
+//   nbar_lj(R) = -sum_{(il),(jk)} conj(V_{(il),(jk)}(R)) Sbar_ik(R)
+//                + delta_{R,0} 2 sum_alpha conj(V_{alpha,beta}(q = 0)) Sbar_alpha(0), beta = (j', k') with (k', j') = (l, j)
+__global__ __launch_bounds__(256) void k_hf_bwd_n(const zd* __restrict__ v_r, const zd* __restrict__ v_q0,
+                                                  const zd* __restrict__ sbar, zd* __restrict__ nbar, int no,
+                                                  int nb, int nk, const int* __restrict__ pairs,
+                                                  const int4* __restrict__ terms_lj,
+                                                  const int* __restrict__ off_lj) {
+  const int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (gi >= int64_t(no) * no * nk) return;
+  const int rr = int(gi % nk);
+  const int lj = int(gi / nk);
+  cpx<double> s = mk(0.0, 0.0);
+  for (int t = off_lj[lj]; t < off_lj[lj + 1]; ++t) {
+    const int4 tm = terms_lj[t];
+    s = fms(s, conj(v_r[(int64_t(tm.x) * nb + tm.y) * nk + rr]), sbar[(int64_t(tm.z) * no + tm.w) * nk + rr]);
+  }
+  if (rr == 0) {
+    const int a = lj / no, b = lj % no;
+    const int be = pairs[2 * nb + b * no + a];  // pair (b, a): first b, second a
+    if (be >= 0) {
+      cpx<double> h = mk(0.0, 0.0);
+      for (int al = 0; al < nb; ++al) {
+        const int i = pairs[al], l = pairs[nb + al];
+        h = fma(h, conj(v_q0[int64_t(al) * nb + be]), sbar[(int64_t(i) * no + l) * nk]);
+      }
+      s = s + scale(h, 2.0);
+    }
+  }
+  nbar[gi] = s;
+}
+
+// Adjoint in V(R): Vbar_{(il),(jk)}(R) = -conj(n_lj(R)) Sbar_ik(R) + 2 conj(n_kj(0)) Sbar_il(0)
+// (the Hartree term sees V(q = 0) = sum_R V(R))
+__global__ __launch_bounds__(256) void k_hf_bwd_v(const zd* __restrict__ n_r, const zd* __restrict__ sbar,
+                                                  zd* __restrict__ vbar, int no, int nb, int nk,
+                                                  const int* __restrict__ pairs) {
+  const int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (gi >= int64_t(nb) * nb * nk) return;
+  const int rr = int(gi % nk);
+  const int ab = int(gi / nk);
+  const int al = ab / nb, be = ab % nb;
+  const int i = pairs[al], l = pairs[nb + al], j = pairs[be], k = pairs[nb + be];
+  cpx<double> v = -(conj(n_r[(int64_t(l) * no + j) * nk + rr]) * sbar[(int64_t(i) * no + k) * nk + rr]);
+  v = v + scale(conj(n_r[(int64_t(k) * no + j) * nk]) * sbar[(int64_t(i) * no + l) * nk], 2.0);
+  vbar[gi] = v;
+}
+
+// pair arrays: slab [nn][A][k] <-> matrix [nn][k][A], A = (alpha, beta)
+__global__ void k_pair_layout(const zd* __restrict__ in, zd* __restrict__ out, int64_t total, int na, int nq,
+                              int to_matrix) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi >= total) return;
+  const int64_t plane = int64_t(na) * nq;
+  const int64_t n = gi / plane, rem = gi - n * plane;
+  if (to_matrix) {
+    const int64_t q = rem / na, a = rem - q * na;
+    out[gi] = in[n * plane + a * nq + q];
+  } else {
+    const int64_t a = rem / nq, q = rem - a * nq;
+    out[gi] = in[n * plane + q * na + a];
+  }
+}
+
 static unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 hipError_t launch_convert(int64_t count, const void* in, void* out, int to_f32, hipStream_t s) {
@@ -182,6 +267,41 @@ hipError_t launch_count_nonfinite(const Plan& p, const void* x, int64_t count, i
     hipLaunchKernelGGL(k_count_nonfinite<double>, dim3(nblk(count, 256)), dim3(256), 0, s, (const zd*)x, count, d_count);
   else
     hipLaunchKernelGGL(k_count_nonfinite<float>, dim3(nblk(count, 256)), dim3(256), 0, s, (const zf*)x, count, d_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_chunks(int64_t n, int chunks, const void* partial, void* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(n, 256)), dim3(256), 0, s, (const zd*)partial, (zd*)out, n, chunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_nodes(const Plan& p, const void* x, void* out, hipStream_t s) {
+  const int64_t n = int64_t(p.no) * p.no * p.nk;
+  hipLaunchKernelGGL(k_sum_nodes, dim3(nblk(n, 256)), dim3(256), 0, s, (const zd*)x, (zd*)out, n, p.r);
+  return hipGetLastError();
+}
+
+hipError_t launch_hartree_fock_bwd(const Plan& p, const void* v_r, const void* v_q0, const void* n_r,
+                                   const void* sbar_r, void* nbar_r, void* vbar_r, hipStream_t s) {
+  const int64_t nn = int64_t(p.no) * p.no * p.nk;
+  const int64_t nv = int64_t(p.nb) * p.nb * p.nk;
+  if (nbar_r)
+    hipLaunchKernelGGL(k_hf_bwd_n, dim3(nblk(nn, 256)), dim3(256), 0, s, (const zd*)v_r, (const zd*)v_q0,
+                       (const zd*)sbar_r, (zd*)nbar_r, p.no, p.nb, p.nk, p.d_pairs, (const int4*)p.terms_lj.d_terms,
+                       p.terms_lj.d_off);
+  if (vbar_r)
+    hipLaunchKernelGGL(k_hf_bwd_v, dim3(nblk(nv, 256)), dim3(256), 0, s, (const zd*)n_r, (const zd*)sbar_r,
+                       (zd*)vbar_r, p.no, p.nb, p.nk, p.d_pairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_layout(const Plan& p, int to_matrix, int64_t nn, const void* in, void* out, hipStream_t s) {
+  const int na = p.nb * p.nb;
+  const int64_t total = nn * na * p.nk;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_layout, dim3(nblk(total, 256)), dim3(256), 0, s, (const zd*)in, (zd*)out, total, na,
+                     p.nk, to_matrix);
   return hipGetLastError();
 }
 

@@ -103,3 +103,27 @@ __host__ __device__ __forceinline__ void fft_reg(cpx<T> (&x)[N], const cpx<T>* _
 }
 
 }  // namespace qgw
+
+namespace qgw {
+
+// A slab is one N x N mesh (row-major, index = x1 N + x2).  In LDS it is
+// stored with a row stride of N + 1 so that strided column reads spread
+// over the banks.
+template <int N>
+struct MeshShape {
+  static constexpr int NN = N * N;
+  static constexpr int LD = N + 1;
+  static constexpr int SLAB = N * LD;  // LDS elements per slab
+};
+
+// Slab count per block: enough lines for a few waves, LDS-bounded.
+template <typename T>
+static inline int slabs_per_block(int n, int lds_budget) {
+  const int slab_bytes = n * (n + 1) * int(sizeof(cpx<T>));
+  int s = 256 / n;
+  if (s < 1) s = 1;
+  while (s > 1 && s * slab_bytes > lds_budget) --s;
+  return s;
+}
+
+}  // namespace qgw

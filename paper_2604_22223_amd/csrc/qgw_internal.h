@@ -23,9 +23,12 @@ namespace qgw {
 
 constexpr int kMaxRank = 96;
 constexpr int kNumMaps = 6;
+// device map slots: 0-5 the forward maps, 6-10 the adjoints T^H of maps 0-4
+constexpr int kAdjMap0 = 6;
+constexpr int kNumDevMaps = 11;
 
 struct DeviceMaps {
-  void* m[kNumMaps] = {nullptr};  // rows padded to a multiple of mt, zero-filled
+  void* m[kNumDevMaps] = {nullptr};  // rows padded to a multiple of mt, zero-filled
   int mt = 32;                    // output rows per thread block chunk
   int rows_padded = 0;
 };
@@ -51,13 +54,17 @@ struct Plan {
   zd* d_tw64 = nullptr;
   zf* d_tw32 = nullptr;
   int* d_pairs = nullptr;  // [2 * nb]: first, second
-  TermTable terms;
+  TermTable terms;     // keyed by (i, k): entries (alpha, beta, l, j)
+  TermTable terms_lj;  // keyed by (l, j): entries (alpha, beta, i, k)
   double* d_wn = nullptr;  // fermionic Matsubara frequencies (r)
   // Dyson-G scratch: partial sums (2 x max blocks x 4), status word
   double* d_partials = nullptr;
   int* d_status = nullptr;
   double* d_scalars = nullptr;  // [8]: mu, n_target, d_sigma, ...
   int max_blocks = 0;
+  // workspace of the adjoint calls, allocated on their first use
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
 };
 
 void set_error(const std::string& msg);
@@ -94,6 +101,35 @@ hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* 
 hipError_t launch_convert(int64_t count, const void* in, void* out, int to_f32, hipStream_t s);
 hipError_t launch_count_nonfinite(const Plan& p, const void* x, int64_t count, int* d_count,
                                   hipStream_t s);
+
+// ---- adjoints (FP64 plans) ----------------------------------------------
+// batched 2-D DFT with sign and output scale given explicitly
+hipError_t launch_lattice_fft_scaled(const Plan& p, int sign, double out_scale, int64_t batch,
+                                     const void* in, void* out, hipStream_t s);
+// xbar[t][c] = conj(s rho_t) ybar[c] for the density row (herm as in launch_dlr)
+hipError_t launch_row_map_bwd(const Plan& p, int64_t ncols, double sre, double sim, int herm,
+                              const void* ybar, void* xbar, hipStream_t s);
+// Wc^bar(q) from Sigma^bar(R): -conj(G_lj(R)) Sbar_ik(R), then R -> q with 1/N_k
+hipError_t launch_sigma_bwd_wc(const Plan& p, const void* g_tau_r, const void* sbar_r, void* wcbar_q,
+                               hipStream_t s);
+// contraction adjoints (see kernels_bwd.hip): mode 0 Sigma -> G, 1 bubble -> G(tau),
+// 2 bubble -> G(beta - tau)
+hipError_t launch_contract_bwd(const Plan& p, int mode, const void* x_pair, const void* y_orb,
+                               void* out, hipStream_t s);
+hipError_t launch_dyson_w_bwd(const Plan& p, const void* v_q, const void* p_nu, const void* wcbar,
+                              void* pbar, void* vbar_partial, int chunks, hipStream_t s);
+hipError_t launch_sum_chunks(int64_t n, int chunks, const void* partial, void* out, hipStream_t s);
+// Dyson G adjoint: sbar = G^H Gbar G^H (+ the chemical-potential term when n_target is finite)
+hipError_t launch_dyson_g_bwd(const Plan& p, const void* h_k, const void* sig_iw, double mu,
+                              double n_target, double mubar, const void* gbar, void* sigbar,
+                              hipStream_t s);
+// hbar[ab][k] = sum_m x[m][ab][k]
+hipError_t launch_sum_nodes(const Plan& p, const void* x, void* out, hipStream_t s);
+hipError_t launch_hartree_fock_bwd(const Plan& p, const void* v_r, const void* v_q0, const void* n_r,
+                                   const void* sbar_r, void* nbar_r, void* vbar_r, hipStream_t s);
+// pair arrays with nn leading blocks: slab [nn][A][B][k] <-> matrix [nn][k][A][B]
+hipError_t launch_pair_layout(const Plan& p, int to_matrix, int64_t nn, const void* in, void* out,
+                              hipStream_t s);
 
 // ---- host DLR -------------------------------------------------------------
 int dlr_build_host(double lambda, double eps, int max_rank, std::vector<double>& x,

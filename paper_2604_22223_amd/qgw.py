@@ -30,7 +30,9 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_sigma", "qgw_hartree_fock", "qgw_dyson_G", "qgw_state_create", "qgw_state_destroy",
            "qgw_state_init_g0", "qgw_gw_iteration", "qgw_state_copy", "qgw_state_profile",
            "qgw_state_set_precision", "qgw_state_info", "qgw_check_finite",
-           "qgw_last_error"]
+           "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
+           "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
+           "qgw_add", "qgw_last_error"]
 
 
 class QGWError(RuntimeError):
@@ -87,6 +89,16 @@ def lib():
             "qgw_state_set_precision": [vp, i32, dbl],
             "qgw_state_info": [vp, pi32, pi32, pi32],
             "qgw_check_finite": [vp, vp, i64, vp],
+            "qgw_dlr_transform_bwd": [vp, i32, i64, dbl, dbl, i32, vp, vp, vp],
+            "qgw_dlr_transform_pairs_bwd": [vp, i32, i32, i32, vp, vp, vp],
+            "qgw_lattice_fft_bwd": [vp, i32, i64, vp, vp, vp],
+            "qgw_bubble_bwd": [vp, vp, vp, vp, vp, vp, vp],
+            "qgw_sigma_bwd": [vp, vp, vp, i32, vp, vp, vp, vp],
+            "qgw_dyson_W_bwd": [vp, vp, vp, vp, vp, vp, vp],
+            "qgw_hartree_fock_bwd": [vp, vp, vp, vp, vp, vp, vp],
+            "qgw_dyson_G_bwd": [vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp],
+            "qgw_pair_layout": [vp, i32, i32, i64, vp, vp, vp],
+            "qgw_add": [vp, i64, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -219,6 +231,60 @@ class Plan:
 
     def check_finite(self, x):
         _check(lib().qgw_check_finite(self.handle, _ptr(x), int(x.numel()), _stream()))
+
+    # ---- adjoints (cotangent convention zbar = dL/dRe z + i dL/dIm z) ----
+    def dlr_transform_bwd(self, which, ybar, xbar, scale=1.0, hermitian=0):
+        ncols = xbar.numel() // self.r
+        s = complex(scale)
+        _check(lib().qgw_dlr_transform_bwd(self.handle, int(which), int(ncols), s.real, s.imag, int(hermitian),
+                                           _ptr(ybar), _ptr(xbar), _stream()))
+        return xbar
+
+    def dlr_transform_pairs_bwd(self, which, in_layout, out_layout, ybar, xbar):
+        _check(lib().qgw_dlr_transform_pairs_bwd(self.handle, int(which), int(in_layout), int(out_layout),
+                                                 _ptr(ybar), _ptr(xbar), _stream()))
+        return xbar
+
+    def lattice_fft_bwd(self, direction, ybar, xbar):
+        batch = ybar.numel() // self.n_k
+        _check(lib().qgw_lattice_fft_bwd(self.handle, int(direction), int(batch), _ptr(ybar), _ptr(xbar), _stream()))
+        return xbar
+
+    def bubble_bwd(self, g_tau_r, g_reflt_r, pbar_q, gbar_tau, gbar_reflt):
+        _check(lib().qgw_bubble_bwd(self.handle, _ptr(g_tau_r), _ptr(g_reflt_r), _ptr(pbar_q), _ptr(gbar_tau),
+                                    _ptr(gbar_reflt), _stream()))
+        return gbar_tau, gbar_reflt
+
+    def sigma_bwd(self, g_tau_r, wc_q, sigbar, gbar_tau, wcbar_q, out_k=True):
+        _check(lib().qgw_sigma_bwd(self.handle, _ptr(g_tau_r), _ptr(wc_q), int(bool(out_k)), _ptr(sigbar),
+                                   _ptr(gbar_tau), _ptr(wcbar_q), _stream()))
+        return gbar_tau, wcbar_q
+
+    def dyson_W_bwd(self, v_q, p_nu, wcbar, pbar, vbar):
+        _check(lib().qgw_dyson_W_bwd(self.handle, _ptr(v_q), _ptr(p_nu), _ptr(wcbar), _ptr(pbar), _ptr(vbar),
+                                     _stream()))
+        return pbar, vbar
+
+    def hartree_fock_bwd(self, v_r, n_r, sbar, nbar=None, vbar=None):
+        _check(lib().qgw_hartree_fock_bwd(self.handle, _ptr(v_r), _ptr(n_r), _ptr(sbar), _ptr(nbar), _ptr(vbar),
+                                          _stream()))
+        return nbar, vbar
+
+    def dyson_G_bwd(self, h_k, sig_iw, mu, gbar, sigbar, hbar=None, n_target=None, mubar=0.0):
+        nt = float("nan") if n_target is None else float(n_target)
+        _check(lib().qgw_dyson_G_bwd(self.handle, _ptr(h_k), _ptr(sig_iw), float(mu), nt, float(mubar), _ptr(gbar),
+                                     _ptr(sigbar), _ptr(hbar), _stream()))
+        return sigbar, hbar
+
+    def add(self, a, b, out):
+        _check(lib().qgw_add(self.handle, int(a.numel()), _ptr(a), _ptr(b), _ptr(out), _stream()))
+        return out
+
+    def pair_layout(self, x, out, in_layout, out_layout):
+        nn = x.numel() // (self.n_b * self.n_b * self.n_k)
+        _check(lib().qgw_pair_layout(self.handle, int(in_layout), int(out_layout), int(nn), _ptr(x), _ptr(out),
+                                     _stream()))
+        return out
 
 
 class State:

@@ -2,20 +2,20 @@
 
 Linear steps: the dot-product identity Re<ybar, A x> = Re<A^H ybar, x> for
 random x, ybar.  Nonlinear steps and the whole iteration: central finite
-differences of the oracle's forward along random directions (step h = 1e-5,
-truncation ~h^2), with the 1e-5 relative bar for gradients.  The cotangent
-convention is zbar = dL/dRe z + i dL/dIm z, so a directional derivative is
-Re sum conj(zbar) d.
+differences of the oracle's forward along random unit directions with one
+Richardson step (h = 3e-5, truncation ~h^4), held to the 1e-5 relative bar
+for gradients.  The cotangent convention is zbar = dL/dRe z + i dL/dIm z, so
+a directional derivative is Re sum conj(zbar) d.
 """
 import numpy as np
 import pytest
 
+from conftest import directional_fd
 from oracle import adjoint as ad
 from oracle import gw, lattice
 from oracle.dlr import DLR, apply_map
 from paper_2604_22223_amd import workloads as wl
 
-H = 1e-5
 GRAD_TOL = 1e-5
 
 
@@ -27,14 +27,12 @@ def rdot(a, b):
     return float(np.sum(np.conj(a) * b).real)
 
 
-def fd(f, x, d, h=H):
-    return (f(x + h * d) - f(x - h * d)) / (2.0 * h)
-
-
 def check(g, f, x, d):
-    num = fd(f, x, d)
+    """Directional derivative along the unit direction d / |d| against Re<g, d / |d|>."""
+    d = d / np.linalg.norm(d)
+    num = directional_fd(f, x, d)
     ana = rdot(g, d)
-    assert abs(num - ana) <= GRAD_TOL * max(abs(num), 1e-3 * np.linalg.norm(g) * np.linalg.norm(d)), (num, ana)
+    assert abs(num - ana) <= GRAD_TOL * abs(num) + 1e-9 * np.linalg.norm(g), (num, ana)
 
 
 @pytest.fixture(scope="module")
@@ -187,9 +185,29 @@ def test_one_iteration_gradient_in_U_J_V():
         return _loss(gw.gw_iteration(mm, d, gw.initial_state(mm, d)), cot)
 
     for name in ("U", "J", "Vnn"):
-        up = dict(base); up[name] += H
-        dn = dict(base); dn[name] -= H
-        num = (L(**up) - L(**dn)) / (2 * H)
-        dv = (wl.five_orbital(**kw, **up)["V_R"] - wl.five_orbital(**kw, **dn)["V_R"]) / (2 * H)
+        def f(t):
+            p = dict(base)
+            p[name] += float(t)
+            return L(**p)
+        num = directional_fd(f, 0.0, 1.0)
+        up = dict(base); up[name] += 1.0
+        dv = wl.five_orbital(**kw, **up)["V_R"] - wl.five_orbital(**kw, **base)["V_R"]   # V is linear in U, J, V_nn
         ana = rdot(g["V_R"], dv)
-        assert abs(num - ana) <= GRAD_TOL * max(abs(num), 1e-6), (name, num, ana)
+        assert abs(num - ana) <= GRAD_TOL * abs(num) + 1e-9, (name, num, ana)
+
+
+def test_two_iteration_gradient_by_finite_differences(small):
+    w, d, m = small
+    rng = np.random.default_rng(8)
+    cot = _loss_parts(rng, m, d)
+    out, g = ad.n_iteration_grad(m, d, cot, 2)
+
+    def L(H_R, V_R):
+        mm = gw.Model(m.mesh, m.site_norb, H_R, V_R, m.beta, m.n_target)
+        st = gw.initial_state(mm, d)
+        for _ in range(2):
+            st = gw.gw_iteration(mm, d, st)
+        return _loss(st, cot)
+
+    check(g["H_R"], lambda x: L(x, m.V_R), m.H_R, _sym_dir(rng, m.H_R.shape))
+    check(g["V_R"], lambda x: L(m.H_R, x), m.V_R, _sym_dir(rng, m.V_R.shape))
