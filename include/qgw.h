@@ -329,9 +329,11 @@ qgw_status qgw_state_copy(qgw_state state, int32_t which, void *dst, int64_t *by
  * FP32 matrix cores for the DLR maps, FP32 Dyson W) while max |Delta Sigma|
  * is above switch_tol and still falling by at least half per iteration; the
  * rest of the solve runs in FP64, so the converged result is an FP64 fixed
- * point (defect correction).  Density, Hartree-Fock, the Dyson G solve and
- * the chemical potential are FP64 in both modes.  qgw_state_init_g0 restarts
- * the schedule. */
+ * point (defect correction).  mode 2: every iteration runs a1-a11 in FP32
+ * (the FP32 phase alone, without the FP64 finish; for measurements).
+ * Density, Hartree-Fock, the Dyson G solve and the chemical potential are
+ * FP64 in every mode.  qgw_state_init_g0 restarts the schedule.  The first
+ * call with mode 1 or 2 allocates the single-precision buffers. */
 qgw_status qgw_state_set_precision(qgw_state state, int32_t mode, double switch_tol);
 
 /* Precision used by the last iteration (0 FP64, 1 FP32) and the number of
@@ -352,6 +354,35 @@ qgw_status qgw_state_info(qgw_state state, int32_t *last_prec, int32_t *n_fp32, 
  *  10 a13  Dyson G with the chemical-potential search */
 #define QGW_NUM_STEPS 11
 qgw_status qgw_state_profile(qgw_state state, int32_t mode, double *ms, int32_t *iters);
+
+/* ---------------------------------------------------------------- batches
+ *
+ * Many independent states -- each with its own plan, so orbital count,
+ * mesh, beta and DLR rank may all differ -- advanced together by one graph
+ * launch.  qgw_batch_create records n_iter GW iterations of every state
+ * into one HIP graph: the states are spread over four worker streams forked
+ * from the capture stream, so independent instances run concurrently, and
+ * each state's iterations stay in order.  Inside the graph the chemical
+ * potential search is a fixed chain of mu_steps Newton evaluations per
+ * iteration that starts from the state's current mu (steps after
+ * convergence return at once); a search that has not converged by then
+ * sets the state's status to 2.  The Dyson-G step is the same search as
+ * qgw_gw_iteration (same grid, same summation order).  precision 0 records
+ * FP64 iterations; 1 records the single-precision form of steps a1-a11 (the
+ * FP32 phase of the mixed solve).  Every state must have been started
+ * (qgw_state_init_g0) before the first launch, must not be profiling, and
+ * must not be used by other calls while a launch is in flight.  Each call of
+ * qgw_batch_launch replays the graph on ``stream`` (no host
+ * synchronisation); qgw_batch_read waits for ``stream`` and returns, per
+ * state, the last max |Delta Sigma|, mu and status (0 ok, 1 no finite mu to
+ * start from, 2 search not converged). */
+typedef struct qgw_batch_s *qgw_batch;
+qgw_status qgw_batch_create(int32_t n, const qgw_state *states, int32_t precision,
+                            int32_t n_iter, int32_t mu_steps, qgw_batch *batch);
+qgw_status qgw_batch_launch(qgw_batch batch, void *stream);
+qgw_status qgw_batch_read(qgw_batch batch, double *d_sigma, double *mu, int32_t *status,
+                          void *stream);
+qgw_status qgw_batch_destroy(qgw_batch batch);
 
 /* Checks ``count`` complex values (precision of the plan) for NaN/Inf;
  * waits for the stream.  QGW_ERR_NONFINITE if any is found. */

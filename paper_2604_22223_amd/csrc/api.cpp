@@ -39,7 +39,12 @@ struct qgw_state_s {
   void *Pq = nullptr, *P_nu = nullptr, *Wc_nu = nullptr;
   double* d_dsig = nullptr;
   double* d_blockmax = nullptr;
-  // single-precision copies for the FP32 phase of the solve
+  // chemical-potential search of this state: scalars [16], partial sums, status
+  double* d_scal = nullptr;
+  double* d_part = nullptr;
+  int* d_stat = nullptr;
+  // single-precision copies for the FP32 phase of the solve (allocated on first use)
+  bool has32 = false;
   Plan p32;
   void *G32 = nullptr, *Gt32 = nullptr, *Gr32 = nullptr, *St32 = nullptr, *Siw32 = nullptr;
   void *Pq32 = nullptr, *Pnu32 = nullptr, *Wc32 = nullptr, *Vqm32 = nullptr;
@@ -470,15 +475,21 @@ qgw_status qgw_hartree_fock(qgw_plan h, const void* V_R, const void* n_R, void* 
 }
 
 static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw, double n_target,
-                              double* mu, void* G_iw, hipStream_t s, double* evals) {
+                              double* mu, void* G_iw, hipStream_t s, double* evals, double* scal = nullptr,
+                              double* part = nullptr, int* stat = nullptr) {
   const int mode = std::isnan(n_target) ? 0 : 1;
+  if (!scal) {
+    scal = p.d_scalars;
+    part = p.d_partials;
+    stat = p.d_status;
+  }
   double sc[2] = {*mu, n_target};
-  QGW_CHECK_HIP(hipMemcpyAsync(p.d_scalars, sc, sizeof(sc), hipMemcpyHostToDevice, s), "qgw_dyson_G");
-  QGW_CHECK_HIP(launch_dyson_g(p, H_k, Sig_iw, mode, G_iw, s), "qgw_dyson_G launch");
+  QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, sizeof(sc), hipMemcpyHostToDevice, s), "qgw_dyson_G");
+  QGW_CHECK_HIP(launch_dyson_g_state(p, H_k, Sig_iw, mode, G_iw, scal, part, stat, s), "qgw_dyson_G launch");
   double res[4];
   int st = 0;
-  QGW_CHECK_HIP(hipMemcpyAsync(res, p.d_scalars, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
-  QGW_CHECK_HIP(hipMemcpyAsync(&st, p.d_status, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
+  QGW_CHECK_HIP(hipMemcpyAsync(res, scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
+  QGW_CHECK_HIP(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
   QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_dyson_G");
   if (mode == 1) {
     *mu = res[0];
@@ -700,9 +711,32 @@ static void free_state(qgw_state st) {
                   st->SigHF_k, st->SigHF_old, st->n_k, st->n_R, st->SigHF_R, st->Hs_k, st->G_tau,
                   st->G_reflt, st->Sig_tau_k, st->Pq, st->P_nu, st->Wc_nu, st->d_dsig, st->d_blockmax,
                   st->G32, st->Gt32, st->Gr32, st->St32, st->Siw32, st->Pq32, st->Pnu32, st->Wc32,
-                  st->Vqm32};
+                  st->Vqm32, st->d_scal, st->d_part, st->d_stat};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+}
+
+// buffers of the single-precision phase, allocated when first needed
+static hipError_t ensure_fp32(qgw_state st) {
+  if (st->has32) return hipSuccess;
+  const Plan& p = st->plan->p;
+  const size_t so = size_t(p.no) * p.no * p.nk * 8;
+  const size_t sp = size_t(p.nb) * p.nb * p.nk * 8;
+  const size_t fo = so * p.r, fp = sp * p.r;
+  struct {
+    void** ptr;
+    size_t bytes;
+  } allocs[] = {{&st->G32, fo},  {&st->Gt32, fo},  {&st->Gr32, fo},  {&st->St32, fo}, {&st->Siw32, fo},
+                {&st->Pq32, fp}, {&st->Pnu32, fp}, {&st->Wc32, fp}, {&st->Vqm32, sp}};
+  hipError_t e = hipSuccess;
+  for (auto& a : allocs) {
+    if (e != hipSuccess) break;
+    if (!*a.ptr) e = hipMalloc(a.ptr, a.bytes);
+  }
+  if (e == hipSuccess) e = launch_convert(int64_t(p.nb) * p.nb * p.nk, st->V_qm, st->Vqm32, 1, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e == hipSuccess) st->has32 = true;
+  return e;
 }
 
 qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, double n_target, double mixing,
@@ -734,9 +768,9 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
                 {&st->n_R, so},       {&st->SigHF_R, so}, {&st->Hs_k, so},       {&st->G_tau, fo},
                 {&st->G_reflt, fo},   {&st->Sig_tau_k, fo}, {&st->Pq, fp},       {&st->P_nu, fp},
                 {&st->Wc_nu, fp},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096},
-                {&st->G32, fo / 2},   {&st->Gt32, fo / 2}, {&st->Gr32, fo / 2},   {&st->St32, fo / 2},
-                {&st->Siw32, fo / 2}, {&st->Pq32, fp / 2}, {&st->Pnu32, fp / 2}, {&st->Wc32, fp / 2},
-                {&st->Vqm32, sp / 2}};
+                {(void**)&st->d_scal, 16 * sizeof(double)},
+                {(void**)&st->d_part, size_t(8) * p.max_blocks * sizeof(double)},
+                {(void**)&st->d_stat, 16 * sizeof(int)}};
   for (auto& a : allocs) {
     if (e != hipSuccess) break;
     e = hipMalloc(a.ptr, a.bytes);
@@ -748,8 +782,11 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
   if (e == hipSuccess) e = launch_lattice_fft(p, QGW_R_TO_K, int64_t(p.no) * p.no, H0_R, st->H_k, s);
   if (e == hipSuccess) e = launch_lattice_fft(p, QGW_R_TO_K, int64_t(p.nb) * p.nb, V_R, st->V_q, s);
   if (e == hipSuccess) e = launch_slab_to_matrix_static(p, st->V_q, st->V_qm, s);
-  if (e == hipSuccess) e = launch_convert(int64_t(p.nb) * p.nb * p.nk, st->V_qm, st->Vqm32, 1, s);
   if (e == hipSuccess) e = launch_pair_sum_r(p, V_R, st->V_q0, s);
+  if (e == hipSuccess) {
+    double sc[2] = {NAN, n_target};
+    e = hipMemcpy(st->d_scal, sc, sizeof(sc), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMemsetAsync(st->Sig_iw, 0, fo, s);
   if (e == hipSuccess) e = hipMemsetAsync(st->Sig_iw_old, 0, fo, s);
   if (e == hipSuccess) e = hipMemsetAsync(st->SigHF_k, 0, so, s);
@@ -783,11 +820,12 @@ qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
   QGW_CHECK_HIP(hipMemsetAsync(st->Sig_iw_old, 0, fo, s), "qgw_state_init_g0");
   QGW_CHECK_HIP(hipMemsetAsync(st->SigHF_old, 0, so, s), "qgw_state_init_g0");
   double m = *mu;
-  qgw_status rc = run_dyson_g(p, st->H_k, nullptr, st->n_target, &m, st->G_iw, s, nullptr);
+  qgw_status rc = run_dyson_g(p, st->H_k, nullptr, st->n_target, &m, st->G_iw, s, nullptr, st->d_scal,
+                              st->d_part, st->d_stat);
   if (rc != QGW_OK) return rc;
   st->mu = m;
   *mu = m;
-  st->in_fp32 = st->prec_mode == 1;
+  st->in_fp32 = st->prec_mode != 0;
   st->n_fp32 = st->n_fp64 = 0;
   st->last_dsig = INFINITY;
   return QGW_OK;
@@ -795,11 +833,15 @@ qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
 
 qgw_status qgw_state_set_precision(qgw_state st, int32_t mode, double switch_tol) {
   QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: null state");
-  QGW_REQUIRE(mode == 0 || mode == 1, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: mode must be 0 or 1");
+  QGW_REQUIRE(mode >= 0 && mode <= 2, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: mode must be 0, 1 or 2");
   QGW_REQUIRE(switch_tol > 0.0, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: switch_tol must be positive");
+  if (mode != 0) {
+    QGW_CHECK_HIP(hipSetDevice(st->plan->p.device), "hipSetDevice");
+    QGW_CHECK_HIP(ensure_fp32(st), "qgw_state_set_precision: single-precision buffers");
+  }
   st->prec_mode = mode;
   st->switch_tol = switch_tol;
-  st->in_fp32 = mode == 1;
+  st->in_fp32 = mode != 0;
   st->last_dsig = INFINITY;
   return QGW_OK;
 }
@@ -812,6 +854,74 @@ qgw_status qgw_state_info(qgw_state st, int32_t* last_prec, int32_t* n_fp32, int
   return QGW_OK;
 }
 
+// a12, a1-a11 (FP64 or single precision), a14 and the static H + Sigma_HF of a13,
+// enqueued on s; with `prof` HIP events mark the step boundaries 0 .. 10
+static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s) {
+  const Plan& p = st->plan->p;
+  const int64_t no2 = int64_t(p.no) * p.no;
+  const int64_t ncol_g = no2 * p.nk;
+  hipError_t e = hipSuccess;
+  auto mark = [&](int i) { if (e == hipSuccess && prof) e = hipEventRecord(st->ev[i], s); };
+  auto run = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+  // a12: density of the incoming G (Hermitian part), Hartree-Fock
+  mark(0);
+  run(launch_dlr(p, QGW_F_IW2BETA, ncol_g, -1.0, 0.0, st->G_iw, st->n_k, s, 2));
+  run(launch_lattice_fft(p, QGW_K_TO_R, no2, st->n_k, st->n_R, s));
+  run(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, s));
+  run(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, s));
+  if (!f32) {
+    mark(1);  // a1
+    run(launch_dlr(p, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G_iw, st->G_tau, s));
+    run(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s));
+    mark(2);  // a2
+    run(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, s));
+    run(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_reflt, st->G_reflt, s));
+    mark(3);  // a3 + a4
+    run(launch_bubble(p, st->G_tau, st->G_reflt, 1, st->Pq, s));
+    mark(4);  // a5
+    run(launch_dlr_pairs(p, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq, st->P_nu, s));
+    mark(5);  // a6
+    run(launch_dyson_w(p, st->V_qm, st->P_nu, st->Wc_nu, s));
+    mark(6);  // a7
+    run(launch_dlr_pairs(p, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc_nu, st->Pq, s));
+    mark(7);  // a8 + a9 + a10
+    run(launch_sigma(p, st->G_tau, st->Pq, 1, 1, st->Sig_tau_k, s));
+    mark(8);  // a11 (Hermitian part of Sigma^C(k, tau))
+    run(launch_dlr(p, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->Sig_tau_k, st->Sig_iw, s, 1));
+  } else {
+    // the same steps in single precision (defect-correction phase of the solve)
+    const Plan& q = st->p32;
+    mark(1);
+    run(launch_convert(ncol_g * p.r, st->G_iw, st->G32, 1, s));
+    run(launch_dlr(q, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G32, st->Gt32, s));
+    run(launch_dlr(q, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G32, st->Gr32, s));
+    mark(2);
+    run(launch_lattice_fft(q, QGW_K_TO_R, no2 * p.r, st->Gt32, st->Gt32, s));
+    run(launch_lattice_fft(q, QGW_K_TO_R, no2 * p.r, st->Gr32, st->Gr32, s));
+    mark(3);
+    run(launch_bubble(q, st->Gt32, st->Gr32, 1, st->Pq32, s));
+    mark(4);
+    run(launch_dlr_pairs(q, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq32, st->Pnu32, s));
+    mark(5);
+    run(launch_dyson_w(q, st->Vqm32, st->Pnu32, st->Wc32, s));
+    mark(6);
+    run(launch_dlr_pairs(q, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc32, st->Pq32, s));
+    mark(7);
+    run(launch_sigma(q, st->Gt32, st->Pq32, 1, 1, st->St32, s));
+    mark(8);
+    run(launch_dlr(q, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->St32, st->Siw32, s, 1));
+    run(launch_convert(ncol_g * p.r, st->Siw32, st->Sig_iw, 0, s));
+  }
+  // a14: change of the total self-energy, mixing
+  mark(9);
+  run(launch_delta_and_mix(p, st->SigHF_k, st->Sig_iw, st->SigHF_old, st->Sig_iw_old, st->mixing, st->d_dsig,
+                           st->d_blockmax, s));
+  // a13 (static part): H0 + Sigma_HF
+  mark(10);
+  run(launch_add(p, ncol_g, st->H_k, st->SigHF_k, st->Hs_k, s));
+  return e;
+}
+
 qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* iters_done, double* d_sigma,
                             double* mu_out, void* stream) {
   QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_gw_iteration: null state");
@@ -819,78 +929,18 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
   const Plan& p = st->plan->p;
   QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t no2 = int64_t(p.no) * p.no;
-  const int64_t ncol_g = no2 * p.nk;
   double dsig = NAN;
   int done = 0;
-  auto mark = [&](int i) -> hipError_t { return st->prof ? hipEventRecord(st->ev[i], s) : hipSuccess; };
   for (int it = 0; it < n_iter; ++it) {
-    // a12: density of the incoming G (Hermitian part), Hartree-Fock
-    QGW_CHECK_HIP(mark(0), "profile");
-    QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2BETA, ncol_g, -1.0, 0.0, st->G_iw, st->n_k, s, 2), "a12 density");
-    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2, st->n_k, st->n_R, s), "a12 fft");
-    QGW_CHECK_HIP(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, s), "a12 hf");
-    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, s), "a12 fft");
-    const bool f32 = st->prec_mode == 1 && st->in_fp32;
-    if (!f32) {
-      // a1, a2
-      QGW_CHECK_HIP(mark(1), "profile");
-      QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G_iw, st->G_tau, s), "a1");
-      QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s), "a1");
-      QGW_CHECK_HIP(mark(2), "profile");
-      QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, s), "a2");
-      QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_reflt, st->G_reflt, s), "a2");
-      // a3 + a4, a5, a6, a7
-      QGW_CHECK_HIP(mark(3), "profile");
-      QGW_CHECK_HIP(launch_bubble(p, st->G_tau, st->G_reflt, 1, st->Pq, s), "a3");
-      QGW_CHECK_HIP(mark(4), "profile");
-      QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq, st->P_nu, s), "a5");
-      QGW_CHECK_HIP(mark(5), "profile");
-      QGW_CHECK_HIP(launch_dyson_w(p, st->V_qm, st->P_nu, st->Wc_nu, s), "a6");
-      QGW_CHECK_HIP(mark(6), "profile");
-      QGW_CHECK_HIP(launch_dlr_pairs(p, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc_nu, st->Pq, s), "a7");
-      // a8 + a9 + a10, a11 (Hermitian part of Sigma^C(k, tau))
-      QGW_CHECK_HIP(mark(7), "profile");
-      QGW_CHECK_HIP(launch_sigma(p, st->G_tau, st->Pq, 1, 1, st->Sig_tau_k, s), "a9");
-      QGW_CHECK_HIP(mark(8), "profile");
-      QGW_CHECK_HIP(launch_dlr(p, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->Sig_tau_k, st->Sig_iw, s, 1), "a11");
-    } else {
-      // the same steps in single precision (defect-correction phase of the solve)
-      const Plan& q = st->p32;
-      QGW_CHECK_HIP(mark(1), "profile");
-      QGW_CHECK_HIP(launch_convert(ncol_g * p.r, st->G_iw, st->G32, 1, s), "a1 f32");
-      QGW_CHECK_HIP(launch_dlr(q, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G32, st->Gt32, s), "a1 f32");
-      QGW_CHECK_HIP(launch_dlr(q, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G32, st->Gr32, s), "a1 f32");
-      QGW_CHECK_HIP(mark(2), "profile");
-      QGW_CHECK_HIP(launch_lattice_fft(q, QGW_K_TO_R, no2 * p.r, st->Gt32, st->Gt32, s), "a2 f32");
-      QGW_CHECK_HIP(launch_lattice_fft(q, QGW_K_TO_R, no2 * p.r, st->Gr32, st->Gr32, s), "a2 f32");
-      QGW_CHECK_HIP(mark(3), "profile");
-      QGW_CHECK_HIP(launch_bubble(q, st->Gt32, st->Gr32, 1, st->Pq32, s), "a3 f32");
-      QGW_CHECK_HIP(mark(4), "profile");
-      QGW_CHECK_HIP(launch_dlr_pairs(q, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq32, st->Pnu32, s), "a5 f32");
-      QGW_CHECK_HIP(mark(5), "profile");
-      QGW_CHECK_HIP(launch_dyson_w(q, st->Vqm32, st->Pnu32, st->Wc32, s), "a6 f32");
-      QGW_CHECK_HIP(mark(6), "profile");
-      QGW_CHECK_HIP(launch_dlr_pairs(q, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc32, st->Pq32, s), "a7 f32");
-      QGW_CHECK_HIP(mark(7), "profile");
-      QGW_CHECK_HIP(launch_sigma(q, st->Gt32, st->Pq32, 1, 1, st->St32, s), "a9 f32");
-      QGW_CHECK_HIP(mark(8), "profile");
-      QGW_CHECK_HIP(launch_dlr(q, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->St32, st->Siw32, s, 1), "a11 f32");
-      QGW_CHECK_HIP(launch_convert(ncol_g * p.r, st->Siw32, st->Sig_iw, 0, s), "a11 f32");
-    }
-    // a14: change of the total self-energy, mixing
-    QGW_CHECK_HIP(mark(9), "profile");
-    QGW_CHECK_HIP(launch_delta_and_mix(p, st->SigHF_k, st->Sig_iw, st->SigHF_old, st->Sig_iw_old, st->mixing,
-                                       st->d_dsig, st->d_blockmax, s),
-                  "a14");
+    const bool f32 = st->prec_mode == 2 || (st->prec_mode == 1 && st->in_fp32);
+    QGW_CHECK_HIP(enqueue_steps(st, f32, st->prof, s), "qgw_gw_iteration");
     // a13: Dyson G with the chemical potential
-    QGW_CHECK_HIP(mark(10), "profile");
-    QGW_CHECK_HIP(launch_add(p, ncol_g, st->H_k, st->SigHF_k, st->Hs_k, s), "a13");
     double m = st->mu;
-    qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, nullptr);
+    qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, nullptr, st->d_scal,
+                                st->d_part, st->d_stat);
     if (rc != QGW_OK) return rc;
     st->mu = m;
-    QGW_CHECK_HIP(mark(QGW_NUM_STEPS), "profile");
+    if (st->prof) QGW_CHECK_HIP(hipEventRecord(st->ev[QGW_NUM_STEPS], s), "profile");
     QGW_CHECK_HIP(hipMemcpyAsync(&dsig, st->d_dsig, sizeof(double), hipMemcpyDeviceToHost, s), "a14");
     QGW_CHECK_HIP(hipStreamSynchronize(s), "a14");
     if (st->prof) {
@@ -906,16 +956,142 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     if (f32) {
       ++st->n_fp32;
       // leave the single-precision phase at its tolerance, or once it stalls
-      if (dsig <= st->switch_tol || dsig > 0.5 * st->last_dsig) st->in_fp32 = false;
+      if (st->prec_mode == 1 && (dsig <= st->switch_tol || dsig > 0.5 * st->last_dsig)) st->in_fp32 = false;
     } else {
       ++st->n_fp64;
     }
     st->last_dsig = dsig;
-    if (dsig <= tol && !(st->prec_mode == 1 && f32)) break;
+    if (dsig <= tol && !(st->prec_mode != 0 && f32)) break;
   }
   if (iters_done) *iters_done = done;
   if (d_sigma) *d_sigma = dsig;
   if (mu_out) *mu_out = st->mu;
+  return QGW_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+struct qgw_batch_s {
+  std::vector<qgw_state> states;
+  int device = 0;
+  hipStream_t cap = nullptr;
+  std::vector<hipStream_t> workers;
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void free_batch(qgw_batch b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  for (hipStream_t w : b->workers) (void)hipStreamDestroy(w);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+}
+
+qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precision, int32_t n_iter,
+                            int32_t mu_steps, qgw_batch* out) {
+  QGW_REQUIRE(out && states && n > 0, QGW_ERR_INVALID_ARG, "qgw_batch_create: need states");
+  QGW_REQUIRE(precision == 0 || precision == 1, QGW_ERR_INVALID_ARG, "qgw_batch_create: bad precision");
+  QGW_REQUIRE(n_iter >= 1 && n_iter <= 64, QGW_ERR_INVALID_ARG, "qgw_batch_create: n_iter must be in [1, 64]");
+  QGW_REQUIRE(mu_steps >= 1 && mu_steps <= 64, QGW_ERR_INVALID_ARG, "qgw_batch_create: mu_steps must be in [1, 64]");
+  *out = nullptr;
+  const int dev = states[0] ? states[0]->plan->p.device : 0;
+  for (int i = 0; i < n; ++i) {
+    QGW_REQUIRE(states[i], QGW_ERR_INVALID_ARG, "qgw_batch_create: null state");
+    QGW_REQUIRE(states[i]->plan->p.device == dev, QGW_ERR_INVALID_ARG, "qgw_batch_create: states on different devices");
+    QGW_REQUIRE(!states[i]->prof, QGW_ERR_INVALID_ARG, "qgw_batch_create: disable profiling first");
+    for (int j = 0; j < i; ++j)
+      QGW_REQUIRE(states[j] != states[i], QGW_ERR_INVALID_ARG, "qgw_batch_create: a state appears twice");
+  }
+  QGW_CHECK_HIP(hipSetDevice(dev), "hipSetDevice");
+  if (precision == 1)
+    for (int i = 0; i < n; ++i) QGW_CHECK_HIP(ensure_fp32(states[i]), "qgw_batch_create: single-precision buffers");
+  qgw_batch b = new (std::nothrow) qgw_batch_s;
+  QGW_REQUIRE(b, QGW_ERR_ALLOC, "qgw_batch_create: out of host memory");
+  b->states.assign(states, states + n);
+  b->device = dev;
+  const int nw = n < 4 ? n : 4;
+  hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  for (int w = 0; w < nw && e == hipSuccess; ++w) {
+    hipStream_t ws = nullptr;
+    e = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking);
+    if (e == hipSuccess) b->workers.push_back(ws);
+  }
+  for (int w = 0; w <= nw && e == hipSuccess; ++w) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->events.push_back(ev);
+  }
+  // capture: fork the workers from the capture stream, instance i on worker i mod nw, join
+  if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t ce = hipEventRecord(b->events[nw], b->cap);
+    for (int w = 0; w < nw && ce == hipSuccess; ++w) ce = hipStreamWaitEvent(b->workers[w], b->events[nw], 0);
+    for (int it = 0; it < n_iter && ce == hipSuccess; ++it)
+      for (int i = 0; i < n && ce == hipSuccess; ++i) {
+        qgw_state st = states[i];
+        const Plan& p = st->plan->p;
+        hipStream_t ws = b->workers[i % nw];
+        ce = enqueue_steps(st, precision == 1, false, ws);
+        if (ce == hipSuccess)
+          ce = launch_dyson_g_chain(p, st->Hs_k, st->Sig_iw, std::isnan(st->n_target) ? 0 : 1, st->G_iw, st->d_scal,
+                                    st->d_part, st->d_stat, mu_steps, ws);
+      }
+    for (int w = 0; w < nw && ce == hipSuccess; ++w) {
+      ce = hipEventRecord(b->events[w], b->workers[w]);
+      if (ce == hipSuccess) ce = hipStreamWaitEvent(b->cap, b->events[w], 0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(b->cap, &g);
+    b->graph = g;
+    e = ce != hipSuccess ? ce : ee;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    set_error(std::string("qgw_batch_create: ") + hipGetErrorString(e));
+    free_batch(b);
+    delete b;
+    return QGW_ERR_DEVICE;
+  }
+  *out = b;
+  return QGW_OK;
+}
+
+qgw_status qgw_batch_launch(qgw_batch b, void* stream) {
+  QGW_REQUIRE(b, QGW_ERR_INVALID_ARG, "qgw_batch_launch: null batch");
+  QGW_CHECK_HIP(hipSetDevice(b->device), "hipSetDevice");
+  QGW_CHECK_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream), "qgw_batch_launch");
+  return QGW_OK;
+}
+
+qgw_status qgw_batch_read(qgw_batch b, double* d_sigma, double* mu, int32_t* status, void* stream) {
+  QGW_REQUIRE(b, QGW_ERR_INVALID_ARG, "qgw_batch_read: null batch");
+  QGW_CHECK_HIP(hipSetDevice(b->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = b->states.size();
+  std::vector<double> ds(n), m(n);
+  std::vector<int> stt(n);
+  for (size_t i = 0; i < n; ++i) {
+    QGW_CHECK_HIP(hipMemcpyAsync(&ds[i], b->states[i]->d_dsig, sizeof(double), hipMemcpyDeviceToHost, s), "qgw_batch_read");
+    QGW_CHECK_HIP(hipMemcpyAsync(&m[i], b->states[i]->d_scal, sizeof(double), hipMemcpyDeviceToHost, s), "qgw_batch_read");
+    QGW_CHECK_HIP(hipMemcpyAsync(&stt[i], b->states[i]->d_stat, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_batch_read");
+  }
+  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_batch_read");
+  for (size_t i = 0; i < n; ++i) {
+    b->states[i]->mu = m[i];
+    if (d_sigma) d_sigma[i] = ds[i];
+    if (mu) mu[i] = m[i];
+    if (status) status[i] = stt[i];
+  }
+  return QGW_OK;
+}
+
+qgw_status qgw_batch_destroy(qgw_batch b) {
+  if (!b) return QGW_OK;
+  (void)hipSetDevice(b->device);
+  free_batch(b);
+  delete b;
   return QGW_OK;
 }
 

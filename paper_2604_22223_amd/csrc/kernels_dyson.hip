@@ -409,6 +409,128 @@ __global__ __launch_bounds__(64) void k_dyson_g(DysonGArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// The same chemical-potential search as a chain of ordinary launches, for
+// callers that capture the iteration into a graph (no grid barrier, no host
+// round trip).  The search state lives in the scalar block:
+//   [0] mu  [1] n_target  [2] evaluations  [3] last N_e  [4] lo  [5] hi
+//   [6] step cap  [7] done flag
+// k_dg_eval and k_dg_newton alternate a fixed number of times; once the
+// search has converged the remaining launches return at once.  The grid
+// size and the summation order equal those of k_dyson_g, so both give the
+// same iterates and the same G.
+// ---------------------------------------------------------------------------
+__global__ void k_dg_begin(double* __restrict__ scal, int* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const bool ok = isfinite(scal[0]);
+  scal[2] = 0.0;
+  scal[3] = 0.0;
+  scal[4] = -INFINITY;
+  scal[5] = INFINITY;
+  scal[6] = 1.0;
+  scal[7] = ok ? 0.0 : 1.0;
+  status[0] = ok ? 0 : 1;
+}
+
+template <int NO>
+__global__ __launch_bounds__(64) void k_dg_eval(DysonGArgs A) {
+  if (A.scal[7] != 0.0) return;
+  const double mu = A.scal[0];
+  const int64_t total = int64_t(A.r) * A.nk;
+  const int64_t stride = int64_t(gridDim.x) * 64;
+  double acc = 0.0, accd = 0.0;
+  for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
+    cpx<double> a[NO][NO];
+    load_base<NO>(A, gi, a);
+#pragma unroll
+    for (int i = 0; i < NO; ++i) a[i][i].re += mu;
+    invert_inplace<NO>(a);
+    cpx<double> tr = mk(0.0, 0.0), tr2 = mk(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      tr = tr + a[i][i];
+#pragma unroll
+      for (int j = 0; j < NO; ++j) tr2 = fma(tr2, a[i][j], a[j][i]);
+    }
+    const zd rh = A.rho[int(gi / A.nk)];
+    acc += rh.re * tr.re - rh.im * tr.im;
+    accd += rh.re * tr2.re - rh.im * tr2.im;
+  }
+  acc = wave_sum(acc);
+  accd = wave_sum(accd);
+  if (threadIdx.x == 0) {
+    A.partials[blockIdx.x] = acc;
+    A.partials[gridDim.x + blockIdx.x] = accd;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_dg_newton(DysonGArgs A, int nblk) {
+  if (A.scal[7] != 0.0) return;
+  double s = 0.0, sd = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) {
+    s += A.partials[b];
+    sd += A.partials[nblk + b];
+  }
+  s = wave_sum(s);
+  sd = wave_sum(sd);
+  if (threadIdx.x != 0) return;
+  const double ne = -2.0 * s / double(A.nk), dne = 2.0 * sd / double(A.nk);
+  double mu = A.scal[0], lo = A.scal[4], hi = A.scal[5], cap = A.scal[6];
+  const double nt = A.scal[1];
+  const double f = ne - nt;
+  A.scal[2] += 1.0;
+  A.scal[3] = ne;
+  if (f < 0.0) lo = fmax(lo, mu);
+  if (f > 0.0) hi = fmin(hi, mu);
+  bool done = false;
+  if (fabs(f) <= A.tol_n) {
+    done = true;
+  } else {
+    double nxt = (dne > 0.0) ? mu - f / dne : NAN;
+    const bool bracket = isfinite(lo) && isfinite(hi);
+    if (bracket) {
+      if (!(nxt > lo && nxt < hi)) nxt = 0.5 * (lo + hi);
+    } else {
+      if (!isfinite(nxt)) nxt = mu + (f < 0.0 ? cap : -cap);
+      if (fabs(nxt - mu) > cap) {
+        nxt = mu + (nxt > mu ? cap : -cap);
+        cap *= 4.0;
+      }
+    }
+    const double tol = A.tol_mu * fmax(1.0, fabs(mu));
+    if (fabs(nxt - mu) <= tol || (bracket && hi - lo <= tol)) done = true;
+    mu = nxt;
+  }
+  A.scal[0] = mu;
+  A.scal[4] = lo;
+  A.scal[5] = hi;
+  A.scal[6] = cap;
+  A.scal[7] = done ? 1.0 : 0.0;
+}
+
+template <int NO>
+__global__ __launch_bounds__(64) void k_dg_final(DysonGArgs A) {
+  const double mu = A.scal[0];
+  const int64_t total = int64_t(A.r) * A.nk;
+  const int64_t stride = int64_t(gridDim.x) * 64;
+  for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
+    cpx<double> a[NO][NO];
+    load_base<NO>(A, gi, a);
+#pragma unroll
+    for (int i = 0; i < NO; ++i) a[i][i].re += mu;
+    invert_inplace<NO>(a);
+    const int m = int(gi / A.nk), k = int(gi - int64_t(m) * A.nk);
+#pragma unroll
+    for (int i = 0; i < NO; ++i)
+#pragma unroll
+      for (int j = 0; j < NO; ++j) A.g[((int64_t(m) * NO + i) * NO + j) * A.nk + k] = a[i][j];
+  }
+  if (A.mode == 1 && blockIdx.x == 0 && threadIdx.x == 0 && A.status[0] == 0) {
+    const bool conv = A.scal[7] != 0.0 || fabs(A.scal[3] - A.scal[1]) <= A.tol_n;
+    if (!conv || !isfinite(mu)) A.status[0] = 2;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // adjoint of Dyson W (FP64).  With A = I - V P and W = A^{-1} V,
 // dW = A^{-1} dV (I + P W) + W dP W.  For a cotangent Wbar of W^C = W - V:
 //   X = A^{-H} Wbar,  Y = X W^H,  Pbar = W^H Wbar W^H = V^H Y,
@@ -661,17 +783,17 @@ hipError_t dyson_w_nb(const Plan& p, const void* v_q, const void* p_nu, void* wc
 }
 
 template <int NO>
-hipError_t dyson_g_no(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                      hipStream_t s) {
+DysonGArgs dyson_g_args(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw, double* scal,
+                        double* partials, int* status) {
   DysonGArgs A;
   A.hk = (const zd*)h_k;
   A.sig = (const zd*)sig_iw;
   A.wn = p.d_wn;
   A.rho = (const zd*)p.dmaps64.m[5];
   A.g = (zd*)g_iw;
-  A.scal = p.d_scalars;
-  A.partials = p.d_partials;
-  A.status = p.d_status;
+  A.scal = scal;
+  A.partials = partials;
+  A.status = status;
   A.r = p.r;
   A.nk = p.nk;
   A.mode = mode;
@@ -679,19 +801,54 @@ hipError_t dyson_g_no(const Plan& p, const void* h_k, const void* sig_iw, int mo
   A.beta = p.beta;
   A.tol_mu = 1e-13;
   A.tol_n = 1e-13;
+  return A;
+}
+
+// grid of the search: one block per 64 (node, k) points, capped at the resident limit
+template <int NO>
+hipError_t dyson_g_grid(const Plan& p, int& blocks) {
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dyson_g<NO>, 64, 0);
   if (e != hipSuccess) return e;
   int dev = 0, ncu = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
   int64_t need = (int64_t(p.r) * p.nk + 63) / 64;
   int64_t cap = int64_t(per_cu) * ncu;
   if (cap > p.max_blocks) cap = p.max_blocks;
-  const int blocks = int(need < cap ? need : cap);
-  if (blocks < 1) return hipErrorInvalidConfiguration;
+  blocks = int(need < cap ? need : cap);
+  return blocks < 1 ? hipErrorInvalidConfiguration : hipSuccess;
+}
+
+template <int NO>
+hipError_t dyson_g_no(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw, double* scal,
+                      double* partials, int* status, hipStream_t s) {
+  DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, mode, g_iw, scal, partials, status);
+  int blocks = 0;
+  hipError_t e = dyson_g_grid<NO>(p, blocks);
+  if (e != hipSuccess) return e;
   void* args[] = {&A};
   return hipLaunchCooperativeKernel((const void*)k_dyson_g<NO>, dim3(blocks), dim3(64), args, 0, s);
+}
+
+template <int NO>
+hipError_t dyson_g_chain_no(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
+                            double* scal, double* partials, int* status, int steps, hipStream_t s) {
+  DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, mode, g_iw, scal, partials, status);
+  int blocks = 0;
+  hipError_t e = dyson_g_grid<NO>(p, blocks);
+  if (e != hipSuccess) return e;
+  if (mode == 1) {
+    hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status);
+    for (int i = 0; i < steps; ++i) {
+      hipLaunchKernelGGL((k_dg_eval<NO>), dim3(blocks), dim3(64), 0, s, A);
+      hipLaunchKernelGGL(k_dg_newton, dim3(1), dim3(64), 0, s, A, blocks);
+    }
+  }
+  hipLaunchKernelGGL((k_dg_final<NO>), dim3(blocks), dim3(64), 0, s, A);
+  return hipGetLastError();
 }
 
 template <int NB>
@@ -774,10 +931,28 @@ hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void
 
 hipError_t launch_dyson_g(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                           hipStream_t s) {
+  return launch_dyson_g_state(p, h_k, sig_iw, mode, g_iw, p.d_scalars, p.d_partials, p.d_status, s);
+}
+
+hipError_t launch_dyson_g_state(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
+                                double* scal, double* partials, int* status, hipStream_t s) {
   switch (p.no) {
 #define QGW_CASE(NOV) \
   case NOV:           \
-    return dyson_g_no<NOV>(p, h_k, sig_iw, mode, g_iw, s);
+    return dyson_g_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s);
+    QGW_FOR_EACH_NO(QGW_CASE)
+#undef QGW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
+                                double* scal, double* partials, int* status, int steps, hipStream_t s) {
+  switch (p.no) {
+#define QGW_CASE(NOV) \
+  case NOV:           \
+    return dyson_g_chain_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, steps, s);
     QGW_FOR_EACH_NO(QGW_CASE)
 #undef QGW_CASE
     default:

@@ -89,6 +89,12 @@ hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStre
 // Dyson G.  mode 0: fixed mu (scalars[0]); mode 1: solve mu for scalars[1].
 hipError_t launch_dyson_g(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                           hipStream_t s);
+// the same with caller-owned scalars [16], partial sums [8 max_blocks] and status word
+hipError_t launch_dyson_g_state(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
+                                double* scal, double* partials, int* status, hipStream_t s);
+// graph-capturable form: `steps` evaluation / Newton-update launch pairs, then G
+hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
+                                double* scal, double* partials, int* status, int steps, hipStream_t s);
 hipError_t launch_slab_to_matrix_static(const Plan& p, const void* in, void* out, hipStream_t s);
 hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b, void* out,
                       hipStream_t s);

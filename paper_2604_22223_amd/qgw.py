@@ -32,7 +32,8 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_state_set_precision", "qgw_state_info", "qgw_check_finite",
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
-           "qgw_add", "qgw_last_error"]
+           "qgw_add", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
+           "qgw_last_error"]
 
 
 class QGWError(RuntimeError):
@@ -99,6 +100,10 @@ def lib():
             "qgw_dyson_G_bwd": [vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp],
             "qgw_pair_layout": [vp, i32, i32, i64, vp, vp, vp],
             "qgw_add": [vp, i64, vp, vp, vp, vp],
+            "qgw_batch_create": [i32, ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(vp)],
+            "qgw_batch_launch": [vp, vp],
+            "qgw_batch_read": [vp, pd, pd, pi32, vp],
+            "qgw_batch_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -361,3 +366,40 @@ class State:
         _check(lib().qgw_state_copy(self.handle, int(which), _ptr(out), ctypes.byref(nbytes), _stream()))
         assert nbytes.value == out.numel() * 16
         return out
+
+
+class Batch:
+    """Many started states advanced together by one graph launch (qgw_batch_*)."""
+
+    def __init__(self, states, precision=F64, n_iter=1, mu_steps=10):
+        self.states = list(states)
+        arr = (ctypes.c_void_p * len(self.states))(*[s.handle.value for s in self.states])
+        h = ctypes.c_void_p()
+        _check(lib().qgw_batch_create(len(self.states), arr, int(precision), int(n_iter), int(mu_steps),
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        _check(lib().qgw_batch_launch(self.handle, _stream()))
+
+    def read(self):
+        """(max |Delta Sigma|, mu, status) per state, after the stream has drained."""
+        n = len(self.states)
+        ds, mu = np.zeros(n), np.zeros(n)
+        st = np.zeros(n, dtype=np.int32)
+        _check(lib().qgw_batch_read(self.handle, ds.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream()))
+        return ds, mu, st
+
+    def close(self):
+        if self.handle:
+            lib().qgw_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
