@@ -158,9 +158,11 @@ hipError_t dlr_launch(const Plan& p, int map, int64_t ncols, int na, int nq, dou
 // r x r map with ~10^5-10^6 columns, done as four real products per 4-deep
 // slice on the 16x16x4 matrix cores (FP64 or FP32).  A block of 8 waves
 // keeps Re T and Im T in LDS ([16 MT][KP], zero padded); each wave computes a
-// strip of 16 columns for all rows.  Strips are ordered so that the 8 waves
-// of a block write 8 adjacent elements of every output run (128 bytes in
-// FP64), the input side reads 16 contiguous elements per 4-deep slice.
+// strip of 16 columns for all rows.  When the layout changes, the 16 lanes
+// of a strip run along the index that is contiguous in the output, so every
+// wave writes whole 256-byte (FP64) runs per row; the 8 waves of a block take
+// 8 adjacent values of the other index, so together they read whole lines
+// of the input.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Mfma;
@@ -204,18 +206,18 @@ __global__ __launch_bounds__(512) void k_dlr_mfma(const cpx<T>* __restrict__ in,
   for (int64_t strip = int64_t(blockIdx.x) * 8 + wave; strip < nstrips; strip += int64_t(gridDim.x) * 8) {
     int64_t cin, cout;
     bool valid;
-    if (MODE == kSlabToMatrix) {
-      const int64_t qb = strip / na;
-      const int a = int(strip - qb * na);
-      const int q = int(qb) * 16 + lc;
-      valid = q < nq;
-      cin = int64_t(a) * nq + q;
-      cout = int64_t(q) * na + a;
-    } else if (MODE == kMatrixToSlab) {
+    if (MODE == kSlabToMatrix) {  // lanes along a (contiguous in the output), strips along q
       const int64_t ab = strip / nq;
       const int q = int(strip - ab * nq);
       const int a = int(ab) * 16 + lc;
       valid = a < na;
+      cin = int64_t(a) * nq + q;
+      cout = int64_t(q) * na + a;
+    } else if (MODE == kMatrixToSlab) {  // lanes along q (contiguous in the output), strips along a
+      const int64_t qb = strip / na;
+      const int a = int(strip - qb * na);
+      const int q = int(qb) * 16 + lc;
+      valid = q < nq;
       cin = int64_t(q) * na + a;
       cout = int64_t(a) * nq + q;
     } else {
@@ -286,9 +288,9 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
   const int mt = (p.r + 15) / 16;
   int64_t nstrips;
   if (MODE == kSlabToMatrix)
-    nstrips = int64_t((nq + 15) / 16) * na;
-  else if (MODE == kMatrixToSlab)
     nstrips = int64_t((na + 15) / 16) * nq;
+  else if (MODE == kMatrixToSlab)
+    nstrips = int64_t((nq + 15) / 16) * na;
   else
     nstrips = (int64_t(na) * nq + 15) / 16;
   int dev = 0, ncu = 0;
