@@ -485,17 +485,26 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
   }
   double sc[2] = {*mu, n_target};
   QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, sizeof(sc), hipMemcpyHostToDevice, s), "qgw_dyson_G");
-  QGW_CHECK_HIP(launch_dyson_g_state(p, H_k, Sig_iw, mode, G_iw, scal, part, stat, s), "qgw_dyson_G launch");
-  double res[4];
+  QGW_CHECK_HIP(hipMemsetAsync(stat, 0, sizeof(int), s), "qgw_dyson_G");
+  if (mode == 1) QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, s), "qgw_dyson_G");
+  double res[8] = {};
   int st = 0;
-  QGW_CHECK_HIP(hipMemcpyAsync(res, scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
-  QGW_CHECK_HIP(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
-  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_dyson_G");
+  for (int round = 0;; ++round) {
+    // a few Newton evaluations, G at the current mu, one read-back; more rounds only if needed
+    if (mode == 1)
+      QGW_CHECK_HIP(launch_dyson_g_steps(p, H_k, Sig_iw, scal, part, stat, round == 0 ? 6 : 16, s), "qgw_dyson_G");
+    QGW_CHECK_HIP(launch_dyson_g_final(p, H_k, Sig_iw, mode, G_iw, scal, part, stat, s), "qgw_dyson_G");
+    QGW_CHECK_HIP(hipMemcpyAsync(res, scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
+    QGW_CHECK_HIP(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
+    QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_dyson_G");
+    if (mode == 0 || st != 2 || res[2] >= 200.0) break;
+    QGW_CHECK_HIP(hipMemsetAsync(stat, 0, sizeof(int), s), "qgw_dyson_G");
+  }
   if (mode == 1) {
     *mu = res[0];
     if (evals) *evals = res[2];
     if (st == 1) {
-      set_error("qgw_dyson_G: no bracket for the chemical potential");
+      set_error("qgw_dyson_G: no finite starting point for the chemical potential");
       return QGW_ERR_NOT_CONVERGED;
     }
     if (st == 2) {

@@ -72,6 +72,7 @@ __global__ __launch_bounds__(256) void k_dlr(const cpx<T>* __restrict__ in, cpx<
     }
   } else if (HERM == 1) {
     const T h = T(0.5);
+#pragma unroll 4
     for (int t = 0; t < r; ++t) {
       cpx<T> x = mk(T(0), T(0));
       if (valid) x = scale(src[int64_t(t) * plane] + conj(srcs[int64_t(t) * plane]), h);
@@ -82,6 +83,7 @@ __global__ __launch_bounds__(256) void k_dlr(const cpx<T>* __restrict__ in, cpx<
     cpx<T> acc2[MT];
 #pragma unroll
     for (int mm = 0; mm < MT; ++mm) acc2[mm] = mk(T(0), T(0));
+#pragma unroll 4
     for (int t = 0; t < r; ++t) {
       cpx<T> x = mk(T(0), T(0)), y = mk(T(0), T(0));
       if (valid) {

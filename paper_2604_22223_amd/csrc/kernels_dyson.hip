@@ -16,20 +16,16 @@
 // Green's function (Eq. full-green-freq): one thread per (fermionic node, k)
 // inverts the n_o x n_o matrix (i w + mu) - H(k) - Sigma(k, i w) in registers
 // (in-place Gauss-Jordan with partial pivoting).  The chemical potential for
-// the target filling is found inside one cooperative launch by a safeguarded
-// Newton iteration on N_e(mu) = -2/N_k sum_{k,m} Re rho_m Tr G(k, i w_m), with
+// the target filling comes from a safeguarded Newton iteration on
+// N_e(mu) = -2/N_k sum_{k,m} Re rho_m Tr G(k, i w_m), with
 // dN_e/dmu = 2/N_k sum Re rho_m Tr G^2 (dG/dmu = -G^2): steps stay inside the
 // sign-change bracket once one is known (bisection otherwise) and are capped
-// before.  Each evaluation ends in a grid-wide barrier after which every block
-// sums the same per-block partials in the same order, so all blocks take
-// identical steps.
-#include <hip/hip_cooperative_groups.h>
-
+// before.  Each evaluation is one launch that writes per-block partial sums;
+// a one-block launch sums them in a fixed order and takes the step, so the
+// search is deterministic and needs no grid-wide barrier.
 #include <cmath>
 
 #include "qgw_internal.h"
-
-namespace cg = cooperative_groups;
 
 namespace qgw {
 
@@ -272,155 +268,54 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// N_e(mu) and dN_e/dmu; ends with a grid barrier
-template <int NO>
-__device__ __forceinline__ void count_electrons(const DysonGArgs& A, double mu, cg::grid_group& grid, int buf,
-                                             double& n_e, double& dn_e) {
-  const int64_t total = int64_t(A.r) * A.nk;
-  const int64_t stride = int64_t(gridDim.x) * 64;
-  double acc = 0.0, accd = 0.0;
-  for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
-    cpx<double> a[NO][NO];
-    load_base<NO>(A, gi, a);
-#pragma unroll
-    for (int i = 0; i < NO; ++i) a[i][i].re += mu;
-    invert_inplace<NO>(a);
-    cpx<double> tr = mk(0.0, 0.0), tr2 = mk(0.0, 0.0);
-#pragma unroll
-    for (int i = 0; i < NO; ++i) {
-      tr = tr + a[i][i];
-#pragma unroll
-      for (int j = 0; j < NO; ++j) tr2 = fma(tr2, a[i][j], a[j][i]);
-    }
-    const zd rh = A.rho[int(gi / A.nk)];
-    acc += rh.re * tr.re - rh.im * tr.im;
-    accd += rh.re * tr2.re - rh.im * tr2.im;
-  }
-  acc = wave_sum(acc);
-  accd = wave_sum(accd);
-  double* part = A.partials + int64_t(buf) * 4 * gridDim.x;
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = acc;
-    part[gridDim.x + blockIdx.x] = accd;
-  }
-  grid.sync();
-  double s = 0.0, sd = 0.0;
-  for (int b = threadIdx.x; b < int(gridDim.x); b += 64) {
-    s += part[b];
-    sd += part[gridDim.x + b];
-  }
-  s = wave_sum(s);
-  sd = wave_sum(sd);
-  n_e = -2.0 * s / double(A.nk);
-  dn_e = 2.0 * sd / double(A.nk);
-}
-
-template <int NO>
-__global__ __launch_bounds__(64) void k_dyson_g(DysonGArgs A) {
-  cg::grid_group grid = cg::this_grid();
-  const int64_t total = int64_t(A.r) * A.nk;
-  const int64_t stride = int64_t(gridDim.x) * 64;
-  double mu = A.scal[0];
-  int status = 0, evals = 0;
-  double n_final = 0.0;
-  if (A.mode == 1) {
-    const double nt = A.scal[1];
-    if (!isfinite(mu)) {
-      // no starting point: the centre of the Gershgorin bounds of H
-      double glo = 1e300, ghi = -1e300;
-      for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
-        const int k = int(gi % A.nk);
-#pragma unroll
-        for (int i = 0; i < NO; ++i) {
-          double rad = 0.0;
-#pragma unroll
-          for (int j = 0; j < NO; ++j)
-            if (j != i) rad += sqrt(norm2(A.hk[(int64_t(i) * NO + j) * A.nk + k]));
-          const double d = A.hk[(int64_t(i) * NO + i) * A.nk + k].re;
-          glo = fmin(glo, d - rad);
-          ghi = fmax(ghi, d + rad);
-        }
-      }
-      glo = wave_min(glo);
-      ghi = wave_max(ghi);
-      double* part = A.partials + int64_t(1) * 4 * gridDim.x;
-      if (threadIdx.x == 0) {
-        part[2 * gridDim.x + blockIdx.x] = glo;
-        part[3 * gridDim.x + blockIdx.x] = ghi;
-      }
-      grid.sync();
-      glo = 1e300;
-      ghi = -1e300;
-      for (int b = threadIdx.x; b < int(gridDim.x); b += 64) {
-        glo = fmin(glo, part[2 * gridDim.x + b]);
-        ghi = fmax(ghi, part[3 * gridDim.x + b]);
-      }
-      mu = 0.5 * (wave_min(glo) + wave_max(ghi));
-    }
-    double lo = -INFINITY, hi = INFINITY, cap = 1.0;
-    bool done = false;
-    int buf = 0;
-    for (int it = 0; it < A.max_evals && !done; ++it) {
-      double ne, dne;
-      count_electrons<NO>(A, mu, grid, buf, ne, dne);
-      buf ^= 1;
-      ++evals;
-      const double f = ne - nt;
-      n_final = ne;
-      if (f < 0.0) lo = fmax(lo, mu);
-      if (f > 0.0) hi = fmin(hi, mu);
-      if (fabs(f) <= A.tol_n) break;
-      double nxt = (dne > 0.0) ? mu - f / dne : NAN;
-      const bool bracket = isfinite(lo) && isfinite(hi);
-      if (bracket) {
-        if (!(nxt > lo && nxt < hi)) nxt = 0.5 * (lo + hi);
-      } else {
-        if (!isfinite(nxt)) nxt = mu + (f < 0.0 ? cap : -cap);
-        if (fabs(nxt - mu) > cap) {
-          nxt = mu + (nxt > mu ? cap : -cap);
-          cap *= 4.0;
-        }
-      }
-      const double tol = A.tol_mu * fmax(1.0, fabs(mu));
-      if (fabs(nxt - mu) <= tol || (bracket && hi - lo <= tol)) done = true;
-      mu = nxt;
-    }
-    if (!done && !(fabs(n_final - nt) <= A.tol_n)) status = 2;
-  }
-  // G at the final mu
-  for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
-    cpx<double> a[NO][NO];
-    load_base<NO>(A, gi, a);
-#pragma unroll
-    for (int i = 0; i < NO; ++i) a[i][i].re += mu;
-    invert_inplace<NO>(a);
-    const int m = int(gi / A.nk), k = int(gi - int64_t(m) * A.nk);
-#pragma unroll
-    for (int i = 0; i < NO; ++i)
-#pragma unroll
-      for (int j = 0; j < NO; ++j) A.g[((int64_t(m) * NO + i) * NO + j) * A.nk + k] = a[i][j];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    A.scal[0] = mu;
-    A.scal[2] = double(evals);
-    A.scal[3] = n_final;
-    A.status[0] = status;
-  }
-}
-
 // ---------------------------------------------------------------------------
-// The same chemical-potential search as a chain of ordinary launches, for
-// callers that capture the iteration into a graph (no grid barrier, no host
-// round trip).  The search state lives in the scalar block:
+// The search as a chain of launches.  Its state lives in the scalar block:
 //   [0] mu  [1] n_target  [2] evaluations  [3] last N_e  [4] lo  [5] hi
 //   [6] step cap  [7] done flag
-// k_dg_eval and k_dg_newton alternate a fixed number of times; once the
-// search has converged the remaining launches return at once.  The grid
-// size and the summation order equal those of k_dyson_g, so both give the
-// same iterates and the same G.
+// k_dg_eval and k_dg_newton alternate; once the search has converged the
+// remaining launches return at once, so a caller may queue a fixed number of
+// steps (graph capture) or queue a few, read the done flag and continue.
 // ---------------------------------------------------------------------------
-__global__ void k_dg_begin(double* __restrict__ scal, int* __restrict__ status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+
+// partial Gershgorin bounds of H(k) (no starting point given)
+template <int NO>
+__global__ __launch_bounds__(64) void k_dg_gersh(DysonGArgs A) {
+  if (isfinite(A.scal[0])) return;
+  double glo = 1e300, ghi = -1e300;
+  for (int64_t k = int64_t(blockIdx.x) * 64 + threadIdx.x; k < A.nk; k += int64_t(gridDim.x) * 64) {
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      double rad = 0.0;
+#pragma unroll
+      for (int j = 0; j < NO; ++j)
+        if (j != i) rad += sqrt(norm2(A.hk[(int64_t(i) * NO + j) * A.nk + k]));
+      const double d = A.hk[(int64_t(i) * NO + i) * A.nk + k].re;
+      glo = fmin(glo, d - rad);
+      ghi = fmax(ghi, d + rad);
+    }
+  }
+  glo = wave_min(glo);
+  ghi = wave_max(ghi);
+  if (threadIdx.x == 0) {
+    A.partials[blockIdx.x] = glo;
+    A.partials[gridDim.x + blockIdx.x] = ghi;
+  }
+}
+
+// mu <- centre of the Gershgorin bounds if no finite start was given; resets the search
+__global__ __launch_bounds__(64) void k_dg_begin(double* __restrict__ scal, int* __restrict__ status,
+                                                 const double* __restrict__ partials, int nblk) {
+  if (!isfinite(scal[0])) {
+    double glo = 1e300, ghi = -1e300;
+    for (int b = threadIdx.x; b < nblk; b += 64) {
+      glo = fmin(glo, partials[b]);
+      ghi = fmax(ghi, partials[nblk + b]);
+    }
+    glo = wave_min(glo);
+    ghi = wave_max(ghi);
+    if (threadIdx.x == 0) scal[0] = 0.5 * (glo + ghi);
+  }
+  if (threadIdx.x != 0) return;
   const bool ok = isfinite(scal[0]);
   scal[2] = 0.0;
   scal[3] = 0.0;
@@ -804,50 +699,39 @@ DysonGArgs dyson_g_args(const Plan& p, const void* h_k, const void* sig_iw, int 
   return A;
 }
 
-// grid of the search: one block per 64 (node, k) points, capped at the resident limit
-template <int NO>
-hipError_t dyson_g_grid(const Plan& p, int& blocks) {
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dyson_g<NO>, 64, 0);
-  if (e != hipSuccess) return e;
-  int dev = 0, ncu = 0;
-  e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return e;
-  int64_t need = (int64_t(p.r) * p.nk + 63) / 64;
-  int64_t cap = int64_t(per_cu) * ncu;
-  if (cap > p.max_blocks) cap = p.max_blocks;
-  blocks = int(need < cap ? need : cap);
-  return blocks < 1 ? hipErrorInvalidConfiguration : hipSuccess;
+// grid of the search: one block per 64 (node, k) points, at most max_blocks (grid-stride beyond)
+static int dyson_g_blocks(const Plan& p) {
+  const int64_t need = (int64_t(p.r) * p.nk + 63) / 64;
+  return int(need < p.max_blocks ? need : p.max_blocks);
 }
 
 template <int NO>
-hipError_t dyson_g_no(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw, double* scal,
-                      double* partials, int* status, hipStream_t s) {
-  DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, mode, g_iw, scal, partials, status);
-  int blocks = 0;
-  hipError_t e = dyson_g_grid<NO>(p, blocks);
-  if (e != hipSuccess) return e;
-  void* args[] = {&A};
-  return hipLaunchCooperativeKernel((const void*)k_dyson_g<NO>, dim3(blocks), dim3(64), args, 0, s);
+hipError_t dyson_g_begin_no(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
+                            hipStream_t s) {
+  DysonGArgs A = dyson_g_args<NO>(p, h_k, nullptr, 1, nullptr, scal, partials, status);
+  const int gb = int((p.nk + 63) / 64 < 1024 ? (p.nk + 63) / 64 : 1024);
+  hipLaunchKernelGGL((k_dg_gersh<NO>), dim3(gb), dim3(64), 0, s, A);
+  hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status, (const double*)partials, gb);
+  return hipGetLastError();
 }
 
 template <int NO>
-hipError_t dyson_g_chain_no(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                            double* scal, double* partials, int* status, int steps, hipStream_t s) {
-  DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, mode, g_iw, scal, partials, status);
-  int blocks = 0;
-  hipError_t e = dyson_g_grid<NO>(p, blocks);
-  if (e != hipSuccess) return e;
-  if (mode == 1) {
-    hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status);
-    for (int i = 0; i < steps; ++i) {
-      hipLaunchKernelGGL((k_dg_eval<NO>), dim3(blocks), dim3(64), 0, s, A);
-      hipLaunchKernelGGL(k_dg_newton, dim3(1), dim3(64), 0, s, A, blocks);
-    }
+hipError_t dyson_g_steps_no(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
+                            int* status, int steps, hipStream_t s) {
+  DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, 1, nullptr, scal, partials, status);
+  const int blocks = dyson_g_blocks(p);
+  for (int i = 0; i < steps; ++i) {
+    hipLaunchKernelGGL((k_dg_eval<NO>), dim3(blocks), dim3(64), 0, s, A);
+    hipLaunchKernelGGL(k_dg_newton, dim3(1), dim3(64), 0, s, A, blocks);
   }
-  hipLaunchKernelGGL((k_dg_final<NO>), dim3(blocks), dim3(64), 0, s, A);
+  return hipGetLastError();
+}
+
+template <int NO>
+hipError_t dyson_g_final_no(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
+                            double* scal, double* partials, int* status, hipStream_t s) {
+  DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, mode, g_iw, scal, partials, status);
+  hipLaunchKernelGGL((k_dg_final<NO>), dim3(dyson_g_blocks(p)), dim3(64), 0, s, A);
   return hipGetLastError();
 }
 
@@ -929,35 +813,45 @@ hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void
   }
 }
 
-hipError_t launch_dyson_g(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                          hipStream_t s) {
-  return launch_dyson_g_state(p, h_k, sig_iw, mode, g_iw, p.d_scalars, p.d_partials, p.d_status, s);
+#define QGW_NO_SWITCH(CALL)    \
+  switch (p.no) {              \
+    case 1: { constexpr int NOV = 1; return CALL; } \
+    case 2: { constexpr int NOV = 2; return CALL; } \
+    case 3: { constexpr int NOV = 3; return CALL; } \
+    case 4: { constexpr int NOV = 4; return CALL; } \
+    case 5: { constexpr int NOV = 5; return CALL; } \
+    case 6: { constexpr int NOV = 6; return CALL; } \
+    case 7: { constexpr int NOV = 7; return CALL; } \
+    case 8: { constexpr int NOV = 8; return CALL; } \
+    default: return hipErrorInvalidValue;          \
+  }
+
+hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
+                                hipStream_t s) {
+  QGW_NO_SWITCH((dyson_g_begin_no<NOV>(p, h_k, scal, partials, status, s)))
 }
 
-hipError_t launch_dyson_g_state(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
+hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
+                                int* status, int steps, hipStream_t s) {
+  QGW_NO_SWITCH((dyson_g_steps_no<NOV>(p, h_k, sig_iw, scal, partials, status, steps, s)))
+}
+
+hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, hipStream_t s) {
-  switch (p.no) {
-#define QGW_CASE(NOV) \
-  case NOV:           \
-    return dyson_g_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s);
-    QGW_FOR_EACH_NO(QGW_CASE)
-#undef QGW_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
+  QGW_NO_SWITCH((dyson_g_final_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s)))
 }
 
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, int steps, hipStream_t s) {
-  switch (p.no) {
-#define QGW_CASE(NOV) \
-  case NOV:           \
-    return dyson_g_chain_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, steps, s);
-    QGW_FOR_EACH_NO(QGW_CASE)
-#undef QGW_CASE
-    default:
-      return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+  if (mode == 1) {
+    e = launch_dyson_g_begin(p, h_k, scal, partials, status, s);
+    if (e == hipSuccess) e = launch_dyson_g_steps(p, h_k, sig_iw, scal, partials, status, steps, s);
   }
+  if (e == hipSuccess) e = launch_dyson_g_final(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s);
+  return e;
 }
+
+#undef QGW_NO_SWITCH
 
 }  // namespace qgw

@@ -86,13 +86,19 @@ hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void
 hipError_t launch_hartree_fock(const Plan& p, const void* v_r, const void* v_q0, const void* n_r,
                                void* sig_hf_r, hipStream_t s);
 hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStream_t s);
-// Dyson G.  mode 0: fixed mu (scalars[0]); mode 1: solve mu for scalars[1].
-hipError_t launch_dyson_g(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                          hipStream_t s);
-// the same with caller-owned scalars [16], partial sums [8 max_blocks] and status word
-hipError_t launch_dyson_g_state(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
+// Dyson G with the chemical-potential search as a chain of launches.  Scalar
+// block scal[16] ([0] mu, [1] n_target, [2] evaluations, [3] last N_e,
+// [4-6] bracket and step cap, [7] done flag), partial sums [8 max_blocks],
+// status word.  begin: Gershgorin start if mu is not finite, resets the
+// search; steps: `steps` Newton evaluations (no-ops once done); final: G at
+// mu (mode 0: mu as given; mode 1: also status 2 if the search has not
+// converged).  chain = begin + steps + final (graph-capturable).
+hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
+                                hipStream_t s);
+hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
+                                int* status, int steps, hipStream_t s);
+hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, hipStream_t s);
-// graph-capturable form: `steps` evaluation / Newton-update launch pairs, then G
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, int steps, hipStream_t s);
 hipError_t launch_slab_to_matrix_static(const Plan& p, const void* in, void* out, hipStream_t s);

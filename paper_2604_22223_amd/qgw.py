@@ -371,7 +371,7 @@ class State:
 class Batch:
     """Many started states advanced together by one graph launch (qgw_batch_*)."""
 
-    def __init__(self, states, precision=F64, n_iter=1, mu_steps=10):
+    def __init__(self, states, precision=F64, n_iter=1, mu_steps=12):
         self.states = list(states)
         arr = (ctypes.c_void_p * len(self.states))(*[s.handle.value for s in self.states])
         h = ctypes.c_void_p()
