@@ -24,6 +24,7 @@
 // a one-block launch sums them in a fixed order and takes the step, so the
 // search is deterministic and needs no grid-wide barrier.
 #include <cmath>
+#include <utility>
 
 #include "qgw_internal.h"
 
@@ -157,6 +158,221 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
   }
   __syncthreads();
   for (int e = lane; e < nload; e += 64) wc[mat0 * S::NN + e] = sp[e];
+}
+
+// ---------------------------------------------------------------------------
+// Register-blocked form of the same solve for N_b = 25 (the five-orbital
+// product basis).  One wavefront per (node, q) matrix; the augmented system
+// [I - V P | V] (25 x 50) is split into blocks of 4 rows x 7 columns, lane
+// = 8 cg + rg holding rows 4 rg .. 4 rg + 3 and columns 7 cg .. 7 cg + 6
+// (rows >= 25 and columns >= 50 are zero padding).  A Gauss-Jordan step
+// reads the pivot row's 7 columns and the 4 multipliers of its rows from LDS
+// and does 28 complex updates, so every value read is used four times.  The
+// pivot row is found by an arg-max over the 8 lanes that hold column k (the
+// lane index of that group, the column slot and the step are compile-time
+// constants; the winner is read back with a wave-uniform readlane), and the
+// pivot row's owner writes it through a wave-uniform branch on its slot, so
+// no register array is indexed dynamically.
+// ---------------------------------------------------------------------------
+// lane l takes the (value, index) of lane l + n of its DPP row (row_shl:n) if
+// that value is larger; lanes without a source keep their own
+template <int CTRL>
+__device__ __forceinline__ int dpp_shl_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_shl(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_shl_i<CTRL>(int(b & 0xffffffffLL));
+  const int hi = dpp_shl_i<CTRL>(int(b >> 32));
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_shl(float v) {
+  return __int_as_float(dpp_shl_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ void dpp_argmax_step(T& bv, int& bi) {
+  const T ov = dpp_shl<CTRL>(bv);
+  const int oi = dpp_shl_i<CTRL>(bi);
+  if (ov > bv) {
+    bv = ov;
+    bi = oi;
+  }
+}
+
+// one Gauss-Jordan step of k_dyson_w25 on column K (K a compile-time constant)
+template <typename T, int K>
+__device__ __forceinline__ void gj25_step(cpx<T> (&x)[4][7], bool (&used)[4], int (&step_of)[4], int rg, int cg,
+                                          cpx<T> (*prow)[56], cpx<T> (*mult)[32]) {
+  constexpr int NB = 25, RPL = 4, CPL = 7;
+  constexpr int cgk = K / CPL, ck = K % CPL, buf = K & 1;
+  // arg-max of |a_rk| over the unused rows, in the 8 lanes holding column K
+  T bv = T(-1);
+  int bi = rg * RPL;
+  if (cg == cgk) {
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int row = rg * RPL + s;
+      const T v = (row < NB && !used[s]) ? norm2(x[s][ck]) : T(-1);
+      if (v > bv) {
+        bv = v;
+        bi = row;
+      }
+    }
+  }
+  // shift reductions inside the 16-lane DPP row: after the three rounds the
+  // group's first lane holds the arg-max of its 8 lanes (on ties the lower
+  // lane, i.e. the lower row, stays)
+  dpp_argmax_step<0x104>(bv, bi);
+  dpp_argmax_step<0x102>(bv, bi);
+  dpp_argmax_step<0x101>(bv, bi);
+  const int p = __builtin_amdgcn_readlane(bi, cgk * 8);
+  const int rgp = p >> 2, sp = p & 3;
+  // the pivot row's owners publish it; the column-K owners publish the multipliers
+  if (rg == rgp) {
+    if (sp == 0) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) prow[buf][cg * CPL + c] = x[0][c];
+      used[0] = true;
+      step_of[0] = K;
+    } else if (sp == 1) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) prow[buf][cg * CPL + c] = x[1][c];
+      used[1] = true;
+      step_of[1] = K;
+    } else if (sp == 2) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) prow[buf][cg * CPL + c] = x[2][c];
+      used[2] = true;
+      step_of[2] = K;
+    } else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) prow[buf][cg * CPL + c] = x[3][c];
+      used[3] = true;
+      step_of[3] = K;
+    }
+  }
+  if (cg == cgk) {
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) mult[buf][rg * RPL + s] = x[s][ck];
+  }
+  __syncthreads();
+  cpx<T> pr[CPL], f[RPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) pr[c] = prow[buf][cg * CPL + c];
+  const cpx<T> pinv = inv(prow[buf][K]);
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const bool is_p = (rg == rgp) && (s == sp);
+    f[s] = is_p ? mk(T(1), T(0)) - pinv : mult[buf][rg * RPL + s] * pinv;
+  }
+#pragma unroll
+  for (int s = 0; s < RPL; ++s)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) x[s][c] = fms(x[s][c], f[s], pr[c]);
+}
+
+template <typename T, int... K>
+__device__ __forceinline__ void gj25_all(cpx<T> (&x)[4][7], bool (&used)[4], int (&step_of)[4], int rg, int cg,
+                                         cpx<T> (*prow)[56], cpx<T> (*mult)[32], std::integer_sequence<int, K...>) {
+  (gj25_step<T, K>(x, used, step_of, rg, cg, prow, mult), ...);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
+                                                  cpx<T>* __restrict__ wc, int64_t nmat, int nk) {
+  constexpr int NB = 25, NN = NB * NB, RPL = 4, CPL = 7, NCOL = 8 * CPL;
+  __shared__ cpx<T> sbuf[NN];          // P, then I - V P, then W^C for the store
+  __shared__ cpx<T> sv[NN];            // V(q)
+  __shared__ cpx<T> prow[2][NCOL];     // pivot row (double-buffered by step parity)
+  __shared__ cpx<T> mult[2][8 * RPL];  // column k of every row
+  const int lane = threadIdx.x;
+  const int rg = lane & 7, cg = lane >> 3;
+  const int64_t mat = blockIdx.x;
+  const int q = int(mat % nk);
+  const cpx<T>* vm = vq + int64_t(q) * NN;
+  const cpx<T> zero = mk(T(0), T(0));
+  for (int e = lane; e < NN; e += 64) {
+    sbuf[e] = pnu[mat * NN + e];
+    sv[e] = vm[e];
+  }
+  __syncthreads();
+  // V P by 52 lanes: lane = 13 r7 + c2 (r7 < 4) owns rows 7 r7 .. 7 r7 + 6 and columns 2 c2, 2 c2 + 1
+  {
+    const int r7 = lane / 13, c2 = lane - 13 * (lane / 13);
+    const bool act = r7 < 4;
+    const int ca = 2 * c2, cb = 2 * c2 + 1 < NB ? 2 * c2 + 1 : NB - 1;
+    cpx<T> acc[7][2];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc[i][0] = acc[i][1] = zero;
+    if (act) {
+      for (int j = 0; j < NB; ++j) {
+        const cpx<T> pa = sbuf[j * NB + ca], pb = sbuf[j * NB + cb];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+          const int row = 7 * r7 + i < NB ? 7 * r7 + i : NB - 1;
+          const cpx<T> v = sv[row * NB + j];
+          acc[i][0] = fma(acc[i][0], v, pa);
+          acc[i][1] = fma(acc[i][1], v, pb);
+        }
+      }
+    }
+    __syncthreads();  // every lane has read P
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        const int row = 7 * r7 + i;
+        if (row < NB) {
+          sbuf[row * NB + ca] = mk(T(row == ca ? 1 : 0) - acc[i][0].re, -acc[i][0].im);
+          if (2 * c2 + 1 < NB) sbuf[row * NB + cb] = mk(T(row == cb ? 1 : 0) - acc[i][1].re, -acc[i][1].im);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // this lane's block of [I - V P | V]
+  cpx<T> x[RPL][CPL];
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const int row = rg * RPL + s;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int col = cg * CPL + c;
+      cpx<T> val = zero;
+      if (row < NB) {
+        if (col < NB)
+          val = sbuf[row * NB + col];
+        else if (col < 2 * NB)
+          val = sv[row * NB + col - NB];
+      }
+      x[s][c] = val;
+    }
+  }
+  bool used[RPL];
+  int step_of[RPL];
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    used[s] = false;
+    step_of[s] = 0;
+  }
+  gj25_all<T>(x, used, step_of, rg, cg, prow, mult, std::make_integer_sequence<int, NB>{});
+  // row r of the V part is row step_of[r] of W; W^C = W - V, staged for a contiguous store
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const int row = rg * RPL + s;
+    if (row < NB) {
+      const int k = step_of[s];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int col = cg * CPL + c - NB;
+        if (col >= 0 && col < NB) sbuf[k * NB + col] = x[s][c] - sv[k * NB + col];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = lane; e < NN; e += 64) wc[mat * NN + e] = sbuf[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -671,6 +887,11 @@ template <int NB, typename T>
 hipError_t dyson_w_nb(const Plan& p, const void* v_q, const void* p_nu, void* wc_nu, hipStream_t s) {
   constexpr int MPW = DysonWShape<NB>::MPW;
   const int64_t nmat = int64_t(p.r) * p.nk;
+  if (NB == 25) {
+    hipLaunchKernelGGL((k_dyson_w25<T>), dim3(unsigned(nmat)), dim3(64), 0, s, (const cpx<T>*)v_q,
+                       (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk);
+    return hipGetLastError();
+  }
   const unsigned blocks = unsigned((nmat + MPW - 1) / MPW);
   hipLaunchKernelGGL((k_dyson_w<NB, T>), dim3(blocks), dim3(64), 0, s, (const cpx<T>*)v_q,
                      (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk);
