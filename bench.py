@@ -159,6 +159,66 @@ def timed_solves(torch, st, mode, tol, steps):
     return time.perf_counter() - t0
 
 
+def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
+    """Seeded instances of uneven size (1-5 orbitals, 12^2-48^2 meshes, beta 10-100) advanced by one
+    graph launch per iteration, FP64 and FP32 bulk steps, against the same states iterated one by one."""
+    from paper_2604_22223_amd import workloads as wl
+    t0 = time.perf_counter()
+    ws = wl.batch_sweep(count)
+    plans, states, t_tune = [], [], 0.0
+    flat = lambda x: torch.from_numpy(np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))).to("cuda:0")
+    for w in ws:
+        nodes = qgw.dlr_build(w["beta"] * w["omega_max"], w["eps"])
+        nodes["omega"] = nodes["x"] / w["beta"]
+        pl = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], nodes)
+        t1 = time.perf_counter()
+        pl.autotune()
+        t_tune += time.perf_counter() - t1
+        st = qgw.State(pl, flat(w["H_R"]), flat(w["V_R"]), n_target=w["n_target"])
+        st.init_g0()
+        plans.append(pl)
+        states.append(st)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    log("[bench] batch: %d instances built in %.1f s (autotuning %.1f s)" % (count, setup, t_tune))
+    res = {"instances": count, "launches": launches, "setup_s": round(setup, 2), "autotune_s": round(t_tune, 2),
+           "mu_steps_per_iteration": mu_steps,
+           "recipe": "workloads.batch_sweep(%d): n_o 1-5, meshes 12^2-48^2, beta 10-100/eV, U 1-6 eV" % count}
+    # one by one (eager), FP64
+    for st in states:
+        st.iterate(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(launches):
+        for st in states:
+            st.iterate(1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res["eager_fp64"] = {"instance_iterations_per_s": round(count * launches / el, 2), "s_per_sweep": round(el / launches, 5)}
+    log("[bench] batch eager FP64: %.4f s per sweep of %d instances" % (el / launches, count))
+    for name, prec in (("graph_fp64", qgw.F64), ("graph_fp32", qgw.F32)):
+        b = qgw.Batch(states, precision=prec, n_iter=1, mu_steps=mu_steps)
+        for _ in range(warmup):
+            b.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(launches):
+            b.launch()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ds, mu, status = b.read()
+        res[name] = {"instance_iterations_per_s": round(count * launches / el, 2), "s_per_sweep": round(el / launches, 5),
+                     "unconverged_mu_searches": int(np.count_nonzero(status))}
+        log("[bench] batch %s: %.4f s per sweep (%d unconverged mu searches)" % (name, el / launches,
+                                                                              int(np.count_nonzero(status))))
+        b.close()
+    for st in states:
+        st.close()
+    for pl in plans:
+        pl.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +226,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--batch", type=int, default=64, metavar="N",
+                    help="instances of the batched leg (0 skips it)")
+    ap.add_argument("--batch-launches", type=int, default=5)
+    ap.add_argument("--batch-mu-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer three times (a plain copy kernel of known size "
                          "that scales the HBM byte counters of a profiler run)")
@@ -257,6 +321,8 @@ def main():
                 "frac": dd["frac"], "traffic": dd["traffic"], "kernel": dom,
                 "per_launch": dict(dd["per_launch"], ms=dd["ms"])}
 
+    batch = batch_leg(torch, qgw, a.batch, a.batch_launches, 1, a.batch_mu_steps) if a.batch > 0 else None
+
     cpu = None
     if not a.no_cpu_baseline:
         log("[bench] CPU baseline: oracle iterations on the host ...")
@@ -281,6 +347,7 @@ def main():
         "sigma_diff_chosen_vs_fp64": sig_diff,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batch": batch,
         "steps_detail": steps,
     }
     print(json.dumps(out), flush=True)

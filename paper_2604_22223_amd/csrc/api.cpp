@@ -22,10 +22,6 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 using namespace qgw;
 
-struct qgw_plan_s {
-  Plan p;
-};
-
 struct qgw_state_s {
   qgw_plan plan = nullptr;
   double n_target = 0.0, mixing = 1.0, mu = 0.0;
@@ -869,6 +865,7 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
   const Plan& p = st->plan->p;
   const int64_t no2 = int64_t(p.no) * p.no;
   const int64_t ncol_g = no2 * p.nk;
+  st->p32.tune = p.tune;
   hipError_t e = hipSuccess;
   auto mark = [&](int i) { if (e == hipSuccess && prof) e = hipEventRecord(st->ev[i], s); };
   auto run = [&](hipError_t r) { if (e == hipSuccess) e = r; };

@@ -125,7 +125,8 @@ hipError_t dlr_launch(const Plan& p, int map, int64_t ncols, int na, int nq, dou
   const int rows_out = (map == 5) ? 1 : p.r;
   // small column counts: 64-thread blocks and 8-row chunks for enough blocks
   const bool small = (MODE == kPlain) && ncols <= 65536;
-  const int mt = small ? 8 : d.mt;
+  int mt = small ? 8 : d.mt;
+  if (MODE == kPlain && p.tune.orb_mt > 0) mt = p.tune.orb_mt;
   const int bs = small ? 64 : 256;
   const unsigned chunks = unsigned((rows_out + mt - 1) / mt);
   unsigned bx;
@@ -299,7 +300,8 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   int64_t blocks = (nstrips + 7) / 8;
-  if (blocks > 2 * ncu) blocks = 2 * ncu;
+  const int bpc = p.tune.mfma_bpc > 0 ? p.tune.mfma_bpc : 2;
+  if (blocks > int64_t(bpc) * ncu) blocks = int64_t(bpc) * ncu;
   const size_t lds = size_t(2) * mt * 16 * kp * sizeof(T);
   const cpx<T>* mp = map_ptr<T>(p, map);
 #define QGW_MFMA_MT(MTV)                                                                                 \
@@ -325,7 +327,7 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
 hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double sim, const void* in,
                       void* out, hipStream_t s, int herm) {
   const int64_t ng = int64_t(p.no) * p.no * p.nk;
-  if (p.r <= 64 && map != 5 && herm != 2 && (herm == 0 || ncols == ng)) {
+  if (p.r <= 64 && map != 5 && herm != 2 && (herm == 0 || ncols == ng) && p.tune.orb_valu != 1) {
     const int na = herm ? p.no * p.no : 1;
     const int nq = herm ? p.nk : int(ncols);
     if (herm == 0 && ncols > (int64_t(1) << 30)) return hipErrorInvalidValue;

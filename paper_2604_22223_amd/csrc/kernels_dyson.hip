@@ -258,19 +258,20 @@ __device__ __forceinline__ void gj25_step(cpx<T> (&x)[4][7], bool (&used)[4], in
     for (int s = 0; s < RPL; ++s) mult[buf][rg * RPL + s] = x[s][ck];
   }
   __syncthreads();
-  cpx<T> pr[CPL], f[RPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) pr[c] = prow[buf][cg * CPL + c];
+  cpx<T> f[RPL];
   const cpx<T> pinv = inv(prow[buf][K]);
 #pragma unroll
   for (int s = 0; s < RPL; ++s) {
     const bool is_p = (rg == rgp) && (s == sp);
     f[s] = is_p ? mk(T(1), T(0)) - pinv : mult[buf][rg * RPL + s] * pinv;
   }
+  // column by column, so that only one pivot-row value is live at a time
 #pragma unroll
-  for (int s = 0; s < RPL; ++s)
+  for (int c = 0; c < CPL; ++c) {
+    const cpx<T> pc = prow[buf][cg * CPL + c];
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) x[s][c] = fms(x[s][c], f[s], pr[c]);
+    for (int s = 0; s < RPL; ++s) x[s][c] = fms(x[s][c], f[s], pc);
+  }
 }
 
 template <typename T, int... K>

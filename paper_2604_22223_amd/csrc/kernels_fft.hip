@@ -247,6 +247,14 @@ namespace {
 
 constexpr int kLdsBudget = 64 * 1024;
 
+// slabs per block: the tuned value if set (within the LDS and 256-thread limits), else the default
+template <typename T>
+int tuned_spb(int n, int want) {
+  const int cap = slabs_per_block<T>(n, kLdsBudget);
+  if (want <= 0) return cap;
+  return want < cap ? want : cap;
+}
+
 template <typename T>
 const cpx<T>* twiddles(const Plan& p);
 template <>
@@ -261,7 +269,7 @@ const cpx<float>* twiddles<float>(const Plan& p) {
 template <int N, typename T>
 hipError_t fft_signed(const Plan& p, int sign, T sc, int64_t batch, const void* in, void* out, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
-  const int spb = slabs_per_block<T>(N, kLdsBudget);
+  const int spb = tuned_spb<T>(N, p.tune.fft_spb);
   const size_t lds = size_t(spb) * MeshShape<N>::SLAB * sizeof(cpx<T>);
   const int64_t blocks = (batch + spb - 1) / spb;
   if (sign > 0)
@@ -283,7 +291,7 @@ template <int N, typename T>
 hipError_t bubble_n(const Plan& p, const void* gt, const void* gr, int out_q, void* out,
                     hipStream_t s) {
   const int64_t nslabs = int64_t(p.r) * p.nb * p.nb;
-  const int spb = slabs_per_block<T>(N, kLdsBudget);
+  const int spb = tuned_spb<T>(N, p.tune.bubble_spb);
   const int64_t blocks = (nslabs + spb - 1) / spb;
   if (out_q) {
     const size_t lds = size_t(spb) * MeshShape<N>::SLAB * sizeof(cpx<T>);
@@ -307,6 +315,7 @@ hipError_t sigma_n(const Plan& p, const void* gt, const void* wc, int in_q, int 
   int spb = 1;
   for (int d = 1; d <= terms && d <= cap; ++d)
     if (terms % d == 0) spb = d;
+  if (p.tune.sigma_spb > 0) spb = p.tune.sigma_spb < cap ? p.tune.sigma_spb : cap;
   const size_t lds = size_t(spb) * MeshShape<N>::SLAB * sizeof(cpx<T>);
   const unsigned blocks = unsigned(int64_t(p.r) * p.no * p.no);
   const dim3 blk(spb * N);

@@ -42,6 +42,16 @@ struct TermTable {
   int max_terms = 0;
 };
 
+// Launch shapes picked by the autotuner (0 or -1: the built-in heuristic).
+struct Tune {
+  int fft_spb = 0;      // slabs per block of the lattice transform
+  int bubble_spb = 0;   // slabs per block of the bubble
+  int sigma_spb = 0;    // term lanes per block of the self-energy
+  int mfma_bpc = 0;     // resident blocks per CU of the MFMA DLR maps
+  int orb_valu = -1;    // orbital-array maps: 1 VALU kernel, 0 matrix cores
+  int orb_mt = 0;       // rows per block chunk of the VALU map kernel
+};
+
 struct Plan {
   int device = 0;
   int n = 0, nk = 0, no = 0, nb = 0, r = 0, prec = 0;
@@ -65,6 +75,7 @@ struct Plan {
   // workspace of the adjoint calls, allocated on their first use
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
+  Tune tune;
 };
 
 void set_error(const std::string& msg);
@@ -152,3 +163,8 @@ bool dlr_maps_host(double beta, const std::vector<double>& omega, const std::vec
                    std::vector<std::complex<double>> maps[kNumMaps], std::string& err);
 
 }  // namespace qgw
+
+// opaque handle of the C ABI
+struct qgw_plan_s {
+  qgw::Plan p;
+};

@@ -32,7 +32,7 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_state_set_precision", "qgw_state_info", "qgw_check_finite",
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
-           "qgw_add", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
+           "qgw_add", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
            "qgw_last_error"]
 
 
@@ -100,6 +100,7 @@ def lib():
             "qgw_dyson_G_bwd": [vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp],
             "qgw_pair_layout": [vp, i32, i32, i64, vp, vp, vp],
             "qgw_add": [vp, i64, vp, vp, vp, vp],
+            "qgw_plan_autotune": [vp, pi32, vp],
             "qgw_batch_create": [i32, ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(vp)],
             "qgw_batch_launch": [vp, vp],
             "qgw_batch_read": [vp, pd, pd, pi32, vp],
@@ -280,6 +281,15 @@ class Plan:
         _check(lib().qgw_dyson_G_bwd(self.handle, _ptr(h_k), _ptr(sig_iw), float(mu), nt, float(mubar), _ptr(gbar),
                                      _ptr(sigbar), _ptr(hbar), _stream()))
         return sigbar, hbar
+
+    TUNE_NAMES = ("fft_slabs_per_block", "bubble_slabs_per_block", "sigma_term_lanes", "mfma_blocks_per_cu",
+                  "orbital_map_valu", "orbital_map_rows")
+
+    def autotune(self):
+        """Times the candidate launch shapes on this plan and keeps the fastest; returns them."""
+        ch = (ctypes.c_int32 * 6)()
+        _check(lib().qgw_plan_autotune(self.handle, ch, _stream()))
+        return dict(zip(self.TUNE_NAMES, list(ch)))
 
     def add(self, a, b, out):
         _check(lib().qgw_add(self.handle, int(a.numel()), _ptr(a), _ptr(b), _ptr(out), _stream()))

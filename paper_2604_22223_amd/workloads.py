@@ -200,6 +200,36 @@ def random_model(mesh, site_norb, seed, bandwidth=3.0, U=2.0, J=0.3, Vnn=0.4,
             "n_target": float(n_target)}
 
 
+def batch_sweep(count=64, seed=22223):
+    """Seeded instances of uneven size for the batched runs.
+
+    Instance i draws, from default_rng(seed + i): orbitals n_o in 1..5; mesh
+    side in {12, 16, 18, 20, 24, 30, 32, 36, 40, 48}; beta log-uniform in
+    [10, 100] /eV; U uniform in [1, 6] eV, J = U x U[0, 0.2] (0 for one
+    orbital), V_nn = U x U[0, 0.3]; band width uniform in [2, 6] eV; filling
+    per spin-orbital uniform in [0.2, 0.8]; omega_max = 25 eV, eps = 1e-10.
+    The hopping of instance i is the five-orbital construction with seed
+    seed + i.
+    """
+    sides = [12, 16, 18, 20, 24, 30, 32, 36, 40, 48]
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed + i)
+        norb = int(rng.integers(1, 6))
+        n = int(sides[int(rng.integers(0, len(sides)))])
+        beta = float(10.0 ** rng.uniform(1.0, 2.0))
+        U = float(rng.uniform(1.0, 6.0))
+        J = float(U * rng.uniform(0.0, 0.2)) if norb > 1 else 0.0
+        Vnn = float(U * rng.uniform(0.0, 0.3))
+        bw = float(rng.uniform(2.0, 6.0))
+        fill = float(rng.uniform(0.2, 0.8))
+        w = five_orbital(n=n, seed=seed + i, bandwidth=bw, U=U, J=J, Vnn=Vnn, beta=beta, omega_max=25.0,
+                         eps=1e-10, n_target=2.0 * norb * fill, norb=norb, scale_mesh=n)
+        w["name"] = "sweep_%02d_o%d_%dx%d" % (i, norb, n, n)
+        out.append(w)
+    return out
+
+
 # The benchmark workloads, by name.
 def workload(name):
     if name == "graphene_g0w0_12":

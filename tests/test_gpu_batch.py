@@ -132,3 +132,25 @@ def test_batch_rejects_bad_arguments(insts):
     with pytest.raises(qgw.QGWError):
         qgw.Batch([st], n_iter=0)
     st.close()
+
+
+def test_autotuned_plan_matches_default(insts):
+    """The tuned launch shapes change only the order of some sums."""
+    inst = insts[3]
+    w = inst.w
+    tuned = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], inst.d.nodes())
+    ch = tuned.autotune()
+    print("[batch] tuned shapes", ch, flush=True)
+    assert ch["fft_slabs_per_block"] >= 1 and ch["bubble_slabs_per_block"] >= 1 and ch["sigma_term_lanes"] >= 1
+    assert ch["orbital_map_valu"] in (0, 1)
+    a = inst.state()
+    b = qgw.State(tuned, inst.H, inst.V, n_target=w["n_target"])
+    b.init_g0()
+    for _ in range(2):
+        da, _, ma = a.iterate(1)
+        db, _, mb = b.iterate(1)
+        assert abs(ma - mb) <= 1e-12 * max(1.0, abs(ma))
+    assert rel_err(b.array(1).cpu().numpy(), a.array(1).cpu().numpy()) < 1e-12
+    a.close()
+    b.close()
+    tuned.close()
