@@ -89,8 +89,10 @@ PEAK_TFLOPS = {"f64": FP64_PEAK_TFLOPS, "f32": FP32_PEAK_TFLOPS}
 # for a 256 MiB device copy: FETCH x 1.9997, WRITE x 1.0000; profiles/hbm_traffic_gw_iteration_five_orbital_24.md).
 # Valid for the kernels as they were profiled; a changed kernel drops its entry until it is profiled again.
 MEASURED_TRAFFIC = {
-    "a3a4_bubble:f64": 501.1e6, "a8a9a10_sigma:f64": 418.3e6,
-    "a3a4_bubble:f32": 232.2e6, "a8a9a10_sigma:f32": 208.0e6,
+    "a3a4_bubble:f64": 501.1e6, "a5_dlr_p:f64": 628.4e6, "a6_dyson_w:f64": 626.1e6, "a7_dlr_w:f64": 885.9e6,
+    "a8a9a10_sigma:f64": 417.7e6,
+    "a3a4_bubble:f32": 232.2e6, "a5_dlr_p:f32": 630.3e6, "a6_dyson_w:f32": 314.0e6, "a7_dlr_w:f32": 732.1e6,
+    "a8a9a10_sigma:f32": 208.0e6,
 }
 FP64_STEPS = ("a12_density_hf", "a14_delta_mix", "a13_dyson_g")
 
