@@ -136,6 +136,19 @@ qgw_status qgw_plan_destroy(qgw_plan plan);
  * r*2 for QGW_F_IW2BETA) of ``map`` to host memory ``out``. */
 qgw_status qgw_plan_get_map(qgw_plan plan, int32_t map, double *out);
 
+/* Launch-shape autotuner: times the candidate shapes of the kernels whose
+ * best shape depends on the instance, on scratch arrays of the plan's sizes
+ * (allocated and freed inside the call; waits for ``stream``), and keeps the
+ * fastest in the plan for every later call (and for states built on it):
+ * slabs per block of the lattice transform and of the bubble, term lanes of
+ * the self-energy, resident blocks per CU of the matrix-core DLR maps, and
+ * the kernel of the orbital-array maps (matrix cores, or the VALU kernel with
+ * 8, 16 or 32 rows per chunk).  choices[6] (may be NULL) receives them in
+ * that order (orbital maps as two entries: 1 = VALU, and its chunk).  The
+ * candidates compute the same values; the self-energy lane count and the
+ * orbital-map kernel change only the order of floating-point sums. */
+qgw_status qgw_plan_autotune(qgw_plan plan, int32_t *choices, void *stream);
+
 /* Sizes of the plan: any output pointer may be NULL. */
 qgw_status qgw_plan_sizes(qgw_plan plan, int32_t *rank, int32_t *n_o,
                           int32_t *n_b, int32_t *n_k);
