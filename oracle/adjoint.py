@@ -17,7 +17,7 @@ import numpy as np
 
 from . import lattice
 from .dlr import apply_map
-from .gw import dyson_G, hermitian_part
+from .gw import density_k, dyson_G, hermitian_part
 
 
 # ----------------------------------------------------------------------------
@@ -158,6 +158,32 @@ def dyson_G_adj(gbar, H_k, sig_hf_k, sig_iw, dlr, mu, n_target, mubar=0.0):
 
 
 # ----------------------------------------------------------------------------
+# a14: total energy
+# ----------------------------------------------------------------------------
+
+def energy_vjp(model, dlr, state, ebar):
+    """Cotangents of ebar * gw.total_energy(model, dlr, state)[0].
+
+    E_HF = 2/N_k Re sum A_ab n_ba with A = H0 + Sigma_HF / 2 gives
+    Abar = c conj(n^T), nbar = c conj(A^T) (c = 2 ebar / N_k), and n = Herm(-rho G);
+    E_c = 1/N_k Re sum S_m,ab F_gm[m, m'] G_m',ba gives
+    Sbar = ebar/N_k conj((F_gm G)^T), Gbar += ebar/N_k conj((F_gm^T S)^T).
+    Returns cotangents of H_k, sig_hf_k, sig_iw and G_iw.
+    """
+    G = state["G_iw"]
+    n_k = density_k(G, dlr)
+    c = 2.0 * ebar / model.n_k
+    a = model.H_k + 0.5 * state["sig_hf_k"]
+    abar = c * np.conj(np.swapaxes(n_k, 0, 1))
+    gbar = density_k_adj(c * np.conj(np.swapaxes(a, 0, 1)), dlr)
+    qg = apply_map(dlr.F_gm, G)
+    sq = apply_map(dlr.F_gm.T, state["sig_iw"])
+    sbar = ebar / model.n_k * np.conj(np.swapaxes(qg, 1, 2))
+    gbar = gbar + ebar / model.n_k * np.conj(np.swapaxes(sq, 1, 2))
+    return {"H_k": abar, "sig_hf_k": 0.5 * abar, "sig_iw": sbar, "G_iw": gbar}
+
+
+# ----------------------------------------------------------------------------
 # one iteration, and the parameter chain from G0
 # ----------------------------------------------------------------------------
 
@@ -165,8 +191,8 @@ def iteration_vjp(model, dlr, state_in, out, cot):
     """Cotangents of one gw.gw_iteration (mixing 1) through all its steps.
 
     ``out`` is the iteration's result with ``keep=True``.  ``cot`` holds the
-    cotangents of the outputs: "G_iw", "sig_iw", "sig_hf_k" (arrays or None)
-    and "mu" (float).  Returns a dict with the cotangents of the incoming
+    cotangents of the outputs: "G_iw", "sig_iw", "sig_hf_k" (arrays or None),
+    "mu" and "energy" (floats; the energy is that of the output state).  Returns a dict with the cotangents of the incoming
     G_iw and of the model inputs H_k and V_R (V enters as V(R) in
     Hartree-Fock and as V(q) = FT V(R) in Dyson W).
     """
@@ -176,6 +202,10 @@ def iteration_vjp(model, dlr, state_in, out, cot):
     gbar_new = cot.get("G_iw")
     if gbar_new is None:
         gbar_new = np.zeros_like(G_iw)
+    ev = None
+    if cot.get("energy"):
+        ev = energy_vjp(model, dlr, out, cot["energy"])
+        gbar_new = gbar_new + ev["G_iw"]
     # a13
     xbar = dyson_G_adj(gbar_new, model.H_k, out["sig_hf_k"], out["sig_iw"], dlr, out["mu"], model.n_target,
                        mubar=cot.get("mu", 0.0))
@@ -186,6 +216,10 @@ def iteration_vjp(model, dlr, state_in, out, cot):
     sc_bar = xbar.copy()
     if cot.get("sig_iw") is not None:
         sc_bar = sc_bar + cot["sig_iw"]
+    if ev is not None:
+        hbar_k = hbar_k + ev["H_k"]
+        shf_bar = shf_bar + ev["sig_hf_k"]
+        sc_bar = sc_bar + ev["sig_iw"]
     # a11, a10 (Hermitian part), a9
     stk_bar = hermitian_part(apply_map_adj(dlr.F_tau2iw, sc_bar), axes=(1, 2))
     str_bar = k_from_R_adj(stk_bar)

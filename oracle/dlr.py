@@ -105,6 +105,24 @@ def kernel_iw_b(n, omega, beta):
     return out
 
 
+def fermi_divided_differences(omega, beta):
+    """D[l, l'] = (1/beta) sum_n 1 / ((i w_n - w_l)(i w_n - w_l')) over all fermionic n.
+
+    Partial fractions and sum_n 1/(i w_n - x) e^{i w_n 0+} = beta f(x) give the
+    divided difference (f(w_l) - f(w_l')) / (w_l - w_l') of the Fermi function
+    f(x) = 1 / (1 + e^{beta x}), and -beta f (1 - f) on the diagonal.
+    """
+    w = np.asarray(omega, dtype=np.float64)
+    f = 0.5 * (1.0 - np.tanh(0.5 * beta * w))
+    dw = w[:, None] - w[None, :]
+    df = f[:, None] - f[None, :]
+    same = dw == 0.0
+    out = np.where(same, 0.0, df / np.where(same, 1.0, dw))
+    diag = -beta * f * (1.0 - f)
+    out[np.arange(len(w)), np.arange(len(w))] = diag
+    return out
+
+
 # ----------------------------------------------------------------------------
 # node selection
 # ----------------------------------------------------------------------------
@@ -219,6 +237,11 @@ class DLR:
         self.B_tau2iw = _right_solve(self.K_b, self.K_tau.astype(np.complex128))
         self.B_iw2tau = _right_solve(self.K_tau.astype(np.complex128), self.K_b)
         self.F_iw2beta = _right_solve(self.K_beta[None, :].astype(np.complex128), self.K_f)[0]
+        # Matsubara-sum form: (1/beta) sum_n A(i w_n) B(i w_n) = sum_{m m'} A_m F_gm[m, m'] B_m'
+        # over the node values of two fermionic DLR functions (all n, not only the nodes)
+        self.D_sum = fermi_divided_differences(self.omega, b)
+        kinv_t_d = np.linalg.solve(self.K_f.T, self.D_sum.astype(np.complex128))     # K^{-T} D
+        self.F_gm = np.linalg.solve(self.K_f.T, kinv_t_d.T).T                        # K^{-T} D K^{-1}
 
     # coefficient-level helpers (used by the tests and the energy)
     def coeffs_from_iw_f(self, x_iw):

@@ -226,6 +226,34 @@ def sigma(G_tau_R, Wc_tau_R, pairs, n_o):
 
 
 # ----------------------------------------------------------------------------
+# a14: total energy
+# ----------------------------------------------------------------------------
+
+def total_energy(model, dlr, state):
+    """Galitskii-Migdal energy per cell (two spins), reading A16 of the design notes.
+
+    E = 2/N_k sum_k Re Tr[(H0(k) + Sigma_HF(k) / 2) n(k)]
+        + 1/N_k sum_k Re (1/beta) sum_n Tr[Sigma^C(k, i w_n) G(k, i w_n)]
+
+    with n = -G(beta^-) from the state's G (Hermitian part) and the Matsubara
+    sum over all n taken exactly from the DLR expansions of Sigma^C and G:
+    (1/beta) sum_n A(i w_n) B(i w_n) = sum_{l l'} a_l b_l' D[l, l'] with
+    D the divided differences of the Fermi function (fermi_divided_differences).
+    Returns (E, E_HF part, correlation part).
+    """
+    G = state["G_iw"]
+    n_k = density_k(G, dlr)
+    nk = model.n_k
+    a = model.H_k + 0.5 * state["sig_hf_k"]
+    e_hf = 2.0 / nk * float(np.einsum("abxy,baxy->", a, n_k).real)
+    sig_c = dlr.coeffs_from_iw_f(state["sig_iw"])          # [l, a, b, n1, n2]
+    g_c = dlr.coeffs_from_iw_f(G)
+    tr = np.einsum("labxy,mbaxy->lm", sig_c, g_c)            # sum_k Tr[sigma_l g_m]
+    e_c = float(np.sum(dlr.D_sum * tr).real) / nk
+    return e_hf + e_c, e_hf, e_c
+
+
+# ----------------------------------------------------------------------------
 # the iteration (Fig. fig-self (b))
 # ----------------------------------------------------------------------------
 

@@ -135,12 +135,15 @@ def test_dyson_g_adjoint(small, with_mu):
 def _loss_parts(rng, m, d):
     shp = (d.r, m.n_o, m.n_o) + m.mesh
     return {"sig_iw": crand(rng, shp), "sig_hf_k": crand(rng, (m.n_o, m.n_o) + m.mesh),
-            "G_iw": crand(rng, shp), "mu": 0.9}
+            "G_iw": crand(rng, shp), "mu": 0.9, "energy": 1.7}
 
 
-def _loss(out, cot):
-    return (rdot(cot["sig_iw"], out["sig_iw"]) + rdot(cot["sig_hf_k"], out["sig_hf_k"])
-            + rdot(cot["G_iw"], out["G_iw"]) + cot["mu"] * out["mu"])
+def _loss(out, cot, m=None, d=None):
+    val = (rdot(cot["sig_iw"], out["sig_iw"]) + rdot(cot["sig_hf_k"], out["sig_hf_k"])
+           + rdot(cot["G_iw"], out["G_iw"]) + cot["mu"] * out["mu"])
+    if m is not None:
+        val += cot["energy"] * gw.total_energy(m, d, out)[0]
+    return val
 
 
 def _sym_dir(rng, shape):
@@ -158,14 +161,35 @@ def test_one_iteration_gradient_by_finite_differences(small):
     def L(H_R, V_R):
         mm = gw.Model(m.mesh, m.site_norb, H_R, V_R, m.beta, m.n_target)
         st0 = gw.initial_state(mm, d)
-        return _loss(gw.gw_iteration(mm, d, st0), cot)
+        return _loss(gw.gw_iteration(mm, d, st0), cot, mm, d)
 
-    assert abs(L(m.H_R, m.V_R) - _loss(out, cot)) < 1e-12 * abs(_loss(out, cot))
+    assert abs(L(m.H_R, m.V_R) - _loss(out, cot, m, d)) < 1e-12 * abs(_loss(out, cot, m, d))
     for trial in range(2):
         dh = _sym_dir(rng, m.H_R.shape)
         check(g["H_R"], lambda x: L(x, m.V_R), m.H_R, dh)
         dv = _sym_dir(rng, m.V_R.shape)
         check(g["V_R"], lambda x: L(m.H_R, x), m.V_R, dv)
+
+
+def test_energy_adjoint(small):
+    """The energy alone, in every argument, by finite differences."""
+    w, d, m = small
+    rng = np.random.default_rng(9)
+    st = gw.gw_iteration(m, d, gw.initial_state(m, d))
+    ev = ad.energy_vjp(m, d, st, 1.0)
+
+    def E(**over):
+        s2 = dict(st)
+        mm = m
+        if "H_k" in over:
+            mm = gw.Model(m.mesh, m.site_norb, m.H_R, m.V_R, m.beta, m.n_target)
+            mm.H_k = over.pop("H_k")
+        s2.update(over)
+        return gw.total_energy(mm, d, s2)[0]
+
+    for key in ("G_iw", "sig_iw", "sig_hf_k"):
+        check(ev[key], lambda x, key=key: E(**{key: x}), st[key], crand(rng, st[key].shape))
+    check(ev["H_k"], lambda x: E(H_k=x), m.H_k, crand(rng, m.H_k.shape))
 
 
 def test_one_iteration_gradient_in_U_J_V():
@@ -182,7 +206,7 @@ def test_one_iteration_gradient_in_U_J_V():
     def L(**p):
         ww = wl.five_orbital(**kw, **p)
         mm = gw.Model(ww["mesh"], ww["site_norb"], ww["H_R"], ww["V_R"], ww["beta"], ww["n_target"])
-        return _loss(gw.gw_iteration(mm, d, gw.initial_state(mm, d)), cot)
+        return _loss(gw.gw_iteration(mm, d, gw.initial_state(mm, d)), cot, mm, d)
 
     for name in ("U", "J", "Vnn"):
         def f(t):
@@ -207,7 +231,7 @@ def test_two_iteration_gradient_by_finite_differences(small):
         st = gw.initial_state(mm, d)
         for _ in range(2):
             st = gw.gw_iteration(mm, d, st)
-        return _loss(st, cot)
+        return _loss(st, cot, mm, d)
 
     check(g["H_R"], lambda x: L(x, m.V_R), m.H_R, _sym_dir(rng, m.H_R.shape))
     check(g["V_R"], lambda x: L(m.H_R, x), m.V_R, _sym_dir(rng, m.V_R.shape))

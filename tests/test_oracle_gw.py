@@ -337,3 +337,52 @@ def test_scf_converges_and_keeps_filling():
     assert hist[-1][0] <= 1e-8
     assert len(hist) < 40
     assert max(abs(x - 3.6) for x in seen) < 1e-10
+
+
+# ----------------------------------------------------------------------------
+# a14: total energy
+# ----------------------------------------------------------------------------
+
+def test_fermi_divided_differences_brute_force():
+    """(1/beta) sum_n 1/((i w_n - x)(i w_n - y)) by direct summation over |n| <= N plus the 1/w^2 tail."""
+    from oracle.dlr import fermi_divided_differences
+    beta = 7.0
+    w = np.array([-1.3, -0.2, 0.0, 0.45, 2.1])
+    D = fermi_divided_differences(w, beta)
+    N = 400000
+    n = np.arange(-N, N)
+    wn = (2 * n + 1) * np.pi / beta
+    for i in range(len(w)):
+        for j in range(len(w)):
+            s = np.sum(1.0 / ((1j * wn - w[i]) * (1j * wn - w[j]))) / beta
+            # remaining terms behave as -1/w_n^2: (1/beta) sum_{|n| >= N} -beta^2/((2n+1)^2 pi^2)
+            tail = -2.0 * beta / np.pi ** 2 * (1.0 / (4.0 * N))
+            assert abs((s + tail).real - D[i, j]) < 1e-8 * max(1.0, abs(D[i, j])), (i, j, s, D[i, j])
+            assert abs(s.imag) < 1e-10
+
+
+def test_matsubara_sum_map_against_brute_force():
+    """sum_{m m'} A_m F_gm[m, m'] B_m' over node values equals the Matsubara sum over all n."""
+    d = DLR(6.0, 15.0, 1e-10)
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal(d.r) + 1j * rng.standard_normal(d.r)
+    b = rng.standard_normal(d.r) + 1j * rng.standard_normal(d.r)
+    A = d.K_f @ a
+    B = d.K_f @ b
+    via_nodes = A @ d.F_gm @ B
+    N = 400000
+    wn = (2 * np.arange(-N, N) + 1) * np.pi / d.beta
+    K = 1.0 / (1j * wn[:, None] - d.omega[None, :])
+    s = np.sum((K @ a) * (K @ b)) / d.beta
+    tail = -2.0 * d.beta / np.pi ** 2 / (4.0 * N) * np.sum(a) * np.sum(b)
+    assert abs(s + tail - via_nodes) < 1e-7 * max(1.0, abs(via_nodes)), (s + tail, via_nodes)
+
+
+def test_energy_non_interacting_closed_form(small):
+    """G0 and no self-energy: E = 2/N_k sum_{k,a} e_a(k) f(e_a(k) - mu)."""
+    w, d, m, st0, st1 = small
+    e, e_hf, e_c = gw.total_energy(m, d, st0)
+    xi, _ = eig_k(m.H_k)
+    ref = 2.0 / m.n_k * float(np.sum(xi * fermi(d.beta * (xi - st0["mu"]))))
+    assert e_c == 0.0
+    assert abs(e - ref) < 1e-9 * max(1.0, abs(ref)), (e, ref)
