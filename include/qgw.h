@@ -73,14 +73,20 @@ enum { QGW_F64 = 0, QGW_F32 = 1 };
  *   QGW_F_TAU2IW   tau_k -> fermionic Matsubara nodes
  *   QGW_B_TAU2IW   tau_k -> bosonic Matsubara nodes
  *   QGW_B_IW2TAU   bosonic Matsubara nodes -> tau_k
- *   QGW_F_IW2BETA  fermionic Matsubara nodes -> beta^- (one output row)   */
+ *   QGW_F_IW2BETA  fermionic Matsubara nodes -> beta^- (one output row)
+ *   QGW_F_IW2GM    fermionic Matsubara nodes -> Matsubara-sum weights: with
+ *                  Y = T x, sum_m Y_m B_m = (1/beta) sum over all n of
+ *                  x(i w_n) B(i w_n) for fermionic DLR functions x and B
+ *                  (T = K_F^{-T} D K_F^{-1}, D the divided differences of the
+ *                  Fermi function; the Galitskii-Migdal correlation energy) */
 enum {
   QGW_F_IW2TAU = 0,
   QGW_F_IW2TAUR = 1,
   QGW_F_TAU2IW = 2,
   QGW_B_TAU2IW = 3,
   QGW_B_IW2TAU = 4,
-  QGW_F_IW2BETA = 5
+  QGW_F_IW2BETA = 5,
+  QGW_F_IW2GM = 6
 };
 
 /* Pair-array layouts. */
@@ -301,6 +307,22 @@ qgw_status qgw_dyson_G_bwd(qgw_plan plan, const void *H_k, const void *Sig_iw,
  * permutation; its adjoint is the opposite change).  FP64 plans. */
 qgw_status qgw_pair_layout(qgw_plan plan, int32_t in_layout, int32_t out_layout,
                            int64_t nn, const void *in, void *out, void *stream);
+
+/* a14: Galitskii-Migdal total energy per cell (two spins) of a state
+ * (H0(k), Sigma_HF(k), Sigma^C(k, i w), G(k, i w)), FP64 plans:
+ *   E = 2/N_k sum_k Re Tr[(H0 + Sigma_HF / 2) n]
+ *       + 1/N_k sum_k Re (1/beta) sum_n Tr[Sigma^C(i w_n) G(i w_n)]
+ * with n = Herm(-G(beta^-)) and the Matsubara sum over all n taken exactly
+ * from the DLR expansions (map QGW_F_IW2GM).  e_out[3] = (E, HF part,
+ * correlation part).  Waits for ``stream``.  Workspace. */
+qgw_status qgw_energy(qgw_plan plan, const void *H_k, const void *SigHF_k,
+                      const void *Sig_iw, const void *G_iw, double *e_out, void *stream);
+
+/* Adjoint of qgw_energy's E for a cotangent ebar: writes Hbar, SigHFbar
+ * (static orbital layout), Sigbar and Gbar (orbital layout).  Workspace. */
+qgw_status qgw_energy_bwd(qgw_plan plan, const void *H_k, const void *SigHF_k,
+                          const void *Sig_iw, const void *G_iw, double ebar, void *Hbar,
+                          void *SigHFbar, void *Sigbar, void *Gbar, void *stream);
 
 /* out = a + b over ``count`` complex FP64 entries (the static H0(k) +
  * Sigma_HF(k) of the Dyson equation for G); out may alias a or b. */

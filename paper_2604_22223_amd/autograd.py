@@ -232,6 +232,29 @@ class DysonG(torch.autograd.Function):
         return None, hb, (sb if has_sig else None), None, None
 
 
+class Energy(torch.autograd.Function):
+    """a14: Galitskii-Migdal total energy of (H0(k), Sigma_HF(k), Sigma^C(i w), G(i w)); a 0-d host tensor."""
+
+    @staticmethod
+    def forward(ctx, plan, h_k, shf_k, sig_iw, g_iw):
+        h_k, shf_k, sig_iw, g_iw = _c(h_k), _c(shf_k), _c(sig_iw), _c(g_iw)
+        e = plan.energy(h_k, shf_k, sig_iw, g_iw)[0]
+        ctx.save_for_backward(h_k, shf_k, sig_iw, g_iw)
+        ctx.plan = plan
+        return torch.tensor(e, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, ge):
+        h_k, shf_k, sig_iw, g_iw = ctx.saved_tensors
+        hb, sb, cb, gb = (torch.empty_like(t) for t in (h_k, shf_k, sig_iw, g_iw))
+        ctx.plan.energy_bwd(h_k, shf_k, sig_iw, g_iw, float(ge), hb, sb, cb, gb)
+        return None, hb, sb, cb, gb
+
+
+def energy(plan, H_k, shf_k, sig_iw, G_iw):
+    return Energy.apply(plan, H_k, shf_k, sig_iw, G_iw)
+
+
 # ----------------------------------------------------------------------------
 # the iteration
 # ----------------------------------------------------------------------------

@@ -306,7 +306,8 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
       if (e == hipSuccess) e = upload(&p.dmaps32.m[m], h32.data(), h32.size() * sizeof(zf));
     }
     // adjoint maps T^H of the square maps (FP64 only: the adjoint calls run in FP64)
-    for (int m = 0; m < 5 && e == hipSuccess; ++m) {
+    for (int m = 0; m < kNumMaps && e == hipSuccess; ++m) {
+      if (m == QGW_F_IW2BETA) continue;
       std::vector<zd> h64(size_t(rp) * p.r, mk(0.0, 0.0));
       for (int i = 0; i < p.r; ++i)
         for (int j = 0; j < p.r; ++j) {
@@ -664,6 +665,63 @@ qgw_status qgw_dyson_G_bwd(qgw_plan h, const void* H_k, const void* Sig_iw, doub
   hipStream_t s = (hipStream_t)stream;
   QGW_CHECK_HIP(launch_dyson_g_bwd(p, H_k, Sig_iw, mu, n_target, mubar, Gbar, Sigbar, s), "qgw_dyson_G_bwd");
   if (Hbar) QGW_CHECK_HIP(launch_sum_nodes(p, Sigbar, Hbar, s), "qgw_dyson_G_bwd");
+  return QGW_OK;
+}
+
+// ---------------------------------------------------------------- energy
+
+qgw_status qgw_energy(qgw_plan h, const void* H_k, const void* SigHF_k, const void* Sig_iw, const void* G_iw,
+                      double* e_out, void* stream) {
+  QGW_BWD_PLAN(h, "qgw_energy");
+  QGW_REQUIRE(H_k && SigHF_k && Sig_iw && G_iw && e_out, QGW_ERR_INVALID_ARG, "qgw_energy: null argument");
+  const size_t so = size_t(p.no) * p.no * p.nk * sizeof(zd);
+  const size_t fo = so * p.r;
+  QGW_CHECK_HIP(ensure_ws(h->p, 2 * so + fo + size_t(2) * 8192 * sizeof(double) + 64), "qgw_energy: workspace");
+  char* ws = (char*)p.d_ws;
+  void* n_k = ws;
+  void* y = ws + 2 * so;
+  double* part = (double*)(ws + 2 * so + fo);
+  double* sums = part + 2 * 4096;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ncol = int64_t(p.no) * p.no * p.nk;
+  QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2BETA, ncol, -1.0, 0.0, G_iw, n_k, s, 2), "qgw_energy");
+  QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2GM, ncol, 1.0, 0.0, Sig_iw, y, s), "qgw_energy");
+  QGW_CHECK_HIP(launch_energy_sums(p, H_k, SigHF_k, n_k, y, G_iw, part, sums, s), "qgw_energy");
+  double host[2];
+  QGW_CHECK_HIP(hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, s), "qgw_energy");
+  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_energy");
+  const double e_hf = 2.0 / double(p.nk) * host[0];
+  const double e_c = host[1] / double(p.nk);
+  e_out[0] = e_hf + e_c;
+  e_out[1] = e_hf;
+  e_out[2] = e_c;
+  return QGW_OK;
+}
+
+qgw_status qgw_energy_bwd(qgw_plan h, const void* H_k, const void* SigHF_k, const void* Sig_iw, const void* G_iw,
+                          double ebar, void* Hbar, void* SigHFbar, void* Sigbar, void* Gbar, void* stream) {
+  QGW_BWD_PLAN(h, "qgw_energy_bwd");
+  QGW_REQUIRE(H_k && SigHF_k && Sig_iw && G_iw && Hbar && SigHFbar && Sigbar && Gbar, QGW_ERR_INVALID_ARG,
+              "qgw_energy_bwd: null argument");
+  QGW_REQUIRE(Gbar != G_iw && Sigbar != Sig_iw && Sigbar != Gbar, QGW_ERR_INVALID_ARG,
+              "qgw_energy_bwd: outputs alias inputs");
+  const size_t so = size_t(p.no) * p.no * p.nk * sizeof(zd);
+  const size_t fo = so * p.r;
+  QGW_CHECK_HIP(ensure_ws(h->p, 2 * so + 2 * fo), "qgw_energy_bwd: workspace");
+  char* ws = (char*)p.d_ws;
+  void* n_k = ws;
+  void* nbar = ws + so;
+  void* y = ws + 2 * so;
+  void* ybar = ws + 2 * so + fo;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ncol = int64_t(p.no) * p.no * p.nk;
+  QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2BETA, ncol, -1.0, 0.0, G_iw, n_k, s, 2), "qgw_energy_bwd");
+  QGW_CHECK_HIP(launch_dlr(p, QGW_F_IW2GM, ncol, 1.0, 0.0, Sig_iw, y, s), "qgw_energy_bwd");
+  QGW_CHECK_HIP(launch_energy_bwd_static(p, H_k, SigHF_k, n_k, 2.0 * ebar / double(p.nk), Hbar, SigHFbar, nbar, s),
+                "qgw_energy_bwd");
+  QGW_CHECK_HIP(launch_row_map_bwd(p, ncol, -1.0, 0.0, 2, nbar, Gbar, s), "qgw_energy_bwd");
+  QGW_CHECK_HIP(launch_energy_bwd_nodes(p, y, G_iw, ebar / double(p.nk), Gbar, ybar, s), "qgw_energy_bwd");
+  QGW_CHECK_HIP(launch_dlr(p, kAdjMap0 + QGW_F_IW2GM, ncol, 1.0, 0.0, ybar, Sigbar, s), "qgw_energy_bwd");
   return QGW_OK;
 }
 

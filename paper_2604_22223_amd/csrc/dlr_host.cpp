@@ -262,6 +262,25 @@ bool dlr_maps_host(double beta, const std::vector<double>& omega, const std::vec
   bool ok = right_divide(r, r, kfm, kt, maps[0]) && right_divide(r, r, kfm, ktr, maps[1]) &&
             right_divide(r, r, kt, kfm, maps[2]) && right_divide(r, r, kt, kbm, maps[3]) &&
             right_divide(r, r, kbm, kt, maps[4]) && right_divide(r, 1, kfm, kbeta, maps[5]);
+  // Matsubara sums: (1/beta) sum over all n of A(i w_n) B(i w_n) = sum_{l l'} a_l D_ll' b_l' for
+  // fermionic DLR expansions, with D the divided differences of the Fermi function
+  // f(x) = 1 / (1 + e^{beta x}) (partial fractions of 1 / ((i w - x)(i w - y)));
+  // in node values Q = K_F^{-T} D K_F^{-1}, symmetric
+  if (ok) {
+    std::vector<double> f(r);
+    for (int l = 0; l < r; ++l) f[l] = 0.5 * (1.0 - std::tanh(0.5 * beta * omega[l]));
+    std::vector<cd> d(size_t(r) * r), b, bt(size_t(r) * r);
+    for (int l = 0; l < r; ++l)
+      for (int m = 0; m < r; ++m)
+        d[size_t(l) * r + m] = (l == m) ? -beta * f[l] * (1.0 - f[l])
+                                        : (f[l] - f[m]) / (omega[l] - omega[m]);
+    ok = right_divide(r, r, kfm, d, b);  // D K^{-1}
+    if (ok) {
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) bt[size_t(i) * r + j] = b[size_t(j) * r + i];
+      ok = right_divide(r, r, kfm, bt, maps[6]);  // (D K^{-1})^T K^{-1} = K^{-T} D K^{-1}
+    }
+  }
   if (!ok) err = "DLR interpolation matrix is singular for the given nodes";
   return ok;
 }

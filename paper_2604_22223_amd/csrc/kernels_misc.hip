@@ -1,6 +1,8 @@
 // Small kernels: Hartree-Fock self-energy (Eqs. eq-hartree-self-energy,
 // eq-fock-self-energy), V(q = 0), layout changes of static arrays, the
 // self-energy change / mixing of the self-consistency loop, finiteness check.
+#include <algorithm>
+
 #include "qgw_internal.h"
 
 namespace qgw {
@@ -208,6 +210,102 @@ __global__ void k_pair_layout(const zd* __restrict__ in, zd* __restrict__ out, i
   }
 }
 
+// ---- total energy ----------------------------------------------------------
+
+// per-block partial sums of Re (H + Sigma_HF / 2)_ab n_ba (static entries) and of
+// Re Y_m,ab G_m,ba (node entries), orbital transposes read directly
+__global__ __launch_bounds__(256) void k_energy_sums(const zd* __restrict__ h, const zd* __restrict__ shf,
+                                                     const zd* __restrict__ n, const zd* __restrict__ y,
+                                                     const zd* __restrict__ g, int no, int nk, int r,
+                                                     double* __restrict__ part) {
+  __shared__ double red[2][256];
+  const int64_t ns = int64_t(no) * no * nk, nt = ns * r;
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  double a = 0.0, b = 0.0;
+  for (int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x; gi < nt; gi += stride) {
+    const int64_t k = gi % nk, mab = gi / nk;
+    const int ab = int(mab % (int64_t(no) * no));
+    const int64_t m = mab / (int64_t(no) * no);
+    const int i = ab / no, j = ab % no;
+    const int64_t tr = (m * no * no + int64_t(j) * no + i) * nk + k;
+    const cpx<double> p = y[gi] * g[tr];
+    b += p.re;
+    if (gi < ns) {
+      const cpx<double> av = h[gi] + scale(shf[gi], 0.5);
+      const cpx<double> q = av * n[(int64_t(j) * no + i) * nk + k];
+      a += q.re;
+    }
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = red[0][0];
+    part[gridDim.x + blockIdx.x] = red[1][0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ part, int nblk,
+                                                      double* __restrict__ out) {
+  __shared__ double red[2][256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) {
+    a += part[i];
+    b += part[nblk + i];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+  }
+}
+
+// Abar = c conj(n^T): hbar = Abar, shfbar = Abar / 2; nbar = c conj(A^T), A = H + Sigma_HF / 2
+__global__ void k_energy_bwd_static(const zd* __restrict__ h, const zd* __restrict__ shf, const zd* __restrict__ n,
+                                    double c, zd* __restrict__ hbar, zd* __restrict__ shfbar, zd* __restrict__ nbar,
+                                    int no, int nk) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi >= int64_t(no) * no * nk) return;
+  const int64_t k = gi % nk;
+  const int ab = int(gi / nk), i = ab / no, j = ab % no;
+  const int64_t tr = (int64_t(j) * no + i) * nk + k;
+  const cpx<double> abar = scale(conj(n[tr]), c);
+  hbar[gi] = abar;
+  shfbar[gi] = scale(abar, 0.5);
+  nbar[gi] = scale(conj(h[tr] + scale(shf[tr], 0.5)), c);
+}
+
+// gbar += c conj(Y^T); ybar = c conj(G^T) (transpose over the orbital pair at each node and k)
+__global__ void k_energy_bwd_nodes(const zd* __restrict__ y, const zd* __restrict__ g, double c,
+                                   zd* __restrict__ gbar, zd* __restrict__ ybar, int no, int nk, int r) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nt = int64_t(no) * no * nk * r;
+  if (gi >= nt) return;
+  const int64_t k = gi % nk, mab = gi / nk;
+  const int ab = int(mab % (int64_t(no) * no));
+  const int64_t m = mab / (int64_t(no) * no);
+  const int i = ab / no, j = ab % no;
+  const int64_t tr = (m * no * no + int64_t(j) * no + i) * nk + k;
+  gbar[gi] = gbar[gi] + scale(conj(y[tr]), c);
+  ybar[gi] = scale(conj(g[tr]), c);
+}
+
 static unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 hipError_t launch_convert(int64_t count, const void* in, void* out, int to_f32, hipStream_t s) {
@@ -293,6 +391,32 @@ hipError_t launch_hartree_fock_bwd(const Plan& p, const void* v_r, const void* v
   if (vbar_r)
     hipLaunchKernelGGL(k_hf_bwd_v, dim3(nblk(nv, 256)), dim3(256), 0, s, (const zd*)n_r, (const zd*)sbar_r,
                        (zd*)vbar_r, p.no, p.nb, p.nk, p.d_pairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_sums(const Plan& p, const void* h_k, const void* shf_k, const void* n_k, const void* y,
+                              const void* g, double* partials, double* out2, hipStream_t s) {
+  const int64_t nt = int64_t(p.no) * p.no * p.nk * p.r;
+  const int blocks = int(std::min<int64_t>((nt + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_energy_sums, dim3(blocks), dim3(256), 0, s, (const zd*)h_k, (const zd*)shf_k, (const zd*)n_k,
+                     (const zd*)y, (const zd*)g, p.no, p.nk, p.r, partials);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, (const double*)partials, blocks, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_bwd_static(const Plan& p, const void* h_k, const void* shf_k, const void* n_k, double c,
+                                    void* hbar, void* shfbar, void* nbar, hipStream_t s) {
+  const int64_t n = int64_t(p.no) * p.no * p.nk;
+  hipLaunchKernelGGL(k_energy_bwd_static, dim3(nblk(n, 256)), dim3(256), 0, s, (const zd*)h_k, (const zd*)shf_k,
+                     (const zd*)n_k, c, (zd*)hbar, (zd*)shfbar, (zd*)nbar, p.no, p.nk);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_bwd_nodes(const Plan& p, const void* y, const void* g, double c, void* gbar, void* ybar,
+                                   hipStream_t s) {
+  const int64_t n = int64_t(p.no) * p.no * p.nk * p.r;
+  hipLaunchKernelGGL(k_energy_bwd_nodes, dim3(nblk(n, 256)), dim3(256), 0, s, (const zd*)y, (const zd*)g, c,
+                     (zd*)gbar, (zd*)ybar, p.no, p.nk, p.r);
   return hipGetLastError();
 }
 

@@ -22,10 +22,10 @@ namespace qgw {
 #define QGW_FOR_EACH_NO(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 
 constexpr int kMaxRank = 96;
-constexpr int kNumMaps = 6;
-// device map slots: 0-5 the forward maps, 6-10 the adjoints T^H of maps 0-4
-constexpr int kAdjMap0 = 6;
-constexpr int kNumDevMaps = 11;
+constexpr int kNumMaps = 7;
+// device map slots: 0-6 the forward maps, 7 + m the adjoint T^H of the square map m (m != 5)
+constexpr int kAdjMap0 = 7;
+constexpr int kNumDevMaps = 14;
 
 struct DeviceMaps {
   void* m[kNumDevMaps] = {nullptr};  // rows padded to a multiple of mt, zero-filled
@@ -150,6 +150,14 @@ hipError_t launch_dyson_g_bwd(const Plan& p, const void* h_k, const void* sig_iw
 hipError_t launch_sum_nodes(const Plan& p, const void* x, void* out, hipStream_t s);
 hipError_t launch_hartree_fock_bwd(const Plan& p, const void* v_r, const void* v_q0, const void* n_r,
                                    const void* sbar_r, void* nbar_r, void* vbar_r, hipStream_t s);
+// total energy: parts[2] = (sum Re (H + Sigma_HF/2)_ab n_ba, sum Re Y_m,ab G_m,ba) over all entries
+hipError_t launch_energy_sums(const Plan& p, const void* h_k, const void* shf_k, const void* n_k, const void* y,
+                              const void* g, double* partials, double* out2, hipStream_t s);
+// energy adjoint pieces: abar -> hbar, shfbar (= abar / 2), nbar (static); then gbar += c conj(Y^T), ybar = c conj(G^T)
+hipError_t launch_energy_bwd_static(const Plan& p, const void* h_k, const void* shf_k, const void* n_k, double c,
+                                    void* hbar, void* shfbar, void* nbar, hipStream_t s);
+hipError_t launch_energy_bwd_nodes(const Plan& p, const void* y, const void* g, double c, void* gbar, void* ybar,
+                                   hipStream_t s);
 // pair arrays with nn leading blocks: slab [nn][A][B][k] <-> matrix [nn][k][A][B]
 hipError_t launch_pair_layout(const Plan& p, int to_matrix, int64_t nn, const void* in, void* out,
                               hipStream_t s);

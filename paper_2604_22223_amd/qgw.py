@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "QGW_OK", 1: "QGW_ERR_INVALID_ARG", 2: "QGW_ERR_SHAPE", 3: "Q
                 4: "QGW_ERR_DEVICE", 5: "QGW_ERR_NOT_CONVERGED", 6: "QGW_ERR_NONFINITE",
                 7: "QGW_ERR_ALLOC"}
 F64, F32 = 0, 1
-F_IW2TAU, F_IW2TAUR, F_TAU2IW, B_TAU2IW, B_IW2TAU, F_IW2BETA = range(6)
+F_IW2TAU, F_IW2TAUR, F_TAU2IW, B_TAU2IW, B_IW2TAU, F_IW2BETA, F_IW2GM = range(7)
 LAYOUT_SLAB, LAYOUT_MATRIX = 0, 1
 R_TO_K, K_TO_R = -1, +1
 
@@ -32,7 +32,7 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_state_set_precision", "qgw_state_info", "qgw_check_finite",
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
-           "qgw_add", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
+           "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
            "qgw_last_error"]
 
 
@@ -101,6 +101,8 @@ def lib():
             "qgw_pair_layout": [vp, i32, i32, i64, vp, vp, vp],
             "qgw_add": [vp, i64, vp, vp, vp, vp],
             "qgw_plan_autotune": [vp, pi32, vp],
+            "qgw_energy": [vp, vp, vp, vp, vp, pd, vp],
+            "qgw_energy_bwd": [vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp],
             "qgw_batch_create": [i32, ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(vp)],
             "qgw_batch_launch": [vp, vp],
             "qgw_batch_read": [vp, pd, pd, pi32, vp],
@@ -290,6 +292,18 @@ class Plan:
         ch = (ctypes.c_int32 * 6)()
         _check(lib().qgw_plan_autotune(self.handle, ch, _stream()))
         return dict(zip(self.TUNE_NAMES, list(ch)))
+
+    def energy(self, h_k, shf_k, sig_iw, g_iw):
+        """(E, HF part, correlation part) of the Galitskii-Migdal energy."""
+        e = np.zeros(3)
+        _check(lib().qgw_energy(self.handle, _ptr(h_k), _ptr(shf_k), _ptr(sig_iw), _ptr(g_iw),
+                                e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+        return tuple(e.tolist())
+
+    def energy_bwd(self, h_k, shf_k, sig_iw, g_iw, ebar, hbar, shfbar, sigbar, gbar):
+        _check(lib().qgw_energy_bwd(self.handle, _ptr(h_k), _ptr(shf_k), _ptr(sig_iw), _ptr(g_iw), float(ebar),
+                                    _ptr(hbar), _ptr(shfbar), _ptr(sigbar), _ptr(gbar), _stream()))
+        return hbar, shfbar, sigbar, gbar
 
     def add(self, a, b, out):
         _check(lib().qgw_add(self.handle, int(a.numel()), _ptr(a), _ptr(b), _ptr(out), _stream()))

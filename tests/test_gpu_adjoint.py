@@ -23,7 +23,7 @@ import pytest
 from conftest import directional_fd, rel_err
 from oracle import adjoint as ad
 from oracle import gw, lattice
-from oracle.dlr import DLR
+from oracle.dlr import DLR, apply_map
 from paper_2604_22223_amd import qgw
 from paper_2604_22223_amd import workloads as wl
 
@@ -118,7 +118,7 @@ def test_dlr_bwd(case):
     yb, x = crand(rng, shp), crand(rng, shp)
     s = 0.5 - 0.25j
     for which, mat in [(qgw.F_IW2TAU, d.F_iw2tau), (qgw.F_IW2TAUR, d.F_iw2taur), (qgw.F_TAU2IW, d.F_tau2iw),
-                       (qgw.B_TAU2IW, d.B_tau2iw), (qgw.B_IW2TAU, d.B_iw2tau)]:
+                       (qgw.B_TAU2IW, d.B_tau2iw), (qgw.B_IW2TAU, d.B_iw2tau), (qgw.F_IW2GM, d.F_gm)]:
         for herm in (0, 1, 2):
             fwd = torch.empty_like(dev(flat(x)))
             p.dlr_transform(which, dev(flat(x)), fwd, scale=s, hermitian=herm)
@@ -126,6 +126,17 @@ def test_dlr_bwd(case):
             p.dlr_transform_bwd(which, dev(flat(yb)), out, scale=s, hermitian=herm)
             assert _dot_identity(host(fwd), flat(yb), host(out), flat(x)) < 1e-12, (which, herm)
         out = torch.empty_like(dev(flat(yb)))
+        if which == qgw.F_IW2GM:
+            # The Matsubara-sum map is meaningful only as a bilinear form on representable
+            # data (its entries carry the square of the kernel's condition number): pair
+            # the adjoint of conj(K c1) with K c2, which must give s c1^T D c2.
+            c1, c2 = crand(rng, shp), crand(rng, shp)
+            y_rep, x_rep = np.conj(apply_map(d.K_f, c1)), apply_map(d.K_f, c2)
+            p.dlr_transform_bwd(which, dev(flat(y_rep)), out, scale=s)
+            got = np.sum(np.conj(host(out)) * flat(x_rep))
+            want = s * np.einsum("lm,lx,mx->", d.D_sum, c1.reshape(d.r, -1), c2.reshape(d.r, -1))
+            assert abs(got - want) <= 1e-9 * abs(want), (got, want)
+            continue
         p.dlr_transform_bwd(which, dev(flat(yb)), out, scale=s)
         assert rel_err(host(out), flat(np.conj(s) * ad.apply_map_adj(mat, yb))) < MAP_TOL, which
     # a11 with the Hermitian part of its input
@@ -272,15 +283,21 @@ def _cotangents(case, seed):
     d, m = case.d, case.m
     shp = (d.r, m.n_o, m.n_o) + case.mesh
     return {"sig_iw": crand(rng, shp), "sig_hf_k": crand(rng, (m.n_o, m.n_o) + case.mesh),
-            "G_iw": crand(rng, shp), "mu": 0.9}
+            "G_iw": crand(rng, shp), "mu": 0.9, "energy": 1.7}
 
 
-def _torch_loss(res, cot):
+def _torch_loss(res, cot, plan=None, H_R=None):
+    """Projections of the outputs, plus the total energy of the output state when H_R is given."""
+    from paper_2604_22223_amd import autograd as qa
     G, mu, Siw, shf = res
     tot = 0.0
     for t, c in ((Siw, cot["sig_iw"]), (shf, cot["sig_hf_k"]), (G, cot["G_iw"])):
         tot = tot + (dev(flat(c)).conj() * t).real.sum()
-    return tot + cot["mu"] * mu.to(tot.device)
+    tot = tot + cot["mu"] * mu.to(tot.device)
+    if H_R is not None:
+        H_k = qa.FFT.apply(plan, qgw.R_TO_K, H_R)
+        tot = tot + cot["energy"] * qa.energy(plan, H_k, shf, Siw, G).to(tot.device)
+    return tot
 
 
 @pytest.mark.parametrize("n_iter", [1, 2])
@@ -292,11 +309,11 @@ def test_iteration_gradients_match_oracle_adjoint(case, n_iter):
     H_R = dev(flat(m.H_R)).requires_grad_(True)
     V_R = dev(flat(m.V_R)).requires_grad_(True)
     res = qa.run(p, H_R, V_R, m.n_target, n_iter=n_iter, checkpointed=True)[-1]
-    loss = _torch_loss(res, cot)
+    loss = _torch_loss(res, cot, p, H_R)
     loss.backward()
     ref_out, ref = ad.n_iteration_grad(m, d, cot, n_iter)
     assert rel_err(host(res[2]), flat(ref_out["sig_iw"])) < TOL
-    assert abs(float(res[1]) - ref_out["mu"]) <= 1e-10 * max(1.0, abs(ref_out["mu"]))
+    assert abs(float(res[1].detach()) - ref_out["mu"]) <= 1e-10 * max(1.0, abs(ref_out["mu"]))
     assert rel_err(host(H_R.grad), flat(ref["H_R"])) < 1e-9
     assert rel_err(host(V_R.grad), flat(ref["V_R"])) < 1e-9
 
@@ -310,7 +327,7 @@ def test_checkpointing_changes_nothing(case):
     for ck in (True, False):
         H_R = dev(flat(m.H_R)).requires_grad_(True)
         V_R = dev(flat(m.V_R)).requires_grad_(True)
-        _torch_loss(qa.run(p, H_R, V_R, m.n_target, n_iter=2, checkpointed=ck)[-1], cot).backward()
+        _torch_loss(qa.run(p, H_R, V_R, m.n_target, n_iter=2, checkpointed=ck)[-1], cot, p, H_R).backward()
         grads.append((host(H_R.grad), host(V_R.grad)))
     assert rel_err(grads[0][0], grads[1][0]) < 1e-13
     assert rel_err(grads[0][1], grads[1][1]) < 1e-13
@@ -325,11 +342,12 @@ def test_gradient_against_gpu_finite_differences(case):
     rng = np.random.default_rng(31)
     H_R = dev(flat(m.H_R)).requires_grad_(True)
     V_R = dev(flat(m.V_R)).requires_grad_(True)
-    _torch_loss(qa.run(p, H_R, V_R, m.n_target, n_iter=1)[-1], cot).backward()
+    _torch_loss(qa.run(p, H_R, V_R, m.n_target, n_iter=1)[-1], cot, p, H_R).backward()
 
     def L(h, v):
         with torch.no_grad():
-            return float(_torch_loss(qa.run(p, dev(flat(h)), dev(flat(v)), m.n_target, n_iter=1)[-1], cot))
+            hh = dev(flat(h))
+            return float(_torch_loss(qa.run(p, hh, dev(flat(v)), m.n_target, n_iter=1)[-1], cot, p, hh))
 
     def sym(shape):
         x = crand(rng, shape)
@@ -342,6 +360,33 @@ def test_gradient_against_gpu_finite_differences(case):
         num = directional_fd(f, x0, dirn)
         ana = float(np.sum(np.conj(g) * flat(dirn)).real)
         assert abs(num - ana) <= 1e-5 * abs(num) + 1e-9 * np.linalg.norm(g), (name, num, ana)
+
+
+def test_energy_and_its_adjoint(case):
+    torch = _torch()
+    m, d, p, out = case.m, case.d, case.plan, case.out
+    ref = gw.total_energy(m, d, out)
+    args = [dev(flat(m.H_k)), dev(flat(out["sig_hf_k"])), dev(flat(out["sig_iw"])), dev(flat(out["G_iw"]))]
+    e = p.energy(*args)
+    for got, want in zip(e, ref):
+        assert abs(got - want) <= 1e-10 * max(1.0, abs(ref[0])), (e, ref)
+    outs = [torch.empty_like(t) for t in args]
+    p.energy_bwd(*args, 0.8, *outs)
+    rv = ad.energy_vjp(m, d, out, 0.8)
+    for key, got in zip(("H_k", "sig_hf_k"), outs[:2]):
+        assert rel_err(host(got), flat(rv[key])) < 1e-9, key
+    # The Sigma and G cotangents pass through the Matsubara-sum map K^{-T} D K^{-1}, which
+    # the two sides build independently; entry by entry they agree only to what the
+    # kernel's conditioning allows.  Paired with representable directions K c (the
+    # derivative of the energy along a DLR-representable change) they agree to rounding.
+    rng = np.random.default_rng(7)
+    for key, got in zip(("sig_iw", "G_iw"), outs[2:]):
+        assert rel_err(host(got), flat(rv[key])) < MAP_TOL, key
+        for _ in range(3):
+            x_rep = apply_map(d.K_f, crand(rng, rv[key].shape))
+            a = float(np.sum(np.conj(host(got)) * flat(x_rep)).real)
+            b = float(np.sum(np.conj(rv[key]) * x_rep).real)
+            assert abs(a - b) <= 1e-9 * abs(b), (key, a, b)
 
 
 def test_adjoints_reject_fp32_plans(case):

@@ -81,6 +81,13 @@ def test_dlr_maps_match_oracle(case):
         # matrices themselves to what their conditioning allows
         assert rel_err(lib_map, getattr(case.d, name)) < 1e-5
     assert rel_err(case.plan.get_map(qgw.F_IW2BETA)[0], case.d.F_iw2beta) < 1e-5
+    # The Matsubara-sum map K^{-T} D K^{-1} of the energy carries the square of the
+    # condition number of the fermionic kernel (about 1e11 here), so two independent
+    # builds of it differ at O(1) entry by entry.  What it defines is the bilinear form
+    # on DLR-representable data: K^T Q K must give the divided-difference matrix D.
+    K = case.d.K_f
+    form = K.T @ case.plan.get_map(qgw.F_IW2GM) @ K
+    assert rel_err(form, case.d.D_sum) < 1e-9
 
 
 def test_a1_dlr_transform(case):
