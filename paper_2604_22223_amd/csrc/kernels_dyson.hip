@@ -162,218 +162,203 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
 
 // ---------------------------------------------------------------------------
 // Register-blocked form of the same solve for N_b = 25 (the five-orbital
-// product basis).  One wavefront per (node, q) matrix; the augmented system
-// [I - V P | V] (25 x 50) is split into blocks of 4 rows x 7 columns, lane
-// = 8 cg + rg holding rows 4 rg .. 4 rg + 3 and columns 7 cg .. 7 cg + 6
-// (rows >= 25 and columns >= 50 are zero padding).  A Gauss-Jordan step
-// reads the pivot row's 7 columns and the 4 multipliers of its rows from LDS
-// and does 28 complex updates, so every value read is used four times.  The
-// pivot row is found by an arg-max over the 8 lanes that hold column k (the
-// lane index of that group, the column slot and the step are compile-time
-// constants; the winner is read back with a wave-uniform readlane), and the
-// pivot row's owner writes it through a wave-uniform branch on its slot, so
-// no register array is indexed dynamically.
+// product basis).  One wavefront per (node, q) matrix.  The augmented system
+// [I - V P | V] (25 x 50, padded to 32 x 56) is spread over the 64 lanes with
+// rows and columns interleaved: lane = rg + 8 cg holds rows rg + 8 s (s < 4)
+// and columns cg + 8 t (t < 7) of the combined column index (0..24 for
+// I - V P, 25..49 for V; everything else is zero padding).
+//  * V P is formed in that layout from P and V in LDS: per summation index a
+//    lane reads 4 values of V and 4 of P and does 16 complex multiply-adds.
+//    The V rows rg + 8 s of one read sit in distinct banks.
+//  * Gauss-Jordan step K (a compile-time constant): the lanes holding column
+//    K rank their unused rows by |Re| + |Im|, packed with the row number into
+//    one 32-bit key (ties go to the lower row); three DPP shifts inside the
+//    8-lane group and one readlane give the pivot row p.  The owners of row
+//    p publish it, the owners of column K publish the multipliers (the
+//    pivot's own entry less one), and every lane subtracts f_r * (pivot row)
+//    with f_r = m_r / a_pK, which normalises the pivot row and clears column
+//    K in every other row.
+//  * Columns of I - V P left of K are never read again, so a slot whose
+//    columns are all <= K drops out of the update: 145 slot updates over the
+//    25 steps instead of 175.
+// LDS holds P and V (20,000 bytes in FP64, so eight blocks fit a CU); the P
+// area is reused for the pivot exchange and then for staging the store.
 // ---------------------------------------------------------------------------
-// lane l takes the (value, index) of lane l + n of its DPP row (row_shl:n) if
-// that value is larger; lanes without a source keep their own
 template <int CTRL>
 __device__ __forceinline__ int dpp_shl_i(int v) {
   return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
 }
-template <int CTRL>
-__device__ __forceinline__ double dpp_shl(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = dpp_shl_i<CTRL>(int(b & 0xffffffffLL));
-  const int hi = dpp_shl_i<CTRL>(int(b >> 32));
-  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+
+// 1 / d by the hardware estimate and Newton-Raphson steps r <- r (2 - d r)
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
 }
-template <int CTRL>
-__device__ __forceinline__ float dpp_shl(float v) {
-  return __int_as_float(dpp_shl_i<CTRL>(__float_as_int(v)));
-}
-template <int CTRL, typename T>
-__device__ __forceinline__ void dpp_argmax_step(T& bv, int& bi) {
-  const T ov = dpp_shl<CTRL>(bv);
-  const int oi = dpp_shl_i<CTRL>(bi);
-  if (ov > bv) {
-    bv = ov;
-    bi = oi;
-  }
+__device__ __forceinline__ float rcp_nr(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return __builtin_fmaf(r, __builtin_fmaf(-d, r, 1.0f), r);
 }
 
-// one Gauss-Jordan step of k_dyson_w25 on column K (K a compile-time constant)
+// arg-max key of a pivot candidate: |Re| + |Im| rounded to FP32 with the low
+// five bits replaced by 31 - row (larger key = larger value, then lower row)
+template <typename T>
+__device__ __forceinline__ int pivot_key(cpx<T> a, int row, bool ok) {
+  const float n = float(fabs(a.re) + fabs(a.im));
+  const int k = (__float_as_int(n) & ~31) | (31 - row);
+  return ok ? k : -1;
+}
+
+struct W25 {
+  static constexpr int NB = 25, NS = 4, NT = 7;
+  static constexpr int ROW = 56;             // pivot-row buffer: 56 combined columns
+  static constexpr int MULT = 2 * 4 * ROW;   // offset of the multiplier buffers
+};
+
+// the owners of pivot row p = rg + 8 S publish it (slots from the one holding
+// column K on) and record the step; the owner of a_pK also stores a_pK - 1 as
+// the pivot row's multiplier
+template <typename T, int K, int S>
+__device__ __forceinline__ void gj25_publish(const cpx<T> (&x)[4][7], cpx<T>* xs, int cg, int p, int& used,
+                                             int (&kof)[4]) {
+  constexpr int tk = K / 8, buf = K & 1;
+  cpx<T>* pr = xs + (buf * 4 + S) * W25::ROW;
+#pragma unroll
+  for (int t = tk; t < W25::NT; ++t) pr[cg + 8 * t] = x[S][t];
+  if (cg == K % 8) xs[W25::MULT + buf * 32 + p] = mk(x[S][tk].re - T(1), x[S][tk].im);
+  used |= 1 << S;
+  kof[S] = K;
+}
+
 template <typename T, int K>
-__device__ __forceinline__ void gj25_step(cpx<T> (&x)[4][7], bool (&used)[4], int (&step_of)[4], int rg, int cg,
-                                          cpx<T> (*prow)[56], cpx<T> (*mult)[32]) {
-  constexpr int NB = 25, RPL = 4, CPL = 7;
-  constexpr int cgk = K / CPL, ck = K % CPL, buf = K & 1;
-  // arg-max of |a_rk| over the unused rows, in the 8 lanes holding column K
-  T bv = T(-1);
-  int bi = rg * RPL;
-  if (cg == cgk) {
+__device__ __forceinline__ void gj25_step(cpx<T> (&x)[4][7], int& used, int (&kof)[4], int rg, int cg, cpx<T>* xs) {
+  constexpr int NB = W25::NB, NS = W25::NS, NT = W25::NT;
+  constexpr int cgk = K % 8, tk = K / 8, buf = K & 1, t0 = (K + 1) / 8;
+  const bool mine = cg == cgk;
+  int key = -1;
 #pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-      const int row = rg * RPL + s;
-      const T v = (row < NB && !used[s]) ? norm2(x[s][ck]) : T(-1);
-      if (v > bv) {
-        bv = v;
-        bi = row;
-      }
-    }
+  for (int s = 0; s < NS; ++s) {
+    const int row = rg + 8 * s;
+    key = max(key, pivot_key(x[s][tk], row, mine && row < NB && !((used >> s) & 1)));
   }
-  // shift reductions inside the 16-lane DPP row: after the three rounds the
-  // group's first lane holds the arg-max of its 8 lanes (on ties the lower
-  // lane, i.e. the lower row, stays)
-  dpp_argmax_step<0x104>(bv, bi);
-  dpp_argmax_step<0x102>(bv, bi);
-  dpp_argmax_step<0x101>(bv, bi);
-  const int p = __builtin_amdgcn_readlane(bi, cgk * 8);
-  const int rgp = p >> 2, sp = p & 3;
-  // the pivot row's owners publish it; the column-K owners publish the multipliers
+  key = max(key, dpp_shl_i<0x104>(key));
+  key = max(key, dpp_shl_i<0x102>(key));
+  key = max(key, dpp_shl_i<0x101>(key));
+  const int p = 31 - (__builtin_amdgcn_readlane(key, cgk * 8) & 31);
+  const int rgp = p & 7, sp = p >> 3;
+  cpx<T>* mu = xs + W25::MULT + buf * 32;
+  if (mine) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) mu[rg + 8 * s] = x[s][tk];
+  }
   if (rg == rgp) {
-    if (sp == 0) {
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) prow[buf][cg * CPL + c] = x[0][c];
-      used[0] = true;
-      step_of[0] = K;
-    } else if (sp == 1) {
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) prow[buf][cg * CPL + c] = x[1][c];
-      used[1] = true;
-      step_of[1] = K;
-    } else if (sp == 2) {
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) prow[buf][cg * CPL + c] = x[2][c];
-      used[2] = true;
-      step_of[2] = K;
-    } else {
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) prow[buf][cg * CPL + c] = x[3][c];
-      used[3] = true;
-      step_of[3] = K;
-    }
-  }
-  if (cg == cgk) {
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) mult[buf][rg * RPL + s] = x[s][ck];
+    if (sp == 0)
+      gj25_publish<T, K, 0>(x, xs, cg, p, used, kof);
+    else if (sp == 1)
+      gj25_publish<T, K, 1>(x, xs, cg, p, used, kof);
+    else if (sp == 2)
+      gj25_publish<T, K, 2>(x, xs, cg, p, used, kof);
+    else
+      gj25_publish<T, K, 3>(x, xs, cg, p, used, kof);
   }
   __syncthreads();
-  cpx<T> f[RPL];
-  const cpx<T> pinv = inv(prow[buf][K]);
+  const cpx<T>* pr = xs + (buf * 4 + sp) * W25::ROW;
+  const cpx<T> pv = pr[K];
+  const T d = rcp_nr(norm2(pv));
+  const cpx<T> pinv = mk(pv.re * d, -pv.im * d);
+  cpx<T> f[NS];
 #pragma unroll
-  for (int s = 0; s < RPL; ++s) {
-    const bool is_p = (rg == rgp) && (s == sp);
-    f[s] = is_p ? mk(T(1), T(0)) - pinv : mult[buf][rg * RPL + s] * pinv;
-  }
-  // column by column, so that only one pivot-row value is live at a time
+  for (int s = 0; s < NS; ++s) f[s] = mu[rg + 8 * s] * pinv;
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    const cpx<T> pc = prow[buf][cg * CPL + c];
+  for (int t = t0; t < NT; ++t) {
+    const cpx<T> pc = pr[cg + 8 * t];
 #pragma unroll
-    for (int s = 0; s < RPL; ++s) x[s][c] = fms(x[s][c], f[s], pc);
+    for (int s = 0; s < NS; ++s) x[s][t] = fms(x[s][t], f[s], pc);
   }
 }
 
 template <typename T, int... K>
-__device__ __forceinline__ void gj25_all(cpx<T> (&x)[4][7], bool (&used)[4], int (&step_of)[4], int rg, int cg,
-                                         cpx<T> (*prow)[56], cpx<T> (*mult)[32], std::integer_sequence<int, K...>) {
-  (gj25_step<T, K>(x, used, step_of, rg, cg, prow, mult), ...);
+__device__ __forceinline__ void gj25_all(cpx<T> (&x)[4][7], int& used, int (&kof)[4], int rg, int cg, cpx<T>* xs,
+                                         std::integer_sequence<int, K...>) {
+  (gj25_step<T, K>(x, used, kof, rg, cg, xs), ...);
 }
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
                                                   cpx<T>* __restrict__ wc, int64_t nmat, int nk) {
-  constexpr int NB = 25, NN = NB * NB, RPL = 4, CPL = 7, NCOL = 8 * CPL;
-  __shared__ cpx<T> sbuf[NN];          // P, then I - V P, then W^C for the store
-  __shared__ cpx<T> sv[NN];            // V(q)
-  __shared__ cpx<T> prow[2][NCOL];     // pivot row (double-buffered by step parity)
-  __shared__ cpx<T> mult[2][8 * RPL];  // column k of every row
+  constexpr int NB = W25::NB, NN = NB * NB, NS = W25::NS, NT = W25::NT;
+  __shared__ cpx<T> sp_[NN];  // P; then the pivot exchange; then W^C for the store
+  __shared__ cpx<T> sv[NN];   // V(q)
   const int lane = threadIdx.x;
   const int rg = lane & 7, cg = lane >> 3;
   const int64_t mat = blockIdx.x;
   const int q = int(mat % nk);
   const cpx<T>* vm = vq + int64_t(q) * NN;
-  const cpx<T> zero = mk(T(0), T(0));
+  const cpx<T>* pm = pnu + mat * NN;
   for (int e = lane; e < NN; e += 64) {
-    sbuf[e] = pnu[mat * NN + e];
+    sp_[e] = pm[e];
     sv[e] = vm[e];
   }
   __syncthreads();
-  // V P by 52 lanes: lane = 13 r7 + c2 (r7 < 4) owns rows 7 r7 .. 7 r7 + 6 and columns 2 c2, 2 c2 + 1
+  cpx<T> x[NS][NT];
   {
-    const int r7 = lane / 13, c2 = lane - 13 * (lane / 13);
-    const bool act = r7 < 4;
-    const int ca = 2 * c2, cb = 2 * c2 + 1 < NB ? 2 * c2 + 1 : NB - 1;
-    cpx<T> acc[7][2];
+    // V P on the slots of I - V P (t < 3, and t = 3 where cg = 0: column 24)
+    cpx<T> acc[NS][4];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) acc[i][0] = acc[i][1] = zero;
-    if (act) {
-      for (int j = 0; j < NB; ++j) {
-        const cpx<T> pa = sbuf[j * NB + ca], pb = sbuf[j * NB + cb];
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int i = 0; i < 7; ++i) {
-          const int row = 7 * r7 + i < NB ? 7 * r7 + i : NB - 1;
-          const cpx<T> v = sv[row * NB + j];
-          acc[i][0] = fma(acc[i][0], v, pa);
-          acc[i][1] = fma(acc[i][1], v, pb);
-        }
-      }
+      for (int t = 0; t < 4; ++t) acc[s][t] = mk(T(0), T(0));
+#pragma unroll 5
+    for (int j = 0; j < NB; ++j) {
+      cpx<T> v[NS], pj[4];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) v[s] = sv[min(rg + 8 * s, NB - 1) * NB + j];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) pj[t] = sp_[j * NB + min(cg + 8 * t, NB - 1)];
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[s][t] = fma(acc[s][t], v[s], pj[t]);
     }
-    __syncthreads();  // every lane has read P
-    if (act) {
 #pragma unroll
-      for (int i = 0; i < 7; ++i) {
-        const int row = 7 * r7 + i;
+    for (int s = 0; s < NS; ++s) {
+      const int row = rg + 8 * s;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int c = cg + 8 * t;
+        cpx<T> val = mk(T(0), T(0));
         if (row < NB) {
-          sbuf[row * NB + ca] = mk(T(row == ca ? 1 : 0) - acc[i][0].re, -acc[i][0].im);
-          if (2 * c2 + 1 < NB) sbuf[row * NB + cb] = mk(T(row == cb ? 1 : 0) - acc[i][1].re, -acc[i][1].im);
+          if (t < 4 && c < NB)
+            val = mk(T(row == c ? 1 : 0) - acc[s][t < 4 ? t : 0].re, -acc[s][t < 4 ? t : 0].im);
+          else if (c >= NB && c < 2 * NB)
+            val = sv[row * NB + c - NB];
         }
+        x[s][t] = val;
       }
     }
-    __syncthreads();
   }
-  // this lane's block of [I - V P | V]
-  cpx<T> x[RPL][CPL];
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) {
-    const int row = rg * RPL + s;
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int col = cg * CPL + c;
-      cpx<T> val = zero;
-      if (row < NB) {
-        if (col < NB)
-          val = sbuf[row * NB + col];
-        else if (col < 2 * NB)
-          val = sv[row * NB + col - NB];
-      }
-      x[s][c] = val;
-    }
-  }
-  bool used[RPL];
-  int step_of[RPL];
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) {
-    used[s] = false;
-    step_of[s] = 0;
-  }
-  gj25_all<T>(x, used, step_of, rg, cg, prow, mult, std::make_integer_sequence<int, NB>{});
-  // row r of the V part is row step_of[r] of W; W^C = W - V, staged for a contiguous store
+  __syncthreads();  // P is no longer read: its area takes the pivot exchange
+  int used = 0;
+  int kof[NS] = {0, 0, 0, 0};
+  gj25_all<T>(x, used, kof, rg, cg, sp_, std::make_integer_sequence<int, NB>{});
+  // row r of the V part is row kof of W; W^C = W - V, staged for a contiguous store
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < RPL; ++s) {
-    const int row = rg * RPL + s;
+  for (int s = 0; s < NS; ++s) {
+    const int row = rg + 8 * s;
     if (row < NB) {
-      const int k = step_of[s];
+      const int k = kof[s];
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int col = cg * CPL + c - NB;
-        if (col >= 0 && col < NB) sbuf[k * NB + col] = x[s][c] - sv[k * NB + col];
+      for (int t = 3; t < NT; ++t) {
+        const int col = cg + 8 * t - NB;
+        if (col >= 0 && col < NB) sp_[k * NB + col] = x[s][t] - sv[k * NB + col];
       }
     }
   }
   __syncthreads();
-  for (int e = lane; e < NN; e += 64) wc[mat * NN + e] = sbuf[e];
+  for (int e = lane; e < NN; e += 64) wc[mat * NN + e] = sp_[e];
 }
 
 // ---------------------------------------------------------------------------
