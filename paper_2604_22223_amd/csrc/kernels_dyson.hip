@@ -163,26 +163,30 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
 // ---------------------------------------------------------------------------
 // Register-blocked form of the same solve for N_b = 25 (the five-orbital
 // product basis).  One wavefront per (node, q) matrix.  The augmented system
-// [I - V P | V] (25 x 50, padded to 32 x 56) is spread over the 64 lanes with
-// rows and columns interleaved: lane = rg + 8 cg holds rows rg + 8 s (s < 4)
-// and columns cg + 8 t (t < 7) of the combined column index (0..24 for
-// I - V P, 25..49 for V; everything else is zero padding).
-//  * V P is formed in that layout from P and V in LDS: per summation index a
-//    lane reads 4 values of V and 4 of P and does 16 complex multiply-adds.
-//    The V rows rg + 8 s of one read sit in distinct banks.
+// [I - V P | V] is 25 x 50; its columns are numbered 0..24 for I - V P and
+// 25..49 for V (56 with zero padding).  Lane = rg + 8 cg holds
+//  * rows rg + 8 s (s < 3, rows 0..23) in columns cg + 8 t (t < 7), and
+//  * one entry of row 24, column cg + 8 rg,
+// so the last row costs one register pair per lane instead of a mostly empty
+// fourth row slot.
+//  * V P is formed in that layout: per summation index j a lane reads 3
+//    values of V (rows rg + 8 s sit in distinct banks), V(24, j) (one
+//    address) and 4 + 1 values of P, and does 13 complex multiply-adds.  P
+//    is staged in LDS seven rows at a time, each chunk read into registers
+//    while the previous one is used.
 //  * Gauss-Jordan step K (a compile-time constant): the lanes holding column
-//    K rank their unused rows by |Re| + |Im|, packed with the row number into
-//    one 32-bit key (ties go to the lower row); three DPP shifts inside the
-//    8-lane group and one readlane give the pivot row p.  The owners of row
-//    p publish it, the owners of column K publish the multipliers (the
-//    pivot's own entry less one), and every lane subtracts f_r * (pivot row)
-//    with f_r = m_r / a_pK, which normalises the pivot row and clears column
-//    K in every other row.
+//    K rank their unused rows by |Re| + |Im|, rounded to FP32 and packed with
+//    31 - row into one 32-bit key (ties go to the lower row); three DPP
+//    shifts inside the 8-lane group and one readlane give the pivot row p.
+//    The owners of row p publish it, the owners of column K publish the
+//    multipliers (the pivot's own entry less one), and every lane subtracts
+//    f_r * (pivot row) with f_r = m_r / a_pK, which normalises the pivot
+//    row and clears column K in every other row.
 //  * Columns of I - V P left of K are never read again, so a slot whose
-//    columns are all <= K drops out of the update: 145 slot updates over the
-//    25 steps instead of 175.
-// LDS holds P and V (20,000 bytes in FP64, so eight blocks fit a CU); the P
-// area is reused for the pivot exchange and then for staging the store.
+//    columns are all <= K drops out of the update.
+// LDS holds V (10,000 bytes in FP64) and a 3,072-byte area shared by the P
+// chunks and the pivot exchange (two buffers, alternating by step): twelve
+// blocks fit a CU.
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ int dpp_shl_i(int v) {
@@ -202,125 +206,157 @@ __device__ __forceinline__ float rcp_nr(float d) {
   return __builtin_fmaf(r, __builtin_fmaf(-d, r, 1.0f), r);
 }
 
-// arg-max key of a pivot candidate: |Re| + |Im| rounded to FP32 with the low
-// five bits replaced by 31 - row (larger key = larger value, then lower row)
+// |Re| + |Im| rounded to FP32, as bits; a larger value compares larger
 template <typename T>
-__device__ __forceinline__ int pivot_key(cpx<T> a, int row, bool ok) {
-  const float n = float(fabs(a.re) + fabs(a.im));
-  const int k = (__float_as_int(n) & ~31) | (31 - row);
-  return ok ? k : -1;
+__device__ __forceinline__ int mag_bits(cpx<T> a) {
+  return __float_as_int(float(fabs(a.re) + fabs(a.im)));
 }
 
 struct W25 {
-  static constexpr int NB = 25, NS = 4, NT = 7;
-  static constexpr int ROW = 56;             // pivot-row buffer: 56 combined columns
-  static constexpr int MULT = 2 * 4 * ROW;   // offset of the multiplier buffers
+  static constexpr int NB = 25, NS = 3, NT = 7;
+  static constexpr int CH = 7;                   // rows of P per staged chunk
+  static constexpr int NCH = (NB + CH - 1) / CH;
+  static constexpr int ROW = 64;                 // pivot row: 56 columns and 8 zeros
+  static constexpr int EX = ROW + 32;            // pivot row and multipliers of one step
+  static constexpr int XS = 2 * EX;              // area shared by the P chunks and the pivot exchange
+  static constexpr int MIN = int(0x80000000u);
 };
+static_assert(W25::CH * W25::NB <= W25::XS, "a chunk of P must fit the exchange area");
 
-// the owners of pivot row p = rg + 8 S publish it (slots from the one holding
-// column K on) and record the step; the owner of a_pK also stores a_pK - 1 as
-// the pivot row's multiplier
+// The owners of pivot row p = rg + 8 S (S < 3) publish it from the slot
+// holding column K on, mark the row as used and record the step; the owner
+// of a_pK also stores a_pK - 1 as the pivot row's multiplier.
 template <typename T, int K, int S>
-__device__ __forceinline__ void gj25_publish(const cpx<T> (&x)[4][7], cpx<T>* xs, int cg, int p, int& used,
-                                             int (&kof)[4]) {
-  constexpr int tk = K / 8, buf = K & 1;
-  cpx<T>* pr = xs + (buf * 4 + S) * W25::ROW;
+__device__ __forceinline__ void gj25_publish(const cpx<T> (&x)[3][7], cpx<T>* xs, int cg, int p, int (&cs)[3],
+                                             int (&kof)[3]) {
+  constexpr int tk = K / 8;
+  xs += (K & 1) * W25::EX;
 #pragma unroll
-  for (int t = tk; t < W25::NT; ++t) pr[cg + 8 * t] = x[S][t];
-  if (cg == K % 8) xs[W25::MULT + buf * 32 + p] = mk(x[S][tk].re - T(1), x[S][tk].im);
-  used |= 1 << S;
+  for (int t = tk; t < W25::NT; ++t) xs[cg + 8 * t] = x[S][t];
+  if (cg == K % 8) xs[W25::ROW + p] = mk(x[S][tk].re - T(1), x[S][tk].im);
+  cs[S] |= W25::MIN;
   kof[S] = K;
 }
 
+// cs[s] = 31 - row for a candidate row, with the sign bit set once the row
+// has pivoted, so that a set sign drops it from the max
 template <typename T, int K>
-__device__ __forceinline__ void gj25_step(cpx<T> (&x)[4][7], int& used, int (&kof)[4], int rg, int cg, cpx<T>* xs) {
-  constexpr int NB = W25::NB, NS = W25::NS, NT = W25::NT;
-  constexpr int cgk = K % 8, tk = K / 8, buf = K & 1, t0 = (K + 1) / 8;
-  const bool mine = cg == cgk;
-  int key = -1;
+__device__ __forceinline__ void gj25_step(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs)[3], int (&kof)[3], int& k24,
+                                          int rg, int cg, cpx<T>* xs) {
+  constexpr int NS = W25::NS, NT = W25::NT, ROW = W25::ROW, MIN = W25::MIN;
+  constexpr int cgk = K % 8, tk = K / 8, t0 = (K + 1) / 8;
+  const bool used24 = k24 >= 0;
+  int key = (!used24 && rg == tk) ? ((mag_bits(y) & ~31) | (31 - 24)) : MIN;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int row = rg + 8 * s;
-    key = max(key, pivot_key(x[s][tk], row, mine && row < NB && !((used >> s) & 1)));
-  }
+  for (int s = 0; s < NS; ++s) key = max(key, (mag_bits(x[s][tk]) & ~31) | cs[s]);
+  key = cg == cgk ? key : MIN;
   key = max(key, dpp_shl_i<0x104>(key));
   key = max(key, dpp_shl_i<0x102>(key));
   key = max(key, dpp_shl_i<0x101>(key));
   const int p = 31 - (__builtin_amdgcn_readlane(key, cgk * 8) & 31);
   const int rgp = p & 7, sp = p >> 3;
-  cpx<T>* mu = xs + W25::MULT + buf * 32;
-  if (mine) {
+  cpx<T>* ex = xs + (K & 1) * W25::EX;  // exchange buffers alternate by step parity
+  cpx<T>* mu = ex + ROW;
+  if (cg == cgk) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) mu[rg + 8 * s] = x[s][tk];
+    if (rg == tk) mu[24] = y;
   }
-  if (rg == rgp) {
+  if (p == 24) {
+    if (rg < 7) ex[cg + 8 * rg] = y;
+    if (rg == tk && cg == cgk) mu[24] = mk(y.re - T(1), y.im);
+    k24 = K;
+  } else if (rg == rgp) {
     if (sp == 0)
-      gj25_publish<T, K, 0>(x, xs, cg, p, used, kof);
+      gj25_publish<T, K, 0>(x, xs, cg, p, cs, kof);
     else if (sp == 1)
-      gj25_publish<T, K, 1>(x, xs, cg, p, used, kof);
-    else if (sp == 2)
-      gj25_publish<T, K, 2>(x, xs, cg, p, used, kof);
+      gj25_publish<T, K, 1>(x, xs, cg, p, cs, kof);
     else
-      gj25_publish<T, K, 3>(x, xs, cg, p, used, kof);
+      gj25_publish<T, K, 2>(x, xs, cg, p, cs, kof);
   }
   __syncthreads();
-  const cpx<T>* pr = xs + (buf * 4 + sp) * W25::ROW;
-  const cpx<T> pv = pr[K];
+  const cpx<T> pv = ex[K];
   const T d = rcp_nr(norm2(pv));
   const cpx<T> pinv = mk(pv.re * d, -pv.im * d);
   cpx<T> f[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) f[s] = mu[rg + 8 * s] * pinv;
+  y = fms(y, mu[24] * pinv, ex[cg + 8 * rg]);
 #pragma unroll
   for (int t = t0; t < NT; ++t) {
-    const cpx<T> pc = pr[cg + 8 * t];
+    const cpx<T> pc = ex[cg + 8 * t];
 #pragma unroll
     for (int s = 0; s < NS; ++s) x[s][t] = fms(x[s][t], f[s], pc);
   }
 }
 
 template <typename T, int... K>
-__device__ __forceinline__ void gj25_all(cpx<T> (&x)[4][7], int& used, int (&kof)[4], int rg, int cg, cpx<T>* xs,
-                                         std::integer_sequence<int, K...>) {
-  (gj25_step<T, K>(x, used, kof, rg, cg, xs), ...);
+__device__ __forceinline__ void gj25_all(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs)[3], int (&kof)[3], int& k24, int rg,
+                                         int cg, cpx<T>* xs, std::integer_sequence<int, K...>) {
+  (gj25_step<T, K>(x, y, cs, kof, k24, rg, cg, xs), ...);
 }
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
                                                   cpx<T>* __restrict__ wc, int64_t nmat, int nk) {
-  constexpr int NB = W25::NB, NN = NB * NB, NS = W25::NS, NT = W25::NT;
-  __shared__ cpx<T> sp_[NN];  // P; then the pivot exchange; then W^C for the store
-  __shared__ cpx<T> sv[NN];   // V(q)
+  constexpr int NB = W25::NB, NN = NB * NB, NS = W25::NS, NT = W25::NT, CH = W25::CH, NCH = W25::NCH;
+  __shared__ cpx<T> xs[W25::XS];  // a chunk of P rows; then the pivot exchange
+  __shared__ cpx<T> sv[NN];       // V(q)
   const int lane = threadIdx.x;
   const int rg = lane & 7, cg = lane >> 3;
+  const int c24 = cg + 8 * rg;  // this lane's column of row 24
   const int64_t mat = blockIdx.x;
   const int q = int(mat % nk);
   const cpx<T>* vm = vq + int64_t(q) * NN;
   const cpx<T>* pm = pnu + mat * NN;
-  for (int e = lane; e < NN; e += 64) {
-    sp_[e] = pm[e];
-    sv[e] = vm[e];
-  }
-  __syncthreads();
-  cpx<T> x[NS][NT];
+  // chunk c of P (rows CH c ..) is read into registers one chunk ahead; a
+  // chunk has at most 175 entries, three per lane
+  static_assert(CH * NB <= 3 * 64, "a chunk of P must fit three entries per lane");
+  cpx<T> pre0 = mk(T(0), T(0)), pre1 = pre0, pre2 = pre0;
+  auto load_chunk = [&](int c) {
+    const int n = min(CH, NB - CH * c) * NB;
+    const cpx<T>* src = pm + CH * c * NB;
+    if (lane < n) pre0 = src[lane];
+    if (lane + 64 < n) pre1 = src[lane + 64];
+    if (lane + 128 < n) pre2 = src[lane + 128];
+  };
+  load_chunk(0);
+  for (int e = lane; e < NN; e += 64) sv[e] = vm[e];
+  cpx<T> x[NS][NT], y;
   {
-    // V P on the slots of I - V P (t < 3, and t = 3 where cg = 0: column 24)
-    cpx<T> acc[NS][4];
+    // V P on the columns of I - V P: slots t < 3, t = 3 where cg = 0 (column
+    // 24), and row 24 at column c24 < 25
+    cpx<T> acc[NS][4], a24 = mk(T(0), T(0));
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[s][t] = mk(T(0), T(0));
-#pragma unroll 5
-    for (int j = 0; j < NB; ++j) {
-      cpx<T> v[NS], pj[4];
+    const int j24 = min(c24, NB - 1);
+#pragma unroll 1
+    for (int c = 0; c < NCH; ++c) {
+      const int rows = min(CH, NB - CH * c);
+      __syncthreads();  // the previous chunk has been read
+      if (lane < rows * NB) xs[lane] = pre0;
+      if (lane + 64 < rows * NB) xs[lane + 64] = pre1;
+      if (lane + 128 < rows * NB) xs[lane + 128] = pre2;
+      if (c + 1 < NCH) load_chunk(c + 1);
+      __syncthreads();
 #pragma unroll
-      for (int s = 0; s < NS; ++s) v[s] = sv[min(rg + 8 * s, NB - 1) * NB + j];
+      for (int jj = 0; jj < CH; ++jj) {
+        if (jj < rows) {
+          const int j = CH * c + jj;
+          cpx<T> v[NS], pj[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) pj[t] = sp_[j * NB + min(cg + 8 * t, NB - 1)];
+          for (int s = 0; s < NS; ++s) v[s] = sv[(rg + 8 * s) * NB + j];
 #pragma unroll
-      for (int s = 0; s < NS; ++s)
+          for (int t = 0; t < 4; ++t) pj[t] = xs[jj * NB + min(cg + 8 * t, NB - 1)];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[s][t] = fma(acc[s][t], v[s], pj[t]);
+          for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[s][t] = fma(acc[s][t], v[s], pj[t]);
+          a24 = fma(a24, sv[24 * NB + j], xs[jj * NB + j24]);
+        }
+      }
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -329,36 +365,40 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
       for (int t = 0; t < NT; ++t) {
         const int c = cg + 8 * t;
         cpx<T> val = mk(T(0), T(0));
-        if (row < NB) {
-          if (t < 4 && c < NB)
-            val = mk(T(row == c ? 1 : 0) - acc[s][t < 4 ? t : 0].re, -acc[s][t < 4 ? t : 0].im);
-          else if (c >= NB && c < 2 * NB)
-            val = sv[row * NB + c - NB];
-        }
+        if (t < 4 && c < NB)
+          val = mk(T(row == c ? 1 : 0) - acc[s][t < 4 ? t : 0].re, -acc[s][t < 4 ? t : 0].im);
+        else if (c >= NB && c < 2 * NB)
+          val = sv[row * NB + c - NB];
         x[s][t] = val;
       }
     }
+    y = mk(T(0), T(0));
+    if (c24 < NB)
+      y = mk(T(c24 == 24 ? 1 : 0) - a24.re, -a24.im);
+    else if (c24 < 2 * NB)
+      y = sv[24 * NB + c24 - NB];
   }
-  __syncthreads();  // P is no longer read: its area takes the pivot exchange
-  int used = 0;
-  int kof[NS] = {0, 0, 0, 0};
-  gj25_all<T>(x, used, kof, rg, cg, sp_, std::make_integer_sequence<int, NB>{});
-  // row r of the V part is row kof of W; W^C = W - V, staged for a contiguous store
-  __syncthreads();
+  __syncthreads();  // the last chunk has been read: its area takes the pivot exchange
+  if (lane < 16) xs[(lane >> 3) * W25::EX + 56 + (lane & 7)] = mk(T(0), T(0));  // pivot-row padding columns
+  int cs[NS], kof[NS], k24 = -1;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const int row = rg + 8 * s;
-    if (row < NB) {
-      const int k = kof[s];
+    cs[s] = 31 - (rg + 8 * s);
+    kof[s] = 0;
+  }
+  gj25_all<T>(x, y, cs, kof, k24, rg, cg, xs, std::make_integer_sequence<int, NB>{});
+  // row r of the V part is row kof of W; W^C = W - V
+  cpx<T>* wm = wc + mat * NN;
 #pragma unroll
-      for (int t = 3; t < NT; ++t) {
-        const int col = cg + 8 * t - NB;
-        if (col >= 0 && col < NB) sp_[k * NB + col] = x[s][t] - sv[k * NB + col];
-      }
+  for (int s = 0; s < NS; ++s) {
+    const int k = kof[s];
+#pragma unroll
+    for (int t = 3; t < NT; ++t) {
+      const int col = cg + 8 * t - NB;
+      if (col >= 0 && col < NB) wm[k * NB + col] = x[s][t] - sv[k * NB + col];
     }
   }
-  __syncthreads();
-  for (int e = lane; e < NN; e += 64) wc[mat * NN + e] = sp_[e];
+  if (c24 >= NB && c24 < 2 * NB) wm[k24 * NB + c24 - NB] = y - sv[k24 * NB + c24 - NB];
 }
 
 // ---------------------------------------------------------------------------
