@@ -129,8 +129,12 @@ __global__ __launch_bounds__(256) void k_bubble(const cpx<T>* __restrict__ gt,
 
 // ---------------------------------------------------------------------------
 // self-energy: Sigma_{ik}(R, tau) = - sum_{(il),(jk)} W^C_{(il),(jk)}(R, tau) G_{lj}(R, tau)
-// one block per output slab (t, i, k); ``spb`` term lanes work on different
-// (alpha, beta) terms at once and are summed at the end.
+// One block per output slab (t, i, k); ``spb`` term lanes work on different
+// (alpha, beta) terms at once and are summed at the end.  Per term a thread
+// loads one column of the W^C(q) slab straight into registers (24
+// independent, coalesced loads), transforms it along q1, passes it through
+// LDS once to hold a row R1 of the slab, transforms along q2, and
+// accumulates -W G for that row.  The summed slab goes R -> k through LDS.
 // ---------------------------------------------------------------------------
 template <int N, bool INQ, bool OUTK, typename T>
 __global__ __launch_bounds__(256) void k_sigma(const cpx<T>* __restrict__ gt,
@@ -149,88 +153,80 @@ __global__ __launch_bounds__(256) void k_sigma(const cpx<T>* __restrict__ gt,
   const int lane = threadIdx.x / N, line = threadIdx.x - lane * N;
   const bool act = lane < spb;
   const T inv_nk = INQ ? T(1) / T(M::NN) : T(1);
-  cpx<T> acc[N];
+  cpx<T> acc[N];  // row R1 = line of this lane's partial sum
 #pragma unroll
   for (int j = 0; j < N; ++j) acc[j] = mk(T(0), T(0));
   cpx<T> x[N];
+  cpx<T>* slab = lds + lane * M::SLAB;
   for (int c0 = tb; c0 < te; c0 += spb) {
-    const int nloc = (te - c0 < spb) ? te - c0 : spb;
-    if (INQ) {
-      // stage the W^C slabs of this chunk (q domain) in LDS
-      for (int e = threadIdx.x; e < nloc * M::NN; e += blockDim.x) {
-        const int sl = e / M::NN, rem = e - sl * M::NN;
-        const int4 tm = terms[c0 + sl];
-        const cpx<T>* w = wc + ((t * nb + tm.x) * nb + tm.y) * M::NN;
-        const int q1 = rem / N, q2 = rem - q1 * N;
-        lds[sl * M::SLAB + q1 * M::LD + q2] = w[rem];
-      }
-      __syncthreads();
-      if (act && lane < nloc) {
-        cpx<T>* slab = lds + lane * M::SLAB;
-#pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = slab[line * M::LD + j];
-        fft_reg<N, +1>(x, tw);  // q2 -> R2
-#pragma unroll
-        for (int j = 0; j < N; ++j) slab[line * M::LD + j] = x[j];
-      }
-      __syncthreads();
-    }
-    if (act && lane < nloc) {
-      const int4 tm = terms[c0 + lane];
+    const bool mine = act && c0 + lane < te;
+    int4 tm = make_int4(0, 0, 0, 0);
+    if (mine) {
+      tm = terms[c0 + lane];
+      const cpx<T>* w = wc + ((t * nb + tm.x) * nb + tm.y) * M::NN;
       if (INQ) {
-        const cpx<T>* slab = lds + lane * M::SLAB;
 #pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = slab[j * M::LD + line];
-        fft_reg<N, +1>(x, tw);  // q1 -> R1
+        for (int j = 0; j < N; ++j) x[j] = w[j * N + line];  // column q2 = line
+        fft_reg<N, +1>(x, tw);                                 // q1 -> R1
+#pragma unroll
+        for (int j = 0; j < N; ++j) slab[j * M::LD + line] = x[j];
       } else {
-        const cpx<T>* w = wc + ((t * nb + tm.x) * nb + tm.y) * M::NN;
 #pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = w[j * N + line];
+        for (int j = 0; j < N; ++j) x[j] = w[line * N + j];  // row R1 = line
       }
-      const cpx<T>* g = gt + ((t * no + tm.z) * no + tm.w) * M::NN;
-#pragma unroll
-      for (int j = 0; j < N; ++j) acc[j] = fms(acc[j], x[j], g[j * N + line]);
     }
-    if (INQ) __syncthreads();
-  }
-  // reduce the term lanes: lane partial sums -> LDS, lane 0 threads add up
-  if (act) {
-    cpx<T>* slab = lds + lane * M::SLAB;
+    if (INQ) {
+      __syncthreads();
+      if (mine) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) slab[j * M::LD + line] = acc[j];
+        for (int j = 0; j < N; ++j) x[j] = slab[line * M::LD + j];  // row R1 = line
+        fft_reg<N, +1>(x, tw);                                       // q2 -> R2
+      }
+      __syncthreads();  // the slab is free for the next term
+    }
+    if (mine) {
+      const cpx<T>* g = gt + ((t * no + tm.z) * no + tm.w) * M::NN + line * N;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc[j] = fms(acc[j], x[j], g[j]);
+    }
+  }
+  // reduce the term lanes: lane partial rows -> LDS, lane 0 threads add up
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) slab[line * M::LD + j] = acc[j];
   }
   __syncthreads();
   const bool lead = threadIdx.x < N;
   if (lead) {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      cpx<T> s = lds[j * M::LD + line];
-      for (int l2 = 1; l2 < spb; ++l2) s = s + lds[l2 * M::SLAB + j * M::LD + line];
+      cpx<T> s = lds[line * M::LD + j];
+      for (int l2 = 1; l2 < spb; ++l2) s = s + lds[l2 * M::SLAB + line * M::LD + j];
       x[j] = scale(s, inv_nk);
     }
   }
   if (!OUTK) {
     if (lead) {
-      cpx<T>* o = sig + int64_t(out_slab) * M::NN;
+      cpx<T>* o = sig + int64_t(out_slab) * M::NN + line * N;
 #pragma unroll
-      for (int j = 0; j < N; ++j) o[j * N + line] = x[j];
+      for (int j = 0; j < N; ++j) o[j] = x[j];
     }
     return;
   }
-  // forward transform of the summed slab: R1 -> k1 (columns), then R2 -> k2
+  // forward transform of the summed slab: R2 -> k2 along the row, then R1 -> k1
   __syncthreads();  // every lane has read its partial sums
   if (lead) {
     fft_reg<N, -1>(x, tw);
 #pragma unroll
-    for (int j = 0; j < N; ++j) lds[j * M::LD + line] = x[j];
+    for (int j = 0; j < N; ++j) lds[line * M::LD + j] = x[j];
   }
   __syncthreads();
   if (lead) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) x[j] = lds[line * M::LD + j];
+    for (int j = 0; j < N; ++j) x[j] = lds[j * M::LD + line];
     fft_reg<N, -1>(x, tw);
 #pragma unroll
-    for (int j = 0; j < N; ++j) lds[line * M::LD + j] = x[j];
+    for (int j = 0; j < N; ++j) lds[j * M::LD + line] = x[j];
   }
   __syncthreads();
   cpx<T>* o = sig + int64_t(out_slab) * M::NN;
