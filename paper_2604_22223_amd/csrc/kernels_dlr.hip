@@ -160,12 +160,13 @@ hipError_t dlr_launch(const Plan& p, int map, int64_t ncols, int na, int nq, dou
 // MFMA form for pair arrays (r <= 64): out = T in as a complex GEMM of an
 // r x r map with ~10^5-10^6 columns, done as four real products per 4-deep
 // slice on the 16x16x4 matrix cores (FP64 or FP32).  A block of 8 waves
-// keeps Re T and Im T in LDS ([16 MT][KP], zero padded); each wave computes a
-// strip of 16 columns for all rows.  When the layout changes, the 16 lanes
-// of a strip run along the index that is contiguous in the output, so every
-// wave writes whole 256-byte (FP64) runs per row; the 8 waves of a block take
-// 8 adjacent values of the other index, so together they read whole lines
-// of the input.
+// keeps Re T and Im T in LDS, zero padded and in operand order (the 64 values
+// one MFMA takes are consecutive, so the reads are free of bank conflicts);
+// each wave computes a strip of 16 columns for all rows.  When the layout
+// changes, the 16 lanes of a strip run along the index that is contiguous in
+// the output, so every wave writes whole 256-byte (FP64) runs per row; the 8
+// waves of a block take 8 adjacent values of the other index, so together
+// they read whole lines of the input.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Mfma;
@@ -187,8 +188,23 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
+// identity on a register value through a DPP move (quad_perm [0,1,2,3]); the
+// compiler cannot see through it, which keeps a software-pipelined load from
+// being folded back into its use
+template <typename T>
+__device__ __forceinline__ T dpp_identity(T v) {
+  static_assert(sizeof(T) % 4 == 0, "32-bit words");
+  int w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < int(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_update_dpp(w[i], w[i], 0xE4, 0xF, 0xF, false);
+  __builtin_memcpy(&v, w, sizeof(T));
+  return v;
+}
+
+// four waves per SIMD: two 512-thread blocks fit a CU
 template <typename T, int MT, int MODE, bool HERM_IN>
-__global__ __launch_bounds__(512) void k_dlr_mfma(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dlr_mfma(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                                   const cpx<T>* __restrict__ map, int r, int kp, int na,
                                                   int nq, int64_t nstrips, int no, T sre, T sim) {
   using M = Mfma<T>;
@@ -196,8 +212,12 @@ __global__ __launch_bounds__(512) void k_dlr_mfma(const cpx<T>* __restrict__ in,
   extern __shared__ unsigned char smem_raw[];
   T* tre = reinterpret_cast<T*>(smem_raw);
   T* tim = tre + MT * 16 * kp;
+  // operand order: entry ((k / 4) MT + mt) 64 + lane holds T[mt 16 + lane % 16][4 (k / 4) + lane / 16],
+  // so that the 64 lanes of one operand read 64 consecutive values
   for (int e = threadIdx.x; e < MT * 16 * kp; e += blockDim.x) {
-    const int i = e / kp, k = e - i * kp;
+    const int l = e & 63, g = e >> 6;
+    const int kk = g / MT, mt = g - kk * MT;
+    const int i = mt * 16 + (l & 15), k = 4 * kk + (l >> 4);
     const cpx<T> v = (i < r && k < r) ? map[int64_t(i) * r + k] : mk(T(0), T(0));
     tre[e] = v.re;
     tim[e] = v.im;
@@ -239,23 +259,28 @@ __global__ __launch_bounds__(512) void k_dlr_mfma(const cpx<T>* __restrict__ in,
       accr[mt] = v4{T(0), T(0), T(0), T(0)};
       acci[mt] = v4{T(0), T(0), T(0), T(0)};
     }
-    const cpx<T>* src = in + cin;
-    const cpx<T>* srcs = in + cswap;
+    // Loads are unconditional, so that two stay in flight: the node index is
+    // clamped to r - 1 (the map's zero padding for k >= r cancels what is
+    // read there) and a column outside the array reads column 0 (its results
+    // are not stored; every output column depends on its own input column only).
+    const cpx<T>* src = in + (valid ? cin : 0);
+    const cpx<T>* srcs = in + (valid ? cswap : 0);
     auto load = [&](int t) -> cpx<T> {
-      if (!(valid && t < r)) return mk(T(0), T(0));
-      cpx<T> v = src[int64_t(t) * plane];
-      if (HERM_IN) v = scale(v + conj(srcs[int64_t(t) * plane]), T(0.5));
+      const int64_t tc = t < r ? t : r - 1;
+      cpx<T> v = src[tc * plane];
+      if (HERM_IN) v = scale(v + conj(srcs[tc * plane]), T(0.5));
       return v;
     };
-    cpx<T> x = load(lk);
+    // the input slice is read two steps ahead of its use
+    cpx<T> x = dpp_identity(load(lk)), xn = dpp_identity(load(4 + lk));
     for (int kb = 0; kb < kp; kb += 4) {
-      const cpx<T> xn = load(kb + 4 + lk);
-      const int k = kb + lk;
+      const cpx<T> xnn = load(kb + 8 + lk);
+      const int kk = kb >> 2;
       T ar[MT], ai[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        ar[mt] = tre[(mt * 16 + lc) * kp + k];
-        ai[mt] = tim[(mt * 16 + lc) * kp + k];
+        ar[mt] = tre[(kk * MT + mt) * 64 + lane];
+        ai[mt] = tim[(kk * MT + mt) * 64 + lane];
       }
       // 2 MT independent accumulator chains per half-slice
 #pragma unroll
@@ -269,6 +294,7 @@ __global__ __launch_bounds__(512) void k_dlr_mfma(const cpx<T>* __restrict__ in,
         acci[mt] = M::mac(ai[mt], x.re, acci[mt]);
       }
       x = xn;
+      xn = xnn;
     }
     if (valid) {
       const cpx<T> sc = mk(sre, sim);
@@ -283,12 +309,139 @@ __global__ __launch_bounds__(512) void k_dlr_mfma(const cpx<T>* __restrict__ in,
   }
 }
 
+// Pair arrays with the slab <-> matrix layout change.  A block of 8 waves
+// takes a tile of 16 x 8 columns: 16 values of the index L that is contiguous
+// in the output (one per lane of a strip) and 8 values of the index W that is
+// contiguous in the input (one per wave).  Per 4-deep slice of the node axis
+// the block reads the 4 x 16 x 8 input values with one load per thread (eight
+// threads cover 128 contiguous bytes), issued a slice ahead, and passes them
+// through LDS (two buffers, alternating by slice); each wave then multiplies
+// its 16-column strip on the matrix cores and writes whole 16-value runs of
+// the output.  Slab -> matrix: L = pair index a, W = q; matrix -> slab:
+// L = q, W = a.
+template <typename T, int MT, int MODE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dlr_mfma_pairs(
+    const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ map, int r, int kp,
+    int na, int nq, int tiles_l, int64_t ntiles, T sre, T sim) {
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int WP = 9;             // padded W extent of the LDS tile
+  constexpr int XT = 4 * 16 * WP;   // one tile buffer (complex values)
+  extern __shared__ unsigned char smem_raw[];
+  T* tre = reinterpret_cast<T*>(smem_raw);
+  T* tim = tre + MT * 16 * kp;
+  cpx<T>* xt = reinterpret_cast<cpx<T>*>(tim + MT * 16 * kp);
+  for (int e = threadIdx.x; e < MT * 16 * kp; e += blockDim.x) {
+    const int l = e & 63, g = e >> 6;
+    const int kk = g / MT, mt = g - kk * MT;
+    const int i = mt * 16 + (l & 15), k = 4 * kk + (l >> 4);
+    const cpx<T> v = (i < r && k < r) ? map[int64_t(i) * r + k] : mk(T(0), T(0));
+    tre[e] = v.re;
+    tim[e] = v.im;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lc = lane & 15, lk = lane >> 4;
+  // the value this thread loads per slice: node lt, column (lL, lW) of the tile
+  const int lt = threadIdx.x >> 7, lL = (threadIdx.x >> 3) & 15, lW = threadIdx.x & 7;
+  const int nL = MODE == kSlabToMatrix ? na : nq, nW = MODE == kSlabToMatrix ? nq : na;
+  const int64_t plane = int64_t(na) * nq;
+  int buf = 0;  // slice parity, continued across tiles
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int tL = int(tile % tiles_l), tW = int(tile / tiles_l);
+    // input column of this thread's loads (clamped into the array: values
+    // outside it feed only columns that are not stored)
+    const int Lld = min(tL * 16 + lL, nL - 1), Wld = min(tW * 8 + lW, nW - 1);
+    const cpx<T>* src = in + int64_t(Lld) * nW + Wld;
+    // node index clamped to r - 1: the map's zero padding cancels it
+    auto gload = [&](int kb) -> cpx<T> { return src[int64_t(min(kb + lt, r - 1)) * plane]; };
+    const int Lo = tL * 16 + lc, Wo = tW * 8 + wave;
+    const bool valid = Lo < nL && Wo < nW;
+    const int64_t cout = int64_t(Wo) * nL + Lo;
+    v4 accr[MT], acci[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      accr[mt] = v4{T(0), T(0), T(0), T(0)};
+      acci[mt] = v4{T(0), T(0), T(0), T(0)};
+    }
+    cpx<T> g = dpp_identity(gload(0));
+    for (int kb = 0; kb < kp; kb += 4, buf ^= 1) {
+      cpx<T>* xb = xt + buf * XT;
+      xb[(lt * 16 + lL) * WP + lW] = g;
+      __syncthreads();  // the slice is in LDS; the buffer written next was read two slices ago
+      g = gload(kb + 4);
+      const cpx<T> x = xb[(lk * 16 + lc) * WP + wave];
+      const int kk = kb >> 2;
+      T ar[MT], ai[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        ar[mt] = tre[(kk * MT + mt) * 64 + lane];
+        ai[mt] = tim[(kk * MT + mt) * 64 + lane];
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        accr[mt] = M::mac(ar[mt], x.re, accr[mt]);
+        acci[mt] = M::mac(ar[mt], x.im, acci[mt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        accr[mt] = M::mac(-ai[mt], x.im, accr[mt]);
+        acci[mt] = M::mac(ai[mt], x.re, acci[mt]);
+      }
+    }
+    if (valid) {
+      const cpx<T> sc = mk(sre, sim);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = mt * 16 + M::row(lane, v);
+          if (m < r) out[int64_t(m) * plane + cout] = sc * mk(accr[mt][v], acci[mt][v]);
+        }
+    }
+  }
+}
+
+// pair arrays with a layout change (MODE = kSlabToMatrix or kMatrixToSlab)
+template <typename T, int MODE>
+hipError_t dlr_mfma_pairs_launch(const Plan& p, int map, int na, int nq, double sre, double sim, const void* in,
+                                 void* out, hipStream_t s) {
+  const int kp = (p.r + 3) / 4 * 4;
+  const int mt = (p.r + 15) / 16;
+  const int nL = MODE == kSlabToMatrix ? na : nq, nW = MODE == kSlabToMatrix ? nq : na;
+  const int tiles_l = (nL + 15) / 16;
+  const int64_t ntiles = int64_t(tiles_l) * ((nW + 7) / 8);
+  int dev = 0, ncu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int bpc = p.tune.mfma_bpc > 0 ? p.tune.mfma_bpc : 2;
+  int64_t blocks = ntiles;
+  if (blocks > int64_t(bpc) * ncu) blocks = int64_t(bpc) * ncu;
+  const size_t lds = size_t(2) * mt * 16 * kp * sizeof(T) + size_t(2) * 4 * 16 * 9 * sizeof(cpx<T>);
+  const cpx<T>* mp = map_ptr<T>(p, map);
+#define QGW_MFMA_MT(MTV)                                                                                       \
+  case MTV:                                                                                                    \
+    hipLaunchKernelGGL((k_dlr_mfma_pairs<T, MTV, MODE>), dim3(unsigned(blocks)), dim3(512), lds, s,            \
+                       (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, tiles_l, ntiles, T(sre), T(sim)); \
+    break;
+  switch (mt) {
+    QGW_MFMA_MT(1)
+    QGW_MFMA_MT(2)
+    QGW_MFMA_MT(3)
+    QGW_MFMA_MT(4)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef QGW_MFMA_MT
+  return hipGetLastError();
+}
+
 // na x nq columns; HERM_IN: orbital arrays (na = n_o^2, nq = N_k)
 template <typename T, int MODE, bool HERM_IN>
 hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, double sim, const void* in,
                            void* out, hipStream_t s) {
   const int kp = (p.r + 3) / 4 * 4;
   const int mt = (p.r + 15) / 16;
+  if constexpr (MODE != kPlain) return dlr_mfma_pairs_launch<T, MODE>(p, map, na, nq, sre, sim, in, out, s);
   int64_t nstrips;
   if (MODE == kSlabToMatrix)
     nstrips = int64_t((na + 15) / 16) * nq;
@@ -297,8 +450,8 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
   else
     nstrips = (int64_t(na) * nq + 15) / 16;
   int dev = 0, ncu = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   int64_t blocks = (nstrips + 7) / 8;
   const int bpc = p.tune.mfma_bpc > 0 ? p.tune.mfma_bpc : 2;
   if (blocks > int64_t(bpc) * ncu) blocks = int64_t(bpc) * ncu;
