@@ -3,9 +3,9 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring): not for the product path.
 
 The paper has no gradients; this module differentiates the forward steps of
-``gw`` as written (reading A15 of the design notes: a fixed number of
-iterations from G0, the chemical potential through the implicit function
-N_e(mu, H, Sigma) = N_target).
+``gw`` as written: a fixed number of iterations from G0, with the chemical
+potential differentiated through the implicit function
+N_e(mu, H, Sigma) = N_target.
 
 Convention for a real loss L of complex arrays: the cotangent of z is
     zbar = dL/dRe z + i dL/dIm z,

@@ -60,7 +60,7 @@ def kernel_tau(tau_t, omega, beta, reflect=False):
 
     ``tau_t`` are dimensionless nodes t in [0, 1]; with ``reflect`` the kernel
     is evaluated at beta - tau, i.e. at t' = 1 - t (the reflected point that
-    the bubble needs, reading A11 in the design notes).
+    the bubble needs; the tau nodes are not symmetric about beta / 2).
     """
     t = np.asarray(tau_t, dtype=np.float64)[:, None]
     x = beta * np.asarray(omega, dtype=np.float64)[None, :]

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring): not for the product path.
 
-Conventions (the readings are listed in the design notes):
+Conventions (where the paper leaves a choice open):
 
 * Arrays carry the DLR node axis first, then orbital or pair indices, then
   the two mesh axes: G[node, a, b, n1, n2], P[node, alpha, beta, n1, n2].
@@ -95,7 +95,8 @@ def electron_count(n_k):
 
 
 def mu_bracket(H_k, sig_hf_k, sig_iw, beta):
-    """A bracket [lo, hi] containing the chemical potential (reading A12)."""
+    """A bracket [lo, hi] containing the chemical potential: the spectrum of H0 + Sigma_HF padded by
+    10 / beta + max|Sigma^C| + 1."""
     h = np.moveaxis(H_k + sig_hf_k, (0, 1), (-2, -1))
     h = 0.5 * (h + np.conj(np.swapaxes(h, -1, -2)))
     ev = np.linalg.eigvalsh(h)
@@ -105,7 +106,7 @@ def mu_bracket(H_k, sig_hf_k, sig_iw, beta):
 
 
 def solve_mu(H_k, sig_hf_k, sig_iw, dlr, n_target, tol=1e-13, max_steps=200):
-    """Chemical potential by bisection on N_e(mu) = n_target (reading A12).
+    """Chemical potential by bisection on N_e(mu) = n_target, to |d mu| <= 1e-13 max(1, |mu|).
 
     N_e(mu) is evaluated through the same Dyson equation and the DLR density.
     Returns (mu, G_iw at mu, number of evaluations).
@@ -230,7 +231,7 @@ def sigma(G_tau_R, Wc_tau_R, pairs, n_o):
 # ----------------------------------------------------------------------------
 
 def total_energy(model, dlr, state):
-    """Galitskii-Migdal energy per cell (two spins), reading A16 of the design notes.
+    """Galitskii-Migdal energy per cell (two spins); the paper names no formula, this is the standard one.
 
     E = 2/N_k sum_k Re Tr[(H0(k) + Sigma_HF(k) / 2) n(k)]
         + 1/N_k sum_k Re (1/beta) sum_n Tr[Sigma^C(k, i w_n) G(k, i w_n)]
@@ -258,7 +259,7 @@ def total_energy(model, dlr, state):
 # ----------------------------------------------------------------------------
 
 def initial_state(model, dlr):
-    """G0 at the chemical potential that gives the target filling (A18)."""
+    """G0 at the chemical potential that gives the target filling (the iteration starts from G0, with no prior HF loop)."""
     zero = np.zeros_like(model.H_k)
     if model.n_target is None:
         raise ValueError("initial_state needs a target filling; use g0_fixed_mu")
@@ -339,7 +340,8 @@ def gw_iteration(model, dlr, state, mixing=1.0, keep=False):
 
 
 def scf(model, dlr, tol=1e-6, max_iter=100, mixing=1.0, state=None, callback=None):
-    """GW self-consistency from G0 until max|Delta Sigma| <= tol (reading A13)."""
+    """GW self-consistency from G0 until max|Delta Sigma| <= tol, where Delta Sigma is the change of
+    Sigma_HF + Sigma^C(k, i w_m) over k, node and orbital pair in one iteration."""
     if state is None:
         state = initial_state(model, dlr)
     history = []

@@ -73,7 +73,7 @@ def test_g0_closed_form(small):
 # ----------------------------------------------------------------------------
 
 def test_bubble_lindhard(small):
-    """For G = G0 (derivation in the design notes):
+    """For G = G0 (insert the eigen-decomposition of G0 into the bubble and sum over n):
     P_{(il),(jk)}(q, i nu) = -(2/N_k) sum_k sum_{n,m} U_ln(k) U*_jn(k) U_km(k-q) U*_im(k-q)
                               (f_n(k) - f_m(k-q)) / (i nu + xi_m(k-q) - xi_n(k)),
     with the degenerate limit beta f (1 - f)."""
