@@ -324,6 +324,27 @@ qgw_status qgw_energy_bwd(qgw_plan plan, const void *H_k, const void *SigHF_k,
                           const void *Sig_iw, const void *G_iw, double ebar, void *Hbar,
                           void *SigHFbar, void *Sigbar, void *Gbar, void *stream);
 
+/* Quasiparticle post-processing (Z class, SigStc class, Eq. eq-z-factor,
+ * Eq. eq-quasi-particle-Hamiltonian), FP64 plans.  The zero-frequency limit
+ * of the self-energy is taken at the Matsubara frequencies closest to zero,
+ * +-i pi/beta, where its DLR expansion follows it: with
+ * S(k) = Sigma^C(k, i pi/beta) (the DLR interpolant of Sig_iw) and
+ * Sigma(-i w) = Sigma(i w)^H,
+ *   Sig0 = Sigma(k, 0) = Herm(Sigma_HF(k) + S(k)),
+ *   Z^{-1}(k)  = 1 - (S - S^H) / (2 i pi/beta)   (dSigma/d(i w) at 0 as a
+ *                 central difference over +-pi/beta),
+ *   Hqp  = sqrt(Z) (Herm H0(k) + Sigma(k, 0) - mu) sqrt(Z), Hermitian part,
+ *   bands = eigenvalues of Hqp(k), ascending.
+ * mu = 0 is the equation as printed; the chemical potential puts the bands
+ * relative to the Fermi level.  H_k, SigHF_k: [n_o][n_o][N_k]; Sig_iw:
+ * [r][n_o][n_o][N_k] (orbital layout); outputs Sig0, Z, Hqp: [n_o][n_o][N_k]
+ * complex; bands: [n_o][N_k] double.  Waits for ``stream``.  Workspace.
+ * QGW_ERR_NONFINITE if Z^{-1}(k) is not positive definite at some k (the
+ * outputs there are not meaningful). */
+qgw_status qgw_quasiparticle(qgw_plan plan, const void *H_k, const void *SigHF_k,
+                             const void *Sig_iw, double mu, void *Sig0, void *Z, void *Hqp,
+                             double *bands, void *stream);
+
 /* out = a + b over ``count`` complex FP64 entries (the static H0(k) +
  * Sigma_HF(k) of the Dyson equation for G); out may alias a or b. */
 qgw_status qgw_add(qgw_plan plan, int64_t count, const void *a, const void *b,

@@ -103,7 +103,7 @@ static void free_plan_device(Plan& p) {
     p.dmaps64.m[m] = p.dmaps32.m[m] = nullptr;
   }
   void* ptrs[] = {p.d_tw64, p.d_tw32, p.d_pairs, p.terms.d_terms, p.terms.d_off, p.terms_lj.d_terms,
-                  p.terms_lj.d_off, p.d_wn, p.d_partials, p.d_status, p.d_scalars, p.d_ws};
+                  p.terms_lj.d_off, p.d_wn, p.d_qp_row, p.d_partials, p.d_status, p.d_scalars, p.d_ws};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   p.d_tw64 = nullptr;
@@ -114,6 +114,7 @@ static void free_plan_device(Plan& p) {
   p.d_ws = nullptr;
   p.ws_bytes = 0;
   p.d_wn = nullptr;
+  p.d_qp_row = nullptr;
   p.d_partials = nullptr;
   p.d_status = nullptr;
   p.d_scalars = nullptr;
@@ -347,6 +348,19 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
     e = upload((void**)&p.d_wn, wn.data(), wn.size() * sizeof(double));
   }
   if (e == hipSuccess) {
+    std::vector<std::complex<double>> row;
+    std::string rerr;
+    if (!dlr_qp_row_host(p.beta, p.omega, p.n_f, row, rerr)) {
+      free_plan_device(p);
+      delete h;
+      set_error("qgw_plan_create: " + rerr);
+      return QGW_ERR_INVALID_ARG;
+    }
+    std::vector<zd> hr(p.r);
+    for (int m = 0; m < p.r; ++m) hr[m] = mk(row[m].real(), row[m].imag());
+    e = upload((void**)&p.d_qp_row, hr.data(), hr.size() * sizeof(zd));
+  }
+  if (e == hipSuccess) {
     p.max_blocks = 8192;
     e = hipMalloc((void**)&p.d_partials, size_t(2) * 4 * p.max_blocks * sizeof(double));
   }
@@ -471,9 +485,12 @@ qgw_status qgw_hartree_fock(qgw_plan h, const void* V_R, const void* n_R, void* 
   return QGW_OK;
 }
 
+// extra_src / extra_dst: one more device scalar read back with the search's
+// result (the iteration's |dSigma|), end_ev: recorded after the last kernel
 static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw, double n_target,
                               double* mu, void* G_iw, hipStream_t s, double* evals, double* scal = nullptr,
-                              double* part = nullptr, int* stat = nullptr) {
+                              double* part = nullptr, int* stat = nullptr, const double* extra_src = nullptr,
+                              double* extra_dst = nullptr, hipEvent_t end_ev = nullptr) {
   const int mode = std::isnan(n_target) ? 0 : 1;
   if (!scal) {
     scal = p.d_scalars;
@@ -482,18 +499,25 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
   }
   double sc[2] = {*mu, n_target};
   QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, sizeof(sc), hipMemcpyHostToDevice, s), "qgw_dyson_G");
-  QGW_CHECK_HIP(hipMemsetAsync(stat, 0, sizeof(int), s), "qgw_dyson_G");
-  if (mode == 1) QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, s), "qgw_dyson_G");
-  double res[8] = {};
+  // the search's first launch resets the status word; a fixed-mu call has no search
+  if (mode == 1)
+    QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, s), "qgw_dyson_G");
+  else
+    QGW_CHECK_HIP(hipMemsetAsync(stat, 0, sizeof(int), s), "qgw_dyson_G");
+  // scal[0..9]: mu, n_target, evaluations, N_e, search state, status, extra
+  double res[10] = {};
   int st = 0;
   for (int round = 0;; ++round) {
     // a few Newton evaluations, G at the current mu, one read-back; more rounds only if needed
     if (mode == 1)
       QGW_CHECK_HIP(launch_dyson_g_steps(p, H_k, Sig_iw, scal, part, stat, round == 0 ? 6 : 16, s), "qgw_dyson_G");
-    QGW_CHECK_HIP(launch_dyson_g_final(p, H_k, Sig_iw, mode, G_iw, scal, part, stat, s), "qgw_dyson_G");
+    QGW_CHECK_HIP(launch_dyson_g_final(p, H_k, Sig_iw, mode, G_iw, scal, part, stat, s, extra_src),
+                  "qgw_dyson_G");
+    if (end_ev) QGW_CHECK_HIP(hipEventRecord(end_ev, s), "qgw_dyson_G");
     QGW_CHECK_HIP(hipMemcpyAsync(res, scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
-    QGW_CHECK_HIP(hipMemcpyAsync(&st, stat, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
     QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_dyson_G");
+    st = int(res[8]);
+    if (extra_src && round == 0) *extra_dst = res[9];
     if (mode == 0 || st != 2 || res[2] >= 200.0) break;
     QGW_CHECK_HIP(hipMemsetAsync(stat, 0, sizeof(int), s), "qgw_dyson_G");
   }
@@ -722,6 +746,28 @@ qgw_status qgw_energy_bwd(qgw_plan h, const void* H_k, const void* SigHF_k, cons
   QGW_CHECK_HIP(launch_row_map_bwd(p, ncol, -1.0, 0.0, 2, nbar, Gbar, s), "qgw_energy_bwd");
   QGW_CHECK_HIP(launch_energy_bwd_nodes(p, y, G_iw, ebar / double(p.nk), Gbar, ybar, s), "qgw_energy_bwd");
   QGW_CHECK_HIP(launch_dlr(p, kAdjMap0 + QGW_F_IW2GM, ncol, 1.0, 0.0, ybar, Sigbar, s), "qgw_energy_bwd");
+  return QGW_OK;
+}
+
+// ---------------------------------------------------------- quasiparticle
+
+qgw_status qgw_quasiparticle(qgw_plan h, const void* H_k, const void* SigHF_k, const void* Sig_iw, double mu,
+                             void* Sig0, void* Z, void* Hqp, double* bands, void* stream) {
+  QGW_PLAN(h, "qgw_quasiparticle");
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_quasiparticle: FP64 plans only");
+  QGW_REQUIRE(H_k && SigHF_k && Sig_iw && Sig0 && Z && Hqp && bands, QGW_ERR_INVALID_ARG,
+              "qgw_quasiparticle: null argument");
+  QGW_REQUIRE(std::isfinite(mu), QGW_ERR_INVALID_ARG, "qgw_quasiparticle: mu must be finite");
+  QGW_CHECK_HIP(ensure_ws(h->p, 64), "qgw_quasiparticle: workspace");
+  int* flag = (int*)p.d_ws;
+  hipStream_t s = (hipStream_t)stream;
+  QGW_CHECK_HIP(hipMemsetAsync(flag, 0, sizeof(int), s), "qgw_quasiparticle");
+  QGW_CHECK_HIP(launch_quasiparticle(p, H_k, SigHF_k, Sig_iw, mu, Sig0, Z, Hqp, bands, flag, s),
+                "qgw_quasiparticle");
+  int bad = 0;
+  QGW_CHECK_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_quasiparticle");
+  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_quasiparticle");
+  QGW_REQUIRE(bad == 0, QGW_ERR_NONFINITE, "qgw_quasiparticle: Z(k)^{-1} is not positive definite at some k");
   return QGW_OK;
 }
 
@@ -999,14 +1045,13 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     const bool f32 = st->prec_mode == 2 || (st->prec_mode == 1 && st->in_fp32);
     QGW_CHECK_HIP(enqueue_steps(st, f32, st->prof, s), "qgw_gw_iteration");
     // a13: Dyson G with the chemical potential
+    // |dSigma| (a14, already enqueued) comes back with the search's result: one wait per iteration
     double m = st->mu;
     qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, nullptr, st->d_scal,
-                                st->d_part, st->d_stat);
+                                st->d_part, st->d_stat, st->d_dsig, &dsig,
+                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr);
     if (rc != QGW_OK) return rc;
     st->mu = m;
-    if (st->prof) QGW_CHECK_HIP(hipEventRecord(st->ev[QGW_NUM_STEPS], s), "profile");
-    QGW_CHECK_HIP(hipMemcpyAsync(&dsig, st->d_dsig, sizeof(double), hipMemcpyDeviceToHost, s), "a14");
-    QGW_CHECK_HIP(hipStreamSynchronize(s), "a14");
     if (st->prof) {
       for (int i = 0; i < QGW_NUM_STEPS; ++i) {
         float ms = 0.0f;

@@ -285,4 +285,27 @@ bool dlr_maps_host(double beta, const std::vector<double>& omega, const std::vec
   return ok;
 }
 
+// The DLR interpolant of fermionic node values evaluated at the first
+// Matsubara frequency i pi / beta: x(i pi / beta) = sum_m row[m] x(i w_m),
+// row = K_F(i pi / beta, w_l) K_F^{-1} (the quasiparticle zero-frequency
+// limit is taken at +-i pi / beta, where the expansion follows the function).
+bool dlr_qp_row_host(double beta, const std::vector<double>& omega, const std::vector<int64_t>& n_f,
+                     std::vector<std::complex<double>>& row, std::string& err) {
+  const int r = int(omega.size());
+  std::vector<cd> kfm(size_t(r) * r), k0(r);
+  const double w0 = kPi / beta;
+  for (int l = 0; l < r; ++l) {
+    for (int m = 0; m < r; ++m) {
+      const double wn = (2.0 * double(n_f[m]) + 1.0) * kPi / beta;
+      kfm[size_t(m) * r + l] = 1.0 / cd(-omega[l], wn);
+    }
+    k0[l] = 1.0 / cd(-omega[l], w0);
+  }
+  if (!right_divide(r, 1, kfm, k0, row)) {
+    err = "DLR interpolation matrix is singular for the given nodes";
+    return false;
+  }
+  return true;
+}
+
 }  // namespace qgw

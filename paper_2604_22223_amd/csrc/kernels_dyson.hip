@@ -466,9 +466,11 @@ struct DysonGArgs {
   const double* wn;   // [r]
   const zd* rho;      // [r]: G(beta^-) = sum_m rho_m G(i w_m)
   zd* g;              // [r][no][no][nk]
-  double* scal;       // [0] mu (in: start / fixed; out), [1] n_target, [2] evaluations, [3] final N_e
+  double* scal;       // [0] mu (in: start / fixed; out), [1] n_target, [2] evaluations, [3] final N_e,
+                      // [8] status (copy), [9] the value at ``extra`` (copy), so one read returns all
   double* partials;   // [2][4][max blocks]
   int* status;        // 0 ok, 2 not converged
+  const double* extra;  // optional scalar copied to scal[9] by the final pass
   int r, nk, mode, max_evals;
   double beta, tol_mu, tol_n;
 };
@@ -661,9 +663,13 @@ __global__ __launch_bounds__(64) void k_dg_final(DysonGArgs A) {
 #pragma unroll
       for (int j = 0; j < NO; ++j) A.g[((int64_t(m) * NO + i) * NO + j) * A.nk + k] = a[i][j];
   }
-  if (A.mode == 1 && blockIdx.x == 0 && threadIdx.x == 0 && A.status[0] == 0) {
-    const bool conv = A.scal[7] != 0.0 || fabs(A.scal[3] - A.scal[1]) <= A.tol_n;
-    if (!conv || !isfinite(mu)) A.status[0] = 2;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (A.mode == 1 && A.status[0] == 0) {
+      const bool conv = A.scal[7] != 0.0 || fabs(A.scal[3] - A.scal[1]) <= A.tol_n;
+      if (!conv || !isfinite(mu)) A.status[0] = 2;
+    }
+    A.scal[8] = double(A.status[0]);
+    if (A.extra) A.scal[9] = *A.extra;
   }
 }
 
@@ -943,6 +949,7 @@ DysonGArgs dyson_g_args(const Plan& p, const void* h_k, const void* sig_iw, int 
   A.beta = p.beta;
   A.tol_mu = 1e-13;
   A.tol_n = 1e-13;
+  A.extra = nullptr;
   return A;
 }
 
@@ -976,8 +983,9 @@ hipError_t dyson_g_steps_no(const Plan& p, const void* h_k, const void* sig_iw, 
 
 template <int NO>
 hipError_t dyson_g_final_no(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                            double* scal, double* partials, int* status, hipStream_t s) {
+                            double* scal, double* partials, int* status, const double* extra, hipStream_t s) {
   DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, mode, g_iw, scal, partials, status);
+  A.extra = extra;
   hipLaunchKernelGGL((k_dg_final<NO>), dim3(dyson_g_blocks(p)), dim3(64), 0, s, A);
   return hipGetLastError();
 }
@@ -1084,8 +1092,8 @@ hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_
 }
 
 hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                                double* scal, double* partials, int* status, hipStream_t s) {
-  QGW_NO_SWITCH((dyson_g_final_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s)))
+                                double* scal, double* partials, int* status, hipStream_t s, const double* extra) {
+  QGW_NO_SWITCH((dyson_g_final_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, extra, s)))
 }
 
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,

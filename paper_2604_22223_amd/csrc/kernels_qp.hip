@@ -1,0 +1,258 @@
+// Quasiparticle post-processing of a GW self-energy (Z class, SigStc class,
+// Eq. eq-z-factor, Eq. eq-quasi-particle-Hamiltonian), FP64.
+//
+// The zero-frequency limit is taken at the Matsubara frequencies closest to
+// zero, +-i pi/beta, where the DLR expansion of Sigma(k, i w) follows the
+// function; with S = Sigma^C(k, i pi/beta) (one row of the DLR interpolant
+// applied to the node values) and Sigma(-i w) = Sigma(i w)^H:
+//   Sigma(k, 0)  = Sigma_HF(k) + (S + S^H) / 2
+//   Z(k)^{-1}    = 1 - (S - S^H) / (2 i pi/beta)     (central difference)
+//   H_QP(k)      = sqrt(Z) (H0 + Sigma(k, 0) - mu) sqrt(Z)
+// and the bands are the eigenvalues of H_QP(k), ascending.
+//
+// One thread per k: the n_o x n_o Hermitian matrices stay in registers and
+// are diagonalised by cyclic complex Jacobi rotations (each rotation first
+// turns a_pq real with a phase on column q, then zeroes it with a real plane
+// rotation), to an off-diagonal norm below 1e-30 of the total.
+#include "qgw_internal.h"
+
+namespace qgw {
+
+namespace {
+
+template <int NO>
+struct HermEig {
+  cpx<double> a[NO][NO];  // in: Hermitian matrix; out: diagonal holds the eigenvalues
+  cpx<double> v[NO][NO];  // eigenvectors (columns)
+};
+
+template <int NO>
+__device__ __forceinline__ double offdiag2(const cpx<double> (&a)[NO][NO], double& total) {
+  double off = 0.0, all = 0.0;
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const double v = norm2(a[i][j]);
+      all += v;
+      if (i != j) off += v;
+    }
+  total = all;
+  return off;
+}
+
+template <int NO, int P, int Q>
+__device__ __forceinline__ void jacobi_rotate(HermEig<NO>& h) {
+  const cpx<double> apq = h.a[P][Q];
+  const double g = sqrt(norm2(apq));
+  if (g == 0.0) return;
+  const cpx<double> e = mk(apq.re / g, apq.im / g);  // a_pq = g e
+  const double app = h.a[P][P].re, aqq = h.a[Q][Q].re;
+  const double tau = (aqq - app) / (2.0 * g);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+  // W on the (P, Q) plane: W_PP = c, W_PQ = s, W_QP = -s conj(e), W_QQ = c conj(e)
+  const cpx<double> ce = conj(e);
+  // columns: A <- A W, V <- V W
+#pragma unroll
+  for (int i = 0; i < NO; ++i) {
+    const cpx<double> ap = h.a[i][P], aq = h.a[i][Q];
+    h.a[i][P] = scale(ap, c) - scale(aq * ce, s);
+    h.a[i][Q] = scale(ap, s) + scale(aq * ce, c);
+    const cpx<double> vp = h.v[i][P], vq = h.v[i][Q];
+    h.v[i][P] = scale(vp, c) - scale(vq * ce, s);
+    h.v[i][Q] = scale(vp, s) + scale(vq * ce, c);
+  }
+  // rows: A <- W^H A (W^H_PP = c, W^H_PQ = -s e, W^H_QP = s, W^H_QQ = c e)
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    const cpx<double> ap = h.a[P][j], aq = h.a[Q][j];
+    h.a[P][j] = scale(ap, c) - scale(e * aq, s);
+    h.a[Q][j] = scale(ap, s) + scale(e * aq, c);
+  }
+  h.a[P][Q] = mk(0.0, 0.0);
+  h.a[Q][P] = mk(0.0, 0.0);
+  h.a[P][P].im = 0.0;
+  h.a[Q][Q].im = 0.0;
+}
+
+template <int NO, int P, int Q>
+__device__ __forceinline__ void jacobi_row(HermEig<NO>& h) {
+  if constexpr (Q < NO) {
+    jacobi_rotate<NO, P, Q>(h);
+    jacobi_row<NO, P, Q + 1>(h);
+  }
+}
+
+template <int NO, int P>
+__device__ __forceinline__ void jacobi_sweep(HermEig<NO>& h) {
+  if constexpr (P < NO - 1) {
+    jacobi_row<NO, P, P + 1>(h);
+    jacobi_sweep<NO, P + 1>(h);
+  }
+}
+
+template <int NO>
+__device__ __forceinline__ void herm_eig(HermEig<NO>& h) {
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) h.v[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double total = 0.0;
+    const double off = offdiag2<NO>(h.a, total);
+    if (!(off > 1e-30 * total)) break;
+    jacobi_sweep<NO, 0>(h);
+  }
+}
+
+// out = V diag(f) V^H, Hermitian by construction
+template <int NO>
+__device__ __forceinline__ void spectral(const cpx<double> (&v)[NO][NO], const double (&f)[NO],
+                                         cpx<double> (&out)[NO][NO]) {
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      cpx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int n = 0; n < NO; ++n) acc = acc + scale(v[i][n] * conj(v[j][n]), f[n]);
+      out[i][j] = acc;
+    }
+}
+
+template <int NO>
+__global__ __launch_bounds__(64) void k_quasiparticle(const zd* __restrict__ hk, const zd* __restrict__ shf,
+                                                      const zd* __restrict__ sig, const zd* __restrict__ row, int r,
+                                                      int nk, double w0, double mu, zd* __restrict__ sig0,
+                                                      zd* __restrict__ zout, zd* __restrict__ hqp,
+                                                      double* __restrict__ bands, int* __restrict__ status) {
+  const int k = blockIdx.x * 64 + threadIdx.x;
+  if (k >= nk) return;
+  auto at = [&](int i, int j) { return int64_t(i * NO + j) * nk + k; };
+  // S = sum_m row[m] Sigma^C(i w_m)
+  cpx<double> s[NO][NO];
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) s[i][j] = mk(0.0, 0.0);
+  for (int m = 0; m < r; ++m) {
+    const cpx<double> w = row[m];
+    const zd* sm = sig + int64_t(m) * NO * NO * nk;
+#pragma unroll
+    for (int i = 0; i < NO; ++i)
+#pragma unroll
+      for (int j = 0; j < NO; ++j) s[i][j] = fma(s[i][j], w, sm[at(i, j)]);
+  }
+  // Z^{-1} = 1 - (S - S^H) / (2 i w0); Sigma(k, 0) = Herm(Sigma_HF + S) goes to t
+  HermEig<NO> h;
+  cpx<double> t[NO][NO], sq[NO][NO];
+  const double inv2w = 0.5 / w0;
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const cpx<double> d = s[i][j] - conj(s[j][i]);  // (S - S^H)_ij; d / (2 i w0) = -i d / (2 w0)
+      h.a[i][j] = mk((i == j ? 1.0 : 0.0) - d.im * inv2w, d.re * inv2w);
+      const cpx<double> hs = shf[at(i, j)], hst = shf[at(j, i)];
+      t[i][j] = scale((hs + conj(hst)) + (s[i][j] + conj(s[j][i])), 0.5);
+    }
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) sig0[at(i, j)] = t[i][j];
+  herm_eig<NO>(h);
+  double fz[NO], fs[NO];
+  bool pos = true;
+#pragma unroll
+  for (int n = 0; n < NO; ++n) {
+    const double lam = h.a[n][n].re;
+    pos = pos && lam > 0.0;
+    fz[n] = 1.0 / lam;
+    fs[n] = 1.0 / sqrt(lam);
+  }
+  if (!pos) status[0] = 1;
+  spectral<NO>(h.v, fz, s);  // Z
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) zout[at(i, j)] = s[i][j];
+  spectral<NO>(h.v, fs, sq);  // sqrt(Z)
+  // A = Herm(H0) + Sigma(k, 0) - mu, in s
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const cpx<double> a0 = hk[at(i, j)], a1 = hk[at(j, i)];
+      s[i][j] = scale(a0 + conj(a1), 0.5) + t[i][j];
+      if (i == j) s[i][j].re -= mu;
+    }
+  // H_QP = sqrt(Z) A sqrt(Z): t = A sqrt(Z), s = sqrt(Z) t
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      cpx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int n = 0; n < NO; ++n) acc = fma(acc, s[i][n], sq[n][j]);
+      t[i][j] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      cpx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int n = 0; n < NO; ++n) acc = fma(acc, sq[i][n], t[n][j]);
+      s[i][j] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      h.a[i][j] = scale(s[i][j] + conj(s[j][i]), 0.5);
+      hqp[at(i, j)] = h.a[i][j];
+    }
+  herm_eig<NO>(h);
+  double ev[NO];
+#pragma unroll
+  for (int n = 0; n < NO; ++n) ev[n] = h.a[n][n].re;
+  // ascending order (exchange sort on registers)
+#pragma unroll
+  for (int i = 0; i < NO; ++i)
+#pragma unroll
+    for (int j = i + 1; j < NO; ++j) {
+      const double lo = fmin(ev[i], ev[j]), hi = fmax(ev[i], ev[j]);
+      ev[i] = lo;
+      ev[j] = hi;
+    }
+#pragma unroll
+  for (int n = 0; n < NO; ++n) bands[int64_t(n) * nk + k] = ev[n];
+}
+
+template <int NO>
+hipError_t quasiparticle_no(const Plan& p, const void* h_k, const void* shf_k, const void* sig_iw, double mu,
+                            void* sig0, void* z, void* hqp, double* bands, int* status, hipStream_t s) {
+  const double w0 = 3.14159265358979323846 / p.beta;
+  hipLaunchKernelGGL((k_quasiparticle<NO>), dim3(unsigned((p.nk + 63) / 64)), dim3(64), 0, s, (const zd*)h_k,
+                     (const zd*)shf_k, (const zd*)sig_iw, p.d_qp_row, p.r, p.nk, w0, mu, (zd*)sig0, (zd*)z,
+                     (zd*)hqp, bands, status);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_quasiparticle(const Plan& p, const void* h_k, const void* shf_k, const void* sig_iw, double mu,
+                                void* sig0, void* z, void* hqp, double* bands, int* status, hipStream_t s) {
+  switch (p.no) {
+#define QGW_CASE(NOV) \
+  case NOV:           \
+    return quasiparticle_no<NOV>(p, h_k, shf_k, sig_iw, mu, sig0, z, hqp, bands, status, s);
+    QGW_FOR_EACH_NO(QGW_CASE)
+#undef QGW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace qgw

@@ -67,6 +67,7 @@ struct Plan {
   TermTable terms;     // keyed by (i, k): entries (alpha, beta, l, j)
   TermTable terms_lj;  // keyed by (l, j): entries (alpha, beta, i, k)
   double* d_wn = nullptr;  // fermionic Matsubara frequencies (r)
+  zd* d_qp_row = nullptr;  // node values -> value at i pi / beta (r)
   // Dyson-G scratch: partial sums (2 x max blocks x 4), status word
   double* d_partials = nullptr;
   int* d_status = nullptr;
@@ -79,6 +80,10 @@ struct Plan {
 };
 
 void set_error(const std::string& msg);
+
+// quasiparticle outputs per k (FP64); status[0] is set to 1 where Z^{-1} is not positive definite
+hipError_t launch_quasiparticle(const Plan& p, const void* h_k, const void* shf_k, const void* sig_iw, double mu,
+                                void* sig0, void* z, void* hqp, double* bands, int* status, hipStream_t s);
 
 // ---- kernels (each returns hipSuccess or the launch error) ----------------
 hipError_t launch_lattice_fft(const Plan& p, int dir, int64_t batch, const void* in, void* out,
@@ -108,8 +113,10 @@ hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, do
                                 hipStream_t s);
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
                                 int* status, int steps, hipStream_t s);
+// also copies the status to scal[8] and, if extra is given, *extra to scal[9]
 hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                                double* scal, double* partials, int* status, hipStream_t s);
+                                double* scal, double* partials, int* status, hipStream_t s,
+                                const double* extra = nullptr);
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, int steps, hipStream_t s);
 hipError_t launch_slab_to_matrix_static(const Plan& p, const void* in, void* out, hipStream_t s);
@@ -166,6 +173,8 @@ hipError_t launch_pair_layout(const Plan& p, int to_matrix, int64_t nn, const vo
 int dlr_build_host(double lambda, double eps, int max_rank, std::vector<double>& x,
                    std::vector<double>& tau_t, std::vector<int64_t>& n_f,
                    std::vector<int64_t>& n_b, std::string& err);
+bool dlr_qp_row_host(double beta, const std::vector<double>& omega, const std::vector<int64_t>& n_f,
+                     std::vector<std::complex<double>>& row, std::string& err);
 bool dlr_maps_host(double beta, const std::vector<double>& omega, const std::vector<double>& tau_t,
                    const std::vector<int64_t>& n_f, const std::vector<int64_t>& n_b,
                    std::vector<std::complex<double>> maps[kNumMaps], std::string& err);

@@ -32,7 +32,7 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_state_set_precision", "qgw_state_info", "qgw_check_finite",
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
-           "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
+           "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_quasiparticle", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
            "qgw_last_error"]
 
 
@@ -103,6 +103,7 @@ def lib():
             "qgw_plan_autotune": [vp, pi32, vp],
             "qgw_energy": [vp, vp, vp, vp, vp, pd, vp],
             "qgw_energy_bwd": [vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp],
+            "qgw_quasiparticle": [vp, vp, vp, vp, dbl, vp, vp, vp, pd, vp],
             "qgw_batch_create": [i32, ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(vp)],
             "qgw_batch_launch": [vp, vp],
             "qgw_batch_read": [vp, pd, pd, pi32, vp],
@@ -304,6 +305,21 @@ class Plan:
         _check(lib().qgw_energy_bwd(self.handle, _ptr(h_k), _ptr(shf_k), _ptr(sig_iw), _ptr(g_iw), float(ebar),
                                     _ptr(hbar), _ptr(shfbar), _ptr(sigbar), _ptr(gbar), _stream()))
         return hbar, shfbar, sigbar, gbar
+
+    def quasiparticle(self, h_k, shf_k, sig_iw, mu=0.0):
+        """Static self-energy, Z(k), the quasiparticle Hamiltonian and its bands (qgw_quasiparticle).
+
+        Returns (sig0, z, hqp, bands): three [n_o, n_o, N_k] complex tensors and [n_o, N_k] real bands."""
+        import torch
+        shape = tuple(h_k.shape)
+        sig0 = torch.empty(shape, dtype=torch.complex128, device=h_k.device)
+        z = torch.empty_like(sig0)
+        hqp = torch.empty_like(sig0)
+        bands = torch.empty((shape[0], shape[-1]), dtype=torch.float64, device=h_k.device)
+        _check(lib().qgw_quasiparticle(self.handle, _ptr(h_k), _ptr(shf_k), _ptr(sig_iw), float(mu), _ptr(sig0),
+                                       _ptr(z), _ptr(hqp), ctypes.cast(_ptr(bands), ctypes.POINTER(ctypes.c_double)),
+                                       _stream()))
+        return sig0, z, hqp, bands
 
     def add(self, a, b, out):
         _check(lib().qgw_add(self.handle, int(a.numel()), _ptr(a), _ptr(b), _ptr(out), _stream()))
