@@ -16,6 +16,8 @@ lattice  k <-> R transforms (Eq. eq:fourier-transform-kr) in the cell-periodic
          gauge.
 gw       G0, bubble P, screened W, GW self-energy, Hartree/Fock, Dyson G with
          the chemical-potential bisection, the SCF loop (Fig. fig-self (b)).
+hf       Hartree-Fock self-consistency (Fig. fig-self (a)): Fermi-function
+         density of the static Hamiltonian, chemical potential, the loop.
 quasiparticle  static self-energy, renormalisation Z(k) (Eq. eq-z-factor) and
          the quasiparticle Hamiltonian and bands
          (Eq. eq-quasi-particle-Hamiltonian).
