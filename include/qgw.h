@@ -324,6 +324,15 @@ qgw_status qgw_energy_bwd(qgw_plan plan, const void *H_k, const void *SigHF_k,
                           const void *Sig_iw, const void *G_iw, double ebar, void *Hbar,
                           void *SigHFbar, void *Sigbar, void *Gbar, void *stream);
 
+/* Hartree-Fock density of a static Hamiltonian (Fig. fig-self (a), H class
+ * paragraph), FP64 plans: for H_k [n_o][n_o][N_k] (its Hermitian part is
+ * used) writes n_k = U f(beta (eps - mu)) U^H, f(x) = 1 / (e^x + 1), with
+ * H(k) = U diag(eps) U^H per k.  mu (in/out) is found by bisection to the
+ * target filling N_e = (2 / N_k) sum_{k,n} f(beta (eps_n(k) - mu)), or is
+ * used as given if n_target is NaN.  Waits for ``stream``.  Workspace. */
+qgw_status qgw_hf_density(qgw_plan plan, const void *H_k, double n_target, double *mu,
+                          void *n_k, void *stream);
+
 /* Quasiparticle post-processing (Z class, SigStc class, Eq. eq-z-factor,
  * Eq. eq-quasi-particle-Hamiltonian), FP64 plans.  The zero-frequency limit
  * of the self-energy is taken at the Matsubara frequencies closest to zero,
@@ -373,10 +382,28 @@ qgw_status qgw_gw_iteration(qgw_state state, int32_t n_iter, double tol,
                             int32_t *iters_done, double *d_sigma, double *mu,
                             void *stream);
 
+/* Hartree-Fock self-consistency of a state (Fig. fig-self (a); H class
+ * paragraph): from Sigma_HF = 0 and the density of H0, each pass computes
+ * Sigma_H + Sigma_F from n (Eqs. eq-hartree-self-energy,
+ * eq-fock-self-energy), mixes it with the state's mixing weight, and sets
+ * n(k) = 1 / (e^{beta (H(k) - mu)} + 1) for H = H0 + Sigma_HF, with mu at
+ * the target filling (or the state's mu if n_target is NaN).  Stops after
+ * max_iter passes or once max |Delta Sigma_HF| <= tol (a negative tol runs
+ * exactly max_iter passes).  Leaves Sigma_HF, n,
+ * mu in the state and G = [(i w + mu) - H0 - Sigma_HF]^{-1} with
+ * Sigma^C = 0, so a GW solve can continue from the HF solution.  Outputs
+ * (any may be NULL): passes done, the last max |Delta Sigma_HF|, mu.
+ * Waits for ``stream``.  Uses the plan workspace. */
+qgw_status qgw_state_hf_solve(qgw_state state, double tol, int32_t max_iter,
+                              int32_t *iters_done, double *d_sigma, double *mu,
+                              void *stream);
+
 /* Copies a state array (FP64) into the caller's device buffer ``dst`` on
  * ``stream``: which = 0 G(k, i w) [orbital], 1 Sigma^C(k, i w) [orbital],
  * 2 Sigma_HF(k) [static orbital], 3 P(q, i nu) [pair matrix],
- * 4 W^C(q, i nu) [pair matrix].  *bytes (if not NULL) receives the size. */
+ * 4 W^C(q, i nu) [pair matrix], 5 n(k) [static orbital; the density of the
+ * last Hartree-Fock pass or of the last GW iteration's a12].  *bytes (if not
+ * NULL) receives the size. */
 qgw_status qgw_state_copy(qgw_state state, int32_t which, void *dst, int64_t *bytes,
                           void *stream);
 

@@ -749,6 +749,98 @@ qgw_status qgw_energy_bwd(qgw_plan h, const void* H_k, const void* SigHF_k, cons
   return QGW_OK;
 }
 
+// ----------------------------------------------------------- Hartree-Fock
+
+qgw_status qgw_hf_density(qgw_plan h, const void* H_k, double n_target, double* mu, void* n_k, void* stream) {
+  QGW_PLAN(h, "qgw_hf_density");
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_hf_density: FP64 plans only");
+  QGW_REQUIRE(H_k && mu && n_k, QGW_ERR_INVALID_ARG, "qgw_hf_density: null argument");
+  if (!std::isnan(n_target))
+    QGW_REQUIRE(n_target > 0.0 && n_target < 2.0 * p.no, QGW_ERR_INVALID_ARG,
+                "qgw_hf_density: target filling must lie in (0, 2 n_o)");
+  else
+    QGW_REQUIRE(std::isfinite(*mu), QGW_ERR_INVALID_ARG, "qgw_hf_density: fixed mu must be finite");
+  const size_t so = size_t(p.no) * p.no * p.nk * sizeof(zd);
+  const size_t se = size_t(p.no) * p.nk * sizeof(double);
+  QGW_CHECK_HIP(ensure_ws(h->p, so + se + 64 * sizeof(double)), "qgw_hf_density: workspace");
+  char* ws = (char*)p.d_ws;
+  double* scal = (double*)(ws + so + se);
+  int* stat = (int*)(scal + 16);
+  hipStream_t s = (hipStream_t)stream;
+  double sc[2] = {*mu, n_target};
+  QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, sizeof(sc), hipMemcpyHostToDevice, s), "qgw_hf_density");
+  QGW_CHECK_HIP(launch_hf_density(p, H_k, scal, stat, ws, (double*)(ws + so), n_k, s), "qgw_hf_density");
+  double res[4];
+  int bad = 0;
+  QGW_CHECK_HIP(hipMemcpyAsync(res, scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_hf_density");
+  QGW_CHECK_HIP(hipMemcpyAsync(&bad, stat, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_hf_density");
+  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_hf_density");
+  QGW_REQUIRE(bad == 0, QGW_ERR_NONFINITE, "qgw_hf_density: non-finite chemical potential or filling");
+  *mu = res[0];
+  return QGW_OK;
+}
+
+qgw_status qgw_state_hf_solve(qgw_state st, double tol, int32_t max_iter, int32_t* iters_done, double* d_sigma,
+                              double* mu_out, void* stream) {
+  QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_hf_solve: null state");
+  QGW_REQUIRE(max_iter >= 0, QGW_ERR_INVALID_ARG, "qgw_state_hf_solve: negative max_iter");
+  qgw_plan h = st->plan;
+  const Plan& p = h->p;
+  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
+  if (std::isnan(st->n_target))
+    QGW_REQUIRE(std::isfinite(st->mu), QGW_ERR_INVALID_ARG, "qgw_state_hf_solve: fixed mu must be finite");
+  const int64_t so_n = int64_t(p.no) * p.no * p.nk;
+  const size_t so = size_t(so_n) * sizeof(zd);
+  const size_t se = size_t(p.no) * p.nk * sizeof(double);
+  QGW_CHECK_HIP(ensure_ws(h->p, so + se), "qgw_state_hf_solve: workspace");
+  void* u = p.d_ws;
+  double* eps = (double*)((char*)p.d_ws + so);
+  hipStream_t s = (hipStream_t)stream;
+  // start: Sigma_HF = 0 and the density of H0 at the target filling (or at the state's mu)
+  QGW_CHECK_HIP(hipMemsetAsync(st->SigHF_k, 0, so, s), "qgw_state_hf_solve");
+  QGW_CHECK_HIP(hipMemsetAsync(st->SigHF_old, 0, so, s), "qgw_state_hf_solve");
+  double sc[2] = {st->mu, st->n_target};
+  QGW_CHECK_HIP(hipMemcpyAsync(st->d_scal, sc, sizeof(sc), hipMemcpyHostToDevice, s), "qgw_state_hf_solve");
+  QGW_CHECK_HIP(launch_hf_density(p, st->H_k, st->d_scal, st->d_stat, u, eps, st->n_k, s), "qgw_state_hf_solve");
+  double res[4] = {};
+  double dsig = NAN;
+  int bad = 0, done = 0;
+  for (int it = 0; it < max_iter; ++it) {
+    // SigH + SigF from n, the change and mixing, H = H0 + Sigma_HF, then mu and n (H class)
+    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_K_TO_R, int64_t(p.no) * p.no, st->n_k, st->n_R, s), "qgw_state_hf_solve");
+    QGW_CHECK_HIP(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, s), "qgw_state_hf_solve");
+    QGW_CHECK_HIP(launch_lattice_fft(p, QGW_R_TO_K, int64_t(p.no) * p.no, st->SigHF_R, st->SigHF_k, s),
+                  "qgw_state_hf_solve");
+    QGW_CHECK_HIP(launch_hf_delta_mix(p, st->SigHF_k, st->SigHF_old, st->mixing, st->d_dsig, s), "qgw_state_hf_solve");
+    QGW_CHECK_HIP(launch_add(p, so_n, st->H_k, st->SigHF_k, st->Hs_k, s), "qgw_state_hf_solve");
+    QGW_CHECK_HIP(launch_hf_density(p, st->Hs_k, st->d_scal, st->d_stat, u, eps, st->n_k, s), "qgw_state_hf_solve");
+    QGW_CHECK_HIP(hipMemcpyAsync(&dsig, st->d_dsig, sizeof(double), hipMemcpyDeviceToHost, s), "qgw_state_hf_solve");
+    QGW_CHECK_HIP(hipMemcpyAsync(res, st->d_scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_state_hf_solve");
+    QGW_CHECK_HIP(hipMemcpyAsync(&bad, st->d_stat, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_state_hf_solve");
+    QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_state_hf_solve");
+    ++done;
+    QGW_REQUIRE(bad == 0, QGW_ERR_NONFINITE, "qgw_state_hf_solve: non-finite chemical potential or filling");
+    if (dsig <= tol) break;
+  }
+  if (done == 0) {
+    QGW_CHECK_HIP(hipMemcpyAsync(res, st->d_scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_state_hf_solve");
+    QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_state_hf_solve");
+  }
+  st->mu = res[0];
+  // G = [(i w + mu) - H0 - Sigma_HF]^{-1} with Sigma^C = 0, so that a GW solve can continue from HF
+  QGW_CHECK_HIP(hipMemsetAsync(st->Sig_iw, 0, so * p.r, s), "qgw_state_hf_solve");
+  QGW_CHECK_HIP(hipMemsetAsync(st->Sig_iw_old, 0, so * p.r, s), "qgw_state_hf_solve");
+  QGW_CHECK_HIP(launch_add(p, so_n, st->H_k, st->SigHF_k, st->Hs_k, s), "qgw_state_hf_solve");
+  QGW_CHECK_HIP(launch_dyson_g_final(p, st->Hs_k, nullptr, 0, st->G_iw, st->d_scal, st->d_part, st->d_stat, s),
+                "qgw_state_hf_solve");
+  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_state_hf_solve");
+  st->last_dsig = INFINITY;
+  if (iters_done) *iters_done = done;
+  if (d_sigma) *d_sigma = dsig;
+  if (mu_out) *mu_out = st->mu;
+  return QGW_OK;
+}
+
 // ---------------------------------------------------------- quasiparticle
 
 qgw_status qgw_quasiparticle(qgw_plan h, const void* H_k, const void* SigHF_k, const void* Sig_iw, double mu,
@@ -1217,6 +1309,7 @@ qgw_status qgw_state_copy(qgw_state st, int32_t which, void* dst, int64_t* bytes
     case 2: src = st->SigHF_k; n = so; break;
     case 3: src = st->P_nu; n = fp; break;
     case 4: src = st->Wc_nu; n = fp; break;
+    case 5: src = st->n_k; n = so; break;
     default:
       set_error("qgw_state_copy: bad selector");
       return QGW_ERR_INVALID_ARG;

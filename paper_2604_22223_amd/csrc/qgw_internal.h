@@ -81,6 +81,14 @@ struct Plan {
 
 void set_error(const std::string& msg);
 
+// Hartree-Fock density of the static Hamiltonian hs (FP64): eigen-decomposition per k into u, eps
+// (workspace: n_o^2 N_k complex, n_o N_k double), mu at the filling scal[1] (or scal[0] if scal[1] is
+// NaN) into scal[0], n = U f U^H into n
+hipError_t launch_hf_density(const Plan& p, const void* hs, double* scal, int* status, void* u, double* eps, void* n,
+                             hipStream_t s);
+// d_out = max |x_new - x_old| over a static orbital array, then x_new <- x_old + alpha (x_new - x_old), x_old <- x_new
+hipError_t launch_hf_delta_mix(const Plan& p, void* x_new, void* x_old, double alpha, double* d_out, hipStream_t s);
+
 // quasiparticle outputs per k (FP64); status[0] is set to 1 where Z^{-1} is not positive definite
 hipError_t launch_quasiparticle(const Plan& p, const void* h_k, const void* shf_k, const void* sig_iw, double mu,
                                 void* sig0, void* z, void* hqp, double* bands, int* status, hipStream_t s);

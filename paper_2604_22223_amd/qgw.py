@@ -32,7 +32,7 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_state_set_precision", "qgw_state_info", "qgw_check_finite",
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
-           "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_quasiparticle", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
+           "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_quasiparticle", "qgw_hf_density", "qgw_state_hf_solve", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
            "qgw_last_error"]
 
 
@@ -104,6 +104,8 @@ def lib():
             "qgw_energy": [vp, vp, vp, vp, vp, pd, vp],
             "qgw_energy_bwd": [vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp],
             "qgw_quasiparticle": [vp, vp, vp, vp, dbl, vp, vp, vp, pd, vp],
+            "qgw_hf_density": [vp, vp, dbl, pd, vp, vp],
+            "qgw_state_hf_solve": [vp, dbl, i32, pi32, pd, pd, vp],
             "qgw_batch_create": [i32, ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(vp)],
             "qgw_batch_launch": [vp, vp],
             "qgw_batch_read": [vp, pd, pd, pi32, vp],
@@ -321,6 +323,15 @@ class Plan:
                                        _stream()))
         return sig0, z, hqp, bands
 
+    def hf_density(self, h_k, n_target=None, mu=0.0, out=None):
+        """(mu, n(k)): Fermi-function density of the static Hamiltonian h_k (qgw_hf_density)."""
+        import torch
+        out = torch.empty_like(h_k) if out is None else out
+        m = ctypes.c_double(mu)
+        nt = float("nan") if n_target is None else float(n_target)
+        _check(lib().qgw_hf_density(self.handle, _ptr(h_k), nt, ctypes.byref(m), _ptr(out), _stream()))
+        return m.value, out
+
     def add(self, a, b, out):
         _check(lib().qgw_add(self.handle, int(a.numel()), _ptr(a), _ptr(b), _ptr(out), _stream()))
         return out
@@ -367,6 +378,15 @@ class State:
                                       ctypes.byref(mu), _stream()))
         return done.value, ds.value, mu.value
 
+    def hf_solve(self, tol=1e-10, max_iter=200):
+        """Hartree-Fock self-consistency (qgw_state_hf_solve): (passes, last max |dSigma_HF|, mu)."""
+        done = ctypes.c_int32(0)
+        ds = ctypes.c_double(math.nan)
+        mu = ctypes.c_double(math.nan)
+        _check(lib().qgw_state_hf_solve(self.handle, float(tol), int(max_iter), ctypes.byref(done),
+                                        ctypes.byref(ds), ctypes.byref(mu), _stream()))
+        return done.value, ds.value, mu.value
+
     STEP_NAMES = ["a12_density_hf", "a1_dlr_g", "a2_fft_g", "a3a4_bubble", "a5_dlr_p", "a6_dyson_w",
                   "a7_dlr_w", "a8a9a10_sigma", "a11_dlr_sigma", "a14_delta_mix", "a13_dyson_g"]
 
@@ -396,11 +416,11 @@ class State:
         return a.value, b.value, c.value
 
     def array(self, which):
-        """Copy of a state array as a torch tensor (0 G, 1 Sigma_C, 2 Sigma_HF, 3 P, 4 W^C)."""
+        """Copy of a state array as a torch tensor (0 G, 1 Sigma_C, 2 Sigma_HF, 3 P, 4 W^C, 5 n)."""
         import torch
         p = self.plan
         shapes = {0: (p.r, p.n_o, p.n_o, p.n_k), 1: (p.r, p.n_o, p.n_o, p.n_k), 2: (p.n_o, p.n_o, p.n_k),
-                  3: (p.r, p.n_k, p.n_b, p.n_b), 4: (p.r, p.n_k, p.n_b, p.n_b)}
+                  3: (p.r, p.n_k, p.n_b, p.n_b), 4: (p.r, p.n_k, p.n_b, p.n_b), 5: (p.n_o, p.n_o, p.n_k)}
         out = torch.empty(shapes[which], dtype=torch.complex128, device="cuda:%d" % p.device)
         nbytes = ctypes.c_int64(0)
         _check(lib().qgw_state_copy(self.handle, int(which), _ptr(out), ctypes.byref(nbytes), _stream()))
