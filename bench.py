@@ -89,8 +89,10 @@ PEAK_TFLOPS = {"f64": FP64_PEAK_TFLOPS, "f32": FP32_PEAK_TFLOPS}
 # for a 256 MiB device copy: FETCH x 1.9997, WRITE x 1.0000; profiles/hbm_traffic_gw_iteration_five_orbital_24.md).
 # Valid for the kernels as they were profiled; a changed kernel drops its entry until it is profiled again.
 MEASURED_TRAFFIC = {
-    "a3a4_bubble:f64": 501.1e6,
-    "a3a4_bubble:f32": 232.2e6,
+    "a3a4_bubble:f64": 501.1e6, "a5_dlr_p:f64": 671.8e6, "a6_dyson_w:f64": 629.3e6, "a7_dlr_w:f64": 921.9e6,
+    "a8a9a10_sigma:f64": 421.2e6,
+    "a3a4_bubble:f32": 232.2e6, "a5_dlr_p:f32": 348.2e6, "a6_dyson_w:f32": 315.0e6, "a7_dlr_w:f32": 481.8e6,
+    "a8a9a10_sigma:f32": 208.3e6,
 }
 FP64_STEPS = ("a12_density_hf", "a14_delta_mix", "a13_dyson_g")
 
@@ -174,7 +176,7 @@ def quasiparticle_leg(torch, qgw, plan, st, H_R, mu, reps=20):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
-    zr = torch.linalg.eigvalsh(z.permute(2, 0, 1).contiguous())
+    zr = np.linalg.eigvalsh(np.moveaxis(z.cpu().numpy(), -1, 0))
     return {"ms_per_call": round(ms, 4), "z_min": round(float(zr.min()), 6), "z_max": round(float(zr.max()), 6),
             "band_min_eV": round(float(bands.min()), 6), "band_max_eV": round(float(bands.max()), 6),
             "note": "bands relative to the chemical potential of the converged solve; includes the call's wait"}
