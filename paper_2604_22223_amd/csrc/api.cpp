@@ -4,6 +4,7 @@
 // the FP64 DLR maps once per plan.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -39,6 +40,7 @@ struct qgw_state_s {
   double* d_scal = nullptr;
   double* d_part = nullptr;
   int* d_stat = nullptr;
+  int mu_steps0 = 10;  // Newton steps queued in the first round of the next search
   // single-precision copies for the FP32 phase of the solve (allocated on first use)
   bool has32 = false;
   Plan p32;
@@ -490,7 +492,7 @@ qgw_status qgw_hartree_fock(qgw_plan h, const void* V_R, const void* n_R, void* 
 static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw, double n_target,
                               double* mu, void* G_iw, hipStream_t s, double* evals, double* scal = nullptr,
                               double* part = nullptr, int* stat = nullptr, const double* extra_src = nullptr,
-                              double* extra_dst = nullptr, hipEvent_t end_ev = nullptr) {
+                              double* extra_dst = nullptr, hipEvent_t end_ev = nullptr, int steps0 = 6) {
   const int mode = std::isnan(n_target) ? 0 : 1;
   if (!scal) {
     scal = p.d_scalars;
@@ -510,7 +512,8 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
   for (int round = 0;; ++round) {
     // a few Newton evaluations, G at the current mu, one read-back; more rounds only if needed
     if (mode == 1)
-      QGW_CHECK_HIP(launch_dyson_g_steps(p, H_k, Sig_iw, scal, part, stat, round == 0 ? 6 : 16, s), "qgw_dyson_G");
+      QGW_CHECK_HIP(launch_dyson_g_steps(p, H_k, Sig_iw, scal, part, stat, round == 0 ? steps0 : 16, s),
+                    "qgw_dyson_G");
     QGW_CHECK_HIP(launch_dyson_g_final(p, H_k, Sig_iw, mode, G_iw, scal, part, stat, s, extra_src),
                   "qgw_dyson_G");
     if (end_ev) QGW_CHECK_HIP(hipEventRecord(end_ev, s), "qgw_dyson_G");
@@ -1014,6 +1017,7 @@ qgw_status qgw_state_destroy(qgw_state st) {
 qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
   QGW_REQUIRE(st && mu, QGW_ERR_INVALID_ARG, "qgw_state_init_g0: null argument");
   const Plan& p = st->plan->p;
+  st->mu_steps0 = 10;
   QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   const size_t so = size_t(p.no) * p.no * p.nk * 16;
@@ -1138,12 +1142,14 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     QGW_CHECK_HIP(enqueue_steps(st, f32, st->prof, s), "qgw_gw_iteration");
     // a13: Dyson G with the chemical potential
     // |dSigma| (a14, already enqueued) comes back with the search's result: one wait per iteration
-    double m = st->mu;
-    qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, nullptr, st->d_scal,
+    // the first round queues the previous search's evaluation count + 3 Newton steps (4 .. 12; 10 after G0)
+    double m = st->mu, evals = 0.0;
+    qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, &evals, st->d_scal,
                                 st->d_part, st->d_stat, st->d_dsig, &dsig,
-                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr);
+                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr, st->mu_steps0);
     if (rc != QGW_OK) return rc;
     st->mu = m;
+    st->mu_steps0 = std::min(12, std::max(4, int(evals) + 3));
     if (st->prof) {
       for (int i = 0; i < QGW_NUM_STEPS; ++i) {
         float ms = 0.0f;

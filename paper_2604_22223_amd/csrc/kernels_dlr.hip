@@ -110,6 +110,52 @@ __global__ __launch_bounds__(256) void k_dlr(const cpx<T>* __restrict__ in, cpx<
   }
 }
 
+// One-row maps (the density row G(beta^-) from G(i w_m)): out[c] = s sum_t row[t] in[t][c].  A block of
+// four waves takes 64 columns; wave w sums the nodes t = w, w + 4, ... for its lane's column (coalesced
+// 64-column reads), and the four partial sums are added in a fixed order.  HERM as for k_dlr.
+template <typename T, int HERM>
+__global__ __launch_bounds__(256) void k_dlr_row(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                                 const cpx<T>* __restrict__ row, int r, int64_t ncols, int na, int nq,
+                                                 T sre, T sim) {
+  __shared__ cpx<T> part[2][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t c = int64_t(blockIdx.x) * 64 + lane;
+  const bool valid = c < ncols;
+  const int64_t cc = valid ? c : 0;
+  int64_t cs = cc;
+  if (HERM) {  // column (a na + b) nq + k -> (b na + a) nq + k
+    const int64_t k = cc % nq, ab = cc / nq;
+    const int a = int(ab / na), b = int(ab % na);
+    cs = (int64_t(b) * na + a) * nq + k;
+  }
+  cpx<T> acc = mk(T(0), T(0)), acc2 = mk(T(0), T(0));
+#pragma unroll 4
+  for (int t = w; t < r; t += 4) {
+    const cpx<T> m = row[t];
+    const cpx<T> x = in[int64_t(t) * ncols + cc];
+    if (HERM == 0) {
+      acc = fma(acc, m, x);
+    } else if (HERM == 1) {
+      acc = fma(acc, m, scale(x + conj(in[int64_t(t) * ncols + cs]), T(0.5)));
+    } else {
+      acc = fma(acc, m, x);
+      acc2 = fma(acc2, m, in[int64_t(t) * ncols + cs]);
+    }
+  }
+  part[0][w][lane] = acc;
+  part[1][w][lane] = acc2;
+  __syncthreads();
+  if (w != 0 || !valid) return;
+  cpx<T> a = part[0][0][lane], b = part[1][0][lane];
+#pragma unroll
+  for (int i = 1; i < 4; ++i) {
+    a = a + part[0][i][lane];
+    b = b + part[1][i][lane];
+  }
+  const cpx<T> sc = mk(sre, sim);
+  out[c] = HERM == 2 ? scale(sc * a + conj(sc * b), T(0.5)) : sc * a;
+}
+
 namespace {
 
 template <typename T>
@@ -490,6 +536,25 @@ hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double 
     }
     if (herm) return dlr_mfma_launch<float, kPlain, true>(p, map, na, nq, sre, sim, in, out, s);
     return dlr_mfma_launch<float, kPlain, false>(p, map, na, nq, sre, sim, in, out, s);
+  }
+  if (map == 5) {  // one output row
+    if (herm && ncols != ng) return hipErrorInvalidValue;
+    if (ncols <= 0) return hipSuccess;
+    const unsigned blocks = unsigned((ncols + 63) / 64);
+#define QGW_ROW(T, H)                                                                                     \
+  hipLaunchKernelGGL((k_dlr_row<T, H>), dim3(blocks), dim3(256), 0, s, (const cpx<T>*)in, (cpx<T>*)out, \
+                     map_ptr<T>(p, 5), p.r, ncols, p.no, p.nk, T(sre), T(sim))
+    if (p.prec == 0) {
+      if (herm == 0) QGW_ROW(double, 0);
+      else if (herm == 1) QGW_ROW(double, 1);
+      else QGW_ROW(double, 2);
+    } else {
+      if (herm == 0) QGW_ROW(float, 0);
+      else if (herm == 1) QGW_ROW(float, 1);
+      else QGW_ROW(float, 2);
+    }
+#undef QGW_ROW
+    return hipGetLastError();
   }
   if (herm) {
     if (ncols != int64_t(p.no) * p.no * p.nk) return hipErrorInvalidValue;
