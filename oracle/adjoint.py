@@ -29,22 +29,23 @@ def apply_map_adj(mat, ybar):
     return apply_map(np.conj(mat.T), ybar)
 
 
-def k_from_R_adj(xbar_k):
+def k_from_R_adj(xbar_k, d=2):
     """Adjoint of X(k) = sum_R X(R) e^{-ik.R}: Xbar(R) = sum_k Xbar(k) e^{+ik.R}."""
-    n_k = xbar_k.shape[-1] * xbar_k.shape[-2]
-    return n_k * lattice.R_from_k(xbar_k)
+    n_k = int(np.prod(xbar_k.shape[-d:]))
+    return n_k * lattice.R_from_k(xbar_k, d)
 
 
-def R_from_k_adj(xbar_r):
+def R_from_k_adj(xbar_r, d=2):
     """Adjoint of X(R) = (1/N_k) sum_k X(k) e^{+ik.R}: Xbar(k) = (1/N_k) sum_R Xbar(R) e^{-ik.R}."""
-    n_k = xbar_r.shape[-1] * xbar_r.shape[-2]
-    return lattice.k_from_R(xbar_r) / n_k
+    n_k = int(np.prod(xbar_r.shape[-d:]))
+    return lattice.k_from_R(xbar_r, d) / n_k
 
 
 def density_k_adj(nbar_k, dlr):
     """Adjoint of n(k) = Herm(-rho_beta . G(k, i w)): Gbar[m] = -conj(rho_m) Herm(nbar)."""
     h = hermitian_part(nbar_k)
-    return -np.conj(dlr.F_iw2beta)[:, None, None, None, None] * h[None]
+    rho = np.conj(dlr.F_iw2beta).reshape((-1,) + (1,) * h.ndim)
+    return -rho * h[None]
 
 
 # ----------------------------------------------------------------------------
@@ -59,15 +60,17 @@ def hartree_fock_R_adj(sbar_R, n_R, V_R, pairs):
     """
     nbar = np.zeros_like(n_R)
     vbar = np.zeros_like(V_R)
-    vq0 = np.sum(V_R, axis=(-2, -1))
+    d = n_R.ndim - 2
+    r0 = (0,) * d                                               # R = 0
+    vq0 = np.sum(V_R, axis=lattice.mesh_axes(d))
     vq0bar = np.zeros_like(vq0)
     for al, (i, l) in enumerate(pairs):
         for be, (j, k) in enumerate(pairs):
             vbar[al, be] -= np.conj(n_R[l, j]) * sbar_R[i, k]
             nbar[l, j] -= np.conj(V_R[al, be]) * sbar_R[i, k]
-            vq0bar[al, be] += 2.0 * np.conj(n_R[k, j, 0, 0]) * sbar_R[i, l, 0, 0]
-            nbar[k, j, 0, 0] += 2.0 * np.conj(vq0[al, be]) * sbar_R[i, l, 0, 0]
-    vbar += vq0bar[:, :, None, None]
+            vq0bar[al, be] += 2.0 * np.conj(n_R[(k, j) + r0]) * sbar_R[(i, l) + r0]
+            nbar[(k, j) + r0] += 2.0 * np.conj(vq0[al, be]) * sbar_R[(i, l) + r0]
+    vbar += vq0bar.reshape(vq0bar.shape + (1,) * d)
     return nbar, vbar
 
 
@@ -76,14 +79,15 @@ def bubble_adj(pbar, G_tau_R, G_reflt_R, pairs, spin_factor=2.0):
 
     P_ab(R) = -s G_lj(R, tau) G_ki(-R, beta - tau) for a = (i, l), b = (j, k).
     """
-    g_minus_r = lattice.reflect(G_reflt_R)
+    d = G_tau_R.ndim - 3
+    g_minus_r = lattice.reflect(G_reflt_R, d)
     gt_bar = np.zeros_like(G_tau_R)
     gm_bar = np.zeros_like(G_reflt_R)
     for al, (i, l) in enumerate(pairs):
         for be, (j, k) in enumerate(pairs):
             gt_bar[:, l, j] -= spin_factor * np.conj(g_minus_r[:, k, i]) * pbar[:, al, be]
             gm_bar[:, k, i] -= spin_factor * np.conj(G_tau_R[:, l, j]) * pbar[:, al, be]
-    return gt_bar, lattice.reflect(gm_bar)      # the reflection is its own inverse and adjoint
+    return gt_bar, lattice.reflect(gm_bar, d)   # the reflection is its own inverse and adjoint
 
 
 def sigma_adj(sbar, G_tau_R, Wc_tau_R, pairs):
@@ -147,12 +151,13 @@ def dyson_G_adj(gbar, H_k, sig_hf_k, sig_iw, dlr, mu, n_target, mubar=0.0):
     gmh = np.conj(np.swapaxes(gm, -1, -2))
     s = gmh @ gb @ gmh
     if n_target is not None:
-        n_kpts = g.shape[-1] * g.shape[-2]
-        rho = dlr.F_iw2beta
+        d = g.ndim - 3
+        n_kpts = int(np.prod(g.shape[3:]))
+        rho = dlr.F_iw2beta.reshape((-1,) + (1,) * d)
         g2 = gm @ gm
-        n_mu = 2.0 / n_kpts * float(np.sum((rho[:, None, None] * np.trace(g2, axis1=-2, axis2=-1)).real))
+        n_mu = 2.0 / n_kpts * float(np.sum((rho * np.trace(g2, axis1=-2, axis2=-1)).real))
         mu_bar_total = mubar - float(np.sum(np.trace(s, axis1=-2, axis2=-1).real))
-        n_x = -2.0 / n_kpts * np.conj(rho)[:, None, None, None, None] * np.conj(np.swapaxes(g2, -1, -2))
+        n_x = -2.0 / n_kpts * np.conj(rho)[..., None, None] * np.conj(np.swapaxes(g2, -1, -2))
         s = s - (mu_bar_total / n_mu) * n_x
     return np.moveaxis(s, (-2, -1), (1, 2))
 
@@ -198,6 +203,7 @@ def iteration_vjp(model, dlr, state_in, out, cot):
     """
     inter = out["intermediates"]
     pairs = model.pairs
+    d = model.dim
     G_iw = state_in["G_iw"]
     gbar_new = cot.get("G_iw")
     if gbar_new is None:
@@ -222,24 +228,25 @@ def iteration_vjp(model, dlr, state_in, out, cot):
         sc_bar = sc_bar + ev["sig_iw"]
     # a11, a10 (Hermitian part), a9
     stk_bar = hermitian_part(apply_map_adj(dlr.F_tau2iw, sc_bar), axes=(1, 2))
-    str_bar = k_from_R_adj(stk_bar)
+    str_bar = k_from_R_adj(stk_bar, d)
     gt_bar, wct_r_bar = sigma_adj(str_bar, inter["G_tau_R"], inter["Wc_tau_R"], pairs)
     # a8, a7, a6
-    wct_q_bar = R_from_k_adj(wct_r_bar)
+    wct_q_bar = R_from_k_adj(wct_r_bar, d)
     wcn_bar = apply_map_adj(dlr.B_iw2tau, wct_q_bar)
     vq_bar, pn_bar = dyson_W_adj(wcn_bar, model.V_q, inter["P_nu_q"])
     # a5, a4, a3
     ptq_bar = apply_map_adj(dlr.B_tau2iw, pn_bar)
-    ptr_bar = k_from_R_adj(ptq_bar)
+    ptr_bar = k_from_R_adj(ptq_bar, d)
     gt2, gr_bar = bubble_adj(ptr_bar, inter["G_tau_R"], inter["G_reflt_R"], pairs)
     gt_bar = gt_bar + gt2
     # a2, a1
-    gin_bar = apply_map_adj(dlr.F_iw2tau, R_from_k_adj(gt_bar)) + apply_map_adj(dlr.F_iw2taur, R_from_k_adj(gr_bar))
+    gin_bar = (apply_map_adj(dlr.F_iw2tau, R_from_k_adj(gt_bar, d))
+               + apply_map_adj(dlr.F_iw2taur, R_from_k_adj(gr_bar, d)))
     # a12: Hartree-Fock from the density of the incoming G
-    shf_r_bar = k_from_R_adj(shf_bar)
+    shf_r_bar = k_from_R_adj(shf_bar, d)
     n_r_bar, vr_bar = hartree_fock_R_adj(shf_r_bar, inter["n_R"], model.V_R, pairs)
-    gin_bar = gin_bar + density_k_adj(R_from_k_adj(n_r_bar), dlr)
-    vr_bar = vr_bar + k_from_R_adj(vq_bar)
+    gin_bar = gin_bar + density_k_adj(R_from_k_adj(n_r_bar, d), dlr)
+    vr_bar = vr_bar + k_from_R_adj(vq_bar, d)
     return {"G_iw": gin_bar, "H_k": hbar_k, "V_R": vr_bar}
 
 
@@ -261,7 +268,7 @@ def one_iteration_grad(model, dlr, cot):
     out = gw.gw_iteration(model, dlr, st0, keep=True)
     c = iteration_vjp(model, dlr, st0, out, cot)
     hbar_k = c["H_k"] + g0_vjp(model, dlr, st0, c["G_iw"])
-    return out, {"H_R": k_from_R_adj(hbar_k), "V_R": c["V_R"]}
+    return out, {"H_R": k_from_R_adj(hbar_k, model.dim), "V_R": c["V_R"]}
 
 
 def n_iteration_grad(model, dlr, cot, n_iter):
@@ -288,4 +295,4 @@ def n_iteration_grad(model, dlr, cot, n_iter):
         vbar_r = vbar_r + res["V_R"]
         c = {"G_iw": res["G_iw"]}
     hbar_k = hbar_k + g0_vjp(model, dlr, states[0], c["G_iw"])
-    return outs[-1], {"H_R": k_from_R_adj(hbar_k), "V_R": vbar_r}
+    return outs[-1], {"H_R": k_from_R_adj(hbar_k, model.dim), "V_R": vbar_r}

@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring): not for the product path.
 Conventions (where the paper leaves a choice open):
 
 * Arrays carry the DLR node axis first, then orbital or pair indices, then
-  the two mesh axes: G[node, a, b, n1, n2], P[node, alpha, beta, n1, n2].
+  the d mesh axes: G[node, a, b, n1, n2], P[node, alpha, beta, n1, n2] on a
+  2-D mesh, G[node, a, b, n1, n2, n3] on a 3-D one.
 * Orbital indices a = (p, i) are global; pair indices alpha = (p; i, l) come
   from ``lattice.pair_list`` and X_{(il),(jk)} stands for the paper's X_{ijkl}
   (Eq. eq:many-body-hamiltonian pairs c+_i ... c_l at one site and
@@ -42,9 +43,10 @@ class Model:
         self.n_b = len(self.pairs)
         assert self.H_R.shape == (self.n_o, self.n_o) + self.mesh
         assert self.V_R.shape == (self.n_b, self.n_b) + self.mesh
-        self.n_k = self.mesh[0] * self.mesh[1]
-        self.H_k = lattice.k_from_R(self.H_R)           # H0(k), Eq. eq:fourier-transform-kr
-        self.V_q = lattice.k_from_R(self.V_R)           # V(q)
+        self.dim = len(self.mesh)
+        self.n_k = int(np.prod(self.mesh))
+        self.H_k = lattice.k_from_R(self.H_R, self.dim)           # H0(k), Eq. eq:fourier-transform-kr
+        self.V_q = lattice.k_from_R(self.V_R, self.dim)           # V(q)
 
 
 # ----------------------------------------------------------------------------
@@ -89,7 +91,7 @@ def density_k(G_iw, dlr):
 
 def electron_count(n_k):
     """N_e = (2 / N_k) sum_k Re Tr n(k)  (two spins)."""
-    n_kpts = n_k.shape[-1] * n_k.shape[-2]
+    n_kpts = int(np.prod(lattice.mesh_of(n_k, 2)))
     tr = np.einsum("aa...->...", n_k)
     return 2.0 * float(np.sum(tr.real)) / n_kpts
 
@@ -154,13 +156,14 @@ def hartree_fock_R(n_R, V_R, pairs):
         Sigma_H_{il} = 2 sum_{(jk)} V_{(il),(jk)}(q = 0) n_{kj}(R = 0)
     """
     n_o = n_R.shape[0]
-    mesh = n_R.shape[-2:]
+    mesh = lattice.mesh_of(n_R, 2)
+    r0 = (0,) * len(mesh)                                       # R = 0
     sig = np.zeros((n_o, n_o) + mesh, dtype=np.complex128)
-    v_q0 = np.sum(V_R, axis=(-2, -1))
+    v_q0 = np.sum(V_R, axis=lattice.mesh_axes(len(mesh)))
     for al, (i, l) in enumerate(pairs):
         for be, (j, k) in enumerate(pairs):
             sig[i, k] -= V_R[al, be] * n_R[l, j]
-            sig[i, l, 0, 0] += 2.0 * v_q0[al, be] * n_R[k, j, 0, 0]
+            sig[(i, l) + r0] += 2.0 * v_q0[al, be] * n_R[(k, j) + r0]
     return sig
 
 
@@ -177,9 +180,9 @@ def bubble(G_tau_R, G_reflt_R, pairs, spin_factor=2.0):
     G(R, beta - tau_k) at the DLR time nodes (unreflected in R).
     """
     r = G_tau_R.shape[0]
-    mesh = G_tau_R.shape[-2:]
+    mesh = lattice.mesh_of(G_tau_R, 3)
     nb = len(pairs)
-    g_minus_r = lattice.reflect(G_reflt_R)                      # G(-R, beta - tau)
+    g_minus_r = lattice.reflect(G_reflt_R, len(mesh))           # G(-R, beta - tau)
     p = np.empty((r, nb, nb) + mesh, dtype=np.complex128)
     for al, (i, l) in enumerate(pairs):
         for be, (j, k) in enumerate(pairs):
@@ -218,7 +221,7 @@ def sigma(G_tau_R, Wc_tau_R, pairs, n_o):
     Eq. eq:many-body-hamiltonian (the same contraction as the Fock term).
     """
     r = G_tau_R.shape[0]
-    mesh = G_tau_R.shape[-2:]
+    mesh = lattice.mesh_of(G_tau_R, 3)
     sig = np.zeros((r, n_o, n_o) + mesh, dtype=np.complex128)
     for al, (i, l) in enumerate(pairs):
         for be, (j, k) in enumerate(pairs):
@@ -246,10 +249,11 @@ def total_energy(model, dlr, state):
     n_k = density_k(G, dlr)
     nk = model.n_k
     a = model.H_k + 0.5 * state["sig_hf_k"]
-    e_hf = 2.0 / nk * float(np.einsum("abxy,baxy->", a, n_k).real)
+    e_hf = 2.0 / nk * float(np.sum(np.einsum("ab...,ba...->...", a, n_k)).real)
     sig_c = dlr.coeffs_from_iw_f(state["sig_iw"])          # [l, a, b, n1, n2]
     g_c = dlr.coeffs_from_iw_f(G)
-    tr = np.einsum("labxy,mbaxy->lm", sig_c, g_c)            # sum_k Tr[sigma_l g_m]
+    flat = lambda x: x.reshape(x.shape[:3] + (-1,))           # mesh axes as one k axis
+    tr = np.einsum("labk,mbak->lm", flat(sig_c), flat(g_c))  # sum_k Tr[sigma_l g_m]
     e_c = float(np.sum(dlr.D_sum * tr).real) / nk
     return e_hf + e_c, e_hf, e_c
 
@@ -283,22 +287,23 @@ def gw_iteration(model, dlr, state, mixing=1.0, keep=False):
     """
     G_iw = state["G_iw"]
     pairs = model.pairs
+    d = model.dim
     inter = {}
     # a12: density of the incoming G, then Hartree + Fock
     n_k = density_k(G_iw, dlr)
-    n_R = lattice.R_from_k(n_k)
+    n_R = lattice.R_from_k(n_k, d)
     sig_hf_R = hartree_fock_R(n_R, model.V_R, pairs)
-    sig_hf_k = lattice.k_from_R(sig_hf_R)
+    sig_hf_k = lattice.k_from_R(sig_hf_R, d)
     # a1: Matsubara -> tau and beta - tau
     G_tau = apply_map(dlr.F_iw2tau, G_iw)
     G_reflt = apply_map(dlr.F_iw2taur, G_iw)
     # a2: k -> R
-    G_tau_R = lattice.R_from_k(G_tau)
-    G_reflt_R = lattice.R_from_k(G_reflt)
+    G_tau_R = lattice.R_from_k(G_tau, d)
+    G_reflt_R = lattice.R_from_k(G_reflt, d)
     # a3: bubble
     P_tau_R = bubble(G_tau_R, G_reflt_R, pairs)
     # a4: R -> q
-    P_tau_q = lattice.k_from_R(P_tau_R)
+    P_tau_q = lattice.k_from_R(P_tau_R, d)
     # a5: tau -> i nu (bosonic)
     P_nu_q = apply_map(dlr.B_tau2iw, P_tau_q)
     # a6: Dyson W, W^C = W - V
@@ -306,11 +311,11 @@ def gw_iteration(model, dlr, state, mixing=1.0, keep=False):
     # a7: i nu -> tau (bosonic)
     Wc_tau_q = apply_map(dlr.B_iw2tau, Wc_nu_q)
     # a8: q -> R
-    Wc_tau_R = lattice.R_from_k(Wc_tau_q)
+    Wc_tau_R = lattice.R_from_k(Wc_tau_q, d)
     # a9: self-energy
     sig_tau_R = sigma(G_tau_R, Wc_tau_R, pairs, model.n_o)
     # a10: R -> k; Sigma^C(k, tau) is Hermitian (Lehmann form), keep that part
-    sig_tau_k = hermitian_part(lattice.k_from_R(sig_tau_R), axes=(1, 2))
+    sig_tau_k = hermitian_part(lattice.k_from_R(sig_tau_R, d), axes=(1, 2))
     # a11: tau -> i omega (fermionic)
     sig_iw = apply_map(dlr.F_tau2iw, sig_tau_k)
     # a14 (part): linear mixing of the total self-energy

@@ -23,7 +23,7 @@ def fermi(x):
 
 
 def eigen_k(H_k):
-    """Eigenvalues [n1, n2, band] and eigenvectors [n1, n2, a, band] of the Hermitian part of H(k)."""
+    """Eigenvalues [*mesh, band] and eigenvectors [*mesh, a, band] of the Hermitian part of H(k)."""
     h = np.moveaxis(H_k, (0, 1), (-2, -1))
     h = 0.5 * (h + np.conj(np.swapaxes(h, -1, -2)))
     return np.linalg.eigh(h)
@@ -31,7 +31,7 @@ def eigen_k(H_k):
 
 def electron_count(eps, mu, beta):
     """N_e(mu) = (2 / N_k) sum_{k, n} f(beta (eps_n(k) - mu)) (two spins)."""
-    n_k = eps.shape[0] * eps.shape[1]
+    n_k = int(np.prod(eps.shape[:-1]))
     return 2.0 * float(np.sum(fermi(beta * (eps - mu)))) / n_k
 
 
@@ -51,7 +51,7 @@ def solve_mu(eps, beta, n_target, tol=1e-13, max_steps=400):
 
 
 def fermi_density(H_k, beta, n_target=None, mu=None):
-    """(mu, n(k)) for the static Hamiltonian H(k): n = U f(beta (eps - mu)) U^H, [a, b, n1, n2]."""
+    """(mu, n(k)) for the static Hamiltonian H(k): n = U f(beta (eps - mu)) U^H, [a, b, *mesh]."""
     eps, u = eigen_k(H_k)
     if n_target is not None:
         mu = solve_mu(eps, beta, n_target)
@@ -62,8 +62,8 @@ def fermi_density(H_k, beta, n_target=None, mu=None):
 
 def hf_self_energy_k(model, n_k):
     """Sigma_HF(k) from the density (SigH and SigF classes)."""
-    n_R = lattice.R_from_k(n_k)
-    return lattice.k_from_R(hartree_fock_R(n_R, model.V_R, model.pairs))
+    n_R = lattice.R_from_k(n_k, model.dim)
+    return lattice.k_from_R(hartree_fock_R(n_R, model.V_R, model.pairs), model.dim)
 
 
 def initial_state(model):

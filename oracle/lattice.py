@@ -7,29 +7,40 @@ and X(R) = (1/N_k) sum_k X(k) exp(+i k.(R + tau_p - tau_q)).  The basis-vector
 phase exp(-i k.(tau_p - tau_q)) is a k-dependent diagonal unitary gauge that
 cancels in every product of k-space matrices and in every R-space quantity, so
 the oracle works in the cell-periodic gauge (phase dropped): the transforms are
-plain 2-D DFTs over the mesh, with k.R = 2 pi (k1 R1 / n1 + k2 R2 / n2).
+plain d-dimensional DFTs over the mesh, with k.R = 2 pi sum_a k_a R_a / n_a.
 
-The mesh axes are the last two axes of every array.
+The mesh axes are the last ``d`` axes of every array (d = 2 for a square or
+rectangular mesh, d = 3 for a cubic one).
 """
 import numpy as np
 
 
-def k_from_R(x_r):
+def mesh_axes(d):
+    return tuple(range(-d, 0))
+
+
+def k_from_R(x_r, d=2):
     """X(k) = sum_R X(R) exp(-i k.R)  (numpy's forward DFT, unnormalised)."""
-    return np.fft.fft2(x_r, axes=(-2, -1))
+    return np.fft.fftn(x_r, axes=mesh_axes(d))
 
 
-def R_from_k(x_k):
+def R_from_k(x_k, d=2):
     """X(R) = (1/N_k) sum_k X(k) exp(+i k.R)  (numpy's inverse DFT)."""
-    return np.fft.ifft2(x_k, axes=(-2, -1))
+    return np.fft.ifftn(x_k, axes=mesh_axes(d))
 
 
-def reflect(x_r):
-    """X(-R) on the periodic mesh: index R -> (-R) mod n along both mesh axes."""
-    n1, n2 = x_r.shape[-2:]
-    i1 = (-np.arange(n1)) % n1
-    i2 = (-np.arange(n2)) % n2
-    return x_r[..., i1, :][..., :, i2]
+def reflect(x_r, d=2):
+    """X(-R) on the periodic mesh: index R -> (-R) mod n along every mesh axis."""
+    out = x_r
+    for ax in mesh_axes(d):
+        n = x_r.shape[ax]
+        out = np.take(out, (-np.arange(n)) % n, axis=ax)
+    return out
+
+
+def mesh_of(x, lead):
+    """The mesh shape of an array with ``lead`` leading (node / orbital / pair) axes."""
+    return tuple(x.shape[lead:])
 
 
 def pair_list(site_norb):

@@ -23,7 +23,7 @@ when n = 0 and n = -1 are nodes):
   printed, a chemical potential puts the bands relative to the Fermi level;
 * quasiparticle bands: the eigenvalues of H_QP(k), ascending.
 
-Arrays carry orbital indices first and the two mesh axes last; the
+Arrays carry orbital indices first and the mesh axes last; the
 self-energy carries the node axis before them.
 """
 import numpy as np
@@ -32,7 +32,7 @@ from .gw import hermitian_part
 
 
 def _orbital_last(x):
-    """[a, b, n1, n2] -> [n1, n2, a, b]."""
+    """[a, b, *mesh] -> [*mesh, a, b]."""
     return np.moveaxis(x, (0, 1), (-2, -1))
 
 
@@ -86,7 +86,7 @@ def qp_hamiltonian(H_k, sig0_k, zinv_k, mu=0.0):
 
 
 def qp_bands(hqp_k):
-    """Eigenvalues of H_QP(k), ascending: [band, n1, n2]."""
+    """Eigenvalues of H_QP(k), ascending: [band, *mesh]."""
     ev = np.linalg.eigvalsh(_orbital_last(hqp_k))
     return np.moveaxis(ev, -1, 0)
 

@@ -11,7 +11,8 @@ Both the HIP path and the test oracle consume its arrays.
 Array conventions
 -----------------
 * ``H_R[a, b, R1, R2]`` is the matrix element of H0 between orbital a in cell
-  R = R1 a1 + R2 a2 and orbital b in cell 0 (eV), indices taken mod the mesh.
+  R = R1 a1 + R2 a2 and orbital b in cell 0 (eV), indices taken mod the mesh;
+  on a 3-D mesh ``H_R[a, b, R1, R2, R3]`` with R = R1 a1 + R2 a2 + R3 a3.
 * ``V_R[alpha, beta, R1, R2]`` is the interaction between pair alpha = (p; i, l)
   in cell R and pair beta = (q; j, k) in cell 0, i.e. V_{ijkl}^{pq}(R) of the
   paper's Hamiltonian with c+_i c_l at p and c+_j c_k at q.  Pairs are ordered
@@ -141,15 +142,16 @@ def graphene(n=12, t=-2.7, U=3.0, ohno=False, beta=10.0, omega_max=100.0, eps=1e
 
 
 def local_model(mesh, site_norb, levels, V_local, beta, omega_max, eps, n_target=None):
-    """Flat-band (atomic-limit) model: no hopping, on-site levels and interaction."""
-    n1, n2 = mesh
+    """Flat-band (atomic-limit) model: no hopping, on-site levels and interaction (2-D or 3-D mesh)."""
+    mesh = tuple(int(x) for x in mesh)
+    r0 = (0,) * len(mesh)
     n_o = int(sum(site_norb))
-    H_R = np.zeros((n_o, n_o, n1, n2), dtype=np.complex128)
-    H_R[:, :, 0, 0] = np.diag(np.asarray(levels, dtype=np.float64))
+    H_R = np.zeros((n_o, n_o) + mesh, dtype=np.complex128)
+    H_R[(slice(None), slice(None)) + r0] = np.diag(np.asarray(levels, dtype=np.float64))
     nb = pair_count(site_norb)
-    V_R = np.zeros((nb, nb, n1, n2), dtype=np.complex128)
-    V_R[:, :, 0, 0] = V_local
-    return {"name": "local", "mesh": (n1, n2), "site_norb": list(site_norb), "H_R": H_R,
+    V_R = np.zeros((nb, nb) + mesh, dtype=np.complex128)
+    V_R[(slice(None), slice(None)) + r0] = V_local
+    return {"name": "local", "mesh": mesh, "site_norb": list(site_norb), "H_R": H_R,
             "V_R": V_R, "beta": float(beta), "omega_max": float(omega_max), "eps": float(eps),
             "n_target": n_target}
 
@@ -200,6 +202,84 @@ def random_model(mesh, site_norb, seed, bandwidth=3.0, U=2.0, J=0.3, Vnn=0.4,
             "n_target": float(n_target)}
 
 
+def _bandwidth_nd(hops, norb, n, d):
+    """max_k eps_max - min_k eps_min of H0(k) = sum_R t(R) e^{-ik.R} on an n^d mesh."""
+    ks = np.stack(np.meshgrid(*([2.0 * np.pi * np.arange(n) / n] * d), indexing="ij"), axis=-1).reshape(-1, d)
+    h = np.zeros((len(ks), norb, norb), dtype=np.complex128)
+    for r, t in hops.items():
+        h += np.exp(-1j * (ks @ np.asarray(r, dtype=np.float64)))[:, None, None] * t
+    ev = np.linalg.eigvalsh(0.5 * (h + np.conj(np.swapaxes(h, -1, -2))))
+    return float(ev.max() - ev.min())
+
+
+def cubic_five_orbital(n=8, t=1.0, U=1.0, J=0.1, Vnn=0.2, beta=100.0, omega_max=25.0, eps=1e-10,
+                       n_target=None, norb=5):
+    """Degenerate ``norb``-orbital extended Hund-Hubbard model on a simple cubic lattice.
+
+    The benchmark model of the paper's performance section: orbital-diagonal
+    nearest-neighbour hopping -t on the six bonds +-x, +-y, +-z (so that
+    H0(k) = -2 t (cos k1 + cos k2 + cos k3) I), on-site Kanamori (U, J) and a
+    nearest-neighbour density-density V_(ii),(jj) = Vnn on the same bonds,
+    on an n x n x n mesh.  The paper states no filling; the default is half
+    filling (one electron per spin-orbital pair, n_target = norb).
+    """
+    if n_target is None:
+        n_target = float(norb)
+    H_R = np.zeros((norb, norb, n, n, n), dtype=np.complex128)
+    nb = norb * norb
+    V_R = np.zeros((nb, nb, n, n, n), dtype=np.complex128)
+    V_R[:, :, 0, 0, 0] = _kanamori_block(norb, U, J)
+    for r in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]:
+        idx = tuple(x % n for x in r)
+        for i in range(norb):
+            H_R[(i, i) + idx] += -t
+            for j in range(norb):
+                V_R[(i * norb + i, j * norb + j) + idx] += Vnn
+    return {"name": "cubic_five_orbital_%d^3" % n, "mesh": (n, n, n), "site_norb": [norb],
+            "H_R": H_R, "V_R": V_R, "beta": float(beta), "omega_max": float(omega_max),
+            "eps": float(eps), "n_target": float(n_target)}
+
+
+def random_model_3d(mesh, site_norb, seed, bandwidth=3.0, U=2.0, J=0.3, Vnn=0.4,
+                    beta=10.0, omega_max=20.0, eps=1e-8, n_target=None):
+    """``random_model`` on a 3-D mesh: random complex hoppings between all
+    orbitals on the bonds x, y, z, x+y, y+z (and their Hermitian partners),
+    random on-site levels, Kanamori on every site, density-density V between
+    every site pair on the six bonds +-x, +-y, +-z."""
+    rng = np.random.default_rng(seed)
+    mesh = tuple(int(x) for x in mesh)
+    n_o = int(sum(site_norb))
+    hops = {}
+    onsite = rng.standard_normal((n_o, n_o)) + 1j * rng.standard_normal((n_o, n_o))
+    hops[(0, 0, 0)] = 0.25 * (onsite + onsite.conj().T)
+    for r in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (0, 1, 1)]:
+        t = (rng.standard_normal((n_o, n_o)) + 1j * rng.standard_normal((n_o, n_o))) / math.sqrt(2.0)
+        hops[r] = t
+        hops[tuple(-x for x in r)] = t.conj().T
+    scale = bandwidth / max(_bandwidth_nd(hops, n_o, 4, 3), 1e-12)
+    H_R = np.zeros((n_o, n_o) + mesh, dtype=np.complex128)
+    for r, t in hops.items():
+        H_R[(slice(None), slice(None)) + tuple(x % m for x, m in zip(r, mesh))] += scale * t
+    nb = pair_count(site_norb)
+    V_R = np.zeros((nb, nb) + mesh, dtype=np.complex128)
+    offs = np.cumsum([0] + [n * n for n in site_norb])
+    for p, n in enumerate(site_norb):
+        V_R[offs[p]:offs[p + 1], offs[p]:offs[p + 1], 0, 0, 0] = _kanamori_block(n, U, J)
+    for p, npp in enumerate(site_norb):
+        for q, nq in enumerate(site_norb):
+            for r in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]:
+                idx = tuple(x % m for x, m in zip(r, mesh))
+                for i in range(npp):
+                    for j in range(nq):
+                        V_R[(offs[p] + i * npp + i, offs[q] + j * nq + j) + idx] += Vnn
+    if n_target is None:
+        n_target = float(n_o)
+    return {"name": "random3d_%s_%dx%dx%d_s%d" % (("-".join(map(str, site_norb)),) + mesh + (seed,)),
+            "mesh": mesh, "site_norb": list(site_norb), "H_R": H_R, "V_R": V_R,
+            "beta": float(beta), "omega_max": float(omega_max), "eps": float(eps),
+            "n_target": float(n_target)}
+
+
 def batch_sweep(count=64, seed=22223):
     """Seeded instances of uneven size for the batched runs.
 
@@ -240,4 +320,6 @@ def workload(name):
         return five_orbital(n=24, beta=50.0, omega_max=25.0, eps=1e-10)
     if name == "five_orbital_48":
         return five_orbital(n=48, beta=100.0, omega_max=25.0, eps=1e-10)
+    if name == "cubic_five_orbital_8":
+        return cubic_five_orbital(n=8, t=1.0, U=1.0, J=0.1, Vnn=0.2, beta=100.0, omega_max=25.0, eps=1e-10)
     raise KeyError(name)

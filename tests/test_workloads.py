@@ -42,3 +42,20 @@ def test_random_model_seeded():
     b = wl.random_model((4, 4), [2, 1], seed=3)
     assert np.array_equal(a["H_R"], b["H_R"]) and np.array_equal(a["V_R"], b["V_R"])
     assert a["V_R"].shape == (5, 5, 4, 4)
+
+
+def test_cubic_models():
+    w = wl.cubic_five_orbital(n=8)
+    assert w["H_R"].shape == (5, 5, 8, 8, 8) and w["V_R"].shape == (25, 25, 8, 8, 8)
+    assert w["n_target"] == 5.0 and w["beta"] == 100.0 and w["omega_max"] == 25.0
+    refl = lambda x: lattice.reflect(np.swapaxes(x, 0, 1), 3)
+    assert np.abs(w["H_R"] - np.conj(refl(w["H_R"]))).max() == 0.0
+    assert np.abs(w["V_R"] - refl(w["V_R"])).max() == 0.0
+    # band width 12 t of the simple cubic lattice
+    hk = np.moveaxis(np.fft.fftn(w["H_R"], axes=(-3, -2, -1)), (0, 1), (-2, -1))
+    ev = np.linalg.eigvalsh(hk)
+    assert abs((ev.max() - ev.min()) - 12.0) < 1e-12
+    r = wl.random_model_3d((4, 3, 2), [2, 1], seed=3)
+    assert r["H_R"].shape == (3, 3, 4, 3, 2) and r["V_R"].shape == (5, 5, 4, 3, 2)
+    assert np.abs(r["H_R"] - np.conj(refl(r["H_R"]))).max() < 1e-15
+    assert np.abs(r["V_R"] - refl(r["V_R"])).max() == 0.0
