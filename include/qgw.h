@@ -104,7 +104,7 @@ typedef struct qgw_plan_s *qgw_plan;
  * qgw_dlr_build (or any other node set of the same rank).  All host arrays
  * are read during qgw_plan_create only. */
 typedef struct {
-  int32_t n;                 /* mesh side: N_k = n * n                             */
+  int32_t n;                 /* mesh side: N_k = n * n (n^3 when dim is 3)        */
   int32_t n_sites;           /* basis sites per cell                               */
   const int32_t *site_norb;  /* [n_sites] orbitals per site                        */
   double beta;               /* inverse temperature (1/eV)                         */
@@ -115,6 +115,9 @@ typedef struct {
   const int64_t *n_b;        /* [r] bosonic nodes:   nu = 2 n pi / beta            */
   int32_t precision;         /* QGW_F64 or QGW_F32                                 */
   int32_t device;            /* HIP device ordinal                                 */
+  int32_t dim;               /* mesh dimension: 2 (n x n; 0 also means 2) or 3     */
+                             /* (simple cubic n x n x n, N_k = n^3, index          */
+                             /* (R1 n + R2) n + R3)                                */
 } qgw_plan_desc;
 
 /* ------------------------------------------------------------------ set-up */
@@ -134,7 +137,9 @@ qgw_status qgw_dlr_build(double lambda, double eps, int32_t max_rank,
  * FP64 on the host by LU solves (never an explicit inverse), uploads them,
  * builds FFT twiddles and allocates the plan's private device scratch.
  * Supported: n in {1,2,3,4,5,6,8,9,10,12,15,16,18,20,24,25,27,30,32,36,40,
- * 45,48}; N_b in {1,2,4,5,8,9,16,25}; 1 <= r <= 96. */
+ * 45,48} for a square mesh, n in {1,2,3,4,5,6,8,10,12} for a cubic one (the
+ * 8 x 8 x 8 mesh of the performance section); N_b in {1,2,4,5,8,9,16,25};
+ * 1 <= r <= 96.  Any other dim is QGW_ERR_INVALID_ARG. */
 qgw_status qgw_plan_create(const qgw_plan_desc *desc, qgw_plan *plan);
 qgw_status qgw_plan_destroy(qgw_plan plan);
 

@@ -67,6 +67,15 @@ struct qgw_state_s {
     }                                                                         \
   } while (0)
 
+// Makes the device current and clears the runtime's last-error state, which any
+// earlier HIP call of the process (the caller's included) may have left set, so
+// that the launchers' hipGetLastError reports their own launches only.
+static hipError_t enter_device(int dev) {
+  const hipError_t e = hipSetDevice(dev);
+  (void)hipGetLastError();
+  return e;
+}
+
 #define QGW_REQUIRE(cond, code, msg) \
   do {                               \
     if (!(cond)) {                   \
@@ -75,7 +84,17 @@ struct qgw_state_s {
     }                                \
   } while (0)
 
-static bool mesh_supported(int n) {
+static bool mesh_supported(int n, int dim) {
+  if (dim == 3) {
+    switch (n) {
+#define QGW_CASE(NN) case NN:
+      QGW_FOR_EACH_CUBE(QGW_CASE)
+#undef QGW_CASE
+      return true;
+      default:
+        return false;
+    }
+  }
   switch (n) {
 #define QGW_CASE(NN) case NN:
     QGW_FOR_EACH_MESH(QGW_CASE)
@@ -169,8 +188,12 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
   QGW_REQUIRE(d && out, QGW_ERR_INVALID_ARG, "qgw_plan_create: null argument");
   *out = nullptr;
   QGW_REQUIRE(d->n >= 1, QGW_ERR_INVALID_ARG, "qgw_plan_create: mesh side must be >= 1");
-  QGW_REQUIRE(mesh_supported(d->n), QGW_ERR_UNSUPPORTED,
-              "qgw_plan_create: mesh side " + std::to_string(d->n) + " has no compiled transform");
+  QGW_REQUIRE(d->dim == 0 || d->dim == 2 || d->dim == 3, QGW_ERR_INVALID_ARG,
+              "qgw_plan_create: mesh dimension must be 2 or 3 (0 means 2)");
+  const int dim = d->dim == 3 ? 3 : 2;
+  QGW_REQUIRE(mesh_supported(d->n, dim), QGW_ERR_UNSUPPORTED,
+              "qgw_plan_create: mesh side " + std::to_string(d->n) + " has no compiled " + std::to_string(dim) +
+                  "-D transform");
   QGW_REQUIRE(d->n_sites >= 1 && d->site_norb, QGW_ERR_INVALID_ARG, "qgw_plan_create: need n_sites >= 1 and site_norb");
   QGW_REQUIRE(d->beta > 0.0 && std::isfinite(d->beta), QGW_ERR_INVALID_ARG, "qgw_plan_create: beta must be positive");
   QGW_REQUIRE(d->rank >= 1 && d->rank <= kMaxRank, QGW_ERR_UNSUPPORTED, "qgw_plan_create: DLR rank must be in [1, 96]");
@@ -195,14 +218,15 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
     return QGW_ERR_DEVICE;
   }
   QGW_REQUIRE(d->device >= 0 && d->device < ndev, QGW_ERR_INVALID_ARG, "qgw_plan_create: bad device ordinal");
-  QGW_CHECK_HIP(hipSetDevice(d->device), "hipSetDevice");
+  QGW_CHECK_HIP(enter_device(d->device), "hipSetDevice");
 
   qgw_plan h = new (std::nothrow) qgw_plan_s;
   QGW_REQUIRE(h, QGW_ERR_ALLOC, "qgw_plan_create: out of host memory");
   Plan& p = h->p;
   p.device = d->device;
   p.n = d->n;
-  p.nk = d->n * d->n;
+  p.dim = dim;
+  p.nk = dim == 3 ? d->n * d->n * d->n : d->n * d->n;
   p.no = no;
   p.nb = nb;
   p.r = d->rank;
@@ -411,7 +435,7 @@ qgw_status qgw_plan_sizes(qgw_plan h, int32_t* rank, int32_t* n_o, int32_t* n_b,
 #define QGW_PLAN(h, name)                                                   \
   QGW_REQUIRE(h, QGW_ERR_INVALID_ARG, std::string(name) + ": null plan"); \
   const Plan& p = h->p;                                                     \
-  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice")
+  QGW_CHECK_HIP(enter_device(p.device), "hipSetDevice")
 
 qgw_status qgw_dlr_transform(qgw_plan h, int32_t map, int64_t ncols, double sre, double sim,
                              int32_t hermitian, const void* in, void* out, void* stream) {
@@ -789,7 +813,7 @@ qgw_status qgw_state_hf_solve(qgw_state st, double tol, int32_t max_iter, int32_
   QGW_REQUIRE(max_iter >= 0, QGW_ERR_INVALID_ARG, "qgw_state_hf_solve: negative max_iter");
   qgw_plan h = st->plan;
   const Plan& p = h->p;
-  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
+  QGW_CHECK_HIP(enter_device(p.device), "hipSetDevice");
   if (std::isnan(st->n_target))
     QGW_REQUIRE(std::isfinite(st->mu), QGW_ERR_INVALID_ARG, "qgw_state_hf_solve: fixed mu must be finite");
   const int64_t so_n = int64_t(p.no) * p.no * p.nk;
@@ -1018,7 +1042,7 @@ qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
   QGW_REQUIRE(st && mu, QGW_ERR_INVALID_ARG, "qgw_state_init_g0: null argument");
   const Plan& p = st->plan->p;
   st->mu_steps0 = 10;
-  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
+  QGW_CHECK_HIP(enter_device(p.device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   const size_t so = size_t(p.no) * p.no * p.nk * 16;
   const size_t fo = so * p.r;
@@ -1041,7 +1065,7 @@ qgw_status qgw_state_set_precision(qgw_state st, int32_t mode, double switch_tol
   QGW_REQUIRE(mode >= 0 && mode <= 2, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: mode must be 0, 1 or 2");
   QGW_REQUIRE(switch_tol > 0.0, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: switch_tol must be positive");
   if (mode != 0) {
-    QGW_CHECK_HIP(hipSetDevice(st->plan->p.device), "hipSetDevice");
+    QGW_CHECK_HIP(enter_device(st->plan->p.device), "hipSetDevice");
     QGW_CHECK_HIP(ensure_fp32(st), "qgw_state_set_precision: single-precision buffers");
   }
   st->prec_mode = mode;
@@ -1133,7 +1157,7 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
   QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_gw_iteration: null state");
   QGW_REQUIRE(n_iter >= 0, QGW_ERR_INVALID_ARG, "qgw_gw_iteration: negative n_iter");
   const Plan& p = st->plan->p;
-  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
+  QGW_CHECK_HIP(enter_device(p.device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   double dsig = NAN;
   int done = 0;
@@ -1211,7 +1235,7 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
     for (int j = 0; j < i; ++j)
       QGW_REQUIRE(states[j] != states[i], QGW_ERR_INVALID_ARG, "qgw_batch_create: a state appears twice");
   }
-  QGW_CHECK_HIP(hipSetDevice(dev), "hipSetDevice");
+  QGW_CHECK_HIP(enter_device(dev), "hipSetDevice");
   if (precision == 1)
     for (int i = 0; i < n; ++i) QGW_CHECK_HIP(ensure_fp32(states[i]), "qgw_batch_create: single-precision buffers");
   qgw_batch b = new (std::nothrow) qgw_batch_s;
@@ -1267,14 +1291,14 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
 
 qgw_status qgw_batch_launch(qgw_batch b, void* stream) {
   QGW_REQUIRE(b, QGW_ERR_INVALID_ARG, "qgw_batch_launch: null batch");
-  QGW_CHECK_HIP(hipSetDevice(b->device), "hipSetDevice");
+  QGW_CHECK_HIP(enter_device(b->device), "hipSetDevice");
   QGW_CHECK_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream), "qgw_batch_launch");
   return QGW_OK;
 }
 
 qgw_status qgw_batch_read(qgw_batch b, double* d_sigma, double* mu, int32_t* status, void* stream) {
   QGW_REQUIRE(b, QGW_ERR_INVALID_ARG, "qgw_batch_read: null batch");
-  QGW_CHECK_HIP(hipSetDevice(b->device), "hipSetDevice");
+  QGW_CHECK_HIP(enter_device(b->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   const size_t n = b->states.size();
   std::vector<double> ds(n), m(n);
@@ -1322,7 +1346,7 @@ qgw_status qgw_state_copy(qgw_state st, int32_t which, void* dst, int64_t* bytes
   }
   if (bytes) *bytes = int64_t(n);
   if (!dst) return QGW_OK;
-  QGW_CHECK_HIP(hipSetDevice(p.device), "hipSetDevice");
+  QGW_CHECK_HIP(enter_device(p.device), "hipSetDevice");
   QGW_CHECK_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, (hipStream_t)stream), "qgw_state_copy");
   return QGW_OK;
 }
@@ -1330,7 +1354,7 @@ qgw_status qgw_state_copy(qgw_state st, int32_t which, void* dst, int64_t* bytes
 qgw_status qgw_state_profile(qgw_state st, int32_t mode, double* ms, int32_t* iters) {
   QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_profile: null state");
   QGW_REQUIRE(mode >= 0 && mode <= 2, QGW_ERR_INVALID_ARG, "qgw_state_profile: bad mode");
-  QGW_CHECK_HIP(hipSetDevice(st->plan->p.device), "hipSetDevice");
+  QGW_CHECK_HIP(enter_device(st->plan->p.device), "hipSetDevice");
   if (mode == 1) {
     for (auto& e : st->ev)
       if (!e) QGW_CHECK_HIP(hipEventCreate(&e), "qgw_state_profile");

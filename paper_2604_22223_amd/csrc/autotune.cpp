@@ -78,7 +78,9 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
     return QGW_ERR_INVALID_ARG;
   }
   Plan& p = h->p;
-  if (hipSetDevice(p.device) != hipSuccess) {
+  const bool dev_ok = hipSetDevice(p.device) == hipSuccess;
+  (void)hipGetLastError();  // a stale error of an earlier call must not fail the trial launches
+  if (!dev_ok) {
     set_error("qgw_plan_autotune: hipSetDevice failed");
     return QGW_ERR_DEVICE;
   }
@@ -106,7 +108,7 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
     return QGW_ERR_DEVICE;
   }
   const int64_t no2 = int64_t(p.no) * p.no;
-  const int lane_cap = std::max(1, 256 / p.n);
+  const int lane_cap = std::max(1, 256 / lines_per_slab(p));
   std::vector<int> spb;
   for (int v = 1; v <= lane_cap; v *= 2) spb.push_back(v);
   if (spb.back() != lane_cap) spb.push_back(lane_cap);

@@ -237,6 +237,7 @@ hipError_t launch_row_map_bwd(const Plan& p, int64_t ncols, double sre, double s
 }
 
 hipError_t launch_sigma_bwd_wc(const Plan& p, const void* gt, const void* sbar, void* out, hipStream_t s) {
+  if (p.dim == 3) return launch_sigma_bwd_wc3(p, gt, sbar, out, s);
   switch (p.n) {
 #define QGW_CASE(NN) \
   case NN:           \
@@ -249,6 +250,7 @@ hipError_t launch_sigma_bwd_wc(const Plan& p, const void* gt, const void* sbar, 
 }
 
 hipError_t launch_contract_bwd(const Plan& p, int mode, const void* xq, const void* y, void* out, hipStream_t s) {
+  if (p.dim == 3) return launch_contract_bwd3(p, mode, xq, y, out, s);
   switch (p.n) {
 #define QGW_CASE(NN) \
   case NN:           \

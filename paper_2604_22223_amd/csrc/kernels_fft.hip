@@ -331,6 +331,7 @@ hipError_t sigma_n(const Plan& p, const void* gt, const void* wc, int in_q, int 
 
 hipError_t launch_lattice_fft(const Plan& p, int dir, int64_t batch, const void* in, void* out,
                               hipStream_t s) {
+  if (p.dim == 3) return launch_lattice_fft3(p, dir > 0 ? +1 : -1, dir > 0 ? 1.0 / double(p.nk) : 1.0, batch, in, out, s);
   switch (p.n) {
 #define QGW_CASE(NN) \
   case NN:           \
@@ -344,6 +345,7 @@ hipError_t launch_lattice_fft(const Plan& p, int dir, int64_t batch, const void*
 
 hipError_t launch_lattice_fft_scaled(const Plan& p, int sign, double out_scale, int64_t batch,
                                      const void* in, void* out, hipStream_t s) {
+  if (p.dim == 3) return launch_lattice_fft3(p, sign, out_scale, batch, in, out, s);
   switch (p.n) {
 #define QGW_CASE(NN)                                                                                   \
   case NN:                                                                                             \
@@ -358,6 +360,7 @@ hipError_t launch_lattice_fft_scaled(const Plan& p, int sign, double out_scale, 
 
 hipError_t launch_bubble(const Plan& p, const void* gt, const void* gr, int out_q, void* out,
                          hipStream_t s) {
+  if (p.dim == 3) return launch_bubble3(p, gt, gr, out_q, out, s);
   switch (p.n) {
 #define QGW_CASE(NN) \
   case NN:           \
@@ -371,6 +374,7 @@ hipError_t launch_bubble(const Plan& p, const void* gt, const void* gr, int out_
 
 hipError_t launch_sigma(const Plan& p, const void* gt, const void* wc, int in_q, int out_k,
                         void* sig, hipStream_t s) {
+  if (p.dim == 3) return launch_sigma3(p, gt, wc, in_q, out_k, sig, s);
   switch (p.n) {
 #define QGW_CASE(NN) \
   case NN:           \

@@ -15,6 +15,9 @@ namespace qgw {
 #define QGW_FOR_EACH_MESH(X) \
   X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48)
 
+// Sides of a cubic N x N x N mesh with a compiled 3-D transform.
+#define QGW_FOR_EACH_CUBE(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12)
+
 // Pair-basis sizes with a compiled Dyson-W solver.
 #define QGW_FOR_EACH_NB(X) X(1) X(2) X(4) X(5) X(8) X(9) X(16) X(25)
 
@@ -54,7 +57,7 @@ struct Tune {
 
 struct Plan {
   int device = 0;
-  int n = 0, nk = 0, no = 0, nb = 0, r = 0, prec = 0;
+  int n = 0, dim = 2, nk = 0, no = 0, nb = 0, r = 0, prec = 0;  // mesh side n, N_k = n^dim
   double beta = 0.0;
   std::vector<int> site_norb, pair_first, pair_second, orb_site, pair_of;  // pair_of[a*no+b] or -1
   std::vector<double> omega, tau_t;
@@ -154,6 +157,15 @@ hipError_t launch_sigma_bwd_wc(const Plan& p, const void* g_tau_r, const void* s
 // 2 bubble -> G(beta - tau)
 hipError_t launch_contract_bwd(const Plan& p, int mode, const void* x_pair, const void* y_orb,
                                void* out, hipStream_t s);
+// the same five steps on a cubic mesh (p.dim == 3); the 2-D launchers route to them
+hipError_t launch_lattice_fft3(const Plan& p, int sign, double out_scale, int64_t batch, const void* in, void* out,
+                               hipStream_t s);
+hipError_t launch_bubble3(const Plan& p, const void* gt, const void* gr, int out_q, void* out, hipStream_t s);
+hipError_t launch_sigma3(const Plan& p, const void* gt, const void* wc, int in_q, int out_k, void* sig, hipStream_t s);
+hipError_t launch_sigma_bwd_wc3(const Plan& p, const void* gt, const void* sbar, void* out, hipStream_t s);
+hipError_t launch_contract_bwd3(const Plan& p, int mode, const void* xq, const void* y, void* out, hipStream_t s);
+// threads per slab line set: n for a square mesh, n^2 for a cube
+inline int lines_per_slab(const Plan& p) { return p.dim == 3 ? p.n * p.n : p.n; }
 hipError_t launch_dyson_w_bwd(const Plan& p, const void* v_q, const void* p_nu, const void* wcbar,
                               void* pbar, void* vbar_partial, int chunks, hipStream_t s);
 hipError_t launch_sum_chunks(int64_t n, int chunks, const void* partial, void* out, hipStream_t s);

@@ -48,7 +48,7 @@ class PlanDesc(ctypes.Structure):
                 ("rank", ctypes.c_int32), ("omega", ctypes.POINTER(ctypes.c_double)),
                 ("tau_t", ctypes.POINTER(ctypes.c_double)), ("n_f", ctypes.POINTER(ctypes.c_int64)),
                 ("n_b", ctypes.POINTER(ctypes.c_int64)), ("precision", ctypes.c_int32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("dim", ctypes.c_int32)]
 
 
 _lib = None
@@ -152,9 +152,9 @@ def dlr_build(lam, eps, max_rank=96):
 
 
 class Plan:
-    """A libqgw plan: mesh n x n, sites/orbitals, DLR nodes, precision."""
+    """A libqgw plan: mesh n x n (or n x n x n with dim=3), sites/orbitals, DLR nodes, precision."""
 
-    def __init__(self, n, site_norb, beta, omega, tau_t, n_f, n_b, precision=F64, device=0):
+    def __init__(self, n, site_norb, beta, omega, tau_t, n_f, n_b, precision=F64, device=0, dim=2):
         self._keep = [np.ascontiguousarray(site_norb, dtype=np.int32),
                       np.ascontiguousarray(omega, dtype=np.float64),
                       np.ascontiguousarray(tau_t, dtype=np.float64),
@@ -165,7 +165,7 @@ class Plan:
                      len(om), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                      tt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                      nf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                     nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(precision), int(device))
+                     nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(precision), int(device), int(dim))
         h = ctypes.c_void_p()
         _check(lib().qgw_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
@@ -173,15 +173,16 @@ class Plan:
         _check(lib().qgw_plan_sizes(h, ctypes.byref(r), ctypes.byref(no), ctypes.byref(nbp), ctypes.byref(nk)))
         self.r, self.n_o, self.n_b, self.n_k = r.value, no.value, nbp.value, nk.value
         self.n = int(n)
+        self.dim = int(dim)
         self.beta = float(beta)
         self.precision = int(precision)
         self.device = int(device)
 
     @classmethod
-    def from_nodes(cls, n, site_norb, beta, nodes, precision=F64, device=0):
+    def from_nodes(cls, n, site_norb, beta, nodes, precision=F64, device=0, dim=2):
         """``nodes``: dict with omega (eV), tau_t, n_f, n_b."""
         return cls(n, site_norb, beta, nodes["omega"], nodes["tau_t"], nodes["n_f"], nodes["n_b"],
-                   precision, device)
+                   precision, device, dim)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

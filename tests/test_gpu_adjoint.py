@@ -47,8 +47,13 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
+# number of mesh axes of the current case (2, or 3 on a cubic mesh); set by the ``case`` fixture
+_MESH_DIM = [2]
+
+
 def flat(x):
-    return np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))
+    """oracle [..., n1, n2] (or [..., n1, n2, n3]) -> library [..., N_k]"""
+    return np.ascontiguousarray(x.reshape(x.shape[:-_MESH_DIM[0]] + (-1,)))
 
 
 def crand(rng, shape):
@@ -75,8 +80,9 @@ class Case:
         self.st0 = gw.initial_state(self.m, self.d)
         self.out = gw.gw_iteration(self.m, self.d, self.st0, keep=True)
         self.inter = self.out["intermediates"]
-        self.plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], self.d.nodes())
-        self.mesh = w["mesh"]
+        self.mesh = tuple(w["mesh"])
+        self.dim = len(self.mesh)
+        self.plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], self.d.nodes(), dim=self.dim)
 
 
 CASES = {
@@ -85,13 +91,17 @@ CASES = {
                                               U=0.7, J=0.1, Vnn=0.1),
     "five_orbital_6x6": lambda: wl.five_orbital(n=6, U=1.0, J=0.1, Vnn=0.2, beta=10.0, omega_max=20.0, eps=1e-10,
                                                 scale_mesh=6),
+    "random3d_2+1_4x4x4": lambda: wl.random_model_3d((4, 4, 4), [2, 1], seed=11, beta=8.0, omega_max=15.0,
+                                                     eps=1e-10, U=0.7, J=0.1, Vnn=0.1),
 }
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
     print("\n[adjoint case] %s" % request.param, flush=True)
-    return Case(CASES[request.param]())
+    c = Case(CASES[request.param]())
+    _MESH_DIM[0] = c.dim
+    return c
 
 
 def _rdot(a, b):
@@ -180,7 +190,7 @@ def test_dlr_pairs_and_fft_bwd(case):
     for direction, fn in [(qgw.K_TO_R, ad.R_from_k_adj), (qgw.R_TO_K, ad.k_from_R_adj)]:
         xx = dev(flat(yb))
         p.lattice_fft_bwd(direction, xx, xx)
-        assert rel_err(host(xx), flat(fn(yb))) < TOL
+        assert rel_err(host(xx), flat(fn(yb, case.dim))) < TOL
 
 
 def test_bubble_bwd(case):
@@ -191,7 +201,7 @@ def test_bubble_bwd(case):
     gt, gr = dev(flat(it["G_tau_R"])), dev(flat(it["G_reflt_R"]))
     a, b = torch.empty_like(gt), torch.empty_like(gr)
     p.bubble_bwd(gt, gr, dev(flat(pb)), a, b)
-    ra, rb = ad.bubble_adj(ad.k_from_R_adj(pb), it["G_tau_R"], it["G_reflt_R"], m.pairs)
+    ra, rb = ad.bubble_adj(ad.k_from_R_adj(pb, case.dim), it["G_tau_R"], it["G_reflt_R"], m.pairs)
     assert rel_err(host(a), flat(ra)) < TOL
     assert rel_err(host(b), flat(rb)) < TOL
 
@@ -204,9 +214,9 @@ def test_sigma_bwd(case):
     gt, wc = dev(flat(it["G_tau_R"])), dev(flat(it["Wc_tau_q"]))
     a, b = torch.empty_like(gt), torch.empty_like(wc)
     p.sigma_bwd(gt, wc, dev(flat(sb)), a, b, out_k=True)
-    ga, wr = ad.sigma_adj(ad.k_from_R_adj(sb), it["G_tau_R"], it["Wc_tau_R"], m.pairs)
+    ga, wr = ad.sigma_adj(ad.k_from_R_adj(sb, case.dim), it["G_tau_R"], it["Wc_tau_R"], m.pairs)
     assert rel_err(host(a), flat(ga)) < TOL
-    assert rel_err(host(b), flat(ad.R_from_k_adj(wr))) < TOL
+    assert rel_err(host(b), flat(ad.R_from_k_adj(wr, case.dim))) < TOL
 
 
 def test_dyson_w_bwd(case):
@@ -351,7 +361,7 @@ def test_gradient_against_gpu_finite_differences(case):
 
     def sym(shape):
         x = crand(rng, shape)
-        x = x + np.conj(np.swapaxes(lattice.reflect(x), 0, 1))
+        x = x + np.conj(np.swapaxes(lattice.reflect(x, case.dim), 0, 1))
         return x / np.linalg.norm(x)
 
     for name, x0, g in (("H", m.H_R, host(H_R.grad)), ("V", m.V_R, host(V_R.grad))):
@@ -392,7 +402,8 @@ def test_energy_and_its_adjoint(case):
 def test_adjoints_reject_fp32_plans(case):
     torch = _torch()
     d = case.d
-    p32 = qgw.Plan.from_nodes(case.mesh[0], case.w["site_norb"], d.beta, d.nodes(), precision=qgw.F32)
+    p32 = qgw.Plan.from_nodes(case.mesh[0], case.w["site_norb"], d.beta, d.nodes(), precision=qgw.F32,
+                              dim=case.dim)
     x = torch.zeros((d.r, case.m.n_o, case.m.n_o, case.m.n_k), dtype=torch.complex64, device="cuda:0")
     with pytest.raises(qgw.QGWError) as e:
         p32.dlr_transform_bwd(qgw.F_IW2TAU, x, x.clone())

@@ -24,6 +24,8 @@ CASES = {
     "five_orbital_10x10": lambda: wl.five_orbital(n=10, U=1.0, J=0.1, Vnn=0.2, beta=20.0, omega_max=25.0,
                                                   eps=1e-10, scale_mesh=10),
     "graphene_12": lambda: wl.graphene(n=12, U=3.0, beta=10.0, omega_max=100.0, eps=1e-8),
+    "random3d_2+1_4x4x4": lambda: wl.random_model_3d((4, 4, 4), [2, 1], seed=3, beta=10.0, omega_max=20.0,
+                                                     eps=1e-10, U=1.0, J=0.1, Vnn=0.2),
 }
 
 
@@ -33,8 +35,12 @@ def _torch():
     return torch
 
 
+# number of mesh axes of the current case (2, or 3 on a cubic mesh); set by the ``case`` fixture
+_MESH_DIM = [2]
+
+
 def flat(x):
-    return np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))
+    return np.ascontiguousarray(x.reshape(x.shape[:-_MESH_DIM[0]] + (-1,)))
 
 
 def dev(x):
@@ -51,7 +57,8 @@ class Case:
         self.w = w
         self.d = DLR(w["beta"], w["omega_max"], w["eps"])
         self.m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
-        self.plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], self.d.nodes())
+        self.dim = len(w["mesh"])
+        self.plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], self.d.nodes(), dim=self.dim)
         self.H_R, self.V_R = dev(w["H_R"]), dev(w["V_R"])
 
     def state(self, mixing=1.0):
@@ -61,7 +68,9 @@ class Case:
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
     print("\n[hf case] %s" % request.param, flush=True)
-    return Case(CASES[request.param]())
+    c = Case(CASES[request.param]())
+    _MESH_DIM[0] = c.dim
+    return c
 
 
 def test_hf_density(case):

@@ -49,11 +49,12 @@ class Case:
         self.st1 = gw.gw_iteration(self.m, self.d, self.st0, keep=True)
         self.inter = self.st1["intermediates"]
         self.n = w["mesh"][0]
-        self.plan = qgw.Plan.from_nodes(self.n, w["site_norb"], w["beta"], self.d.nodes())
+        self.dim = len(w["mesh"])
+        self.plan = qgw.Plan.from_nodes(self.n, w["site_norb"], w["beta"], self.d.nodes(), dim=self.dim)
 
     def flat(self, x):
-        """oracle [..., n1, n2] -> library [..., N_k]"""
-        return np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))
+        """oracle [..., n1, n2] (or [..., n1, n2, n3]) -> library [..., N_k]"""
+        return np.ascontiguousarray(x.reshape(x.shape[:-self.dim] + (-1,)))
 
 
 CASE_SPECS = {
@@ -64,6 +65,17 @@ CASE_SPECS = {
                                                   eps=1e-10, scale_mesh=10),
     # graphene G0W0 workload at its full size (12 x 12, r = 43)
     "graphene_g0w0_12": lambda: wl.workload("graphene_g0w0_12"),
+    # cubic meshes: 3 orbitals on two sites on 4 x 4 x 4, five orbitals on 6 x 6 x 6 (radix 3 and 2).
+    # The coupling is that of the five-orbital case above: with six neighbours the stronger default
+    # interaction pushes the plasmon of W^C beyond omega_max, where the DLR basis no longer holds it
+    # and two independently built maps differ by more than rounding.  The seeds give iterations that
+    # do not amplify rounding: a 1e-13 relative change of the incoming G changes Sigma after three
+    # iterations by less than 1e-12 in the oracle (some seeds amplify it a thousandfold, and then
+    # no two FP64 implementations agree to 1e-10 after the first iteration).
+    "random3d_2+1_4x4x4": lambda: wl.random_model_3d((4, 4, 4), [2, 1], seed=3, beta=10.0, omega_max=20.0,
+                                                     eps=1e-10, U=1.0, J=0.1, Vnn=0.2),
+    "random3d_5_6x6x6": lambda: wl.random_model_3d((6, 6, 6), [5], seed=12, beta=10.0, omega_max=25.0,
+                                                   eps=1e-10, U=1.0, J=0.1, Vnn=0.2),
 }
 
 
@@ -165,7 +177,7 @@ def test_a8_a9_a10_a11_self_energy(case):
     r, no, nk = case.d.r, case.m.n_o, case.m.n_k
     gt = dev(case.flat(case.inter["G_tau_R"]))
     sig = torch.empty((r, no, no, nk), dtype=torch.complex128, device="cuda:0")
-    raw_k = case.flat(lattice.k_from_R(case.inter["sig_tau_R"]))
+    raw_k = case.flat(lattice.k_from_R(case.inter["sig_tau_R"], case.dim))
     for in_q, win in [(True, case.inter["Wc_tau_q"]), (False, case.inter["Wc_tau_R"])]:
         w = dev(case.flat(win))
         case.plan.sigma(gt, w, sig, in_q=in_q, out_k=False)
@@ -224,6 +236,28 @@ def test_whole_iterations(case):
         assert rel_err(host(st.array(1)), case.flat(ref["sig_iw"])) < TOL
         assert rel_err(host(st.array(2)), case.flat(ref["sig_hf_k"])) < TOL
     st.close()
+
+
+def test_stale_runtime_error_is_not_reported():
+    """An error code that an earlier HIP call of the process left set (here a rejected hipSetDevice
+    ordinal, refused on the host) is not reported as the failure of the next library call."""
+    import ctypes
+    import os
+    torch = _torch()
+    w = wl.random_model((4, 4), [1], seed=1, beta=5.0, omega_max=10.0, eps=1e-8)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    p = qgw.Plan.from_nodes(4, [1], w["beta"], d.nodes())
+    # the HIP runtime already in the process (loaded by torch, used by the library): never a second copy
+    hip = ctypes.CDLL("libamdhip64.so.7", mode=os.RTLD_NOLOAD | os.RTLD_LAZY)
+    x = torch.ones((d.r, 1, 1, 16), dtype=torch.complex128, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    assert hip.hipSetDevice(ctypes.c_int(4096)) != 0       # leaves hipErrorInvalidDevice as the last error
+    p.lattice_fft(qgw.K_TO_R, x, y)                         # must not report it
+    assert hip.hipGetLastError() == 0                       # and the library cleared it
+    torch.cuda.synchronize()
+    assert abs(complex(y[0, 0, 0, 0]) - 1.0) < 1e-15 and abs(complex(y[0, 0, 0, 1])) < 1e-15
+    p.close()
 
 
 def test_nonfinite_detection():

@@ -25,6 +25,8 @@ CASES = {
     "five_orbital_10x10": lambda: wl.five_orbital(n=10, U=1.0, J=0.1, Vnn=0.2, beta=20.0, omega_max=25.0,
                                                   eps=1e-10, scale_mesh=10),
     "graphene_12": lambda: wl.graphene(n=12, U=3.0, beta=10.0, omega_max=100.0, eps=1e-8),
+    "random3d_2+1_4x4x4": lambda: wl.random_model_3d((4, 4, 4), [2, 1], seed=3, beta=10.0, omega_max=20.0,
+                                                     eps=1e-10, U=1.0, J=0.1, Vnn=0.2),
 }
 
 
@@ -34,8 +36,12 @@ def _torch():
     return torch
 
 
+# number of mesh axes of the current case (2, or 3 on a cubic mesh); set by the ``case`` fixture
+_MESH_DIM = [2]
+
+
 def flat(x):
-    return np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))
+    return np.ascontiguousarray(x.reshape(x.shape[:-_MESH_DIM[0]] + (-1,)))
 
 
 def dev(x):
@@ -53,13 +59,16 @@ class Case:
         self.d = DLR(w["beta"], w["omega_max"], w["eps"])
         self.m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
         self.st = gw.gw_iteration(self.m, self.d, gw.initial_state(self.m, self.d))
-        self.plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], self.d.nodes())
+        self.dim = len(w["mesh"])
+        self.plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], self.d.nodes(), dim=self.dim)
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
     print("\n[quasiparticle case] %s" % request.param, flush=True)
-    return Case(CASES[request.param]())
+    c = Case(CASES[request.param]())
+    _MESH_DIM[0] = c.dim
+    return c
 
 
 @pytest.mark.parametrize("mu_mode", ["printed", "fermi_level"])
@@ -89,8 +98,9 @@ def test_rejects_non_positive_z(case):
     """A self-energy whose slope makes Z^{-1} negative is reported, not returned as numbers."""
     st, m, d = case.st, case.m, case.d
     n_o = m.n_o
-    a = -5.0 * np.eye(n_o)[:, :, None, None] * np.ones(m.mesh)  # Z^{-1} = 1 + a / (w0^2 + e^2) < 0
-    bad = a[None] / (d.iw[:, None, None, None, None] - 0.01)
+    # Z^{-1} = 1 + a / (w0^2 + e^2) < 0
+    a = -5.0 * np.eye(n_o).reshape((n_o, n_o) + (1,) * case.dim) * np.ones(m.mesh)
+    bad = a[None] / (d.iw.reshape((-1,) + (1,) * a.ndim) - 0.01)
     with pytest.raises(qgw.QGWError) as e:
         case.plan.quasiparticle(dev(m.H_k), dev(st["sig_hf_k"]), dev(bad))
     assert e.value.status == 6
