@@ -17,7 +17,10 @@ chosen schedule's iterations/s.  Per-step durations come from HIP events the
 library records on the same stream inside the timed region.  One solve per
 schedule is also timed on its own (iterations and time to solution).  The
 oracle is timed on the host for one iteration of the same workload (the CPU
-baseline).
+baseline).  Further legs, reported beside the headline line: quasiparticle
+post-processing, the Hartree-Fock solve, the paper's own five-orbital
+benchmark on its 8 x 8 x 8 cubic mesh (per-iteration times grouped into the
+quantities of the paper's timing table), and the batched sweep.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -85,14 +88,15 @@ def step_model(r, n_o, n_b, n_k, prec="f64"):
 PEAK_TFLOPS = {"f64": FP64_PEAK_TFLOPS, "f32": FP32_PEAK_TFLOPS}
 
 # Measured HBM bytes per launch of the kernels that carry a step (rocprofv3 FETCH_SIZE and WRITE_SIZE runs of
-# `bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-calibration 256`, each counter scaled by what it reads
-# for a 256 MiB device copy: FETCH x 1.9997, WRITE x 1.0000; profiles/hbm_traffic_gw_iteration_five_orbital_24.md).
+# `bench.py --steps 3 --warmup 1 --no-cpu-baseline --batch 0 --paper-steps 0 --copy-calibration 256`, each
+# counter scaled by what it reads for a 256 MiB device copy: FETCH x 1.9997, WRITE x 1.0000;
+# profiles/hbm_traffic_gw_iteration_five_orbital_24.md).
 # Valid for the kernels as they were profiled; a changed kernel drops its entry until it is profiled again.
 MEASURED_TRAFFIC = {
-    "a3a4_bubble:f64": 501.1e6, "a5_dlr_p:f64": 671.8e6, "a6_dyson_w:f64": 629.3e6, "a7_dlr_w:f64": 921.9e6,
-    "a8a9a10_sigma:f64": 421.6e6,
-    "a3a4_bubble:f32": 232.2e6, "a5_dlr_p:f32": 348.1e6, "a6_dyson_w:f32": 315.1e6, "a7_dlr_w:f32": 481.8e6,
-    "a8a9a10_sigma:f32": 208.3e6,
+    "a3a4_bubble:f64": 331.7e6, "a5_dlr_p:f64": 671.8e6, "a6_dyson_w:f64": 629.3e6, "a7_dlr_w:f64": 921.9e6,
+    "a8a9a10_sigma:f64": 333.8e6,
+    "a3a4_bubble:f32": 166.2e6, "a5_dlr_p:f32": 348.2e6, "a6_dyson_w:f32": 315.0e6, "a7_dlr_w:f32": 481.7e6,
+    "a8a9a10_sigma:f32": 166.0e6,
 }
 FP64_STEPS = ("a12_density_hf", "a14_delta_mix", "a13_dyson_g")
 
@@ -201,6 +205,78 @@ def hf_leg(torch, qgw, plan, H_R, V_R, n_target, tol=1e-10, reps=3):
             "time_to_solution_s": round(el, 6), "passes_per_s": round(passes / el, 1)}
 
 
+# The paper's own timing of one GW iteration of its five-orbital benchmark (8 x 8 x 8 mesh, beta = 100,
+# Lambda = 25 eV), DLR + vectorised NumPy on an unstated CPU, seconds per iteration by quantity (table
+# tab:performance_5orb).  Context only: other hardware, unstated precision and DLR accuracy.
+PAPER_DLR_VEC_S = {"G": 2.21, "P": 137.55, "W": 65.48, "Sigma": 27.32}
+# the library's steps grouped into the table's four quantities
+PAPER_COLUMNS = {"G": ("a13_dyson_g", "a14_delta_mix"),
+                 "P": ("a1_dlr_g", "a2_fft_g", "a3a4_bubble", "a5_dlr_p"),
+                 "W": ("a6_dyson_w", "a7_dlr_w"),
+                 "Sigma": ("a12_density_hf", "a8a9a10_sigma", "a11_dlr_sigma")}
+
+
+def paper_workload_leg(torch, qgw, steps, tol, warmup=3, mixing=0.5):
+    """The paper's five-orbital benchmark model on its 8 x 8 x 8 cubic mesh (t = 1, U = 1, J = 0.1,
+    V = 0.2 eV, beta = 100/eV, omega_max = 25 eV, half filling; DLR eps = 1e-10): exactly ``steps``
+    iterations from G0 in each schedule (FP64 throughout; FP32 bulk steps then FP64), per-step times from
+    the library's HIP events grouped into the table's G, P, W and Sigma, and one solve to ``tol`` per
+    schedule (linear mixing ``mixing``: the undamped loop oscillates on this model)."""
+    from paper_2604_22223_amd import workloads as wl
+    w = wl.workload("cubic_five_orbital_8")
+    nodes = qgw.dlr_build(w["beta"] * w["omega_max"], w["eps"])
+    nodes["omega"] = nodes["x"] / w["beta"]
+    plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], nodes, dim=3)
+    flat = lambda x: torch.from_numpy(np.ascontiguousarray(x.reshape(x.shape[:2] + (-1,)))).to("cuda:0")
+    st = qgw.State(plan, flat(w["H_R"]), flat(w["V_R"]), n_target=w["n_target"], mixing=mixing)
+    res = {"workload": "cubic_five_orbital_8", "mesh": "8x8x8", "n_orb": plan.n_o, "n_pair": plan.n_b,
+           "beta": w["beta"], "omega_max": w["omega_max"], "dlr_eps": w["eps"], "dlr_rank": plan.r,
+           "t": 1.0, "U": 1.0, "J": 0.1, "V_nn": 0.2, "filling": w["n_target"], "mixing": mixing,
+           "paper_dlr_vec_s_per_iteration": dict(PAPER_DLR_VEC_S, total=round(sum(PAPER_DLR_VEC_S.values()), 2))}
+    for name, mode in (("fp64", 0), ("mixed", 1)):
+        st.set_precision(mode, SWITCH_TOL)
+        st.init_g0()
+        st.iterate(warmup)
+        st.init_g0()
+        torch.cuda.synchronize()
+        st.profile(1)
+        t0 = time.perf_counter()
+        done, _, _ = st.iterate(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = st.profile(0, per_precision=True)
+        entry = {"iterations": done, "ms_per_iteration": round(1e3 * el / max(done, 1), 4)}
+        for prec in ("f64", "f32"):
+            ms_tot, iters = prof[prec]
+            if iters == 0:
+                continue
+            cols = {c: round(sum(ms_tot[s] for s in ss) / iters, 4) for c, ss in PAPER_COLUMNS.items()}
+            entry["%s_ms_by_quantity" % prec] = cols
+            entry["%s_iterations" % prec] = iters
+        # one solve to the tolerance from G0
+        st.init_g0()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = []
+        for _ in range(200):
+            _, dsig, mu = st.iterate(1)
+            hist.append((dsig, st.info()[0]))
+            if dsig <= tol and hist[-1][1] == 0:
+                break
+        torch.cuda.synchronize()
+        entry["solve"] = {"iterations": len(hist), "fp32_iterations": sum(1 for _, p in hist if p == 1),
+                          "final_dsigma": hist[-1][0], "mu": mu,
+                          "time_to_solution_s": round(time.perf_counter() - t0, 5)}
+        res[name] = entry
+        log("[bench] cubic 8^3 %-5s: %.3f ms/iteration; solve %d iterations in %.4f s"
+            % (name, entry["ms_per_iteration"], len(hist), entry["solve"]["time_to_solution_s"]))
+    res["speedup_vs_paper_dlr_vec_fp64"] = round(sum(PAPER_DLR_VEC_S.values())
+                                                 / (1e-3 * res["fp64"]["ms_per_iteration"]), 1)
+    st.close()
+    plan.close()
+    return res
+
+
 def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
     """Seeded instances of uneven size (1-5 orbitals, 12^2-48^2 meshes, beta 10-100) advanced by one
     graph launch per iteration, FP64 and FP32 bulk steps, against the same states iterated one by one."""
@@ -271,6 +347,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, metavar="N",
                     help="instances of the batched leg (0 skips it)")
     ap.add_argument("--batch-launches", type=int, default=5)
+    ap.add_argument("--paper-steps", type=int, default=20, metavar="K",
+                    help="timed iterations of the paper's 8x8x8 five-orbital workload per schedule (0 skips it)")
     ap.add_argument("--batch-mu-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer three times (a plain copy kernel of known size "
@@ -372,6 +450,9 @@ def main():
     log("[bench] Hartree-Fock solve: %d passes to |dSigma_HF| = %.1e in %.4f s (%.0f passes/s)"
         % (hfl["passes"], hfl["final_dsigma_hf"], hfl["time_to_solution_s"], hfl["passes_per_s"]))
 
+    paper = None
+    if a.paper_steps > 0:
+        paper = paper_workload_leg(torch, qgw, a.paper_steps, a.tol)
     batch = batch_leg(torch, qgw, a.batch, a.batch_launches, 1, a.batch_mu_steps) if a.batch > 0 else None
 
     cpu = None
@@ -401,6 +482,7 @@ def main():
         "batch": batch,
         "quasiparticle": qpl,
         "hartree_fock": hfl,
+        "paper_workload": paper,
         "steps_detail": steps,
     }
     print(json.dumps(out), flush=True)

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_bubble3(const cpx<T>* __restrict__ gt, 
   using C = Cube<N>;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int64_t s0 = int64_t(blockIdx.x) * spb;
+  const int64_t s0 = xcd_block(blockIdx.x, gridDim.x) * spb;
   const int nloc = int(nslabs - s0 < spb ? nslabs - s0 : spb);
   const int sl = threadIdx.x / C::LINES, l = threadIdx.x - sl * C::LINES;
   const bool act = sl < nloc;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_sigma3(const cpx<T>* __restrict__ gt, c
   using C = Cube<N>;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int out_slab = blockIdx.x;  // (t * no + i) * no + k
+  const int out_slab = int(xcd_block(blockIdx.x, gridDim.x));  // (t * no + i) * no + k
   const int ik = out_slab % (no * no);
   const int64_t t = out_slab / (no * no);
   const int tb = term_off[ik], te = term_off[ik + 1];

@@ -116,6 +116,16 @@ struct MeshShape {
   static constexpr int SLAB = N * LD;  // LDS elements per slab
 };
 
+// Logical block of hardware block b in a grid of nb blocks.  The dispatcher deals
+// blocks round-robin to the eight XCDs (block b runs on XCD b mod 8), each with
+// its own L2; this bijection hands every XCD one contiguous range of logical
+// blocks instead, so blocks that read the same G slabs (neighbouring pair slabs,
+// or the outputs of one time node) share an L2 and those slabs leave HBM once.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t per = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 // Slab count per block: enough lines for a few waves, LDS-bounded.
 template <typename T>
 static inline int slabs_per_block(int n, int lds_budget) {
