@@ -21,6 +21,9 @@ hf       Hartree-Fock self-consistency (Fig. fig-self (a)): Fermi-function
 quasiparticle  static self-energy, renormalisation Z(k) (Eq. eq-z-factor) and
          the quasiparticle Hamiltonian and bands
          (Eq. eq-quasi-particle-Hamiltonian).
+mf       the same iteration on uniform Matsubara and imaginary-time grids
+         (the conventional representation the performance section compares
+         the DLR with).
 
 Every function is written for readability against the paper, not speed.
 """
