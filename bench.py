@@ -20,7 +20,9 @@ oracle is timed on the host for one iteration of the same workload (the CPU
 baseline).  Further legs, reported beside the headline line: quasiparticle
 post-processing, the Hartree-Fock solve, the paper's own five-orbital
 benchmark on its 8 x 8 x 8 cubic mesh (per-iteration times grouped into the
-quantities of the paper's timing table), and the batched sweep.
+quantities of the paper's timing table), both workloads on a uniform
+Matsubara grid of the same cutoff (the MF axis of the paper's table), and the
+batched sweep.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -277,6 +279,53 @@ def paper_workload_leg(torch, qgw, steps, tol, warmup=3, mixing=0.5):
     return res
 
 
+def mf_leg(torch, qgw, w, steps, tol, warmup=2, mixing=1.0, dlr_ms=None, name=""):
+    """The same workload on a uniform Matsubara grid reaching the same omega_max (qgw_plan_create_mf): exactly
+    ``steps`` FP64 iterations from G0 with per-step HIP events, and one solve to ``tol``; ``dlr_ms`` is the DLR
+    plan's FP64 ms per iteration on the workload, for the ratio."""
+    n_nodes = qgw.mf_nodes_for(w["beta"], w["omega_max"])
+    d = len(w["mesh"])
+    plan = qgw.Plan.uniform(w["mesh"][0], w["site_norb"], w["beta"], n_nodes, dim=d)
+    flat = lambda x: torch.from_numpy(np.ascontiguousarray(x.reshape(x.shape[:2] + (-1,)))).to("cuda:0")
+    st = qgw.State(plan, flat(w["H_R"]), flat(w["V_R"]), n_target=w["n_target"], mixing=mixing)
+    st.init_g0()
+    st.iterate(warmup)
+    st.init_g0()
+    torch.cuda.synchronize()
+    st.profile(1)
+    t0 = time.perf_counter()
+    done, _, _ = st.iterate(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_tot, iters = st.profile(0)
+    ms = 1e3 * el / max(done, 1)
+    res = {"workload": name, "nodes": n_nodes, "omega_max": w["omega_max"], "iterations": done,
+           "ms_per_iteration": round(ms, 4),
+           "ms_by_quantity": {c: round(sum(ms_tot[s] for s in ss) / max(iters, 1), 4) for c, ss in PAPER_COLUMNS.items()},
+           "pair_array_GB": round(n_nodes * plan.n_b ** 2 * plan.n_k * 16 / 1e9, 3)}
+    if dlr_ms:
+        res["dlr_ms_per_iteration"] = round(dlr_ms, 4)
+        res["mf_over_dlr"] = round(ms / dlr_ms, 2)
+    st.init_g0()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = []
+    for _ in range(200):
+        _, dsig, mu = st.iterate(1)
+        hist.append(dsig)
+        if dsig <= tol:
+            break
+    torch.cuda.synchronize()
+    res["solve"] = {"iterations": len(hist), "final_dsigma": hist[-1], "mu": mu, "mixing": mixing,
+                    "time_to_solution_s": round(time.perf_counter() - t0, 5)}
+    log("[bench] uniform grid %s: N = %d, %.3f ms/iteration (%s); solve %d iterations in %.4f s"
+        % (name, n_nodes, ms, ("%.1fx the DLR plan" % res["mf_over_dlr"]) if dlr_ms else "", len(hist),
+           res["solve"]["time_to_solution_s"]))
+    st.close()
+    plan.close()
+    return res
+
+
 def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
     """Seeded instances of uneven size (1-5 orbitals, 12^2-48^2 meshes, beta 10-100) advanced by one
     graph launch per iteration, FP64 and FP32 bulk steps, against the same states iterated one by one."""
@@ -347,6 +396,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, metavar="N",
                     help="instances of the batched leg (0 skips it)")
     ap.add_argument("--batch-launches", type=int, default=5)
+    ap.add_argument("--mf-steps", type=int, default=10, metavar="K",
+                    help="timed iterations of the uniform-Matsubara-grid plans (0 skips them)")
     ap.add_argument("--paper-steps", type=int, default=20, metavar="K",
                     help="timed iterations of the paper's 8x8x8 five-orbital workload per schedule (0 skips it)")
     ap.add_argument("--batch-mu-steps", type=int, default=20)
@@ -453,6 +504,14 @@ def main():
     paper = None
     if a.paper_steps > 0:
         paper = paper_workload_leg(torch, qgw, a.paper_steps, a.tol)
+    mf = None
+    if a.mf_steps > 0:
+        from paper_2604_22223_amd import workloads as wl
+        mf = [mf_leg(torch, qgw, w, a.mf_steps, a.tol, dlr_ms=1e3 * timed["fp64"]["elapsed"] / a.steps,
+                     name=WORKLOAD)]
+        if paper is not None:
+            mf.append(mf_leg(torch, qgw, wl.workload("cubic_five_orbital_8"), a.mf_steps, a.tol, mixing=0.5,
+                             dlr_ms=paper["fp64"]["ms_per_iteration"], name="cubic_five_orbital_8"))
     batch = batch_leg(torch, qgw, a.batch, a.batch_launches, 1, a.batch_mu_steps) if a.batch > 0 else None
 
     cpu = None
@@ -483,6 +542,7 @@ def main():
         "quasiparticle": qpl,
         "hartree_fock": hfl,
         "paper_workload": paper,
+        "uniform_grid": mf,
         "steps_detail": steps,
     }
     print(json.dumps(out), flush=True)

@@ -143,6 +143,43 @@ qgw_status qgw_dlr_build(double lambda, double eps, int32_t max_rank,
 qgw_status qgw_plan_create(const qgw_plan_desc *desc, qgw_plan *plan);
 qgw_status qgw_plan_destroy(qgw_plan plan);
 
+/* Uniform-grid plan: the same iteration on the conventional Matsubara grid
+ * that the performance section compares the DLR with (its "MF" rows).  The
+ * node axis holds n_nodes = N = 2M points: fermionic w_n = (2n + 1) pi / beta
+ * and bosonic nu_n = 2 n pi / beta for n = -M .. M-1 (index n + M), and
+ * midpoint times tau_j = (j + 1/2) beta / N (so beta - tau_j = tau_{N-1-j}).
+ * desc's mesh, sites, beta and device are used; rank and the node arrays are
+ * ignored and may be NULL; precision must be QGW_F64.  N must be one of
+ * {16, 32, 48, 64, 80, 96, 128, 160, 192, 200, 256, 320, 400, 512, 640, 800,
+ * 1024} (QGW_ERR_UNSUPPORTED otherwise); qgw_mf_nodes_for picks one.
+ *
+ * On such a plan the map calls apply the grid's transforms along the node
+ * axis (FFTs), in the same argument conventions:
+ *   QGW_F_IW2TAU   G(tau_j) = (1/beta) sum_n e^{-i w_n tau_j} G(i w_n)
+ *                  - delta_ab (t_j + 1/2), t_j the grid's own sum of the
+ *                  1/(i w_n) tail, whose exact transform is -1/2 (so the tail
+ *                  of the orbital diagonal is transformed exactly);
+ *   QGW_F_IW2TAUR  the same at beta - tau_j;
+ *   QGW_F_TAU2IW   (beta/N) sum_j e^{i w_n tau_j} X(tau_j) (midpoint rule);
+ *   QGW_B_TAU2IW   (beta/N) sum_j e^{i nu_n tau_j} X(tau_j);
+ *   QGW_B_IW2TAU   (1/beta) sum_n e^{-i nu_n tau_j} X(i nu_n);
+ *   QGW_F_IW2BETA  G(beta^-) = -(1/beta) sum_n G(i w_n) - delta_ab / 2.
+ * F_IW2TAU, F_IW2TAUR and F_IW2BETA take orbital arrays (ncols = n_o^2 N_k,
+ * QGW_ERR_DEVICE otherwise); the scale multiplies the whole affine result.
+ * qgw_dlr_transform_pairs with a layout change transposes into out and then
+ * transforms out in place (in is not modified).  Dyson G, the chemical
+ * potential (N_e = 2/N_k sum_k Re Tr n(k) with n as above), Hartree-Fock,
+ * bubble, Dyson W, Sigma, the composite iteration, the Hartree-Fock solve and
+ * qgw_quasiparticle (i pi / beta is node n = 0) work unchanged.  Not
+ * available on a uniform-grid plan (QGW_ERR_UNSUPPORTED): qgw_plan_get_map,
+ * the adjoint calls, qgw_energy / qgw_energy_bwd, the FP32 schedules of
+ * qgw_state_set_precision, batches and the autotuner. */
+qgw_status qgw_plan_create_mf(const qgw_plan_desc *desc, int32_t n_nodes, qgw_plan *plan);
+
+/* The smallest supported uniform-grid node count N with w_{M-1} >= omega_max
+ * (M = N / 2), or 0 if none is large enough or the arguments are not positive. */
+int32_t qgw_mf_nodes_for(double beta, double omega_max);
+
 /* Copies the FP64 r x r map (row-major, interleaved complex, r*r*2 doubles;
  * r*2 for QGW_F_IW2BETA) of ``map`` to host memory ``out``. */
 qgw_status qgw_plan_get_map(qgw_plan plan, int32_t map, double *out);

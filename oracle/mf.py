@@ -64,7 +64,7 @@ class MatsubaraGrid:
     @classmethod
     def for_cutoff(cls, beta, omega_max, sizes=None):
         """The smallest grid (from ``sizes`` if given) whose last fermionic frequency reaches omega_max."""
-        m = max(1, math.ceil(omega_max * beta / (2.0 * math.pi) - 0.5))
+        m = max(1, math.ceil(omega_max * beta / (2.0 * math.pi) + 0.5))      # (2M - 1) pi / beta >= omega_max
         n = 2 * m
         if sizes is not None:
             n = min(s for s in sizes if s >= n)

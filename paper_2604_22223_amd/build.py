@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqgw.so")
 
 SOURCES = ["api.cpp", "dlr_host.cpp", "kernels_fft.hip", "kernels_dlr.hip", "kernels_dyson.hip",
-           "kernels_misc.hip", "kernels_bwd.hip", "kernels_qp.hip", "kernels_hf.hip", "kernels_fft3.hip",
+           "kernels_misc.hip", "kernels_bwd.hip", "kernels_qp.hip", "kernels_hf.hip", "kernels_fft3.hip", "kernels_mf.hip",
            "autotune.cpp"]
 
 ARCH = os.environ.get("QGW_OFFLOAD_ARCH", "gfx950")

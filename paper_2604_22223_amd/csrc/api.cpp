@@ -124,7 +124,7 @@ static void free_plan_device(Plan& p) {
     p.dmaps64.m[m] = p.dmaps32.m[m] = nullptr;
   }
   void* ptrs[] = {p.d_tw64, p.d_tw32, p.d_pairs, p.terms.d_terms, p.terms.d_off, p.terms_lj.d_terms,
-                  p.terms_lj.d_off, p.d_wn, p.d_qp_row, p.d_partials, p.d_status, p.d_scalars, p.d_ws};
+                  p.terms_lj.d_off, p.d_wn, p.d_qp_row, p.d_partials, p.d_status, p.d_scalars, p.d_ws, p.d_mf};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   p.d_tw64 = nullptr;
@@ -139,6 +139,61 @@ static void free_plan_device(Plan& p) {
   p.d_partials = nullptr;
   p.d_status = nullptr;
   p.d_scalars = nullptr;
+  p.d_mf = nullptr;
+}
+
+// e^{i pi q / den} with q reduced exactly modulo 2 den first
+static zd cis_pi(int64_t q, int64_t den) {
+  const int64_t per = 2 * den;
+  q %= per;
+  if (q < 0) q += per;
+  const long double a = 3.141592653589793238462643383279502884L * (long double)q / (long double)den;
+  return mk(double(cosl(a)), double(sinl(a)));
+}
+
+// Tables of the uniform-grid transforms (kernels_mf.hip), N = 2M nodes, fermionic w_m = (2m - N + 1) pi / beta,
+// bosonic nu_m = (2m - N) pi / beta, tau_j = (j + 1/2) beta / N.  Each transform is
+// out_k = post_k sum_j e^{s 2 pi i j k / N} pre_j in_j, from
+//   w_m tau_j = 2 pi m j / N + pi m / N + pi (1 - N)(2j + 1) / (2N),   nu_m tau_j = 2 pi m j / N + pi m / N - pi (j + 1/2).
+// Layout: e^{-2 pi i e / N} (N), the same for N1 and N2, then pre / post of iw -> tau (fermionic), tau -> iw
+// (fermionic), tau -> i nu, i nu -> tau (N each), then the orbital-diagonal constant of iw -> tau,
+// -(t_j + 1/2) with t_j = (1/beta) sum_m e^{-i w_m tau_j} / (i w_m) (the grid's sum of the 1/(iw) tail, whose
+// exact transform is -1/2).
+static std::vector<zd> mf_tables_host(int N, int n1, int n2, double beta) {
+  std::vector<zd> t;
+  t.reserve(size_t(10) * N + n1 + n2);
+  for (int e = 0; e < N; ++e) t.push_back(cis_pi(-2 * e, N));
+  for (int e = 0; e < n1; ++e) t.push_back(cis_pi(-2 * e, n1));
+  for (int e = 0; e < n2; ++e) t.push_back(cis_pi(-2 * e, n2));
+  const double ib = 1.0 / beta, bn = beta / double(N);
+  auto push = [&](zd v, double s) { t.push_back(mk(v.re * s, v.im * s)); };
+  // fermionic iw -> tau
+  for (int m = 0; m < N; ++m) push(cis_pi(-m, N), ib);
+  for (int j = 0; j < N; ++j) push(cis_pi(-int64_t(1 - N) * (2 * j + 1), 2 * int64_t(N)), 1.0);
+  // fermionic tau -> iw
+  for (int j = 0; j < N; ++j) push(cis_pi(int64_t(1 - N) * (2 * j + 1), 2 * int64_t(N)), bn);
+  for (int m = 0; m < N; ++m) push(cis_pi(m, N), 1.0);
+  // bosonic tau -> i nu
+  for (int j = 0; j < N; ++j) push(cis_pi(-(2 * j + 1), 2), bn);
+  for (int m = 0; m < N; ++m) push(cis_pi(m, N), 1.0);
+  // bosonic i nu -> tau
+  for (int m = 0; m < N; ++m) push(cis_pi(-m, N), ib);
+  for (int j = 0; j < N; ++j) push(cis_pi(2 * j + 1, 2), 1.0);
+  // orbital-diagonal constant of fermionic iw -> tau
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int j = 0; j < N; ++j) {
+    long double sr = 0.0L, si = 0.0L;
+    for (int m = 0; m < N; ++m) {
+      const int64_t k = 2 * int64_t(m) - N + 1;          // w_m = k pi / beta
+      const zd e = cis_pi(-k * (2 * j + 1), 2 * int64_t(N));  // e^{-i w_m tau_j}
+      // e / (i w_m) = -i e beta / (k pi); the 1/beta prefactor cancels beta
+      const long double c = 1.0L / ((long double)k * pi);
+      sr += (long double)e.im * c;
+      si -= (long double)e.re * c;
+    }
+    t.push_back(mk(-double(sr + 0.5L), -double(si)));
+  }
+  return t;
 }
 
 template <typename V>
@@ -184,7 +239,8 @@ qgw_status qgw_dlr_build(double lambda, double eps, int32_t max_rank, double* x,
   return QGW_OK;
 }
 
-qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
+// mf_nodes == 0: DLR plan from the descriptor's node set; mf_nodes = N > 0: uniform Matsubara grid of N nodes
+static qgw_status plan_create_impl(const qgw_plan_desc* d, int mf_nodes, qgw_plan* out) {
   QGW_REQUIRE(d && out, QGW_ERR_INVALID_ARG, "qgw_plan_create: null argument");
   *out = nullptr;
   QGW_REQUIRE(d->n >= 1, QGW_ERR_INVALID_ARG, "qgw_plan_create: mesh side must be >= 1");
@@ -196,9 +252,16 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
                   "-D transform");
   QGW_REQUIRE(d->n_sites >= 1 && d->site_norb, QGW_ERR_INVALID_ARG, "qgw_plan_create: need n_sites >= 1 and site_norb");
   QGW_REQUIRE(d->beta > 0.0 && std::isfinite(d->beta), QGW_ERR_INVALID_ARG, "qgw_plan_create: beta must be positive");
-  QGW_REQUIRE(d->rank >= 1 && d->rank <= kMaxRank, QGW_ERR_UNSUPPORTED, "qgw_plan_create: DLR rank must be in [1, 96]");
-  QGW_REQUIRE(d->omega && d->tau_t && d->n_f && d->n_b, QGW_ERR_INVALID_ARG, "qgw_plan_create: null DLR node array");
-  QGW_REQUIRE(d->precision == QGW_F64 || d->precision == QGW_F32, QGW_ERR_INVALID_ARG, "qgw_plan_create: bad precision");
+  int mf_n1 = 0, mf_n2 = 0;
+  if (mf_nodes == 0) {
+    QGW_REQUIRE(d->rank >= 1 && d->rank <= kMaxRank, QGW_ERR_UNSUPPORTED, "qgw_plan_create: DLR rank must be in [1, 96]");
+    QGW_REQUIRE(d->omega && d->tau_t && d->n_f && d->n_b, QGW_ERR_INVALID_ARG, "qgw_plan_create: null DLR node array");
+    QGW_REQUIRE(d->precision == QGW_F64 || d->precision == QGW_F32, QGW_ERR_INVALID_ARG, "qgw_plan_create: bad precision");
+  } else {
+    QGW_REQUIRE(mf_grid_split(mf_nodes, &mf_n1, &mf_n2), QGW_ERR_UNSUPPORTED,
+                "qgw_plan_create_mf: " + std::to_string(mf_nodes) + " nodes have no compiled transform");
+    QGW_REQUIRE(d->precision == QGW_F64, QGW_ERR_UNSUPPORTED, "qgw_plan_create_mf: the uniform grid runs in FP64");
+  }
   int no = 0, nb = 0;
   for (int s = 0; s < d->n_sites; ++s) {
     QGW_REQUIRE(d->site_norb[s] >= 1, QGW_ERR_INVALID_ARG, "qgw_plan_create: site with no orbitals");
@@ -208,7 +271,7 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
   QGW_REQUIRE(no <= 8, QGW_ERR_UNSUPPORTED, "qgw_plan_create: at most 8 orbitals per cell");
   QGW_REQUIRE(nb_supported(nb), QGW_ERR_UNSUPPORTED,
               "qgw_plan_create: pair basis size " + std::to_string(nb) + " has no compiled Dyson-W solver");
-  for (int i = 0; i < d->rank; ++i) {
+  for (int i = 0; mf_nodes == 0 && i < d->rank; ++i) {
     QGW_REQUIRE(d->tau_t[i] > 0.0 && d->tau_t[i] < 1.0, QGW_ERR_INVALID_ARG, "qgw_plan_create: tau_t must lie in (0, 1)");
     QGW_REQUIRE(std::isfinite(d->omega[i]), QGW_ERR_INVALID_ARG, "qgw_plan_create: non-finite omega");
   }
@@ -229,14 +292,29 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
   p.nk = dim == 3 ? d->n * d->n * d->n : d->n * d->n;
   p.no = no;
   p.nb = nb;
-  p.r = d->rank;
   p.prec = d->precision;
   p.beta = d->beta;
   p.site_norb.assign(d->site_norb, d->site_norb + d->n_sites);
-  p.omega.assign(d->omega, d->omega + p.r);
-  p.tau_t.assign(d->tau_t, d->tau_t + p.r);
-  p.n_f.assign(d->n_f, d->n_f + p.r);
-  p.n_b.assign(d->n_b, d->n_b + p.r);
+  if (mf_nodes == 0) {
+    p.r = d->rank;
+    p.omega.assign(d->omega, d->omega + p.r);
+    p.tau_t.assign(d->tau_t, d->tau_t + p.r);
+    p.n_f.assign(d->n_f, d->n_f + p.r);
+    p.n_b.assign(d->n_b, d->n_b + p.r);
+  } else {
+    // n = -M .. M-1 for both statistics, midpoint times; no real-frequency nodes
+    p.grid = kGridMF;
+    p.r = mf_nodes;
+    p.mf_n1 = mf_n1;
+    p.mf_n2 = mf_n2;
+    p.ne_offset = double(no);
+    p.omega.assign(p.r, 0.0);
+    for (int j = 0; j < p.r; ++j) {
+      p.tau_t.push_back((j + 0.5) / double(p.r));
+      p.n_f.push_back(j - p.r / 2);
+      p.n_b.push_back(j - p.r / 2);
+    }
+  }
   // orbital / pair bookkeeping
   p.pair_of.assign(size_t(no) * no, -1);
   int off = 0, al = 0;
@@ -295,7 +373,10 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
   p.terms_lj.max_terms = max_lj;
   // DLR maps (FP64, host)
   std::string err;
-  if (!dlr_maps_host(p.beta, p.omega, p.tau_t, p.n_f, p.n_b, p.maps, err)) {
+  if (p.grid == kGridMF) {
+    // the density row only: G(beta^-) = -(1/beta) sum_m G(i w_m) - 1/2 on the orbital diagonal
+    p.maps[QGW_F_IW2BETA].assign(p.r, std::complex<double>(-1.0 / p.beta, 0.0));
+  } else if (!dlr_maps_host(p.beta, p.omega, p.tau_t, p.n_f, p.n_b, p.maps, err)) {
     delete h;
     set_error("qgw_plan_create: " + err);
     return QGW_ERR_INVALID_ARG;
@@ -320,6 +401,7 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
   {
     const int rp = p.dmaps64.rows_padded;
     for (int m = 0; m < kNumMaps && e == hipSuccess; ++m) {
+      if (p.grid == kGridMF && m != QGW_F_IW2BETA) continue;
       const int rows = (m == 5) ? 1 : p.r;
       std::vector<zd> h64(size_t(rp) * p.r, mk(0.0, 0.0));
       std::vector<zf> h32(size_t(rp) * p.r, mk(0.0f, 0.0f));
@@ -333,7 +415,7 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
       if (e == hipSuccess) e = upload(&p.dmaps32.m[m], h32.data(), h32.size() * sizeof(zf));
     }
     // adjoint maps T^H of the square maps (FP64 only: the adjoint calls run in FP64)
-    for (int m = 0; m < kNumMaps && e == hipSuccess; ++m) {
+    for (int m = 0; m < kNumMaps && e == hipSuccess && p.grid == kGridDLR; ++m) {
       if (m == QGW_F_IW2BETA) continue;
       std::vector<zd> h64(size_t(rp) * p.r, mk(0.0, 0.0));
       for (int i = 0; i < p.r; ++i)
@@ -373,7 +455,17 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
     for (int m = 0; m < p.r; ++m) wn[m] = (2.0 * double(p.n_f[m]) + 1.0) * 3.14159265358979323846 / p.beta;
     e = upload((void**)&p.d_wn, wn.data(), wn.size() * sizeof(double));
   }
-  if (e == hipSuccess) {
+  if (e == hipSuccess && p.grid == kGridMF) {
+    // i pi / beta is the grid's node n = 0 (index M)
+    std::vector<zd> hr(p.r, mk(0.0, 0.0));
+    hr[p.r / 2] = mk(1.0, 0.0);
+    e = upload((void**)&p.d_qp_row, hr.data(), hr.size() * sizeof(zd));
+    if (e == hipSuccess) {
+      const std::vector<zd> tab = mf_tables_host(p.r, p.mf_n1, p.mf_n2, p.beta);
+      e = upload((void**)&p.d_mf, tab.data(), tab.size() * sizeof(zd));
+    }
+  }
+  if (e == hipSuccess && p.grid == kGridDLR) {
     std::vector<std::complex<double>> row;
     std::string rerr;
     if (!dlr_qp_row_host(p.beta, p.omega, p.n_f, row, rerr)) {
@@ -402,6 +494,25 @@ qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) {
   return QGW_OK;
 }
 
+qgw_status qgw_plan_create(const qgw_plan_desc* d, qgw_plan* out) { return plan_create_impl(d, 0, out); }
+
+qgw_status qgw_plan_create_mf(const qgw_plan_desc* d, int32_t n_nodes, qgw_plan* out) {
+  QGW_REQUIRE(n_nodes > 0, QGW_ERR_INVALID_ARG, "qgw_plan_create_mf: the node count must be positive");
+  return plan_create_impl(d, n_nodes, out);
+}
+
+int32_t qgw_mf_nodes_for(double beta, double omega_max) {
+  if (!(beta > 0.0) || !(omega_max > 0.0) || !std::isfinite(beta * omega_max)) return 0;
+  const double m = std::ceil(omega_max * beta / (2.0 * 3.14159265358979323846) + 0.5);  // (2M - 1) pi / beta >= omega_max
+  const int need = 2 * int(m < 1.0 ? 1.0 : m);
+  int best = 0;
+#define QGW_CASE(NN, A, B) \
+  if (NN >= need && (best == 0 || NN < best)) best = NN;
+  QGW_FOR_EACH_MF_GRID(QGW_CASE)
+#undef QGW_CASE
+  return best;
+}
+
 qgw_status qgw_plan_destroy(qgw_plan h) {
   if (!h) return QGW_OK;
   (void)hipSetDevice(h->p.device);
@@ -412,6 +523,7 @@ qgw_status qgw_plan_destroy(qgw_plan h) {
 
 qgw_status qgw_plan_get_map(qgw_plan h, int32_t map, double* out) {
   QGW_REQUIRE(h && out, QGW_ERR_INVALID_ARG, "qgw_plan_get_map: null argument");
+  QGW_REQUIRE(h->p.grid == kGridDLR, QGW_ERR_UNSUPPORTED, "qgw_plan_get_map: a uniform-grid plan holds no dense maps");
   QGW_REQUIRE(map >= 0 && map < kNumMaps, QGW_ERR_INVALID_ARG, "qgw_plan_get_map: bad map");
   const auto& v = h->p.maps[map];
   for (size_t i = 0; i < v.size(); ++i) {
@@ -598,7 +710,8 @@ static hipError_t ensure_ws(Plan& p, size_t bytes) {
 
 #define QGW_BWD_PLAN(h, name)                                                                        \
   QGW_PLAN(h, name);                                                                                 \
-  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, std::string(name) + ": adjoints need an FP64 plan")
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, std::string(name) + ": adjoints need an FP64 plan"); \
+  QGW_REQUIRE(p.grid == kGridDLR, QGW_ERR_UNSUPPORTED, std::string(name) + ": adjoints need a DLR plan")
 
 qgw_status qgw_dlr_transform_bwd(qgw_plan h, int32_t map, int64_t ncols, double sre, double sim,
                                  int32_t hermitian, const void* ybar, void* xbar, void* stream) {
@@ -1064,6 +1177,8 @@ qgw_status qgw_state_set_precision(qgw_state st, int32_t mode, double switch_tol
   QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: null state");
   QGW_REQUIRE(mode >= 0 && mode <= 2, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: mode must be 0, 1 or 2");
   QGW_REQUIRE(switch_tol > 0.0, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: switch_tol must be positive");
+  QGW_REQUIRE(mode == 0 || st->plan->p.grid == kGridDLR, QGW_ERR_UNSUPPORTED,
+              "qgw_state_set_precision: a uniform-grid plan runs in FP64 only");
   if (mode != 0) {
     QGW_CHECK_HIP(enter_device(st->plan->p.device), "hipSetDevice");
     QGW_CHECK_HIP(ensure_fp32(st), "qgw_state_set_precision: single-precision buffers");
@@ -1101,8 +1216,12 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
   run(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, s));
   if (!f32) {
     mark(1);  // a1
-    run(launch_dlr(p, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G_iw, st->G_tau, s));
-    run(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s));
+    if (p.grid == kGridMF) {
+      run(launch_mf_g_tau(p, st->G_iw, st->G_tau, st->G_reflt, s));  // one transform, both time orders
+    } else {
+      run(launch_dlr(p, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G_iw, st->G_tau, s));
+      run(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s));
+    }
     mark(2);  // a2
     run(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, s));
     run(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_reflt, st->G_reflt, s));
@@ -1232,6 +1351,7 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
     QGW_REQUIRE(states[i], QGW_ERR_INVALID_ARG, "qgw_batch_create: null state");
     QGW_REQUIRE(states[i]->plan->p.device == dev, QGW_ERR_INVALID_ARG, "qgw_batch_create: states on different devices");
     QGW_REQUIRE(!states[i]->prof, QGW_ERR_INVALID_ARG, "qgw_batch_create: disable profiling first");
+    QGW_REQUIRE(states[i]->plan->p.grid == kGridDLR, QGW_ERR_UNSUPPORTED, "qgw_batch_create: DLR plans only");
     for (int j = 0; j < i; ++j)
       QGW_REQUIRE(states[j] != states[i], QGW_ERR_INVALID_ARG, "qgw_batch_create: a state appears twice");
   }

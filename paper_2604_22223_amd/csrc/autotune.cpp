@@ -78,6 +78,10 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
     return QGW_ERR_INVALID_ARG;
   }
   Plan& p = h->p;
+  if (p.grid != kGridDLR) {
+    set_error("qgw_plan_autotune: DLR plans only");
+    return QGW_ERR_UNSUPPORTED;
+  }
   const bool dev_ok = hipSetDevice(p.device) == hipSuccess;
   (void)hipGetLastError();  // a stale error of an earlier call must not fail the trial launches
   if (!dev_ok) {

@@ -523,8 +523,31 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
 
 }  // namespace
 
+hipError_t launch_row_map(const Plan& p, int64_t ncols, double sre, double sim, int herm, const void* in, void* out,
+                          hipStream_t s) {
+  const int64_t ng = int64_t(p.no) * p.no * p.nk;
+  if (herm && ncols != ng) return hipErrorInvalidValue;
+  if (ncols <= 0) return hipSuccess;
+  const unsigned blocks = unsigned((ncols + 63) / 64);
+#define QGW_ROW(T, H)                                                                                     \
+  hipLaunchKernelGGL((k_dlr_row<T, H>), dim3(blocks), dim3(256), 0, s, (const cpx<T>*)in, (cpx<T>*)out, \
+                     map_ptr<T>(p, 5), p.r, ncols, p.no, p.nk, T(sre), T(sim))
+  if (p.prec == 0) {
+    if (herm == 0) QGW_ROW(double, 0);
+    else if (herm == 1) QGW_ROW(double, 1);
+    else QGW_ROW(double, 2);
+  } else {
+    if (herm == 0) QGW_ROW(float, 0);
+    else if (herm == 1) QGW_ROW(float, 1);
+    else QGW_ROW(float, 2);
+  }
+#undef QGW_ROW
+  return hipGetLastError();
+}
+
 hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double sim, const void* in,
                       void* out, hipStream_t s, int herm) {
+  if (p.grid == kGridMF) return launch_mf(p, map, ncols, sre, sim, in, out, s, herm);
   const int64_t ng = int64_t(p.no) * p.no * p.nk;
   if (p.r <= 64 && map != 5 && herm != 2 && (herm == 0 || ncols == ng) && p.tune.orb_valu != 1) {
     const int na = herm ? p.no * p.no : 1;
@@ -537,25 +560,7 @@ hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double 
     if (herm) return dlr_mfma_launch<float, kPlain, true>(p, map, na, nq, sre, sim, in, out, s);
     return dlr_mfma_launch<float, kPlain, false>(p, map, na, nq, sre, sim, in, out, s);
   }
-  if (map == 5) {  // one output row
-    if (herm && ncols != ng) return hipErrorInvalidValue;
-    if (ncols <= 0) return hipSuccess;
-    const unsigned blocks = unsigned((ncols + 63) / 64);
-#define QGW_ROW(T, H)                                                                                     \
-  hipLaunchKernelGGL((k_dlr_row<T, H>), dim3(blocks), dim3(256), 0, s, (const cpx<T>*)in, (cpx<T>*)out, \
-                     map_ptr<T>(p, 5), p.r, ncols, p.no, p.nk, T(sre), T(sim))
-    if (p.prec == 0) {
-      if (herm == 0) QGW_ROW(double, 0);
-      else if (herm == 1) QGW_ROW(double, 1);
-      else QGW_ROW(double, 2);
-    } else {
-      if (herm == 0) QGW_ROW(float, 0);
-      else if (herm == 1) QGW_ROW(float, 1);
-      else QGW_ROW(float, 2);
-    }
-#undef QGW_ROW
-    return hipGetLastError();
-  }
+  if (map == 5) return launch_row_map(p, ncols, sre, sim, herm, in, out, s);  // one output row
   if (herm) {
     if (ncols != int64_t(p.no) * p.no * p.nk) return hipErrorInvalidValue;
     if (p.prec == 0) {
@@ -571,6 +576,7 @@ hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double 
 
 hipError_t launch_dlr_pairs(const Plan& p, int map, int in_layout, int out_layout, const void* in,
                             void* out, hipStream_t s) {
+  if (p.grid == kGridMF) return launch_mf_pairs(p, map, in_layout, out_layout, in, out, s);
   const int na = p.nb * p.nb, nq = p.nk;
   const int64_t ncols = int64_t(na) * nq;
   int mode = kPlain;

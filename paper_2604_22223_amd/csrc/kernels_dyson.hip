@@ -473,6 +473,7 @@ struct DysonGArgs {
   const double* extra;  // optional scalar copied to scal[9] by the final pass
   int r, nk, mode, max_evals;
   double beta, tol_mu, tol_n;
+  double ne_offset;   // added to -(2/N_k) sum Re rho_m Tr G_m (the uniform grid's 1/2 per spin-orbital)
 };
 
 template <int NO>
@@ -612,7 +613,7 @@ __global__ __launch_bounds__(64) void k_dg_newton(DysonGArgs A, int nblk) {
   s = wave_sum(s);
   sd = wave_sum(sd);
   if (threadIdx.x != 0) return;
-  const double ne = -2.0 * s / double(A.nk), dne = 2.0 * sd / double(A.nk);
+  const double ne = -2.0 * s / double(A.nk) + A.ne_offset, dne = 2.0 * sd / double(A.nk);
   double mu = A.scal[0], lo = A.scal[4], hi = A.scal[5], cap = A.scal[6];
   const double nt = A.scal[1];
   const double f = ne - nt;
@@ -950,6 +951,7 @@ DysonGArgs dyson_g_args(const Plan& p, const void* h_k, const void* sig_iw, int 
   A.tol_mu = 1e-13;
   A.tol_n = 1e-13;
   A.extra = nullptr;
+  A.ne_offset = p.ne_offset;
   return A;
 }
 
@@ -1016,6 +1018,8 @@ hipError_t dyson_g_bwd_no(const Plan& p, const void* h_k, const void* sig_iw, do
   A.max_evals = 0;
   A.beta = p.beta;
   A.tol_mu = A.tol_n = 0.0;
+  A.extra = nullptr;
+  A.ne_offset = p.ne_offset;
   const int64_t total = int64_t(p.r) * p.nk;
   const int nblk = int((total + 63) / 64);
   if (2 * int64_t(nblk) > 8 * int64_t(p.max_blocks)) return hipErrorInvalidValue;

@@ -18,6 +18,12 @@ namespace qgw {
 // Sides of a cubic N x N x N mesh with a compiled 3-D transform.
 #define QGW_FOR_EACH_CUBE(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12)
 
+// Node counts N = N1 N2 of the uniform Matsubara grid with a compiled transform, X(N, N1, N2).
+#define QGW_FOR_EACH_MF_GRID(X)                                                                              \
+  X(16, 4, 4) X(32, 4, 8) X(48, 6, 8) X(64, 8, 8) X(80, 8, 10) X(96, 8, 12) X(128, 8, 16) X(160, 10, 16)      \
+  X(192, 12, 16) X(200, 10, 20) X(256, 16, 16) X(320, 16, 20) X(400, 16, 25) X(512, 16, 32) X(640, 20, 32) \
+  X(800, 25, 32) X(1024, 32, 32)
+
 // Pair-basis sizes with a compiled Dyson-W solver.
 #define QGW_FOR_EACH_NB(X) X(1) X(2) X(4) X(5) X(8) X(9) X(16) X(25)
 
@@ -25,6 +31,7 @@ namespace qgw {
 #define QGW_FOR_EACH_NO(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 
 constexpr int kMaxRank = 96;
+constexpr int kGridDLR = 0, kGridMF = 1;
 constexpr int kNumMaps = 7;
 // device map slots: 0-6 the forward maps, 7 + m the adjoint T^H of the square map m (m != 5)
 constexpr int kAdjMap0 = 7;
@@ -58,6 +65,11 @@ struct Tune {
 struct Plan {
   int device = 0;
   int n = 0, dim = 2, nk = 0, no = 0, nb = 0, r = 0, prec = 0;  // mesh side n, N_k = n^dim
+  // node axis: kGridDLR (r DLR nodes) or kGridMF (r = N uniform Matsubara frequencies / midpoint times)
+  int grid = 0;
+  int mf_n1 = 0, mf_n2 = 0;   // N = N1 N2 (kGridMF)
+  zd* d_mf = nullptr;         // kGridMF transform tables (kernels_mf.hip)
+  double ne_offset = 0.0;     // N_e = -(2/N_k) sum Re rho_m Tr G_m + ne_offset (n_o on the uniform grid)
   double beta = 0.0;
   std::vector<int> site_norb, pair_first, pair_second, orb_site, pair_of;  // pair_of[a*no+b] or -1
   std::vector<double> omega, tau_t;
@@ -164,6 +176,18 @@ hipError_t launch_bubble3(const Plan& p, const void* gt, const void* gr, int out
 hipError_t launch_sigma3(const Plan& p, const void* gt, const void* wc, int in_q, int out_k, void* sig, hipStream_t s);
 hipError_t launch_sigma_bwd_wc3(const Plan& p, const void* gt, const void* sbar, void* out, hipStream_t s);
 hipError_t launch_contract_bwd3(const Plan& p, int mode, const void* xq, const void* y, void* out, hipStream_t s);
+// uniform-grid (MF) plans: the transforms behind launch_dlr / launch_dlr_pairs, G(tau) and G(beta - tau) in one
+// pass, the split N = N1 N2 of a supported node count
+hipError_t launch_mf(const Plan& p, int map, int64_t ncols, double sre, double sim, const void* in, void* out,
+                     hipStream_t s, int herm);
+hipError_t launch_mf_pairs(const Plan& p, int map, int in_layout, int out_layout, const void* in, void* out,
+                           hipStream_t s);
+hipError_t launch_mf_g_tau(const Plan& p, const void* g_iw, void* g_tau, void* g_reflt, hipStream_t s);
+bool mf_grid_split(int n, int* n1, int* n2);
+// the density row y = s sum_m row_m x_m (map 5), with the Hermitian part of the input (herm 1) or output (herm 2)
+hipError_t launch_row_map(const Plan& p, int64_t ncols, double sre, double sim, int herm, const void* in, void* out,
+                          hipStream_t s);
+
 // threads per slab line set: n for a square mesh, n^2 for a cube
 inline int lines_per_slab(const Plan& p) { return p.dim == 3 ? p.n * p.n : p.n; }
 hipError_t launch_dyson_w_bwd(const Plan& p, const void* v_q, const void* p_nu, const void* wcbar,

@@ -33,7 +33,7 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
            "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_quasiparticle", "qgw_hf_density", "qgw_state_hf_solve", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
-           "qgw_last_error"]
+           "qgw_plan_create_mf", "qgw_mf_nodes_for", "qgw_last_error"]
 
 
 class QGWError(RuntimeError):
@@ -70,6 +70,8 @@ def lib():
         sig = {
             "qgw_dlr_build": [dbl, dbl, i32, pd, pd, pi64, pi64, pi32],
             "qgw_plan_create": [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)],
+            "qgw_plan_create_mf": [ctypes.POINTER(PlanDesc), i32, ctypes.POINTER(vp)],
+            "qgw_mf_nodes_for": [dbl, dbl],
             "qgw_plan_destroy": [vp],
             "qgw_plan_get_map": [vp, i32, pd],
             "qgw_plan_sizes": [vp, pi32, pi32, pi32, pi32],
@@ -151,10 +153,15 @@ def dlr_build(lam, eps, max_rank=96):
     return {"x": x[:r].copy(), "tau_t": t[:r].copy(), "n_f": nf[:r].copy(), "n_b": nb[:r].copy()}
 
 
+def mf_nodes_for(beta, omega_max):
+    """The smallest supported uniform-grid node count reaching omega_max (qgw_mf_nodes_for); 0 if none."""
+    return int(lib().qgw_mf_nodes_for(float(beta), float(omega_max)))
+
+
 class Plan:
     """A libqgw plan: mesh n x n (or n x n x n with dim=3), sites/orbitals, DLR nodes, precision."""
 
-    def __init__(self, n, site_norb, beta, omega, tau_t, n_f, n_b, precision=F64, device=0, dim=2):
+    def __init__(self, n, site_norb, beta, omega, tau_t, n_f, n_b, precision=F64, device=0, dim=2, mf_nodes=0):
         self._keep = [np.ascontiguousarray(site_norb, dtype=np.int32),
                       np.ascontiguousarray(omega, dtype=np.float64),
                       np.ascontiguousarray(tau_t, dtype=np.float64),
@@ -167,8 +174,12 @@ class Plan:
                      nf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                      nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(precision), int(device), int(dim))
         h = ctypes.c_void_p()
-        _check(lib().qgw_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        if mf_nodes:
+            _check(lib().qgw_plan_create_mf(ctypes.byref(d), int(mf_nodes), ctypes.byref(h)))
+        else:
+            _check(lib().qgw_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
+        self.grid = "mf" if mf_nodes else "dlr"
         r, no, nbp, nk = (ctypes.c_int32() for _ in range(4))
         _check(lib().qgw_plan_sizes(h, ctypes.byref(r), ctypes.byref(no), ctypes.byref(nbp), ctypes.byref(nk)))
         self.r, self.n_o, self.n_b, self.n_k = r.value, no.value, nbp.value, nk.value
@@ -183,6 +194,12 @@ class Plan:
         """``nodes``: dict with omega (eV), tau_t, n_f, n_b."""
         return cls(n, site_norb, beta, nodes["omega"], nodes["tau_t"], nodes["n_f"], nodes["n_b"],
                    precision, device, dim)
+
+    @classmethod
+    def uniform(cls, n, site_norb, beta, n_nodes, device=0, dim=2):
+        """Uniform Matsubara-grid plan (qgw_plan_create_mf) with ``n_nodes`` = N frequencies / times."""
+        none_d, none_i = np.zeros(1), np.zeros(1, dtype=np.int64)
+        return cls(n, site_norb, beta, none_d, none_d, none_i, none_i, F64, device, dim, mf_nodes=n_nodes)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_functions():
     text = open(os.path.join(ROOT, "include", "qgw.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:qgw_status|const char \*)\s*(qgw_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:qgw_status|const char \*|int32_t)\s*(qgw_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -126,3 +126,22 @@ def test_host_dlr_builder_errors():
     with pytest.raises(qgw.QGWError) as e:
         qgw.dlr_build(-1.0, 1e-10)
     assert e.value.status == 1
+
+
+def test_uniform_grid_node_choice_and_checks():
+    """qgw_mf_nodes_for is host arithmetic; qgw_plan_create_mf rejects unsupported grids before any device call."""
+    L = qgw.lib()
+    assert L.qgw_mf_nodes_for(50.0, 25.0) == 400
+    assert L.qgw_mf_nodes_for(100.0, 25.0) == 800
+    assert L.qgw_mf_nodes_for(10.0, 1.0) == 16
+    assert L.qgw_mf_nodes_for(-1.0, 1.0) == 0
+    # the smallest supported N with (2M - 1) pi / beta >= omega_max
+    for beta, wmax in [(7.0, 3.0), (20.0, 25.0), (40.0, 30.0)]:
+        n = L.qgw_mf_nodes_for(beta, wmax)
+        assert (n - 1) * math.pi / beta >= wmax - 1e-9
+    d, keep = _desc()
+    h = ctypes.c_void_p()
+    assert L.qgw_plan_create_mf(ctypes.byref(d), 100, ctypes.byref(h)) == 3       # no compiled transform
+    assert L.qgw_plan_create_mf(ctypes.byref(d), 0, ctypes.byref(h)) == 1
+    d32, keep32 = _desc(precision=1)
+    assert L.qgw_plan_create_mf(ctypes.byref(d32), 64, ctypes.byref(h)) == 3      # FP64 only
