@@ -28,6 +28,9 @@ SPECS = [
                             scale_mesh=5),
     lambda: wl.five_orbital(n=8, norb=1, n_target=1.0, U=2.0, J=0.0, Vnn=0.3, beta=20.0, omega_max=10.0,
                             eps=1e-10, scale_mesh=8),
+    # a cubic mesh in the same graph
+    lambda: wl.random_model_3d((4, 4, 4), [2, 1], seed=3, beta=8.0, omega_max=20.0, eps=1e-10, U=1.0, J=0.1,
+                               Vnn=0.2),
 ]
 
 
@@ -37,17 +40,18 @@ def _torch():
     return torch
 
 
-def dev(x):
+def dev(x, dim=2):
     torch = _torch()
-    return torch.from_numpy(np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)), dtype=np.complex128)).to("cuda:0")
+    return torch.from_numpy(np.ascontiguousarray(x.reshape(x.shape[:-dim] + (-1,)), dtype=np.complex128)).to("cuda:0")
 
 
 class Inst:
     def __init__(self, w):
         self.w = w
         self.d = DLR(w["beta"], w["omega_max"], w["eps"])
-        self.plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], self.d.nodes())
-        self.H, self.V = dev(w["H_R"]), dev(w["V_R"])
+        self.dim = len(w["mesh"])
+        self.plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], self.d.nodes(), dim=self.dim)
+        self.H, self.V = dev(w["H_R"], self.dim), dev(w["V_R"], self.dim)
 
     def state(self):
         st = qgw.State(self.plan, self.H, self.V, n_target=self.w["n_target"])
@@ -154,3 +158,37 @@ def test_autotuned_plan_matches_default(insts):
     a.close()
     b.close()
     tuned.close()
+
+
+def test_autotuned_cubic_plan_matches_default(insts):
+    """The autotuner on a cubic-mesh plan (line counts of n^2 per slab) changes only the order of some sums."""
+    inst = insts[5]
+    w = inst.w
+    tuned = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], inst.d.nodes(), dim=3)
+    ch = tuned.autotune()
+    print("[batch] tuned shapes (cubic)", ch, flush=True)
+    a = inst.state()
+    b = qgw.State(tuned, inst.H, inst.V, n_target=w["n_target"])
+    b.init_g0()
+    for _ in range(2):
+        da, _, ma = a.iterate(1)
+        db, _, mb = b.iterate(1)
+        assert abs(ma - mb) <= 1e-12 * max(1.0, abs(ma))
+    assert rel_err(b.array(1).cpu().numpy(), a.array(1).cpu().numpy()) < 1e-12
+    a.close()
+    b.close()
+    tuned.close()
+
+
+def test_batch_rejects_uniform_grid_states(insts):
+    w = insts[0].w
+    p = qgw.Plan.uniform(w["mesh"][0], w["site_norb"], w["beta"], 32)
+    st = qgw.State(p, insts[0].H, insts[0].V, n_target=w["n_target"])
+    with pytest.raises(qgw.QGWError) as e:
+        qgw.Batch([st])
+    assert e.value.status == 3
+    with pytest.raises(qgw.QGWError) as e:
+        p.autotune()
+    assert e.value.status == 3
+    st.close()
+    p.close()

@@ -145,3 +145,17 @@ def test_uniform_grid_node_choice_and_checks():
     assert L.qgw_plan_create_mf(ctypes.byref(d), 0, ctypes.byref(h)) == 1
     d32, keep32 = _desc(precision=1)
     assert L.qgw_plan_create_mf(ctypes.byref(d32), 64, ctypes.byref(h)) == 3      # FP64 only
+
+
+def test_cubic_mesh_checks():
+    """A cubic mesh side without a compiled 3-D transform, or a mesh dimension other than 2 and 3, is refused
+    before any device call."""
+    L = qgw.lib()
+    h = ctypes.c_void_p()
+    d, keep = _desc(n=7)
+    d.dim = 3
+    assert L.qgw_plan_create(ctypes.byref(d), ctypes.byref(h)) == 3
+    d.n = 16
+    assert L.qgw_plan_create(ctypes.byref(d), ctypes.byref(h)) == 3      # 16^3 exceeds the cubic set
+    d.n, d.dim = 8, 4
+    assert L.qgw_plan_create(ctypes.byref(d), ctypes.byref(h)) == 1
