@@ -9,21 +9,33 @@ namespace qgw {
 
 // Sigma_HF_{ik}(R) = - sum_terms V_{(il),(jk)}(R) n_{lj}(R)
 //                    + delta_{R,0} 2 sum_beta V_{(ik),beta}(q=0) n_{k_beta j_beta}(0)
+// Four adjacent lanes share one output (i, k, R): each sums every fourth term, and two xor shuffles add the four
+// partial sums in a fixed order.
 __global__ __launch_bounds__(256) void k_hartree_fock(const zd* __restrict__ v_r, const zd* __restrict__ v_q0,
                                                       const zd* __restrict__ n_r, zd* __restrict__ out,
                                                       int no, int nb, int nk, const int* __restrict__ pairs,
                                                       const int4* __restrict__ terms,
                                                       const int* __restrict__ term_off) {
-  const int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (gi >= int64_t(no) * no * nk) return;
-  const int rr = int(gi % nk);
-  const int ik = int(gi / nk);
+  const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int part = int(g & 3);
+  const int64_t gi = g >> 2;
+  const bool valid = gi < int64_t(no) * no * nk;
+  const int rr = valid ? int(gi % nk) : 0;
+  const int ik = valid ? int(gi / nk) : 0;
   const int i = ik / no, k = ik % no;
   cpx<double> s = mk(0.0, 0.0);
-  for (int t = term_off[ik]; t < term_off[ik + 1]; ++t) {
-    const int4 tm = terms[t];
-    s = fms(s, v_r[(int64_t(tm.x) * nb + tm.y) * nk + rr], n_r[(int64_t(tm.z) * no + tm.w) * nk + rr]);
+  if (valid) {
+    for (int t = term_off[ik] + part; t < term_off[ik + 1]; t += 4) {
+      const int4 tm = terms[t];
+      s = fms(s, v_r[(int64_t(tm.x) * nb + tm.y) * nk + rr], n_r[(int64_t(tm.z) * no + tm.w) * nk + rr]);
+    }
   }
+  // every lane of the wave takes part in the shuffles
+  s.re += __shfl_xor(s.re, 1, 64);
+  s.im += __shfl_xor(s.im, 1, 64);
+  s.re += __shfl_xor(s.re, 2, 64);
+  s.im += __shfl_xor(s.im, 2, 64);
+  if (!valid || part != 0) return;
   if (rr == 0) {
     const int al = pairs[2 * nb + i * no + k];  // pair (i, k) if on one site
     if (al >= 0) {
@@ -320,7 +332,7 @@ hipError_t launch_convert(int64_t count, const void* in, void* out, int to_f32, 
 hipError_t launch_hartree_fock(const Plan& p, const void* v_r, const void* v_q0, const void* n_r,
                                void* sig_hf_r, hipStream_t s) {
   const int64_t n = int64_t(p.no) * p.no * p.nk;
-  hipLaunchKernelGGL(k_hartree_fock, dim3(nblk(n, 256)), dim3(256), 0, s, (const zd*)v_r,
+  hipLaunchKernelGGL(k_hartree_fock, dim3(nblk(4 * n, 256)), dim3(256), 0, s, (const zd*)v_r,
                      (const zd*)v_q0, (const zd*)n_r, (zd*)sig_hf_r, p.no, p.nb, p.nk, p.d_pairs,
                      (const int4*)p.terms.d_terms, p.terms.d_off);
   return hipGetLastError();
