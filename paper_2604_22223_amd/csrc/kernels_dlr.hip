@@ -111,13 +111,14 @@ __global__ __launch_bounds__(256) void k_dlr(const cpx<T>* __restrict__ in, cpx<
 }
 
 // One-row maps (the density row G(beta^-) from G(i w_m)): out[c] = s sum_t row[t] in[t][c].  A block of
-// four waves takes 64 columns; wave w sums the nodes t = w, w + 4, ... for its lane's column (coalesced
-// 64-column reads), and the four partial sums are added in a fixed order.  HERM as for k_dlr.
+// kRowWaves waves takes 64 columns; wave w sums the nodes t = w, w + kRowWaves, ... for its lane's column
+// (coalesced 64-column reads), and the partial sums are added in a fixed order.  HERM as for k_dlr.
+constexpr int kRowWaves = 8;
 template <typename T, int HERM>
-__global__ __launch_bounds__(256) void k_dlr_row(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
-                                                 const cpx<T>* __restrict__ row, int r, int64_t ncols, int na, int nq,
-                                                 T sre, T sim) {
-  __shared__ cpx<T> part[2][4][64];
+__global__ __launch_bounds__(64 * kRowWaves) void k_dlr_row(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                                            const cpx<T>* __restrict__ row, int r, int64_t ncols,
+                                                            int na, int nq, T sre, T sim) {
+  __shared__ cpx<T> part[2][kRowWaves][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t c = int64_t(blockIdx.x) * 64 + lane;
   const bool valid = c < ncols;
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(256) void k_dlr_row(const cpx<T>* __restrict__ in, 
   }
   cpx<T> acc = mk(T(0), T(0)), acc2 = mk(T(0), T(0));
 #pragma unroll 4
-  for (int t = w; t < r; t += 4) {
+  for (int t = w; t < r; t += kRowWaves) {
     const cpx<T> m = row[t];
     const cpx<T> x = in[int64_t(t) * ncols + cc];
     if (HERM == 0) {
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(256) void k_dlr_row(const cpx<T>* __restrict__ in, 
   if (w != 0 || !valid) return;
   cpx<T> a = part[0][0][lane], b = part[1][0][lane];
 #pragma unroll
-  for (int i = 1; i < 4; ++i) {
+  for (int i = 1; i < kRowWaves; ++i) {
     a = a + part[0][i][lane];
     b = b + part[1][i][lane];
   }
@@ -530,7 +531,7 @@ hipError_t launch_row_map(const Plan& p, int64_t ncols, double sre, double sim, 
   if (ncols <= 0) return hipSuccess;
   const unsigned blocks = unsigned((ncols + 63) / 64);
 #define QGW_ROW(T, H)                                                                                     \
-  hipLaunchKernelGGL((k_dlr_row<T, H>), dim3(blocks), dim3(256), 0, s, (const cpx<T>*)in, (cpx<T>*)out, \
+  hipLaunchKernelGGL((k_dlr_row<T, H>), dim3(blocks), dim3(64 * kRowWaves), 0, s, (const cpx<T>*)in, (cpx<T>*)out, \
                      map_ptr<T>(p, 5), p.r, ncols, p.no, p.nk, T(sre), T(sim))
   if (p.prec == 0) {
     if (herm == 0) QGW_ROW(double, 0);
