@@ -194,7 +194,9 @@ qgw_status qgw_plan_get_map(qgw_plan plan, int32_t map, double *out);
  * 8, 16 or 32 rows per chunk).  choices[6] (may be NULL) receives them in
  * that order (orbital maps as two entries: 1 = VALU, and its chunk).  The
  * candidates compute the same values; the self-energy lane count and the
- * orbital-map kernel change only the order of floating-point sums. */
+ * orbital-map kernel change only the order of floating-point sums.  An FP64
+ * plan is tuned a second time for its FP32 kernels, which a state's
+ * single-precision iterations use (choices reports the FP64 shapes). */
 qgw_status qgw_plan_autotune(qgw_plan plan, int32_t *choices, void *stream);
 
 /* Sizes of the plan: any output pointer may be NULL. */

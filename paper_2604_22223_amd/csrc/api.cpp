@@ -1204,7 +1204,7 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
   const Plan& p = st->plan->p;
   const int64_t no2 = int64_t(p.no) * p.no;
   const int64_t ncol_g = no2 * p.nk;
-  st->p32.tune = p.tune;
+  st->p32.tune = p.has_tune32 ? p.tune32 : p.tune;
   hipError_t e = hipSuccess;
   auto mark = [&](int i) { if (e == hipSuccess && prof) e = hipEventRecord(st->ev[i], s); };
   auto run = [&](hipError_t r) { if (e == hipSuccess) e = r; };

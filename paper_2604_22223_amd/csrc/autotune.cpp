@@ -8,7 +8,9 @@
 //   pair DLR maps:      resident blocks per CU of the matrix-core kernel
 //   orbital DLR maps:   matrix cores, or the VALU kernel with 8 / 16 / 32 rows per chunk
 // Every candidate computes the same thing; only the self-energy lane count
-// and the orbital-map kernel change the order of floating-point sums.
+// and the orbital-map kernel change the order of floating-point sums.  An
+// FP64 plan is also tuned for its FP32 kernels (the single-precision
+// iterations of a state's mixed schedule), whose best shapes differ.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -89,7 +91,7 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
     return QGW_ERR_DEVICE;
   }
   hipStream_t s = (hipStream_t)stream;
-  const size_t c = p.prec == 0 ? 16 : 8;
+  const size_t c = 16;  // sized for FP64, large enough for the FP32 trials too
   const size_t sg = size_t(p.r) * p.no * p.no * p.nk * c;
   const size_t sp = size_t(p.r) * p.nb * p.nb * p.nk * c;
   void *gt = nullptr, *gr = nullptr, *og = nullptr, *pa = nullptr, *pb = nullptr;
@@ -116,30 +118,43 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
   std::vector<int> spb;
   for (int v = 1; v <= lane_cap; v *= 2) spb.push_back(v);
   if (spb.back() != lane_cap) spb.push_back(lane_cap);
-  Tune& tn = p.tune;
-  pick(t, s, spb, tn.fft_spb, [&] { return launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, gt, og, s); });
-  pick(t, s, spb, tn.bubble_spb, [&] { return launch_bubble(p, gt, gr, 1, pa, s); });
-  std::vector<int> lanes;
-  for (int v = 1; v <= std::min(lane_cap, std::max(1, p.terms.max_terms)); ++v) lanes.push_back(v);
-  pick(t, s, lanes, tn.sigma_spb, [&] { return launch_sigma(p, gt, pa, 1, 1, og, s); });
-  if (p.r <= 64) {
-    pick(t, s, {1, 2, 3, 4, 6, 8}, tn.mfma_bpc, [&] {
-      hipError_t r = launch_dlr_pairs(p, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, pa, pb, s);
-      if (r == hipSuccess) r = launch_dlr_pairs(p, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, pb, pa, s);
-      return r;
+  // every knob of q.tune, timed with q's precision
+  auto tune_one = [&](Plan& q) {
+    Tune& tn = q.tune;
+    pick(t, s, spb, tn.fft_spb, [&] { return launch_lattice_fft(q, QGW_K_TO_R, no2 * q.r, gt, og, s); });
+    pick(t, s, spb, tn.bubble_spb, [&] { return launch_bubble(q, gt, gr, 1, pa, s); });
+    std::vector<int> lanes;
+    for (int v = 1; v <= std::min(lane_cap, std::max(1, q.terms.max_terms)); ++v) lanes.push_back(v);
+    pick(t, s, lanes, tn.sigma_spb, [&] { return launch_sigma(q, gt, pa, 1, 1, og, s); });
+    if (q.r <= 64) {
+      pick(t, s, {1, 2, 3, 4, 6, 8}, tn.mfma_bpc, [&] {
+        hipError_t r = launch_dlr_pairs(q, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, pa, pb, s);
+        if (r == hipSuccess) r = launch_dlr_pairs(q, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, pb, pa, s);
+        return r;
+      });
+    }
+    // orbital maps: code 0 = matrix cores, 8 / 16 / 32 = VALU kernel with that chunk
+    std::vector<int> orb = {8, 16, 32};
+    if (q.r <= 64) orb.insert(orb.begin(), 0);
+    int code = 0;
+    pick(t, s, orb, code, [&] {
+      tn.orb_valu = code == 0 ? 0 : 1;
+      tn.orb_mt = code;
+      return launch_dlr(q, QGW_F_IW2TAU, no2 * q.nk, 1.0, 0.0, gt, og, s);
     });
-  }
-  // orbital maps: code 0 = matrix cores, 8 / 16 / 32 = VALU kernel with that chunk
-  std::vector<int> orb = {8, 16, 32};
-  if (p.r <= 64) orb.insert(orb.begin(), 0);
-  int code = 0;
-  pick(t, s, orb, code, [&] {
     tn.orb_valu = code == 0 ? 0 : 1;
     tn.orb_mt = code;
-    return launch_dlr(p, QGW_F_IW2TAU, no2 * p.nk, 1.0, 0.0, gt, og, s);
-  });
-  tn.orb_valu = code == 0 ? 0 : 1;
-  tn.orb_mt = code;
+  };
+  tune_one(p);
+  if (p.prec == QGW_F64) {
+    Plan q = p;  // the same device data read by the FP32 kernels
+    q.prec = QGW_F32;
+    q.tune = Tune();
+    tune_one(q);
+    p.tune32 = q.tune;
+    p.has_tune32 = true;
+  }
+  const Tune& tn = p.tune;
   e = hipStreamSynchronize(s);
   for (void* q : {gt, gr, og, pa, pb}) (void)hipFree(q);
   if (e != hipSuccess) {

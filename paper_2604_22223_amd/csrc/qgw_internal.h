@@ -92,6 +92,8 @@ struct Plan {
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   Tune tune;
+  Tune tune32;              // shapes of the FP32 kernels of an FP64 plan (a state's single-precision iterations)
+  bool has_tune32 = false;
 };
 
 void set_error(const std::string& msg);
