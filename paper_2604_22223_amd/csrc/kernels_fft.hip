@@ -287,7 +287,10 @@ template <int N, typename T>
 hipError_t bubble_n(const Plan& p, const void* gt, const void* gr, int out_q, void* out,
                     hipStream_t s) {
   const int64_t nslabs = int64_t(p.r) * p.nb * p.nb;
-  const int spb = tuned_spb<T>(N, p.tune.bubble_spb);
+  // untuned: the FP64 transform holds 150 VGPRs per thread on meshes from 16 up, and two slabs per block (more,
+  // smaller blocks) measured fastest at 24 x 24 (0.097 -> 0.083 ms); otherwise as many slabs as fit
+  const int want = p.tune.bubble_spb > 0 ? p.tune.bubble_spb : (sizeof(T) == 8 && N >= 16 ? 2 : 0);
+  const int spb = tuned_spb<T>(N, want);
   const int64_t blocks = (nslabs + spb - 1) / spb;
   if (out_q) {
     const size_t lds = size_t(spb) * MeshShape<N>::SLAB * sizeof(cpx<T>);
