@@ -90,12 +90,12 @@ def step_model(r, n_o, n_b, n_k, prec="f64"):
 PEAK_TFLOPS = {"f64": FP64_PEAK_TFLOPS, "f32": FP32_PEAK_TFLOPS}
 
 # Measured HBM bytes per launch of the kernels that carry a step (rocprofv3 FETCH_SIZE and WRITE_SIZE runs of
-# `bench.py --steps 3 --warmup 1 --no-cpu-baseline --batch 0 --paper-steps 0 --copy-calibration 256`, each
+# `bench.py --steps 3 --warmup 1 --no-cpu-baseline --batch 0 --paper-steps 0 --mf-steps 0 --copy-calibration 256`, each
 # counter scaled by what it reads for a 256 MiB device copy: FETCH x 1.9997, WRITE x 1.0000;
 # profiles/hbm_traffic_gw_iteration_five_orbital_24.md).
 # Valid for the kernels as they were profiled; a changed kernel drops its entry until it is profiled again.
 MEASURED_TRAFFIC = {
-    "a3a4_bubble:f64": 331.7e6, "a5_dlr_p:f64": 671.8e6, "a6_dyson_w:f64": 629.3e6, "a7_dlr_w:f64": 921.9e6,
+    "a3a4_bubble:f64": 332.2e6, "a5_dlr_p:f64": 671.8e6, "a6_dyson_w:f64": 629.3e6, "a7_dlr_w:f64": 921.9e6,
     "a8a9a10_sigma:f64": 333.8e6,
     "a3a4_bubble:f32": 166.2e6, "a5_dlr_p:f32": 348.2e6, "a6_dyson_w:f32": 315.0e6, "a7_dlr_w:f32": 481.7e6,
     "a8a9a10_sigma:f32": 166.0e6,
@@ -301,7 +301,8 @@ def mf_leg(torch, qgw, w, steps, tol, warmup=2, mixing=1.0, dlr_ms=None, name=""
     ms = 1e3 * el / max(done, 1)
     res = {"workload": name, "nodes": n_nodes, "omega_max": w["omega_max"], "iterations": done,
            "ms_per_iteration": round(ms, 4),
-           "ms_by_quantity": {c: round(sum(ms_tot[s] for s in ss) / max(iters, 1), 4) for c, ss in PAPER_COLUMNS.items()},
+           "ms_by_quantity": {c: round(sum(ms_tot[s] for s in ss) / max(iters, 1), 4)
+                              for c, ss in PAPER_COLUMNS.items()},
            "pair_array_GB": round(n_nodes * plan.n_b ** 2 * plan.n_k * 16 / 1e9, 3)}
     if dlr_ms:
         res["dlr_ms_per_iteration"] = round(dlr_ms, 4)
