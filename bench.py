@@ -56,7 +56,7 @@ def make_workload():
     omega_max = 25 eV (Lambda = 1250), eps = 1e-10, N_b = 25; interaction of
     the paper's five-orbital benchmark (U = 1, J = 0.1, V = 0.2 eV)."""
     from paper_2604_22223_amd import workloads as wl
-    return wl.five_orbital(n=24, U=1.0, J=0.1, Vnn=0.2, beta=50.0, omega_max=25.0, eps=1e-10)
+    return wl.workload(WORKLOAD)
 
 
 def step_model(r, n_o, n_b, n_k, prec="f64"):
