@@ -41,6 +41,10 @@ struct qgw_state_s {
   double* d_part = nullptr;
   int* d_stat = nullptr;
   int mu_steps0 = 10;  // Newton steps queued in the first round of the next search
+  // pinned host words of the search's per-iteration exchange (start point in, result out) and the
+  // event the host polls for the result: no staging copy and no blocking wait per iteration
+  double* h_io = nullptr;
+  hipEvent_t ev_io = nullptr;
   // single-precision copies for the FP32 phase of the solve (allocated on first use)
   bool has32 = false;
   Plan p32;
@@ -628,15 +632,24 @@ qgw_status qgw_hartree_fock(qgw_plan h, const void* V_R, const void* n_R, void* 
 static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw, double n_target,
                               double* mu, void* G_iw, hipStream_t s, double* evals, double* scal = nullptr,
                               double* part = nullptr, int* stat = nullptr, const double* extra_src = nullptr,
-                              double* extra_dst = nullptr, hipEvent_t end_ev = nullptr, int steps0 = 6) {
+                              double* extra_dst = nullptr, hipEvent_t end_ev = nullptr, int steps0 = 6,
+                              double* h_io = nullptr, hipEvent_t io_ev = nullptr) {
   const int mode = std::isnan(n_target) ? 0 : 1;
   if (!scal) {
     scal = p.d_scalars;
     part = p.d_partials;
     stat = p.d_status;
   }
-  double sc[2] = {*mu, n_target};
-  QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, sizeof(sc), hipMemcpyHostToDevice, s), "qgw_dyson_G");
+  // with pinned words (h_io[0..9] result, h_io[16..17] start point) the copies need no staging
+  // buffer and the host polls an event for the result instead of blocking on the stream
+  double sc_pageable[2] = {*mu, n_target};
+  double* sc = sc_pageable;
+  if (h_io) {
+    sc = h_io + 16;
+    sc[0] = *mu;
+    sc[1] = n_target;
+  }
+  QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, 2 * sizeof(double), hipMemcpyHostToDevice, s), "qgw_dyson_G");
   // the search's first launch resets the status word; a fixed-mu call has no search
   if (mode == 1)
     QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, s), "qgw_dyson_G");
@@ -653,8 +666,18 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
     QGW_CHECK_HIP(launch_dyson_g_final(p, H_k, Sig_iw, mode, G_iw, scal, part, stat, s, extra_src),
                   "qgw_dyson_G");
     if (end_ev) QGW_CHECK_HIP(hipEventRecord(end_ev, s), "qgw_dyson_G");
-    QGW_CHECK_HIP(hipMemcpyAsync(res, scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
-    QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_dyson_G");
+    if (h_io) {
+      QGW_CHECK_HIP(hipMemcpyAsync(h_io, scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
+      QGW_CHECK_HIP(hipEventRecord(io_ev, s), "qgw_dyson_G");
+      hipError_t q;
+      while ((q = hipEventQuery(io_ev)) == hipErrorNotReady) {
+      }
+      QGW_CHECK_HIP(q, "qgw_dyson_G");
+      std::memcpy(res, h_io, sizeof(res));
+    } else {
+      QGW_CHECK_HIP(hipMemcpyAsync(res, scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
+      QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_dyson_G");
+    }
     st = int(res[8]);
     if (extra_src && round == 0) *extra_dst = res[9];
     if (mode == 0 || st != 2 || res[2] >= 200.0) break;
@@ -1048,6 +1071,8 @@ qgw_status qgw_check_finite(qgw_plan h, const void* x, int64_t count, void* stre
 static void free_state(qgw_state st) {
   for (auto& e : st->ev)
     if (e) (void)hipEventDestroy(e);
+  if (st->ev_io) (void)hipEventDestroy(st->ev_io);
+  if (st->h_io) (void)hipHostFree(st->h_io);
   void* ptrs[] = {st->H_k, st->V_R, st->V_q, st->V_qm, st->V_q0, st->G_iw, st->Sig_iw, st->Sig_iw_old,
                   st->SigHF_k, st->SigHF_old, st->n_k, st->n_R, st->SigHF_R, st->Hs_k, st->G_tau,
                   st->G_reflt, st->Sig_tau_k, st->Pq, st->P_nu, st->Wc_nu, st->d_dsig, st->d_blockmax,
@@ -1116,6 +1141,8 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
     if (e != hipSuccess) break;
     e = hipMalloc(a.ptr, a.bytes);
   }
+  if (e == hipSuccess) e = hipHostMalloc((void**)&st->h_io, 32 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_io, hipEventDisableTiming);
   st->p32 = p;
   st->p32.prec = QGW_F32;
   hipStream_t s = nullptr;
@@ -1163,7 +1190,7 @@ qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
   QGW_CHECK_HIP(hipMemsetAsync(st->SigHF_old, 0, so, s), "qgw_state_init_g0");
   double m = *mu;
   qgw_status rc = run_dyson_g(p, st->H_k, nullptr, st->n_target, &m, st->G_iw, s, nullptr, st->d_scal,
-                              st->d_part, st->d_stat);
+                              st->d_part, st->d_stat, nullptr, nullptr, nullptr, 6, st->h_io, st->ev_io);
   if (rc != QGW_OK) return rc;
   st->mu = m;
   *mu = m;
@@ -1289,7 +1316,7 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     double m = st->mu, evals = 0.0;
     qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, &evals, st->d_scal,
                                 st->d_part, st->d_stat, st->d_dsig, &dsig,
-                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr, st->mu_steps0);
+                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr, st->mu_steps0, st->h_io, st->ev_io);
     if (rc != QGW_OK) return rc;
     st->mu = m;
     st->mu_steps0 = std::min(12, std::max(4, int(evals) + 3));
