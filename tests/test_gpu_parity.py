@@ -238,6 +238,34 @@ def test_whole_iterations(case):
     st.close()
 
 
+def test_iterations_in_one_call_equal_single_calls(case):
+    """Several iterations in one call give the states of one call per iteration bit for bit, in FP64 and in the
+    mixed schedule, and a tolerance stop leaves n(k) and Sigma_HF of the last iteration in place."""
+    p, m = case.plan, case.m
+    for mode in (0, 1):
+        a = qgw.State(p, dev(case.flat(m.H_R)), dev(case.flat(m.V_R)), n_target=m.n_target)
+        b = qgw.State(p, dev(case.flat(m.H_R)), dev(case.flat(m.V_R)), n_target=m.n_target)
+        for st in (a, b):
+            st.set_precision(mode, 1e-2)
+            st.init_g0()
+        done, dsig_a, mu_a = a.iterate(4)
+        assert done == 4
+        for _ in range(4):
+            _, dsig_b, mu_b = b.iterate(1)
+        assert mu_a == mu_b and dsig_a == dsig_b
+        for which in (0, 1, 2, 5):
+            assert np.array_equal(host(a.array(which)), host(b.array(which))), (mode, which)
+        # stop at a tolerance the first iteration meets: the queued density of a second one is dropped
+        done, dsig_a, _ = a.iterate(3, tol=1e3)
+        for _ in range(done):
+            _, dsig_b, _ = b.iterate(1)
+        assert dsig_a == dsig_b and (done == 1 or mode == 1)   # the mixed schedule stops only on FP64 iterations
+        for which in (0, 1, 2, 5):
+            assert np.array_equal(host(a.array(which)), host(b.array(which))), (mode, which)
+        a.close()
+        b.close()
+
+
 def test_stale_runtime_error_is_not_reported():
     """An error code that an earlier HIP call of the process left set (here a rejected hipSetDevice
     ordinal, refused on the host) is not reported as the failure of the next library call."""
