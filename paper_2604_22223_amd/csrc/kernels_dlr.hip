@@ -259,12 +259,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   extern __shared__ unsigned char smem_raw[];
   T* tre = reinterpret_cast<T*>(smem_raw);
   T* tim = tre + MT * 16 * kp;
-  // operand order: entry ((k / 4) MT + mt) 64 + lane holds T[mt 16 + lane % 16][4 (k / 4) + lane / 16],
+  // a block computes the MT row tiles from tile blockIdx.y MT on (several blocks share a column strip
+  // when there are too few strips to fill the GPU)
+  const int row0 = int(blockIdx.y) * MT * 16;
+  // operand order: entry ((k / 4) MT + mt) 64 + lane holds T[row0 + mt 16 + lane % 16][4 (k / 4) + lane / 16],
   // so that the 64 lanes of one operand read 64 consecutive values
   for (int e = threadIdx.x; e < MT * 16 * kp; e += blockDim.x) {
     const int l = e & 63, g = e >> 6;
     const int kk = g / MT, mt = g - kk * MT;
-    const int i = mt * 16 + (l & 15), k = 4 * kk + (l >> 4);
+    const int i = row0 + mt * 16 + (l & 15), k = 4 * kk + (l >> 4);
     const cpx<T> v = (i < r && k < r) ? map[int64_t(i) * r + k] : mk(T(0), T(0));
     tre[e] = v.re;
     tim[e] = v.im;
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int m = mt * 16 + M::row(lane, v);
+          const int m = row0 + mt * 16 + M::row(lane, v);
           if (m < r) out[int64_t(m) * plane + cout] = sc * mk(accr[mt][v], acci[mt][v]);
         }
     }
@@ -501,16 +504,20 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   int64_t blocks = (nstrips + 7) / 8;
   const int bpc = p.tune.mfma_bpc > 0 ? p.tune.mfma_bpc : 2;
+  // too few strips for the GPU (the orbital-sized arrays): one block per row tile of a strip group, each
+  // reading the same inputs (from L2) for its own 16 rows
+  const int ysplit = (blocks < 2 * int64_t(ncu)) ? mt : 1;
+  const int mtb = mt / ysplit;
   if (blocks > int64_t(bpc) * ncu) blocks = int64_t(bpc) * ncu;
-  const size_t lds = size_t(2) * mt * 16 * kp * sizeof(T);
+  const size_t lds = size_t(2) * mtb * 16 * kp * sizeof(T);
   const cpx<T>* mp = map_ptr<T>(p, map);
-#define QGW_MFMA_MT(MTV)                                                                                 \
-  case MTV:                                                                                              \
-    hipLaunchKernelGGL((k_dlr_mfma<T, MTV, MODE, HERM_IN>), dim3(unsigned(blocks)), dim3(512), lds, s,  \
-                       (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, nstrips, p.no, T(sre),     \
-                       T(sim));                                                                         \
+#define QGW_MFMA_MT(MTV)                                                                                  \
+  case MTV:                                                                                               \
+    hipLaunchKernelGGL((k_dlr_mfma<T, MTV, MODE, HERM_IN>), dim3(unsigned(blocks), unsigned(ysplit)),     \
+                       dim3(512), lds, s, (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, nstrips, \
+                       p.no, T(sre), T(sim));                                                            \
     break;
-  switch (mt) {
+  switch (mtb) {
     QGW_MFMA_MT(1)
     QGW_MFMA_MT(2)
     QGW_MFMA_MT(3)
