@@ -253,15 +253,25 @@ __device__ __forceinline__ T dpp_identity(T v) {
 template <typename T, int MT, int MODE, bool HERM_IN>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dlr_mfma(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                                   const cpx<T>* __restrict__ map, int r, int kp, int na,
-                                                  int nq, int64_t nstrips, int no, T sre, T sim) {
+                                                  int nq, int64_t nstrips, int no, T sre, T sim, int ysplit) {
   using M = Mfma<T>;
   using v4 = typename M::v4;
   extern __shared__ unsigned char smem_raw[];
   T* tre = reinterpret_cast<T*>(smem_raw);
   T* tim = tre + MT * 16 * kp;
-  // a block computes the MT row tiles from tile blockIdx.y MT on (several blocks share a column strip
-  // when there are too few strips to fill the GPU)
-  const int row0 = int(blockIdx.y) * MT * 16;
+  // With ysplit > 1 a block computes only the MT row tiles from tile ``tile`` MT on, and the ysplit blocks of
+  // one group of strips are hardware blocks g 8 ysplit + 8 tile + x (x < 8): the same XCD (hardware blocks are
+  // dealt round-robin to the 8 XCDs) at nearly the same time, so the group's inputs leave HBM once and the other
+  // tiles read them from that XCD's L2.  The group count is a multiple of 8.
+  int64_t group = blockIdx.x, ngroups = gridDim.x;
+  int tile = 0;
+  if (ysplit > 1) {
+    const int64_t i = int64_t(blockIdx.x) >> 3;
+    tile = int(i % ysplit);
+    group = (i / ysplit) * 8 + (blockIdx.x & 7);
+    ngroups = gridDim.x / ysplit;
+  }
+  const int row0 = tile * MT * 16;
   // operand order: entry ((k / 4) MT + mt) 64 + lane holds T[row0 + mt 16 + lane % 16][4 (k / 4) + lane / 16],
   // so that the 64 lanes of one operand read 64 consecutive values
   for (int e = threadIdx.x; e < MT * 16 * kp; e += blockDim.x) {
@@ -276,7 +286,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lk = lane >> 4;
   const int64_t plane = int64_t(na) * nq;
-  for (int64_t strip = int64_t(blockIdx.x) * 8 + wave; strip < nstrips; strip += int64_t(gridDim.x) * 8) {
+  for (int64_t strip = group * 8 + wave; strip < nstrips; strip += ngroups * 8) {
     int64_t cin, cout;
     bool valid;
     if (MODE == kSlabToMatrix) {  // lanes along a (contiguous in the output), strips along q
@@ -509,13 +519,14 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
   const int ysplit = (blocks < 2 * int64_t(ncu)) ? mt : 1;
   const int mtb = mt / ysplit;
   if (blocks > int64_t(bpc) * ncu) blocks = int64_t(bpc) * ncu;
+  if (ysplit > 1) blocks = (blocks + 7) / 8 * 8 * ysplit;  // groups rounded up to a multiple of 8, ysplit blocks each
   const size_t lds = size_t(2) * mtb * 16 * kp * sizeof(T);
   const cpx<T>* mp = map_ptr<T>(p, map);
 #define QGW_MFMA_MT(MTV)                                                                                  \
   case MTV:                                                                                               \
-    hipLaunchKernelGGL((k_dlr_mfma<T, MTV, MODE, HERM_IN>), dim3(unsigned(blocks), unsigned(ysplit)),     \
-                       dim3(512), lds, s, (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, nstrips, \
-                       p.no, T(sre), T(sim));                                                            \
+    hipLaunchKernelGGL((k_dlr_mfma<T, MTV, MODE, HERM_IN>), dim3(unsigned(blocks)), dim3(512), lds, s,   \
+                       (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, nstrips, p.no, T(sre), T(sim), \
+                       ysplit);                                                                            \
     break;
   switch (mtb) {
     QGW_MFMA_MT(1)
