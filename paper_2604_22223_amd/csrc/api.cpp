@@ -1093,7 +1093,8 @@ static hipError_t ensure_fp32(qgw_state st) {
     void** ptr;
     size_t bytes;
   } allocs[] = {{&st->G32, fo},  {&st->Gt32, fo},  {&st->Gr32, fo},  {&st->St32, fo}, {&st->Siw32, fo},
-                {&st->Pq32, fp}, {&st->Pnu32, fp}, {&st->Wc32, fp}, {&st->Vqm32, sp}};
+                {&st->Pq32, fp}, {&st->Pnu32, fp}, {&st->Wc32, size_t(state_w_ld(p)) * p.nk * 8 * p.r},
+                {&st->Vqm32, sp}};
   hipError_t e = hipSuccess;
   for (auto& a : allocs) {
     if (e != hipSuccess) break;
@@ -1124,6 +1125,7 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
   const size_t sp = size_t(p.nb) * p.nb * p.nk * 16;         // static pair
   const size_t fo = so * p.r;                                // fermionic orbital
   const size_t fp = sp * p.r;                                // pair with nodes
+  const size_t fw = size_t(state_w_ld(p)) * p.nk * 16 * p.r;  // W^C: matrix rows padded to whole lines
   hipError_t e = hipSuccess;
   struct {
     void** ptr;
@@ -1133,7 +1135,7 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
                 {&st->Sig_iw_old, fo}, {&st->SigHF_k, so}, {&st->SigHF_old, so},  {&st->n_k, so},
                 {&st->n_R, so},       {&st->SigHF_R, so}, {&st->Hs_k, so},       {&st->G_tau, fo},
                 {&st->G_reflt, fo},   {&st->Sig_tau_k, fo}, {&st->Pq, fp},       {&st->P_nu, fp},
-                {&st->Wc_nu, fp},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096},
+                {&st->Wc_nu, fw},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096},
                 {(void**)&st->d_scal, 16 * sizeof(double)},
                 {(void**)&st->d_part, size_t(8) * p.max_blocks * sizeof(double)},
                 {(void**)&st->d_stat, 16 * sizeof(int)}};
@@ -1257,9 +1259,9 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     mark(4);  // a5
     run(launch_dlr_pairs(p, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq, st->P_nu, s));
     mark(5);  // a6
-    run(launch_dyson_w(p, st->V_qm, st->P_nu, st->Wc_nu, s));
+    run(launch_dyson_w(p, st->V_qm, st->P_nu, st->Wc_nu, s, state_w_ld(p)));
     mark(6);  // a7
-    run(launch_dlr_pairs(p, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc_nu, st->Pq, s));
+    run(launch_dlr_pairs(p, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc_nu, st->Pq, s, state_w_ld(p)));
     mark(7);  // a8 + a9 + a10
     run(launch_sigma(p, st->G_tau, st->Pq, 1, 1, st->Sig_tau_k, s));
     mark(8);  // a11 (Hermitian part of Sigma^C(k, tau))
@@ -1279,9 +1281,9 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     mark(4);
     run(launch_dlr_pairs(q, QGW_B_TAU2IW, QGW_LAYOUT_SLAB, QGW_LAYOUT_MATRIX, st->Pq32, st->Pnu32, s));
     mark(5);
-    run(launch_dyson_w(q, st->Vqm32, st->Pnu32, st->Wc32, s));
+    run(launch_dyson_w(q, st->Vqm32, st->Pnu32, st->Wc32, s, state_w_ld(p)));
     mark(6);
-    run(launch_dlr_pairs(q, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc32, st->Pq32, s));
+    run(launch_dlr_pairs(q, QGW_B_IW2TAU, QGW_LAYOUT_MATRIX, QGW_LAYOUT_SLAB, st->Wc32, st->Pq32, s, state_w_ld(p)));
     mark(7);
     run(launch_sigma(q, st->Gt32, st->Pq32, 1, 1, st->St32, s));
     mark(8);
@@ -1485,7 +1487,7 @@ qgw_status qgw_state_copy(qgw_state st, int32_t which, void* dst, int64_t* bytes
     case 1: src = st->Sig_iw; n = so * p.r; break;
     case 2: src = st->SigHF_k; n = so; break;
     case 3: src = st->P_nu; n = fp; break;
-    case 4: src = st->Wc_nu; n = fp; break;
+    case 4: src = st->Wc_nu; n = fp; break;  // rows padded to state_w_ld: copied row by row below
     case 5: src = st->n_k; n = so; break;
     default:
       set_error("qgw_state_copy: bad selector");
@@ -1494,7 +1496,13 @@ qgw_status qgw_state_copy(qgw_state st, int32_t which, void* dst, int64_t* bytes
   if (bytes) *bytes = int64_t(n);
   if (!dst) return QGW_OK;
   QGW_CHECK_HIP(enter_device(p.device), "hipSetDevice");
-  QGW_CHECK_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, (hipStream_t)stream), "qgw_state_copy");
+  const int64_t nb2 = int64_t(p.nb) * p.nb, ld = state_w_ld(p);
+  if (which == 4 && ld != nb2)
+    QGW_CHECK_HIP(hipMemcpy2DAsync(dst, size_t(nb2) * 16, src, size_t(ld) * 16, size_t(nb2) * 16,
+                                   size_t(p.r) * p.nk, hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                  "qgw_state_copy");
+  else
+    QGW_CHECK_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, (hipStream_t)stream), "qgw_state_copy");
   return QGW_OK;
 }
 

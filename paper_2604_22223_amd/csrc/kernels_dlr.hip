@@ -382,7 +382,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 template <typename T, int MT, int MODE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dlr_mfma_pairs(
     const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ map, int r, int kp,
-    int na, int nq, int tiles_l, int64_t ntiles, T sre, T sim) {
+    int na, int nq, int tiles_l, int64_t ntiles, T sre, T sim, int64_t in_ld) {
   using M = Mfma<T>;
   using v4 = typename M::v4;
   constexpr int WP = 9;             // padded W extent of the LDS tile
@@ -405,15 +405,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int lt = threadIdx.x >> 7, lL = (threadIdx.x >> 3) & 15, lW = threadIdx.x & 7;
   const int nL = MODE == kSlabToMatrix ? na : nq, nW = MODE == kSlabToMatrix ? nq : na;
   const int64_t plane = int64_t(na) * nq;
+  // the input's rows (index L) are in_ld apart, its node planes nL in_ld (in_ld >= nW: padded rows)
+  const int64_t in_plane = int64_t(nL) * in_ld;
   int buf = 0;  // slice parity, continued across tiles
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int tL = int(tile % tiles_l), tW = int(tile / tiles_l);
     // input column of this thread's loads (clamped into the array: values
     // outside it feed only columns that are not stored)
     const int Lld = min(tL * 16 + lL, nL - 1), Wld = min(tW * 8 + lW, nW - 1);
-    const cpx<T>* src = in + int64_t(Lld) * nW + Wld;
+    const cpx<T>* src = in + int64_t(Lld) * in_ld + Wld;
     // node index clamped to r - 1: the map's zero padding cancels it
-    auto gload = [&](int kb) -> cpx<T> { return src[int64_t(min(kb + lt, r - 1)) * plane]; };
+    auto gload = [&](int kb) -> cpx<T> { return src[int64_t(min(kb + lt, r - 1)) * in_plane]; };
     const int Lo = tL * 16 + lc, Wo = tW * 8 + wave;
     const bool valid = Lo < nL && Wo < nW;
     const int64_t cout = int64_t(Wo) * nL + Lo;
@@ -464,10 +466,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 // pair arrays with a layout change (MODE = kSlabToMatrix or kMatrixToSlab)
 template <typename T, int MODE>
 hipError_t dlr_mfma_pairs_launch(const Plan& p, int map, int na, int nq, double sre, double sim, const void* in,
-                                 void* out, hipStream_t s) {
+                                 void* out, hipStream_t s, int64_t in_ld) {
   const int kp = (p.r + 3) / 4 * 4;
   const int mt = (p.r + 15) / 16;
   const int nL = MODE == kSlabToMatrix ? na : nq, nW = MODE == kSlabToMatrix ? nq : na;
+  if (in_ld == 0) in_ld = nW;
+  if (in_ld < nW) return hipErrorInvalidValue;
   const int tiles_l = (nL + 15) / 16;
   const int64_t ntiles = int64_t(tiles_l) * ((nW + 7) / 8);
   int dev = 0, ncu = 0;
@@ -481,7 +485,8 @@ hipError_t dlr_mfma_pairs_launch(const Plan& p, int map, int na, int nq, double 
 #define QGW_MFMA_MT(MTV)                                                                                       \
   case MTV:                                                                                                    \
     hipLaunchKernelGGL((k_dlr_mfma_pairs<T, MTV, MODE>), dim3(unsigned(blocks)), dim3(512), lds, s,            \
-                       (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, tiles_l, ntiles, T(sre), T(sim)); \
+                       (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, tiles_l, ntiles, T(sre), T(sim), \
+                       in_ld);                                                                                 \
     break;
   switch (mt) {
     QGW_MFMA_MT(1)
@@ -498,10 +503,11 @@ hipError_t dlr_mfma_pairs_launch(const Plan& p, int map, int na, int nq, double 
 // na x nq columns; HERM_IN: orbital arrays (na = n_o^2, nq = N_k)
 template <typename T, int MODE, bool HERM_IN>
 hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, double sim, const void* in,
-                           void* out, hipStream_t s) {
+                           void* out, hipStream_t s, int64_t in_ld = 0) {
   const int kp = (p.r + 3) / 4 * 4;
   const int mt = (p.r + 15) / 16;
-  if constexpr (MODE != kPlain) return dlr_mfma_pairs_launch<T, MODE>(p, map, na, nq, sre, sim, in, out, s);
+  if constexpr (MODE != kPlain) return dlr_mfma_pairs_launch<T, MODE>(p, map, na, nq, sre, sim, in, out, s, in_ld);
+  if (in_ld != 0) return hipErrorInvalidValue;
   int64_t nstrips;
   if (MODE == kSlabToMatrix)
     nstrips = int64_t((na + 15) / 16) * nq;
@@ -594,22 +600,31 @@ hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double 
 }
 
 hipError_t launch_dlr_pairs(const Plan& p, int map, int in_layout, int out_layout, const void* in,
-                            void* out, hipStream_t s) {
-  if (p.grid == kGridMF) return launch_mf_pairs(p, map, in_layout, out_layout, in, out, s);
+                            void* out, hipStream_t s, int64_t in_ld) {
   const int na = p.nb * p.nb, nq = p.nk;
+  // padded input rows: only the matrix -> slab change of the matrix-core path reads them
+  if (in_ld == (in_layout == 1 ? na : nq)) in_ld = 0;
+  if (in_ld != 0 && !(p.grid == kGridDLR && p.r <= 64 && in_layout == 1 &&
+                      out_layout == 0))
+    return hipErrorInvalidValue;
+  if (p.grid == kGridMF) return launch_mf_pairs(p, map, in_layout, out_layout, in, out, s);
   const int64_t ncols = int64_t(na) * nq;
   int mode = kPlain;
   if (in_layout == 0 && out_layout == 1) mode = kSlabToMatrix;
   if (in_layout == 1 && out_layout == 0) mode = kMatrixToSlab;
   if (p.r <= 64) {  // matrix-core path
     if (p.prec == 0) {
-      if (mode == kPlain) return dlr_mfma_launch<double, kPlain, false>(p, map, na, nq, 1, 0, in, out, s);
+      if (mode == kPlain && in_ld == 0) return dlr_mfma_launch<double, kPlain, false>(p, map, na, nq, 1, 0, in, out, s);
       if (mode == kSlabToMatrix) return dlr_mfma_launch<double, kSlabToMatrix, false>(p, map, na, nq, 1, 0, in, out, s);
-      return dlr_mfma_launch<double, kMatrixToSlab, false>(p, map, na, nq, 1, 0, in, out, s);
+      if (mode == kMatrixToSlab)
+        return dlr_mfma_launch<double, kMatrixToSlab, false>(p, map, na, nq, 1, 0, in, out, s, in_ld);
+      return hipErrorInvalidValue;  // matrix -> matrix with padded rows
     }
-    if (mode == kPlain) return dlr_mfma_launch<float, kPlain, false>(p, map, na, nq, 1, 0, in, out, s);
+    if (mode == kPlain && in_ld == 0) return dlr_mfma_launch<float, kPlain, false>(p, map, na, nq, 1, 0, in, out, s);
     if (mode == kSlabToMatrix) return dlr_mfma_launch<float, kSlabToMatrix, false>(p, map, na, nq, 1, 0, in, out, s);
-    return dlr_mfma_launch<float, kMatrixToSlab, false>(p, map, na, nq, 1, 0, in, out, s);
+    if (mode == kMatrixToSlab)
+      return dlr_mfma_launch<float, kMatrixToSlab, false>(p, map, na, nq, 1, 0, in, out, s, in_ld);
+    return hipErrorInvalidValue;
   }
   if (p.prec == 0) {
     if (mode == kPlain) return dlr_launch<double, kPlain, 0>(p, map, ncols, na, nq, 1, 0, in, out, s);

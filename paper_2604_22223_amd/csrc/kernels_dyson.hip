@@ -56,7 +56,7 @@ __device__ __forceinline__ cpx<T> shfl_cpx(cpx<T> v, int src, int width) {
 template <int NB, typename T>
 __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
                                                 const cpx<T>* __restrict__ pnu,
-                                                cpx<T>* __restrict__ wc, int64_t nmat, int nk) {
+                                                cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld) {
   using S = DysonWShape<NB>;
   __shared__ cpx<T> sp[S::MPW * S::NN];
   __shared__ cpx<T> piv[2][S::MPW][2 * NB];
@@ -157,7 +157,10 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
     for (int c = 0; c < NB; ++c) sp[mw * S::NN + my_step * NB + c] = x[c] - vr[c];
   }
   __syncthreads();
-  for (int e = lane; e < nload; e += 64) wc[mat0 * S::NN + e] = sp[e];
+  for (int e = lane; e < nload; e += 64) {
+    const int mi = e / S::NN;
+    wc[(mat0 + mi) * ld + (e - mi * S::NN)] = sp[e];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -298,7 +301,7 @@ __device__ __forceinline__ void gj25_all(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs)
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
-                                                  cpx<T>* __restrict__ wc, int64_t nmat, int nk) {
+                                                  cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld) {
   constexpr int NB = W25::NB, NN = NB * NB, NS = W25::NS, NT = W25::NT, CH = W25::CH, NCH = W25::NCH;
   __shared__ cpx<T> xs[W25::XS];  // a chunk of P rows; then the pivot exchange
   __shared__ cpx<T> sv[NN];       // V(q)
@@ -388,7 +391,7 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
   }
   gj25_all<T>(x, y, cs, kof, k24, rg, cg, xs, std::make_integer_sequence<int, NB>{});
   // row r of the V part is row kof of W; W^C = W - V
-  cpx<T>* wm = wc + mat * NN;
+  cpx<T>* wm = wc + mat * ld;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int k = kof[s];
@@ -917,17 +920,19 @@ __global__ __launch_bounds__(64) void k_dyson_g_bwd2(DysonGArgs A, double mu, do
 namespace {
 
 template <int NB, typename T>
-hipError_t dyson_w_nb(const Plan& p, const void* v_q, const void* p_nu, void* wc_nu, hipStream_t s) {
+hipError_t dyson_w_nb(const Plan& p, const void* v_q, const void* p_nu, void* wc_nu, hipStream_t s, int64_t ld) {
   constexpr int MPW = DysonWShape<NB>::MPW;
   const int64_t nmat = int64_t(p.r) * p.nk;
+  if (ld == 0) ld = int64_t(NB) * NB;
+  if (ld < int64_t(NB) * NB) return hipErrorInvalidValue;
   if (NB == 25) {
     hipLaunchKernelGGL((k_dyson_w25<T>), dim3(unsigned(nmat)), dim3(64), 0, s, (const cpx<T>*)v_q,
-                       (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk);
+                       (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld);
     return hipGetLastError();
   }
   const unsigned blocks = unsigned((nmat + MPW - 1) / MPW);
   hipLaunchKernelGGL((k_dyson_w<NB, T>), dim3(blocks), dim3(64), 0, s, (const cpx<T>*)v_q,
-                     (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk);
+                     (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld);
   return hipGetLastError();
 }
 
@@ -1060,11 +1065,12 @@ hipError_t launch_dyson_g_bwd(const Plan& p, const void* h_k, const void* sig_iw
 }
 
 hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void* wc_nu,
-                          hipStream_t s) {
+                          hipStream_t s, int64_t out_ld) {
   switch (p.nb) {
-#define QGW_CASE(NBV) \
-  case NBV:           \
-    return p.prec == 0 ? dyson_w_nb<NBV, double>(p, v_q, p_nu, wc_nu, s) : dyson_w_nb<NBV, float>(p, v_q, p_nu, wc_nu, s);
+#define QGW_CASE(NBV)                                                                     \
+  case NBV:                                                                               \
+    return p.prec == 0 ? dyson_w_nb<NBV, double>(p, v_q, p_nu, wc_nu, s, out_ld)          \
+                       : dyson_w_nb<NBV, float>(p, v_q, p_nu, wc_nu, s, out_ld);
     QGW_FOR_EACH_NB(QGW_CASE)
 #undef QGW_CASE
     default:

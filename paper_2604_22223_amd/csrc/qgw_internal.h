@@ -120,10 +120,18 @@ hipError_t launch_sigma(const Plan& p, const void* g_tau_r, const void* wc, int 
 // herm: 0 plain, 1 Hermitian part of the input, 2 of the output (orbital arrays)
 hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double sim, const void* in,
                       void* out, hipStream_t s, int herm = 0);
+// in_ld: row stride (elements) of a matrix-layout input, 0 for N_b^2 (only the matrix-core path takes another)
 hipError_t launch_dlr_pairs(const Plan& p, int map, int in_layout, int out_layout, const void* in,
-                            void* out, hipStream_t s);
+                            void* out, hipStream_t s, int64_t in_ld = 0);
+// out_ld: row stride (elements) of the W^C matrices written, 0 for N_b^2
 hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void* wc_nu,
-                          hipStream_t s);
+                          hipStream_t s, int64_t out_ld = 0);
+// row stride of the W^C matrices a state keeps: rounded up to 128-byte lines (16 complex FP32 values) when the
+// matrix-core pair maps read them, so that the matrix -> slab map reads whole lines
+inline int64_t state_w_ld(const Plan& p) {
+  const int64_t na = int64_t(p.nb) * p.nb;
+  return (p.grid == 0 && p.r <= 64) ? (na + 15) / 16 * 16 : na;
+}
 hipError_t launch_hartree_fock(const Plan& p, const void* v_r, const void* v_q0, const void* n_r,
                                void* sig_hf_r, hipStream_t s);
 hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStream_t s);

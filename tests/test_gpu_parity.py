@@ -238,6 +238,17 @@ def test_whole_iterations(case):
     st.close()
 
 
+def test_state_pair_arrays(case):
+    """P(q, i nu) and W^C(q, i nu) a state keeps (W^C with its matrix rows padded to whole cache lines inside the
+    state) come out in the matrix layout and match the oracle's first iteration."""
+    st = qgw.State(case.plan, dev(case.flat(case.m.H_R)), dev(case.flat(case.m.V_R)), n_target=case.m.n_target)
+    st.init_g0()
+    st.iterate(1)
+    assert rel_err(host(st.array(3)), _matrix_layout(case.flat(case.inter["P_nu_q"]))) < TOL
+    assert rel_err(host(st.array(4)), _matrix_layout(case.flat(case.inter["Wc_nu_q"]))) < TOL
+    st.close()
+
+
 def test_iterations_in_one_call_equal_single_calls(case):
     """Several iterations in one call give the states of one call per iteration bit for bit, in FP64 and in the
     mixed schedule, and a tolerance stop leaves n(k) and Sigma_HF of the last iteration in place."""
