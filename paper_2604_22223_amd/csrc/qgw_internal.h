@@ -130,7 +130,7 @@ hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void
 // matrix-core pair maps read them, so that the matrix -> slab map reads whole lines
 inline int64_t state_w_ld(const Plan& p) {
   const int64_t na = int64_t(p.nb) * p.nb;
-  return (p.grid == 0 && p.r <= 64) ? (na + 15) / 16 * 16 : na;
+  return (p.grid == kGridDLR && p.r <= 64) ? (na + 15) / 16 * 16 : na;
 }
 hipError_t launch_hartree_fock(const Plan& p, const void* v_r, const void* v_q0, const void* n_r,
                                void* sig_hf_r, hipStream_t s);
