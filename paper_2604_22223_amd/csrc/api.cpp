@@ -487,7 +487,7 @@ static qgw_status plan_create_impl(const qgw_plan_desc* d, int mf_nodes, qgw_pla
     e = hipMalloc((void**)&p.d_partials, size_t(2) * 4 * p.max_blocks * sizeof(double));
   }
   if (e == hipSuccess) e = hipMalloc((void**)&p.d_status, 16 * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc((void**)&p.d_scalars, 16 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&p.d_scalars, 32 * sizeof(double));
   if (e != hipSuccess) {
     set_error(std::string("qgw_plan_create: ") + hipGetErrorString(e));
     free_plan_device(p);
@@ -660,10 +660,10 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
   int st = 0;
   for (int round = 0;; ++round) {
     // a few Newton evaluations, G at the current mu, one read-back; more rounds only if needed
+    const int steps = mode == 1 ? (round == 0 ? steps0 : 16) : 0;
     if (mode == 1)
-      QGW_CHECK_HIP(launch_dyson_g_steps(p, H_k, Sig_iw, scal, part, stat, round == 0 ? steps0 : 16, s),
-                    "qgw_dyson_G");
-    QGW_CHECK_HIP(launch_dyson_g_final(p, H_k, Sig_iw, mode, G_iw, scal, part, stat, s, extra_src),
+      QGW_CHECK_HIP(launch_dyson_g_steps(p, H_k, Sig_iw, scal, part, stat, steps, s), "qgw_dyson_G");
+    QGW_CHECK_HIP(launch_dyson_g_final(p, H_k, Sig_iw, mode, G_iw, scal, part, stat, s, extra_src, steps),
                   "qgw_dyson_G");
     if (end_ev) QGW_CHECK_HIP(hipEventRecord(end_ev, s), "qgw_dyson_G");
     if (h_io) {
@@ -1136,7 +1136,7 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
                 {&st->n_R, so},       {&st->SigHF_R, so}, {&st->Hs_k, so},       {&st->G_tau, fo},
                 {&st->G_reflt, fo},   {&st->Sig_tau_k, fo}, {&st->Pq, fp},       {&st->P_nu, fp},
                 {&st->Wc_nu, fw},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096},
-                {(void**)&st->d_scal, 16 * sizeof(double)},
+                {(void**)&st->d_scal, 32 * sizeof(double)},
                 {(void**)&st->d_part, size_t(8) * p.max_blocks * sizeof(double)},
                 {(void**)&st->d_stat, 16 * sizeof(int)}};
   for (auto& a : allocs) {

@@ -520,9 +520,12 @@ __device__ __forceinline__ double wave_max(double v) {
 // The search as a chain of launches.  Its state lives in the scalar block:
 //   [0] mu  [1] n_target  [2] evaluations  [3] last N_e  [4] lo  [5] hi
 //   [6] step cap  [7] done flag
-// k_dg_eval and k_dg_newton alternate; once the search has converged the
-// remaining launches return at once, so a caller may queue a fixed number of
-// steps (graph capture) or queue a few, read the done flag and continue.
+// Each k_dg_eval launch first takes the Newton step of the previous
+// evaluation (every block takes the same step from the same partial sums),
+// then evaluates; the final pass takes the last step.  Once the search has
+// converged the remaining launches return at once, so a caller may queue a
+// fixed number of steps (graph capture) or queue a few, read the done flag
+// and continue.
 // ---------------------------------------------------------------------------
 
 // partial Gershgorin bounds of H(k) (no starting point given)
@@ -574,54 +577,20 @@ __global__ __launch_bounds__(64) void k_dg_begin(double* __restrict__ scal, int*
   status[0] = ok ? 0 : 1;
 }
 
-template <int NO>
-__global__ __launch_bounds__(64) void k_dg_eval(DysonGArgs A) {
-  if (A.scal[7] != 0.0) return;
-  const double mu = A.scal[0];
-  const int64_t total = int64_t(A.r) * A.nk;
-  const int64_t stride = int64_t(gridDim.x) * 64;
-  double acc = 0.0, accd = 0.0;
-  for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
-    cpx<double> a[NO][NO];
-    load_base<NO>(A, gi, a);
-#pragma unroll
-    for (int i = 0; i < NO; ++i) a[i][i].re += mu;
-    invert_inplace<NO>(a);
-    cpx<double> tr = mk(0.0, 0.0), tr2 = mk(0.0, 0.0);
-#pragma unroll
-    for (int i = 0; i < NO; ++i) {
-      tr = tr + a[i][i];
-#pragma unroll
-      for (int j = 0; j < NO; ++j) tr2 = fma(tr2, a[i][j], a[j][i]);
-    }
-    const zd rh = A.rho[int(gi / A.nk)];
-    acc += rh.re * tr.re - rh.im * tr.im;
-    accd += rh.re * tr2.re - rh.im * tr2.im;
-  }
-  acc = wave_sum(acc);
-  accd = wave_sum(accd);
-  if (threadIdx.x == 0) {
-    A.partials[blockIdx.x] = acc;
-    A.partials[gridDim.x + blockIdx.x] = accd;
-  }
-}
+// The search state after j Newton steps: mu, n_target, steps taken, N_e at the last evaluation, bracket lo / hi,
+// step cap, done.  The host-visible words scal[0..7] hold it between rounds; inside a round the state after step
+// j sits in slot j % 2 (scal[16 + 8 (j % 2) ..]) and the partial sums of evaluation j in half j % 2 of the
+// partials, so that a launch reads the previous launch's slot and half while its block 0 writes the other ones.
+constexpr int kDgSlot = 16;
 
-__global__ __launch_bounds__(64) void k_dg_newton(DysonGArgs A, int nblk) {
-  if (A.scal[7] != 0.0) return;
-  double s = 0.0, sd = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) {
-    s += A.partials[b];
-    sd += A.partials[nblk + b];
-  }
-  s = wave_sum(s);
-  sd = wave_sum(sd);
-  if (threadIdx.x != 0) return;
+// one Newton step of the search from the summed partials (s: sum of rho Tr G, sd: of rho Tr G^2)
+__device__ __forceinline__ void dg_newton_update(const DysonGArgs& A, double s, double sd, double (&st)[8]) {
   const double ne = -2.0 * s / double(A.nk) + A.ne_offset, dne = 2.0 * sd / double(A.nk);
-  double mu = A.scal[0], lo = A.scal[4], hi = A.scal[5], cap = A.scal[6];
-  const double nt = A.scal[1];
+  double mu = st[0], lo = st[4], hi = st[5], cap = st[6];
+  const double nt = st[1];
   const double f = ne - nt;
-  A.scal[2] += 1.0;
-  A.scal[3] = ne;
+  st[2] += 1.0;
+  st[3] = ne;
   if (f < 0.0) lo = fmax(lo, mu);
   if (f > 0.0) hi = fmin(hi, mu);
   bool done = false;
@@ -643,16 +612,86 @@ __global__ __launch_bounds__(64) void k_dg_newton(DysonGArgs A, int nblk) {
     if (fabs(nxt - mu) <= tol || (bracket && hi - lo <= tol)) done = true;
     mu = nxt;
   }
-  A.scal[0] = mu;
-  A.scal[4] = lo;
-  A.scal[5] = hi;
-  A.scal[6] = cap;
-  A.scal[7] = done ? 1.0 : 0.0;
+  st[0] = mu;
+  st[4] = lo;
+  st[5] = hi;
+  st[6] = cap;
+  st[7] = done ? 1.0 : 0.0;
 }
 
+// the state after j steps of this round: step j (j >= 1) is taken from the state after j - 1 steps and the
+// partial sums of evaluation j - 1.  Every lane of every block sums the partials in the same order (the
+// butterfly reduction leaves the same bits in every lane), so all take the same step.
+__device__ __forceinline__ void dg_state(const DysonGArgs& A, int j, int nblk, double (&st)[8]) {
+  const double* src = (j == 0) ? A.scal : A.scal + kDgSlot + 8 * ((j - 1) & 1);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) st[i] = src[i];
+  if (j >= 1 && st[7] == 0.0) {
+    const double* part = A.partials + int64_t(2) * nblk * ((j - 1) & 1);
+    double s = 0.0, sd = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 64) {
+      s += part[b];
+      sd += part[nblk + b];
+    }
+    s = wave_sum(s);
+    sd = wave_sum(sd);
+    dg_newton_update(A, s, sd, st);
+  }
+}
+
+// evaluation j of a round: N_e(mu) and dN_e/dmu at the state after j steps, as per-block partial sums
 template <int NO>
-__global__ __launch_bounds__(64) void k_dg_final(DysonGArgs A) {
-  const double mu = A.scal[0];
+__global__ __launch_bounds__(64) void k_dg_eval(DysonGArgs A, int j, int nblk) {
+  double st[8];
+  dg_state(A, j, nblk, st);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double* dst = A.scal + kDgSlot + 8 * (j & 1);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) dst[i] = st[i];
+  }
+  if (st[7] != 0.0) return;
+  const double mu = st[0];
+  const int64_t total = int64_t(A.r) * A.nk;
+  const int64_t stride = int64_t(gridDim.x) * 64;
+  double acc = 0.0, accd = 0.0;
+  for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
+    cpx<double> a[NO][NO];
+    load_base<NO>(A, gi, a);
+#pragma unroll
+    for (int i = 0; i < NO; ++i) a[i][i].re += mu;
+    invert_inplace<NO>(a);
+    cpx<double> tr = mk(0.0, 0.0), tr2 = mk(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      tr = tr + a[i][i];
+#pragma unroll
+      for (int jj = 0; jj < NO; ++jj) tr2 = fma(tr2, a[i][jj], a[jj][i]);
+    }
+    const zd rh = A.rho[int(gi / A.nk)];
+    acc += rh.re * tr.re - rh.im * tr.im;
+    accd += rh.re * tr2.re - rh.im * tr2.im;
+  }
+  acc = wave_sum(acc);
+  accd = wave_sum(accd);
+  if (threadIdx.x == 0) {
+    double* part = A.partials + int64_t(2) * nblk * (j & 1);
+    part[blockIdx.x] = acc;
+    part[nblk + blockIdx.x] = accd;
+  }
+}
+
+// G at the search's result: with n >= 1 evaluations in this round the last step (from evaluation n - 1) is
+// taken here, and block 0 writes the state back to the host-visible words
+template <int NO>
+__global__ __launch_bounds__(64) void k_dg_final(DysonGArgs A, int n, int nblk) {
+  double st[8];
+  if (A.mode == 1 && n >= 1) {
+    dg_state(A, n, nblk, st);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) st[i] = A.scal[i];
+  }
+  const double mu = st[0];
   const int64_t total = int64_t(A.r) * A.nk;
   const int64_t stride = int64_t(gridDim.x) * 64;
   for (int64_t gi = int64_t(blockIdx.x) * 64 + threadIdx.x; gi < total; gi += stride) {
@@ -668,8 +707,12 @@ __global__ __launch_bounds__(64) void k_dg_final(DysonGArgs A) {
       for (int j = 0; j < NO; ++j) A.g[((int64_t(m) * NO + i) * NO + j) * A.nk + k] = a[i][j];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (A.mode == 1 && n >= 1) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) A.scal[i] = st[i];
+    }
     if (A.mode == 1 && A.status[0] == 0) {
-      const bool conv = A.scal[7] != 0.0 || fabs(A.scal[3] - A.scal[1]) <= A.tol_n;
+      const bool conv = st[7] != 0.0 || fabs(st[3] - st[1]) <= A.tol_n;
       if (!conv || !isfinite(mu)) A.status[0] = 2;
     }
     A.scal[8] = double(A.status[0]);
@@ -981,19 +1024,18 @@ hipError_t dyson_g_steps_no(const Plan& p, const void* h_k, const void* sig_iw, 
                             int* status, int steps, hipStream_t s) {
   DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, 1, nullptr, scal, partials, status);
   const int blocks = dyson_g_blocks(p);
-  for (int i = 0; i < steps; ++i) {
-    hipLaunchKernelGGL((k_dg_eval<NO>), dim3(blocks), dim3(64), 0, s, A);
-    hipLaunchKernelGGL(k_dg_newton, dim3(1), dim3(64), 0, s, A, blocks);
-  }
+  for (int i = 0; i < steps; ++i) hipLaunchKernelGGL((k_dg_eval<NO>), dim3(blocks), dim3(64), 0, s, A, i, blocks);
   return hipGetLastError();
 }
 
 template <int NO>
 hipError_t dyson_g_final_no(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                            double* scal, double* partials, int* status, const double* extra, hipStream_t s) {
+                            double* scal, double* partials, int* status, const double* extra, int steps,
+                            hipStream_t s) {
   DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, mode, g_iw, scal, partials, status);
   A.extra = extra;
-  hipLaunchKernelGGL((k_dg_final<NO>), dim3(dyson_g_blocks(p)), dim3(64), 0, s, A);
+  const int blocks = dyson_g_blocks(p);
+  hipLaunchKernelGGL((k_dg_final<NO>), dim3(blocks), dim3(64), 0, s, A, mode == 1 ? steps : 0, blocks);
   return hipGetLastError();
 }
 
@@ -1102,8 +1144,9 @@ hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_
 }
 
 hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                                double* scal, double* partials, int* status, hipStream_t s, const double* extra) {
-  QGW_NO_SWITCH((dyson_g_final_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, extra, s)))
+                                double* scal, double* partials, int* status, hipStream_t s, const double* extra,
+                                int steps) {
+  QGW_NO_SWITCH((dyson_g_final_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, extra, steps, s)))
 }
 
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
@@ -1113,7 +1156,8 @@ hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_
     e = launch_dyson_g_begin(p, h_k, scal, partials, status, s);
     if (e == hipSuccess) e = launch_dyson_g_steps(p, h_k, sig_iw, scal, partials, status, steps, s);
   }
-  if (e == hipSuccess) e = launch_dyson_g_final(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s);
+  if (e == hipSuccess) e = launch_dyson_g_final(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s, nullptr,
+                                                mode == 1 ? steps : 0);
   return e;
 }
 

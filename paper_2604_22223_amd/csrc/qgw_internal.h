@@ -146,10 +146,12 @@ hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, do
                                 hipStream_t s);
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
                                 int* status, int steps, hipStream_t s);
-// also copies the status to scal[8] and, if extra is given, *extra to scal[9]
+// also copies the status to scal[8] and, if extra is given, *extra to scal[9]; ``steps`` is the number of
+// evaluations launch_dyson_g_steps queued in this round (the final pass takes the step of the last one).
+// scal holds 32 doubles: the host-visible words 0..9 and the two state slots of a round at 16..31.
 hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, hipStream_t s,
-                                const double* extra = nullptr);
+                                const double* extra = nullptr, int steps = 0);
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, int steps, hipStream_t s);
 hipError_t launch_slab_to_matrix_static(const Plan& p, const void* in, void* out, hipStream_t s);
