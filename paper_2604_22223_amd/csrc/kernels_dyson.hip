@@ -1004,9 +1004,12 @@ DysonGArgs dyson_g_args(const Plan& p, const void* h_k, const void* sig_iw, int 
 }
 
 // grid of the search: one block per 64 (node, k) points, at most max_blocks (grid-stride beyond)
+// one-wave blocks over the (node, k) points, at most 1024: every evaluation re-sums the previous one's per-block
+// partials in each block, so that work grows with the square of the block count
 static int dyson_g_blocks(const Plan& p) {
   const int64_t need = (int64_t(p.r) * p.nk + 63) / 64;
-  return int(need < p.max_blocks ? need : p.max_blocks);
+  const int64_t cap = p.max_blocks < 1024 ? p.max_blocks : 1024;
+  return int(need < cap ? need : cap);
 }
 
 template <int NO>
