@@ -1252,8 +1252,7 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
       run(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s));
     }
     mark(2);  // a2
-    run(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, s));
-    run(launch_lattice_fft(p, QGW_K_TO_R, no2 * p.r, st->G_reflt, st->G_reflt, s));
+    run(launch_lattice_fft2(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, st->G_reflt, st->G_reflt, s));
     mark(3);  // a3 + a4
     run(launch_bubble(p, st->G_tau, st->G_reflt, 1, st->Pq, s));
     mark(4);  // a5
@@ -1274,8 +1273,7 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     run(launch_dlr(q, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G32, st->Gt32, s));
     run(launch_dlr(q, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G32, st->Gr32, s));
     mark(2);
-    run(launch_lattice_fft(q, QGW_K_TO_R, no2 * p.r, st->Gt32, st->Gt32, s));
-    run(launch_lattice_fft(q, QGW_K_TO_R, no2 * p.r, st->Gr32, st->Gr32, s));
+    run(launch_lattice_fft2(q, QGW_K_TO_R, no2 * p.r, st->Gt32, st->Gt32, st->Gr32, st->Gr32, s));
     mark(3);
     run(launch_bubble(q, st->Gt32, st->Gr32, 1, st->Pq32, s));
     mark(4);

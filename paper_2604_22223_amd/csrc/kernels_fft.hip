@@ -17,14 +17,21 @@ namespace qgw {
 // plain batched 2-D transform
 // ---------------------------------------------------------------------------
 template <int N, int SIGN, typename T>
-__global__ __launch_bounds__(256) void k_lattice_fft(const cpx<T>* __restrict__ in,
-                                                     cpx<T>* __restrict__ out, int64_t nslabs,
+__global__ __launch_bounds__(256) void k_lattice_fft(const cpx<T>* __restrict__ in1,
+                                                     cpx<T>* __restrict__ out1, int64_t nslabs1,
                                                      int spb, const cpx<T>* __restrict__ tw,
-                                                     T out_scale) {
+                                                     T out_scale, const cpx<T>* __restrict__ in2,
+                                                     cpx<T>* __restrict__ out2, int64_t nslabs2) {
   using M = MeshShape<N>;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int64_t s0 = int64_t(blockIdx.x) * spb;
+  // two arrays in one launch (both time orders of G): the first nb1 blocks take array 1, the rest array 2
+  const int64_t nb1 = (nslabs1 + spb - 1) / spb;
+  const bool second = int64_t(blockIdx.x) >= nb1;
+  const cpx<T>* in = second ? in2 : in1;
+  cpx<T>* out = second ? out2 : out1;
+  const int64_t nslabs = second ? nslabs2 : nslabs1;
+  const int64_t s0 = (int64_t(blockIdx.x) - (second ? nb1 : 0)) * spb;
   const int nloc = int(nslabs - s0 < spb ? nslabs - s0 : spb);
   // coalesced load
   for (int e = threadIdx.x; e < nloc * M::NN; e += blockDim.x) {
@@ -263,24 +270,28 @@ const cpx<float>* twiddles<float>(const Plan& p) {
 }
 
 template <int N, typename T>
-hipError_t fft_signed(const Plan& p, int sign, T sc, int64_t batch, const void* in, void* out, hipStream_t s) {
+hipError_t fft_signed(const Plan& p, int sign, T sc, int64_t batch, const void* in, void* out, hipStream_t s,
+                      const void* in2 = nullptr, void* out2 = nullptr) {
   if (batch <= 0) return hipSuccess;
   const int spb = tuned_spb<T>(N, p.tune.fft_spb);
   const size_t lds = size_t(spb) * MeshShape<N>::SLAB * sizeof(cpx<T>);
-  const int64_t blocks = (batch + spb - 1) / spb;
+  const int64_t blocks = (batch + spb - 1) / spb + (in2 ? (batch + spb - 1) / spb : 0);
   if (sign > 0)
     hipLaunchKernelGGL((k_lattice_fft<N, +1, T>), dim3(unsigned(blocks)), dim3(spb * N), lds, s,
-                       (const cpx<T>*)in, (cpx<T>*)out, batch, spb, twiddles<T>(p), sc);
+                       (const cpx<T>*)in, (cpx<T>*)out, batch, spb, twiddles<T>(p), sc, (const cpx<T>*)in2,
+                       (cpx<T>*)out2, batch);
   else
     hipLaunchKernelGGL((k_lattice_fft<N, -1, T>), dim3(unsigned(blocks)), dim3(spb * N), lds, s,
-                       (const cpx<T>*)in, (cpx<T>*)out, batch, spb, twiddles<T>(p), sc);
+                       (const cpx<T>*)in, (cpx<T>*)out, batch, spb, twiddles<T>(p), sc, (const cpx<T>*)in2,
+                       (cpx<T>*)out2, batch);
   return hipGetLastError();
 }
 
 // X(R) = (1/N_k) sum_k X(k) e^{+ik.R} for dir > 0, X(k) = sum_R X(R) e^{-ik.R} for dir < 0
 template <int N, typename T>
-hipError_t fft_n(const Plan& p, int dir, int64_t batch, const void* in, void* out, hipStream_t s) {
-  return fft_signed<N, T>(p, dir > 0 ? +1 : -1, dir > 0 ? T(1) / T(N * N) : T(1), batch, in, out, s);
+hipError_t fft_n(const Plan& p, int dir, int64_t batch, const void* in, void* out, hipStream_t s,
+                 const void* in2 = nullptr, void* out2 = nullptr) {
+  return fft_signed<N, T>(p, dir > 0 ? +1 : -1, dir > 0 ? T(1) / T(N * N) : T(1), batch, in, out, s, in2, out2);
 }
 
 template <int N, typename T>
@@ -339,6 +350,24 @@ hipError_t launch_lattice_fft(const Plan& p, int dir, int64_t batch, const void*
 #define QGW_CASE(NN) \
   case NN:           \
     return p.prec == 0 ? fft_n<NN, double>(p, dir, batch, in, out, s) : fft_n<NN, float>(p, dir, batch, in, out, s);
+    QGW_FOR_EACH_MESH(QGW_CASE)
+#undef QGW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_lattice_fft2(const Plan& p, int dir, int64_t batch, const void* in1, void* out1, const void* in2,
+                               void* out2, hipStream_t s) {
+  if (p.dim == 3) {
+    hipError_t e = launch_lattice_fft(p, dir, batch, in1, out1, s);
+    return e == hipSuccess ? launch_lattice_fft(p, dir, batch, in2, out2, s) : e;
+  }
+  switch (p.n) {
+#define QGW_CASE(NN)                                                                       \
+  case NN:                                                                                 \
+    return p.prec == 0 ? fft_n<NN, double>(p, dir, batch, in1, out1, s, in2, out2)         \
+                       : fft_n<NN, float>(p, dir, batch, in1, out1, s, in2, out2);
     QGW_FOR_EACH_MESH(QGW_CASE)
 #undef QGW_CASE
     default:

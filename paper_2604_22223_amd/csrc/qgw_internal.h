@@ -113,6 +113,9 @@ hipError_t launch_quasiparticle(const Plan& p, const void* h_k, const void* shf_
 // ---- kernels (each returns hipSuccess or the launch error) ----------------
 hipError_t launch_lattice_fft(const Plan& p, int dir, int64_t batch, const void* in, void* out,
                               hipStream_t s);
+// the same transform of two arrays of ``batch`` slabs each, in one launch on a square mesh
+hipError_t launch_lattice_fft2(const Plan& p, int dir, int64_t batch, const void* in1, void* out1, const void* in2,
+                               void* out2, hipStream_t s);
 hipError_t launch_bubble(const Plan& p, const void* g_tau_r, const void* g_reflt_r, int out_q,
                          void* out, hipStream_t s);
 hipError_t launch_sigma(const Plan& p, const void* g_tau_r, const void* wc, int in_q, int out_k,
