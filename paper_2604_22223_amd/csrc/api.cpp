@@ -1248,8 +1248,7 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     if (p.grid == kGridMF) {
       run(launch_mf_g_tau(p, st->G_iw, st->G_tau, st->G_reflt, s));  // one transform, both time orders
     } else {
-      run(launch_dlr(p, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G_iw, st->G_tau, s));
-      run(launch_dlr(p, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G_iw, st->G_reflt, s));
+      run(launch_dlr2(p, QGW_F_IW2TAU, QGW_F_IW2TAUR, ncol_g, st->G_iw, st->G_tau, st->G_reflt, s));
     }
     mark(2);  // a2
     run(launch_lattice_fft2(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, st->G_reflt, st->G_reflt, s));
@@ -1270,8 +1269,7 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     const Plan& q = st->p32;
     mark(1);
     run(launch_convert(ncol_g * p.r, st->G_iw, st->G32, 1, s));
-    run(launch_dlr(q, QGW_F_IW2TAU, ncol_g, 1.0, 0.0, st->G32, st->Gt32, s));
-    run(launch_dlr(q, QGW_F_IW2TAUR, ncol_g, 1.0, 0.0, st->G32, st->Gr32, s));
+    run(launch_dlr2(q, QGW_F_IW2TAU, QGW_F_IW2TAUR, ncol_g, st->G32, st->Gt32, st->Gr32, s));
     mark(2);
     run(launch_lattice_fft2(q, QGW_K_TO_R, no2 * p.r, st->Gt32, st->Gt32, st->Gr32, st->Gr32, s));
     mark(3);

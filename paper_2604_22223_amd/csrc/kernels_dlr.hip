@@ -253,7 +253,9 @@ __device__ __forceinline__ T dpp_identity(T v) {
 template <typename T, int MT, int MODE, bool HERM_IN>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dlr_mfma(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                                   const cpx<T>* __restrict__ map, int r, int kp, int na,
-                                                  int nq, int64_t nstrips, int no, T sre, T sim, int ysplit) {
+                                                  int nq, int64_t nstrips, int no, T sre, T sim, int ysplit,
+                                                  const cpx<T>* __restrict__ map2, cpx<T>* __restrict__ out2,
+                                                  int tiles_per_map) {
   using M = Mfma<T>;
   using v4 = typename M::v4;
   extern __shared__ unsigned char smem_raw[];
@@ -270,6 +272,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     tile = int(i % ysplit);
     group = (i / ysplit) * 8 + (blockIdx.x & 7);
     ngroups = gridDim.x / ysplit;
+  }
+  // a second map of the same input (map2, out2): the tiles from tiles_per_map on are its row tiles
+  if (map2 != nullptr && tile >= tiles_per_map) {
+    map = map2;
+    out = out2;
+    tile -= tiles_per_map;
   }
   const int row0 = tile * MT * 16;
   // operand order: entry ((k / 4) MT + mt) 64 + lane holds T[row0 + mt 16 + lane % 16][4 (k / 4) + lane / 16],
@@ -503,7 +511,7 @@ hipError_t dlr_mfma_pairs_launch(const Plan& p, int map, int na, int nq, double 
 // na x nq columns; HERM_IN: orbital arrays (na = n_o^2, nq = N_k)
 template <typename T, int MODE, bool HERM_IN>
 hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, double sim, const void* in,
-                           void* out, hipStream_t s, int64_t in_ld = 0) {
+                           void* out, hipStream_t s, int64_t in_ld = 0, int map2 = -1, void* out2 = nullptr) {
   const int kp = (p.r + 3) / 4 * 4;
   const int mt = (p.r + 15) / 16;
   if constexpr (MODE != kPlain) return dlr_mfma_pairs_launch<T, MODE>(p, map, na, nq, sre, sim, in, out, s, in_ld);
@@ -522,17 +530,23 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
   const int bpc = p.tune.mfma_bpc > 0 ? p.tune.mfma_bpc : 2;
   // too few strips for the GPU (the orbital-sized arrays): one block per row tile of a strip group, each
   // reading the same inputs (from L2) for its own 16 rows
-  const int ysplit = (blocks < 2 * int64_t(ncu)) ? mt : 1;
-  const int mtb = mt / ysplit;
+  const int tiles = (blocks < 2 * int64_t(ncu)) ? mt : 1;  // row-tile blocks per strip group and map
+  const int mtb = mt / tiles;
+  if (map2 >= 0 && tiles == 1) {  // a second map of the same input: one launch only when the row tiles are split
+    hipError_t e = dlr_mfma_launch<T, MODE, HERM_IN>(p, map, na, nq, sre, sim, in, out, s);
+    return e == hipSuccess ? dlr_mfma_launch<T, MODE, HERM_IN>(p, map2, na, nq, sre, sim, in, out2, s) : e;
+  }
+  const int ysplit = map2 >= 0 ? 2 * tiles : tiles;
   if (blocks > int64_t(bpc) * ncu) blocks = int64_t(bpc) * ncu;
   if (ysplit > 1) blocks = (blocks + 7) / 8 * 8 * ysplit;  // groups rounded up to a multiple of 8, ysplit blocks each
   const size_t lds = size_t(2) * mtb * 16 * kp * sizeof(T);
   const cpx<T>* mp = map_ptr<T>(p, map);
+  const cpx<T>* mp2 = map2 >= 0 ? map_ptr<T>(p, map2) : nullptr;
 #define QGW_MFMA_MT(MTV)                                                                                  \
   case MTV:                                                                                               \
     hipLaunchKernelGGL((k_dlr_mfma<T, MTV, MODE, HERM_IN>), dim3(unsigned(blocks)), dim3(512), lds, s,   \
                        (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, nstrips, p.no, T(sre), T(sim), \
-                       ysplit);                                                                            \
+                       ysplit, mp2, (cpx<T>*)out2, tiles);                                                 \
     break;
   switch (mtb) {
     QGW_MFMA_MT(1)
@@ -597,6 +611,17 @@ hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double 
   }
   if (p.prec == 0) return dlr_launch<double, kPlain, 0>(p, map, ncols, 0, 0, sre, sim, in, out, s);
   return dlr_launch<float, kPlain, 0>(p, map, ncols, 0, 0, sre, sim, in, out, s);
+}
+
+hipError_t launch_dlr2(const Plan& p, int map1, int map2, int64_t ncols, const void* in, void* out1, void* out2,
+                       hipStream_t s) {
+  if (p.grid == kGridDLR && p.r <= 64 && map1 != 5 && map2 != 5 && p.tune.orb_valu != 1 && ncols <= (int64_t(1) << 30)) {
+    if (p.prec == 0)
+      return dlr_mfma_launch<double, kPlain, false>(p, map1, 1, int(ncols), 1, 0, in, out1, s, 0, map2, out2);
+    return dlr_mfma_launch<float, kPlain, false>(p, map1, 1, int(ncols), 1, 0, in, out1, s, 0, map2, out2);
+  }
+  hipError_t e = launch_dlr(p, map1, ncols, 1.0, 0.0, in, out1, s);
+  return e == hipSuccess ? launch_dlr(p, map2, ncols, 1.0, 0.0, in, out2, s) : e;
 }
 
 hipError_t launch_dlr_pairs(const Plan& p, int map, int in_layout, int out_layout, const void* in,

@@ -123,6 +123,9 @@ hipError_t launch_sigma(const Plan& p, const void* g_tau_r, const void* wc, int 
 // herm: 0 plain, 1 Hermitian part of the input, 2 of the output (orbital arrays)
 hipError_t launch_dlr(const Plan& p, int map, int64_t ncols, double sre, double sim, const void* in,
                       void* out, hipStream_t s, int herm = 0);
+// two maps of the same input (scale 1), in one launch where the matrix-core path splits the map's row tiles
+hipError_t launch_dlr2(const Plan& p, int map1, int map2, int64_t ncols, const void* in, void* out1, void* out2,
+                       hipStream_t s);
 // in_ld: row stride (elements) of a matrix-layout input, 0 for N_b^2 (only the matrix-core path takes another)
 hipError_t launch_dlr_pairs(const Plan& p, int map, int in_layout, int out_layout, const void* in,
                             void* out, hipStream_t s, int64_t in_ld = 0);
