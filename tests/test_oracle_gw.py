@@ -174,6 +174,81 @@ def test_atomic_limit_kanamori(norb, U, J):
     assert np.abs(st["sig_hf_k"] - hf * np.eye(norb)[:, :, None, None]).max() < 1e-9
 
 
+
+def _atom_two_pole(norb, U, J, beta, level, mu):
+    """The closed form of one GW iteration at fixed mu from G0 in the flat-band Kanamori atom, carried through
+    Dyson's equation for G (Eq. full-green-freq) with the atom's Sigma^C = A / (i w - xi) and its Hartree-Fock
+    level shift h (derived in test_atomic_limit_kanamori):
+        G(i w) = 1 / (i w - xi - h - A / (i w - xi)),   xi = level - mu,
+    a two-pole function: with x_pm = xi + h/2 +- sqrt(h^2/4 + A), G = sum_pm w_pm / (i w - x_pm) and
+    w_pm = (x_pm - xi) / (x_pm - x_mp), so w_+ + w_- = 1 and the density is n = sum_pm w_pm f(beta x_pm)."""
+    xi = level - mu
+    f = float(fermi(beta * xi))
+    a = 2 * f * (1 - f)
+    Up = U - 2 * J
+    modes = [(U + (norb - 1) * Up, 1.0 / norb), (U - Up, (norb - 1) / norb)]
+    A = sum(wt * lam * lam * a / (1 + beta * a * lam) for lam, wt in modes)
+    A += (norb - 1) * 2 * a * J * J / (1 + 2 * beta * a * J)
+    h = f * (U + (norb - 1) * (2 * Up - J))
+    root = math.sqrt(0.25 * h * h + A)
+    xp, xm = xi + 0.5 * h + root, xi + 0.5 * h - root
+    wp, wm = (xp - xi) / (xp - xm), (xm - xi) / (xm - xp)
+    return xi, h, A, (xp, wp), (xm, wm)
+
+
+def _atom_iteration(norb, U, J, beta, level, mu):
+    w = wl.local_model((2, 2), [norb], [level] * norb, wl.kanamori(norb, U, J), beta, 20.0, 1e-12)
+    d = DLR(beta, 20.0, 1e-12)
+    m = model_of(w, n_target=None)
+    return d, gw.gw_iteration(m, d, gw.g0_fixed_mu(m, d, mu))
+
+
+@pytest.mark.parametrize("norb,U,J,level", [(1, 2.0, 0.0, 0.3), (3, 2.0, 0.4, 0.3), (2, 3.0, 0.5, -0.2)])
+def test_atom_dyson_g_with_sigma_two_poles(norb, U, J, level):
+    """Dyson G with a non-zero Sigma^C (Eq. full-green-freq): after one iteration at fixed mu the atom's G is the
+    two-pole function of _atom_two_pole at every DLR Matsubara node, orbital-diagonal, and its DLR density
+    -G(beta^-) is sum_pm w_pm f(beta x_pm).  A flipped sign of Sigma^C (or of Sigma_HF) in the Dyson equation
+    moves the poles, so both checks fail."""
+    beta, mu = 8.0, 0.0
+    d, st = _atom_iteration(norb, U, J, beta, level, mu)
+    xi, h, A, (xp, wp), (xm, wm) = _atom_two_pole(norb, U, J, beta, level, mu)
+    assert A > 0.01 and abs(wp + wm - 1.0) < 1e-14
+    g_exact = wp / (d.iw - xp) + wm / (d.iw - xm)
+    direct = 1.0 / (d.iw - xi - h - A / (d.iw - xi))
+    assert np.abs(g_exact - direct).max() < 1e-14
+    for i in range(norb):
+        # h comes from the DLR density of G0 (its accuracy ~1e-10), as in the Hartree-Fock check of the atom
+        assert np.abs(st["G_iw"][:, i, i, 0, 1] - g_exact).max() < 1e-9 * np.abs(g_exact).max()
+    off = st["G_iw"] - np.einsum("ab,t...->tab...", np.eye(norb), st["G_iw"][:, 0, 0])
+    assert np.abs(off).max() < 1e-11
+    n_exact = wp * float(fermi(beta * xp)) + wm * float(fermi(beta * xm))
+    n = gw.density_k(st["G_iw"], d)
+    assert np.abs(n - n_exact * np.eye(norb)[:, :, None, None]).max() < 1e-9
+
+
+def test_atom_dyson_g_planted_sign_flip_fails(monkeypatch):
+    """The two-pole pin catches a Dyson equation that adds Sigma instead of subtracting it (planted in the
+    oracle on the CPU): the G it produces differs from the closed form at O(A) at the low nodes."""
+    beta, mu, norb, U, J, level = 8.0, 0.0, 2, 3.0, 0.5, -0.2
+    good = gw.dyson_G
+
+    def flipped(H_k, sig_hf_k, sig_iw, iw, mu_):
+        return good(H_k, -sig_hf_k, None if sig_iw is None else -sig_iw, iw, mu_)
+
+    monkeypatch.setattr(gw, "dyson_G", flipped)
+    d, st = _atom_iteration(norb, U, J, beta, level, mu)
+    _, _, _, (xp, wp), (xm, wm) = _atom_two_pole(norb, U, J, beta, level, mu)
+    g_exact = wp / (d.iw - xp) + wm / (d.iw - xm)
+    assert np.abs(st["G_iw"][:, 0, 0, 0, 0] - g_exact).max() > 1e-2 * np.abs(g_exact).max()
+
+    def flipped_c(H_k, sig_hf_k, sig_iw, iw, mu_):
+        return good(H_k, sig_hf_k, None if sig_iw is None else -sig_iw, iw, mu_)
+
+    monkeypatch.setattr(gw, "dyson_G", flipped_c)
+    d, st = _atom_iteration(norb, U, J, beta, level, mu)
+    assert np.abs(st["G_iw"][:, 0, 0, 0, 0] - g_exact).max() > 1e-2 * np.abs(g_exact).max()
+
+
 def test_graphene_half_filling_mu():
     """Particle-hole symmetric graphene at half filling (on-site U, A-B
     nearest-neighbour V1 and same-sublattice next-nearest V2): the correlation
