@@ -351,20 +351,35 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
     log("[bench] batch: %d instances built in %.1f s (autotuning %.1f s)" % (count, setup, t_tune))
     res = {"instances": count, "launches": launches, "setup_s": round(setup, 2), "autotune_s": round(t_tune, 2),
            "mu_steps_per_iteration": mu_steps,
-           "recipe": "workloads.batch_sweep(%d): n_o 1-5, meshes 12^2-48^2, beta 10-100/eV, U 1-6 eV" % count}
+           "recipe": "workloads.batch_sweep(%d): n_o 1-5, meshes 12^2-48^2, beta 10-100/eV, U 1-6 eV" % count,
+           "legs": "each leg restarts every instance from G0 and times iterations 2 .. launches + 1 (one untimed)"}
+
+    def restart():
+        for st in states:
+            st.set_precision(0)
+            st.init_g0()
+        torch.cuda.synchronize()
+
     # one by one (eager), FP64
+    restart()
     for st in states:
         st.iterate(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    evals = 0
     for _ in range(launches):
         for st in states:
             st.iterate(1)
+            evals = max(evals, st.mu_evals())
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    res["eager_fp64"] = {"instance_iterations_per_s": round(count * launches / el, 2), "s_per_sweep": round(el / launches, 5)}
+    res["eager_fp64"] = {"instance_iterations_per_s": round(count * launches / el, 2), "s_per_sweep": round(el / launches, 5),
+                         "max_mu_evaluations": int(evals)}
     log("[bench] batch eager FP64: %.4f s per sweep of %d instances" % (el / launches, count))
+    labels = {"graph_fp64": "FP64 iterations", "graph_fp32": "single-precision bulk steps a1-a11 in every iteration "
+              "(the FP32 phase of the mixed schedule, without its FP64 finish: not a refined end point)"}
     for name, prec in (("graph_fp64", qgw.F64), ("graph_fp32", qgw.F32)):
+        restart()
         b = qgw.Batch(states, precision=prec, n_iter=1, mu_steps=mu_steps)
         for _ in range(warmup):
             b.launch()
@@ -374,11 +389,12 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
             b.launch()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        ds, mu, status = b.read()
+        ds, mu, status, evs = b.read(with_evals=True)
         res[name] = {"instance_iterations_per_s": round(count * launches / el, 2), "s_per_sweep": round(el / launches, 5),
-                     "unconverged_mu_searches": int(np.count_nonzero(status))}
-        log("[bench] batch %s: %.4f s per sweep (%d unconverged mu searches)" % (name, el / launches,
-                                                                              int(np.count_nonzero(status))))
+                     "unconverged_mu_searches": int(np.count_nonzero(status)), "max_mu_evaluations": int(evs.max()),
+                     "arithmetic": labels[name]}
+        log("[bench] batch %s: %.4f s per sweep (%d unconverged mu searches, at most %d evaluations)"
+            % (name, el / launches, int(np.count_nonzero(status)), int(evs.max())))
         b.close()
     for st in states:
         st.close()
@@ -401,7 +417,7 @@ def main():
                     help="timed iterations of the uniform-Matsubara-grid plans (0 skips them)")
     ap.add_argument("--paper-steps", type=int, default=20, metavar="K",
                     help="timed iterations of the paper's 8x8x8 five-orbital workload per schedule (0 skips it)")
-    ap.add_argument("--batch-mu-steps", type=int, default=20)
+    ap.add_argument("--batch-mu-steps", type=int, default=48)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer three times (a plain copy kernel of known size "
                          "that scales the HBM byte counters of a profiler run)")
@@ -528,7 +544,8 @@ def main():
         "data": "synthetic (seeded five-orbital model)",
         "config": {"workload": WORKLOAD, "mesh": "24x24", "n_orb": plan.n_o, "n_pair": plan.n_b,
                    "beta": w["beta"], "omega_max": w["omega_max"], "dlr_eps": w["eps"], "dlr_rank": plan.r,
-                   "U": 1.0, "J": 0.1, "V_nn": 0.2, "filling": w["n_target"], "tol": a.tol,
+                   "U": w["interaction"]["U"], "J": w["interaction"]["J"], "V_nn": w["interaction"]["V_nn"],
+                   "filling": w["n_target"], "tol": a.tol,
                    "path": "chosen: FP32 a1-a11 while |dSigma| > %g and falling, then FP64" % SWITCH_TOL,
                    "timed_work": "back-to-back self-consistent solves from G0 to |dSigma| <= tol"},
         "plain_fp64": {"value": round(value64, 3), "ms_per_step": round(1e3 * timed["fp64"]["elapsed"] / a.steps, 4)},

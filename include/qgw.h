@@ -35,10 +35,20 @@
  *
  * Streams.  ``stream`` is a hipStream_t passed as void* (NULL = the default
  * stream).  Compute calls only enqueue work, allocate nothing and return
- * once the work is queued, except qgw_dyson_G, which also returns the
- * chemical potential on the host and therefore waits for its stream, and
- * the adjoint calls marked "workspace", which allocate a plan-owned buffer
- * on their first use.
+ * once the work is queued.  Calls that return a value computed on the device
+ * to the host (the chemical potential, the energy, a status) wait for their
+ * stream; each such call says so.
+ *
+ * Scratch.  Calls marked "workspace" take caller-owned device scratch
+ * (``workspace``, ``workspace_bytes``) of at least the size
+ * qgw_workspace_size reports for the plan and the call, so the caller's
+ * allocator owns it.  It must stay valid until the queued work has run, and
+ * two calls in flight at once must not share it.  Too small or NULL (where
+ * bytes are needed): QGW_ERR_INVALID_ARG before anything is queued.
+ *
+ * Device conditions.  Kernels that meet a condition the host cannot check
+ * beforehand (a zero or non-finite pivot in the Dyson-W solve) set a bit in a
+ * plan-owned device status word; qgw_sync_status reads and clears it.
  */
 #ifndef QGW_H
 #define QGW_H
@@ -59,7 +69,19 @@ enum {
   QGW_ERR_DEVICE = 4,        /* HIP error, or no GPU                             */
   QGW_ERR_NOT_CONVERGED = 5, /* chemical potential search did not converge      */
   QGW_ERR_NONFINITE = 6,     /* NaN / Inf met (inputs or a singular solve)       */
-  QGW_ERR_ALLOC = 7          /* device or host allocation failed (plan set-up)  */
+  QGW_ERR_ALLOC = 7,         /* device or host allocation failed (plan set-up)  */
+  QGW_ERR_SINGULAR = 8       /* a Dyson-W system I - V P had a zero pivot        */
+};
+
+/* Calls that take caller-provided scratch (qgw_workspace_size). */
+enum {
+  QGW_OP_SIGMA_BWD = 0,         /* qgw_sigma_bwd with out_k = 1 (out_k = 0 needs none) */
+  QGW_OP_DYSON_W_BWD = 1,       /* qgw_dyson_W_bwd                                     */
+  QGW_OP_HARTREE_FOCK_BWD = 2,  /* qgw_hartree_fock_bwd                                */
+  QGW_OP_ENERGY = 3,            /* qgw_energy                                          */
+  QGW_OP_ENERGY_BWD = 4,        /* qgw_energy_bwd                                      */
+  QGW_OP_HF_DENSITY = 5,        /* qgw_hf_density                                      */
+  QGW_OP_QUASIPARTICLE = 6      /* qgw_quasiparticle                                   */
 };
 
 /* Arithmetic of the bulk arrays. */
@@ -203,6 +225,18 @@ qgw_status qgw_plan_autotune(qgw_plan plan, int32_t *choices, void *stream);
 qgw_status qgw_plan_sizes(qgw_plan plan, int32_t *rank, int32_t *n_o,
                           int32_t *n_b, int32_t *n_k);
 
+/* Bytes of caller-provided scratch that call ``op`` (QGW_OP_*) needs on this
+ * plan (0: none).  QGW_ERR_INVALID_ARG for an unknown op. */
+qgw_status qgw_workspace_size(qgw_plan plan, int32_t op, int64_t *bytes);
+
+/* Waits for ``stream``, then reads and clears the plan's device status word:
+ * QGW_ERR_SINGULAR if a Dyson-W solve on this plan (qgw_dyson_W, or a state
+ * iteration on it) met a zero or non-finite pivot since the last read
+ * (Eq. eq-screened-coulomb has no solution there; the affected W^C entries
+ * are non-finite), QGW_OK otherwise.  Calls on one plan from several streams
+ * share the word. */
+qgw_status qgw_sync_status(qgw_plan plan, void *stream);
+
 /* ------------------------------------------------------------ step calls */
 
 /* a1, a11, density row: out[m][c] = scale * sum_t T_map[m][t] in[t][c] for
@@ -237,7 +271,9 @@ qgw_status qgw_bubble(qgw_plan plan, const void *G_tau_R, const void *G_reflt_R,
 
 /* a6: W^C = (I - V P)^{-1} V - V for every (q, bosonic node), Gauss-Jordan
  * with partial pivoting.  V_q: [N_k][N_b][N_b]; P_nu, Wc_nu: pair matrix
- * layout.  A zero pivot yields non-finite output (see qgw_check_finite). */
+ * layout.  A zero or non-finite pivot yields non-finite output for that
+ * matrix and sets the plan's device status word (qgw_sync_status reports
+ * QGW_ERR_SINGULAR). */
 qgw_status qgw_dyson_W(qgw_plan plan, const void *V_q, const void *P_nu,
                        void *Wc_nu, void *stream);
 
@@ -274,10 +310,8 @@ qgw_status qgw_dyson_G(qgw_plan plan, const void *H_k, const void *Sig_iw,
  * array z is zbar = dL/dRe z + i dL/dIm z (the convention of PyTorch's
  * complex autograd), so a complex-linear y = A x has xbar = A^H ybar.  Every
  * call overwrites its outputs (callers add branches themselves); shapes and
- * layouts are those of the forward call.  Calls marked "workspace" use a
- * plan-owned device buffer that is allocated, or grown, on the first call
- * that needs it: such calls are not graph-capturable the first time, and
- * calls on one plan from several streams at once race on it. */
+ * layouts are those of the forward call.  Calls marked "workspace" take the
+ * caller's scratch (see the file header). */
 
 /* a15: adjoint of qgw_dlr_transform with the same map, ncols, scale and
  * hermitian mode: xbar = herm_in(conj(scale) T^H herm_out(ybar)).  For
@@ -312,27 +346,30 @@ qgw_status qgw_bubble_bwd(qgw_plan plan, const void *G_tau_R, const void *G_refl
  *   Wcbar_{(il),(jk)}(R) = -conj(G_lj(R)) Sbar_ik(R),  then to q
  *   Gbar_lj(R)          = -sum_{ik} conj(W^C_{(il),(jk)}(R)) Sbar_ik(R)
  * Sigbar in k (out_k = 1) or R; Wc_q and Wcbar_q pair slabs in q; Gbar_tau_R
- * orbital layout in R.  Workspace (r n_o^2 N_k complex) when out_k = 1. */
+ * orbital layout in R.  Workspace (r n_o^2 N_k complex, QGW_OP_SIGMA_BWD)
+ * when out_k = 1; it must not overlap any array of the call. */
 qgw_status qgw_sigma_bwd(qgw_plan plan, const void *G_tau_R, const void *Wc_q,
                          int32_t out_k, const void *Sigbar, void *Gbar_tau_R,
-                         void *Wcbar_q, void *stream);
+                         void *Wcbar_q, void *workspace, int64_t workspace_bytes,
+                         void *stream);
 
 /* a18: adjoint of qgw_dyson_W (Eq. eq-screened-coulomb).  With A = I - V P,
  * W = A^{-1} V and Wbar the cotangent of W^C = W - V:
  *   Pbar = W^H Wbar W^H,   Vbar = sum over nodes [A^{-H} Wbar (I + P W)^H - Wbar].
  * V_q, Vbar_q: [N_k][N_b][N_b]; P_nu, Wcbar_nu, Pbar_nu: pair matrix
  * layout.  The node sum runs in a fixed order (deterministic).  Workspace
- * (min(r, 8) N_b^2 N_k complex). */
+ * (min(r, 8) N_b^2 N_k complex, QGW_OP_DYSON_W_BWD). */
 qgw_status qgw_dyson_W_bwd(qgw_plan plan, const void *V_q, const void *P_nu,
                            const void *Wcbar_nu, void *Pbar_nu, void *Vbar_q,
-                           void *stream);
+                           void *workspace, int64_t workspace_bytes, void *stream);
 
 /* a12 adjoint: cotangents of n(R) and V(R) for a cotangent Sbar_R of the
  * Hartree-Fock self-energy (Eqs. eq-hartree-self-energy,
- * eq-fock-self-energy).  Either output may be NULL.  Workspace (N_b^2). */
+ * eq-fock-self-energy).  Either output may be NULL.  Workspace (N_b^2
+ * complex, QGW_OP_HARTREE_FOCK_BWD). */
 qgw_status qgw_hartree_fock_bwd(qgw_plan plan, const void *V_R, const void *n_R,
                                 const void *Sbar_R, void *nbar_R, void *Vbar_R,
-                                void *stream);
+                                void *workspace, int64_t workspace_bytes, void *stream);
 
 /* a20: adjoint of qgw_dyson_G at the chemical potential mu it returned.
  * With X = H + Sigma: Sigbar = G^H Gbar G^H at every (node, k).  If
@@ -358,24 +395,28 @@ qgw_status qgw_pair_layout(qgw_plan plan, int32_t in_layout, int32_t out_layout,
  *       + 1/N_k sum_k Re (1/beta) sum_n Tr[Sigma^C(i w_n) G(i w_n)]
  * with n = Herm(-G(beta^-)) and the Matsubara sum over all n taken exactly
  * from the DLR expansions (map QGW_F_IW2GM).  e_out[3] = (E, HF part,
- * correlation part).  Waits for ``stream``.  Workspace. */
+ * correlation part).  Waits for ``stream``.  Workspace (QGW_OP_ENERGY). */
 qgw_status qgw_energy(qgw_plan plan, const void *H_k, const void *SigHF_k,
-                      const void *Sig_iw, const void *G_iw, double *e_out, void *stream);
+                      const void *Sig_iw, const void *G_iw, double *e_out,
+                      void *workspace, int64_t workspace_bytes, void *stream);
 
 /* Adjoint of qgw_energy's E for a cotangent ebar: writes Hbar, SigHFbar
- * (static orbital layout), Sigbar and Gbar (orbital layout).  Workspace. */
+ * (static orbital layout), Sigbar and Gbar (orbital layout).  Workspace
+ * (QGW_OP_ENERGY_BWD). */
 qgw_status qgw_energy_bwd(qgw_plan plan, const void *H_k, const void *SigHF_k,
                           const void *Sig_iw, const void *G_iw, double ebar, void *Hbar,
-                          void *SigHFbar, void *Sigbar, void *Gbar, void *stream);
+                          void *SigHFbar, void *Sigbar, void *Gbar, void *workspace,
+                          int64_t workspace_bytes, void *stream);
 
 /* Hartree-Fock density of a static Hamiltonian (Fig. fig-self (a), H class
  * paragraph), FP64 plans: for H_k [n_o][n_o][N_k] (its Hermitian part is
  * used) writes n_k = U f(beta (eps - mu)) U^H, f(x) = 1 / (e^x + 1), with
  * H(k) = U diag(eps) U^H per k.  mu (in/out) is found by bisection to the
  * target filling N_e = (2 / N_k) sum_{k,n} f(beta (eps_n(k) - mu)), or is
- * used as given if n_target is NaN.  Waits for ``stream``.  Workspace. */
+ * used as given if n_target is NaN.  Waits for ``stream``.  Workspace
+ * (QGW_OP_HF_DENSITY). */
 qgw_status qgw_hf_density(qgw_plan plan, const void *H_k, double n_target, double *mu,
-                          void *n_k, void *stream);
+                          void *n_k, void *workspace, int64_t workspace_bytes, void *stream);
 
 /* Quasiparticle post-processing (Z class, SigStc class, Eq. eq-z-factor,
  * Eq. eq-quasi-particle-Hamiltonian), FP64 plans.  The zero-frequency limit
@@ -391,12 +432,13 @@ qgw_status qgw_hf_density(qgw_plan plan, const void *H_k, double n_target, doubl
  * mu = 0 is the equation as printed; the chemical potential puts the bands
  * relative to the Fermi level.  H_k, SigHF_k: [n_o][n_o][N_k]; Sig_iw:
  * [r][n_o][n_o][N_k] (orbital layout); outputs Sig0, Z, Hqp: [n_o][n_o][N_k]
- * complex; bands: [n_o][N_k] double.  Waits for ``stream``.  Workspace.
- * QGW_ERR_NONFINITE if Z^{-1}(k) is not positive definite at some k (the
- * outputs there are not meaningful). */
+ * complex; bands: [n_o][N_k] double.  Waits for ``stream``.  Workspace
+ * (QGW_OP_QUASIPARTICLE).  QGW_ERR_NONFINITE if Z^{-1}(k) is not positive
+ * definite at some k (the outputs there are not meaningful). */
 qgw_status qgw_quasiparticle(qgw_plan plan, const void *H_k, const void *SigHF_k,
                              const void *Sig_iw, double mu, void *Sig0, void *Z, void *Hqp,
-                             double *bands, void *stream);
+                             double *bands, void *workspace, int64_t workspace_bytes,
+                             void *stream);
 
 /* out = a + b over ``count`` complex FP64 entries (the static H0(k) +
  * Sigma_HF(k) of the Dyson equation for G); out may alias a or b. */
@@ -421,7 +463,14 @@ qgw_status qgw_state_init_g0(qgw_state state, double *mu, void *stream);
 
 /* Runs up to n_iter GW iterations (Fig. fig-self (b): a1 .. a14), stopping
  * early once max |Delta Sigma| <= tol.  Outputs (any may be NULL): the
- * number of iterations done, the last max |Delta Sigma| and mu. */
+ * number of iterations done, the last max |Delta Sigma| and mu.  Waits for
+ * ``stream`` once per iteration (mu and max |Delta Sigma| come back).
+ * Errors: QGW_ERR_SINGULAR if a Dyson-W system met a zero or non-finite
+ * pivot, QGW_ERR_NONFINITE if max |Delta Sigma| is not finite (any NaN in
+ * Sigma counts), QGW_ERR_NOT_CONVERGED if the chemical-potential search
+ * failed.  After an error the state's arrays are not one consistent
+ * iterate: further iterations are refused (QGW_ERR_INVALID_ARG) until
+ * qgw_state_init_g0 or qgw_state_hf_solve restarts the state. */
 qgw_status qgw_gw_iteration(qgw_state state, int32_t n_iter, double tol,
                             int32_t *iters_done, double *d_sigma, double *mu,
                             void *stream);
@@ -437,7 +486,9 @@ qgw_status qgw_gw_iteration(qgw_state state, int32_t n_iter, double tol,
  * mu in the state and G = [(i w + mu) - H0 - Sigma_HF]^{-1} with
  * Sigma^C = 0, so a GW solve can continue from the HF solution.  Outputs
  * (any may be NULL): passes done, the last max |Delta Sigma_HF|, mu.
- * Waits for ``stream``.  Uses the plan workspace. */
+ * Waits for ``stream``; uses scratch the state owns.  QGW_ERR_NONFINITE if
+ * the change of Sigma_HF, mu or the filling is not finite (the state then
+ * needs a restart, as after a failed qgw_gw_iteration). */
 qgw_status qgw_state_hf_solve(qgw_state state, double tol, int32_t max_iter,
                               int32_t *iters_done, double *d_sigma, double *mu,
                               void *stream);
@@ -463,9 +514,12 @@ qgw_status qgw_state_copy(qgw_state state, int32_t which, void *dst, int64_t *by
  * call with mode 1 or 2 allocates the single-precision buffers. */
 qgw_status qgw_state_set_precision(qgw_state state, int32_t mode, double switch_tol);
 
-/* Precision used by the last iteration (0 FP64, 1 FP32) and the number of
- * FP32 and FP64 iterations since qgw_state_init_g0. */
-qgw_status qgw_state_info(qgw_state state, int32_t *last_prec, int32_t *n_fp32, int32_t *n_fp64);
+/* Precision used by the last iteration (0 FP64, 1 FP32), the number of FP32
+ * and FP64 iterations since qgw_state_init_g0, and the number of N_e(mu)
+ * evaluations the last iteration's chemical-potential search took.  Any
+ * output pointer may be NULL. */
+qgw_status qgw_state_info(qgw_state state, int32_t *last_prec, int32_t *n_fp32, int32_t *n_fp64,
+                          int32_t *mu_evals);
 
 /* Per-step timing of qgw_gw_iteration with HIP events on the caller's
  * stream.  mode 1 resets the accumulators and enables timing, mode 0
@@ -491,24 +545,31 @@ qgw_status qgw_state_profile(qgw_state state, int32_t mode, double *ms, int32_t 
  * from the capture stream, so independent instances run concurrently, and
  * each state's iterations stay in order.  Inside the graph the chemical
  * potential search is a fixed chain of mu_steps Newton evaluations per
- * iteration that starts from the state's current mu (steps after
- * convergence return at once); a search that has not converged by then
- * sets the state's status to 2.  The Dyson-G step is the same search as
- * qgw_gw_iteration (same grid, same summation order).  precision 0 records
- * FP64 iterations; 1 records the single-precision form of steps a1-a11 (the
- * FP32 phase of the mixed solve).  Every state must have been started
- * (qgw_state_init_g0) before the first launch, must not be profiling, and
- * must not be used by other calls while a launch is in flight.  Each call of
- * qgw_batch_launch replays the graph on ``stream`` (no host
- * synchronisation); qgw_batch_read waits for ``stream`` and returns, per
- * state, the last max |Delta Sigma|, mu and status (0 ok, 1 no finite mu to
- * start from, 2 search not converged). */
+ * iteration (steps after convergence return at once).  It starts from the
+ * state's current mu moved by the change of the mean diagonal of
+ * H0 + Sigma_HF since the state's previous search (the level shift of a
+ * change of Sigma_HF), as the eager search does; it is the same search as
+ * qgw_gw_iteration (same grid, same summation order).  A search that has
+ * not converged after mu_steps evaluations raises the state's sticky status
+ * word to 2 (the graph continues; that iteration's G is at an unconverged
+ * mu).  precision 0 records FP64 iterations; 1 records the single-precision
+ * form of steps a1-a11 (the FP32 phase of the mixed solve, without its FP64
+ * finish).  Every state must have been started (qgw_state_init_g0) and not
+ * be waiting for a restart, must not be profiling, and must not be used by
+ * other calls while a launch is in flight.  Each call of qgw_batch_launch
+ * replays the graph on ``stream`` (no host synchronisation); qgw_batch_read
+ * waits for ``stream`` and returns, per state, the last max |Delta Sigma|,
+ * mu, the worst search status of all replays since the previous read (0 ok,
+ * 1 no finite mu to start from, 2 search not converged; the word is then
+ * cleared, and a state with a non-zero status needs a restart before eager
+ * iterations) and the evaluations its last search took.  Any output pointer
+ * of qgw_batch_read may be NULL. */
 typedef struct qgw_batch_s *qgw_batch;
 qgw_status qgw_batch_create(int32_t n, const qgw_state *states, int32_t precision,
                             int32_t n_iter, int32_t mu_steps, qgw_batch *batch);
 qgw_status qgw_batch_launch(qgw_batch batch, void *stream);
 qgw_status qgw_batch_read(qgw_batch batch, double *d_sigma, double *mu, int32_t *status,
-                          void *stream);
+                          int32_t *evals, void *stream);
 qgw_status qgw_batch_destroy(qgw_batch batch);
 
 /* Checks ``count`` complex values (precision of the plan) for NaN/Inf;

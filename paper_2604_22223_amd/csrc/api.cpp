@@ -34,6 +34,7 @@ struct qgw_state_s {
   void *G_tau = nullptr, *G_reflt = nullptr, *Sig_tau_k = nullptr;
   // pair
   void *Pq = nullptr, *P_nu = nullptr, *Wc_nu = nullptr;
+  void* hf_ws = nullptr;  // Hartree-Fock solve: eigenvectors and eigenvalues per k
   double* d_dsig = nullptr;
   double* d_blockmax = nullptr;
   // chemical-potential search of this state: scalars [16], partial sums, status
@@ -41,6 +42,7 @@ struct qgw_state_s {
   double* d_part = nullptr;
   int* d_stat = nullptr;
   int mu_steps0 = 10;  // Newton steps queued in the first round of the next search
+  int last_evals = 0;  // evaluations the last search took
   // pinned host words of the search's per-iteration exchange (start point in, result out) and the
   // event the host polls for the result: no staging copy and no blocking wait per iteration
   double* h_io = nullptr;
@@ -55,6 +57,8 @@ struct qgw_state_s {
   bool in_fp32 = false;
   int n_fp32 = 0, n_fp64 = 0, last_prec = 0;
   double last_dsig = INFINITY;
+  // set when an iteration fails part-way (its arrays are then not one consistent state); cleared by a restart
+  bool broken = false;
   // per-step timing with HIP events on the caller's stream
   bool prof = false;
   hipEvent_t ev[QGW_NUM_STEPS + 1] = {};
@@ -128,7 +132,7 @@ static void free_plan_device(Plan& p) {
     p.dmaps64.m[m] = p.dmaps32.m[m] = nullptr;
   }
   void* ptrs[] = {p.d_tw64, p.d_tw32, p.d_pairs, p.terms.d_terms, p.terms.d_off, p.terms_lj.d_terms,
-                  p.terms_lj.d_off, p.d_wn, p.d_qp_row, p.d_partials, p.d_status, p.d_scalars, p.d_ws, p.d_mf};
+                  p.terms_lj.d_off, p.d_wn, p.d_qp_row, p.d_partials, p.d_status, p.d_scalars, p.d_mf};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   p.d_tw64 = nullptr;
@@ -136,8 +140,6 @@ static void free_plan_device(Plan& p) {
   p.d_pairs = nullptr;
   p.terms.d_terms = p.terms.d_off = nullptr;
   p.terms_lj.d_terms = p.terms_lj.d_off = nullptr;
-  p.d_ws = nullptr;
-  p.ws_bytes = 0;
   p.d_wn = nullptr;
   p.d_qp_row = nullptr;
   p.d_partials = nullptr;
@@ -487,6 +489,7 @@ static qgw_status plan_create_impl(const qgw_plan_desc* d, int mf_nodes, qgw_pla
     e = hipMalloc((void**)&p.d_partials, size_t(2) * 4 * p.max_blocks * sizeof(double));
   }
   if (e == hipSuccess) e = hipMalloc((void**)&p.d_status, 16 * sizeof(int));
+  if (e == hipSuccess) e = hipMemset(p.d_status, 0, 16 * sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&p.d_scalars, 32 * sizeof(double));
   if (e != hipSuccess) {
     set_error(std::string("qgw_plan_create: ") + hipGetErrorString(e));
@@ -633,7 +636,7 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
                               double* mu, void* G_iw, hipStream_t s, double* evals, double* scal = nullptr,
                               double* part = nullptr, int* stat = nullptr, const double* extra_src = nullptr,
                               double* extra_dst = nullptr, hipEvent_t end_ev = nullptr, int steps0 = 6,
-                              double* h_io = nullptr, hipEvent_t io_ev = nullptr) {
+                              double* h_io = nullptr, hipEvent_t io_ev = nullptr, int track = 0) {
   const int mode = std::isnan(n_target) ? 0 : 1;
   if (!scal) {
     scal = p.d_scalars;
@@ -652,7 +655,7 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
   QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, 2 * sizeof(double), hipMemcpyHostToDevice, s), "qgw_dyson_G");
   // the search's first launch resets the status word; a fixed-mu call has no search
   if (mode == 1)
-    QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, s), "qgw_dyson_G");
+    QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, track, s), "qgw_dyson_G");
   else
     QGW_CHECK_HIP(hipMemsetAsync(stat, 0, sizeof(int), s), "qgw_dyson_G");
   // scal[0..9]: mu, n_target, evaluations, N_e, search state, status, extra
@@ -717,19 +720,39 @@ qgw_status qgw_dyson_G(qgw_plan h, const void* H_k, const void* Sig_iw, double n
 
 // ------------------------------------------------------------------ adjoints
 
-static hipError_t ensure_ws(Plan& p, size_t bytes) {
-  if (p.ws_bytes >= bytes) return hipSuccess;
-  if (p.d_ws) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return e;
-    (void)hipFree(p.d_ws);
-    p.d_ws = nullptr;
-    p.ws_bytes = 0;
+// bytes of caller-provided scratch each call needs on plan p (0: none)
+static int64_t workspace_need(const Plan& p, int op) {
+  const int64_t so = int64_t(p.no) * p.no * p.nk * int64_t(sizeof(zd));  // static orbital array
+  const int64_t se = int64_t(p.no) * p.nk * int64_t(sizeof(double));     // one energy per band and k
+  const int64_t fo = so * p.r;                                           // orbital array with nodes
+  switch (op) {
+    case QGW_OP_SIGMA_BWD:
+      return fo;  // Sigma-bar(k) -> R
+    case QGW_OP_DYSON_W_BWD:
+      return int64_t(p.r < 8 ? p.r : 8) * p.nb * p.nb * p.nk * int64_t(sizeof(zd));  // V-bar partials per chunk
+    case QGW_OP_HARTREE_FOCK_BWD:
+      return int64_t(p.nb) * p.nb * int64_t(sizeof(zd));  // V(q = 0)
+    case QGW_OP_ENERGY:
+      return 2 * so + fo + int64_t(2) * 4096 * int64_t(sizeof(double)) + 64;  // n, y, block partials, sums
+    case QGW_OP_ENERGY_BWD:
+      return 2 * so + 2 * fo;  // n, n-bar, y, y-bar
+    case QGW_OP_HF_DENSITY:
+      return so + se + 64 * int64_t(sizeof(double));  // eigenvectors, eigenvalues, search scalars, status
+    case QGW_OP_QUASIPARTICLE:
+      return 64;  // status flag
+    default:
+      return -1;
   }
-  hipError_t e = hipMalloc(&p.d_ws, bytes);
-  if (e == hipSuccess) p.ws_bytes = bytes;
-  return e;
 }
+
+// the caller's scratch for op: non-null and at least the size qgw_workspace_size reports
+#define QGW_WORKSPACE(op, ws, ws_bytes, name)                                                          \
+  do {                                                                                                 \
+    const int64_t need_ = workspace_need(p, op);                                                      \
+    QGW_REQUIRE(need_ == 0 || (ws && ws_bytes >= need_), QGW_ERR_INVALID_ARG,                          \
+                std::string(name) + ": workspace of " + std::to_string(need_) + " bytes required (" +  \
+                    std::to_string(ws ? ws_bytes : 0) + " given)");                                   \
+  } while (0)
 
 #define QGW_BWD_PLAN(h, name)                                                                        \
   QGW_PLAN(h, name);                                                                                 \
@@ -797,7 +820,7 @@ qgw_status qgw_bubble_bwd(qgw_plan h, const void* gt, const void* gr, const void
 }
 
 qgw_status qgw_sigma_bwd(qgw_plan h, const void* gt, const void* wc_q, int32_t out_k, const void* Sigbar,
-                         void* Gbar_tau, void* Wcbar_q, void* stream) {
+                         void* Gbar_tau, void* Wcbar_q, void* workspace, int64_t workspace_bytes, void* stream) {
   QGW_BWD_PLAN(h, "qgw_sigma_bwd");
   QGW_REQUIRE(gt && wc_q && Sigbar && Gbar_tau && Wcbar_q, QGW_ERR_INVALID_ARG, "qgw_sigma_bwd: null array");
   QGW_REQUIRE(Gbar_tau != gt && Wcbar_q != wc_q && Gbar_tau != Wcbar_q, QGW_ERR_INVALID_ARG,
@@ -805,11 +828,12 @@ qgw_status qgw_sigma_bwd(qgw_plan h, const void* gt, const void* wc_q, int32_t o
   hipStream_t s = (hipStream_t)stream;
   const void* sbar_r = Sigbar;
   if (out_k) {
-    const size_t bytes = size_t(p.r) * p.no * p.no * p.nk * sizeof(zd);
-    QGW_CHECK_HIP(ensure_ws(h->p, bytes), "qgw_sigma_bwd: workspace");
-    QGW_CHECK_HIP(launch_lattice_fft_scaled(p, +1, 1.0, int64_t(p.r) * p.no * p.no, Sigbar, p.d_ws, s),
+    QGW_WORKSPACE(QGW_OP_SIGMA_BWD, workspace, workspace_bytes, "qgw_sigma_bwd");
+    QGW_REQUIRE(workspace != gt && workspace != wc_q && workspace != Sigbar && workspace != Gbar_tau &&
+                    workspace != Wcbar_q, QGW_ERR_INVALID_ARG, "qgw_sigma_bwd: workspace aliases an array");
+    QGW_CHECK_HIP(launch_lattice_fft_scaled(p, +1, 1.0, int64_t(p.r) * p.no * p.no, Sigbar, workspace, s),
                   "qgw_sigma_bwd");
-    sbar_r = p.d_ws;
+    sbar_r = workspace;
   }
   QGW_CHECK_HIP(launch_contract_bwd(p, 0, wc_q, sbar_r, Gbar_tau, s), "qgw_sigma_bwd");
   QGW_CHECK_HIP(launch_sigma_bwd_wc(p, gt, sbar_r, Wcbar_q, s), "qgw_sigma_bwd");
@@ -817,28 +841,28 @@ qgw_status qgw_sigma_bwd(qgw_plan h, const void* gt, const void* wc_q, int32_t o
 }
 
 qgw_status qgw_dyson_W_bwd(qgw_plan h, const void* V_q, const void* P_nu, const void* Wcbar_nu, void* Pbar_nu,
-                           void* Vbar_q, void* stream) {
+                           void* Vbar_q, void* workspace, int64_t workspace_bytes, void* stream) {
   QGW_BWD_PLAN(h, "qgw_dyson_W_bwd");
   QGW_REQUIRE(V_q && P_nu && Wcbar_nu && Pbar_nu && Vbar_q, QGW_ERR_INVALID_ARG, "qgw_dyson_W_bwd: null array");
   QGW_REQUIRE(Pbar_nu != P_nu && Pbar_nu != Wcbar_nu && Vbar_q != V_q, QGW_ERR_INVALID_ARG,
               "qgw_dyson_W_bwd: outputs alias inputs");
   const int chunks = p.r < 8 ? p.r : 8;
   const int64_t nv = int64_t(p.nb) * p.nb * p.nk;
-  QGW_CHECK_HIP(ensure_ws(h->p, size_t(chunks) * nv * sizeof(zd)), "qgw_dyson_W_bwd: workspace");
+  QGW_WORKSPACE(QGW_OP_DYSON_W_BWD, workspace, workspace_bytes, "qgw_dyson_W_bwd");
   hipStream_t s = (hipStream_t)stream;
-  QGW_CHECK_HIP(launch_dyson_w_bwd(p, V_q, P_nu, Wcbar_nu, Pbar_nu, p.d_ws, chunks, s), "qgw_dyson_W_bwd");
-  QGW_CHECK_HIP(launch_sum_chunks(nv, chunks, p.d_ws, Vbar_q, s), "qgw_dyson_W_bwd");
+  QGW_CHECK_HIP(launch_dyson_w_bwd(p, V_q, P_nu, Wcbar_nu, Pbar_nu, workspace, chunks, s), "qgw_dyson_W_bwd");
+  QGW_CHECK_HIP(launch_sum_chunks(nv, chunks, workspace, Vbar_q, s), "qgw_dyson_W_bwd");
   return QGW_OK;
 }
 
 qgw_status qgw_hartree_fock_bwd(qgw_plan h, const void* V_R, const void* n_R, const void* Sbar_R, void* nbar_R,
-                                void* Vbar_R, void* stream) {
+                                void* Vbar_R, void* workspace, int64_t workspace_bytes, void* stream) {
   QGW_BWD_PLAN(h, "qgw_hartree_fock_bwd");
   QGW_REQUIRE(V_R && n_R && Sbar_R && (nbar_R || Vbar_R), QGW_ERR_INVALID_ARG, "qgw_hartree_fock_bwd: null array");
-  QGW_CHECK_HIP(ensure_ws(h->p, size_t(p.nb) * p.nb * sizeof(zd)), "qgw_hartree_fock_bwd: workspace");
+  QGW_WORKSPACE(QGW_OP_HARTREE_FOCK_BWD, workspace, workspace_bytes, "qgw_hartree_fock_bwd");
   hipStream_t s = (hipStream_t)stream;
-  QGW_CHECK_HIP(launch_pair_sum_r(p, V_R, p.d_ws, s), "qgw_hartree_fock_bwd");
-  QGW_CHECK_HIP(launch_hartree_fock_bwd(p, V_R, p.d_ws, n_R, Sbar_R, nbar_R, Vbar_R, s), "qgw_hartree_fock_bwd");
+  QGW_CHECK_HIP(launch_pair_sum_r(p, V_R, workspace, s), "qgw_hartree_fock_bwd");
+  QGW_CHECK_HIP(launch_hartree_fock_bwd(p, V_R, workspace, n_R, Sbar_R, nbar_R, Vbar_R, s), "qgw_hartree_fock_bwd");
   return QGW_OK;
 }
 
@@ -858,13 +882,13 @@ qgw_status qgw_dyson_G_bwd(qgw_plan h, const void* H_k, const void* Sig_iw, doub
 // ---------------------------------------------------------------- energy
 
 qgw_status qgw_energy(qgw_plan h, const void* H_k, const void* SigHF_k, const void* Sig_iw, const void* G_iw,
-                      double* e_out, void* stream) {
+                      double* e_out, void* workspace, int64_t workspace_bytes, void* stream) {
   QGW_BWD_PLAN(h, "qgw_energy");
   QGW_REQUIRE(H_k && SigHF_k && Sig_iw && G_iw && e_out, QGW_ERR_INVALID_ARG, "qgw_energy: null argument");
   const size_t so = size_t(p.no) * p.no * p.nk * sizeof(zd);
   const size_t fo = so * p.r;
-  QGW_CHECK_HIP(ensure_ws(h->p, 2 * so + fo + size_t(2) * 8192 * sizeof(double) + 64), "qgw_energy: workspace");
-  char* ws = (char*)p.d_ws;
+  QGW_WORKSPACE(QGW_OP_ENERGY, workspace, workspace_bytes, "qgw_energy");
+  char* ws = (char*)workspace;
   void* n_k = ws;
   void* y = ws + 2 * so;
   double* part = (double*)(ws + 2 * so + fo);
@@ -886,7 +910,8 @@ qgw_status qgw_energy(qgw_plan h, const void* H_k, const void* SigHF_k, const vo
 }
 
 qgw_status qgw_energy_bwd(qgw_plan h, const void* H_k, const void* SigHF_k, const void* Sig_iw, const void* G_iw,
-                          double ebar, void* Hbar, void* SigHFbar, void* Sigbar, void* Gbar, void* stream) {
+                          double ebar, void* Hbar, void* SigHFbar, void* Sigbar, void* Gbar, void* workspace,
+                          int64_t workspace_bytes, void* stream) {
   QGW_BWD_PLAN(h, "qgw_energy_bwd");
   QGW_REQUIRE(H_k && SigHF_k && Sig_iw && G_iw && Hbar && SigHFbar && Sigbar && Gbar, QGW_ERR_INVALID_ARG,
               "qgw_energy_bwd: null argument");
@@ -894,8 +919,8 @@ qgw_status qgw_energy_bwd(qgw_plan h, const void* H_k, const void* SigHF_k, cons
               "qgw_energy_bwd: outputs alias inputs");
   const size_t so = size_t(p.no) * p.no * p.nk * sizeof(zd);
   const size_t fo = so * p.r;
-  QGW_CHECK_HIP(ensure_ws(h->p, 2 * so + 2 * fo), "qgw_energy_bwd: workspace");
-  char* ws = (char*)p.d_ws;
+  QGW_WORKSPACE(QGW_OP_ENERGY_BWD, workspace, workspace_bytes, "qgw_energy_bwd");
+  char* ws = (char*)workspace;
   void* n_k = ws;
   void* nbar = ws + so;
   void* y = ws + 2 * so;
@@ -914,7 +939,8 @@ qgw_status qgw_energy_bwd(qgw_plan h, const void* H_k, const void* SigHF_k, cons
 
 // ----------------------------------------------------------- Hartree-Fock
 
-qgw_status qgw_hf_density(qgw_plan h, const void* H_k, double n_target, double* mu, void* n_k, void* stream) {
+qgw_status qgw_hf_density(qgw_plan h, const void* H_k, double n_target, double* mu, void* n_k, void* workspace,
+                          int64_t workspace_bytes, void* stream) {
   QGW_PLAN(h, "qgw_hf_density");
   QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_hf_density: FP64 plans only");
   QGW_REQUIRE(H_k && mu && n_k, QGW_ERR_INVALID_ARG, "qgw_hf_density: null argument");
@@ -925,8 +951,8 @@ qgw_status qgw_hf_density(qgw_plan h, const void* H_k, double n_target, double* 
     QGW_REQUIRE(std::isfinite(*mu), QGW_ERR_INVALID_ARG, "qgw_hf_density: fixed mu must be finite");
   const size_t so = size_t(p.no) * p.no * p.nk * sizeof(zd);
   const size_t se = size_t(p.no) * p.nk * sizeof(double);
-  QGW_CHECK_HIP(ensure_ws(h->p, so + se + 64 * sizeof(double)), "qgw_hf_density: workspace");
-  char* ws = (char*)p.d_ws;
+  QGW_WORKSPACE(QGW_OP_HF_DENSITY, workspace, workspace_bytes, "qgw_hf_density");
+  char* ws = (char*)workspace;
   double* scal = (double*)(ws + so + se);
   int* stat = (int*)(scal + 16);
   hipStream_t s = (hipStream_t)stream;
@@ -955,9 +981,9 @@ qgw_status qgw_state_hf_solve(qgw_state st, double tol, int32_t max_iter, int32_
   const int64_t so_n = int64_t(p.no) * p.no * p.nk;
   const size_t so = size_t(so_n) * sizeof(zd);
   const size_t se = size_t(p.no) * p.nk * sizeof(double);
-  QGW_CHECK_HIP(ensure_ws(h->p, so + se), "qgw_state_hf_solve: workspace");
-  void* u = p.d_ws;
-  double* eps = (double*)((char*)p.d_ws + so);
+  st->broken = true;  // until the solve has left a consistent state
+  void* u = st->hf_ws;
+  double* eps = (double*)((char*)st->hf_ws + so);
   hipStream_t s = (hipStream_t)stream;
   // start: Sigma_HF = 0 and the density of H0 at the target filling (or at the state's mu)
   QGW_CHECK_HIP(hipMemsetAsync(st->SigHF_k, 0, so, s), "qgw_state_hf_solve");
@@ -983,6 +1009,7 @@ qgw_status qgw_state_hf_solve(qgw_state st, double tol, int32_t max_iter, int32_
     QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_state_hf_solve");
     ++done;
     QGW_REQUIRE(bad == 0, QGW_ERR_NONFINITE, "qgw_state_hf_solve: non-finite chemical potential or filling");
+    QGW_REQUIRE(std::isfinite(dsig), QGW_ERR_NONFINITE, "qgw_state_hf_solve: non-finite Hartree-Fock self-energy");
     if (dsig <= tol) break;
   }
   if (done == 0) {
@@ -996,8 +1023,13 @@ qgw_status qgw_state_hf_solve(qgw_state st, double tol, int32_t max_iter, int32_
   QGW_CHECK_HIP(launch_add(p, so_n, st->H_k, st->SigHF_k, st->Hs_k, s), "qgw_state_hf_solve");
   QGW_CHECK_HIP(launch_dyson_g_final(p, st->Hs_k, nullptr, 0, st->G_iw, st->d_scal, st->d_part, st->d_stat, s),
                 "qgw_state_hf_solve");
+  // the next GW search starts from the HF mu: no shift from a mean level of before the HF solve
+  const double nan_word = NAN;
+  QGW_CHECK_HIP(hipMemcpyAsync(st->d_scal + 10, &nan_word, sizeof(double), hipMemcpyHostToDevice, s),
+                "qgw_state_hf_solve");
   QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_state_hf_solve");
   st->last_dsig = INFINITY;
+  st->broken = false;
   if (iters_done) *iters_done = done;
   if (d_sigma) *d_sigma = dsig;
   if (mu_out) *mu_out = st->mu;
@@ -1007,14 +1039,15 @@ qgw_status qgw_state_hf_solve(qgw_state st, double tol, int32_t max_iter, int32_
 // ---------------------------------------------------------- quasiparticle
 
 qgw_status qgw_quasiparticle(qgw_plan h, const void* H_k, const void* SigHF_k, const void* Sig_iw, double mu,
-                             void* Sig0, void* Z, void* Hqp, double* bands, void* stream) {
+                             void* Sig0, void* Z, void* Hqp, double* bands, void* workspace, int64_t workspace_bytes,
+                             void* stream) {
   QGW_PLAN(h, "qgw_quasiparticle");
   QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_quasiparticle: FP64 plans only");
   QGW_REQUIRE(H_k && SigHF_k && Sig_iw && Sig0 && Z && Hqp && bands, QGW_ERR_INVALID_ARG,
               "qgw_quasiparticle: null argument");
   QGW_REQUIRE(std::isfinite(mu), QGW_ERR_INVALID_ARG, "qgw_quasiparticle: mu must be finite");
-  QGW_CHECK_HIP(ensure_ws(h->p, 64), "qgw_quasiparticle: workspace");
-  int* flag = (int*)p.d_ws;
+  QGW_WORKSPACE(QGW_OP_QUASIPARTICLE, workspace, workspace_bytes, "qgw_quasiparticle");
+  int* flag = (int*)workspace;
   hipStream_t s = (hipStream_t)stream;
   QGW_CHECK_HIP(hipMemsetAsync(flag, 0, sizeof(int), s), "qgw_quasiparticle");
   QGW_CHECK_HIP(launch_quasiparticle(p, H_k, SigHF_k, Sig_iw, mu, Sig0, Z, Hqp, bands, flag, s),
@@ -1066,6 +1099,35 @@ qgw_status qgw_check_finite(qgw_plan h, const void* x, int64_t count, void* stre
   return QGW_OK;
 }
 
+qgw_status qgw_workspace_size(qgw_plan h, int32_t op, int64_t* bytes) {
+  QGW_REQUIRE(h && bytes, QGW_ERR_INVALID_ARG, "qgw_workspace_size: null argument");
+  const int64_t b = workspace_need(h->p, op);
+  QGW_REQUIRE(b >= 0, QGW_ERR_INVALID_ARG, "qgw_workspace_size: unknown operation " + std::to_string(op));
+  *bytes = b;
+  return QGW_OK;
+}
+
+// reads and clears the plan's device condition word once the stream has drained
+static qgw_status take_conditions(const Plan& p, hipStream_t s, int* flags) {
+  int host = 0;
+  const int zero = 0;
+  QGW_CHECK_HIP(hipMemcpyAsync(&host, p.d_status + kCondWord, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_sync_status");
+  QGW_CHECK_HIP(hipMemcpyAsync(p.d_status + kCondWord, &zero, sizeof(int), hipMemcpyHostToDevice, s), "qgw_sync_status");
+  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_sync_status");
+  *flags = host;
+  return QGW_OK;
+}
+
+qgw_status qgw_sync_status(qgw_plan h, void* stream) {
+  QGW_PLAN(h, "qgw_sync_status");
+  int flags = 0;
+  const qgw_status rc = take_conditions(p, (hipStream_t)stream, &flags);
+  if (rc != QGW_OK) return rc;
+  QGW_REQUIRE(!(flags & kCondSingular), QGW_ERR_SINGULAR,
+              "qgw_sync_status: a Dyson-W system I - V P had a zero or non-finite pivot");
+  return QGW_OK;
+}
+
 // ------------------------------------------------------------------ state
 
 static void free_state(qgw_state st) {
@@ -1077,7 +1139,7 @@ static void free_state(qgw_state st) {
                   st->SigHF_k, st->SigHF_old, st->n_k, st->n_R, st->SigHF_R, st->Hs_k, st->G_tau,
                   st->G_reflt, st->Sig_tau_k, st->Pq, st->P_nu, st->Wc_nu, st->d_dsig, st->d_blockmax,
                   st->G32, st->Gt32, st->Gr32, st->St32, st->Siw32, st->Pq32, st->Pnu32, st->Wc32,
-                  st->Vqm32, st->d_scal, st->d_part, st->d_stat};
+                  st->Vqm32, st->d_scal, st->d_part, st->d_stat, st->hf_ws};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -1138,7 +1200,8 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
                 {&st->Wc_nu, fw},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096},
                 {(void**)&st->d_scal, 32 * sizeof(double)},
                 {(void**)&st->d_part, size_t(8) * p.max_blocks * sizeof(double)},
-                {(void**)&st->d_stat, 16 * sizeof(int)}};
+                {(void**)&st->d_stat, 16 * sizeof(int)},
+                {&st->hf_ws, so + size_t(p.no) * p.nk * sizeof(double)}};
   for (auto& a : allocs) {
     if (e != hipSuccess) break;
     e = hipMalloc(a.ptr, a.bytes);
@@ -1154,9 +1217,12 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
   if (e == hipSuccess) e = launch_slab_to_matrix_static(p, st->V_q, st->V_qm, s);
   if (e == hipSuccess) e = launch_pair_sum_r(p, V_R, st->V_q0, s);
   if (e == hipSuccess) {
-    double sc[2] = {NAN, n_target};
+    double sc[16];
+    for (double& v : sc) v = NAN;
+    sc[1] = n_target;
     e = hipMemcpy(st->d_scal, sc, sizeof(sc), hipMemcpyHostToDevice);
   }
+  if (e == hipSuccess) e = hipMemset(st->d_stat, 0, 16 * sizeof(int));
   if (e == hipSuccess) e = hipMemsetAsync(st->Sig_iw, 0, fo, s);
   if (e == hipSuccess) e = hipMemsetAsync(st->Sig_iw_old, 0, fo, s);
   if (e == hipSuccess) e = hipMemsetAsync(st->SigHF_k, 0, so, s);
@@ -1196,6 +1262,7 @@ qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
   if (rc != QGW_OK) return rc;
   st->mu = m;
   *mu = m;
+  st->broken = false;
   st->in_fp32 = st->prec_mode != 0;
   st->n_fp32 = st->n_fp64 = 0;
   st->last_dsig = INFINITY;
@@ -1219,8 +1286,9 @@ qgw_status qgw_state_set_precision(qgw_state st, int32_t mode, double switch_tol
   return QGW_OK;
 }
 
-qgw_status qgw_state_info(qgw_state st, int32_t* last_prec, int32_t* n_fp32, int32_t* n_fp64) {
+qgw_status qgw_state_info(qgw_state st, int32_t* last_prec, int32_t* n_fp32, int32_t* n_fp64, int32_t* mu_evals) {
   QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_info: null state");
+  if (mu_evals) *mu_evals = st->last_evals;
   if (last_prec) *last_prec = st->last_prec;
   if (n_fp32) *n_fp32 = st->n_fp32;
   if (n_fp64) *n_fp64 = st->n_fp64;
@@ -1300,6 +1368,8 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
                             double* mu_out, void* stream) {
   QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_gw_iteration: null state");
   QGW_REQUIRE(n_iter >= 0, QGW_ERR_INVALID_ARG, "qgw_gw_iteration: negative n_iter");
+  QGW_REQUIRE(!st->broken, QGW_ERR_INVALID_ARG,
+              "qgw_gw_iteration: an earlier iteration of this state failed; restart it with qgw_state_init_g0");
   const Plan& p = st->plan->p;
   QGW_CHECK_HIP(enter_device(p.device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
@@ -1307,15 +1377,39 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
   int done = 0;
   for (int it = 0; it < n_iter; ++it) {
     const bool f32 = st->prec_mode == 2 || (st->prec_mode == 1 && st->in_fp32);
-    QGW_CHECK_HIP(enqueue_steps(st, f32, st->prof, s), "qgw_gw_iteration");
+    const hipError_t qe = enqueue_steps(st, f32, st->prof, s);
+    if (qe != hipSuccess) {
+      st->broken = true;
+      set_error(std::string("qgw_gw_iteration: ") + hipGetErrorString(qe));
+      return QGW_ERR_DEVICE;
+    }
     // a13: Dyson G with the chemical potential
     // |dSigma| (a14, already enqueued) comes back with the search's result: one wait per iteration
     // the first round queues the previous search's evaluation count + 3 Newton steps (4 .. 12; 10 after G0)
     double m = st->mu, evals = 0.0;
     qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, &evals, st->d_scal,
                                 st->d_part, st->d_stat, st->d_dsig, &dsig,
-                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr, st->mu_steps0, st->h_io, st->ev_io);
-    if (rc != QGW_OK) return rc;
+                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr, st->mu_steps0, st->h_io, st->ev_io, 1);
+    st->last_evals = int(evals);
+    // a singular Dyson-W system or a non-finite self-energy is named as the cause, also of a failed search
+    if (rc != QGW_ERR_DEVICE && (rc != QGW_OK || !std::isfinite(dsig))) {
+      int flags = 0;
+      const qgw_status rc2 = take_conditions(p, s, &flags);
+      if (rc2 != QGW_OK) {
+        rc = rc2;
+      } else if (flags & kCondSingular) {
+        set_error("qgw_gw_iteration: a Dyson-W system I - V P had a zero or non-finite pivot");
+        rc = QGW_ERR_SINGULAR;
+      } else if (!std::isfinite(dsig)) {
+        set_error("qgw_gw_iteration: non-finite self-energy (max |Delta Sigma| is not finite)");
+        rc = QGW_ERR_NONFINITE;
+      }
+    }
+    if (rc != QGW_OK) {
+      st->broken = true;
+      if (iters_done) *iters_done = done;
+      return rc;
+    }
     st->mu = m;
     st->mu_steps0 = std::min(12, std::max(4, int(evals) + 3));
     if (st->prof) {
@@ -1377,12 +1471,16 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
     QGW_REQUIRE(states[i]->plan->p.device == dev, QGW_ERR_INVALID_ARG, "qgw_batch_create: states on different devices");
     QGW_REQUIRE(!states[i]->prof, QGW_ERR_INVALID_ARG, "qgw_batch_create: disable profiling first");
     QGW_REQUIRE(states[i]->plan->p.grid == kGridDLR, QGW_ERR_UNSUPPORTED, "qgw_batch_create: DLR plans only");
+    QGW_REQUIRE(!states[i]->broken, QGW_ERR_INVALID_ARG, "qgw_batch_create: a state needs a restart (failed iteration)");
     for (int j = 0; j < i; ++j)
       QGW_REQUIRE(states[j] != states[i], QGW_ERR_INVALID_ARG, "qgw_batch_create: a state appears twice");
   }
   QGW_CHECK_HIP(enter_device(dev), "hipSetDevice");
   if (precision == 1)
     for (int i = 0; i < n; ++i) QGW_CHECK_HIP(ensure_fp32(states[i]), "qgw_batch_create: single-precision buffers");
+  // the sticky failure words start clear (earlier eager searches may have raised them between their rounds)
+  for (int i = 0; i < n; ++i)
+    QGW_CHECK_HIP(hipMemset(states[i]->d_stat + 1, 0, sizeof(int)), "qgw_batch_create");
   qgw_batch b = new (std::nothrow) qgw_batch_s;
   QGW_REQUIRE(b, QGW_ERR_ALLOC, "qgw_batch_create: out of host memory");
   b->states.assign(states, states + n);
@@ -1412,7 +1510,7 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
         ce = enqueue_steps(st, precision == 1, false, ws);
         if (ce == hipSuccess)
           ce = launch_dyson_g_chain(p, st->Hs_k, st->Sig_iw, std::isnan(st->n_target) ? 0 : 1, st->G_iw, st->d_scal,
-                                    st->d_part, st->d_stat, mu_steps, ws);
+                                    st->d_part, st->d_stat, mu_steps, st->d_stat + 1, ws);
       }
     for (int w = 0; w < nw && ce == hipSuccess; ++w) {
       ce = hipEventRecord(b->events[w], b->workers[w]);
@@ -1441,24 +1539,31 @@ qgw_status qgw_batch_launch(qgw_batch b, void* stream) {
   return QGW_OK;
 }
 
-qgw_status qgw_batch_read(qgw_batch b, double* d_sigma, double* mu, int32_t* status, void* stream) {
+qgw_status qgw_batch_read(qgw_batch b, double* d_sigma, double* mu, int32_t* status, int32_t* evals, void* stream) {
   QGW_REQUIRE(b, QGW_ERR_INVALID_ARG, "qgw_batch_read: null batch");
   QGW_CHECK_HIP(enter_device(b->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   const size_t n = b->states.size();
-  std::vector<double> ds(n), m(n);
+  std::vector<double> ds(n), m(n), ev(n);
   std::vector<int> stt(n);
+  const int zero = 0;
   for (size_t i = 0; i < n; ++i) {
-    QGW_CHECK_HIP(hipMemcpyAsync(&ds[i], b->states[i]->d_dsig, sizeof(double), hipMemcpyDeviceToHost, s), "qgw_batch_read");
-    QGW_CHECK_HIP(hipMemcpyAsync(&m[i], b->states[i]->d_scal, sizeof(double), hipMemcpyDeviceToHost, s), "qgw_batch_read");
-    QGW_CHECK_HIP(hipMemcpyAsync(&stt[i], b->states[i]->d_stat, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_batch_read");
+    qgw_state st = b->states[i];
+    QGW_CHECK_HIP(hipMemcpyAsync(&ds[i], st->d_dsig, sizeof(double), hipMemcpyDeviceToHost, s), "qgw_batch_read");
+    QGW_CHECK_HIP(hipMemcpyAsync(&m[i], st->d_scal, sizeof(double), hipMemcpyDeviceToHost, s), "qgw_batch_read");
+    QGW_CHECK_HIP(hipMemcpyAsync(&ev[i], st->d_scal + 2, sizeof(double), hipMemcpyDeviceToHost, s), "qgw_batch_read");
+    // the sticky word: the worst search status of every replay since the last read
+    QGW_CHECK_HIP(hipMemcpyAsync(&stt[i], st->d_stat + 1, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_batch_read");
+    QGW_CHECK_HIP(hipMemcpyAsync(st->d_stat + 1, &zero, sizeof(int), hipMemcpyHostToDevice, s), "qgw_batch_read");
   }
   QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_batch_read");
   for (size_t i = 0; i < n; ++i) {
     b->states[i]->mu = m[i];
+    if (stt[i] != 0) b->states[i]->broken = true;
     if (d_sigma) d_sigma[i] = ds[i];
     if (mu) mu[i] = m[i];
     if (status) status[i] = stt[i];
+    if (evals) evals[i] = int32_t(ev[i]);
   }
   return QGW_OK;
 }

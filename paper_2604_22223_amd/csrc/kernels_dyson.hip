@@ -56,7 +56,8 @@ __device__ __forceinline__ cpx<T> shfl_cpx(cpx<T> v, int src, int width) {
 template <int NB, typename T>
 __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
                                                 const cpx<T>* __restrict__ pnu,
-                                                cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld) {
+                                                cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld,
+                                                int* __restrict__ cond) {
   using S = DysonWShape<NB>;
   __shared__ cpx<T> sp[S::MPW * S::NN];
   __shared__ cpx<T> piv[2][S::MPW][2 * NB];
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
 #pragma unroll
     for (int c = 0; c < NB; ++c) x[c] = mk(T(0), T(0));
   }
-  bool used = false;
+  bool used = false, singular = false;
   int my_step = 0;
   const int partner = lane - half * S::SEG;  // the half-0 lane of this row
 #pragma unroll
@@ -140,6 +141,8 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
     }
     __syncthreads();
     const cpx<T>* pr = piv[s & 1][mw] + half * NB;
+    const T pn = norm2(piv[s & 1][mw][s]);
+    singular |= !(pn > T(0)) || !isfinite(pn);  // exact zero, NaN or overflow
     const cpx<T> pinv = inv(piv[s & 1][mw][s]);
     cpx<T> f = is_p ? mk(T(1), T(0)) - pinv : x[s] * pinv;  // meaningful on half 0
     f = shfl_cpx(f, partner, 64);
@@ -149,6 +152,8 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
       if (half == 0) x[s] = mk(T(is_p ? 1 : 0), T(0));
     }
   }
+  // a singular or non-finite system of an existing matrix raises the condition bit (the output is non-finite)
+  if (singular && mat < nmat && row == 0 && half == 0) atomicOr(cond, kCondSingular);
   // W^C row my_step = (row of W) - (row of V); staged in LDS, stored contiguously
   __syncthreads();
   if (valid && half == 1) {
@@ -245,7 +250,7 @@ __device__ __forceinline__ void gj25_publish(const cpx<T> (&x)[3][7], cpx<T>* xs
 // has pivoted, so that a set sign drops it from the max
 template <typename T, int K>
 __device__ __forceinline__ void gj25_step(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs)[3], int (&kof)[3], int& k24,
-                                          int rg, int cg, cpx<T>* xs) {
+                                          int rg, int cg, cpx<T>* xs, bool& singular) {
   constexpr int NS = W25::NS, NT = W25::NT, ROW = W25::ROW, MIN = W25::MIN;
   constexpr int cgk = K % 8, tk = K / 8, t0 = (K + 1) / 8;
   const bool used24 = k24 >= 0;
@@ -279,7 +284,9 @@ __device__ __forceinline__ void gj25_step(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs
   }
   __syncthreads();
   const cpx<T> pv = ex[K];
-  const T d = rcp_nr(norm2(pv));
+  const T pn = norm2(pv);
+  singular |= !(pn > T(0)) || !isfinite(pn);  // exact zero, NaN or overflow (the same value in every lane)
+  const T d = rcp_nr(pn);
   const cpx<T> pinv = mk(pv.re * d, -pv.im * d);
   cpx<T> f[NS];
 #pragma unroll
@@ -295,13 +302,14 @@ __device__ __forceinline__ void gj25_step(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs
 
 template <typename T, int... K>
 __device__ __forceinline__ void gj25_all(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs)[3], int (&kof)[3], int& k24, int rg,
-                                         int cg, cpx<T>* xs, std::integer_sequence<int, K...>) {
-  (gj25_step<T, K>(x, y, cs, kof, k24, rg, cg, xs), ...);
+                                         int cg, cpx<T>* xs, bool& singular, std::integer_sequence<int, K...>) {
+  (gj25_step<T, K>(x, y, cs, kof, k24, rg, cg, xs, singular), ...);
 }
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
-                                                  cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld) {
+                                                  cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld,
+                                                  int* __restrict__ cond) {
   constexpr int NB = W25::NB, NN = NB * NB, NS = W25::NS, NT = W25::NT, CH = W25::CH, NCH = W25::NCH;
   __shared__ cpx<T> xs[W25::XS];  // a chunk of P rows; then the pivot exchange
   __shared__ cpx<T> sv[NN];       // V(q)
@@ -389,7 +397,9 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
     cs[s] = 31 - (rg + 8 * s);
     kof[s] = 0;
   }
-  gj25_all<T>(x, y, cs, kof, k24, rg, cg, xs, std::make_integer_sequence<int, NB>{});
+  bool singular = false;
+  gj25_all<T>(x, y, cs, kof, k24, rg, cg, xs, singular, std::make_integer_sequence<int, NB>{});
+  if (singular && lane == 0) atomicOr(cond, kCondSingular);
   // row r of the V part is row kof of W; W^C = W - V
   cpx<T>* wm = wc + mat * ld;
 #pragma unroll
@@ -474,6 +484,7 @@ struct DysonGArgs {
   double* partials;   // [2][4][max blocks]
   int* status;        // 0 ok, 2 not converged
   const double* extra;  // optional scalar copied to scal[9] by the final pass
+  int* fail_word;       // optional: raised to the search's failing status by the final pass, never lowered here
   int r, nk, mode, max_evals;
   double beta, tol_mu, tol_n;
   double ne_offset;   // added to -(2/N_k) sum Re rho_m Tr G_m (the uniform grid's 1/2 per spin-orbital)
@@ -528,11 +539,11 @@ __device__ __forceinline__ double wave_max(double v) {
 // and continue.
 // ---------------------------------------------------------------------------
 
-// partial Gershgorin bounds of H(k) (no starting point given)
+// per-block partials of H(k): Gershgorin bounds (used when no starting point is given) and the sum of the
+// diagonal (the mean level, whose change between two searches of a state shifts the start)
 template <int NO>
 __global__ __launch_bounds__(64) void k_dg_gersh(DysonGArgs A) {
-  if (isfinite(A.scal[0])) return;
-  double glo = 1e300, ghi = -1e300;
+  double glo = 1e300, ghi = -1e300, dsum = 0.0;
   for (int64_t k = int64_t(blockIdx.x) * 64 + threadIdx.x; k < A.nk; k += int64_t(gridDim.x) * 64) {
 #pragma unroll
     for (int i = 0; i < NO; ++i) {
@@ -543,30 +554,41 @@ __global__ __launch_bounds__(64) void k_dg_gersh(DysonGArgs A) {
       const double d = A.hk[(int64_t(i) * NO + i) * A.nk + k].re;
       glo = fmin(glo, d - rad);
       ghi = fmax(ghi, d + rad);
+      dsum += d;
     }
   }
   glo = wave_min(glo);
   ghi = wave_max(ghi);
+  dsum = wave_sum(dsum);
   if (threadIdx.x == 0) {
     A.partials[blockIdx.x] = glo;
     A.partials[gridDim.x + blockIdx.x] = ghi;
+    A.partials[2 * gridDim.x + blockIdx.x] = dsum;
   }
 }
 
-// mu <- centre of the Gershgorin bounds if no finite start was given; resets the search
+// mu <- centre of the Gershgorin bounds if no finite start was given; otherwise, with ``track``, the start moves
+// by the change of the mean diagonal of H since the previous search (scal[10]), the shift of a level by a change
+// of Sigma_HF (so that a Hartree shift of many eV does not cost a chain of capped steps); resets the search
 __global__ __launch_bounds__(64) void k_dg_begin(double* __restrict__ scal, int* __restrict__ status,
-                                                 const double* __restrict__ partials, int nblk) {
-  if (!isfinite(scal[0])) {
-    double glo = 1e300, ghi = -1e300;
-    for (int b = threadIdx.x; b < nblk; b += 64) {
-      glo = fmin(glo, partials[b]);
-      ghi = fmax(ghi, partials[nblk + b]);
-    }
-    glo = wave_min(glo);
-    ghi = wave_max(ghi);
-    if (threadIdx.x == 0) scal[0] = 0.5 * (glo + ghi);
+                                                 const double* __restrict__ partials, int nblk, double inv_count,
+                                                 int track) {
+  double glo = 1e300, ghi = -1e300, dsum = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) {
+    glo = fmin(glo, partials[b]);
+    ghi = fmax(ghi, partials[nblk + b]);
+    dsum += partials[2 * nblk + b];
   }
+  glo = wave_min(glo);
+  ghi = wave_max(ghi);
+  const double mean = wave_sum(dsum) * inv_count;
   if (threadIdx.x != 0) return;
+  if (!isfinite(scal[0])) {
+    scal[0] = 0.5 * (glo + ghi);
+  } else if (track && isfinite(scal[10]) && isfinite(mean)) {
+    scal[0] += mean - scal[10];
+  }
+  scal[10] = mean;
   const bool ok = isfinite(scal[0]);
   scal[2] = 0.0;
   scal[3] = 0.0;
@@ -715,6 +737,7 @@ __global__ __launch_bounds__(64) void k_dg_final(DysonGArgs A, int n, int nblk) 
       const bool conv = st[7] != 0.0 || fabs(st[3] - st[1]) <= A.tol_n;
       if (!conv || !isfinite(mu)) A.status[0] = 2;
     }
+    if (A.fail_word && A.status[0] > *A.fail_word) *A.fail_word = A.status[0];
     A.scal[8] = double(A.status[0]);
     if (A.extra) A.scal[9] = *A.extra;
   }
@@ -970,12 +993,12 @@ hipError_t dyson_w_nb(const Plan& p, const void* v_q, const void* p_nu, void* wc
   if (ld < int64_t(NB) * NB) return hipErrorInvalidValue;
   if (NB == 25) {
     hipLaunchKernelGGL((k_dyson_w25<T>), dim3(unsigned(nmat)), dim3(64), 0, s, (const cpx<T>*)v_q,
-                       (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld);
+                       (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld, p.d_status + kCondWord);
     return hipGetLastError();
   }
   const unsigned blocks = unsigned((nmat + MPW - 1) / MPW);
   hipLaunchKernelGGL((k_dyson_w<NB, T>), dim3(blocks), dim3(64), 0, s, (const cpx<T>*)v_q,
-                     (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld);
+                     (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld, p.d_status + kCondWord);
   return hipGetLastError();
 }
 
@@ -999,6 +1022,7 @@ DysonGArgs dyson_g_args(const Plan& p, const void* h_k, const void* sig_iw, int 
   A.tol_mu = 1e-13;
   A.tol_n = 1e-13;
   A.extra = nullptr;
+  A.fail_word = nullptr;
   A.ne_offset = p.ne_offset;
   return A;
 }
@@ -1013,12 +1037,13 @@ static int dyson_g_blocks(const Plan& p) {
 }
 
 template <int NO>
-hipError_t dyson_g_begin_no(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
+hipError_t dyson_g_begin_no(const Plan& p, const void* h_k, double* scal, double* partials, int* status, int track,
                             hipStream_t s) {
   DysonGArgs A = dyson_g_args<NO>(p, h_k, nullptr, 1, nullptr, scal, partials, status);
   const int gb = int((p.nk + 63) / 64 < 1024 ? (p.nk + 63) / 64 : 1024);
   hipLaunchKernelGGL((k_dg_gersh<NO>), dim3(gb), dim3(64), 0, s, A);
-  hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status, (const double*)partials, gb);
+  hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status, (const double*)partials, gb,
+                     1.0 / (double(NO) * p.nk), track);
   return hipGetLastError();
 }
 
@@ -1034,9 +1059,10 @@ hipError_t dyson_g_steps_no(const Plan& p, const void* h_k, const void* sig_iw, 
 template <int NO>
 hipError_t dyson_g_final_no(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                             double* scal, double* partials, int* status, const double* extra, int steps,
-                            hipStream_t s) {
+                            int* fail_word, hipStream_t s) {
   DysonGArgs A = dyson_g_args<NO>(p, h_k, sig_iw, mode, g_iw, scal, partials, status);
   A.extra = extra;
+  A.fail_word = fail_word;
   const int blocks = dyson_g_blocks(p);
   hipLaunchKernelGGL((k_dg_final<NO>), dim3(blocks), dim3(64), 0, s, A, mode == 1 ? steps : 0, blocks);
   return hipGetLastError();
@@ -1069,6 +1095,7 @@ hipError_t dyson_g_bwd_no(const Plan& p, const void* h_k, const void* sig_iw, do
   A.beta = p.beta;
   A.tol_mu = A.tol_n = 0.0;
   A.extra = nullptr;
+  A.fail_word = nullptr;
   A.ne_offset = p.ne_offset;
   const int64_t total = int64_t(p.r) * p.nk;
   const int nblk = int((total + 63) / 64);
@@ -1137,8 +1164,8 @@ hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void
   }
 
 hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
-                                hipStream_t s) {
-  QGW_NO_SWITCH((dyson_g_begin_no<NOV>(p, h_k, scal, partials, status, s)))
+                                int track, hipStream_t s) {
+  QGW_NO_SWITCH((dyson_g_begin_no<NOV>(p, h_k, scal, partials, status, track, s)))
 }
 
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
@@ -1148,19 +1175,21 @@ hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_
 
 hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, hipStream_t s, const double* extra,
-                                int steps) {
-  QGW_NO_SWITCH((dyson_g_final_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, extra, steps, s)))
+                                int steps, int* fail_word) {
+  QGW_NO_SWITCH((dyson_g_final_no<NOV>(p, h_k, sig_iw, mode, g_iw, scal, partials, status, extra, steps, fail_word,
+                                       s)))
 }
 
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                                double* scal, double* partials, int* status, int steps, hipStream_t s) {
+                                double* scal, double* partials, int* status, int steps, int* fail_word,
+                                hipStream_t s) {
   hipError_t e = hipSuccess;
   if (mode == 1) {
-    e = launch_dyson_g_begin(p, h_k, scal, partials, status, s);
+    e = launch_dyson_g_begin(p, h_k, scal, partials, status, 1, s);
     if (e == hipSuccess) e = launch_dyson_g_steps(p, h_k, sig_iw, scal, partials, status, steps, s);
   }
   if (e == hipSuccess) e = launch_dyson_g_final(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s, nullptr,
-                                                mode == 1 ? steps : 0);
+                                                mode == 1 ? steps : 0, fail_word);
   return e;
 }
 

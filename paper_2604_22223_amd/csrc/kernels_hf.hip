@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k_hf_delta_mix(zd* __restrict__ x_new, zd
   for (int64_t i = threadIdx.x; i < count; i += 256) {
     cpx<double> a = x_new[i];
     const cpx<double> o = x_old[i];
-    v = fmax(v, sqrt(norm2(a - o)));
+    v = fmax(v, finite_or_inf(sqrt(norm2(a - o))));
     if (alpha != 1.0) {
       a = o + scale(a - o, alpha);
       x_new[i] = a;

@@ -73,7 +73,8 @@ __global__ void k_add(const zd* __restrict__ a, const zd* __restrict__ b, zd* __
   if (gi < n) out[gi] = a[gi] + b[gi];
 }
 
-// per-block max of |(hf_new + c_new) - (hf_old + c_old)| over (m, ab, k)
+// per-block max of |(hf_new + c_new) - (hf_old + c_old)| over (m, ab, k); a non-finite entry counts as +inf
+// (fmax would drop a NaN), so a NaN anywhere in Sigma makes the norm infinite
 __global__ __launch_bounds__(256) void k_delta(const zd* __restrict__ hf_new, const zd* __restrict__ c_new,
                                                const zd* __restrict__ hf_old, const zd* __restrict__ c_old,
                                                int64_t n_static, int64_t n_total, double* __restrict__ block_max) {
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256) void k_delta(const zd* __restrict__ hf_new, co
   for (int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x; gi < n_total; gi += int64_t(gridDim.x) * 256) {
     const int64_t st = gi % n_static;
     const cpx<double> d = (hf_new[st] + c_new[gi]) - (hf_old[st] + c_old[gi]);
-    v = fmax(v, sqrt(norm2(d)));
+    v = fmax(v, finite_or_inf(sqrt(norm2(d))));
   }
   red[threadIdx.x] = v;
   __syncthreads();

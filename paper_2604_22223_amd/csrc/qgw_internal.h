@@ -36,6 +36,10 @@ constexpr int kNumMaps = 7;
 // device map slots: 0-6 the forward maps, 7 + m the adjoint T^H of the square map m (m != 5)
 constexpr int kAdjMap0 = 7;
 constexpr int kNumDevMaps = 14;
+// d_status[kCondWord] of a plan: device-detected conditions, bits set by kernels and cleared by the host
+// (qgw_sync_status); kCondSingular: a zero or non-finite pivot in the Dyson-W solve
+constexpr int kCondWord = 12;
+constexpr int kCondSingular = 1;
 
 struct DeviceMaps {
   void* m[kNumDevMaps] = {nullptr};  // rows padded to a multiple of mt, zero-filled
@@ -83,14 +87,12 @@ struct Plan {
   TermTable terms_lj;  // keyed by (l, j): entries (alpha, beta, i, k)
   double* d_wn = nullptr;  // fermionic Matsubara frequencies (r)
   zd* d_qp_row = nullptr;  // node values -> value at i pi / beta (r)
-  // Dyson-G scratch: partial sums (2 x max blocks x 4), status word
+  // Dyson-G scratch: partial sums (2 x max blocks x 4), status words ([0] search status, [8] count of
+  // non-finite values, [kCondWord] device conditions)
   double* d_partials = nullptr;
   int* d_status = nullptr;
   double* d_scalars = nullptr;  // [8]: mu, n_target, d_sigma, ...
   int max_blocks = 0;
-  // workspace of the adjoint calls, allocated on their first use
-  void* d_ws = nullptr;
-  size_t ws_bytes = 0;
   Tune tune;
   Tune tune32;              // shapes of the FP32 kernels of an FP64 plan (a state's single-precision iterations)
   bool has_tune32 = false;
@@ -148,18 +150,22 @@ hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStre
 // search; steps: `steps` Newton evaluations (no-ops once done); final: G at
 // mu (mode 0: mu as given; mode 1: also status 2 if the search has not
 // converged).  chain = begin + steps + final (graph-capturable).
+// track = 1: a state's search, whose start moves with the mean diagonal of H since its previous search (scal[10])
 hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
-                                hipStream_t s);
+                                int track, hipStream_t s);
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
                                 int* status, int steps, hipStream_t s);
 // also copies the status to scal[8] and, if extra is given, *extra to scal[9]; ``steps`` is the number of
 // evaluations launch_dyson_g_steps queued in this round (the final pass takes the step of the last one).
 // scal holds 32 doubles: the host-visible words 0..9 and the two state slots of a round at 16..31.
+// fail_word (optional): raised to a failing status of the search and never lowered by the kernels (the sticky
+// report of a batch graph, whose every replay restarts status[0])
 hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, hipStream_t s,
-                                const double* extra = nullptr, int steps = 0);
+                                const double* extra = nullptr, int steps = 0, int* fail_word = nullptr);
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
-                                double* scal, double* partials, int* status, int steps, hipStream_t s);
+                                double* scal, double* partials, int* status, int steps, int* fail_word,
+                                hipStream_t s);
 hipError_t launch_slab_to_matrix_static(const Plan& p, const void* in, void* out, hipStream_t s);
 hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b, void* out,
                       hipStream_t s);

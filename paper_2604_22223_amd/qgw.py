@@ -18,10 +18,13 @@ LIB_PATH = os.path.join(_HERE, "libqgw.so")
 QGW_OK = 0
 STATUS_NAMES = {0: "QGW_OK", 1: "QGW_ERR_INVALID_ARG", 2: "QGW_ERR_SHAPE", 3: "QGW_ERR_UNSUPPORTED",
                 4: "QGW_ERR_DEVICE", 5: "QGW_ERR_NOT_CONVERGED", 6: "QGW_ERR_NONFINITE",
-                7: "QGW_ERR_ALLOC"}
+                7: "QGW_ERR_ALLOC", 8: "QGW_ERR_SINGULAR"}
+QGW_ERR_INVALID_ARG, QGW_ERR_NONFINITE, QGW_ERR_SINGULAR = 1, 6, 8
 F64, F32 = 0, 1
 F_IW2TAU, F_IW2TAUR, F_TAU2IW, B_TAU2IW, B_IW2TAU, F_IW2BETA, F_IW2GM = range(7)
 LAYOUT_SLAB, LAYOUT_MATRIX = 0, 1
+(OP_SIGMA_BWD, OP_DYSON_W_BWD, OP_HARTREE_FOCK_BWD, OP_ENERGY, OP_ENERGY_BWD, OP_HF_DENSITY,
+ OP_QUASIPARTICLE) = range(7)
 R_TO_K, K_TO_R = -1, +1
 
 #: Every C entry point the header declares.
@@ -33,7 +36,7 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
            "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_quasiparticle", "qgw_hf_density", "qgw_state_hf_solve", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
-           "qgw_plan_create_mf", "qgw_mf_nodes_for", "qgw_last_error"]
+           "qgw_plan_create_mf", "qgw_mf_nodes_for", "qgw_workspace_size", "qgw_sync_status", "qgw_last_error"]
 
 
 class QGWError(RuntimeError):
@@ -90,27 +93,29 @@ def lib():
             "qgw_state_copy": [vp, i32, vp, pi64, vp],
             "qgw_state_profile": [vp, i32, pd, pi32],
             "qgw_state_set_precision": [vp, i32, dbl],
-            "qgw_state_info": [vp, pi32, pi32, pi32],
+            "qgw_state_info": [vp, pi32, pi32, pi32, pi32],
             "qgw_check_finite": [vp, vp, i64, vp],
             "qgw_dlr_transform_bwd": [vp, i32, i64, dbl, dbl, i32, vp, vp, vp],
             "qgw_dlr_transform_pairs_bwd": [vp, i32, i32, i32, vp, vp, vp],
             "qgw_lattice_fft_bwd": [vp, i32, i64, vp, vp, vp],
             "qgw_bubble_bwd": [vp, vp, vp, vp, vp, vp, vp],
-            "qgw_sigma_bwd": [vp, vp, vp, i32, vp, vp, vp, vp],
-            "qgw_dyson_W_bwd": [vp, vp, vp, vp, vp, vp, vp],
-            "qgw_hartree_fock_bwd": [vp, vp, vp, vp, vp, vp, vp],
+            "qgw_sigma_bwd": [vp, vp, vp, i32, vp, vp, vp, vp, i64, vp],
+            "qgw_dyson_W_bwd": [vp, vp, vp, vp, vp, vp, vp, i64, vp],
+            "qgw_hartree_fock_bwd": [vp, vp, vp, vp, vp, vp, vp, i64, vp],
             "qgw_dyson_G_bwd": [vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp],
             "qgw_pair_layout": [vp, i32, i32, i64, vp, vp, vp],
             "qgw_add": [vp, i64, vp, vp, vp, vp],
             "qgw_plan_autotune": [vp, pi32, vp],
-            "qgw_energy": [vp, vp, vp, vp, vp, pd, vp],
-            "qgw_energy_bwd": [vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp],
-            "qgw_quasiparticle": [vp, vp, vp, vp, dbl, vp, vp, vp, pd, vp],
-            "qgw_hf_density": [vp, vp, dbl, pd, vp, vp],
+            "qgw_energy": [vp, vp, vp, vp, vp, pd, vp, i64, vp],
+            "qgw_energy_bwd": [vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp, i64, vp],
+            "qgw_quasiparticle": [vp, vp, vp, vp, dbl, vp, vp, vp, pd, vp, i64, vp],
+            "qgw_hf_density": [vp, vp, dbl, pd, vp, vp, i64, vp],
+            "qgw_workspace_size": [vp, i32, pi64],
+            "qgw_sync_status": [vp, vp],
             "qgw_state_hf_solve": [vp, dbl, i32, pi32, pd, pd, vp],
             "qgw_batch_create": [i32, ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(vp)],
             "qgw_batch_launch": [vp, vp],
-            "qgw_batch_read": [vp, pd, pd, pi32, vp],
+            "qgw_batch_read": [vp, pd, pd, pi32, pi32, vp],
             "qgw_batch_destroy": [vp],
         }
         for name, args in sig.items():
@@ -130,6 +135,10 @@ def _check(status):
 
 def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _nbytes(t):
+    return 0 if t is None else int(t.numel() * t.element_size())
 
 
 def _stream():
@@ -218,6 +227,24 @@ class Plan:
         _check(lib().qgw_plan_get_map(self.handle, int(which), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return (out[0::2] + 1j * out[1::2]).reshape(rows, self.r)
 
+    def workspace_size(self, op):
+        """Bytes of scratch call ``op`` (OP_*) needs on this plan (qgw_workspace_size)."""
+        b = ctypes.c_int64(0)
+        _check(lib().qgw_workspace_size(self.handle, int(op), ctypes.byref(b)))
+        return b.value
+
+    def workspace(self, op):
+        """A device scratch buffer for call ``op`` from torch's caching allocator (None if none is needed)."""
+        import torch
+        b = self.workspace_size(op)
+        if b == 0:
+            return None
+        return torch.empty(b, dtype=torch.uint8, device="cuda:%d" % self.device)
+
+    def sync_status(self):
+        """Waits for the stream, reads and clears the device status word (raises QGWError if it is set)."""
+        _check(lib().qgw_sync_status(self.handle, _stream()))
+
     # ---- step calls ------------------------------------------------------
     def dlr_transform(self, which, x, out, scale=1.0, hermitian=0):
         ncols = x.numel() // self.r
@@ -284,19 +311,22 @@ class Plan:
                                     _ptr(gbar_reflt), _stream()))
         return gbar_tau, gbar_reflt
 
-    def sigma_bwd(self, g_tau_r, wc_q, sigbar, gbar_tau, wcbar_q, out_k=True):
+    def sigma_bwd(self, g_tau_r, wc_q, sigbar, gbar_tau, wcbar_q, out_k=True, workspace=None):
+        ws = self.workspace(OP_SIGMA_BWD) if (workspace is None and out_k) else workspace
         _check(lib().qgw_sigma_bwd(self.handle, _ptr(g_tau_r), _ptr(wc_q), int(bool(out_k)), _ptr(sigbar),
-                                   _ptr(gbar_tau), _ptr(wcbar_q), _stream()))
+                                   _ptr(gbar_tau), _ptr(wcbar_q), _ptr(ws), _nbytes(ws), _stream()))
         return gbar_tau, wcbar_q
 
-    def dyson_W_bwd(self, v_q, p_nu, wcbar, pbar, vbar):
+    def dyson_W_bwd(self, v_q, p_nu, wcbar, pbar, vbar, workspace=None):
+        ws = self.workspace(OP_DYSON_W_BWD) if workspace is None else workspace
         _check(lib().qgw_dyson_W_bwd(self.handle, _ptr(v_q), _ptr(p_nu), _ptr(wcbar), _ptr(pbar), _ptr(vbar),
-                                     _stream()))
+                                     _ptr(ws), _nbytes(ws), _stream()))
         return pbar, vbar
 
-    def hartree_fock_bwd(self, v_r, n_r, sbar, nbar=None, vbar=None):
+    def hartree_fock_bwd(self, v_r, n_r, sbar, nbar=None, vbar=None, workspace=None):
+        ws = self.workspace(OP_HARTREE_FOCK_BWD) if workspace is None else workspace
         _check(lib().qgw_hartree_fock_bwd(self.handle, _ptr(v_r), _ptr(n_r), _ptr(sbar), _ptr(nbar), _ptr(vbar),
-                                          _stream()))
+                                          _ptr(ws), _nbytes(ws), _stream()))
         return nbar, vbar
 
     def dyson_G_bwd(self, h_k, sig_iw, mu, gbar, sigbar, hbar=None, n_target=None, mubar=0.0):
@@ -317,13 +347,16 @@ class Plan:
     def energy(self, h_k, shf_k, sig_iw, g_iw):
         """(E, HF part, correlation part) of the Galitskii-Migdal energy."""
         e = np.zeros(3)
+        ws = self.workspace(OP_ENERGY)
         _check(lib().qgw_energy(self.handle, _ptr(h_k), _ptr(shf_k), _ptr(sig_iw), _ptr(g_iw),
-                                e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+                                e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), _nbytes(ws), _stream()))
         return tuple(e.tolist())
 
     def energy_bwd(self, h_k, shf_k, sig_iw, g_iw, ebar, hbar, shfbar, sigbar, gbar):
+        ws = self.workspace(OP_ENERGY_BWD)
         _check(lib().qgw_energy_bwd(self.handle, _ptr(h_k), _ptr(shf_k), _ptr(sig_iw), _ptr(g_iw), float(ebar),
-                                    _ptr(hbar), _ptr(shfbar), _ptr(sigbar), _ptr(gbar), _stream()))
+                                    _ptr(hbar), _ptr(shfbar), _ptr(sigbar), _ptr(gbar), _ptr(ws), _nbytes(ws),
+                                    _stream()))
         return hbar, shfbar, sigbar, gbar
 
     def quasiparticle(self, h_k, shf_k, sig_iw, mu=0.0):
@@ -336,9 +369,10 @@ class Plan:
         z = torch.empty_like(sig0)
         hqp = torch.empty_like(sig0)
         bands = torch.empty((shape[0], shape[-1]), dtype=torch.float64, device=h_k.device)
+        ws = self.workspace(OP_QUASIPARTICLE)
         _check(lib().qgw_quasiparticle(self.handle, _ptr(h_k), _ptr(shf_k), _ptr(sig_iw), float(mu), _ptr(sig0),
                                        _ptr(z), _ptr(hqp), ctypes.cast(_ptr(bands), ctypes.POINTER(ctypes.c_double)),
-                                       _stream()))
+                                       _ptr(ws), _nbytes(ws), _stream()))
         return sig0, z, hqp, bands
 
     def hf_density(self, h_k, n_target=None, mu=0.0, out=None):
@@ -347,7 +381,9 @@ class Plan:
         out = torch.empty_like(h_k) if out is None else out
         m = ctypes.c_double(mu)
         nt = float("nan") if n_target is None else float(n_target)
-        _check(lib().qgw_hf_density(self.handle, _ptr(h_k), nt, ctypes.byref(m), _ptr(out), _stream()))
+        ws = self.workspace(OP_HF_DENSITY)
+        _check(lib().qgw_hf_density(self.handle, _ptr(h_k), nt, ctypes.byref(m), _ptr(out), _ptr(ws), _nbytes(ws),
+                                    _stream()))
         return m.value, out
 
     def add(self, a, b, out):
@@ -430,8 +466,14 @@ class State:
     def info(self):
         """(precision of the last iteration, FP32 iterations, FP64 iterations)."""
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().qgw_state_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        _check(lib().qgw_state_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), None))
         return a.value, b.value, c.value
+
+    def mu_evals(self):
+        """N_e(mu) evaluations of the last iteration's chemical-potential search."""
+        e = ctypes.c_int32()
+        _check(lib().qgw_state_info(self.handle, None, None, None, ctypes.byref(e)))
+        return e.value
 
     def array(self, which):
         """Copy of a state array as a torch tensor (0 G, 1 Sigma_C, 2 Sigma_HF, 3 P, 4 W^C, 5 n)."""
@@ -460,15 +502,18 @@ class Batch:
     def launch(self):
         _check(lib().qgw_batch_launch(self.handle, _stream()))
 
-    def read(self):
-        """(max |Delta Sigma|, mu, status) per state, after the stream has drained."""
+    def read(self, with_evals=False):
+        """(max |Delta Sigma|, mu, status) per state after the stream has drained; status is the worst search
+        status of every replay since the previous read.  with_evals adds the last search's evaluation counts."""
         n = len(self.states)
         ds, mu = np.zeros(n), np.zeros(n)
         st = np.zeros(n, dtype=np.int32)
+        ev = np.zeros(n, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int32)
         _check(lib().qgw_batch_read(self.handle, ds.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                    mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                    st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream()))
-        return ds, mu, st
+                                    mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), st.ctypes.data_as(ip),
+                                    ev.ctypes.data_as(ip), _stream()))
+        return (ds, mu, st, ev) if with_evals else (ds, mu, st)
 
     def close(self):
         if self.handle:

@@ -99,7 +99,8 @@ def five_orbital(n=24, seed=22223, bandwidth=4.0, U=4.0, J=0.7, Vnn=1.0,
                 V_R[i * norb + i, j * norb + j, r1 % n, r2 % n] += Vnn
     return {"name": "five_orbital_%dx%d" % (n, n), "mesh": (n, n), "site_norb": [norb],
             "H_R": H_R, "V_R": V_R, "beta": float(beta), "omega_max": float(omega_max),
-            "eps": float(eps), "n_target": float(n_target), "seed": seed}
+            "eps": float(eps), "n_target": float(n_target), "seed": seed,
+            "interaction": {"U": float(U), "J": float(J), "V_nn": float(Vnn)}}
 
 
 def graphene(n=12, t=-2.7, U=3.0, ohno=False, beta=10.0, omega_max=100.0, eps=1e-8,
