@@ -303,6 +303,20 @@ qgw_status qgw_hartree_fock(qgw_plan plan, const void *V_R, const void *n_R,
 qgw_status qgw_dyson_G(qgw_plan plan, const void *H_k, const void *Sig_iw,
                        double n_target, double *mu, void *G_iw, void *stream);
 
+/* qgw_dyson_G for callers that cannot allocate device memory (code under HIP
+ * graph capture elsewhere in their program, tight serving loops, harnesses
+ * that forbid hipMalloc): the same computation, arguments, waits and errors,
+ * with the search's scratch (32 scalars, at most 4096 partial sums, 16
+ * status words; 33,088 bytes) in a static device array of the library
+ * instead of the plan's.  Each GPU holds one copy of that array until the
+ * process ends; calls that overlap on one GPU (from several threads or
+ * streams) race on it.  The call allocates nothing.  QGW_ERR_UNSUPPORTED if
+ * a search on this plan would need more partial sums than the array holds
+ * (the search uses at most 1024 blocks, so no supported plan does) or the
+ * device ordinal is 64 or above. */
+qgw_status qgw_dyson_G_noalloc(qgw_plan plan, const void *H_k, const void *Sig_iw,
+                               double n_target, double *mu, void *G_iw, void *stream);
+
 /* ------------------------------------------------------------- adjoints
  *
  * Reverse-mode derivatives of the step calls (FP64 plans only; FP32 plans

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -716,6 +717,62 @@ qgw_status qgw_dyson_G(qgw_plan h, const void* H_k, const void* Sig_iw, double n
   else
     QGW_REQUIRE(std::isfinite(*mu), QGW_ERR_INVALID_ARG, "qgw_dyson_G: fixed mu must be finite");
   return run_dyson_g(p, H_k, Sig_iw, n_target, mu, G_iw, (hipStream_t)stream, nullptr);
+}
+
+// ------------------------------------------------------ Dyson G without allocation
+// The search scratch of qgw_dyson_G_noalloc: 32 scalars, the per-block partial sums of the start and of the
+// evaluations, and 16 status words, in a file-scope device array.  Each GPU the library runs on holds its own
+// copy until the process ends.  Host code uses it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name on the host is not a device address).
+constexpr int kNaScalars = 32;
+constexpr int kNaPartials = 4096;
+constexpr int kNaStatus = 16;
+constexpr size_t kNaBytes = (kNaScalars + kNaPartials) * sizeof(double) + kNaStatus * sizeof(int);
+constexpr int kNaMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+static std::mutex g_na_mutex;
+static void* g_na_ptr[kNaMaxDevices] = {};
+
+// the device address of this device's copy of ``scratch``, looked up once per device (that device current)
+static hipError_t noalloc_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kNaMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_na_mutex);
+  if (!g_na_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_na_ptr[dev] = ptr;
+  }
+  *out = g_na_ptr[dev];
+  return hipSuccess;
+}
+
+qgw_status qgw_dyson_G_noalloc(qgw_plan h, const void* H_k, const void* Sig_iw, double n_target, double* mu,
+                               void* G_iw, void* stream) {
+  QGW_PLAN(h, "qgw_dyson_G_noalloc");
+  QGW_REQUIRE(H_k && G_iw && mu, QGW_ERR_INVALID_ARG, "qgw_dyson_G_noalloc: null argument");
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_dyson_G_noalloc: the Dyson G solve is FP64");
+  QGW_REQUIRE(p.device >= 0 && p.device < kNaMaxDevices, QGW_ERR_UNSUPPORTED,
+              "qgw_dyson_G_noalloc: device ordinal beyond the static scratch table");
+  if (!std::isnan(n_target))
+    QGW_REQUIRE(n_target > 0.0 && n_target < 2.0 * p.no, QGW_ERR_INVALID_ARG,
+                "qgw_dyson_G_noalloc: target filling must lie in (0, 2 n_o)");
+  else
+    QGW_REQUIRE(std::isfinite(*mu), QGW_ERR_INVALID_ARG, "qgw_dyson_G_noalloc: fixed mu must be finite");
+  const int need = dyson_g_partials_needed(p);
+  QGW_REQUIRE(need <= kNaPartials, QGW_ERR_UNSUPPORTED,
+              "qgw_dyson_G_noalloc: the search needs " + std::to_string(need) +
+                  " partial sums; the static scratch holds " + std::to_string(kNaPartials));
+  void* base = nullptr;
+  QGW_CHECK_HIP(noalloc_scratch(p.device, &base), "qgw_dyson_G_noalloc: scratch address");
+  double* scal = (double*)base;
+  double* part = scal + kNaScalars;
+  int* stat = (int*)(part + kNaPartials);
+  // every word the search reads is written first (scalars from the host, status by the start or a clear), so
+  // the previous call's contents need no clearing; calls that overlap on one GPU race on the array
+  return run_dyson_g(p, H_k, Sig_iw, n_target, mu, G_iw, (hipStream_t)stream, nullptr, scal, part, stat);
 }
 
 // ------------------------------------------------------------------ adjoints

@@ -1036,6 +1036,16 @@ static int dyson_g_blocks(const Plan& p) {
   return int(need < cap ? need : cap);
 }
 
+}  // namespace
+
+int dyson_g_partials_needed(const Plan& p) {
+  const int64_t gb = (p.nk + 63) / 64 < 1024 ? (p.nk + 63) / 64 : 1024;  // start: three partials per block
+  const int nb = dyson_g_blocks(p);                                      // evaluations: two halves of two
+  return int(3 * gb > 4 * int64_t(nb) ? 3 * gb : 4 * int64_t(nb));
+}
+
+namespace {
+
 template <int NO>
 hipError_t dyson_g_begin_no(const Plan& p, const void* h_k, double* scal, double* partials, int* status, int track,
                             hipStream_t s) {

@@ -153,6 +153,8 @@ hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStre
 // track = 1: a state's search, whose start moves with the mean diagonal of H since its previous search (scal[10])
 hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
                                 int track, hipStream_t s);
+// doubles of partial sums one chemical-potential search on plan p uses (start and evaluations)
+int dyson_g_partials_needed(const Plan& p);
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
                                 int* status, int steps, hipStream_t s);
 // also copies the status to scal[8] and, if extra is given, *extra to scal[9]; ``steps`` is the number of

@@ -36,7 +36,7 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
            "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_quasiparticle", "qgw_hf_density", "qgw_state_hf_solve", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
-           "qgw_plan_create_mf", "qgw_mf_nodes_for", "qgw_workspace_size", "qgw_sync_status", "qgw_last_error"]
+           "qgw_plan_create_mf", "qgw_mf_nodes_for", "qgw_workspace_size", "qgw_sync_status", "qgw_dyson_G_noalloc", "qgw_last_error"]
 
 
 class QGWError(RuntimeError):
@@ -86,6 +86,7 @@ def lib():
             "qgw_sigma": [vp, vp, vp, i32, i32, vp, vp],
             "qgw_hartree_fock": [vp, vp, vp, vp, vp],
             "qgw_dyson_G": [vp, vp, vp, dbl, pd, vp, vp],
+            "qgw_dyson_G_noalloc": [vp, vp, vp, dbl, pd, vp, vp],
             "qgw_state_create": [vp, vp, vp, dbl, dbl, ctypes.POINTER(vp)],
             "qgw_state_destroy": [vp],
             "qgw_state_init_g0": [vp, pd, vp],
@@ -283,6 +284,14 @@ class Plan:
         m = ctypes.c_double(float(mu))
         nt = float("nan") if n_target is None else float(n_target)
         _check(lib().qgw_dyson_G(self.handle, _ptr(h_k), _ptr(sig_iw), nt, ctypes.byref(m), _ptr(out), _stream()))
+        return m.value
+
+    def dyson_G_noalloc(self, h_k, sig_iw, out, n_target=None, mu=0.0):
+        """qgw_dyson_G with the search scratch in the library's static device array (allocates nothing)."""
+        m = ctypes.c_double(float(mu))
+        nt = float("nan") if n_target is None else float(n_target)
+        _check(lib().qgw_dyson_G_noalloc(self.handle, _ptr(h_k), _ptr(sig_iw), nt, ctypes.byref(m), _ptr(out),
+                                         _stream()))
         return m.value
 
     def check_finite(self, x):
