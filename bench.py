@@ -327,6 +327,131 @@ def mf_leg(torch, qgw, w, steps, tol, warmup=2, mixing=1.0, dlr_ms=None, name=""
     return res
 
 
+def adjoint_model(r, n_o, n_b, n_k):
+    """Algorithmic HBM bytes and flops of one call of each adjoint step (FP64; S_P and S_G are one pair and one
+    orbital array with nodes).  Only what the adjoint must read and write once is counted."""
+    sp = 16.0 * r * n_b * n_b * n_k
+    sg = 16.0 * r * n_o * n_o * n_k
+    so = 16.0 * n_o * n_o * n_k
+    stat_p = 16.0 * n_b * n_b * n_k
+    fft_flops = 5.0 * n_k * math.log2(max(n_k, 2))
+    return {
+        # Pbar (read once), G(tau), G(beta - tau) read, both cotangents written
+        "bubble_bwd": {"bytes": sp + 4 * sg, "flops": r * n_b * n_b * (fft_flops + 16.0 * n_k)},
+        # W^C read, W^C-bar written, G and Sigma-bar read, G-bar written
+        "sigma_bwd": {"bytes": 2 * sp + 3 * sg, "flops": 2 * r * n_b * n_b * (fft_flops + 8.0 * n_k)},
+        # P and W-bar read, P-bar written; per matrix V P, the inverse and five products of N_b^3 complex MACs
+        "dyson_W_bwd": {"bytes": 3 * sp + 2 * stat_p, "flops": 7 * 8.0 * n_b ** 3 * r * n_k},
+        "dlr_transform_pairs_bwd": {"bytes": 2 * sp, "flops": 8.0 * r * r * n_b * n_b * n_k},
+        "dlr_transform_bwd": {"bytes": 2 * sg, "flops": 8.0 * r * r * n_o * n_o * n_k},
+        "lattice_fft_bwd": {"bytes": 2 * sg, "flops": r * n_o * n_o * fft_flops},
+        # G-bar, Sigma, H read, Sigma-bar written (the implicit-mu pass rereads and rewrites it)
+        "dyson_G_bwd": {"bytes": 5 * sg + so, "flops": 0.0},
+        "hartree_fock_bwd": {"bytes": 2 * stat_p + 4 * so, "flops": 0.0},
+        "energy_bwd": {"bytes": 6 * sg, "flops": 8.0 * r * r * n_o * n_o * n_k},
+    }
+
+
+class _CallTimer:
+    """HIP events on torch's current stream (the stream every library call here is queued on) around each call of
+    the wrapped plan methods; durations are read after the timed region's final synchronisation."""
+
+    def __init__(self, torch, plan, names):
+        self.torch, self.plan, self.names = torch, plan, names
+        self.pending = {n: [] for n in names}
+        self.orig = {n: getattr(plan, n) for n in names}
+        for n in names:
+            setattr(plan, n, self._wrap(n, self.orig[n]))
+
+    def _wrap(self, name, f):
+        def g(*a, **k):
+            e0 = self.torch.cuda.Event(enable_timing=True)
+            e1 = self.torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = f(*a, **k)
+            e1.record()
+            self.pending[name].append((e0, e1))
+            return r
+        return g
+
+    def reset(self):
+        for n in self.names:
+            self.pending[n] = []
+
+    def totals(self):
+        return {n: (sum(a.elapsed_time(b) for a, b in v), len(v)) for n, v in self.pending.items() if v}
+
+    def close(self):
+        for n in self.names:
+            setattr(self.plan, n, self.orig[n])
+
+
+def adjoint_leg(torch, qgw, steps, warmup=1):
+    """The five-orbital model at 48 x 48, beta = 100 (r = 59), benchmark interaction: one GW iteration from G0
+    through the autograd layer with per-iteration checkpointing, then the backward pass of
+    L = Re sum conj(C) Sigma^C(k, i w_0) + E (w_0 = pi / beta, C seeded), i.e. the gradients of Sigma(k, i w_0) and of
+    the total energy with respect to H0(R) and V(R) (through them the hoppings, U, J and V).  HIP events time the
+    whole forward + backward and each adjoint call."""
+    from paper_2604_22223_amd import autograd as qa
+    from paper_2604_22223_amd import workloads as wl
+    w = wl.workload("five_orbital_48")
+    nodes = qgw.dlr_build(w["beta"] * w["omega_max"], w["eps"])
+    nodes["omega"] = nodes["x"] / w["beta"]
+    plan = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], nodes)
+    flat = lambda x: torch.from_numpy(np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))).to("cuda:0")
+    m0 = int(np.nonzero(nodes["n_f"] == 0)[0][0])
+    rng = np.random.default_rng(48)
+    shp = (plan.n_o, plan.n_o, plan.n_k)
+    cs = torch.from_numpy(rng.standard_normal(shp) + 1j * rng.standard_normal(shp)).to("cuda:0")
+    H0, V0 = flat(w["H_R"]), flat(w["V_R"])
+
+    def step():
+        H_R = H0.clone().requires_grad_(True)
+        V_R = V0.clone().requires_grad_(True)
+        G, mu, Siw, shf = qa.run(plan, H_R, V_R, w["n_target"], n_iter=1, checkpointed=True)[-1]
+        H_k = qa.FFT.apply(plan, qgw.R_TO_K, H_R)
+        loss = (cs.conj() * Siw[m0]).real.sum() + qa.energy(plan, H_k, shf, Siw, G).to(cs.device)
+        loss.backward()
+        return H_R.grad, V_R.grad
+
+    names = sorted(adjoint_model(1, 1, 1, 1))
+    timer = _CallTimer(torch, plan, names)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    timer.reset()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        gh, gv = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tot = timer.totals()
+    timer.close()
+    model = adjoint_model(plan.r, plan.n_o, plan.n_b, plan.n_k)
+    calls = {}
+    for n, (t, c) in tot.items():
+        per = t / c
+        e = model[n]
+        b = bound_of(e, "f64")
+        calls[n] = dict(roof(e, "f64", per), calls_per_step=c // steps,
+                        per_call={"bytes": e["bytes"], "flops": e["flops"]})
+        log("[bench]   adjoint %-24s %8.4f ms x %d per step  %-3s %9.2f %-7s (%.1f%% of peak)"
+            % (n, per, c // steps, b, calls[n]["achieved"], calls[n]["unit"], 100 * calls[n]["frac"]))
+    res = {"workload": "five_orbital_48", "mesh": "48x48", "beta": w["beta"], "dlr_rank": plan.r,
+           "U": w["interaction"]["U"], "J": w["interaction"]["J"], "V_nn": w["interaction"]["V_nn"],
+           "steps": steps, "ms_per_forward_backward": round(ms, 4),
+           "adjoint_ms_per_step": round(sum(t for t, _ in tot.values()) / steps, 4),
+           "loss": "Re sum conj(C) Sigma^C(k, i pi/beta) + E_GM, gradients in H0(R) and V(R)",
+           "grad_norms": {"H_R": float(gh.abs().max()), "V_R": float(gv.abs().max())},
+           "calls": calls}
+    log("[bench] adjoint leg 48x48: %.3f ms per forward + backward (%.3f ms in adjoint calls)"
+        % (ms, res["adjoint_ms_per_step"]))
+    plan.close()
+    return res
+
+
 def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
     """Seeded instances of uneven size (1-5 orbitals, 12^2-48^2 meshes, beta 10-100) advanced by one
     graph launch per iteration, FP64 and FP32 bulk steps, against the same states iterated one by one."""
@@ -417,7 +542,9 @@ def main():
                     help="timed iterations of the uniform-Matsubara-grid plans (0 skips them)")
     ap.add_argument("--paper-steps", type=int, default=20, metavar="K",
                     help="timed iterations of the paper's 8x8x8 five-orbital workload per schedule (0 skips it)")
-    ap.add_argument("--batch-mu-steps", type=int, default=48)
+    ap.add_argument("--batch-mu-steps", type=int, default=64)
+    ap.add_argument("--adjoint-steps", type=int, default=3, metavar="K",
+                    help="timed forward + backward steps of the 48x48 adjoint leg (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer three times (a plain copy kernel of known size "
                          "that scales the HBM byte counters of a profiler run)")
@@ -530,6 +657,7 @@ def main():
             mf.append(mf_leg(torch, qgw, wl.workload("cubic_five_orbital_8"), a.mf_steps, a.tol, mixing=0.5,
                              dlr_ms=paper["fp64"]["ms_per_iteration"], name="cubic_five_orbital_8"))
     batch = batch_leg(torch, qgw, a.batch, a.batch_launches, 1, a.batch_mu_steps) if a.batch > 0 else None
+    adjoint = adjoint_leg(torch, qgw, a.adjoint_steps) if a.adjoint_steps > 0 else None
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -557,6 +685,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batch": batch,
+        "adjoint": adjoint,
         "quasiparticle": qpl,
         "hartree_fock": hfl,
         "paper_workload": paper,

@@ -197,7 +197,7 @@ def test_five_orbital_48_one_iteration(five48):
 def test_five_orbital_48_gradient_by_gpu_finite_differences():
     torch = _torch()
     from paper_2604_22223_amd import autograd as qa
-    c = Full("five_orbital_48 (U = 4)", wl.five_orbital(n=48, beta=100.0, omega_max=25.0, eps=1e-10), iterate=False)
+    c = Full("five_orbital_48", iterate=False)
     m, p = c.m, c.plan
     rng = np.random.default_rng(48)
     shp = (c.d.r, m.n_o, m.n_o) + m.mesh

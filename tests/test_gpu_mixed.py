@@ -32,14 +32,14 @@ def flat(x):
 
 @pytest.fixture(scope="module")
 def five8():
-    """Five orbitals on an 8 x 8 mesh, beta = 20, converged by the oracle to 1e-10."""
+    """Five orbitals on an 8 x 8 mesh, beta = 20, converged by the oracle to 1e-12."""
     print("\n[mixed case] five_orbital_8x8", flush=True)
     w = wl.five_orbital(n=8, U=1.0, J=0.1, Vnn=0.2, beta=20.0, omega_max=25.0, eps=1e-10, scale_mesh=8)
     d = DLR(w["beta"], w["omega_max"], w["eps"])
     m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
     st0 = gw.initial_state(m, d)
-    conv, hist = gw.scf(m, d, tol=1e-10, max_iter=40, state=st0)
-    assert hist[-1][0] <= 1e-10
+    conv, hist = gw.scf(m, d, tol=1e-12, max_iter=60, state=st0)
+    assert hist[-1][0] <= 1e-12
     return {"w": w, "d": d, "m": m, "st0": st0, "conv": conv}
 
 
@@ -95,6 +95,23 @@ def test_mixed_solve_reaches_oracle_fixed_point(five8):
     assert np.max(np.abs(st.array(2).cpu().numpy() - flat(conv["sig_hf_k"]))) <= 1e-6
     assert np.max(np.abs(st.array(0).cpu().numpy() - flat(conv["G_iw"]))) <= 1e-6
     assert abs(mu - conv["mu"]) <= 1e-7
+    st.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_converged_end_point_at_the_fp64_bar(five8, mode):
+    """Both sides converged to max |Delta Sigma| <= 1e-12 (FP64 iterations finish the mixed schedule too): the
+    GPU fixed point equals the oracle's to the FP64 bar, Sigma^C, Sigma_HF and G at 1e-10 relative, mu at 1e-10."""
+    m, d, conv = five8["m"], five8["d"], five8["conv"]
+    plan = qgw.Plan.from_nodes(8, [5], d.beta, d.nodes())
+    st, hist, mu = _run(plan, m, mode, 1e-12, max_iter=60)
+    print("[mixed] mode %d to 1e-12: %d iterations, last %.1e" % (mode, len(hist), hist[-1][0]), flush=True)
+    assert hist[-1][0] <= 1e-12 and hist[-1][1] == 0
+    for which, key in ((1, "sig_iw"), (2, "sig_hf_k"), (0, "G_iw")):
+        a, b = st.array(which).cpu().numpy(), flat(conv[key])
+        assert np.max(np.abs(a - b)) <= 1e-10 * np.max(np.abs(b)), (key, np.max(np.abs(a - b)))
+    assert abs(mu - conv["mu"]) <= 1e-10 * max(1.0, abs(conv["mu"]))
     st.close()
     plan.close()
 
