@@ -71,13 +71,15 @@ def _hopping_bandwidth(hops, norb, n):
 
 def five_orbital(n=24, seed=22223, bandwidth=4.0, U=4.0, J=0.7, Vnn=1.0,
                  beta=50.0, omega_max=25.0, eps=1e-10, n_target=6.0,
-                 norb=5, scale_mesh=24):
+                 norb=5, scale_mesh=24, slater_F=None):
     """Extended Hund-Hubbard model on a square lattice, one site, ``norb`` orbitals.
 
     Hopping: i.i.d. complex Gaussian norb x norb matrices on the bonds
     x, y, x+y, x-y (seeded), t(-R) = t(R)^dagger, no on-site term, scaled so
     that the band width over a ``scale_mesh`` x ``scale_mesh`` mesh equals
-    ``bandwidth``.  Interaction: on-site Kanamori (U, J) plus a
+    ``bandwidth``.  Interaction: on-site Kanamori (U, J), or with
+    ``slater_F`` = (F^0, F^2, F^4) the full Slater tensor of a d shell in the
+    real-harmonic basis (norb = 5; U and J are then ignored), plus a
     nearest-neighbour density-density V_(ii),(jj)(+-x, +-y) = Vnn.
     """
     rng = np.random.default_rng(seed)
@@ -92,7 +94,13 @@ def five_orbital(n=24, seed=22223, bandwidth=4.0, U=4.0, J=0.7, Vnn=1.0,
         H_R[:, :, r1 % n, r2 % n] += scale * t
     nb = norb * norb
     V_R = np.zeros((nb, nb, n, n), dtype=np.complex128)
-    V_R[:, :, 0, 0] = _kanamori_block(norb, U, J)
+    if slater_F is None:
+        V_R[:, :, 0, 0] = _kanamori_block(norb, U, J)
+    else:
+        from . import interactions
+        assert norb == 5, "the Slater tensor is that of a d shell"
+        V_R[:, :, 0, 0] = interactions.pair_tensor(interactions.slater_tensor(2, slater_F))
+        U, _, J = interactions.kanamori_from_slater(2, slater_F)
     for (r1, r2) in [(1, 0), (-1, 0), (0, 1), (0, -1)]:
         for i in range(norb):
             for j in range(norb):

@@ -15,6 +15,7 @@ from conftest import rel_err
 from oracle import gw, lattice
 from oracle.dlr import DLR
 from paper_2604_22223_amd import qgw
+from paper_2604_22223_amd import interactions
 from paper_2604_22223_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -63,6 +64,10 @@ CASE_SPECS = {
     # five orbitals (N_b = 25) on a 10 x 10 mesh: N_k = 100 leaves ragged tiles
     "five_orbital_10x10": lambda: wl.five_orbital(n=10, U=1.0, J=0.1, Vnn=0.2, beta=20.0, omega_max=25.0,
                                                   eps=1e-10, scale_mesh=10),
+    # the full Slater tensor of a d shell on site (every element of the five-orbital pair basis, not only the
+    # Kanamori ones), with the Slater integrals whose shell averages are U = 1, J = 0.1 eV
+    "slater_d_8x8": lambda: wl.five_orbital(n=8, Vnn=0.2, beta=20.0, omega_max=25.0, eps=1e-10, scale_mesh=8,
+                                            slater_F=interactions.slater_from_kanamori(2, 1.0, 0.1)),
     # graphene G0W0 workload at its full size (12 x 12, r = 43)
     "graphene_g0w0_12": lambda: wl.workload("graphene_g0w0_12"),
     # cubic meshes: 3 orbitals on two sites on 4 x 4 x 4, five orbitals on 6 x 6 x 6 (radix 3 and 2).
