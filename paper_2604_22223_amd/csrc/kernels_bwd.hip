@@ -94,13 +94,18 @@ __global__ __launch_bounds__(256) void k_sigma_bwd_wc(const zd* __restrict__ gt,
 }
 
 // ---------------------------------------------------------------------------
-// contraction adjoints; one block per output slab (t, key)
+// contraction adjoints; one block per output slab (t, key), in the XCD-aware
+// block order of the forward kernels (the outputs of one time node share an
+// L2, which holds the Y slabs they all read)
 //   MODE 0: key (l, j), terms (alpha, beta, i, k); X = conj(W^C(R)) with
 //           W^C(R) = (1/N_k) sum_q e^{iq.R} W^C(q); Y = Sbar_ik(R); c = -1
 //   MODE 1: key (l, j), terms (alpha, beta, i, k); X = Pbar(R) = sum_q e^{iq.R} Pbar(q);
 //           Y = conj(G_ki(-R, beta - t)); c = -2
 //   MODE 2: key (i, k), terms (alpha, beta, l, j); X = Pbar(R); Y = conj(G_lj(R, t)); c = -2;
 //           the sum is the cotangent of G_ki(-R, beta - t), stored in slab (t, k, i) at -R
+// Per term a lane loads one column of the X(q) slab straight into registers (N independent coalesced
+// loads), transforms it along q1, passes it through LDS once to hold a row R1, transforms along q2 and
+// accumulates X Y for that row; the lanes' rows are summed through LDS and stored coalesced.
 // ---------------------------------------------------------------------------
 template <int N, int MODE>
 __global__ __launch_bounds__(256) void k_contract_bwd(const zd* __restrict__ xq, const zd* __restrict__ y,
@@ -111,82 +116,82 @@ __global__ __launch_bounds__(256) void k_contract_bwd(const zd* __restrict__ xq,
   using M = MeshShape<N>;
   extern __shared__ unsigned char smem_raw[];
   cpx<double>* lds = reinterpret_cast<cpx<double>*>(smem_raw);
-  const int out_slab = blockIdx.x;  // t * no^2 + key
+  const int out_slab = int(xcd_block(blockIdx.x, gridDim.x));  // t * no^2 + key
   const int key = out_slab % (no * no);
   const int64_t t = out_slab / (no * no);
   const int tb = term_off[key], te = term_off[key + 1];
   const int lane = threadIdx.x / N, line = threadIdx.x - lane * N;
   const bool act = lane < spb;
-  cpx<double> acc[N];
+  cpx<double> acc[N];  // row R1 = line of this lane's partial sum
 #pragma unroll
   for (int j = 0; j < N; ++j) acc[j] = mk(0.0, 0.0);
   cpx<double> x[N];
+  cpx<double>* slab = lds + lane * M::SLAB;
   for (int c0 = tb; c0 < te; c0 += spb) {
-    const int nloc = (te - c0 < spb) ? te - c0 : spb;
-    for (int e = threadIdx.x; e < nloc * M::NN; e += blockDim.x) {
-      const int sl = e / M::NN, rem = e - sl * M::NN;
-      const int4 tm = terms[c0 + sl];
+    const bool mine = act && c0 + lane < te;
+    int4 tm = make_int4(0, 0, 0, 0);
+    if (mine) {
+      tm = terms[c0 + lane];
       const zd* w = xq + ((t * nb + tm.x) * nb + tm.y) * M::NN;
-      const int q1 = rem / N, q2 = rem - q1 * N;
-      lds[sl * M::SLAB + q1 * M::LD + q2] = w[rem];
+#pragma unroll
+      for (int j = 0; j < N; ++j) x[j] = w[j * N + line];  // column q2 = line
+      fft_reg<N, +1>(x, tw);                                 // q1 -> R1
+#pragma unroll
+      for (int j = 0; j < N; ++j) slab[j * M::LD + line] = x[j];
     }
     __syncthreads();
-    if (act && lane < nloc) {
-      cpx<double>* slab = lds + lane * M::SLAB;
+    if (mine) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) x[j] = slab[line * M::LD + j];
-      fft_reg<N, +1>(x, tw);  // q2 -> R2
-#pragma unroll
-      for (int j = 0; j < N; ++j) slab[line * M::LD + j] = x[j];
-    }
-    __syncthreads();
-    if (act && lane < nloc) {
-      const int4 tm = terms[c0 + lane];
-      const cpx<double>* slab = lds + lane * M::SLAB;
-#pragma unroll
-      for (int j = 0; j < N; ++j) x[j] = slab[j * M::LD + line];
-      fft_reg<N, +1>(x, tw);  // q1 -> R1; x[j] = X(R1 = j, R2 = line)
+      for (int j = 0; j < N; ++j) x[j] = slab[line * M::LD + j];  // row R1 = line
+      fft_reg<N, +1>(x, tw);                                       // q2 -> R2; x[j] = X(R1 = line, R2 = j)
       if (MODE == 0) {
-        const zd* g = y + ((t * no + tm.z) * no + tm.w) * M::NN;
+        const zd* g = y + ((t * no + tm.z) * no + tm.w) * M::NN + line * N;
 #pragma unroll
-        for (int j = 0; j < N; ++j) acc[j] = fma(acc[j], conj(x[j]), g[j * N + line]);
+        for (int j = 0; j < N; ++j) acc[j] = fma(acc[j], conj(x[j]), g[j]);
       } else if (MODE == 1) {
-        const zd* g = y + ((t * no + tm.w) * no + tm.z) * M::NN;
-        const int ml = (N - line) % N;
+        const zd* g = y + ((t * no + tm.w) * no + tm.z) * M::NN + ((N - line) % N) * N;
 #pragma unroll
-        for (int j = 0; j < N; ++j) acc[j] = fma(acc[j], x[j], conj(g[((N - j) % N) * N + ml]));
+        for (int j = 0; j < N; ++j) acc[j] = fma(acc[j], x[j], conj(g[(N - j) % N]));
       } else {
-        const zd* g = y + ((t * no + tm.z) * no + tm.w) * M::NN;
+        const zd* g = y + ((t * no + tm.z) * no + tm.w) * M::NN + line * N;
 #pragma unroll
-        for (int j = 0; j < N; ++j) acc[j] = fma(acc[j], x[j], conj(g[j * N + line]));
+        for (int j = 0; j < N; ++j) acc[j] = fma(acc[j], x[j], conj(g[j]));
       }
     }
-    __syncthreads();
+    __syncthreads();  // the slab is free for the next term
   }
+  // reduce the term lanes: lane partial rows -> LDS, the first lane's threads add them up in a fixed order
   if (act) {
-    cpx<double>* slab = lds + lane * M::SLAB;
 #pragma unroll
-    for (int j = 0; j < N; ++j) slab[j * M::LD + line] = acc[j];
+    for (int j = 0; j < N; ++j) slab[line * M::LD + j] = acc[j];
   }
   __syncthreads();
   if (threadIdx.x < N) {
     const double c = MODE == 0 ? -1.0 / double(M::NN) : -2.0;
-    int oslab = out_slab;
-    if (MODE == 2) {
-      const int i = key / no, k = key - i * no;
-      oslab = int(t) * no * no + k * no + i;
-    }
-    zd* o = out + int64_t(oslab) * M::NN;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      cpx<double> s = lds[j * M::LD + line];
-      for (int l2 = 1; l2 < spb; ++l2) s = s + lds[l2 * M::SLAB + j * M::LD + line];
-      s = scale(s, c);
-      if (MODE == 2)
-        o[((N - j) % N) * N + (N - line) % N] = s;
-      else
-        o[j * N + line] = s;
+      cpx<double> s = lds[line * M::LD + j];
+      for (int l2 = 1; l2 < spb; ++l2) s = s + lds[l2 * M::SLAB + line * M::LD + j];
+      x[j] = scale(s, c);
     }
+  }
+  __syncthreads();  // every lane's partial row has been read
+  if (threadIdx.x < N) {
+    // MODE 2 stores at -R: row (N - line) % N, column (N - j) % N
+    const int r1 = MODE == 2 ? (N - line) % N : line;
+#pragma unroll
+    for (int j = 0; j < N; ++j) lds[r1 * M::LD + (MODE == 2 ? (N - j) % N : j)] = x[j];
+  }
+  __syncthreads();
+  int oslab = out_slab;
+  if (MODE == 2) {
+    const int i = key / no, k = key - i * no;
+    oslab = int(t) * no * no + k * no + i;
+  }
+  zd* o = out + int64_t(oslab) * M::NN;
+  for (int e = threadIdx.x; e < M::NN; e += blockDim.x) {
+    const int r1 = e / N, r2 = e - r1 * N;
+    o[e] = lds[r1 * M::LD + r2];
   }
 }
 
@@ -211,8 +216,11 @@ hipError_t sigma_bwd_wc_n(const Plan& p, const void* gt, const void* sbar, void*
 template <int N>
 hipError_t contract_bwd_n(const Plan& p, int mode, const void* xq, const void* y, void* out, hipStream_t s) {
   const TermTable& tt = (mode == 2) ? p.terms : p.terms_lj;
+  // term lanes: the largest divisor of the per-output term count that fits (every lane gets the same count)
   const int cap = slabs_per_block<double>(N, kLdsBudget);
-  const int spb = tt.max_terms < cap ? (tt.max_terms > 0 ? tt.max_terms : 1) : cap;
+  int spb = 1;
+  for (int d = 1; d <= tt.max_terms && d <= cap; ++d)
+    if (tt.max_terms % d == 0) spb = d;
   const size_t lds = size_t(spb) * MeshShape<N>::SLAB * sizeof(zd);
   const unsigned blocks = unsigned(int64_t(p.r) * p.no * p.no);
   auto go = [&](auto kern) {
