@@ -372,7 +372,9 @@ qgw_status qgw_sigma_bwd(qgw_plan plan, const void *G_tau_R, const void *Wc_q,
  *   Pbar = W^H Wbar W^H,   Vbar = sum over nodes [A^{-H} Wbar (I + P W)^H - Wbar].
  * V_q, Vbar_q: [N_k][N_b][N_b]; P_nu, Wcbar_nu, Pbar_nu: pair matrix
  * layout.  The node sum runs in a fixed order (deterministic).  Workspace
- * (min(r, 8) N_b^2 N_k complex, QGW_OP_DYSON_W_BWD). */
+ * ((2 r + min(r, 8)) N_b^2 N_k complex, QGW_OP_DYSON_W_BWD: W^C and
+ * X = (I - V P)^{-H} Wbar per matrix, and the partial node sums of Vbar).
+ * A zero or non-finite pivot sets the device status word as in qgw_dyson_W. */
 qgw_status qgw_dyson_W_bwd(qgw_plan plan, const void *V_q, const void *P_nu,
                            const void *Wcbar_nu, void *Pbar_nu, void *Vbar_q,
                            void *workspace, int64_t workspace_bytes, void *stream);

@@ -785,8 +785,8 @@ static int64_t workspace_need(const Plan& p, int op) {
   switch (op) {
     case QGW_OP_SIGMA_BWD:
       return fo;  // Sigma-bar(k) -> R
-    case QGW_OP_DYSON_W_BWD:
-      return int64_t(p.r < 8 ? p.r : 8) * p.nb * p.nb * p.nk * int64_t(sizeof(zd));  // V-bar partials per chunk
+    case QGW_OP_DYSON_W_BWD:  // W^C and X = (I - V P)^{-H} Wbar per matrix, V-bar partials per chunk
+      return (2 * int64_t(p.r) + (p.r < 8 ? p.r : 8)) * p.nb * p.nb * p.nk * int64_t(sizeof(zd));
     case QGW_OP_HARTREE_FOCK_BWD:
       return int64_t(p.nb) * p.nb * int64_t(sizeof(zd));  // V(q = 0)
     case QGW_OP_ENERGY:
@@ -908,7 +908,8 @@ qgw_status qgw_dyson_W_bwd(qgw_plan h, const void* V_q, const void* P_nu, const 
   QGW_WORKSPACE(QGW_OP_DYSON_W_BWD, workspace, workspace_bytes, "qgw_dyson_W_bwd");
   hipStream_t s = (hipStream_t)stream;
   QGW_CHECK_HIP(launch_dyson_w_bwd(p, V_q, P_nu, Wcbar_nu, Pbar_nu, workspace, chunks, s), "qgw_dyson_W_bwd");
-  QGW_CHECK_HIP(launch_sum_chunks(nv, chunks, workspace, Vbar_q, s), "qgw_dyson_W_bwd");
+  const zd* vpart = (const zd*)workspace + 2 * int64_t(p.r) * nv;
+  QGW_CHECK_HIP(launch_sum_chunks(nv, chunks, vpart, Vbar_q, s), "qgw_dyson_W_bwd");
   return QGW_OK;
 }
 

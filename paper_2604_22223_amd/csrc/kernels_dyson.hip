@@ -53,11 +53,12 @@ __device__ __forceinline__ cpx<T> shfl_cpx(cpx<T> v, int src, int width) {
   return mk(__shfl(v.re, src, width), __shfl(v.im, src, width));
 }
 
-template <int NB, typename T>
+// ADJ: solve (I - V P)^H X = B instead, with B (pair matrix layout, dense) in place of V, and write X
+template <int NB, typename T, bool ADJ = false>
 __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
                                                 const cpx<T>* __restrict__ pnu,
                                                 cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld,
-                                                int* __restrict__ cond) {
+                                                int* __restrict__ cond, const cpx<T>* __restrict__ rhs = nullptr) {
   using S = DysonWShape<NB>;
   __shared__ cpx<T> sp[S::MPW * S::NN];
   __shared__ cpx<T> piv[2][S::MPW][2 * NB];
@@ -107,7 +108,10 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
   if (valid) {
     if (half == 0) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) x[c] = pm[row * NB + c];
+      for (int c = 0; c < NB; ++c) x[c] = ADJ ? conj(pm[c * NB + row]) : pm[row * NB + c];
+    } else if (ADJ) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) x[c] = rhs[mat * S::NN + row * NB + c];
     } else {
 #pragma unroll
       for (int c = 0; c < NB; ++c) x[c] = vrow[c];
@@ -159,7 +163,7 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
   if (valid && half == 1) {
     const cpx<T>* vr = vq + (int64_t(q) * NB + my_step) * NB;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) sp[mw * S::NN + my_step * NB + c] = x[c] - vr[c];
+    for (int c = 0; c < NB; ++c) sp[mw * S::NN + my_step * NB + c] = ADJ ? x[c] : x[c] - vr[c];
   }
   __syncthreads();
   for (int e = lane; e < nload; e += 64) {
@@ -306,10 +310,12 @@ __device__ __forceinline__ void gj25_all(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs)
   (gj25_step<T, K>(x, y, cs, kof, k24, rg, cg, xs, singular), ...);
 }
 
-template <typename T>
+// ADJ: solve (I - V P)^H X = B instead (A is formed as below, passed through the V area of LDS, which ADJ no
+// longer needs, and read back conjugate-transposed), with B (pair matrix layout, dense) in place of V; writes X
+template <typename T, bool ADJ = false>
 __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
                                                   cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld,
-                                                  int* __restrict__ cond) {
+                                                  int* __restrict__ cond, const cpx<T>* __restrict__ rhs = nullptr) {
   constexpr int NB = W25::NB, NN = NB * NB, NS = W25::NS, NT = W25::NT, CH = W25::CH, NCH = W25::NCH;
   __shared__ cpx<T> xs[W25::XS];  // a chunk of P rows; then the pivot exchange
   __shared__ cpx<T> sv[NN];       // V(q)
@@ -369,6 +375,20 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
         }
       }
     }
+    if (ADJ) {
+      // A = I - V P through the V area (every lane has finished reading V), then back as A^H
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int row = rg + 8 * s, c = cg + 8 * t;
+          if (c < NB) sv[row * NB + c] = mk(T(row == c ? 1 : 0) - acc[s][t].re, -acc[s][t].im);
+        }
+      if (c24 < NB) sv[24 * NB + c24] = mk(T(c24 == 24 ? 1 : 0) - a24.re, -a24.im);
+      __syncthreads();
+    }
+    const cpx<T>* bm = ADJ ? rhs + mat * NN : nullptr;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int row = rg + 8 * s;
@@ -377,17 +397,18 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
         const int c = cg + 8 * t;
         cpx<T> val = mk(T(0), T(0));
         if (t < 4 && c < NB)
-          val = mk(T(row == c ? 1 : 0) - acc[s][t < 4 ? t : 0].re, -acc[s][t < 4 ? t : 0].im);
+          val = ADJ ? conj(sv[c * NB + row]) : mk(T(row == c ? 1 : 0) - acc[s][t < 4 ? t : 0].re,
+                                                   -acc[s][t < 4 ? t : 0].im);
         else if (c >= NB && c < 2 * NB)
-          val = sv[row * NB + c - NB];
+          val = ADJ ? bm[row * NB + c - NB] : sv[row * NB + c - NB];
         x[s][t] = val;
       }
     }
     y = mk(T(0), T(0));
     if (c24 < NB)
-      y = mk(T(c24 == 24 ? 1 : 0) - a24.re, -a24.im);
+      y = ADJ ? conj(sv[c24 * NB + 24]) : mk(T(c24 == 24 ? 1 : 0) - a24.re, -a24.im);
     else if (c24 < 2 * NB)
-      y = sv[24 * NB + c24 - NB];
+      y = ADJ ? bm[24 * NB + c24 - NB] : sv[24 * NB + c24 - NB];
   }
   __syncthreads();  // the last chunk has been read: its area takes the pivot exchange
   if (lane < 16) xs[(lane >> 3) * W25::EX + 56 + (lane & 7)] = mk(T(0), T(0));  // pivot-row padding columns
@@ -400,7 +421,7 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
   bool singular = false;
   gj25_all<T>(x, y, cs, kof, k24, rg, cg, xs, singular, std::make_integer_sequence<int, NB>{});
   if (singular && lane == 0) atomicOr(cond, kCondSingular);
-  // row r of the V part is row kof of W; W^C = W - V
+  // row r of the V part is row kof of W; W^C = W - V (ADJ: row kof of X)
   cpx<T>* wm = wc + mat * ld;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -408,10 +429,10 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
 #pragma unroll
     for (int t = 3; t < NT; ++t) {
       const int col = cg + 8 * t - NB;
-      if (col >= 0 && col < NB) wm[k * NB + col] = x[s][t] - sv[k * NB + col];
+      if (col >= 0 && col < NB) wm[k * NB + col] = ADJ ? x[s][t] : x[s][t] - sv[k * NB + col];
     }
   }
-  if (c24 >= NB && c24 < 2 * NB) wm[k24 * NB + c24 - NB] = y - sv[k24 * NB + c24 - NB];
+  if (c24 >= NB && c24 < 2 * NB) wm[k24 * NB + c24 - NB] = ADJ ? y : y - sv[k24 * NB + c24 - NB];
 }
 
 // ---------------------------------------------------------------------------
@@ -748,146 +769,96 @@ __global__ __launch_bounds__(64) void k_dg_final(DysonGArgs A, int n, int nblk) 
 // dW = A^{-1} dV (I + P W) + W dP W.  For a cotangent Wbar of W^C = W - V:
 //   X = A^{-H} Wbar,  Y = X W^H,  Pbar = W^H Wbar W^H = V^H Y,
 //   Vbar = A^{-H} Wbar (I + P W)^H - Wbar = X + Y P^H - Wbar.
-// V(q) is static, so Vbar(q) sums over the bosonic nodes: block (q, chunk)
-// sums the nodes of its chunk in a fixed order and writes a partial.  The
-// matrices live in LDS; 256 threads share each product; the inverse is
-// Gauss-Jordan with partial pivoting on [A | I].
+// W^C and X come from the register Gauss-Jordan kernels above (the forward
+// solve, and its ADJ form on A^H with Wbar as the right-hand side); this
+// kernel forms the products.  Block (q, chunk of nodes), 256 threads: thread
+// (i, g) owns row i and the columns g, g + G, g + 2G of every product, so
+// each LDS value it loads serves three multiply-adds.  V(q) is static, so
+// Vbar(q) sums over the nodes: each block sums its chunk in a fixed order and
+// writes a partial.
 // ---------------------------------------------------------------------------
 template <int NB>
-__global__ __launch_bounds__(256) void k_dyson_w_bwd(const zd* __restrict__ vq, const zd* __restrict__ pnu,
-                                                     const zd* __restrict__ wbar, zd* __restrict__ pbar,
-                                                     zd* __restrict__ vpart, int r, int nk, int chunks) {
+__global__ __launch_bounds__(256) void k_dyson_w_bwd_prod(const zd* __restrict__ vq, const zd* __restrict__ pnu,
+                                                          const zd* __restrict__ wbar, const zd* __restrict__ wcm,
+                                                          const zd* __restrict__ xm, zd* __restrict__ pbar,
+                                                          zd* __restrict__ vpart, int r, int nk, int chunks) {
   constexpr int NN = NB * NB;
-  constexpr int LA = 2 * NB;
-  constexpr int PER = (NN + 255) / 256;
-  __shared__ cpx<double> sV[NN], sA[NB * LA], sP[NN], sX[NN], sW[NN], sf[NB];
-  __shared__ int spiv;
-  __shared__ cpx<double> spinv;
+  constexpr int CPT = 3;                        // columns per thread
+  constexpr int G = (NB + CPT - 1) / CPT;       // column groups
+  static_assert(NB * G <= 256, "one thread per (row, column group)");
+  __shared__ cpx<double> sV[NN], sP[NN], sX[NN], sW[NN], sY[NN];
   const int q = blockIdx.x, ch = blockIdx.y, tid = threadIdx.x;
   const int m0 = int(int64_t(r) * ch / chunks), m1 = int(int64_t(r) * (ch + 1) / chunks);
+  const bool own = tid < NB * G;
+  const int i = own ? tid / G : 0, g = tid - (tid / G) * G;
   for (int e = tid; e < NN; e += 256) sV[e] = vq[int64_t(q) * NN + e];
-  cpx<double> vacc[PER];
+  cpx<double> vacc[CPT];
 #pragma unroll
-  for (int s = 0; s < PER; ++s) vacc[s] = mk(0.0, 0.0);
+  for (int c = 0; c < CPT; ++c) vacc[c] = mk(0.0, 0.0);
   for (int m = m0; m < m1; ++m) {
     const int64_t base = (int64_t(m) * nk + q) * NN;
-    __syncthreads();
+    __syncthreads();  // the previous node's products are done with the LDS tiles
     for (int e = tid; e < NN; e += 256) {
       sP[e] = pnu[base + e];
-      sX[e] = wbar[base + e];
+      sX[e] = xm[base + e];
+      sW[e] = wcm[base + e] + sV[e];  // W = W^C + V
     }
     __syncthreads();
-    for (int e = tid; e < NN; e += 256) {
-      const int a = e / NB, b = e - (e / NB) * NB;
-      cpx<double> acc = mk(0.0, 0.0);
-      for (int c = 0; c < NB; ++c) acc = fma(acc, sV[a * NB + c], sP[c * NB + b]);
-      const double d = (a == b) ? 1.0 : 0.0;
-      sA[a * LA + b] = mk(d - acc.re, -acc.im);
-      sA[a * LA + NB + b] = mk(d, 0.0);
+    // Y = X W^H
+    if (own) {
+      cpx<double> y[CPT];
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) y[c] = mk(0.0, 0.0);
+      // one k per step: an unrolled loop hoists the operand loads and runs out of registers
+#pragma unroll 1
+      for (int k = 0; k < NB; ++k) {
+        const cpx<double> a = sX[i * NB + k];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          const int j = g + c * G;
+          if (j < NB) y[c] = fma(y[c], a, conj(sW[j * NB + k]));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int j = g + c * G;
+        if (j < NB) sY[i * NB + j] = y[c];
+      }
     }
     __syncthreads();
-    for (int kk = 0; kk < NB; ++kk) {
-      if (tid == 0) {
-        int pv = kk;
-        double best = norm2(sA[kk * LA + kk]);
-        for (int i = kk + 1; i < NB; ++i) {
-          const double v = norm2(sA[i * LA + kk]);
-          if (v > best) {
-            best = v;
-            pv = i;
+    // Pbar = V^H Y;  Vbar += X + Y P^H - Wbar
+    if (own) {
+      cpx<double> pb[CPT], vy[CPT];
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) pb[c] = vy[c] = mk(0.0, 0.0);
+#pragma unroll 1
+      for (int k = 0; k < NB; ++k) {
+        const cpx<double> vki = conj(sV[k * NB + i]), yik = sY[i * NB + k];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          const int j = g + c * G;
+          if (j < NB) {
+            pb[c] = fma(pb[c], vki, sY[k * NB + j]);
+            vy[c] = fma(vy[c], yik, conj(sP[j * NB + k]));
           }
         }
-        spiv = pv;
       }
-      __syncthreads();
-      const int pv = spiv;
-      if (pv != kk) {
-        for (int c = tid; c < LA; c += 256) {
-          const cpx<double> t = sA[kk * LA + c];
-          sA[kk * LA + c] = sA[pv * LA + c];
-          sA[pv * LA + c] = t;
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int j = g + c * G;
+        if (j < NB) {
+          pbar[base + i * NB + j] = pb[c];
+          vacc[c] = vacc[c] + (sX[i * NB + j] - wbar[base + i * NB + j]) + vy[c];
         }
-      }
-      __syncthreads();
-      if (tid == 0) spinv = inv(sA[kk * LA + kk]);
-      for (int i = tid; i < NB; i += 256) sf[i] = sA[i * LA + kk];
-      __syncthreads();
-      const cpx<double> pinv = spinv;
-      for (int c = tid; c < LA; c += 256) sA[kk * LA + c] = sA[kk * LA + c] * pinv;
-      __syncthreads();
-      for (int e = tid; e < NB * LA; e += 256) {
-        const int i = e / LA, c = e - (e / LA) * LA;
-        if (i != kk) sA[e] = fms(sA[e], sf[i], sA[kk * LA + c]);
-      }
-      __syncthreads();
-    }
-    // W = A^{-1} V
-    for (int e = tid; e < NN; e += 256) {
-      const int a = e / NB, b = e - (e / NB) * NB;
-      cpx<double> acc = mk(0.0, 0.0);
-      for (int c = 0; c < NB; ++c) acc = fma(acc, sA[a * LA + NB + c], sV[c * NB + b]);
-      sW[e] = acc;
-    }
-    __syncthreads();
-    // X = A^{-H} Wbar; Vbar += X - Wbar
-    cpx<double> xr[PER];
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int e = tid + 256 * s;
-      xr[s] = mk(0.0, 0.0);
-      if (e < NN) {
-        const int a = e / NB, b = e - (e / NB) * NB;
-        cpx<double> acc = mk(0.0, 0.0);
-        for (int c = 0; c < NB; ++c) acc = fma(acc, conj(sA[c * LA + NB + a]), sX[c * NB + b]);
-        xr[s] = acc;
-        vacc[s] = vacc[s] + (acc - sX[e]);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int e = tid + 256 * s;
-      if (e < NN) sX[e] = xr[s];
-    }
-    __syncthreads();
-    // Y = X W^H into the first NN entries of sA
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int e = tid + 256 * s;
-      if (e < NN) {
-        const int a = e / NB, b = e - (e / NB) * NB;
-        cpx<double> acc = mk(0.0, 0.0);
-        for (int c = 0; c < NB; ++c) acc = fma(acc, sX[a * NB + c], conj(sW[b * NB + c]));
-        xr[s] = acc;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int e = tid + 256 * s;
-      if (e < NN) sA[e] = xr[s];
-    }
-    __syncthreads();
-    // Pbar = V^H Y; Vbar += Y P^H
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int e = tid + 256 * s;
-      if (e < NN) {
-        const int a = e / NB, b = e - (e / NB) * NB;
-        cpx<double> pb = mk(0.0, 0.0), vy = mk(0.0, 0.0);
-        for (int c = 0; c < NB; ++c) {
-          pb = fma(pb, conj(sV[c * NB + a]), sA[c * NB + b]);
-          vy = fma(vy, sA[a * NB + c], conj(sP[b * NB + c]));
-        }
-        pbar[base + e] = pb;
-        vacc[s] = vacc[s] + vy;
       }
     }
   }
+  if (own) {
 #pragma unroll
-  for (int s = 0; s < PER; ++s) {
-    const int e = tid + 256 * s;
-    if (e < NN) vpart[(int64_t(ch) * nk + q) * NN + e] = vacc[s];
+    for (int c = 0; c < CPT; ++c) {
+      const int j = g + c * G;
+      if (j < NB) vpart[(int64_t(ch) * nk + q) * NN + i * NB + j] = vacc[c];
+    }
   }
 }
 
@@ -1078,11 +1049,32 @@ hipError_t dyson_g_final_no(const Plan& p, const void* h_k, const void* sig_iw, 
   return hipGetLastError();
 }
 
+// workspace: W^C and X (pair matrix layout, dense), then the Vbar partials [chunks][N_k][N_b][N_b]
 template <int NB>
 hipError_t dyson_w_bwd_nb(const Plan& p, const void* v_q, const void* p_nu, const void* wbar, void* pbar,
-                          void* vpart, int chunks, hipStream_t s) {
-  hipLaunchKernelGGL((k_dyson_w_bwd<NB>), dim3(unsigned(p.nk), unsigned(chunks)), dim3(256), 0, s,
-                     (const zd*)v_q, (const zd*)p_nu, (const zd*)wbar, (zd*)pbar, (zd*)vpart, p.r, p.nk, chunks);
+                          void* ws, int chunks, hipStream_t s) {
+  constexpr int64_t NN = int64_t(NB) * NB;
+  const int64_t nmat = int64_t(p.r) * p.nk;
+  zd* wcm = (zd*)ws;
+  zd* xm = wcm + nmat * NN;
+  zd* vpart = xm + nmat * NN;
+  int* cond = p.d_status + kCondWord;
+  if (NB == 25) {
+    hipLaunchKernelGGL((k_dyson_w25<double, false>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
+                       (const zd*)p_nu, wcm, nmat, p.nk, NN, cond, nullptr);
+    hipLaunchKernelGGL((k_dyson_w25<double, true>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
+                       (const zd*)p_nu, xm, nmat, p.nk, NN, cond, (const zd*)wbar);
+  } else {
+    constexpr int MPW = DysonWShape<NB>::MPW;
+    const unsigned blocks = unsigned((nmat + MPW - 1) / MPW);
+    hipLaunchKernelGGL((k_dyson_w<NB, double, false>), dim3(blocks), dim3(64), 0, s, (const zd*)v_q,
+                       (const zd*)p_nu, wcm, nmat, p.nk, NN, cond, nullptr);
+    hipLaunchKernelGGL((k_dyson_w<NB, double, true>), dim3(blocks), dim3(64), 0, s, (const zd*)v_q,
+                       (const zd*)p_nu, xm, nmat, p.nk, NN, cond, (const zd*)wbar);
+  }
+  hipLaunchKernelGGL((k_dyson_w_bwd_prod<NB>), dim3(unsigned(p.nk), unsigned(chunks)), dim3(256), 0, s,
+                     (const zd*)v_q, (const zd*)p_nu, (const zd*)wbar, (const zd*)wcm, (const zd*)xm, (zd*)pbar,
+                     vpart, p.r, p.nk, chunks);
   return hipGetLastError();
 }
 

@@ -51,12 +51,24 @@ __global__ __launch_bounds__(256) void k_hartree_fock(const zd* __restrict__ v_r
 }
 
 // V(q = 0) = sum_R V(R), fixed summation order
-__global__ void k_pair_sum_r(const zd* __restrict__ v_r, zd* __restrict__ v_q0, int nbb, int nk) {
-  const int ab = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ab >= nbb) return;
-  cpx<double> s = mk(0.0, 0.0);
-  for (int rr = 0; rr < nk; ++rr) s = s + v_r[int64_t(ab) * nk + rr];
-  v_q0[ab] = s;
+// V(q = 0) = sum_R V(R): one wavefront per pair entry, lanes striding over R (coalesced), then a xor butterfly
+// in a fixed order (the same bits in every lane)
+__global__ __launch_bounds__(64) void k_pair_sum_r(const zd* __restrict__ v_r, zd* __restrict__ v_q0, int nbb,
+                                                   int nk) {
+  const int ab = blockIdx.x;
+  const zd* row = v_r + int64_t(ab) * nk;
+  double re = 0.0, im = 0.0;
+  for (int rr = threadIdx.x; rr < nk; rr += 64) {
+    const zd v = row[rr];
+    re += v.re;
+    im += v.im;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (threadIdx.x == 0 && ab < nbb) v_q0[ab] = mk(re, im);
 }
 
 // [A][q] -> [q][A] for a static pair array
@@ -341,7 +353,7 @@ hipError_t launch_hartree_fock(const Plan& p, const void* v_r, const void* v_q0,
 
 hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStream_t s) {
   const int nbb = p.nb * p.nb;
-  hipLaunchKernelGGL(k_pair_sum_r, dim3(nblk(nbb, 64)), dim3(64), 0, s, (const zd*)v_r, (zd*)v_q0, nbb, p.nk);
+  hipLaunchKernelGGL(k_pair_sum_r, dim3(unsigned(nbb)), dim3(64), 0, s, (const zd*)v_r, (zd*)v_q0, nbb, p.nk);
   return hipGetLastError();
 }
 

@@ -216,8 +216,9 @@ hipError_t launch_row_map(const Plan& p, int64_t ncols, double sre, double sim, 
 
 // threads per slab line set: n for a square mesh, n^2 for a cube
 inline int lines_per_slab(const Plan& p) { return p.dim == 3 ? p.n * p.n : p.n; }
+// workspace: W^C and X = (I - V P)^{-H} Wbar (r N_k N_b^2 complex each), then the Vbar partials (chunks N_k N_b^2)
 hipError_t launch_dyson_w_bwd(const Plan& p, const void* v_q, const void* p_nu, const void* wcbar,
-                              void* pbar, void* vbar_partial, int chunks, hipStream_t s);
+                              void* pbar, void* workspace, int chunks, hipStream_t s);
 hipError_t launch_sum_chunks(int64_t n, int chunks, const void* partial, void* out, hipStream_t s);
 // Dyson G adjoint: sbar = G^H Gbar G^H (+ the chemical-potential term when n_target is finite)
 hipError_t launch_dyson_g_bwd(const Plan& p, const void* h_k, const void* sig_iw, double mu,

@@ -60,7 +60,7 @@ def test_workspace_sizes_and_refusals():
     d, p = _plan(6, [5])
     r, no, nb, nk = p.r, p.n_o, p.n_b, p.n_k
     so, se = no * no * nk * 16, no * nk * 8
-    expect = {qgw.OP_SIGMA_BWD: r * so, qgw.OP_DYSON_W_BWD: min(r, 8) * nb * nb * nk * 16,
+    expect = {qgw.OP_SIGMA_BWD: r * so, qgw.OP_DYSON_W_BWD: (2 * r + min(r, 8)) * nb * nb * nk * 16,
               qgw.OP_HARTREE_FOCK_BWD: nb * nb * 16, qgw.OP_ENERGY: 2 * so + r * so + 2 * 4096 * 8 + 64,
               qgw.OP_ENERGY_BWD: 2 * so + 2 * r * so, qgw.OP_HF_DENSITY: so + se + 64 * 8,
               qgw.OP_QUASIPARTICLE: 64}
