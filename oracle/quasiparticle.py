@@ -23,11 +23,21 @@ when n = 0 and n = -1 are nodes):
   printed, a chemical potential puts the bands relative to the Fermi level;
 * quasiparticle bands: the eigenvalues of H_QP(k), ascending.
 
+Bands along a path of k points off the mesh (Fig. fig-band-dos (a)) need
+H0, Sigma_HF and S at those points.  Reading: Fourier interpolation of the
+mesh values, X(k') = sum_R w(R) exp(-i k'.R) X(R) with X(R) the inverse DFT
+of the mesh values and each axis's R taken in (-n/2, n/2]; for even n the
+n/2 term is split equally between +n/2 and -n/2, which gives the weight
+cos(pi f n) for fractional coordinate f.  On mesh points this returns the
+mesh values themselves; hoppings shorter than half the mesh come back as
+the analytic H0(k').
+
 Arrays carry orbital indices first and the mesh axes last; the
 self-energy carries the node axis before them.
 """
 import numpy as np
 
+from . import lattice
 from .gw import hermitian_part
 
 
@@ -60,8 +70,12 @@ def static_self_energy(dlr, sig_hf_k, sig_iw):
 
 def z_inverse(dlr, sig_iw):
     """Z(k)^{-1} = 1 - (S - S^H) / (2 i pi/beta) (Eq. eq-z-factor, central difference over +-pi/beta)."""
-    s = sigma_first_matsubara(dlr, sig_iw)
-    w0 = np.pi / dlr.beta
+    return z_inverse_from_s(sigma_first_matsubara(dlr, sig_iw), dlr.beta)
+
+
+def z_inverse_from_s(s, beta):
+    """Z^{-1} = 1 - (S - S^H) / (2 i pi/beta) from S = Sigma^C(i pi/beta)."""
+    w0 = np.pi / beta
     ds = (s - np.conj(np.swapaxes(s, 0, 1))) / (2j * w0)
     n_o = s.shape[0]
     eye = np.eye(n_o).reshape((n_o, n_o) + (1,) * (s.ndim - 2))
@@ -98,3 +112,43 @@ def quasiparticle(model, dlr, state, mu=0.0):
     z = matrix_power_hermitian(zinv, -1.0)
     hqp = qp_hamiltonian(model.H_k, sig0, zinv, mu)
     return {"sig0": sig0, "zinv": zinv, "z": z, "hqp": hqp, "bands": qp_bands(hqp)}
+
+
+def interpolation_phases(mesh, kfrac):
+    """w(R) exp(-2 pi i f.R) for every mesh R and path point f (fractional coordinates): [npt, *mesh]."""
+    kfrac = np.atleast_2d(np.asarray(kfrac, dtype=np.float64))
+    out = np.ones((kfrac.shape[0],) + tuple(mesh), dtype=np.complex128)
+    for a, n in enumerate(mesh):
+        R = np.arange(n)
+        rep = np.where(R < n / 2.0, R, R - n).astype(np.float64)
+        f = kfrac[:, a][:, None]
+        ph = np.exp(-2j * np.pi * f * rep[None, :])
+        if n % 2 == 0:
+            ph[:, n // 2] = np.cos(np.pi * f[:, 0] * n)
+        shape = [kfrac.shape[0]] + [1] * len(mesh)
+        shape[1 + a] = n
+        out = out * ph.reshape(shape)
+    return out
+
+
+def fourier_interpolate(x_k, kfrac):
+    """X(k') from the mesh values x_k [a, b, *mesh] at the points kfrac [npt, d]: [a, b, npt]."""
+    d = len(np.atleast_2d(kfrac)[0])
+    mesh = x_k.shape[-d:]
+    x_r = lattice.R_from_k(x_k, d)
+    ph = interpolation_phases(mesh, kfrac)
+    axes = tuple(range(x_k.ndim - d, x_k.ndim))
+    return np.tensordot(x_r, ph, axes=(axes, tuple(range(1, d + 1))))
+
+
+def quasiparticle_path(model, dlr, state, kfrac, mu=0.0):
+    """The quasiparticle outputs at path points kfrac [npt, d] (fractional coordinates of the reciprocal basis):
+    H0, Sigma_HF and S = Sigma^C(i pi/beta) interpolated from the mesh, then the relations above per point."""
+    h = fourier_interpolate(model.H_k, kfrac)
+    shf = fourier_interpolate(state["sig_hf_k"], kfrac)
+    s = fourier_interpolate(sigma_first_matsubara(dlr, state["sig_iw"]), kfrac)
+    sig0 = hermitian_part(shf + s)
+    zinv = z_inverse_from_s(s, dlr.beta)
+    z = matrix_power_hermitian(zinv, -1.0)
+    hqp = qp_hamiltonian(h, sig0, zinv, mu)
+    return {"h0": h, "sig0": sig0, "zinv": zinv, "z": z, "hqp": hqp, "bands": qp_bands(hqp)}

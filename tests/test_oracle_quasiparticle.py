@@ -12,6 +12,7 @@ import pytest
 from conftest import rel_err
 from oracle import gw, quasiparticle as qp
 from oracle.dlr import DLR
+from paper_2604_22223_amd import workloads as wl
 
 
 def herm(rng, shape):
@@ -130,3 +131,59 @@ def test_gw_state_renormalisation_below_one():
     assert ev.min() > 0.0 and ev.max() <= 1.0 + 1e-12
     # a renormalised band is narrower than the band it comes from
     assert np.ptp(out["bands"]) < np.ptp(np.linalg.eigvalsh(np.moveaxis(m.H_k + out["sig0"], (0, 1), (-2, -1))))
+
+
+# ----------------------------------------------------------------------------
+# bands along a k path (Fourier interpolation of the mesh values)
+# ----------------------------------------------------------------------------
+
+def test_path_on_mesh_points_equals_mesh():
+    """At the mesh's own k points the interpolation returns the mesh values: every path output equals the mesh
+    output (a 5 x 6 mesh: odd and even sides, the split n/2 shell included)."""
+    w = wl.random_model((5, 6), [2, 1], seed=3, beta=10.0, omega_max=20.0, eps=1e-10)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
+    st = gw.gw_iteration(m, d, gw.initial_state(m, d))
+    ref = qp.quasiparticle(m, d, st, mu=st["mu"])
+    k = np.array([[i / 5, j / 6] for i in range(5) for j in range(6)])
+    out = qp.quasiparticle_path(m, d, st, k, mu=st["mu"])
+    for key in ("sig0", "zinv", "z", "hqp", "bands"):
+        r = ref[key]
+        assert np.abs(out[key] - r.reshape(r.shape[:-2] + (-1,))).max() < 1e-12, key
+
+
+@pytest.mark.parametrize("seed", [22223, 5])
+def test_path_tight_binding_is_analytic(seed):
+    """With no self-energy the path bands are the eigenvalues of H0(k') - mu with H0(k') summed directly over the
+    model's bond list (x, y, x + y, x - y and their reverses), at points off the mesh.  The random complex hoppings
+    break k -> -k, so a wrong sign of the interpolation phase fails."""
+    n = 6
+    w = wl.five_orbital(n=n, seed=seed, U=1.0, J=0.1, Vnn=0.2, beta=10.0, omega_max=20.0, eps=1e-8, scale_mesh=n)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
+    zero = {"sig_hf_k": np.zeros_like(m.H_k), "sig_iw": np.zeros((d.r,) + m.H_k.shape, dtype=np.complex128)}
+    rng = np.random.default_rng(1)
+    k = rng.uniform(0.0, 1.0, size=(17, 2))
+    mu = 0.37
+    out = qp.quasiparticle_path(m, d, zero, k, mu=mu)
+    bonds = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1)]
+    for p, f in enumerate(k):
+        h = np.zeros((5, 5), dtype=np.complex128)
+        for (r1, r2) in bonds:
+            h += w["H_R"][:, :, r1 % n, r2 % n] * np.exp(-2j * np.pi * (f[0] * r1 + f[1] * r2))
+        ev = np.linalg.eigvalsh(h - mu * np.eye(5))
+        assert np.abs(out["bands"][:, p] - ev).max() < 1e-12, p
+    assert np.abs(out["z"] - np.eye(5)[:, :, None]).max() < 1e-14
+
+
+def test_path_graphene_dispersion():
+    """Graphene with no self-energy: the bands at any k' are -mu -+ |t| |1 + e^{2 pi i f1} + e^{2 pi i f2}|."""
+    w = wl.graphene(n=12, U=3.0, ohno=False, beta=10.0, omega_max=100.0, eps=1e-8)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
+    zero = {"sig_hf_k": np.zeros_like(m.H_k), "sig_iw": np.zeros((d.r,) + m.H_k.shape, dtype=np.complex128)}
+    k = np.array([[0.0, 0.0], [1 / 3, 2 / 3], [0.5, 0.0], [0.123, 0.456], [0.7, 0.31]])
+    out = qp.quasiparticle_path(m, d, zero, k, mu=0.2)
+    gam = np.abs(1.0 + np.exp(2j * np.pi * k[:, 0]) + np.exp(2j * np.pi * k[:, 1]))
+    ref = np.stack([-0.2 - 2.7 * gam, -0.2 + 2.7 * gam])
+    assert np.abs(out["bands"] - ref).max() < 1e-12
