@@ -41,10 +41,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix), TFLOP/s
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 (vector = matrix), TFLOP/s
-SWITCH_TOL = 1e-4              # |Delta Sigma| at which the mixed solve leaves FP32
+SWITCH_FACTOR = 3.0            # the mixed solve leaves FP32 at |Delta Sigma| <= SWITCH_FACTOR x the solve tolerance
 
 WORKLOAD = "five_orbital_24"
 METRIC = "GW iterations/sec (5-orb, 24^2 k), chosen vs plain FP64, at |dSigma|<=1e-6"
+
+
+_TOL = [1e-6]
+
+
+def switch_tol():
+    """|Delta Sigma| at which the chosen schedule leaves its FP32 phase: a few times the solve tolerance, so the
+    FP32 iterations carry the solve close to it and FP64 iterations make the end point an FP64 fixed point."""
+    return SWITCH_FACTOR * _TOL[0]
 
 
 def log(*a):
@@ -141,7 +150,7 @@ def cpu_baseline(w, min_seconds=10.0, max_iter=8):
 
 def solve(st, mode, tol, max_iter=60):
     """One self-consistent solve from G0 under a precision schedule."""
-    st.set_precision(mode, SWITCH_TOL)
+    st.set_precision(mode, switch_tol())
     st.init_g0()
     hist = []
     for _ in range(max_iter):
@@ -155,7 +164,7 @@ def solve(st, mode, tol, max_iter=60):
 def timed_solves(torch, st, mode, tol, steps):
     """Exactly `steps` GW iterations of back-to-back solves from G0 (a converged
     solve restarts from G0), between two device synchronisations."""
-    st.set_precision(mode, SWITCH_TOL)
+    st.set_precision(mode, switch_tol())
     st.init_g0()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -236,7 +245,7 @@ def paper_workload_leg(torch, qgw, steps, tol, warmup=3, mixing=0.5):
            "t": 1.0, "U": 1.0, "J": 0.1, "V_nn": 0.2, "filling": w["n_target"], "mixing": mixing,
            "paper_dlr_vec_s_per_iteration": dict(PAPER_DLR_VEC_S, total=round(sum(PAPER_DLR_VEC_S.values()), 2))}
     for name, mode in (("fp64", 0), ("mixed", 1)):
-        st.set_precision(mode, SWITCH_TOL)
+        st.set_precision(mode, switch_tol())
         st.init_g0()
         st.iterate(warmup)
         st.init_g0()
@@ -549,6 +558,7 @@ def main():
                     help="first copy a MIB-MiB device buffer three times (a plain copy kernel of known size "
                          "that scales the HBM byte counters of a profiler run)")
     a = ap.parse_args()
+    _TOL[0] = a.tol
     if a.gpus != 1:
         print("bench.py measures one GPU: the GW iteration here runs on a single MI355X "
               "(multi-GPU sharding is a design note only); run with --gpus 1.", file=sys.stderr)
@@ -674,7 +684,7 @@ def main():
                    "beta": w["beta"], "omega_max": w["omega_max"], "dlr_eps": w["eps"], "dlr_rank": plan.r,
                    "U": w["interaction"]["U"], "J": w["interaction"]["J"], "V_nn": w["interaction"]["V_nn"],
                    "filling": w["n_target"], "tol": a.tol,
-                   "path": "chosen: FP32 a1-a11 while |dSigma| > %g and falling, then FP64" % SWITCH_TOL,
+                   "path": "chosen: FP32 a1-a11 while |dSigma| > %g and falling, then FP64" % switch_tol(),
                    "timed_work": "back-to-back self-consistent solves from G0 to |dSigma| <= tol"},
         "plain_fp64": {"value": round(value64, 3), "ms_per_step": round(1e3 * timed["fp64"]["elapsed"] / a.steps, 4)},
         "chosen_vs_fp64": round(value / value64, 4),

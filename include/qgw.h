@@ -547,7 +547,7 @@ qgw_status qgw_state_info(qgw_state state, int32_t *last_prec, int32_t *n_fp32, 
  *   2 a2   k -> R of both                             3 a3+a4 bubble, R -> q
  *   4 a5   P: tau -> i nu (to the matrix layout)      5 a6  Dyson W
  *   6 a7   W^C: i nu -> tau (to the slab layout)      7 a8-a10 self-energy
- *   8 a11  Sigma^C: tau -> i w                        9 a14 Delta Sigma, mixing
+ *   8 a11  Sigma^C: tau -> i w                        9 a14 Delta Sigma, mixing, H0 + Sigma_HF
  *  10 a13  Dyson G with the chemical-potential search */
 #define QGW_NUM_STEPS 11
 qgw_status qgw_state_profile(qgw_state state, int32_t mode, double *ms, int32_t *iters);

@@ -1255,7 +1255,7 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
                 {&st->Sig_iw_old, fo}, {&st->SigHF_k, so}, {&st->SigHF_old, so},  {&st->n_k, so},
                 {&st->n_R, so},       {&st->SigHF_R, so}, {&st->Hs_k, so},       {&st->G_tau, fo},
                 {&st->G_reflt, fo},   {&st->Sig_tau_k, fo}, {&st->Pq, fp},       {&st->P_nu, fp},
-                {&st->Wc_nu, fw},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096},
+                {&st->Wc_nu, fw},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096 * sizeof(double)},
                 {(void**)&st->d_scal, 32 * sizeof(double)},
                 {(void**)&st->d_part, size_t(8) * p.max_blocks * sizeof(double)},
                 {(void**)&st->d_stat, 16 * sizeof(int)},
@@ -1413,12 +1413,11 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     run(launch_convert(ncol_g * p.r, st->Siw32, st->Sig_iw, 0, s));
   }
   // a14: change of the total self-energy, mixing
+  // a14 and the static part of a13 (H0 + Sigma_HF) in one pass
   mark(9);
   run(launch_delta_and_mix(p, st->SigHF_k, st->Sig_iw, st->SigHF_old, st->Sig_iw_old, st->mixing, st->d_dsig,
-                           st->d_blockmax, s));
-  // a13 (static part): H0 + Sigma_HF
+                           st->d_blockmax, s, st->H_k, st->Hs_k));
   mark(10);
-  run(launch_add(p, ncol_g, st->H_k, st->SigHF_k, st->Hs_k, s));
   return e;
 }
 

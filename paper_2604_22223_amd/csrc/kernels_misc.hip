@@ -85,20 +85,47 @@ __global__ void k_add(const zd* __restrict__ a, const zd* __restrict__ b, zd* __
   if (gi < n) out[gi] = a[gi] + b[gi];
 }
 
-// per-block max of |(hf_new + c_new) - (hf_old + c_old)| over (m, ab, k); a non-finite entry counts as +inf
-// (fmax would drop a NaN), so a NaN anywhere in Sigma makes the norm infinite
-__global__ __launch_bounds__(256) void k_delta(const zd* __restrict__ hf_new, const zd* __restrict__ c_new,
-                                               const zd* __restrict__ hf_old, const zd* __restrict__ c_old,
-                                               int64_t n_static, int64_t n_total, double* __restrict__ block_max) {
+// a14 in one pass.  A block owns 64 static entries st; its four waves split the r node entries of the
+// self-energy at those st (wave g takes nodes g, g + 4, ..).  Per-block max of |(hf_new + c_new) - (hf_old + c_old)|
+// (a non-finite entry counts as +inf), new <- old + alpha (new - old) and old <- new for the node entries; after a
+// barrier (every wave has read the static Sigma_HF(st)) wave 0 mixes and copies Sigma_HF(st) and, with h0 given,
+// writes the static H = H0 + Sigma_HF of the Dyson equation for G into hs.
+__global__ __launch_bounds__(256) void k_delta_mix(zd* __restrict__ hf_new, zd* __restrict__ c_new,
+                                                   zd* __restrict__ hf_old, zd* __restrict__ c_old, int64_t ns,
+                                                   int r, double alpha, double* __restrict__ block_max,
+                                                   const zd* __restrict__ h0, zd* __restrict__ hs) {
   __shared__ double red[256];
+  const int g = threadIdx.x >> 6;
+  const int64_t st = int64_t(blockIdx.x) * 64 + (threadIdx.x & 63);
+  const bool ok = st < ns;
   double v = 0.0;
-  for (int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x; gi < n_total; gi += int64_t(gridDim.x) * 256) {
-    const int64_t st = gi % n_static;
-    const cpx<double> d = (hf_new[st] + c_new[gi]) - (hf_old[st] + c_old[gi]);
-    v = fmax(v, finite_or_inf(sqrt(norm2(d))));
+  cpx<double> h = mk(0.0, 0.0), ho = mk(0.0, 0.0);
+  if (ok) {
+    h = hf_new[st];
+    ho = hf_old[st];
+    for (int m = g; m < r; m += 4) {
+      const int64_t gi = int64_t(m) * ns + st;
+      cpx<double> c = c_new[gi];
+      const cpx<double> co = c_old[gi];
+      const cpx<double> d = (h + c) - (ho + co);
+      v = fmax(v, finite_or_inf(sqrt(norm2(d))));
+      if (alpha != 1.0) {
+        c = co + scale(c - co, alpha);
+        c_new[gi] = c;
+      }
+      c_old[gi] = c;
+    }
   }
   red[threadIdx.x] = v;
-  __syncthreads();
+  __syncthreads();  // every wave has read hf_new[st] and hf_old[st]
+  if (ok && g == 0) {
+    if (alpha != 1.0) {
+      h = ho + scale(h - ho, alpha);
+      hf_new[st] = h;
+    }
+    hf_old[st] = h;
+    if (h0) hs[st] = h0[st] + h;
+  }
   for (int off = 128; off >= 1; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
     __syncthreads();
@@ -117,19 +144,6 @@ __global__ __launch_bounds__(256) void k_max_reduce(const double* __restrict__ i
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];
-}
-
-// x_new <- x_old + alpha (x_new - x_old); x_old <- x_new
-__global__ void k_mix_copy(zd* __restrict__ x_new, zd* __restrict__ x_old, int64_t n, double alpha) {
-  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (gi >= n) return;
-  cpx<double> v = x_new[gi];
-  if (alpha != 1.0) {
-    const cpx<double> o = x_old[gi];
-    v = o + scale(v - o, alpha);
-    x_new[gi] = v;
-  }
-  x_old[gi] = v;
 }
 
 template <typename T>
@@ -372,15 +386,14 @@ hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b
 }
 
 hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* hf_old, void* c_old,
-                                double alpha, double* d_out, double* block_scratch, hipStream_t s) {
+                                double alpha, double* d_out, double* block_scratch, hipStream_t s, const void* h0,
+                                void* hs) {
   const int64_t ns = int64_t(p.no) * p.no * p.nk;
-  const int64_t nt = ns * p.r;
-  const int blocks = 256;
-  hipLaunchKernelGGL(k_delta, dim3(blocks), dim3(256), 0, s, (const zd*)hf_new, (const zd*)c_new,
-                     (const zd*)hf_old, (const zd*)c_old, ns, nt, block_scratch);
-  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, (const double*)block_scratch, blocks, d_out);
-  hipLaunchKernelGGL(k_mix_copy, dim3(nblk(ns, 256)), dim3(256), 0, s, (zd*)hf_new, (zd*)hf_old, ns, alpha);
-  hipLaunchKernelGGL(k_mix_copy, dim3(nblk(nt, 256)), dim3(256), 0, s, (zd*)c_new, (zd*)c_old, nt, alpha);
+  const int64_t blocks = nblk(ns, 64);
+  if (blocks > 4096) return hipErrorInvalidValue;  // the state's block scratch holds 4096 maxima
+  hipLaunchKernelGGL(k_delta_mix, dim3(unsigned(blocks)), dim3(256), 0, s, (zd*)hf_new, (zd*)c_new, (zd*)hf_old,
+                     (zd*)c_old, ns, p.r, alpha, block_scratch, (const zd*)h0, (zd*)hs);
+  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, (const double*)block_scratch, int(blocks), d_out);
   return hipGetLastError();
 }
 

@@ -171,11 +171,12 @@ hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_
 hipError_t launch_slab_to_matrix_static(const Plan& p, const void* in, void* out, hipStream_t s);
 hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b, void* out,
                       hipStream_t s);
-// d_sigma = max |(hf_new + c_new) - (hf_old + c_old)|; then optional mixing
-// new <- old + alpha (new - old), and old <- new.
+// d_sigma = max |(hf_new + c_new) - (hf_old + c_old)| (non-finite entries count as +inf); then optional mixing
+// new <- old + alpha (new - old), and old <- new; with h0 also hs = h0 + (mixed) hf_new.  block_scratch holds up to
+// 4096 block maxima of 64 static entries (n_o^2 N_k <= 262144).
 hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* hf_old,
                                 void* c_old, double alpha, double* d_out, double* block_scratch,
-                                hipStream_t s);
+                                hipStream_t s, const void* h0 = nullptr, void* hs = nullptr);
 // complex128 <-> complex64 copies (to_f32 = 1: double -> float)
 hipError_t launch_convert(int64_t count, const void* in, void* out, int to_f32, hipStream_t s);
 hipError_t launch_count_nonfinite(const Plan& p, const void* x, int64_t count, int* d_count,
