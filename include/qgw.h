@@ -456,6 +456,26 @@ qgw_status qgw_quasiparticle(qgw_plan plan, const void *H_k, const void *SigHF_k
                              double *bands, void *workspace, int64_t workspace_bytes,
                              void *stream);
 
+/* Quasiparticle bands along a path of arbitrary k points (the band plots of
+ * Fig. fig-band-dos (a)), FP64 plans.  H0, Sigma_HF and S = Sigma^C(i pi/beta)
+ * are brought from the mesh to each point k' by Fourier interpolation,
+ * X(k') = sum_R w(R) e^{-i k'.R} X(R) with X(R) the inverse lattice DFT of
+ * the mesh values, each axis's R taken in (-n/2, n/2] and, for even n, the
+ * n/2 term weighted cos(pi f n) (the half shell split between +-n/2, so the
+ * interpolant is real-symmetric and exact on mesh points); the relations of
+ * qgw_quasiparticle then hold per point.  kfrac: HOST array [n_path][dim] of
+ * fractional coordinates f (k' = 2 pi f along the reciprocal basis of the
+ * mesh); inputs as for qgw_quasiparticle; outputs Sig0, Z, Hqp:
+ * [n_o][n_o][n_path] complex, bands: [n_o][n_path] double (device).
+ * 1 <= n_path <= 65536.  Workspace: qgw_quasiparticle_path_workspace bytes.
+ * Waits for ``stream``.  QGW_ERR_NONFINITE if Z^{-1}(k') is not positive
+ * definite at some point or kfrac holds a non-finite value. */
+qgw_status qgw_quasiparticle_path_workspace(qgw_plan plan, int32_t n_path, int64_t *bytes);
+qgw_status qgw_quasiparticle_path(qgw_plan plan, const void *H_k, const void *SigHF_k,
+                                  const void *Sig_iw, double mu, const double *kfrac,
+                                  int32_t n_path, void *Sig0, void *Z, void *Hqp, double *bands,
+                                  void *workspace, int64_t workspace_bytes, void *stream);
+
 /* out = a + b over ``count`` complex FP64 entries (the static H0(k) +
  * Sigma_HF(k) of the Dyson equation for G); out may alias a or b. */
 qgw_status qgw_add(qgw_plan plan, int64_t count, const void *a, const void *b,

@@ -1117,6 +1117,54 @@ qgw_status qgw_quasiparticle(qgw_plan h, const void* H_k, const void* SigHF_k, c
   return QGW_OK;
 }
 
+static int64_t qp_path_bytes(const Plan& p, int64_t npt) {
+  const int64_t nab = int64_t(p.no) * p.no;
+  return 256 + 16 * nab * (4 * int64_t(p.nk) + 3 * npt) + 8 * int64_t(p.dim) * npt;
+}
+
+qgw_status qgw_quasiparticle_path_workspace(qgw_plan h, int32_t n_path, int64_t* bytes) {
+  QGW_REQUIRE(h && bytes, QGW_ERR_INVALID_ARG, "qgw_quasiparticle_path_workspace: null argument");
+  QGW_REQUIRE(n_path >= 1 && n_path <= 65536, QGW_ERR_INVALID_ARG,
+              "qgw_quasiparticle_path_workspace: n_path must be in [1, 65536]");
+  *bytes = qp_path_bytes(h->p, n_path);
+  return QGW_OK;
+}
+
+qgw_status qgw_quasiparticle_path(qgw_plan h, const void* H_k, const void* SigHF_k, const void* Sig_iw, double mu,
+                                  const double* kfrac, int32_t n_path, void* Sig0, void* Z, void* Hqp, double* bands,
+                                  void* workspace, int64_t workspace_bytes, void* stream) {
+  QGW_PLAN(h, "qgw_quasiparticle_path");
+  QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_quasiparticle_path: FP64 plans only");
+  QGW_REQUIRE(H_k && SigHF_k && Sig_iw && kfrac && Sig0 && Z && Hqp && bands && workspace, QGW_ERR_INVALID_ARG,
+              "qgw_quasiparticle_path: null argument");
+  QGW_REQUIRE(std::isfinite(mu), QGW_ERR_INVALID_ARG, "qgw_quasiparticle_path: mu must be finite");
+  QGW_REQUIRE(n_path >= 1 && n_path <= 65536, QGW_ERR_INVALID_ARG,
+              "qgw_quasiparticle_path: n_path must be in [1, 65536]");
+  QGW_REQUIRE(workspace_bytes >= qp_path_bytes(p, n_path), QGW_ERR_INVALID_ARG,
+              "qgw_quasiparticle_path: workspace needs " + std::to_string(qp_path_bytes(p, n_path)) + " bytes");
+  const int64_t nf = int64_t(n_path) * p.dim;
+  for (int64_t i = 0; i < nf; ++i)
+    QGW_REQUIRE(std::isfinite(kfrac[i]), QGW_ERR_NONFINITE, "qgw_quasiparticle_path: non-finite kfrac");
+  // [flag | pad to 256][S_k, X_R (3), X_path (3)][kfrac]
+  int* flag = (int*)workspace;
+  char* base = (char*)workspace + 256;
+  const int64_t nab = int64_t(p.no) * p.no;
+  double* d_kf = (double*)(base + 16 * nab * (4 * int64_t(p.nk) + 3 * int64_t(n_path)));
+  hipStream_t s = (hipStream_t)stream;
+  QGW_CHECK_HIP(hipMemsetAsync(flag, 0, sizeof(int), s), "qgw_quasiparticle_path");
+  QGW_CHECK_HIP(hipMemcpyAsync(d_kf, kfrac, size_t(nf) * sizeof(double), hipMemcpyHostToDevice, s),
+                "qgw_quasiparticle_path");
+  QGW_CHECK_HIP(launch_quasiparticle_path(p, H_k, SigHF_k, Sig_iw, d_kf, n_path, mu, base, Sig0, Z, Hqp, bands,
+                                          flag, s),
+                "qgw_quasiparticle_path");
+  int bad = 0;
+  QGW_CHECK_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s), "qgw_quasiparticle_path");
+  QGW_CHECK_HIP(hipStreamSynchronize(s), "qgw_quasiparticle_path");
+  QGW_REQUIRE(bad == 0, QGW_ERR_NONFINITE,
+              "qgw_quasiparticle_path: Z(k')^{-1} is not positive definite at some path point");
+  return QGW_OK;
+}
+
 qgw_status qgw_add(qgw_plan h, int64_t count, const void* a, const void* b, void* out, void* stream) {
   QGW_PLAN(h, "qgw_add");
   QGW_REQUIRE(p.prec == 0, QGW_ERR_UNSUPPORTED, "qgw_add: FP64 plans only");

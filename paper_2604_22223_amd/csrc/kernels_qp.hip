@@ -12,6 +12,13 @@
 //
 // One thread per k: the n_o x n_o Hermitian matrices stay in registers and
 // are diagonalised by the Jacobi routine of qgw_herm.h.
+//
+// Off the mesh (bands along a path, Fig. fig-band-dos (a)), H0, Sigma_HF and
+// S come from the mesh by Fourier interpolation: X(k') = sum_R w(R)
+// e^{-2 pi i f.R} X(R), X(R) the inverse DFT of the mesh values, each axis's R
+// taken in (-n/2, n/2] and, for even n, the n/2 term split equally between
+// +n/2 and -n/2 (weight cos(pi f n)); on mesh points that is the mesh value.
+// The same per-point kernel then runs on the path points.
 #include "qgw_herm.h"
 
 namespace qgw {
@@ -34,7 +41,7 @@ __global__ __launch_bounds__(64) void k_quasiparticle(const zd* __restrict__ hk,
 #pragma unroll
     for (int j = 0; j < NO; ++j) s[i][j] = mk(0.0, 0.0);
   for (int m = 0; m < r; ++m) {
-    const cpx<double> w = row[m];
+    const cpx<double> w = row ? row[m] : mk(1.0, 0.0);  // no row: sig already holds S (r = 1)
     const zd* sm = sig + int64_t(m) * NO * NO * nk;
 #pragma unroll
     for (int i = 0; i < NO; ++i)
@@ -127,6 +134,52 @@ __global__ __launch_bounds__(64) void k_quasiparticle(const zd* __restrict__ hk,
   for (int n = 0; n < NO; ++n) bands[int64_t(n) * nk + k] = ev[n];
 }
 
+// out[c] = sum_m row[m] in[m][c]: the DLR interpolant at i pi / beta of node values
+__global__ __launch_bounds__(256) void k_row_apply(const zd* __restrict__ in, const zd* __restrict__ row, int r,
+                                                   int64_t ncols, zd* __restrict__ out) {
+  const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= ncols) return;
+  cpx<double> s = mk(0.0, 0.0);
+  for (int m = 0; m < r; ++m) s = fma(s, row[m], in[int64_t(m) * ncols + c]);
+  out[c] = s;
+}
+
+// per-axis factor w(R) e^{-2 pi i f R} of the interpolation (R a mesh index 0 .. n-1)
+__device__ __forceinline__ cpx<double> interp_phase(double f, int R, int n) {
+  if (2 * R == n) return mk(cospi(f * double(n)), 0.0);
+  const int rep = 2 * R < n ? R : R - n;
+  double sn, cs;
+  sincospi(-2.0 * f * double(rep), &sn, &cs);
+  return mk(cs, sn);
+}
+
+// x_R: `narr` arrays of `nab` slabs [nab][N_k] in R, one after the other; out: [narr][nab][npt]
+__global__ __launch_bounds__(256) void k_interp(const zd* __restrict__ x_r, int narr, int nab, int n, int dim,
+                                                const double* __restrict__ kfrac, int npt, zd* __restrict__ out) {
+  const int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t total = int64_t(narr) * nab * npt;
+  if (gi >= total) return;
+  const int pt = int(gi % npt);
+  const int64_t slab = gi / npt;  // array * nab + ab
+  const int64_t nk = dim == 3 ? int64_t(n) * n * n : int64_t(n) * n;
+  const zd* x = x_r + slab * nk;
+  const double f1 = kfrac[pt * dim], f2 = kfrac[pt * dim + 1], f3 = dim == 3 ? kfrac[pt * dim + 2] : 0.0;
+  cpx<double> acc = mk(0.0, 0.0);
+  for (int r1 = 0; r1 < n; ++r1) {
+    const cpx<double> p1 = interp_phase(f1, r1, n);
+    for (int r2 = 0; r2 < n; ++r2) {
+      const cpx<double> p12 = p1 * interp_phase(f2, r2, n);
+      if (dim == 3) {
+        for (int r3 = 0; r3 < n; ++r3)
+          acc = fma(acc, p12 * interp_phase(f3, r3, n), x[(int64_t(r1) * n + r2) * n + r3]);
+      } else {
+        acc = fma(acc, p12, x[int64_t(r1) * n + r2]);
+      }
+    }
+  }
+  out[slab * npt + pt] = acc;
+}
+
 template <int NO>
 hipError_t quasiparticle_no(const Plan& p, const void* h_k, const void* shf_k, const void* sig_iw, double mu,
                             void* sig0, void* z, void* hqp, double* bands, int* status, hipStream_t s) {
@@ -137,7 +190,50 @@ hipError_t quasiparticle_no(const Plan& p, const void* h_k, const void* shf_k, c
   return hipGetLastError();
 }
 
+template <int NO>
+hipError_t quasiparticle_points_no(const Plan& p, int npt, const void* h, const void* shf, const void* sp, double mu,
+                                   void* sig0, void* z, void* hqp, double* bands, int* status, hipStream_t s) {
+  const double w0 = 3.14159265358979323846 / p.beta;
+  hipLaunchKernelGGL((k_quasiparticle<NO>), dim3(unsigned((npt + 63) / 64)), dim3(64), 0, s, (const zd*)h,
+                     (const zd*)shf, (const zd*)sp, (const zd*)nullptr, 1, npt, w0, mu, (zd*)sig0, (zd*)z, (zd*)hqp,
+                     bands, status);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_quasiparticle_path(const Plan& p, const void* h_k, const void* shf_k, const void* sig_iw,
+                                     const double* kfrac, int npt, double mu, void* ws, void* sig0, void* z,
+                                     void* hqp, double* bands, int* status, hipStream_t s) {
+  const int64_t nab = int64_t(p.no) * p.no, so = nab * p.nk;
+  zd* s_k = (zd*)ws;       // S(k) on the mesh
+  zd* x_r = s_k + so;      // H0, Sigma_HF, S in R
+  zd* x_p = x_r + 3 * so;  // the same at the path points
+  hipLaunchKernelGGL(k_row_apply, dim3(unsigned((so + 255) / 256)), dim3(256), 0, s, (const zd*)sig_iw,
+                     (const zd*)p.d_qp_row, p.r, so, s_k);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_lattice_fft(p, +1, nab, h_k, x_r, s);  // k -> R with 1/N_k
+  if (e == hipSuccess) e = launch_lattice_fft(p, +1, nab, shf_k, x_r + so, s);
+  if (e == hipSuccess) e = launch_lattice_fft(p, +1, nab, s_k, x_r + 2 * so, s);
+  if (e != hipSuccess) return e;
+  const int64_t total = 3 * nab * npt;
+  hipLaunchKernelGGL(k_interp, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, (const zd*)x_r, 3, int(nab),
+                     p.n, p.dim, kfrac, npt, x_p);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const zd* hp = x_p;
+  const zd* shp = x_p + nab * npt;
+  const zd* sp = x_p + 2 * nab * npt;
+  switch (p.no) {
+#define QGW_CASE(NOV) \
+  case NOV:           \
+    return quasiparticle_points_no<NOV>(p, npt, hp, shp, sp, mu, sig0, z, hqp, bands, status, s);
+    QGW_FOR_EACH_NO(QGW_CASE)
+#undef QGW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_quasiparticle(const Plan& p, const void* h_k, const void* shf_k, const void* sig_iw, double mu,
                                 void* sig0, void* z, void* hqp, double* bands, int* status, hipStream_t s) {

@@ -111,6 +111,11 @@ hipError_t launch_hf_delta_mix(const Plan& p, void* x_new, void* x_old, double a
 // quasiparticle outputs per k (FP64); status[0] is set to 1 where Z^{-1} is not positive definite
 hipError_t launch_quasiparticle(const Plan& p, const void* h_k, const void* shf_k, const void* sig_iw, double mu,
                                 void* sig0, void* z, void* hqp, double* bands, int* status, hipStream_t s);
+// the same at npt path points (device kfrac [npt][dim]) by Fourier interpolation from the mesh; workspace:
+// (4 N_k + 3 npt) n_o^2 complex
+hipError_t launch_quasiparticle_path(const Plan& p, const void* h_k, const void* shf_k, const void* sig_iw,
+                                     const double* kfrac, int npt, double mu, void* ws, void* sig0, void* z,
+                                     void* hqp, double* bands, int* status, hipStream_t s);
 
 // ---- kernels (each returns hipSuccess or the launch error) ----------------
 hipError_t launch_lattice_fft(const Plan& p, int dir, int64_t batch, const void* in, void* out,

@@ -36,7 +36,8 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
            "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_quasiparticle", "qgw_hf_density", "qgw_state_hf_solve", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
-           "qgw_plan_create_mf", "qgw_mf_nodes_for", "qgw_workspace_size", "qgw_sync_status", "qgw_dyson_G_noalloc", "qgw_last_error"]
+           "qgw_plan_create_mf", "qgw_mf_nodes_for", "qgw_workspace_size", "qgw_sync_status", "qgw_dyson_G_noalloc", "qgw_quasiparticle_path_workspace",
+           "qgw_quasiparticle_path", "qgw_last_error"]
 
 
 class QGWError(RuntimeError):
@@ -111,6 +112,8 @@ def lib():
             "qgw_energy_bwd": [vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp, i64, vp],
             "qgw_quasiparticle": [vp, vp, vp, vp, dbl, vp, vp, vp, pd, vp, i64, vp],
             "qgw_hf_density": [vp, vp, dbl, pd, vp, vp, i64, vp],
+            "qgw_quasiparticle_path_workspace": [vp, i32, pi64],
+            "qgw_quasiparticle_path": [vp, vp, vp, vp, dbl, pd, i32, vp, vp, vp, pd, vp, i64, vp],
             "qgw_workspace_size": [vp, i32, pi64],
             "qgw_sync_status": [vp, vp],
             "qgw_state_hf_solve": [vp, dbl, i32, pi32, pd, pd, vp],
@@ -382,6 +385,30 @@ class Plan:
         _check(lib().qgw_quasiparticle(self.handle, _ptr(h_k), _ptr(shf_k), _ptr(sig_iw), float(mu), _ptr(sig0),
                                        _ptr(z), _ptr(hqp), ctypes.cast(_ptr(bands), ctypes.POINTER(ctypes.c_double)),
                                        _ptr(ws), _nbytes(ws), _stream()))
+        return sig0, z, hqp, bands
+
+    def quasiparticle_path(self, h_k, shf_k, sig_iw, kfrac, mu=0.0):
+        """The quasiparticle outputs at path points ``kfrac`` ([n_path, dim] fractional coordinates, host data) by
+        Fourier interpolation from the mesh (qgw_quasiparticle_path).
+
+        Returns (sig0, z, hqp, bands): three [n_o, n_o, n_path] complex tensors and [n_o, n_path] real bands."""
+        import numpy as np
+        import torch
+        kf = np.ascontiguousarray(np.asarray(kfrac, dtype=np.float64).reshape(-1, self.dim))
+        npt = kf.shape[0]
+        no = self.n_o
+        dev = h_k.device
+        sig0 = torch.empty((no, no, npt), dtype=torch.complex128, device=dev)
+        z = torch.empty_like(sig0)
+        hqp = torch.empty_like(sig0)
+        bands = torch.empty((no, npt), dtype=torch.float64, device=dev)
+        b = ctypes.c_int64(0)
+        _check(lib().qgw_quasiparticle_path_workspace(self.handle, int(npt), ctypes.byref(b)))
+        ws = torch.empty(b.value, dtype=torch.uint8, device=dev)
+        _check(lib().qgw_quasiparticle_path(
+            self.handle, _ptr(h_k), _ptr(shf_k), _ptr(sig_iw), float(mu),
+            kf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(npt), _ptr(sig0), _ptr(z), _ptr(hqp),
+            ctypes.cast(_ptr(bands), ctypes.POINTER(ctypes.c_double)), _ptr(ws), _nbytes(ws), _stream()))
         return sig0, z, hqp, bands
 
     def hf_density(self, h_k, n_target=None, mu=0.0, out=None):

@@ -1,4 +1,4 @@
-"""qgw_quasiparticle against the oracle (Z class, SigStc class, Eq. eq-z-factor,
+"""qgw_quasiparticle and qgw_quasiparticle_path against the oracle (Z class, SigStc class, Eq. eq-z-factor,
 Eq. eq-quasi-particle-Hamiltonian).
 
 Inputs are the oracle's state after one GW iteration on three models (multi-site
@@ -104,3 +104,45 @@ def test_rejects_non_positive_z(case):
     with pytest.raises(qgw.QGWError) as e:
         case.plan.quasiparticle(dev(m.H_k), dev(st["sig_hf_k"]), dev(bad))
     assert e.value.status == 6
+
+
+def _path_points(dim, n, seed=7):
+    """Mesh points (where the interpolant is the mesh value), a line through Gamma and the zone edge (f = 1/2,
+    the split n/2 shell), and random off-mesh points."""
+    rng = np.random.default_rng(seed)
+    mesh = np.array([[1, 2] + [0] * (dim - 2), [n - 1, 0] + [1] * (dim - 2)], dtype=np.float64) / n
+    line = np.linspace(0.0, 0.5, 9)[:, None] * np.ones((1, dim))
+    return np.concatenate([mesh, line, rng.uniform(-0.5, 1.0, size=(21, dim))])
+
+
+@pytest.mark.parametrize("mu_mode", ["printed", "fermi_level"])
+def test_quasiparticle_path_matches_oracle(case, mu_mode):
+    """Bands along a path (Fig. fig-band-dos (a)): the Fourier-interpolated outputs at mesh, zone-edge and random
+    off-mesh points against the oracle, entry by entry at the FP64 bar."""
+    st, m, d = case.st, case.m, case.d
+    mu = 0.0 if mu_mode == "printed" else st["mu"]
+    kf = _path_points(case.dim, m.mesh[0])
+    ref = qp.quasiparticle_path(m, d, st, kf, mu=mu)
+    sig0, z, hqp, bands = case.plan.quasiparticle_path(dev(m.H_k), dev(st["sig_hf_k"]), dev(st["sig_iw"]), kf, mu=mu)
+    assert rel_err(host(sig0), ref["sig0"]) < TOL
+    assert rel_err(host(z), ref["z"]) < TOL
+    assert rel_err(host(hqp), ref["hqp"]) < TOL
+    assert rel_err(host(bands), ref["bands"]) < TOL
+    # on the mesh points the path call returns the mesh call's values
+    mref = qp.quasiparticle(m, d, st, mu=mu)
+    for p, f in enumerate(kf[:2]):
+        idx = tuple(int(round(x * m.mesh[0])) % m.mesh[0] for x in f)
+        assert np.abs(host(bands)[:, p] - mref["bands"][(slice(None),) + idx]).max() < 1e-10
+
+
+def test_quasiparticle_path_rejects_bad_points(case):
+    st, m = case.st, case.m
+    args = (dev(m.H_k), dev(st["sig_hf_k"]), dev(st["sig_iw"]))
+    kf = np.full((3, case.dim), 0.25)
+    kf[1, 0] = np.nan
+    with pytest.raises(qgw.QGWError) as e:
+        case.plan.quasiparticle_path(*args, kf)
+    assert e.value.status == 6
+    with pytest.raises(qgw.QGWError) as e:
+        case.plan.quasiparticle_path(*args, np.zeros((0, case.dim)))
+    assert e.value.status == 1
