@@ -213,13 +213,25 @@ qgw_status qgw_plan_get_map(qgw_plan plan, int32_t map, double *out);
  * slabs per block of the lattice transform and of the bubble, term lanes of
  * the self-energy, resident blocks per CU of the matrix-core DLR maps, and
  * the kernel of the orbital-array maps (matrix cores, or the VALU kernel with
- * 8, 16 or 32 rows per chunk).  choices[6] (may be NULL) receives them in
- * that order (orbital maps as two entries: 1 = VALU, and its chunk).  The
- * candidates compute the same values; the self-energy lane count and the
- * orbital-map kernel change only the order of floating-point sums.  An FP64
- * plan is tuned a second time for its FP32 kernels, which a state's
- * single-precision iterations use (choices reports the FP64 shapes). */
+ * 8, 16 or 32 rows per chunk), and for N_b = 25 where the Dyson-W product
+ * V P runs (1 = matrix cores, 0 = VALU).  choices[7] (may be NULL) receives
+ * them in that order (orbital maps as two entries: 1 = VALU, and its chunk).
+ * The candidates compute the same values; the self-energy lane count, the
+ * orbital-map kernel and the Dyson-W product change only the order of
+ * floating-point sums.  An FP64 plan is tuned a second time for its FP32
+ * kernels, which a state's single-precision iterations use (choices reports
+ * the FP64 shapes). */
 qgw_status qgw_plan_autotune(qgw_plan plan, int32_t *choices, void *stream);
+
+/* Sets the launch shapes directly, in qgw_plan_autotune's order (choices[7];
+ * 0, or -1 for the two kernel selectors, leaves a knob at its default): to
+ * restore shapes tuned earlier or to pin one kernel variant.  precision
+ * QGW_F64 sets the plan's own shapes, QGW_F32 (FP64 plans only) those of its
+ * FP32 kernels.  Applies to calls enqueued after it; batches keep the shapes
+ * they were captured with.  QGW_ERR_INVALID_ARG for a choice outside its
+ * range (slabs and lanes 0 .. 256 / (mesh lines per slab), blocks per CU
+ * 0 .. 8, orbital-map chunk 0, 8, 16 or 32). */
+qgw_status qgw_plan_set_tuning(qgw_plan plan, int32_t precision, const int32_t *choices);
 
 /* Sizes of the plan: any output pointer may be NULL. */
 qgw_status qgw_plan_sizes(qgw_plan plan, int32_t *rank, int32_t *n_o,

@@ -24,6 +24,10 @@ SOURCES = ["api.cpp", "dlr_host.cpp", "kernels_fft.hip", "kernels_dlr.hip", "ker
 
 ARCH = os.environ.get("QGW_OFFLOAD_ARCH", "gfx950")
 
+# Per-file device options.  The Dyson-W kernel keeps its matrix-core accumulators in ordinary VGPRs: in the
+# split form they would take AGPRs on top of the elimination's VGPRs and cost a wave per SIMD.
+SOURCE_FLAGS = {"kernels_dyson.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 
 def hipcc():
     for c in [os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"]:
@@ -40,7 +44,8 @@ def common_flags():
 
 def compile_one(src, verbose=False, extra=()):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + common_flags() + list(extra)
+    cmd = ([hipcc(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + common_flags()
+           + SOURCE_FLAGS.get(src, []) + list(extra))
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -7,6 +7,7 @@
 //   self-energy:        term lanes per block
 //   pair DLR maps:      resident blocks per CU of the matrix-core kernel
 //   orbital DLR maps:   matrix cores, or the VALU kernel with 8 / 16 / 32 rows per chunk
+//   Dyson W (N_b = 25): V P on the matrix cores or on the VALU
 // Every candidate computes the same thing; only the self-energy lane count
 // and the orbital-map kernel change the order of floating-point sums.  An
 // FP64 plan is also tuned for its FP32 kernels (the single-precision
@@ -94,8 +95,11 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
   const size_t c = 16;  // sized for FP64, large enough for the FP32 trials too
   const size_t sg = size_t(p.r) * p.no * p.no * p.nk * c;
   const size_t sp = size_t(p.r) * p.nb * p.nb * p.nk * c;
-  void *gt = nullptr, *gr = nullptr, *og = nullptr, *pa = nullptr, *pb = nullptr;
+  const size_t sv = size_t(p.nb) * p.nb * p.nk * c;
+  void *gt = nullptr, *gr = nullptr, *og = nullptr, *pa = nullptr, *pb = nullptr, *vv = nullptr;
   hipError_t e = hipMalloc(&gt, sg);
+  if (e == hipSuccess && p.nb == 25) e = hipMalloc(&vv, sv);
+  if (e == hipSuccess && p.nb == 25) e = hipMemsetAsync(vv, 0x3f, sv, s);
   if (e == hipSuccess) e = hipMalloc(&gr, sg);
   if (e == hipSuccess) e = hipMalloc(&og, sg);
   if (e == hipSuccess) e = hipMalloc(&pa, sp);
@@ -108,7 +112,7 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
   if (e == hipSuccess) e = t.init();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
-    for (void* q : {gt, gr, og, pa, pb})
+    for (void* q : {gt, gr, og, pa, pb, vv})
       if (q) (void)hipFree(q);
     set_error(std::string("qgw_plan_autotune: ") + hipGetErrorString(e));
     return QGW_ERR_DEVICE;
@@ -144,6 +148,7 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
     });
     tn.orb_valu = code == 0 ? 0 : 1;
     tn.orb_mt = code;
+    if (q.nb == 25) pick(t, s, {0, 1}, tn.w25_mfma, [&] { return launch_dyson_w(q, vv, pa, pb, s, 0); });
   };
   tune_one(p);
   if (p.prec == QGW_F64) {
@@ -155,8 +160,10 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
     p.has_tune32 = true;
   }
   const Tune& tn = p.tune;
+  // the trial data are arbitrary: a condition the Dyson-W trials raised is not the caller's
+  if (p.nb == 25) (void)hipMemsetAsync(p.d_status + kCondWord, 0, sizeof(int), s);
   e = hipStreamSynchronize(s);
-  for (void* q : {gt, gr, og, pa, pb}) (void)hipFree(q);
+  for (void* q : {gt, gr, og, pa, pb, vv}) (void)hipFree(q);
   if (e != hipSuccess) {
     set_error(std::string("qgw_plan_autotune: ") + hipGetErrorString(e));
     return QGW_ERR_DEVICE;
@@ -168,6 +175,48 @@ qgw_status qgw_plan_autotune(qgw_plan h, int32_t* choices, void* stream) {
     choices[3] = tn.mfma_bpc;
     choices[4] = tn.orb_valu;
     choices[5] = tn.orb_mt;
+    choices[6] = tn.w25_mfma;
+  }
+  return QGW_OK;
+}
+
+qgw_status qgw_plan_set_tuning(qgw_plan h, int32_t precision, const int32_t* choices) {
+  if (!h || !choices) {
+    set_error("qgw_plan_set_tuning: null argument");
+    return QGW_ERR_INVALID_ARG;
+  }
+  Plan& p = h->p;
+  if (precision != QGW_F64 && precision != QGW_F32) {
+    set_error("qgw_plan_set_tuning: precision must be QGW_F64 or QGW_F32");
+    return QGW_ERR_INVALID_ARG;
+  }
+  if (precision == QGW_F32 && p.prec != QGW_F64) {
+    set_error("qgw_plan_set_tuning: the FP32 shapes belong to an FP64 plan (an FP32 plan takes QGW_F64's slot)");
+    return QGW_ERR_INVALID_ARG;
+  }
+  const int lane_cap = std::max(1, 256 / lines_per_slab(p));
+  const bool ok = choices[0] >= 0 && choices[0] <= lane_cap && choices[1] >= 0 && choices[1] <= lane_cap &&
+                  choices[2] >= 0 && choices[2] <= lane_cap && choices[3] >= 0 && choices[3] <= 8 &&
+                  choices[4] >= -1 && choices[4] <= 1 &&
+                  (choices[5] == 0 || choices[5] == 8 || choices[5] == 16 || choices[5] == 32) &&
+                  choices[6] >= -1 && choices[6] <= 1;
+  if (!ok) {
+    set_error("qgw_plan_set_tuning: a choice is outside its range");
+    return QGW_ERR_INVALID_ARG;
+  }
+  Tune tn;
+  tn.fft_spb = choices[0];
+  tn.bubble_spb = choices[1];
+  tn.sigma_spb = choices[2];
+  tn.mfma_bpc = choices[3];
+  tn.orb_valu = choices[4];
+  tn.orb_mt = choices[5];
+  tn.w25_mfma = choices[6];
+  if (precision == QGW_F32 && p.prec == QGW_F64) {
+    p.tune32 = tn;
+    p.has_tune32 = true;
+  } else {
+    p.tune = tn;
   }
   return QGW_OK;
 }

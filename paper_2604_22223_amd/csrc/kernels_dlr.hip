@@ -12,6 +12,7 @@
 // output (HERM = 2): the exact density matrix and the exact Sigma^C(k, tau)
 // are Hermitian, and only their Hermitian parts are kept.
 #include "qgw_internal.h"
+#include "qgw_mfma.h"
 
 namespace qgw {
 
@@ -215,26 +216,6 @@ hipError_t dlr_launch(const Plan& p, int map, int64_t ncols, int na, int nq, dou
 // waves of a block take 8 adjacent values of the other index, so together
 // they read whole lines of the input.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // row of D held in element v by lane l (column l % 16)
-  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
-};
-template <>
-struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
-};
-
 // identity on a register value through a DPP move (quad_perm [0,1,2,3]); the
 // compiler cannot see through it, which keeps a software-pipelined load from
 // being folded back into its use
@@ -416,7 +397,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   // the input's rows (index L) are in_ld apart, its node planes nL in_ld (in_ld >= nW: padded rows)
   const int64_t in_plane = int64_t(nL) * in_ld;
   int buf = 0;  // slice parity, continued across tiles
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // XCD-aware order: with the grid a multiple of 8, block b runs on XCD b mod 8, and each XCD takes one
+  // contiguous eighth of the tiles.  Neighbouring W tiles (which share the input's 128-byte lines when a tile's
+  // 8 W values span half a line, as in FP32) and neighbouring L tiles then meet in one L2.
+  const bool by_xcd = (gridDim.x & 7) == 0;
+  const int64_t nx = by_xcd ? 8 : 1, xi = by_xcd ? (blockIdx.x & 7) : 0;
+  const int64_t bpx = gridDim.x / nx, bi = by_xcd ? (blockIdx.x >> 3) : blockIdx.x;
+  const int64_t t_hi = ntiles * (xi + 1) / nx;
+  for (int64_t tile = ntiles * xi / nx + bi; tile < t_hi; tile += bpx) {
     const int tL = int(tile % tiles_l), tW = int(tile / tiles_l);
     // input column of this thread's loads (clamped into the array: values
     // outside it feed only columns that are not stored)

@@ -27,6 +27,7 @@
 #include <utility>
 
 #include "qgw_internal.h"
+#include "qgw_mfma.h"
 
 namespace qgw {
 
@@ -312,7 +313,15 @@ __device__ __forceinline__ void gj25_all(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs)
 
 // ADJ: solve (I - V P)^H X = B instead (A is formed as below, passed through the V area of LDS, which ADJ no
 // longer needs, and read back conjugate-transposed), with B (pair matrix layout, dense) in place of V; writes X
-template <typename T, bool ADJ = false>
+// MVP: V P on the matrix cores (16x16x4, 2 x 2 tiles over the 25 x 25 product, 7 slices of 4 along the
+// contraction; rows, columns and slices past 25 are zero), V from LDS as the A operand and P straight from memory
+// as the B operand; I - V P then passes through the V area of LDS into the elimination layout, and the final
+// W - V reads V(q) from memory again.  The matrix cores run beside the VALU elimination of the other waves of
+// the SIMD and the product no longer streams V and P through LDS, but on gfx950 the FP64 matrix rate equals the
+// VALU rate and the 32 x 32 x 28 padding costs 1.8x the product's flops: measured at 24 x 24, r = 53 it takes
+// 0.46 ms (FP64) and 0.27 ms (FP32) against 0.42 and 0.25 for the VALU product, so it is an autotuner
+// alternative and not the default.
+template <typename T, bool ADJ = false, bool MVP = false>
 __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
                                                   cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld,
                                                   int* __restrict__ cond, const cpx<T>* __restrict__ rhs = nullptr) {
@@ -329,6 +338,90 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
   // chunk c of P (rows CH c ..) is read into registers one chunk ahead; a
   // chunk has at most 175 entries, three per lane
   static_assert(CH * NB <= 3 * 64, "a chunk of P must fit three entries per lane");
+  cpx<T> x[NS][NT], y;
+  if constexpr (MVP) {
+    using M = Mfma<T>;
+    using v4 = typename M::v4;
+    const int l16 = lane & 15, l4 = lane >> 4;
+    for (int e = lane; e < NN; e += 64) sv[e] = vm[e];
+    // B operand of slice ks, column tile ct: P[4 ks + l4][16 ct + l16]
+    auto ldp = [&](int ks, int ct) -> cpx<T> {
+      const int k = 4 * ks + l4, n = 16 * ct + l16;
+      return (k < NB && n < NB) ? pm[k * NB + n] : mk(T(0), T(0));
+    };
+    v4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = v4{T(0), T(0), T(0), T(0)};
+        ci[a][b] = v4{T(0), T(0), T(0), T(0)};
+      }
+    cpx<T> b0 = ldp(0, 0), b1 = ldp(0, 1);
+    __syncthreads();  // V(q) is in LDS
+#pragma unroll 1
+    for (int ks = 0; ks < 7; ++ks) {
+      const cpx<T> pb[2] = {b0, b1};
+      if (ks + 1 < 7) {
+        b0 = ldp(ks + 1, 0);
+        b1 = ldp(ks + 1, 1);
+      }
+      const int k = 4 * ks + l4;
+      cpx<T> a[2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const int m = 16 * rt + l16;
+        a[rt] = (k < NB && m < NB) ? sv[m * NB + k] : mk(T(0), T(0));
+      }
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          cr[rt][ct] = M::mac(a[rt].re, pb[ct].re, cr[rt][ct]);
+          ci[rt][ct] = M::mac(a[rt].re, pb[ct].im, ci[rt][ct]);
+        }
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          cr[rt][ct] = M::mac(-a[rt].im, pb[ct].im, cr[rt][ct]);
+          ci[rt][ct] = M::mac(a[rt].im, pb[ct].re, ci[rt][ct]);
+        }
+    }
+    __syncthreads();  // every lane has finished reading V: its area takes A = I - V P
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * rt + M::row(lane, v), col = 16 * ct + l16;
+          if (row < NB && col < NB)
+            sv[row * NB + col] = mk(T(row == col ? 1 : 0) - cr[rt][ct][v], -ci[rt][ct][v]);
+        }
+    __syncthreads();
+    // A (ADJ: A^H) from LDS and the right-hand side (V, or Wbar for ADJ) from memory into the elimination layout
+    const cpx<T>* bm = ADJ ? rhs + mat * NN : vm;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int row = rg + 8 * s;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int c = cg + 8 * t;
+        cpx<T> val = mk(T(0), T(0));
+        if (t < 4 && c < NB)
+          val = ADJ ? conj(sv[c * NB + row]) : sv[row * NB + c];
+        else if (c >= NB && c < 2 * NB)
+          val = bm[row * NB + c - NB];
+        x[s][t] = val;
+      }
+    }
+    y = mk(T(0), T(0));
+    if (c24 < NB)
+      y = ADJ ? conj(sv[c24 * NB + 24]) : sv[24 * NB + c24];
+    else if (c24 < 2 * NB)
+      y = bm[24 * NB + c24 - NB];
+  } else {
   cpx<T> pre0 = mk(T(0), T(0)), pre1 = pre0, pre2 = pre0;
   auto load_chunk = [&](int c) {
     const int n = min(CH, NB - CH * c) * NB;
@@ -339,7 +432,6 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
   };
   load_chunk(0);
   for (int e = lane; e < NN; e += 64) sv[e] = vm[e];
-  cpx<T> x[NS][NT], y;
   {
     // V P on the columns of I - V P: slots t < 3, t = 3 where cg = 0 (column
     // 24), and row 24 at column c24 < 25
@@ -410,6 +502,7 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
     else if (c24 < 2 * NB)
       y = ADJ ? bm[24 * NB + c24 - NB] : sv[24 * NB + c24 - NB];
   }
+  }
   __syncthreads();  // the last chunk has been read: its area takes the pivot exchange
   if (lane < 16) xs[(lane >> 3) * W25::EX + 56 + (lane & 7)] = mk(T(0), T(0));  // pivot-row padding columns
   int cs[NS], kof[NS], k24 = -1;
@@ -429,10 +522,10 @@ __global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq,
 #pragma unroll
     for (int t = 3; t < NT; ++t) {
       const int col = cg + 8 * t - NB;
-      if (col >= 0 && col < NB) wm[k * NB + col] = ADJ ? x[s][t] : x[s][t] - sv[k * NB + col];
+      if (col >= 0 && col < NB) wm[k * NB + col] = ADJ ? x[s][t] : x[s][t] - (MVP ? vm : sv)[k * NB + col];
     }
   }
-  if (c24 >= NB && c24 < 2 * NB) wm[k24 * NB + c24 - NB] = ADJ ? y : y - sv[k24 * NB + c24 - NB];
+  if (c24 >= NB && c24 < 2 * NB) wm[k24 * NB + c24 - NB] = ADJ ? y : y - (MVP ? vm : sv)[k24 * NB + c24 - NB];
 }
 
 // ---------------------------------------------------------------------------
@@ -963,8 +1056,12 @@ hipError_t dyson_w_nb(const Plan& p, const void* v_q, const void* p_nu, void* wc
   if (ld == 0) ld = int64_t(NB) * NB;
   if (ld < int64_t(NB) * NB) return hipErrorInvalidValue;
   if (NB == 25) {
-    hipLaunchKernelGGL((k_dyson_w25<T>), dim3(unsigned(nmat)), dim3(64), 0, s, (const cpx<T>*)v_q,
-                       (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld, p.d_status + kCondWord);
+    if (p.tune.w25_mfma == 1)
+      hipLaunchKernelGGL((k_dyson_w25<T, false, true>), dim3(unsigned(nmat)), dim3(64), 0, s, (const cpx<T>*)v_q,
+                         (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld, p.d_status + kCondWord, nullptr);
+    else
+      hipLaunchKernelGGL((k_dyson_w25<T, false, false>), dim3(unsigned(nmat)), dim3(64), 0, s, (const cpx<T>*)v_q,
+                         (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld, p.d_status + kCondWord, nullptr);
     return hipGetLastError();
   }
   const unsigned blocks = unsigned((nmat + MPW - 1) / MPW);
@@ -1059,10 +1156,15 @@ hipError_t dyson_w_bwd_nb(const Plan& p, const void* v_q, const void* p_nu, cons
   zd* xm = wcm + nmat * NN;
   zd* vpart = xm + nmat * NN;
   int* cond = p.d_status + kCondWord;
-  if (NB == 25) {
-    hipLaunchKernelGGL((k_dyson_w25<double, false>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
+  if (NB == 25 && p.tune.w25_mfma == 1) {
+    hipLaunchKernelGGL((k_dyson_w25<double, false, true>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
                        (const zd*)p_nu, wcm, nmat, p.nk, NN, cond, nullptr);
-    hipLaunchKernelGGL((k_dyson_w25<double, true>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
+    hipLaunchKernelGGL((k_dyson_w25<double, true, true>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
+                       (const zd*)p_nu, xm, nmat, p.nk, NN, cond, (const zd*)wbar);
+  } else if (NB == 25) {
+    hipLaunchKernelGGL((k_dyson_w25<double, false, false>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
+                       (const zd*)p_nu, wcm, nmat, p.nk, NN, cond, nullptr);
+    hipLaunchKernelGGL((k_dyson_w25<double, true, false>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
                        (const zd*)p_nu, xm, nmat, p.nk, NN, cond, (const zd*)wbar);
   } else {
     constexpr int MPW = DysonWShape<NB>::MPW;

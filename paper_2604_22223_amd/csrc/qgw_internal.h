@@ -64,6 +64,7 @@ struct Tune {
   int mfma_bpc = 0;     // resident blocks per CU of the MFMA DLR maps
   int orb_valu = -1;    // orbital-array maps: 1 VALU kernel, 0 matrix cores
   int orb_mt = 0;       // rows per block chunk of the VALU map kernel
+  int w25_mfma = -1;    // Dyson W with N_b = 25: 1 V P on the matrix cores, 0 on the VALU, -1 the default (0)
 };
 
 struct Plan {

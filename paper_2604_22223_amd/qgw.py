@@ -37,7 +37,7 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
            "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_quasiparticle", "qgw_hf_density", "qgw_state_hf_solve", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
            "qgw_plan_create_mf", "qgw_mf_nodes_for", "qgw_workspace_size", "qgw_sync_status", "qgw_dyson_G_noalloc", "qgw_quasiparticle_path_workspace",
-           "qgw_quasiparticle_path", "qgw_last_error"]
+           "qgw_quasiparticle_path", "qgw_plan_set_tuning", "qgw_last_error"]
 
 
 class QGWError(RuntimeError):
@@ -108,6 +108,7 @@ def lib():
             "qgw_pair_layout": [vp, i32, i32, i64, vp, vp, vp],
             "qgw_add": [vp, i64, vp, vp, vp, vp],
             "qgw_plan_autotune": [vp, pi32, vp],
+            "qgw_plan_set_tuning": [vp, i32, pi32],
             "qgw_energy": [vp, vp, vp, vp, vp, pd, vp, i64, vp],
             "qgw_energy_bwd": [vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp, i64, vp],
             "qgw_quasiparticle": [vp, vp, vp, vp, dbl, vp, vp, vp, pd, vp, i64, vp],
@@ -348,13 +349,23 @@ class Plan:
         return sigbar, hbar
 
     TUNE_NAMES = ("fft_slabs_per_block", "bubble_slabs_per_block", "sigma_term_lanes", "mfma_blocks_per_cu",
-                  "orbital_map_valu", "orbital_map_rows")
+                  "orbital_map_valu", "orbital_map_rows", "dyson_w25_mfma")
 
     def autotune(self):
         """Times the candidate launch shapes on this plan and keeps the fastest; returns them."""
-        ch = (ctypes.c_int32 * 6)()
+        ch = (ctypes.c_int32 * 7)()
         _check(lib().qgw_plan_autotune(self.handle, ch, _stream()))
         return dict(zip(self.TUNE_NAMES, list(ch)))
+
+    def set_tuning(self, choices, precision=0):
+        """Sets the launch shapes (a dict as autotune returns; missing knobs at their defaults) for the plan's
+        FP64 (precision 0) or, on an FP64 plan, its FP32 kernels (precision 1) (qgw_plan_set_tuning)."""
+        dflt = {n: 0 for n in self.TUNE_NAMES}
+        dflt["orbital_map_valu"] = -1
+        dflt["dyson_w25_mfma"] = -1
+        dflt.update(choices)
+        ch = (ctypes.c_int32 * 7)(*[int(dflt[n]) for n in self.TUNE_NAMES])
+        _check(lib().qgw_plan_set_tuning(self.handle, int(precision), ch))
 
     def energy(self, h_k, shf_k, sig_iw, g_iw):
         """(E, HF part, correlation part) of the Galitskii-Migdal energy."""
