@@ -653,12 +653,14 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
     sc[0] = *mu;
     sc[1] = n_target;
   }
-  QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, 2 * sizeof(double), hipMemcpyHostToDevice, s), "qgw_dyson_G");
-  // the search's first launch resets the status word; a fixed-mu call has no search
-  if (mode == 1)
-    QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, track, s), "qgw_dyson_G");
-  else
+  // the search's first launch takes the start point as arguments and resets the status word; a fixed-mu call
+  // has no search and gets mu by a copy
+  if (mode == 1) {
+    QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, track, s, 1, sc[0], sc[1]), "qgw_dyson_G");
+  } else {
+    QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, 2 * sizeof(double), hipMemcpyHostToDevice, s), "qgw_dyson_G");
     QGW_CHECK_HIP(hipMemsetAsync(stat, 0, sizeof(int), s), "qgw_dyson_G");
+  }
   // scal[0..9]: mu, n_target, evaluations, N_e, search state, status, extra
   double res[10] = {};
   int st = 0;
@@ -1490,7 +1492,7 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     }
     // a13: Dyson G with the chemical potential
     // |dSigma| (a14, already enqueued) comes back with the search's result: one wait per iteration
-    // the first round queues the previous search's evaluation count + 3 Newton steps (4 .. 12; 10 after G0)
+    // the first round queues the previous search's evaluation count + 2 Newton steps (3 .. 12; 10 after G0)
     double m = st->mu, evals = 0.0;
     qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, &evals, st->d_scal,
                                 st->d_part, st->d_stat, st->d_dsig, &dsig,
@@ -1516,7 +1518,7 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
       return rc;
     }
     st->mu = m;
-    st->mu_steps0 = std::min(12, std::max(4, int(evals) + 3));
+    st->mu_steps0 = std::min(12, std::max(3, int(evals) + 2));
     if (st->prof) {
       for (int i = 0; i < QGW_NUM_STEPS; ++i) {
         float ms = 0.0f;

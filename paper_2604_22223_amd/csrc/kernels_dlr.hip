@@ -397,14 +397,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   // the input's rows (index L) are in_ld apart, its node planes nL in_ld (in_ld >= nW: padded rows)
   const int64_t in_plane = int64_t(nL) * in_ld;
   int buf = 0;  // slice parity, continued across tiles
-  // XCD-aware order: with the grid a multiple of 8, block b runs on XCD b mod 8, and each XCD takes one
-  // contiguous eighth of the tiles.  Neighbouring W tiles (which share the input's 128-byte lines when a tile's
-  // 8 W values span half a line, as in FP32) and neighbouring L tiles then meet in one L2.
-  const bool by_xcd = (gridDim.x & 7) == 0;
-  const int64_t nx = by_xcd ? 8 : 1, xi = by_xcd ? (blockIdx.x & 7) : 0;
-  const int64_t bpx = gridDim.x / nx, bi = by_xcd ? (blockIdx.x >> 3) : blockIdx.x;
-  const int64_t t_hi = ntiles * (xi + 1) / nx;
-  for (int64_t tile = ntiles * xi / nx + bi; tile < t_hi; tile += bpx) {
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int tL = int(tile % tiles_l), tW = int(tile / tiles_l);
     // input column of this thread's loads (clamped into the array: values
     // outside it feed only columns that are not stored)

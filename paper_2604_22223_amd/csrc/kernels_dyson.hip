@@ -684,9 +684,10 @@ __global__ __launch_bounds__(64) void k_dg_gersh(DysonGArgs A) {
 // mu <- centre of the Gershgorin bounds if no finite start was given; otherwise, with ``track``, the start moves
 // by the change of the mean diagonal of H since the previous search (scal[10]), the shift of a level by a change
 // of Sigma_HF (so that a Hartree shift of many eV does not cost a chain of capped steps); resets the search
+// set: the start point (mu0, n_target) comes as arguments instead of a copy into scal[0..1]
 __global__ __launch_bounds__(64) void k_dg_begin(double* __restrict__ scal, int* __restrict__ status,
                                                  const double* __restrict__ partials, int nblk, double inv_count,
-                                                 int track) {
+                                                 int track, int set, double mu0, double nt) {
   double glo = 1e300, ghi = -1e300, dsum = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) {
     glo = fmin(glo, partials[b]);
@@ -697,6 +698,10 @@ __global__ __launch_bounds__(64) void k_dg_begin(double* __restrict__ scal, int*
   ghi = wave_max(ghi);
   const double mean = wave_sum(dsum) * inv_count;
   if (threadIdx.x != 0) return;
+  if (set) {
+    scal[0] = mu0;
+    scal[1] = nt;
+  }
   if (!isfinite(scal[0])) {
     scal[0] = 0.5 * (glo + ghi);
   } else if (track && isfinite(scal[10]) && isfinite(mean)) {
@@ -1116,12 +1121,12 @@ namespace {
 
 template <int NO>
 hipError_t dyson_g_begin_no(const Plan& p, const void* h_k, double* scal, double* partials, int* status, int track,
-                            hipStream_t s) {
+                            int set, double mu0, double nt, hipStream_t s) {
   DysonGArgs A = dyson_g_args<NO>(p, h_k, nullptr, 1, nullptr, scal, partials, status);
   const int gb = int((p.nk + 63) / 64 < 1024 ? (p.nk + 63) / 64 : 1024);
   hipLaunchKernelGGL((k_dg_gersh<NO>), dim3(gb), dim3(64), 0, s, A);
   hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status, (const double*)partials, gb,
-                     1.0 / (double(NO) * p.nk), track);
+                     1.0 / (double(NO) * p.nk), track, set, mu0, nt);
   return hipGetLastError();
 }
 
@@ -1268,8 +1273,8 @@ hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void
   }
 
 hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
-                                int track, hipStream_t s) {
-  QGW_NO_SWITCH((dyson_g_begin_no<NOV>(p, h_k, scal, partials, status, track, s)))
+                                int track, hipStream_t s, int set, double mu0, double nt) {
+  QGW_NO_SWITCH((dyson_g_begin_no<NOV>(p, h_k, scal, partials, status, track, set, mu0, nt, s)))
 }
 
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,

@@ -156,9 +156,10 @@ hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStre
 // search; steps: `steps` Newton evaluations (no-ops once done); final: G at
 // mu (mode 0: mu as given; mode 1: also status 2 if the search has not
 // converged).  chain = begin + steps + final (graph-capturable).
-// track = 1: a state's search, whose start moves with the mean diagonal of H since its previous search (scal[10])
+// track = 1: a state's search, whose start moves with the mean diagonal of H since its previous search (scal[10]);
+// set = 1: scal[0..1] = (mu0, nt) first (the host's start point as kernel arguments, no copy)
 hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
-                                int track, hipStream_t s);
+                                int track, hipStream_t s, int set = 0, double mu0 = 0.0, double nt = 0.0);
 // doubles of partial sums one chemical-potential search on plan p uses (start and evaluations)
 int dyson_g_partials_needed(const Plan& p);
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
