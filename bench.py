@@ -91,7 +91,9 @@ def step_model(r, n_o, n_b, n_k, prec="f64"):
         "a8a9a10_sigma": {"bytes": c * npair + 2 * c * ng, "flops": r * n_b * n_b * (fft_flops + 8.0 * n_k) + r * n_o * n_o * fft_flops},
         # read Sigma^C(k, tau), write the FP64 Sigma^C(k, i w)
         "a11_dlr_sigma": {"bytes": c * ng + 16.0 * ng, "flops": 8.0 * r * r * n_o * n_o * n_k},
-        "a14_delta_mix": {"bytes": 4 * 16.0 * ng, "flops": 0.0},
+        # Sigma^C new and old read, old written (at mixing 1, as timed, the new values are not rewritten); Sigma_HF
+        # new and old read, old written, H0 read and H0 + Sigma_HF written
+        "a14_delta_mix": {"bytes": 3 * 16.0 * ng + 5 * stat_o, "flops": 0.0},
         "a13_dyson_g": {"bytes": 2 * 16.0 * ng, "flops": 0.0},
     }
 
@@ -104,10 +106,10 @@ PEAK_TFLOPS = {"f64": FP64_PEAK_TFLOPS, "f32": FP32_PEAK_TFLOPS}
 # profiles/hbm_traffic_gw_iteration_five_orbital_24.md).
 # Valid for the kernels as they were profiled; a changed kernel drops its entry until it is profiled again.
 MEASURED_TRAFFIC = {
-    "a3a4_bubble:f64": 332.2e6, "a5_dlr_p:f64": 671.8e6, "a6_dyson_w:f64": 629.3e6, "a7_dlr_w:f64": 655.2e6,
-    "a8a9a10_sigma:f64": 333.8e6,
-    "a3a4_bubble:f32": 166.2e6, "a5_dlr_p:f32": 348.2e6, "a6_dyson_w:f32": 315.0e6, "a7_dlr_w:f32": 461.6e6,
-    "a8a9a10_sigma:f32": 166.0e6,
+    "a3a4_bubble:f64": 332.7e6, "a5_dlr_p:f64": 671.8e6, "a6_dyson_w:f64": 628.6e6, "a7_dlr_w:f64": 655.2e6,
+    "a8a9a10_sigma:f64": 333.8e6, "a14_delta_mix:f64": 37.8e6,
+    "a3a4_bubble:f32": 166.2e6, "a5_dlr_p:f32": 348.2e6, "a6_dyson_w:f32": 314.6e6, "a7_dlr_w:f32": 461.6e6,
+    "a8a9a10_sigma:f32": 166.1e6, "a14_delta_mix:f32": 37.8e6,
 }
 FP64_STEPS = ("a12_density_hf", "a14_delta_mix", "a13_dyson_g")
 
@@ -510,6 +512,23 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
     res["eager_fp64"] = {"instance_iterations_per_s": round(count * launches / el, 2), "s_per_sweep": round(el / launches, 5),
                          "max_mu_evaluations": int(evals)}
     log("[bench] batch eager FP64: %.4f s per sweep of %d instances" % (el / launches, count))
+    # GPU time of the steps alone: one more sweep per precision with every state's step events on, summed over the
+    # instances (each instance's kernels back to back with no host gaps; the floor of any launch scheme that does not
+    # run two instances' kernels at once)
+    for key, mode in (("fp64", 0), ("fp32", 2)):
+        for st in states:
+            st.set_precision(mode)
+            st.profile(1)
+            st.iterate(1)
+        torch.cuda.synchronize()
+        tot = 0.0
+        for st in states:
+            ms, _ = st.profile(2)
+            tot += sum(ms.values())
+            st.profile(0)
+        res["step_time_sum_%s_s_per_sweep" % key] = round(tot / 1e3, 5)
+    log("[bench] batch: summed step time per sweep %.4f s (FP64), %.4f s (FP32)"
+        % (res["step_time_sum_fp64_s_per_sweep"], res["step_time_sum_fp32_s_per_sweep"]))
     labels = {"graph_fp64": "FP64 iterations", "graph_fp32": "single-precision bulk steps a1-a11 in every iteration "
               "(the FP32 phase of the mixed schedule, without its FP64 finish: not a refined end point)"}
     for name, prec in (("graph_fp64", qgw.F64), ("graph_fp32", qgw.F32)):
