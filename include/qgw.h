@@ -500,7 +500,12 @@ typedef struct qgw_state_s *qgw_state;
 /* A self-consistent GW state bound to a plan: holds H0(k), V(q) and every
  * intermediate array on the device.  H0_R: [n_o][n_o][N_k] and V_R:
  * [N_b][N_b][N_k] are device arrays in R (FP64).  mixing in (0, 1] is the
- * linear mixing weight of the total self-energy (1 = none). */
+ * linear mixing weight of the total self-energy (1 = none).  The state owns
+ * a second stream (default priority) on which each qgw_gw_iteration runs its
+ * a12 beside a1-a11; it is forked from and joined back into the caller's
+ * stream inside the iteration, so work the caller orders after an iteration
+ * on its stream sees all of it.  A batch records a12 on its own worker
+ * stream instead. */
 qgw_status qgw_state_create(qgw_plan plan, const void *H0_R, const void *V_R,
                             double n_target, double mixing, qgw_state *state);
 qgw_status qgw_state_destroy(qgw_state state);
@@ -570,7 +575,10 @@ qgw_status qgw_state_info(qgw_state state, int32_t *last_prec, int32_t *n_fp32, 
                           int32_t *mu_evals);
 
 /* Per-step timing of qgw_gw_iteration with HIP events on the caller's
- * stream.  mode 1 resets the accumulators and enables timing, mode 0
+ * stream (step 0 on the state's second stream, where a12 runs concurrently
+ * with steps 1-8; it joins the caller's stream before step 9, so the steps'
+ * times add up to more than the iteration's span by about step 0's).
+ * mode 1 resets the accumulators and enables timing, mode 0
  * disables it, mode 2 only reads.  ms[2 * QGW_NUM_STEPS] (may be NULL)
  * receives the accumulated milliseconds per step, first over the FP64
  * iterations, then over the FP32 ones; iters[2] (may be NULL) the number of

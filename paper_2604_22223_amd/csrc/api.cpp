@@ -48,6 +48,9 @@ struct qgw_state_s {
   // event the host polls for the result: no staging copy and no blocking wait per iteration
   double* h_io = nullptr;
   hipEvent_t ev_io = nullptr;
+  // a12 runs on this side stream beside a1..a11 (fork and join events); default priority like every stream here
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // single-precision copies for the FP32 phase of the solve (allocated on first use)
   bool has32 = false;
   Plan p32;
@@ -63,6 +66,7 @@ struct qgw_state_s {
   // per-step timing with HIP events on the caller's stream
   bool prof = false;
   hipEvent_t ev[QGW_NUM_STEPS + 1] = {};
+  hipEvent_t ev_a12 = nullptr;  // end of a12 on the side stream (its start is ev[0], recorded there)
   double prof_ms[2][QGW_NUM_STEPS] = {};  // [FP64, FP32 iterations][step]
   int prof_iters[2] = {};
 };
@@ -1242,6 +1246,10 @@ static void free_state(qgw_state st) {
   for (auto& e : st->ev)
     if (e) (void)hipEventDestroy(e);
   if (st->ev_io) (void)hipEventDestroy(st->ev_io);
+  if (st->ev_a12) (void)hipEventDestroy(st->ev_a12);
+  if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
+  if (st->ev_join) (void)hipEventDestroy(st->ev_join);
+  if (st->side) (void)hipStreamDestroy(st->side);
   if (st->h_io) (void)hipHostFree(st->h_io);
   void* ptrs[] = {st->H_k, st->V_R, st->V_q, st->V_qm, st->V_q0, st->G_iw, st->Sig_iw, st->Sig_iw_old,
                   st->SigHF_k, st->SigHF_old, st->n_k, st->n_R, st->SigHF_R, st->Hs_k, st->G_tau,
@@ -1316,6 +1324,9 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
   }
   if (e == hipSuccess) e = hipHostMalloc((void**)&st->h_io, 32 * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_io, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_join, hipEventDisableTiming);
   st->p32 = p;
   st->p32.prec = QGW_F32;
   hipStream_t s = nullptr;
@@ -1404,8 +1415,9 @@ qgw_status qgw_state_info(qgw_state st, int32_t* last_prec, int32_t* n_fp32, int
 }
 
 // a12, a1-a11 (FP64 or single precision), a14 and the static H + Sigma_HF of a13,
-// enqueued on s; with `prof` HIP events mark the step boundaries 0 .. 10
-static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s) {
+// enqueued on s; with `prof` HIP events mark the step boundaries 0 .. 10.  fork: a12 on the state's side stream
+// (eager iterations); without it (batch capture) everything goes on s.
+static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s, bool fork) {
   const Plan& p = st->plan->p;
   const int64_t no2 = int64_t(p.no) * p.no;
   const int64_t ncol_g = no2 * p.nk;
@@ -1413,12 +1425,22 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
   hipError_t e = hipSuccess;
   auto mark = [&](int i) { if (e == hipSuccess && prof) e = hipEventRecord(st->ev[i], s); };
   auto run = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-  // a12: density of the incoming G (Hermitian part), Hartree-Fock
-  mark(0);
-  run(launch_dlr(p, QGW_F_IW2BETA, ncol_g, -1.0, 0.0, st->G_iw, st->n_k, s, 2));
-  run(launch_lattice_fft(p, QGW_K_TO_R, no2, st->n_k, st->n_R, s));
-  run(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, s));
-  run(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, s));
+  // a12: density of the incoming G (Hermitian part), Hartree-Fock.  It reads only G and writes only n and
+  // Sigma_HF, which a14 and a13 use: in an eager iteration it runs on the state's side stream beside a1..a11 and
+  // joins before a14, so its small, latency-bound launches overlap the pair-array steps instead of adding to them.
+  // A batch capture keeps it on the worker stream (a fork from an already forked stream is not recorded).
+  hipStream_t a = fork ? st->side : s;
+  if (fork) {
+    run(hipEventRecord(st->ev_fork, s));
+    run(hipStreamWaitEvent(a, st->ev_fork, 0));
+  }
+  if (e == hipSuccess && prof) e = hipEventRecord(st->ev[0], a);
+  run(launch_dlr(p, QGW_F_IW2BETA, ncol_g, -1.0, 0.0, st->G_iw, st->n_k, a, 2));
+  run(launch_lattice_fft(p, QGW_K_TO_R, no2, st->n_k, st->n_R, a));
+  run(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, a));
+  run(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, a));
+  if (e == hipSuccess && prof) e = hipEventRecord(st->ev_a12, a);
+  if (fork) run(hipEventRecord(st->ev_join, a));
   if (!f32) {
     mark(1);  // a1
     if (p.grid == kGridMF) {
@@ -1462,8 +1484,8 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     run(launch_dlr(q, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->St32, st->Siw32, s, 1));
     run(launch_convert(ncol_g * p.r, st->Siw32, st->Sig_iw, 0, s));
   }
-  // a14: change of the total self-energy, mixing
-  // a14 and the static part of a13 (H0 + Sigma_HF) in one pass
+  // a14 and the static part of a13 (H0 + Sigma_HF) in one pass, once a12 has joined
+  if (fork) run(hipStreamWaitEvent(s, st->ev_join, 0));
   mark(9);
   run(launch_delta_and_mix(p, st->SigHF_k, st->Sig_iw, st->SigHF_old, st->Sig_iw_old, st->mixing, st->d_dsig,
                            st->d_blockmax, s, st->H_k, st->Hs_k));
@@ -1484,7 +1506,7 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
   int done = 0;
   for (int it = 0; it < n_iter; ++it) {
     const bool f32 = st->prec_mode == 2 || (st->prec_mode == 1 && st->in_fp32);
-    const hipError_t qe = enqueue_steps(st, f32, st->prof, s);
+    const hipError_t qe = enqueue_steps(st, f32, st->prof, s, true);
     if (qe != hipSuccess) {
       st->broken = true;
       set_error(std::string("qgw_gw_iteration: ") + hipGetErrorString(qe));
@@ -1521,8 +1543,9 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     st->mu_steps0 = std::min(12, std::max(3, int(evals) + 2));
     if (st->prof) {
       for (int i = 0; i < QGW_NUM_STEPS; ++i) {
+        // step 0 (a12) ran on the side stream, from ev[0] to ev_a12
         float ms = 0.0f;
-        QGW_CHECK_HIP(hipEventElapsedTime(&ms, st->ev[i], st->ev[i + 1]), "profile");
+        QGW_CHECK_HIP(hipEventElapsedTime(&ms, st->ev[i], i == 0 ? st->ev_a12 : st->ev[i + 1]), "profile");
         st->prof_ms[f32 ? 1 : 0][i] += ms;
       }
       ++st->prof_iters[f32 ? 1 : 0];
@@ -1614,7 +1637,7 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
         qgw_state st = states[i];
         const Plan& p = st->plan->p;
         hipStream_t ws = b->workers[i % nw];
-        ce = enqueue_steps(st, precision == 1, false, ws);
+        ce = enqueue_steps(st, precision == 1, false, ws, false);
         if (ce == hipSuccess)
           ce = launch_dyson_g_chain(p, st->Hs_k, st->Sig_iw, std::isnan(st->n_target) ? 0 : 1, st->G_iw, st->d_scal,
                                     st->d_part, st->d_stat, mu_steps, st->d_stat + 1, ws);
@@ -1721,6 +1744,7 @@ qgw_status qgw_state_profile(qgw_state st, int32_t mode, double* ms, int32_t* it
   if (mode == 1) {
     for (auto& e : st->ev)
       if (!e) QGW_CHECK_HIP(hipEventCreate(&e), "qgw_state_profile");
+    if (!st->ev_a12) QGW_CHECK_HIP(hipEventCreate(&st->ev_a12), "qgw_state_profile");
     for (auto& row : st->prof_ms)
       for (double& v : row) v = 0.0;
     st->prof_iters[0] = st->prof_iters[1] = 0;
