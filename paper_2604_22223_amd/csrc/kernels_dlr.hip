@@ -368,14 +368,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 // its 16-column strip on the matrix cores and writes whole 16-value runs of
 // the output.  Slab -> matrix: L = pair index a, W = q; matrix -> slab:
 // L = q, W = a.
-template <typename T, int MT, int MODE>
+// WT: W values per wave (tile 16 x 8 WT).  FP32 takes WT = 2, so that the eight threads' values of one row of the
+// input (8 WT x 8 bytes) are a whole 128-byte line, as the 8 FP64 values of WT = 1 are; each barrier then also
+// carries twice the matrix-core work.
+template <typename T, int MT, int MODE, int WT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dlr_mfma_pairs(
     const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ map, int r, int kp,
     int na, int nq, int tiles_l, int64_t ntiles, T sre, T sim, int64_t in_ld) {
   using M = Mfma<T>;
   using v4 = typename M::v4;
-  constexpr int WP = 9;             // padded W extent of the LDS tile
-  constexpr int XT = 4 * 16 * WP;   // one tile buffer (complex values)
+  constexpr int TW = 8 * WT;         // W extent of a tile
+  constexpr int SW = WT == 2 ? 4 : 3;  // log2(TW)
+  constexpr int WP = TW + 1;         // padded W extent of the LDS tile
+  constexpr int XT = 4 * 16 * WP;    // one tile buffer (complex values)
   extern __shared__ unsigned char smem_raw[];
   T* tre = reinterpret_cast<T*>(smem_raw);
   T* tim = tre + MT * 16 * kp;
@@ -390,8 +395,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lk = lane >> 4;
-  // the value this thread loads per slice: node lt, column (lL, lW) of the tile
-  const int lt = threadIdx.x >> 7, lL = (threadIdx.x >> 3) & 15, lW = threadIdx.x & 7;
+  // the values this thread loads per slice (j < WT): node lt[j], column (lL, lW) of the tile, from the index
+  // threadIdx.x + 512 j over (node, L, W) with W fastest
+  const int lW = threadIdx.x & (TW - 1), lL = (threadIdx.x >> SW) & 15;
+  int lt[WT];
+#pragma unroll
+  for (int j = 0; j < WT; ++j) lt[j] = (threadIdx.x + 512 * j) >> (SW + 4);
   const int nL = MODE == kSlabToMatrix ? na : nq, nW = MODE == kSlabToMatrix ? nq : na;
   const int64_t plane = int64_t(na) * nq;
   // the input's rows (index L) are in_ld apart, its node planes nL in_ld (in_ld >= nW: padded rows)
@@ -401,26 +410,32 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int tL = int(tile % tiles_l), tW = int(tile / tiles_l);
     // input column of this thread's loads (clamped into the array: values
     // outside it feed only columns that are not stored)
-    const int Lld = min(tL * 16 + lL, nL - 1), Wld = min(tW * 8 + lW, nW - 1);
+    const int Lld = min(tL * 16 + lL, nL - 1), Wld = min(tW * TW + lW, nW - 1);
     const cpx<T>* src = in + int64_t(Lld) * in_ld + Wld;
     // node index clamped to r - 1: the map's zero padding cancels it
-    auto gload = [&](int kb) -> cpx<T> { return src[int64_t(min(kb + lt, r - 1)) * in_plane]; };
-    const int Lo = tL * 16 + lc, Wo = tW * 8 + wave;
-    const bool valid = Lo < nL && Wo < nW;
-    const int64_t cout = int64_t(Wo) * nL + Lo;
-    v4 accr[MT], acci[MT];
+    auto gload = [&](int kb, int j) -> cpx<T> { return src[int64_t(min(kb + lt[j], r - 1)) * in_plane]; };
+    const int Lo = tL * 16 + lc;
+    v4 accr[WT][MT], acci[WT][MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      accr[mt] = v4{T(0), T(0), T(0), T(0)};
-      acci[mt] = v4{T(0), T(0), T(0), T(0)};
-    }
-    cpx<T> g = dpp_identity(gload(0));
+    for (int w = 0; w < WT; ++w)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        accr[w][mt] = v4{T(0), T(0), T(0), T(0)};
+        acci[w][mt] = v4{T(0), T(0), T(0), T(0)};
+      }
+    cpx<T> g[WT];
+#pragma unroll
+    for (int j = 0; j < WT; ++j) g[j] = dpp_identity(gload(0, j));
     for (int kb = 0; kb < kp; kb += 4, buf ^= 1) {
       cpx<T>* xb = xt + buf * XT;
-      xb[(lt * 16 + lL) * WP + lW] = g;
+#pragma unroll
+      for (int j = 0; j < WT; ++j) xb[(lt[j] * 16 + lL) * WP + lW] = g[j];
       __syncthreads();  // the slice is in LDS; the buffer written next was read two slices ago
-      g = gload(kb + 4);
-      const cpx<T> x = xb[(lk * 16 + lc) * WP + wave];
+#pragma unroll
+      for (int j = 0; j < WT; ++j) g[j] = gload(kb + 4, j);
+      cpx<T> x[WT];
+#pragma unroll
+      for (int w = 0; w < WT; ++w) x[w] = xb[(lk * 16 + lc) * WP + wave + 8 * w];
       const int kk = kb >> 2;
       T ar[MT], ai[MT];
 #pragma unroll
@@ -429,25 +444,34 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         ai[mt] = tim[(kk * MT + mt) * 64 + lane];
       }
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        accr[mt] = M::mac(ar[mt], x.re, accr[mt]);
-        acci[mt] = M::mac(ar[mt], x.im, acci[mt]);
-      }
+      for (int w = 0; w < WT; ++w)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        accr[mt] = M::mac(-ai[mt], x.im, accr[mt]);
-        acci[mt] = M::mac(ai[mt], x.re, acci[mt]);
-      }
-    }
-    if (valid) {
-      const cpx<T> sc = mk(sre, sim);
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = mt * 16 + M::row(lane, v);
-          if (m < r) out[int64_t(m) * plane + cout] = sc * mk(accr[mt][v], acci[mt][v]);
+        for (int mt = 0; mt < MT; ++mt) {
+          accr[w][mt] = M::mac(ar[mt], x[w].re, accr[w][mt]);
+          acci[w][mt] = M::mac(ar[mt], x[w].im, acci[w][mt]);
         }
+#pragma unroll
+      for (int w = 0; w < WT; ++w)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          accr[w][mt] = M::mac(-ai[mt], x[w].im, accr[w][mt]);
+          acci[w][mt] = M::mac(ai[mt], x[w].re, acci[w][mt]);
+        }
+    }
+    const cpx<T> sc = mk(sre, sim);
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+      const int Wo = tW * TW + wave + 8 * w;
+      if (Lo < nL && Wo < nW) {
+        const int64_t cout = int64_t(Wo) * nL + Lo;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int m = mt * 16 + M::row(lane, v);
+            if (m < r) out[int64_t(m) * plane + cout] = sc * mk(accr[w][mt][v], acci[w][mt][v]);
+          }
+      }
     }
   }
 }
@@ -461,19 +485,20 @@ hipError_t dlr_mfma_pairs_launch(const Plan& p, int map, int na, int nq, double 
   const int nL = MODE == kSlabToMatrix ? na : nq, nW = MODE == kSlabToMatrix ? nq : na;
   if (in_ld == 0) in_ld = nW;
   if (in_ld < nW) return hipErrorInvalidValue;
+  constexpr int WT = sizeof(T) == 4 ? 2 : 1;  // W values per wave (see the kernel)
   const int tiles_l = (nL + 15) / 16;
-  const int64_t ntiles = int64_t(tiles_l) * ((nW + 7) / 8);
+  const int64_t ntiles = int64_t(tiles_l) * ((nW + 8 * WT - 1) / (8 * WT));
   int dev = 0, ncu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const int bpc = p.tune.mfma_bpc > 0 ? p.tune.mfma_bpc : 2;
   int64_t blocks = ntiles;
   if (blocks > int64_t(bpc) * ncu) blocks = int64_t(bpc) * ncu;
-  const size_t lds = size_t(2) * mt * 16 * kp * sizeof(T) + size_t(2) * 4 * 16 * 9 * sizeof(cpx<T>);
+  const size_t lds = size_t(2) * mt * 16 * kp * sizeof(T) + size_t(2) * 4 * 16 * (8 * WT + 1) * sizeof(cpx<T>);
   const cpx<T>* mp = map_ptr<T>(p, map);
 #define QGW_MFMA_MT(MTV)                                                                                       \
   case MTV:                                                                                                    \
-    hipLaunchKernelGGL((k_dlr_mfma_pairs<T, MTV, MODE>), dim3(unsigned(blocks)), dim3(512), lds, s,            \
+    hipLaunchKernelGGL((k_dlr_mfma_pairs<T, MTV, MODE, WT>), dim3(unsigned(blocks)), dim3(512), lds, s,        \
                        (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, tiles_l, ntiles, T(sre), T(sim), \
                        in_ld);                                                                                 \
     break;
