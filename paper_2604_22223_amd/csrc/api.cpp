@@ -641,7 +641,8 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
                               double* mu, void* G_iw, hipStream_t s, double* evals, double* scal = nullptr,
                               double* part = nullptr, int* stat = nullptr, const double* extra_src = nullptr,
                               double* extra_dst = nullptr, hipEvent_t end_ev = nullptr, int steps0 = 6,
-                              double* h_io = nullptr, hipEvent_t io_ev = nullptr, int track = 0) {
+                              double* h_io = nullptr, hipEvent_t io_ev = nullptr, int track = 0,
+                              const double* dpart = nullptr, int dnblk = 0) {
   const int mode = std::isnan(n_target) ? 0 : 1;
   if (!scal) {
     scal = p.d_scalars;
@@ -660,7 +661,11 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
   // the search's first launch takes the start point as arguments and resets the status word; a fixed-mu call
   // has no search and gets mu by a copy
   if (mode == 1) {
-    QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, track, s, 1, sc[0], sc[1]), "qgw_dyson_G");
+    // with the diagonal sums of H from a14 at hand and a finite start, no Gershgorin pass is needed
+    const bool use_d = dpart && std::isfinite(sc[0]);
+    QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, track, s, 1, sc[0], sc[1], use_d ? dpart : nullptr,
+                                       dnblk),
+                  "qgw_dyson_G");
   } else {
     QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, 2 * sizeof(double), hipMemcpyHostToDevice, s), "qgw_dyson_G");
     QGW_CHECK_HIP(hipMemsetAsync(stat, 0, sizeof(int), s), "qgw_dyson_G");
@@ -1313,7 +1318,7 @@ qgw_status qgw_state_create(qgw_plan h, const void* H0_R, const void* V_R, doubl
                 {&st->Sig_iw_old, fo}, {&st->SigHF_k, so}, {&st->SigHF_old, so},  {&st->n_k, so},
                 {&st->n_R, so},       {&st->SigHF_R, so}, {&st->Hs_k, so},       {&st->G_tau, fo},
                 {&st->G_reflt, fo},   {&st->Sig_tau_k, fo}, {&st->Pq, fp},       {&st->P_nu, fp},
-                {&st->Wc_nu, fw},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 4096 * sizeof(double)},
+                {&st->Wc_nu, fw},     {(void**)&st->d_dsig, 64}, {(void**)&st->d_blockmax, 8192 * sizeof(double)},
                 {(void**)&st->d_scal, 32 * sizeof(double)},
                 {(void**)&st->d_part, size_t(8) * p.max_blocks * sizeof(double)},
                 {(void**)&st->d_stat, 16 * sizeof(int)},
@@ -1518,7 +1523,8 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     double m = st->mu, evals = 0.0;
     qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, &evals, st->d_scal,
                                 st->d_part, st->d_stat, st->d_dsig, &dsig,
-                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr, st->mu_steps0, st->h_io, st->ev_io, 1);
+                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr, st->mu_steps0, st->h_io, st->ev_io, 1,
+                                st->d_blockmax + 4096, dyson_g_diag_blocks(p));
     st->last_evals = int(evals);
     // a singular Dyson-W system or a non-finite self-energy is named as the cause, also of a failed search
     if (rc != QGW_ERR_DEVICE && (rc != QGW_OK || !std::isfinite(dsig))) {
@@ -1640,7 +1646,8 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
         ce = enqueue_steps(st, precision == 1, false, ws, false);
         if (ce == hipSuccess)
           ce = launch_dyson_g_chain(p, st->Hs_k, st->Sig_iw, std::isnan(st->n_target) ? 0 : 1, st->G_iw, st->d_scal,
-                                    st->d_part, st->d_stat, mu_steps, st->d_stat + 1, ws);
+                                    st->d_part, st->d_stat, mu_steps, st->d_stat + 1, ws, st->d_blockmax + 4096,
+                                    dyson_g_diag_blocks(p));
       }
     for (int w = 0; w < nw && ce == hipSuccess; ++w) {
       ce = hipEventRecord(b->events[w], b->workers[w]);

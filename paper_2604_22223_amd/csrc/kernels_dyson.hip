@@ -685,15 +685,21 @@ __global__ __launch_bounds__(64) void k_dg_gersh(DysonGArgs A) {
 // by the change of the mean diagonal of H since the previous search (scal[10]), the shift of a level by a change
 // of Sigma_HF (so that a Hartree shift of many eV does not cost a chain of capped steps); resets the search
 // set: the start point (mu0, n_target) comes as arguments instead of a copy into scal[0..1]
+// diag_only: partials holds only nblk diagonal sums (a14's), no Gershgorin bounds
 __global__ __launch_bounds__(64) void k_dg_begin(double* __restrict__ scal, int* __restrict__ status,
                                                  const double* __restrict__ partials, int nblk, double inv_count,
-                                                 int track, int set, double mu0, double nt) {
+                                                 int track, int set, double mu0, double nt, int diag_only) {
   double glo = 1e300, ghi = -1e300, dsum = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) {
-    glo = fmin(glo, partials[b]);
-    ghi = fmax(ghi, partials[nblk + b]);
-    dsum += partials[2 * nblk + b];
+    if (diag_only) {
+      dsum += partials[b];
+    } else {
+      glo = fmin(glo, partials[b]);
+      ghi = fmax(ghi, partials[nblk + b]);
+      dsum += partials[2 * nblk + b];
+    }
   }
+  if (diag_only) glo = ghi = NAN;  // no bounds: a start that is not finite stays so (status 1)
   glo = wave_min(glo);
   ghi = wave_max(ghi);
   const double mean = wave_sum(dsum) * inv_count;
@@ -1121,12 +1127,17 @@ namespace {
 
 template <int NO>
 hipError_t dyson_g_begin_no(const Plan& p, const void* h_k, double* scal, double* partials, int* status, int track,
-                            int set, double mu0, double nt, hipStream_t s) {
+                            int set, double mu0, double nt, const double* dpart, int dnblk, hipStream_t s) {
+  if (dpart) {
+    hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status, dpart, dnblk, 1.0 / (double(NO) * p.nk),
+                       track, set, mu0, nt, 1);
+    return hipGetLastError();
+  }
   DysonGArgs A = dyson_g_args<NO>(p, h_k, nullptr, 1, nullptr, scal, partials, status);
   const int gb = int((p.nk + 63) / 64 < 1024 ? (p.nk + 63) / 64 : 1024);
   hipLaunchKernelGGL((k_dg_gersh<NO>), dim3(gb), dim3(64), 0, s, A);
   hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status, (const double*)partials, gb,
-                     1.0 / (double(NO) * p.nk), track, set, mu0, nt);
+                     1.0 / (double(NO) * p.nk), track, set, mu0, nt, 0);
   return hipGetLastError();
 }
 
@@ -1273,8 +1284,9 @@ hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void
   }
 
 hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
-                                int track, hipStream_t s, int set, double mu0, double nt) {
-  QGW_NO_SWITCH((dyson_g_begin_no<NOV>(p, h_k, scal, partials, status, track, set, mu0, nt, s)))
+                                int track, hipStream_t s, int set, double mu0, double nt, const double* dpart,
+                                int dnblk) {
+  QGW_NO_SWITCH((dyson_g_begin_no<NOV>(p, h_k, scal, partials, status, track, set, mu0, nt, dpart, dnblk, s)))
 }
 
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
@@ -1291,10 +1303,10 @@ hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_
 
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, int steps, int* fail_word,
-                                hipStream_t s) {
+                                hipStream_t s, const double* dpart, int dnblk) {
   hipError_t e = hipSuccess;
   if (mode == 1) {
-    e = launch_dyson_g_begin(p, h_k, scal, partials, status, 1, s);
+    e = launch_dyson_g_begin(p, h_k, scal, partials, status, 1, s, 0, 0.0, 0.0, dpart, dnblk);
     if (e == hipSuccess) e = launch_dyson_g_steps(p, h_k, sig_iw, scal, partials, status, steps, s);
   }
   if (e == hipSuccess) e = launch_dyson_g_final(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s, nullptr,

@@ -93,7 +93,8 @@ __global__ void k_add(const zd* __restrict__ a, const zd* __restrict__ b, zd* __
 __global__ __launch_bounds__(256) void k_delta_mix(zd* __restrict__ hf_new, zd* __restrict__ c_new,
                                                    zd* __restrict__ hf_old, zd* __restrict__ c_old, int64_t ns,
                                                    int r, double alpha, double* __restrict__ block_max,
-                                                   const zd* __restrict__ h0, zd* __restrict__ hs) {
+                                                   const zd* __restrict__ h0, zd* __restrict__ hs, int no, int nk,
+                                                   double* __restrict__ diag_sum) {
   __shared__ double red[256];
   const int g = threadIdx.x >> 6;
   const int64_t st = int64_t(blockIdx.x) * 64 + (threadIdx.x & 63);
@@ -118,13 +119,25 @@ __global__ __launch_bounds__(256) void k_delta_mix(zd* __restrict__ hf_new, zd* 
   }
   red[threadIdx.x] = v;
   __syncthreads();  // every wave has read hf_new[st] and hf_old[st]
-  if (ok && g == 0) {
-    if (alpha != 1.0) {
-      h = ho + scale(h - ho, alpha);
-      hf_new[st] = h;
+  if (g == 0) {
+    double dv = 0.0;
+    if (ok) {
+      if (alpha != 1.0) {
+        h = ho + scale(h - ho, alpha);
+        hf_new[st] = h;
+      }
+      hf_old[st] = h;
+      if (h0) {
+        const cpx<double> t = h0[st] + h;
+        hs[st] = t;
+        if (int(st / nk) % (no + 1) == 0) dv = t.re;  // a diagonal entry (i, i)
+      }
     }
-    hf_old[st] = h;
-    if (h0) hs[st] = h0[st] + h;
+    if (diag_sum) {
+      // this block's part of the diagonal sum of H0 + Sigma_HF, for the start of the next search (fixed order)
+      for (int off = 32; off >= 1; off >>= 1) dv += __shfl_xor(dv, off, 64);
+      if (threadIdx.x == 0) diag_sum[blockIdx.x] = dv;
+    }
   }
   for (int off = 128; off >= 1; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
@@ -392,7 +405,8 @@ hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* 
   const int64_t blocks = nblk(ns, 64);
   if (blocks > 4096) return hipErrorInvalidValue;  // the state's block scratch holds 4096 maxima
   hipLaunchKernelGGL(k_delta_mix, dim3(unsigned(blocks)), dim3(256), 0, s, (zd*)hf_new, (zd*)c_new, (zd*)hf_old,
-                     (zd*)c_old, ns, p.r, alpha, block_scratch, (const zd*)h0, (zd*)hs);
+                     (zd*)c_old, ns, p.r, alpha, block_scratch, (const zd*)h0, (zd*)hs, p.no, p.nk,
+                     h0 ? block_scratch + 4096 : nullptr);
   hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, (const double*)block_scratch, int(blocks), d_out);
   return hipGetLastError();
 }

@@ -158,8 +158,13 @@ hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStre
 // converged).  chain = begin + steps + final (graph-capturable).
 // track = 1: a state's search, whose start moves with the mean diagonal of H since its previous search (scal[10]);
 // set = 1: scal[0..1] = (mu0, nt) first (the host's start point as kernel arguments, no copy)
+// dpart (optional): dnblk block sums of the diagonal of h_k already at hand (from a14); the Gershgorin pass is then
+// skipped, and a start that is not finite is reported as status 1 instead of replaced by the Gershgorin centre
 hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
-                                int track, hipStream_t s, int set = 0, double mu0 = 0.0, double nt = 0.0);
+                                int track, hipStream_t s, int set = 0, double mu0 = 0.0, double nt = 0.0,
+                                const double* dpart = nullptr, int dnblk = 0);
+// number of the diagonal block sums a14 leaves for the search (one per 64 static entries)
+inline int dyson_g_diag_blocks(const Plan& p) { return int((int64_t(p.no) * p.no * p.nk + 63) / 64); }
 // doubles of partial sums one chemical-potential search on plan p uses (start and evaluations)
 int dyson_g_partials_needed(const Plan& p);
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
@@ -174,13 +179,14 @@ hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_
                                 const double* extra = nullptr, int steps = 0, int* fail_word = nullptr);
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, int steps, int* fail_word,
-                                hipStream_t s);
+                                hipStream_t s, const double* dpart = nullptr, int dnblk = 0);
 hipError_t launch_slab_to_matrix_static(const Plan& p, const void* in, void* out, hipStream_t s);
 hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b, void* out,
                       hipStream_t s);
 // d_sigma = max |(hf_new + c_new) - (hf_old + c_old)| (non-finite entries count as +inf); then optional mixing
 // new <- old + alpha (new - old), and old <- new; with h0 also hs = h0 + (mixed) hf_new.  block_scratch holds up to
-// 4096 block maxima of 64 static entries (n_o^2 N_k <= 262144).
+// 4096 block maxima of 64 static entries (n_o^2 N_k <= 262144), and with h0, at block_scratch + 4096, the blocks'
+// sums of the diagonal of hs (dyson_g_diag_blocks of them): the mean level a state's next search starts from.
 hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* hf_old,
                                 void* c_old, double alpha, double* d_out, double* block_scratch,
                                 hipStream_t s, const void* h0 = nullptr, void* hs = nullptr);
