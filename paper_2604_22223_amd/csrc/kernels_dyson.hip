@@ -321,8 +321,9 @@ __device__ __forceinline__ void gj25_all(cpx<T> (&x)[3][7], cpx<T>& y, int (&cs)
 // VALU rate and the 32 x 32 x 28 padding costs 1.8x the product's flops: measured at 24 x 24, r = 53 it takes
 // 0.46 ms (FP64) and 0.27 ms (FP32) against 0.42 and 0.25 for the VALU product, so it is an autotuner
 // alternative and not the default.
+// FP32 asks for five waves per SIMD: its elimination fits 96 VGPRs without spills (97 by default, four waves)
 template <typename T, bool ADJ = false, bool MVP = false>
-__global__ __launch_bounds__(64) void k_dyson_w25(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_dyson_w25(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
                                                   cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld,
                                                   int* __restrict__ cond, const cpx<T>* __restrict__ rhs = nullptr) {
   constexpr int NB = W25::NB, NN = NB * NB, NS = W25::NS, NT = W25::NT, CH = W25::CH, NCH = W25::NCH;
