@@ -144,9 +144,22 @@ def cpu_baseline(w, min_seconds=10.0, max_iter=8):
         st = gw.gw_iteration(m, d, st)
         k += 1
     dt = time.perf_counter() - t0
-    return {"value": k / dt, "unit": "GW iterations/sec", "cores": int(threads), "kind": "oracle",
-            "sample": "the first %d GW iterations from G0 of the same 24x24 five-orbital workload "
-                      "(NumPy FP64, %s BLAS threads, %d host CPUs visible), %.1f s" % (k, threads, os.cpu_count(), dt)}
+    res = {"value": k / dt, "unit": "GW iterations/sec", "cores": int(threads), "kind": "oracle",
+           "sample": "the first %d GW iterations from G0 of the same 24x24 five-orbital workload "
+                     "(NumPy FP64, %s BLAS threads, %d host CPUs visible), %.1f s" % (k, threads, os.cpu_count(), dt)}
+    # the same oracle on one thread: the first two iterations from G0 with every BLAS pool limited to one thread
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        return res
+    st = gw.initial_state(m, d)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for _ in range(2):
+            st = gw.gw_iteration(m, d, st)
+        dt1 = time.perf_counter() - t0
+    res["single_thread"] = {"value": 2 / dt1, "cores": 1, "sample": "the first 2 GW iterations from G0, %.1f s" % dt1}
+    return res
 
 
 def solve(st, mode, tol, max_iter=60):

@@ -63,7 +63,7 @@ __host__ __device__ __forceinline__ T norm2(cpx<T> a) {
   return a.re * a.re + a.im * a.im;
 }
 // x if finite, else +inf: a max-reduction through fmax then keeps NaNs visible
-__host__ __device__ __forceinline__ double finite_or_inf(double x) { return isfinite(x) ? x : INFINITY; }
+__host__ __device__ __forceinline__ double finite_or_inf(double x) { return __builtin_isfinite(x) ? x : INFINITY; }
 // 1 / a
 template <typename T>
 __host__ __device__ __forceinline__ cpx<T> inv(cpx<T> a) {
