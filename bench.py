@@ -490,7 +490,9 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
         t1 = time.perf_counter()
         pl.autotune()
         t_tune += time.perf_counter() - t1
-        st = qgw.State(pl, flat(w["H_R"]), flat(w["V_R"]), n_target=w["n_target"])
+        # linear mixing 0.5: at U up to 6 eV many sweep instances oscillate undamped, so that the solves of the
+        # batch reach a fixed point (the per-sweep rates do not depend on it)
+        st = qgw.State(pl, flat(w["H_R"]), flat(w["V_R"]), n_target=w["n_target"], mixing=0.5)
         st.init_g0()
         plans.append(pl)
         states.append(st)
@@ -499,7 +501,8 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
     log("[bench] batch: %d instances built in %.1f s (autotuning %.1f s)" % (count, setup, t_tune))
     res = {"instances": count, "launches": launches, "setup_s": round(setup, 2), "autotune_s": round(t_tune, 2),
            "mu_steps_per_iteration": mu_steps,
-           "recipe": "workloads.batch_sweep(%d): n_o 1-5, meshes 12^2-48^2, beta 10-100/eV, U 1-6 eV" % count,
+           "recipe": "workloads.batch_sweep(%d): n_o 1-5, meshes 12^2-48^2, beta 10-100/eV, U 1-6 eV; mixing 0.5"
+                     % count,
            "legs": "each leg restarts every instance from G0 and times iterations 2 .. launches + 1 (one untimed)"}
 
     def restart():
@@ -561,6 +564,33 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
         log("[bench] batch %s: %.4f s per sweep (%d unconverged mu searches, at most %d evaluations)"
             % (name, el / launches, int(np.count_nonzero(status)), int(evs.max())))
         b.close()
+    # solves to the tolerance from G0: FP64 replays alone, and the mixed schedule (FP32 replays until every
+    # instance is at the switch tolerance or stalled, then FP64 replays); per instance the time at which its
+    # max |Delta Sigma| first met the tolerance after an FP64 replay
+    tol = _TOL[0]
+    b64 = qgw.Batch(states, precision=qgw.F64, n_iter=1, mu_steps=mu_steps)
+    b32 = qgw.Batch(states, precision=qgw.F32, n_iter=1, mu_steps=mu_steps)
+    runs = {}
+    for name, kw in (("solve_fp64", {}), ("solve_mixed", {"b32": b32, "switch_tol": switch_tol()})):
+        restart()
+        runs[name] = qgw.batch_solve(b64, tol, max_replays=100, **kw)
+    b32.close()
+    b64.close()
+    both = np.ones(count, dtype=bool)
+    for r in runs.values():
+        both &= r["fp64_replays_to_tol"] >= 0
+    for name, r in runs.items():
+        conv = r["fp64_replays_to_tol"] >= 0
+        t = r["seconds_to_tol"][both]
+        res[name] = {"tol": tol, "converged_instances": int(conv.sum()), "fp32_replays": int(r["fp32_replays"]),
+                     "fp64_replays": int(r["fp64_replays"]), "failed_searches": int(np.count_nonzero(r["status"])),
+                     "instances_converged_in_both_solves": int(both.sum()),
+                     "median_s_to_tol_over_those": round(float(np.median(t)), 4) if both.any() else None,
+                     "s_until_the_last_of_those": round(float(t.max()), 4) if both.any() else None}
+        log("[bench] batch %s: %d of %d instances at |dSigma| <= %.0e (%d FP32 + %d FP64 replays); over the %d "
+            "converged in both solves: median %s s, last %s s"
+            % (name, int(conv.sum()), count, tol, r["fp32_replays"], r["fp64_replays"], int(both.sum()),
+               res[name]["median_s_to_tol_over_those"], res[name]["s_until_the_last_of_those"]))
     for st in states:
         st.close()
     for pl in plans:

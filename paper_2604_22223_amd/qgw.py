@@ -535,6 +535,46 @@ class State:
         return out
 
 
+def batch_solve(b64, tol, b32=None, switch_tol=None, max_replays=60):
+    """Replays batches until every state's max |Delta Sigma| <= tol after an FP64 replay, or max_replays.
+
+    Host control only: each replay is one of the library's captured graphs.  With ``b32`` (an FP32 batch over the
+    same states) the FP32 replays come first, until every state is at ``switch_tol`` or stalled (its |Delta Sigma|
+    is not below half its best so far, which also ends the phase for a state that oscillates), the batch form of a
+    state's mixed schedule (qgw_state_set_precision mode 1).
+    Returns a dict: per state the FP64 replay count at which it first met tol (-1 if never) and the seconds since
+    the first replay at that point (nan if never), the FP32 and FP64 replay counts, and the final statuses."""
+    import time
+    n = len(b64.states)
+    at = np.full(n, -1, dtype=np.int64)
+    t_at = np.full(n, np.nan)
+    n32 = n64 = 0
+    best = None
+    phase32 = b32 is not None
+    statuses = np.zeros(n, dtype=np.int32)
+    t0 = time.perf_counter()
+    for _ in range(max_replays):
+        b = b32 if phase32 else b64
+        b.launch()
+        ds, _, st = b.read()
+        now = time.perf_counter() - t0
+        statuses = np.maximum(statuses, st)
+        if phase32:
+            n32 += 1
+            if best is not None and np.all((ds <= switch_tol) | (ds > 0.5 * best)):
+                phase32 = False
+            best = ds if best is None else np.minimum(best, ds)
+            continue
+        n64 += 1
+        hit = (at < 0) & (ds <= tol)
+        at[hit] = n64
+        t_at[hit] = now
+        if np.all(at >= 0):
+            break
+    return {"fp64_replays_to_tol": at, "seconds_to_tol": t_at, "fp32_replays": n32, "fp64_replays": n64,
+            "status": statuses}
+
+
 class Batch:
     """Many started states advanced together by one graph launch (qgw_batch_*)."""
 

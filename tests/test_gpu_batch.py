@@ -192,3 +192,40 @@ def test_batch_rejects_uniform_grid_states(insts):
     assert e.value.status == 3
     st.close()
     p.close()
+
+
+def test_batched_mixed_schedule_reaches_the_fixed_point(insts):
+    """Solves of four 2-D instances in one batch from G0 to max |Delta Sigma| <= 1e-9: FP32 graph replays until
+    every instance is at 3e-9 or stalled, then FP64 replays.  Every end point is the oracle's FP64 fixed point
+    (converged to 1e-11) within the mixed schedule's 1e-6, and the FP64-only replays land on it too."""
+    torch = _torch()
+    sel = [insts[k] for k in (0, 1, 3, 4)]
+    refs = []
+    for inst in sel:
+        w = inst.w
+        m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
+        ref, hist = gw.scf(m, inst.d, tol=1e-11, max_iter=200)
+        assert hist[-1][0] <= 1e-11
+        refs.append(ref)
+    for mixed in (True, False):
+        states = [inst.state() for inst in sel]
+        b64 = qgw.Batch(states, precision=qgw.F64, n_iter=1, mu_steps=16)
+        b32 = qgw.Batch(states, precision=qgw.F32, n_iter=1, mu_steps=16) if mixed else None
+        print("[batch] batched solve, mixed=%s" % mixed, flush=True)
+        r = qgw.batch_solve(b64, 1e-9, b32=b32, switch_tol=3e-9, max_replays=120)
+        torch.cuda.synchronize()
+        assert np.all(r["fp64_replays_to_tol"] >= 0), r
+        assert np.all(r["status"] == 0)
+        if mixed:
+            assert r["fp32_replays"] >= 2
+        for st, ref in zip(states, refs):
+            sig = st.array(1).cpu().numpy()
+            sref = ref["sig_iw"].reshape(sig.shape)
+            assert np.max(np.abs(sig - sref)) <= 1e-6 * max(1.0, np.max(np.abs(sref)))
+            hf = st.array(2).cpu().numpy()
+            assert np.max(np.abs(hf - ref["sig_hf_k"].reshape(hf.shape))) <= 1e-6
+        for b in (b64, b32):
+            if b is not None:
+                b.close()
+        for st in states:
+            st.close()
