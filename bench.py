@@ -534,6 +534,7 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
     for key, mode in (("fp64", 0), ("fp32", 2)):
         for st in states:
             st.set_precision(mode)
+            st.profile_select(None, in_line=True)      # a12 in line: every step's time is its own
             st.profile(1)
             st.iterate(1)
         torch.cuda.synchronize()
@@ -542,6 +543,7 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
             ms, _ = st.profile(2)
             tot += sum(ms.values())
             st.profile(0)
+            st.profile_select(None, in_line=False)
         res["step_time_sum_%s_s_per_sweep" % key] = round(tot / 1e3, 5)
     log("[bench] batch: summed step time per sweep %.4f s (FP64), %.4f s (FP32)"
         % (res["step_time_sum_fp64_s_per_sweep"], res["step_time_sum_fp32_s_per_sweep"]))
@@ -673,23 +675,17 @@ def main():
     for v in solves.values():
         del v["sigma"]
 
-    # plain FP64 and chosen (mixed) schedules: W untimed, then exactly K timed iterations each
-    timed = {}
-    for name, mode in (("fp64", 0), ("mixed", 1)):
-        timed_solves(torch, st, mode, a.tol, a.warmup)
-        st.profile(1)
-        el = timed_solves(torch, st, mode, a.tol, a.steps)
-        timed[name] = {"elapsed": el, "prof": st.profile(0, per_precision=True)}
-        log("[bench] %-5s: %d timed iterations in %.4f s: %.3f ms/iteration, %.1f iterations/s"
-            % (name, a.steps, el, 1e3 * el / a.steps, a.steps / el))
-    value = a.steps / timed["mixed"]["elapsed"]
-    ms_per_step = 1e3 * timed["mixed"]["elapsed"] / a.steps
-    value64 = a.steps / timed["fp64"]["elapsed"]
-
-    # per-step roofline over the chosen schedule's timed region, by precision
+    # per-step breakdown of the chosen schedule: a pass of its own (same length), with a12 on the caller's stream
+    # ahead of a1 so that every step's time is its own
+    timed_solves(torch, st, 1, a.tol, a.warmup)
+    st.profile_select(None, in_line=True)
+    st.profile(1)
+    el_detail = timed_solves(torch, st, 1, a.tol, a.steps)
+    detail = st.profile(0, per_precision=True)
+    log("[bench] step breakdown pass (every step timed, a12 in line): %.3f ms/iteration" % (1e3 * el_detail / a.steps))
     steps, totals = {}, {}
     for prec in ("f64", "f32"):
-        ms_tot, iters = timed["mixed"]["prof"][prec]
+        ms_tot, iters = detail[prec]
         if iters == 0:
             continue
         model = step_model(plan.r, plan.n_o, plan.n_b, plan.n_k, prec)
@@ -704,10 +700,35 @@ def main():
                 % (key, tot / iters, iters, steps[key]["bound"], steps[key]["achieved"], steps[key]["unit"],
                    100 * steps[key]["frac"]))
     dom = max(totals, key=totals.get)
-    dd = steps[dom]
+    dom_step, dom_prec = dom.split(":")
+
+    # plain FP64 and chosen (mixed) schedules: W untimed, then exactly K timed iterations each, with HIP events
+    # around the dominant step only (two per iteration)
+    timed = {}
+    for name, mode in (("fp64", 0), ("mixed", 1)):
+        timed_solves(torch, st, mode, a.tol, a.warmup)
+        st.profile_select([dom_step], in_line=False)
+        st.profile(1)
+        el = timed_solves(torch, st, mode, a.tol, a.steps)
+        timed[name] = {"elapsed": el, "prof": st.profile(0, per_precision=True)}
+        log("[bench] %-5s: %d timed iterations in %.4f s: %.3f ms/iteration, %.1f iterations/s"
+            % (name, a.steps, el, 1e3 * el / a.steps, a.steps / el))
+    st.profile_select(None, in_line=False)
+    value = a.steps / timed["mixed"]["elapsed"]
+    ms_per_step = 1e3 * timed["mixed"]["elapsed"] / a.steps
+    value64 = a.steps / timed["fp64"]["elapsed"]
+
+    # the dominant kernel's roofline from the events inside the chosen schedule's timed region
+    ms_tot, iters = timed["mixed"]["prof"][dom_prec]
+    model = step_model(plan.r, plan.n_o, plan.n_b, plan.n_k, dom_prec)
+    kprec = "f64" if dom_step in FP64_STEPS else dom_prec
+    dd = roof(model[dom_step], kprec, ms_tot[dom_step] / iters)
+    log("[bench] dominant step %s: %.4f ms x %d in the timed region (%.4f ms in the breakdown pass)"
+        % (dom, dd["ms"], iters, steps[dom]["ms"]))
     roofline = {"bound": dd["bound"], "achieved": dd["achieved"], "peak": dd["peak"], "unit": dd["unit"],
-                "frac": dd["frac"], "traffic": dd["traffic"], "kernel": dom,
-                "per_launch": dict(dd["per_launch"], ms=dd["ms"])}
+                "frac": dd["frac"], "traffic": MEASURED_TRAFFIC.get(dom), "kernel": dom,
+                "per_launch": {"bytes": model[dom_step]["bytes"], "flops": model[dom_step]["flops"], "ms": dd["ms"],
+                               "launches_timed": iters}}
 
     _, mu_conv = solve(st, 1, a.tol)           # a converged state for the post-processing leg
     qpl = quasiparticle_leg(torch, qgw, plan, st, H_R, mu_conv)
@@ -764,6 +785,8 @@ def main():
         "paper_workload": paper,
         "uniform_grid": mf,
         "steps_detail": steps,
+        "steps_detail_pass": {"iterations": a.steps, "schedule": "chosen", "a12": "in line (caller's stream)",
+                              "ms_per_iteration": round(1e3 * el_detail / a.steps, 4)},
     }
     print(json.dumps(out), flush=True)
     st.close()

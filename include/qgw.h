@@ -575,14 +575,16 @@ qgw_status qgw_state_info(qgw_state state, int32_t *last_prec, int32_t *n_fp32, 
                           int32_t *mu_evals);
 
 /* Per-step timing of qgw_gw_iteration with HIP events on the caller's
- * stream (step 0 on the state's second stream, where a12 runs concurrently
- * with steps 1-8; it joins the caller's stream before step 9, so the steps'
- * times add up to more than the iteration's span by about step 0's).
- * mode 1 resets the accumulators and enables timing, mode 0
+ * stream.  By default every step is timed and step 0 runs on the state's
+ * second stream, concurrently with steps 1-8 (it joins the caller's stream
+ * before step 9), so its time is the span from its start to its end while
+ * sharing the GPU; qgw_state_profile_select can time fewer steps or run
+ * step 0 in line.  mode 1 resets the accumulators and enables timing, mode 0
  * disables it, mode 2 only reads.  ms[2 * QGW_NUM_STEPS] (may be NULL)
  * receives the accumulated milliseconds per step, first over the FP64
- * iterations, then over the FP32 ones; iters[2] (may be NULL) the number of
- * timed FP64 and FP32 iterations.  Steps, in launch order:
+ * iterations, then over the FP32 ones (0 for steps not timed); iters[2]
+ * (may be NULL) the number of timed FP64 and FP32 iterations.  Steps, in
+ * launch order:
  *   0 a12  density n = -G(beta^-), Hartree-Fock      1 a1  G(tau), G(beta - tau)
  *   2 a2   k -> R of both                             3 a3+a4 bubble, R -> q
  *   4 a5   P: tau -> i nu (to the matrix layout)      5 a6  Dyson W
@@ -591,6 +593,16 @@ qgw_status qgw_state_info(qgw_state state, int32_t *last_prec, int32_t *n_fp32, 
  *  10 a13  Dyson G with the chemical-potential search */
 #define QGW_NUM_STEPS 11
 qgw_status qgw_state_profile(qgw_state state, int32_t mode, double *ms, int32_t *iters);
+
+/* What qgw_state_profile times from its next mode-1 call on: bit i of
+ * step_mask selects step i (events are recorded only at the boundaries of
+ * selected steps, two per step at most, so a mask of one step costs two
+ * events per iteration); in_line != 0 runs step 0 (a12) on the caller's
+ * stream ahead of step 1 while timing is enabled, so that every step's time
+ * is its own and their sum is the iteration's span.  Default: all steps
+ * (0x7FF), step 0 concurrent.  Bits at or above QGW_NUM_STEPS are rejected
+ * with QGW_ERR_INVALID_ARG. */
+qgw_status qgw_state_profile_select(qgw_state state, uint32_t step_mask, int32_t in_line);
 
 /* ---------------------------------------------------------------- batches
  *

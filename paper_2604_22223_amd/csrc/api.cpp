@@ -65,8 +65,13 @@ struct qgw_state_s {
   bool broken = false;
   // per-step timing with HIP events on the caller's stream
   bool prof = false;
-  hipEvent_t ev[QGW_NUM_STEPS + 1] = {};
-  hipEvent_t ev_a12 = nullptr;  // end of a12 on the side stream (its start is ev[0], recorded there)
+  // two sets of step events, used by alternate iterations: one iteration's times are read after the next one
+  // has been queued, so the reads do not hold up the GPU
+  hipEvent_t ev[2][QGW_NUM_STEPS + 1] = {};
+  hipEvent_t ev_a12[2] = {};  // end of a12 on the side stream (its start is ev[set][0], recorded there)
+  int ev_set = 0;
+  uint32_t prof_mask = (1u << QGW_NUM_STEPS) - 1;  // steps timed
+  bool prof_in_line = false;                       // a12 on the caller's stream while timing
   double prof_ms[2][QGW_NUM_STEPS] = {};  // [FP64, FP32 iterations][step]
   int prof_iters[2] = {};
 };
@@ -1248,10 +1253,12 @@ qgw_status qgw_sync_status(qgw_plan h, void* stream) {
 // ------------------------------------------------------------------ state
 
 static void free_state(qgw_state st) {
-  for (auto& e : st->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& set : st->ev)
+    for (auto& e : set)
+      if (e) (void)hipEventDestroy(e);
   if (st->ev_io) (void)hipEventDestroy(st->ev_io);
-  if (st->ev_a12) (void)hipEventDestroy(st->ev_a12);
+  for (auto& e : st->ev_a12)
+    if (e) (void)hipEventDestroy(e);
   if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
   if (st->ev_join) (void)hipEventDestroy(st->ev_join);
   if (st->side) (void)hipStreamDestroy(st->side);
@@ -1428,24 +1435,32 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
   const int64_t ncol_g = no2 * p.nk;
   st->p32.tune = p.has_tune32 ? p.tune32 : p.tune;
   hipError_t e = hipSuccess;
-  auto mark = [&](int i) { if (e == hipSuccess && prof) e = hipEventRecord(st->ev[i], s); };
+  hipEvent_t* ev = st->ev[st->ev_set];
+  const uint32_t m = prof ? st->prof_mask : 0u;
+  if (prof && st->prof_in_line) fork = false;
+  // boundary i opens step i and closes step i - 1 (steps 1 .. 10; step 0 has events of its own)
+  auto mark = [&](int i) {
+    if (e == hipSuccess && (((m >> i) & 1u) || (i >= 2 && ((m >> (i - 1)) & 1u)))) e = hipEventRecord(ev[i], s);
+  };
   auto run = [&](hipError_t r) { if (e == hipSuccess) e = r; };
   // a12: density of the incoming G (Hermitian part), Hartree-Fock.  It reads only G and writes only n and
-  // Sigma_HF, which a14 and a13 use: in an eager iteration it runs on the state's side stream beside a1..a11 and
-  // joins before a14, so its small, latency-bound launches overlap the pair-array steps instead of adding to them.
-  // A batch capture keeps it on the worker stream (a fork from an already forked stream is not recorded).
-  hipStream_t a = fork ? st->side : s;
-  if (fork) {
+  // Sigma_HF, which a14 and a13 use.  In an eager iteration it runs on the state's side stream beside a1..a11 and
+  // joins before a14, so its small, latency-bound launches overlap the pair-array steps instead of adding to them;
+  // the pair-array steps are queued first, so the caller's stream has work as soon as the iteration starts, and
+  // a12 waits for G through an event recorded ahead of them.  A batch capture keeps a12 on the worker stream, in
+  // front (a fork from an already forked stream is not recorded).
+  auto a12 = [&](hipStream_t a) {
+    if (e == hipSuccess && (m & 1u)) e = hipEventRecord(ev[0], a);
+    run(launch_dlr(p, QGW_F_IW2BETA, ncol_g, -1.0, 0.0, st->G_iw, st->n_k, a, 2));
+    run(launch_lattice_fft(p, QGW_K_TO_R, no2, st->n_k, st->n_R, a));
+    run(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, a));
+    run(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, a));
+    if (e == hipSuccess && (m & 1u)) e = hipEventRecord(st->ev_a12[st->ev_set], a);
+  };
+  if (fork)
     run(hipEventRecord(st->ev_fork, s));
-    run(hipStreamWaitEvent(a, st->ev_fork, 0));
-  }
-  if (e == hipSuccess && prof) e = hipEventRecord(st->ev[0], a);
-  run(launch_dlr(p, QGW_F_IW2BETA, ncol_g, -1.0, 0.0, st->G_iw, st->n_k, a, 2));
-  run(launch_lattice_fft(p, QGW_K_TO_R, no2, st->n_k, st->n_R, a));
-  run(launch_hartree_fock(p, st->V_R, st->V_q0, st->n_R, st->SigHF_R, a));
-  run(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, a));
-  if (e == hipSuccess && prof) e = hipEventRecord(st->ev_a12, a);
-  if (fork) run(hipEventRecord(st->ev_join, a));
+  else
+    a12(s);
   if (!f32) {
     mark(1);  // a1
     if (p.grid == kGridMF) {
@@ -1489,6 +1504,11 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     run(launch_dlr(q, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->St32, st->Siw32, s, 1));
     run(launch_convert(ncol_g * p.r, st->Siw32, st->Sig_iw, 0, s));
   }
+  if (fork) {
+    run(hipStreamWaitEvent(st->side, st->ev_fork, 0));
+    a12(st->side);
+    run(hipEventRecord(st->ev_join, st->side));
+  }
   // a14 and the static part of a13 (H0 + Sigma_HF) in one pass, once a12 has joined
   if (fork) run(hipStreamWaitEvent(s, st->ev_join, 0));
   mark(9);
@@ -1509,21 +1529,43 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
   hipStream_t s = (hipStream_t)stream;
   double dsig = NAN;
   int done = 0;
+  // step times of the last finished iteration (event set `pend`, -1: none), read once the next iteration is queued
+  int pend = -1;
+  bool pend_f32 = false;
+  auto read_times = [&]() -> hipError_t {
+    if (pend < 0) return hipSuccess;
+    const hipEvent_t* ev = st->ev[pend];
+    float ms[QGW_NUM_STEPS] = {};
+    for (int i = 0; i < QGW_NUM_STEPS; ++i) {
+      if (!((st->prof_mask >> i) & 1u)) continue;
+      // step 0 (a12) runs from ev[0] to ev_a12
+      const hipError_t e = hipEventElapsedTime(&ms[i], ev[i], i == 0 ? st->ev_a12[pend] : ev[i + 1]);
+      if (e != hipSuccess) return e;
+    }
+    for (int i = 0; i < QGW_NUM_STEPS; ++i) st->prof_ms[pend_f32 ? 1 : 0][i] += ms[i];
+    ++st->prof_iters[pend_f32 ? 1 : 0];
+    pend = -1;
+    return hipSuccess;
+  };
   for (int it = 0; it < n_iter; ++it) {
     const bool f32 = st->prec_mode == 2 || (st->prec_mode == 1 && st->in_fp32);
+    st->ev_set = pend == 0 ? 1 : 0;
     const hipError_t qe = enqueue_steps(st, f32, st->prof, s, true);
     if (qe != hipSuccess) {
       st->broken = true;
       set_error(std::string("qgw_gw_iteration: ") + hipGetErrorString(qe));
       return QGW_ERR_DEVICE;
     }
+    QGW_CHECK_HIP(read_times(), "profile");
     // a13: Dyson G with the chemical potential
     // |dSigma| (a14, already enqueued) comes back with the search's result: one wait per iteration
     // the first round queues the previous search's evaluation count + 2 Newton steps (3 .. 12; 10 after G0)
     double m = st->mu, evals = 0.0;
     qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, &evals, st->d_scal,
                                 st->d_part, st->d_stat, st->d_dsig, &dsig,
-                                st->prof ? st->ev[QGW_NUM_STEPS] : nullptr, st->mu_steps0, st->h_io, st->ev_io, 1,
+                                st->prof && ((st->prof_mask >> 10) & 1u) ? st->ev[st->ev_set][QGW_NUM_STEPS] : nullptr,
+                                st->mu_steps0, st->h_io,
+                                st->ev_io, 1,
                                 st->d_blockmax + 4096, dyson_g_diag_blocks(p));
     st->last_evals = int(evals);
     // a singular Dyson-W system or a non-finite self-energy is named as the cause, also of a failed search
@@ -1548,13 +1590,8 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     st->mu = m;
     st->mu_steps0 = std::min(12, std::max(3, int(evals) + 2));
     if (st->prof) {
-      for (int i = 0; i < QGW_NUM_STEPS; ++i) {
-        // step 0 (a12) ran on the side stream, from ev[0] to ev_a12
-        float ms = 0.0f;
-        QGW_CHECK_HIP(hipEventElapsedTime(&ms, st->ev[i], i == 0 ? st->ev_a12 : st->ev[i + 1]), "profile");
-        st->prof_ms[f32 ? 1 : 0][i] += ms;
-      }
-      ++st->prof_iters[f32 ? 1 : 0];
+      pend = st->ev_set;
+      pend_f32 = f32;
     }
     ++done;
     st->last_prec = f32 ? 1 : 0;
@@ -1568,6 +1605,7 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     st->last_dsig = dsig;
     if (dsig <= tol && !(st->prec_mode != 0 && f32)) break;
   }
+  QGW_CHECK_HIP(read_times(), "profile");
   if (iters_done) *iters_done = done;
   if (d_sigma) *d_sigma = dsig;
   if (mu_out) *mu_out = st->mu;
@@ -1744,14 +1782,26 @@ qgw_status qgw_state_copy(qgw_state st, int32_t which, void* dst, int64_t* bytes
   return QGW_OK;
 }
 
+qgw_status qgw_state_profile_select(qgw_state st, uint32_t step_mask, int32_t in_line) {
+  QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_profile_select: null state");
+  QGW_REQUIRE((step_mask >> QGW_NUM_STEPS) == 0u, QGW_ERR_INVALID_ARG,
+              "qgw_state_profile_select: step_mask has bits past the last step");
+  QGW_REQUIRE(!st->prof, QGW_ERR_INVALID_ARG, "qgw_state_profile_select: disable timing first (mode 0)");
+  st->prof_mask = step_mask;
+  st->prof_in_line = in_line != 0;
+  return QGW_OK;
+}
+
 qgw_status qgw_state_profile(qgw_state st, int32_t mode, double* ms, int32_t* iters) {
   QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_profile: null state");
   QGW_REQUIRE(mode >= 0 && mode <= 2, QGW_ERR_INVALID_ARG, "qgw_state_profile: bad mode");
   QGW_CHECK_HIP(enter_device(st->plan->p.device), "hipSetDevice");
   if (mode == 1) {
-    for (auto& e : st->ev)
+    for (auto& set : st->ev)
+      for (auto& e : set)
+        if (!e) QGW_CHECK_HIP(hipEventCreate(&e), "qgw_state_profile");
+    for (auto& e : st->ev_a12)
       if (!e) QGW_CHECK_HIP(hipEventCreate(&e), "qgw_state_profile");
-    if (!st->ev_a12) QGW_CHECK_HIP(hipEventCreate(&st->ev_a12), "qgw_state_profile");
     for (auto& row : st->prof_ms)
       for (double& v : row) v = 0.0;
     st->prof_iters[0] = st->prof_iters[1] = 0;

@@ -31,7 +31,7 @@ R_TO_K, K_TO_R = -1, +1
 EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get_map", "qgw_plan_sizes",
            "qgw_dlr_transform", "qgw_dlr_transform_pairs", "qgw_lattice_fft", "qgw_bubble", "qgw_dyson_W",
            "qgw_sigma", "qgw_hartree_fock", "qgw_dyson_G", "qgw_state_create", "qgw_state_destroy",
-           "qgw_state_init_g0", "qgw_gw_iteration", "qgw_state_copy", "qgw_state_profile",
+           "qgw_state_init_g0", "qgw_gw_iteration", "qgw_state_copy", "qgw_state_profile", "qgw_state_profile_select",
            "qgw_state_set_precision", "qgw_state_info", "qgw_check_finite",
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
@@ -94,6 +94,7 @@ def lib():
             "qgw_gw_iteration": [vp, i32, dbl, pi32, pd, pd, vp],
             "qgw_state_copy": [vp, i32, vp, pi64, vp],
             "qgw_state_profile": [vp, i32, pd, pi32],
+            "qgw_state_profile_select": [vp, ctypes.c_uint32, i32],
             "qgw_state_set_precision": [vp, i32, dbl],
             "qgw_state_info": [vp, pi32, pi32, pi32, pi32],
             "qgw_check_finite": [vp, vp, i64, vp],
@@ -505,6 +506,15 @@ class State:
         if per_precision:
             return rows
         return dict(zip(self.STEP_NAMES, (ms[:ns] + ms[ns:]).tolist())), it[0] + it[1]
+
+    def profile_select(self, steps=None, in_line=False):
+        """Steps the next profile(1) times (names from STEP_NAMES, None: all) and whether a12 then runs on the
+        caller's stream ahead of a1 (qgw_state_profile_select)."""
+        names = self.STEP_NAMES if steps is None else list(steps)
+        mask = 0
+        for n in names:
+            mask |= 1 << self.STEP_NAMES.index(n)
+        _check(lib().qgw_state_profile_select(self.handle, mask, 1 if in_line else 0))
 
     def set_precision(self, mode, switch_tol=1e-4):
         """mode 0: FP64 throughout; 1: FP32 bulk steps until |dSigma| <= switch_tol, then FP64."""

@@ -1,0 +1,91 @@
+"""Step timing of the GW iteration (qgw_state_profile, qgw_state_profile_select).
+
+Timing changes where a12 is queued (the state's second stream, or the caller's stream ahead of a1) and which
+events are recorded; the kernels and their inputs stay the same, so the state after a few iterations must be
+bitwise equal with and without timing, in both precisions.  A selection times its steps only.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2604_22223_amd import qgw
+from paper_2604_22223_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def flat(x):
+    return np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))
+
+
+@pytest.fixture(scope="module")
+def case():
+    torch = _torch()
+    print("\n[profile case] five orbitals, 8 x 8, beta = 20", flush=True)
+    w = wl.five_orbital(n=8, U=1.0, J=0.1, Vnn=0.2, beta=20.0, omega_max=25.0, eps=1e-10, scale_mesh=8)
+    nodes = qgw.dlr_build(w["beta"] * w["omega_max"], w["eps"])
+    nodes["omega"] = nodes["x"] / w["beta"]
+    plan = qgw.Plan.from_nodes(8, w["site_norb"], w["beta"], nodes)
+    st = qgw.State(plan, torch.from_numpy(flat(w["H_R"])).to("cuda:0"),
+                   torch.from_numpy(flat(w["V_R"])).to("cuda:0"), n_target=w["n_target"])
+    yield st
+    st.close()
+    plan.close()
+
+
+def _run(st, per_call):
+    """Two FP32 iterations from G0, then two FP64 ones, per_call iterations per call."""
+    torch = _torch()
+    st.set_precision(2, 1e-3)
+    st.init_g0()
+    for prec in (2, 0):
+        st.set_precision(prec, 1e-3)
+        for _ in range(2 // per_call):
+            st.iterate(per_call)
+    torch.cuda.synchronize()
+    _, n32, n64 = st.info()
+    return [st.array(k).cpu().numpy().copy() for k in (0, 1, 2)], (n32, n64)
+
+
+@pytest.mark.parametrize("per_call", [2, 1])
+def test_timing_leaves_the_iteration_bitwise_unchanged(case, per_call):
+    st = case
+    ref, counts = _run(st, per_call)
+    assert counts == (2, 2), counts
+    names = st.STEP_NAMES
+    for steps, in_line in ((None, True), (["a6_dyson_w"], False), (None, False)):
+        st.profile_select(steps, in_line=in_line)
+        st.profile(1)
+        got, c2 = _run(st, per_call)
+        rows = st.profile(0, per_precision=True)
+        assert c2 == counts
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), (steps, in_line)
+        for prec, n_it in (("f32", counts[0]), ("f64", counts[1])):
+            ms, iters = rows[prec]
+            assert iters == n_it
+            for name in names:
+                if steps is None or name in steps:
+                    assert ms[name] > 0.0, (prec, name)
+                else:
+                    assert ms[name] == 0.0, (prec, name)
+    st.profile_select(None, in_line=False)
+
+
+def test_selection_is_checked(case):
+    st = case
+    L = qgw.lib()
+    assert L.qgw_state_profile_select(st.handle, ctypes.c_uint32(1 << len(st.STEP_NAMES)), 0) != qgw.QGW_OK
+    st.profile(1)
+    with pytest.raises(qgw.QGWError):
+        st.profile_select(["a6_dyson_w"])       # timing is on: select first, then enable
+    st.profile(0)
+    st.profile_select(["a13_dyson_g", "a12_density_hf"], in_line=True)
+    st.profile_select(None, in_line=False)
