@@ -647,7 +647,8 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
                               double* part = nullptr, int* stat = nullptr, const double* extra_src = nullptr,
                               double* extra_dst = nullptr, hipEvent_t end_ev = nullptr, int steps0 = 6,
                               double* h_io = nullptr, hipEvent_t io_ev = nullptr, int track = 0,
-                              const double* dpart = nullptr, int dnblk = 0) {
+                              const double* dpart = nullptr, int dnblk = 0, int* rounds_out = nullptr,
+                              void (*on_queued)(void*) = nullptr, void* on_ctx = nullptr) {
   const int mode = std::isnan(n_target) ? 0 : 1;
   if (!scal) {
     scal = p.d_scalars;
@@ -678,7 +679,9 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
   // scal[0..9]: mu, n_target, evaluations, N_e, search state, status, extra
   double res[10] = {};
   int st = 0;
+  int rounds = 0;
   for (int round = 0;; ++round) {
+    rounds = round + 1;
     // a few Newton evaluations, G at the current mu, one read-back; more rounds only if needed
     const int steps = mode == 1 ? (round == 0 ? steps0 : 16) : 0;
     if (mode == 1)
@@ -689,6 +692,8 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
     if (h_io) {
       QGW_CHECK_HIP(hipMemcpyAsync(h_io, scal, sizeof(res), hipMemcpyDeviceToHost, s), "qgw_dyson_G");
       QGW_CHECK_HIP(hipEventRecord(io_ev, s), "qgw_dyson_G");
+      // work the caller queues behind the read-back (on_queued), so the GPU has it while the host waits
+      if (round == 0 && on_queued) on_queued(on_ctx);
       hipError_t q;
       while ((q = hipEventQuery(io_ev)) == hipErrorNotReady) {
       }
@@ -703,6 +708,7 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
     if (mode == 0 || st != 2 || res[2] >= 200.0) break;
     QGW_CHECK_HIP(hipMemsetAsync(stat, 0, sizeof(int), s), "qgw_dyson_G");
   }
+  if (rounds_out) *rounds_out = rounds;
   if (mode == 1) {
     *mu = res[0];
     if (evals) *evals = res[2];
@@ -1426,10 +1432,33 @@ qgw_status qgw_state_info(qgw_state st, int32_t* last_prec, int32_t* n_fp32, int
   return QGW_OK;
 }
 
+// a1 of an iteration, G(tau) and G(beta - tau), on s; with `fork` first the event that a12 waits on for G.  Queued
+// by enqueue_steps, or ahead of time into event set `set` while the previous iteration's host waits for its search.
+static hipError_t enqueue_a1(qgw_state st, bool f32, bool prof, hipStream_t s, bool fork, int set) {
+  const Plan& p = st->plan->p;
+  const int64_t ncol_g = int64_t(p.no) * p.no * p.nk;
+  hipError_t e = hipSuccess;
+  auto run = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+  if (fork) run(hipEventRecord(st->ev_fork, s));
+  if (prof && (st->prof_mask & 2u)) run(hipEventRecord(st->ev[set][1], s));
+  if (!f32) {
+    if (p.grid == kGridMF) {
+      run(launch_mf_g_tau(p, st->G_iw, st->G_tau, st->G_reflt, s));  // one transform, both time orders
+    } else {
+      run(launch_dlr2(p, QGW_F_IW2TAU, QGW_F_IW2TAUR, ncol_g, st->G_iw, st->G_tau, st->G_reflt, s));
+    }
+  } else {
+    st->p32.tune = p.has_tune32 ? p.tune32 : p.tune;
+    run(launch_convert(ncol_g * p.r, st->G_iw, st->G32, 1, s));
+    run(launch_dlr2(st->p32, QGW_F_IW2TAU, QGW_F_IW2TAUR, ncol_g, st->G32, st->Gt32, st->Gr32, s));
+  }
+  return e;
+}
+
 // a12, a1-a11 (FP64 or single precision), a14 and the static H + Sigma_HF of a13,
 // enqueued on s; with `prof` HIP events mark the step boundaries 0 .. 10.  fork: a12 on the state's side stream
 // (eager iterations); without it (batch capture) everything goes on s.
-static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s, bool fork) {
+static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s, bool fork, bool a1_queued = false) {
   const Plan& p = st->plan->p;
   const int64_t no2 = int64_t(p.no) * p.no;
   const int64_t ncol_g = no2 * p.nk;
@@ -1457,17 +1486,10 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     run(launch_lattice_fft(p, QGW_R_TO_K, no2, st->SigHF_R, st->SigHF_k, a));
     if (e == hipSuccess && (m & 1u)) e = hipEventRecord(st->ev_a12[st->ev_set], a);
   };
-  if (fork)
-    run(hipEventRecord(st->ev_fork, s));
-  else
-    a12(s);
+  // a1_queued: a1 and the fork event are already on s (queued during the previous iteration's wait)
+  if (!fork) a12(s);
+  if (!a1_queued) run(enqueue_a1(st, f32, prof, s, fork, st->ev_set));
   if (!f32) {
-    mark(1);  // a1
-    if (p.grid == kGridMF) {
-      run(launch_mf_g_tau(p, st->G_iw, st->G_tau, st->G_reflt, s));  // one transform, both time orders
-    } else {
-      run(launch_dlr2(p, QGW_F_IW2TAU, QGW_F_IW2TAUR, ncol_g, st->G_iw, st->G_tau, st->G_reflt, s));
-    }
     mark(2);  // a2
     run(launch_lattice_fft2(p, QGW_K_TO_R, no2 * p.r, st->G_tau, st->G_tau, st->G_reflt, st->G_reflt, s));
     mark(3);  // a3 + a4
@@ -1485,9 +1507,6 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
   } else {
     // the same steps in single precision (defect-correction phase of the solve)
     const Plan& q = st->p32;
-    mark(1);
-    run(launch_convert(ncol_g * p.r, st->G_iw, st->G32, 1, s));
-    run(launch_dlr2(q, QGW_F_IW2TAU, QGW_F_IW2TAUR, ncol_g, st->G32, st->Gt32, st->Gr32, s));
     mark(2);
     run(launch_lattice_fft2(q, QGW_K_TO_R, no2 * p.r, st->Gt32, st->Gt32, st->Gr32, st->Gr32, s));
     mark(3);
@@ -1516,6 +1535,25 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
                            st->d_blockmax, s, st->H_k, st->Hs_k));
   mark(10);
   return e;
+}
+
+// The next iteration's a1, queued behind an iteration's search read-back while the host waits for it.  Its
+// precision is the current one; it is kept if the search ended in its first round (G is final) and the next
+// iteration runs in that precision, and queued again otherwise.  A solve that stops there leaves it as the
+// G(tau) of the final G.
+struct NextA1 {
+  qgw_state st;
+  hipStream_t s;
+  bool f32;
+  int set;
+  bool queued;
+  hipError_t err;
+};
+
+static void queue_next_a1(void* c) {
+  NextA1* x = static_cast<NextA1*>(c);
+  x->err = enqueue_a1(x->st, x->f32, x->st->prof, x->s, true, x->set);
+  x->queued = true;
 }
 
 qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* iters_done, double* d_sigma,
@@ -1547,10 +1585,12 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     pend = -1;
     return hipSuccess;
   };
+  bool a1_next = false, a1_next_f32 = false;  // the next iteration's a1 is on s, in that precision
   for (int it = 0; it < n_iter; ++it) {
     const bool f32 = st->prec_mode == 2 || (st->prec_mode == 1 && st->in_fp32);
     st->ev_set = pend == 0 ? 1 : 0;
-    const hipError_t qe = enqueue_steps(st, f32, st->prof, s, true);
+    const hipError_t qe = enqueue_steps(st, f32, st->prof, s, true, a1_next && a1_next_f32 == f32);
+    a1_next = false;
     if (qe != hipSuccess) {
       st->broken = true;
       set_error(std::string("qgw_gw_iteration: ") + hipGetErrorString(qe));
@@ -1561,12 +1601,24 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     // |dSigma| (a14, already enqueued) comes back with the search's result: one wait per iteration
     // the first round queues the previous search's evaluation count + 2 Newton steps (3 .. 12; 10 after G0)
     double m = st->mu, evals = 0.0;
+    // not with a12 timed in line (it must stay ahead of a1), nor past this call's last iteration
+    NextA1 nx{st, s, f32, st->prof ? (st->ev_set ^ 1) : 0, false, hipSuccess};
+    const bool ahead = it + 1 < n_iter && !(st->prof && st->prof_in_line);
+    int rounds = 0;
     qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, &evals, st->d_scal,
                                 st->d_part, st->d_stat, st->d_dsig, &dsig,
                                 st->prof && ((st->prof_mask >> 10) & 1u) ? st->ev[st->ev_set][QGW_NUM_STEPS] : nullptr,
                                 st->mu_steps0, st->h_io,
                                 st->ev_io, 1,
-                                st->d_blockmax + 4096, dyson_g_diag_blocks(p));
+                                st->d_blockmax + 4096, dyson_g_diag_blocks(p), &rounds,
+                                ahead ? queue_next_a1 : nullptr, &nx);
+    if (nx.queued && nx.err != hipSuccess) {
+      st->broken = true;
+      set_error(std::string("qgw_gw_iteration: ") + hipGetErrorString(nx.err));
+      return QGW_ERR_DEVICE;
+    }
+    a1_next = nx.queued && rounds == 1;
+    a1_next_f32 = nx.f32;
     st->last_evals = int(evals);
     // a singular Dyson-W system or a non-finite self-energy is named as the cause, also of a failed search
     if (rc != QGW_ERR_DEVICE && (rc != QGW_OK || !std::isfinite(dsig))) {

@@ -89,3 +89,34 @@ def test_selection_is_checked(case):
     st.profile(0)
     st.profile_select(["a13_dyson_g", "a12_density_hf"], in_line=True)
     st.profile_select(None, in_line=False)
+
+
+def _solve(st, per_call, n, tol):
+    """The mixed schedule from G0 (FP64 once |dSigma| <= 5e-2): n iterations, or to tol, per_call per call."""
+    torch = _torch()
+    st.set_precision(1, 5e-2)
+    st.init_g0()
+    done = 0
+    while done < n:
+        k, ds, _ = st.iterate(min(per_call, n - done), tol)
+        done += k
+        if ds <= tol and st.info()[0] == 0:
+            break
+    torch.cuda.synchronize()
+    return [st.array(k).cpu().numpy().copy() for k in (0, 1, 2)], st.info(), done
+
+
+@pytest.mark.parametrize("tol", [0.0, 1e-8])
+def test_next_a1_queued_ahead_changes_nothing(case, tol):
+    """Within one call each iteration queues the next one's a1 while the host waits for its search; a call of one
+    iteration queues nothing ahead.  Both must give the same states bit for bit, across the FP32 -> FP64 switch
+    and, with a tolerance, at the stop."""
+    st = case
+    one, info1, n1 = _solve(st, 1, 40, tol)
+    many, info2, n2 = _solve(st, 40, 40, tol)
+    assert info1 == info2 and n1 == n2, (info1, info2, n1, n2)
+    assert info1[1] >= 1 and info1[2] >= 1, info1        # both precisions ran
+    if tol > 0.0:
+        assert n1 < 40
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b)
