@@ -1449,8 +1449,7 @@ static hipError_t enqueue_a1(qgw_state st, bool f32, bool prof, hipStream_t s, b
     }
   } else {
     st->p32.tune = p.has_tune32 ? p.tune32 : p.tune;
-    run(launch_convert(ncol_g * p.r, st->G_iw, st->G32, 1, s));
-    run(launch_dlr2(st->p32, QGW_F_IW2TAU, QGW_F_IW2TAUR, ncol_g, st->G32, st->Gt32, st->Gr32, s));
+    run(launch_dlr2_from_f64(st->p32, QGW_F_IW2TAU, QGW_F_IW2TAUR, ncol_g, st->G_iw, st->Gt32, st->Gr32, st->G32, s));
   }
   return e;
 }
@@ -1520,8 +1519,7 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
     mark(7);
     run(launch_sigma(q, st->Gt32, st->Pq32, 1, 1, st->St32, s));
     mark(8);
-    run(launch_dlr(q, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->St32, st->Siw32, s, 1));
-    run(launch_convert(ncol_g * p.r, st->Siw32, st->Sig_iw, 0, s));
+    run(launch_dlr_to_f64(q, QGW_F_TAU2IW, ncol_g, 1.0, 0.0, st->St32, st->Sig_iw, st->Siw32, s, 1));
   }
   if (fork) {
     run(hipStreamWaitEvent(st->side, st->ev_fork, 0));

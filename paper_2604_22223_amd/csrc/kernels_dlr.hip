@@ -230,13 +230,16 @@ __device__ __forceinline__ T dpp_identity(T v) {
   return v;
 }
 
-// four waves per SIMD: two 512-thread blocks fit a CU
-template <typename T, int MT, int MODE, bool HERM_IN>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dlr_mfma(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+// four waves per SIMD: two 512-thread blocks fit a CU.  TI, TO: element types of the input and the output when
+// they differ from the arithmetic type T (an FP64 input rounded to FP32 as it is used, an FP32 result widened to
+// FP64 as it is stored), which gives the same values as a separate conversion pass before or after the map
+template <typename T, int MT, int MODE, bool HERM_IN, typename TI = T, typename TO = T>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dlr_mfma(const cpx<TI>* __restrict__ in, cpx<TO>* __restrict__ out,
                                                   const cpx<T>* __restrict__ map, int r, int kp, int na,
                                                   int nq, int64_t nstrips, int no, T sre, T sim, int ysplit,
-                                                  const cpx<T>* __restrict__ map2, cpx<T>* __restrict__ out2,
+                                                  const cpx<T>* __restrict__ map2, cpx<TO>* __restrict__ out2,
                                                   int tiles_per_map) {
+  static_assert(!HERM_IN || sizeof(TI) == sizeof(T), "the Hermitian part is taken in the arithmetic type");
   using M = Mfma<T>;
   using v4 = typename M::v4;
   extern __shared__ unsigned char smem_raw[];
@@ -312,18 +315,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     // clamped to r - 1 (the map's zero padding for k >= r cancels what is
     // read there) and a column outside the array reads column 0 (its results
     // are not stored; every output column depends on its own input column only).
-    const cpx<T>* src = in + (valid ? cin : 0);
-    const cpx<T>* srcs = in + (valid ? cswap : 0);
-    auto load = [&](int t) -> cpx<T> {
+    const cpx<TI>* src = in + (valid ? cin : 0);
+    const cpx<TI>* srcs = in + (valid ? cswap : 0);
+    // the loaded values stay in the input type until their use, so that the conversion does not wait on the load
+    auto load = [&](int t) -> cpx<TI> {
       const int64_t tc = t < r ? t : r - 1;
-      cpx<T> v = src[tc * plane];
-      if (HERM_IN) v = scale(v + conj(srcs[tc * plane]), T(0.5));
+      cpx<TI> v = src[tc * plane];
+      if (HERM_IN) v = scale(v + conj(srcs[tc * plane]), TI(0.5));
       return v;
     };
     // the input slice is read two steps ahead of its use
-    cpx<T> x = dpp_identity(load(lk)), xn = dpp_identity(load(4 + lk));
+    cpx<TI> xi = dpp_identity(load(lk)), xn = dpp_identity(load(4 + lk));
     for (int kb = 0; kb < kp; kb += 4) {
-      const cpx<T> xnn = load(kb + 8 + lk);
+      const cpx<TI> xnn = load(kb + 8 + lk);
+      const cpx<T> x = cast<T>(xi);
       const int kk = kb >> 2;
       T ar[MT], ai[MT];
 #pragma unroll
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         accr[mt] = M::mac(-ai[mt], x.im, accr[mt]);
         acci[mt] = M::mac(ai[mt], x.re, acci[mt]);
       }
-      x = xn;
+      xi = xn;
       xn = xnn;
     }
     if (valid) {
@@ -352,7 +357,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int m = row0 + mt * 16 + M::row(lane, v);
-          if (m < r) out[int64_t(m) * plane + cout] = sc * mk(accr[mt][v], acci[mt][v]);
+          if (m < r) out[int64_t(m) * plane + cout] = cast<TO>(sc * mk(accr[mt][v], acci[mt][v]));
         }
     }
   }
@@ -514,13 +519,16 @@ hipError_t dlr_mfma_pairs_launch(const Plan& p, int map, int na, int nq, double 
   return hipGetLastError();
 }
 
-// na x nq columns; HERM_IN: orbital arrays (na = n_o^2, nq = N_k)
-template <typename T, int MODE, bool HERM_IN>
+// na x nq columns; HERM_IN: orbital arrays (na = n_o^2, nq = N_k); TI, TO: input and output element types
+template <typename T, int MODE, bool HERM_IN, typename TI = T, typename TO = T>
 hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, double sim, const void* in,
                            void* out, hipStream_t s, int64_t in_ld = 0, int map2 = -1, void* out2 = nullptr) {
   const int kp = (p.r + 3) / 4 * 4;
   const int mt = (p.r + 15) / 16;
-  if constexpr (MODE != kPlain) return dlr_mfma_pairs_launch<T, MODE>(p, map, na, nq, sre, sim, in, out, s, in_ld);
+  if constexpr (MODE != kPlain) {
+    static_assert(sizeof(TI) == sizeof(T) && sizeof(TO) == sizeof(T), "pair maps keep the arithmetic type");
+    return dlr_mfma_pairs_launch<T, MODE>(p, map, na, nq, sre, sim, in, out, s, in_ld);
+  }
   if (in_ld != 0) return hipErrorInvalidValue;
   int64_t nstrips;
   if (MODE == kSlabToMatrix)
@@ -539,8 +547,8 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
   const int tiles = (blocks < 2 * int64_t(ncu)) ? mt : 1;  // row-tile blocks per strip group and map
   const int mtb = mt / tiles;
   if (map2 >= 0 && tiles == 1) {  // a second map of the same input: one launch only when the row tiles are split
-    hipError_t e = dlr_mfma_launch<T, MODE, HERM_IN>(p, map, na, nq, sre, sim, in, out, s);
-    return e == hipSuccess ? dlr_mfma_launch<T, MODE, HERM_IN>(p, map2, na, nq, sre, sim, in, out2, s) : e;
+    hipError_t e = dlr_mfma_launch<T, MODE, HERM_IN, TI, TO>(p, map, na, nq, sre, sim, in, out, s);
+    return e == hipSuccess ? dlr_mfma_launch<T, MODE, HERM_IN, TI, TO>(p, map2, na, nq, sre, sim, in, out2, s) : e;
   }
   const int ysplit = map2 >= 0 ? 2 * tiles : tiles;
   if (blocks > int64_t(bpc) * ncu) blocks = int64_t(bpc) * ncu;
@@ -550,9 +558,9 @@ hipError_t dlr_mfma_launch(const Plan& p, int map, int na, int nq, double sre, d
   const cpx<T>* mp2 = map2 >= 0 ? map_ptr<T>(p, map2) : nullptr;
 #define QGW_MFMA_MT(MTV)                                                                                  \
   case MTV:                                                                                               \
-    hipLaunchKernelGGL((k_dlr_mfma<T, MTV, MODE, HERM_IN>), dim3(unsigned(blocks)), dim3(512), lds, s,   \
-                       (const cpx<T>*)in, (cpx<T>*)out, mp, p.r, kp, na, nq, nstrips, p.no, T(sre), T(sim), \
-                       ysplit, mp2, (cpx<T>*)out2, tiles);                                                 \
+    hipLaunchKernelGGL((k_dlr_mfma<T, MTV, MODE, HERM_IN, TI, TO>), dim3(unsigned(blocks)), dim3(512), lds, s, \
+                       (const cpx<TI>*)in, (cpx<TO>*)out, mp, p.r, kp, na, nq, nstrips, p.no, T(sre), T(sim),   \
+                       ysplit, mp2, (cpx<TO>*)out2, tiles);                                                   \
     break;
   switch (mtb) {
     QGW_MFMA_MT(1)
@@ -628,6 +636,35 @@ hipError_t launch_dlr2(const Plan& p, int map1, int map2, int64_t ncols, const v
   }
   hipError_t e = launch_dlr(p, map1, ncols, 1.0, 0.0, in, out1, s);
   return e == hipSuccess ? launch_dlr(p, map2, ncols, 1.0, 0.0, in, out2, s) : e;
+}
+
+// An FP32 plan's two maps of an FP64 input (both time orders of G): the input is rounded to FP32 as the maps read
+// it.  Where the matrix-core path does not apply, the input is first converted into `stage` (ncols r values).
+hipError_t launch_dlr2_from_f64(const Plan& p, int map1, int map2, int64_t ncols, const void* in64, void* out1,
+                                void* out2, void* stage, hipStream_t s) {
+  if (p.prec != 1) return hipErrorInvalidValue;
+  if (p.grid == kGridDLR && p.r <= 64 && map1 != 5 && map2 != 5 && p.tune.orb_valu != 1 && ncols <= (int64_t(1) << 30))
+    return dlr_mfma_launch<float, kPlain, false, double, float>(p, map1, 1, int(ncols), 1, 0, in64, out1, s, 0, map2,
+                                                               out2);
+  hipError_t e = launch_convert(ncols * p.r, in64, stage, 1, s);
+  return e == hipSuccess ? launch_dlr2(p, map1, map2, ncols, stage, out1, out2, s) : e;
+}
+
+// An FP32 plan's map of an orbital array (herm = 1: its Hermitian part) with the result widened to FP64 as it is
+// stored.  Where the matrix-core path does not apply, the FP32 result goes to `stage` and is converted from there.
+hipError_t launch_dlr_to_f64(const Plan& p, int map, int64_t ncols, double sre, double sim, const void* in,
+                             void* out64, void* stage, hipStream_t s, int herm) {
+  if (p.prec != 1) return hipErrorInvalidValue;
+  const int64_t ng = int64_t(p.no) * p.no * p.nk;
+  if (p.grid == kGridDLR && p.r <= 64 && map != 5 && herm != 2 && (herm == 0 || ncols == ng) &&
+      p.tune.orb_valu != 1 && (herm != 0 || ncols <= (int64_t(1) << 30))) {
+    const int na = herm ? p.no * p.no : 1;
+    const int nq = herm ? p.nk : int(ncols);
+    if (herm) return dlr_mfma_launch<float, kPlain, true, float, double>(p, map, na, nq, sre, sim, in, out64, s);
+    return dlr_mfma_launch<float, kPlain, false, float, double>(p, map, na, nq, sre, sim, in, out64, s);
+  }
+  hipError_t e = launch_dlr(p, map, ncols, sre, sim, in, stage, s, herm);
+  return e == hipSuccess ? launch_convert(ncols * p.r, stage, out64, 0, s) : e;
 }
 
 hipError_t launch_dlr_pairs(const Plan& p, int map, int in_layout, int out_layout, const void* in,

@@ -192,6 +192,12 @@ hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* 
                                 hipStream_t s, const void* h0 = nullptr, void* hs = nullptr);
 // complex128 <-> complex64 copies (to_f32 = 1: double -> float)
 hipError_t launch_convert(int64_t count, const void* in, void* out, int to_f32, hipStream_t s);
+// FP32 plans: the two maps of an FP64 input (rounded as read), and a map whose result is widened to FP64 as stored;
+// `stage` (r ncols FP32 values) serves the conversion pass where the matrix-core path does not apply
+hipError_t launch_dlr2_from_f64(const Plan& p, int map1, int map2, int64_t ncols, const void* in64, void* out1,
+                                void* out2, void* stage, hipStream_t s);
+hipError_t launch_dlr_to_f64(const Plan& p, int map, int64_t ncols, double sre, double sim, const void* in,
+                             void* out64, void* stage, hipStream_t s, int herm);
 hipError_t launch_count_nonfinite(const Plan& p, const void* x, int64_t count, int* d_count,
                                   hipStream_t s);
 

@@ -147,3 +147,28 @@ def test_first_fp32_iteration_tracks_oracle(five8):
     assert abs(mu - ref["mu"]) <= 1e-4 * max(1.0, abs(ref["mu"]))
     st.close()
     plan.close()
+
+
+def test_fp32_iterations_through_staged_conversions(five8):
+    """An FP32 iteration rounds G(i w) to FP32 inside the matrix-core maps of a1 and widens Sigma^C(i w) to FP64 as
+    a11 stores it.  With the orbital maps on the VALU kernel (orbital_map_valu = 1) it converts through staging
+    buffers instead.  Both routes round the same values; they differ only in the maps' summation order, so two
+    FP32 iterations from G0 agree to FP32 rounding."""
+    torch = _torch()
+    m, d = five8["m"], five8["d"]
+    plan = qgw.Plan.from_nodes(8, [5], d.beta, d.nodes())
+    st = qgw.State(plan, torch.from_numpy(flat(m.H_R)).to("cuda:0"), torch.from_numpy(flat(m.V_R)).to("cuda:0"),
+                   n_target=m.n_target)
+    out = []
+    for valu in (0, 1):
+        plan.set_tuning({"orbital_map_valu": valu}, precision=1)
+        st.set_precision(2, 1e-4)
+        st.init_g0()
+        st.iterate(2)
+        torch.cuda.synchronize()
+        out.append([st.array(k).cpu().numpy() for k in (0, 1, 2)])
+    for a, b in zip(*out):
+        scale = float(np.max(np.abs(a)))
+        assert np.max(np.abs(a - b)) <= 1e-4 * scale, float(np.max(np.abs(a - b)) / scale)
+    st.close()
+    plan.close()
