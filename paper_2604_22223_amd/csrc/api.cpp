@@ -648,7 +648,8 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
                               double* extra_dst = nullptr, hipEvent_t end_ev = nullptr, int steps0 = 6,
                               double* h_io = nullptr, hipEvent_t io_ev = nullptr, int track = 0,
                               const double* dpart = nullptr, int dnblk = 0, int* rounds_out = nullptr,
-                              void (*on_queued)(void*) = nullptr, void* on_ctx = nullptr) {
+                              void (*on_queued)(void*) = nullptr, void* on_ctx = nullptr,
+                              const double* bmax = nullptr, int nbmax = 0, double* dsig_out = nullptr) {
   const int mode = std::isnan(n_target) ? 0 : 1;
   if (!scal) {
     scal = p.d_scalars;
@@ -670,7 +671,7 @@ static qgw_status run_dyson_g(const Plan& p, const void* H_k, const void* Sig_iw
     // with the diagonal sums of H from a14 at hand and a finite start, no Gershgorin pass is needed
     const bool use_d = dpart && std::isfinite(sc[0]);
     QGW_CHECK_HIP(launch_dyson_g_begin(p, H_k, scal, part, stat, track, s, 1, sc[0], sc[1], use_d ? dpart : nullptr,
-                                       dnblk),
+                                       dnblk, bmax, nbmax, dsig_out),
                   "qgw_dyson_G");
   } else {
     QGW_CHECK_HIP(hipMemcpyAsync(scal, sc, 2 * sizeof(double), hipMemcpyHostToDevice, s), "qgw_dyson_G");
@@ -1529,8 +1530,9 @@ static hipError_t enqueue_steps(qgw_state st, bool f32, bool prof, hipStream_t s
   // a14 and the static part of a13 (H0 + Sigma_HF) in one pass, once a12 has joined
   if (fork) run(hipStreamWaitEvent(s, st->ev_join, 0));
   mark(9);
+  // with a target filling the search's first launch reduces the block maxima into |dSigma| (one launch less)
   run(launch_delta_and_mix(p, st->SigHF_k, st->Sig_iw, st->SigHF_old, st->Sig_iw_old, st->mixing, st->d_dsig,
-                           st->d_blockmax, s, st->H_k, st->Hs_k));
+                           st->d_blockmax, s, st->H_k, st->Hs_k, std::isnan(st->n_target)));
   mark(10);
   return e;
 }
@@ -1609,7 +1611,8 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
                                 st->mu_steps0, st->h_io,
                                 st->ev_io, 1,
                                 st->d_blockmax + 4096, dyson_g_diag_blocks(p), &rounds,
-                                ahead ? queue_next_a1 : nullptr, &nx);
+                                ahead ? queue_next_a1 : nullptr, &nx, st->d_blockmax, dyson_g_diag_blocks(p),
+                                st->d_dsig);
     if (nx.queued && nx.err != hipSuccess) {
       st->broken = true;
       set_error(std::string("qgw_gw_iteration: ") + hipGetErrorString(nx.err));
@@ -1735,7 +1738,7 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
         if (ce == hipSuccess)
           ce = launch_dyson_g_chain(p, st->Hs_k, st->Sig_iw, std::isnan(st->n_target) ? 0 : 1, st->G_iw, st->d_scal,
                                     st->d_part, st->d_stat, mu_steps, st->d_stat + 1, ws, st->d_blockmax + 4096,
-                                    dyson_g_diag_blocks(p));
+                                    dyson_g_diag_blocks(p), st->d_blockmax, dyson_g_diag_blocks(p), st->d_dsig);
       }
     for (int w = 0; w < nw && ce == hipSuccess; ++w) {
       ce = hipEventRecord(b->events[w], b->workers[w]);

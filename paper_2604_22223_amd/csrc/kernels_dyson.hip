@@ -687,9 +687,19 @@ __global__ __launch_bounds__(64) void k_dg_gersh(DysonGArgs A) {
 // of Sigma_HF (so that a Hartree shift of many eV does not cost a chain of capped steps); resets the search
 // set: the start point (mu0, n_target) comes as arguments instead of a copy into scal[0..1]
 // diag_only: partials holds only nblk diagonal sums (a14's), no Gershgorin bounds
+// bmax (optional): a14's nbmax block maxima of |Delta Sigma| (non-finite ones already +inf); their maximum goes to
+// *dsig, so that a14 needs no reduction launch of its own (the maximum is exact, so the order does not matter)
 __global__ __launch_bounds__(64) void k_dg_begin(double* __restrict__ scal, int* __restrict__ status,
                                                  const double* __restrict__ partials, int nblk, double inv_count,
-                                                 int track, int set, double mu0, double nt, int diag_only) {
+                                                 int track, int set, double mu0, double nt, int diag_only,
+                                                 const double* __restrict__ bmax, int nbmax,
+                                                 double* __restrict__ dsig) {
+  if (bmax) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nbmax; b += 64) v = fmax(v, bmax[b]);
+    v = wave_max(v);
+    if (threadIdx.x == 0) *dsig = v;
+  }
   double glo = 1e300, ghi = -1e300, dsum = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) {
     if (diag_only) {
@@ -1128,17 +1138,18 @@ namespace {
 
 template <int NO>
 hipError_t dyson_g_begin_no(const Plan& p, const void* h_k, double* scal, double* partials, int* status, int track,
-                            int set, double mu0, double nt, const double* dpart, int dnblk, hipStream_t s) {
+                            int set, double mu0, double nt, const double* dpart, int dnblk, const double* bmax,
+                            int nbmax, double* dsig, hipStream_t s) {
   if (dpart) {
     hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status, dpart, dnblk, 1.0 / (double(NO) * p.nk),
-                       track, set, mu0, nt, 1);
+                       track, set, mu0, nt, 1, bmax, nbmax, dsig);
     return hipGetLastError();
   }
   DysonGArgs A = dyson_g_args<NO>(p, h_k, nullptr, 1, nullptr, scal, partials, status);
   const int gb = int((p.nk + 63) / 64 < 1024 ? (p.nk + 63) / 64 : 1024);
   hipLaunchKernelGGL((k_dg_gersh<NO>), dim3(gb), dim3(64), 0, s, A);
   hipLaunchKernelGGL(k_dg_begin, dim3(1), dim3(64), 0, s, scal, status, (const double*)partials, gb,
-                     1.0 / (double(NO) * p.nk), track, set, mu0, nt, 0);
+                     1.0 / (double(NO) * p.nk), track, set, mu0, nt, 0, bmax, nbmax, dsig);
   return hipGetLastError();
 }
 
@@ -1286,8 +1297,9 @@ hipError_t launch_dyson_w(const Plan& p, const void* v_q, const void* p_nu, void
 
 hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
                                 int track, hipStream_t s, int set, double mu0, double nt, const double* dpart,
-                                int dnblk) {
-  QGW_NO_SWITCH((dyson_g_begin_no<NOV>(p, h_k, scal, partials, status, track, set, mu0, nt, dpart, dnblk, s)))
+                                int dnblk, const double* bmax, int nbmax, double* dsig) {
+  QGW_NO_SWITCH((dyson_g_begin_no<NOV>(p, h_k, scal, partials, status, track, set, mu0, nt, dpart, dnblk, bmax, nbmax,
+                                       dsig, s)))
 }
 
 hipError_t launch_dyson_g_steps(const Plan& p, const void* h_k, const void* sig_iw, double* scal, double* partials,
@@ -1304,10 +1316,11 @@ hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_
 
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, int steps, int* fail_word,
-                                hipStream_t s, const double* dpart, int dnblk) {
+                                hipStream_t s, const double* dpart, int dnblk, const double* bmax, int nbmax,
+                                double* dsig) {
   hipError_t e = hipSuccess;
   if (mode == 1) {
-    e = launch_dyson_g_begin(p, h_k, scal, partials, status, 1, s, 0, 0.0, 0.0, dpart, dnblk);
+    e = launch_dyson_g_begin(p, h_k, scal, partials, status, 1, s, 0, 0.0, 0.0, dpart, dnblk, bmax, nbmax, dsig);
     if (e == hipSuccess) e = launch_dyson_g_steps(p, h_k, sig_iw, scal, partials, status, steps, s);
   }
   if (e == hipSuccess) e = launch_dyson_g_final(p, h_k, sig_iw, mode, g_iw, scal, partials, status, s, nullptr,

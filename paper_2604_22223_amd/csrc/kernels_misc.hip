@@ -400,14 +400,15 @@ hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b
 
 hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* hf_old, void* c_old,
                                 double alpha, double* d_out, double* block_scratch, hipStream_t s, const void* h0,
-                                void* hs) {
+                                void* hs, bool reduce) {
   const int64_t ns = int64_t(p.no) * p.no * p.nk;
   const int64_t blocks = nblk(ns, 64);
   if (blocks > 4096) return hipErrorInvalidValue;  // the state's block scratch holds 4096 maxima
   hipLaunchKernelGGL(k_delta_mix, dim3(unsigned(blocks)), dim3(256), 0, s, (zd*)hf_new, (zd*)c_new, (zd*)hf_old,
                      (zd*)c_old, ns, p.r, alpha, block_scratch, (const zd*)h0, (zd*)hs, p.no, p.nk,
                      h0 ? block_scratch + 4096 : nullptr);
-  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, (const double*)block_scratch, int(blocks), d_out);
+  if (reduce)
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, (const double*)block_scratch, int(blocks), d_out);
   return hipGetLastError();
 }
 

@@ -160,9 +160,12 @@ hipError_t launch_pair_sum_r(const Plan& p, const void* v_r, void* v_q0, hipStre
 // set = 1: scal[0..1] = (mu0, nt) first (the host's start point as kernel arguments, no copy)
 // dpart (optional): dnblk block sums of the diagonal of h_k already at hand (from a14); the Gershgorin pass is then
 // skipped, and a start that is not finite is reported as status 1 instead of replaced by the Gershgorin centre
+// bmax (optional): a14's nbmax block maxima of |Delta Sigma|, reduced into *dsig by the same launch (a14 then runs
+// without its own reduction)
 hipError_t launch_dyson_g_begin(const Plan& p, const void* h_k, double* scal, double* partials, int* status,
                                 int track, hipStream_t s, int set = 0, double mu0 = 0.0, double nt = 0.0,
-                                const double* dpart = nullptr, int dnblk = 0);
+                                const double* dpart = nullptr, int dnblk = 0, const double* bmax = nullptr,
+                                int nbmax = 0, double* dsig = nullptr);
 // number of the diagonal block sums a14 leaves for the search (one per 64 static entries)
 inline int dyson_g_diag_blocks(const Plan& p) { return int((int64_t(p.no) * p.no * p.nk + 63) / 64); }
 // doubles of partial sums one chemical-potential search on plan p uses (start and evaluations)
@@ -179,7 +182,8 @@ hipError_t launch_dyson_g_final(const Plan& p, const void* h_k, const void* sig_
                                 const double* extra = nullptr, int steps = 0, int* fail_word = nullptr);
 hipError_t launch_dyson_g_chain(const Plan& p, const void* h_k, const void* sig_iw, int mode, void* g_iw,
                                 double* scal, double* partials, int* status, int steps, int* fail_word,
-                                hipStream_t s, const double* dpart = nullptr, int dnblk = 0);
+                                hipStream_t s, const double* dpart = nullptr, int dnblk = 0,
+                                const double* bmax = nullptr, int nbmax = 0, double* dsig = nullptr);
 hipError_t launch_slab_to_matrix_static(const Plan& p, const void* in, void* out, hipStream_t s);
 hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b, void* out,
                       hipStream_t s);
@@ -187,9 +191,11 @@ hipError_t launch_add(const Plan& p, int64_t count, const void* a, const void* b
 // new <- old + alpha (new - old), and old <- new; with h0 also hs = h0 + (mixed) hf_new.  block_scratch holds up to
 // 4096 block maxima of 64 static entries (n_o^2 N_k <= 262144), and with h0, at block_scratch + 4096, the blocks'
 // sums of the diagonal of hs (dyson_g_diag_blocks of them): the mean level a state's next search starts from.
+// reduce = false leaves the block maxima unreduced (d_out untouched) for the chemical-potential search's first
+// launch to reduce (launch_dyson_g_begin with bmax).
 hipError_t launch_delta_and_mix(const Plan& p, void* hf_new, void* c_new, void* hf_old,
                                 void* c_old, double alpha, double* d_out, double* block_scratch,
-                                hipStream_t s, const void* h0 = nullptr, void* hs = nullptr);
+                                hipStream_t s, const void* h0 = nullptr, void* hs = nullptr, bool reduce = true);
 // complex128 <-> complex64 copies (to_f32 = 1: double -> float)
 hipError_t launch_convert(int64_t count, const void* in, void* out, int to_f32, hipStream_t s);
 // FP32 plans: the two maps of an FP64 input (rounded as read), and a map whose result is widened to FP64 as stored;
