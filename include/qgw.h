@@ -517,7 +517,11 @@ qgw_status qgw_state_init_g0(qgw_state state, double *mu, void *stream);
 /* Runs up to n_iter GW iterations (Fig. fig-self (b): a1 .. a14), stopping
  * early once max |Delta Sigma| <= tol.  Outputs (any may be NULL): the
  * number of iterations done, the last max |Delta Sigma| and mu.  Waits for
- * ``stream`` once per iteration (mu and max |Delta Sigma| come back).
+ * ``stream`` once per iteration (mu and max |Delta Sigma| come back); while
+ * it waits, the next iteration's first step (G(tau), which depends only on
+ * the new G) is already queued behind the read-back, so when the call
+ * returns after stopping early the stream may still hold that step, which
+ * rewrites only internal G(tau) buffers (none that qgw_state_copy exposes).
  * Errors: QGW_ERR_SINGULAR if a Dyson-W system met a zero or non-finite
  * pivot, QGW_ERR_NONFINITE if max |Delta Sigma| is not finite (any NaN in
  * Sigma counts), QGW_ERR_NOT_CONVERGED if the chemical-potential search
