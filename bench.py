@@ -265,12 +265,18 @@ def paper_workload_leg(torch, qgw, steps, tol, warmup=3, mixing=0.5):
         st.iterate(warmup)
         st.init_g0()
         torch.cuda.synchronize()
-        st.profile(1)
         t0 = time.perf_counter()
         done, _, _ = st.iterate(steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        # the per-step breakdown: the same iterations again, every step timed, a12 in line
+        st.init_g0()
+        st.profile_select(None, in_line=True)
+        st.profile(1)
+        st.iterate(steps)
+        torch.cuda.synchronize()
         prof = st.profile(0, per_precision=True)
+        st.profile_select(None, in_line=False)
         entry = {"iterations": done, "ms_per_iteration": round(1e3 * el / max(done, 1), 4)}
         for prec in ("f64", "f32"):
             ms_tot, iters = prof[prec]
@@ -316,12 +322,18 @@ def mf_leg(torch, qgw, w, steps, tol, warmup=2, mixing=1.0, dlr_ms=None, name=""
     st.iterate(warmup)
     st.init_g0()
     torch.cuda.synchronize()
-    st.profile(1)
     t0 = time.perf_counter()
     done, _, _ = st.iterate(steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # the per-step breakdown: the same iterations again, every step timed, a12 in line
+    st.init_g0()
+    st.profile_select(None, in_line=True)
+    st.profile(1)
+    st.iterate(steps)
+    torch.cuda.synchronize()
     ms_tot, iters = st.profile(0)
+    st.profile_select(None, in_line=False)
     ms = 1e3 * el / max(done, 1)
     res = {"workload": name, "nodes": n_nodes, "omega_max": w["omega_max"], "iterations": done,
            "ms_per_iteration": round(ms, 4),
