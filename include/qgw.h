@@ -511,7 +511,10 @@ qgw_status qgw_state_create(qgw_plan plan, const void *H0_R, const void *V_R,
 qgw_status qgw_state_destroy(qgw_state state);
 
 /* Sets G = G0 at the chemical potential for the target filling (or at *mu
- * if n_target is NaN). */
+ * if n_target is NaN).  With a target filling *mu is the search's start
+ * and receives the result; a NaN start begins at the state's previous G0
+ * mu (the same H0: the search then stops at its first evaluation), or at
+ * the centre of H0's Gershgorin bounds the first time. */
 qgw_status qgw_state_init_g0(qgw_state state, double *mu, void *stream);
 
 /* Runs up to n_iter GW iterations (Fig. fig-self (b): a1 .. a14), stopping

@@ -43,6 +43,7 @@ struct qgw_state_s {
   double* d_part = nullptr;
   int* d_stat = nullptr;
   int mu_steps0 = 10;  // Newton steps queued in the first round of the next search
+  double mu_g0 = NAN;  // mu of the state's last G0 at its target filling (the next G0's start if none is given)
   int last_evals = 0;  // evaluations the last search took
   // pinned host words of the search's per-iteration exchange (start point in, result out) and the
   // event the host polls for the result: no staging copy and no blocking wait per iteration
@@ -1395,9 +1396,15 @@ qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
   QGW_CHECK_HIP(hipMemsetAsync(st->Sig_iw_old, 0, fo, s), "qgw_state_init_g0");
   QGW_CHECK_HIP(hipMemsetAsync(st->SigHF_old, 0, so, s), "qgw_state_init_g0");
   double m = *mu;
+  // with a target filling and no finite start given, the search starts from the state's previous G0 (the same
+  // H0, so the same mu up to the search's tolerance): a couple of Newton steps instead of a search from the
+  // Gershgorin centre
+  const bool warm = !std::isnan(st->n_target) && !std::isfinite(m) && std::isfinite(st->mu_g0);
+  if (warm) m = st->mu_g0;
   qgw_status rc = run_dyson_g(p, st->H_k, nullptr, st->n_target, &m, st->G_iw, s, nullptr, st->d_scal,
-                              st->d_part, st->d_stat, nullptr, nullptr, nullptr, 6, st->h_io, st->ev_io);
+                              st->d_part, st->d_stat, nullptr, nullptr, nullptr, warm ? 3 : 6, st->h_io, st->ev_io);
   if (rc != QGW_OK) return rc;
+  if (!std::isnan(st->n_target)) st->mu_g0 = m;
   st->mu = m;
   *mu = m;
   st->broken = false;

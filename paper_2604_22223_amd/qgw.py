@@ -467,8 +467,10 @@ class State:
         except Exception:
             pass
 
-    def init_g0(self, mu=0.0):
-        m = ctypes.c_double(float(mu))
+    def init_g0(self, mu=None):
+        """G = G0 (qgw_state_init_g0).  mu: the search's start (with a target filling) or the fixed mu; None starts
+        from the state's previous G0, or from the centre of H0's Gershgorin bounds the first time."""
+        m = ctypes.c_double(math.nan if mu is None else float(mu))
         _check(lib().qgw_state_init_g0(self.handle, ctypes.byref(m), _stream()))
         return m.value
 
