@@ -201,9 +201,11 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
 // chunks and the pivot exchange (two buffers, alternating by step): twelve
 // blocks fit a CU.
 // ---------------------------------------------------------------------------
+// row shift by DPP; a lane whose source lies outside its row gets INT_MIN, the identity of the max it feeds, so the
+// shift folds into the max instruction (no copy of the value first)
 template <int CTRL>
 __device__ __forceinline__ int dpp_shl_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(int(0x80000000u), v, CTRL, 0xF, 0xF, false);
 }
 
 // 1 / d by the hardware estimate and Newton-Raphson steps r <- r (2 - d r)
