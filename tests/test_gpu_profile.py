@@ -120,3 +120,19 @@ def test_next_a1_queued_ahead_changes_nothing(case, tol):
         assert n1 < 40
     for a, b in zip(one, many):
         assert np.array_equal(a, b)
+
+
+def test_g0_warm_start_gives_the_same_g0(case):
+    """qgw_state_init_g0 without a start begins the search at the state's previous G0 mu: the search stops at
+    its first evaluation, so mu and G0 come out bit for bit as from the cold start."""
+    torch = _torch()
+    st = case
+    st.set_precision(0)
+    mu_cold = st.init_g0(0.0)
+    torch.cuda.synchronize()
+    g_cold = st.array(0).cpu().numpy().copy()
+    for _ in range(2):
+        mu_warm = st.init_g0()
+        torch.cuda.synchronize()
+        assert mu_warm == mu_cold
+        assert np.array_equal(st.array(0).cpu().numpy(), g_cold)
