@@ -574,6 +574,15 @@ qgw_status qgw_state_copy(qgw_state state, int32_t which, void *dst, int64_t *by
  * call with mode 1 or 2 allocates the single-precision buffers. */
 qgw_status qgw_state_set_precision(qgw_state state, int32_t mode, double switch_tol);
 
+/* Newton evaluations of the chemical potential that qgw_gw_iteration queues
+ * before its one read-back per iteration: 0 (the default) adapts them (the
+ * previous search's count + 2, between 3 and 12; 10 after G0), 1 .. 64
+ * fixes them.  A search that needs more continues in further rounds of 16,
+ * each with a read-back; the evaluations and the result are the same either
+ * way, only launches and read-backs trade places.  QGW_ERR_INVALID_ARG
+ * outside [0, 64]. */
+qgw_status qgw_state_set_search_steps(qgw_state state, int32_t first_round);
+
 /* Precision used by the last iteration (0 FP64, 1 FP32), the number of FP32
  * and FP64 iterations since qgw_state_init_g0, and the number of N_e(mu)
  * evaluations the last iteration's chemical-potential search took.  Any

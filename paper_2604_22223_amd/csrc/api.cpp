@@ -43,6 +43,7 @@ struct qgw_state_s {
   double* d_part = nullptr;
   int* d_stat = nullptr;
   int mu_steps0 = 10;  // Newton steps queued in the first round of the next search
+  int mu_steps_fixed = 0;  // > 0: that many instead (qgw_state_set_search_steps)
   double mu_g0 = NAN;  // mu of the state's last G0 at its target filling (the next G0's start if none is given)
   int last_evals = 0;  // evaluations the last search took
   // pinned host words of the search's per-iteration exchange (start point in, result out) and the
@@ -1414,6 +1415,14 @@ qgw_status qgw_state_init_g0(qgw_state st, double* mu, void* stream) {
   return QGW_OK;
 }
 
+qgw_status qgw_state_set_search_steps(qgw_state st, int32_t first_round) {
+  QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_set_search_steps: null state");
+  QGW_REQUIRE(first_round >= 0 && first_round <= 64, QGW_ERR_INVALID_ARG,
+              "qgw_state_set_search_steps: first_round must be in [0, 64]");
+  st->mu_steps_fixed = first_round;
+  return QGW_OK;
+}
+
 qgw_status qgw_state_set_precision(qgw_state st, int32_t mode, double switch_tol) {
   QGW_REQUIRE(st, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: null state");
   QGW_REQUIRE(mode >= 0 && mode <= 2, QGW_ERR_INVALID_ARG, "qgw_state_set_precision: mode must be 0, 1 or 2");
@@ -1615,7 +1624,7 @@ qgw_status qgw_gw_iteration(qgw_state st, int32_t n_iter, double tol, int32_t* i
     qgw_status rc = run_dyson_g(p, st->Hs_k, st->Sig_iw, st->n_target, &m, st->G_iw, s, &evals, st->d_scal,
                                 st->d_part, st->d_stat, st->d_dsig, &dsig,
                                 st->prof && ((st->prof_mask >> 10) & 1u) ? st->ev[st->ev_set][QGW_NUM_STEPS] : nullptr,
-                                st->mu_steps0, st->h_io,
+                                st->mu_steps_fixed > 0 ? st->mu_steps_fixed : st->mu_steps0, st->h_io,
                                 st->ev_io, 1,
                                 st->d_blockmax + 4096, dyson_g_diag_blocks(p), &rounds,
                                 ahead ? queue_next_a1 : nullptr, &nx, st->d_blockmax, dyson_g_diag_blocks(p),

@@ -32,7 +32,7 @@ EXPORTS = ["qgw_dlr_build", "qgw_plan_create", "qgw_plan_destroy", "qgw_plan_get
            "qgw_dlr_transform", "qgw_dlr_transform_pairs", "qgw_lattice_fft", "qgw_bubble", "qgw_dyson_W",
            "qgw_sigma", "qgw_hartree_fock", "qgw_dyson_G", "qgw_state_create", "qgw_state_destroy",
            "qgw_state_init_g0", "qgw_gw_iteration", "qgw_state_copy", "qgw_state_profile", "qgw_state_profile_select",
-           "qgw_state_set_precision", "qgw_state_info", "qgw_check_finite",
+           "qgw_state_set_precision", "qgw_state_set_search_steps", "qgw_state_info", "qgw_check_finite",
            "qgw_dlr_transform_bwd", "qgw_dlr_transform_pairs_bwd", "qgw_lattice_fft_bwd", "qgw_bubble_bwd",
            "qgw_sigma_bwd", "qgw_dyson_W_bwd", "qgw_hartree_fock_bwd", "qgw_dyson_G_bwd", "qgw_pair_layout",
            "qgw_add", "qgw_energy", "qgw_energy_bwd", "qgw_quasiparticle", "qgw_hf_density", "qgw_state_hf_solve", "qgw_plan_autotune", "qgw_batch_create", "qgw_batch_launch", "qgw_batch_read", "qgw_batch_destroy",
@@ -96,6 +96,7 @@ def lib():
             "qgw_state_profile": [vp, i32, pd, pi32],
             "qgw_state_profile_select": [vp, ctypes.c_uint32, i32],
             "qgw_state_set_precision": [vp, i32, dbl],
+            "qgw_state_set_search_steps": [vp, i32],
             "qgw_state_info": [vp, pi32, pi32, pi32, pi32],
             "qgw_check_finite": [vp, vp, i64, vp],
             "qgw_dlr_transform_bwd": [vp, i32, i64, dbl, dbl, i32, vp, vp, vp],
@@ -517,6 +518,10 @@ class State:
         for n in names:
             mask |= 1 << self.STEP_NAMES.index(n)
         _check(lib().qgw_state_profile_select(self.handle, mask, 1 if in_line else 0))
+
+    def set_search_steps(self, first_round=0):
+        """Newton evaluations of mu queued per iteration before the read-back (qgw_state_set_search_steps; 0 adapts)."""
+        _check(lib().qgw_state_set_search_steps(self.handle, int(first_round)))
 
     def set_precision(self, mode, switch_tol=1e-4):
         """mode 0: FP64 throughout; 1: FP32 bulk steps until |dSigma| <= switch_tol, then FP64."""

@@ -136,3 +136,29 @@ def test_g0_warm_start_gives_the_same_g0(case):
         torch.cuda.synchronize()
         assert mu_warm == mu_cold
         assert np.array_equal(st.array(0).cpu().numpy(), g_cold)
+
+
+@pytest.mark.parametrize("per_call", [1, 40])
+def test_searches_in_several_rounds_give_the_same_states(case, per_call):
+    """With one Newton evaluation queued per iteration (qgw_state_set_search_steps(1)) nearly every search
+    continues in a second round after a read-back, and within a call the next iteration's a1, queued during the
+    first read-back, is queued again.  The evaluations are the same as with the adaptive count, so the states are
+    bit for bit the same, across the FP32 -> FP64 switch and at the stop."""
+    st = case
+    ref, info_ref, n_ref = _solve(st, per_call, 40, 1e-8)
+    try:
+        st.set_search_steps(1)
+        got, info, n = _solve(st, per_call, 40, 1e-8)
+    finally:
+        st.set_search_steps(0)
+    assert (info, n) == (info_ref, n_ref)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
+def test_search_steps_are_checked(case):
+    with pytest.raises(qgw.QGWError):
+        case.set_search_steps(65)
+    with pytest.raises(qgw.QGWError):
+        case.set_search_steps(-1)
+    case.set_search_steps(0)
