@@ -172,3 +172,36 @@ def test_fp32_iterations_through_staged_conversions(five8):
         assert np.max(np.abs(a - b)) <= 1e-4 * scale, float(np.max(np.abs(a - b)) / scale)
     st.close()
     plan.close()
+
+
+def test_gradients_at_the_mixed_solution(five8):
+    """The chosen schedule's end point feeds the differentiable layer.  One FP64 iteration
+    (autograd.gw_iteration) at the G of the mixed solve and at the G of the plain FP64 solve, both converged to
+    max |Delta Sigma| <= 1e-10, gives the same gradients of a loss in Sigma^C and the new G with respect to H0(R)
+    and V(R) (at a fixed input G, Sigma^C depends on V only; H0 enters through the Dyson equation for G)."""
+    torch = _torch()
+    from paper_2604_22223_amd import autograd as qa
+    m, d = five8["m"], five8["d"]
+    plan = qgw.Plan.from_nodes(8, [5], d.beta, d.nodes())
+    ends = []
+    for mode in (1, 0):
+        st, hist, mu = _run(plan, m, mode, 1e-10, max_iter=80)
+        assert hist[-1][0] <= 1e-10 and hist[-1][1] == 0, hist[-3:]
+        ends.append((st.array(0).clone(), float(mu)))
+        st.close()
+    rng = np.random.default_rng(5)
+    grads, C = [], None
+    for G, mu in ends:
+        H_R = torch.from_numpy(flat(m.H_R)).to("cuda:0").requires_grad_(True)
+        V_R = torch.from_numpy(flat(m.V_R)).to("cuda:0").requires_grad_(True)
+        H_k, V_qm = qa.model_arrays(plan, H_R, V_R)
+        g_new, _, siw, _ = qa.gw_iteration(plan, H_k, V_R, V_qm, G, m.n_target, mu)
+        if C is None:
+            C = [torch.from_numpy(rng.standard_normal(tuple(x.shape))
+                                  + 1j * rng.standard_normal(tuple(x.shape))).to("cuda:0") for x in (siw, g_new)]
+        loss = (torch.conj(C[0]) * siw).real.sum() + (torch.conj(C[1]) * g_new).real.sum()
+        gh, gv = torch.autograd.grad(loss, (H_R, V_R))
+        grads.append((gh.cpu().numpy(), gv.cpu().numpy()))
+    for a, b in zip(*grads):
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b), float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    plan.close()
