@@ -488,7 +488,7 @@ def adjoint_leg(torch, qgw, steps, warmup=1):
     return res
 
 
-def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
+def batch_leg(torch, qgw, count, launches, warmup, mu_steps, solve_replays=100):
     """Seeded instances of uneven size (1-5 orbitals, 12^2-48^2 meshes, beta 10-100) advanced by one
     graph launch per iteration, FP64 and FP32 bulk steps, against the same states iterated one by one."""
     from paper_2604_22223_amd import workloads as wl
@@ -583,12 +583,18 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps):
     # instance is at the switch tolerance or stalled, then FP64 replays); per instance the time at which its
     # max |Delta Sigma| first met the tolerance after an FP64 replay
     tol = _TOL[0]
+    if solve_replays <= 0:  # (a profiling run of the sweep alone)
+        for st in states:
+            st.close()
+        for pl in plans:
+            pl.close()
+        return res
     b64 = qgw.Batch(states, precision=qgw.F64, n_iter=1, mu_steps=mu_steps)
     b32 = qgw.Batch(states, precision=qgw.F32, n_iter=1, mu_steps=mu_steps)
     runs = {}
     for name, kw in (("solve_fp64", {}), ("solve_mixed", {"b32": b32, "switch_tol": switch_tol()})):
         restart()
-        runs[name] = qgw.batch_solve(b64, tol, max_replays=100, **kw)
+        runs[name] = qgw.batch_solve(b64, tol, max_replays=solve_replays, **kw)
     b32.close()
     b64.close()
     both = np.ones(count, dtype=bool)
@@ -628,6 +634,8 @@ def main():
     ap.add_argument("--paper-steps", type=int, default=20, metavar="K",
                     help="timed iterations of the paper's 8x8x8 five-orbital workload per schedule (0 skips it)")
     ap.add_argument("--batch-mu-steps", type=int, default=64)
+    ap.add_argument("--batch-solve-replays", type=int, default=100, metavar="K",
+                    help="replays per batched solve to the tolerance (0 skips the solves)")
     ap.add_argument("--adjoint-steps", type=int, default=3, metavar="K",
                     help="timed forward + backward steps of the 48x48 adjoint leg (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -762,7 +770,8 @@ def main():
         if paper is not None:
             mf.append(mf_leg(torch, qgw, wl.workload("cubic_five_orbital_8"), a.mf_steps, a.tol, mixing=0.5,
                              dlr_ms=paper["fp64"]["ms_per_iteration"], name="cubic_five_orbital_8"))
-    batch = batch_leg(torch, qgw, a.batch, a.batch_launches, 1, a.batch_mu_steps) if a.batch > 0 else None
+    batch = (batch_leg(torch, qgw, a.batch, a.batch_launches, 1, a.batch_mu_steps, a.batch_solve_replays)
+             if a.batch > 0 else None)
     adjoint = adjoint_leg(torch, qgw, a.adjoint_steps) if a.adjoint_steps > 0 else None
 
     cpu = None
