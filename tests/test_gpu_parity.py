@@ -68,6 +68,13 @@ CASE_SPECS = {
     # Kanamori ones), with the Slater integrals whose shell averages are U = 1, J = 0.1 eV
     "slater_d_8x8": lambda: wl.five_orbital(n=8, Vnn=0.2, beta=20.0, omega_max=25.0, eps=1e-10, scale_mesh=8,
                                             slater_F=interactions.slater_from_kanamori(2, 1.0, 0.1)),
+    # three and four orbitals on one site (N_b = 9 and 16: the general Dyson-W kernel, the Dyson-G search for
+    # n_o = 3 and 4), with the benchmark coupling; a 1e-13 relative change of G0 changes Sigma after three oracle
+    # iterations by at most 2e-13 for these seeds
+    "random_3_6x6": lambda: wl.random_model((6, 6), [3], seed=4, beta=10.0, omega_max=20.0, eps=1e-10,
+                                            U=1.0, J=0.1, Vnn=0.2),
+    "random_4_6x6": lambda: wl.random_model((6, 6), [4], seed=4, beta=10.0, omega_max=20.0, eps=1e-10,
+                                            U=1.0, J=0.1, Vnn=0.2),
     # graphene G0W0 workload at its full size (12 x 12, r = 43)
     "graphene_g0w0_12": lambda: wl.workload("graphene_g0w0_12"),
     # cubic meshes: 3 orbitals on two sites on 4 x 4 x 4, five orbitals on 6 x 6 x 6 (radix 3 and 2).
