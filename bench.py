@@ -494,11 +494,12 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps, solve_replays=100):
     from paper_2604_22223_amd import workloads as wl
     t0 = time.perf_counter()
     ws = wl.batch_sweep(count)
-    plans, states, t_tune = [], [], 0.0
+    plans, states, n_f, t_tune = [], [], [], 0.0
     flat = lambda x: torch.from_numpy(np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))).to("cuda:0")
     for w in ws:
         nodes = qgw.dlr_build(w["beta"] * w["omega_max"], w["eps"])
         nodes["omega"] = nodes["x"] / w["beta"]
+        n_f.append(nodes["n_f"])
         pl = qgw.Plan.from_nodes(w["mesh"][0], w["site_norb"], w["beta"], nodes)
         t1 = time.perf_counter()
         pl.autotune()
@@ -586,6 +587,7 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps, solve_replays=100):
     if solve_replays <= 0:  # (a profiling run of the sweep alone)
         for st in states:
             st.close()
+        res["backward"] = batch_backward(torch, qgw, plans, ws, n_f, launches)
         for pl in plans:
             pl.close()
         return res
@@ -614,10 +616,74 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps, solve_replays=100):
                res[name]["median_s_to_tol_over_those"], res[name]["s_until_the_last_of_those"]))
     for st in states:
         st.close()
+    res["backward"] = batch_backward(torch, qgw, plans, ws, n_f, launches)
     for pl in plans:
         pl.close()
     return res
 
+
+def batch_backward(torch, qgw, plans, ws, n_f, launches, nstreams=4):
+    """The sweep's backward: per instance one GW iteration from G0 through the autograd layer (no checkpointing), loss
+    Re sum conj(C) Sigma^C(k, i w_0) with a seeded C, gradients in H0(R) and V(R).  The instances are dealt to four
+    streams, as in the forward graph.  The backward of all instances is timed as eager autograd (one call per
+    stream) and as one captured graph; the graph's gradients must equal the eager ones."""
+    from paper_2604_22223_amd import autograd as qa
+    rng = np.random.default_rng(64)
+    flat = lambda x: torch.from_numpy(np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))).to("cuda:0")
+    groups = [(torch.cuda.Stream(), []) for _ in range(nstreams)]
+    leaves = []
+    t0 = time.perf_counter()
+    for i, (pl, w, nf) in enumerate(zip(plans, ws, n_f)):
+        s, losses = groups[i % nstreams]
+        with torch.cuda.stream(s):
+            H = flat(w["H_R"]).requires_grad_(True)
+            V = flat(w["V_R"]).requires_grad_(True)
+            G, mu, Siw, shf = qa.run(pl, H, V, w["n_target"], n_iter=1, checkpointed=False)[-1]
+            m0 = int(np.nonzero(np.asarray(nf) == 0)[0][0])
+            shp = tuple(Siw[m0].shape)
+            C = torch.from_numpy(rng.standard_normal(shp) + 1j * rng.standard_normal(shp)).to("cuda:0")
+            losses.append((C.conj() * Siw[m0]).real.sum())
+        leaves.append((H, V))
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+
+    def eager():
+        for H, V in leaves:
+            H.grad, V.grad = None, None
+        for s, losses in groups:
+            with torch.cuda.stream(s):
+                torch.autograd.backward(losses, retain_graph=True)
+
+    eager()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(launches):
+        eager()
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / launches
+    ref = [(H.grad.clone(), V.grad.clone()) for H, V in leaves]
+    for H, V in leaves:
+        H.grad, V.grad = None, None
+    g = qa.backward_graph(groups)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(launches):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / launches
+    diff = 0.0
+    for (H, V), (rh, rv) in zip(leaves, ref):
+        for a, b in ((H.grad, rh), (V.grad, rv)):
+            diff = max(diff, float((a - b).abs().max()) / max(float(b.abs().max()), 1e-300))
+    del g
+    res = {"loss": "Re sum conj(C) Sigma^C(k, i pi/beta) after one iteration from G0; gradients in H0(R) and V(R)",
+           "streams": nstreams, "forward_s": round(t_fwd, 4), "eager_backward_s_per_sweep": round(t_eager, 5),
+           "graph_backward_s_per_sweep": round(t_graph, 5), "graph_vs_eager_max_rel_diff": diff}
+    log("[bench] batch backward: forward of %d instances (autograd, one iteration from G0) %.3f s; backward per "
+        "sweep %.4f s eager, %.4f s as one graph on %d streams (max rel. difference %.1e)"
+        % (len(plans), t_fwd, t_eager, t_graph, nstreams, diff))
+    return res
 
 def main():
     ap = argparse.ArgumentParser()

@@ -303,3 +303,30 @@ def run(plan, H_R, V_R, n_target, n_iter=1, checkpointed=True):
         out.append(res)
         G, mu = res[0], res[1]
     return out
+
+
+
+def backward_graph(groups):
+    """One HIP graph holding the backward pass of many losses (many model instances in one launch).
+
+    ``groups`` is a list of (stream, losses): each group's losses were built from the Functions above on its stream,
+    without checkpointing (a checkpointed backward recomputes the forward, whose chemical-potential search reads its
+    state back to the host). The capture runs on the first group's stream; the other streams are forked from it and
+    joined back at the end, so the groups' adjoint chains run side by side, each group's in the order given. The
+    forward's saved tensors are kept (``retain_graph``). The leaves' ``.grad`` must be None before the call; the
+    gradients are then allocated from the graph's memory pool, and every ``replay()`` recomputes them into the same
+    tensors from that forward.
+    """
+    s0 = groups[0][0]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s0):
+        fork = torch.cuda.Event()
+        fork.record(s0)
+        for s, _ in groups[1:]:
+            s.wait_event(fork)
+        for s, losses in groups:
+            with torch.cuda.stream(s):
+                torch.autograd.backward(losses, retain_graph=True)
+        for s, _ in groups[1:]:
+            s0.wait_stream(s)
+    return g

@@ -1,4 +1,5 @@
-"""Batched instances in one graph launch against the same instances run one by one.
+"""Batched instances in one graph launch against the same instances run one by one (forward), and the
+backward of every instance captured in one graph against the eager backward.
 
 Five instances of uneven size (orbitals 1-5, product bases 1-25, meshes
 4-8, different beta and DLR rank) are started twice: one copy is iterated by
@@ -229,3 +230,53 @@ def test_batched_mixed_schedule_reaches_the_fixed_point(insts):
                 b.close()
         for st in states:
             st.close()
+
+
+def test_backward_of_every_instance_in_one_graph(insts):
+    """The adjoint chains of every instance in one captured graph.  Per instance: one GW iteration from G0 through
+    the autograd layer (no checkpointing), loss Re sum conj(C) Sigma^C(k, i w_0) with a seeded C, gradients in
+    H0(R) and V(R).  The instances are dealt to three streams, so the graph runs three chains side by side.  The
+    eager backward gives the reference; the captured backward is replayed three times, with eager work and a
+    synchronisation between replays, and every replay must give the same gradients."""
+    torch = _torch()
+    from paper_2604_22223_amd import autograd as qa
+    rng = np.random.default_rng(17)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    groups = [(s, []) for s in streams]
+    leaves = []
+    print("\n[batch] forward of %d instances for the batched backward" % len(insts), flush=True)
+    for i, inst in enumerate(insts):
+        s, losses = groups[i % len(groups)]
+        with torch.cuda.stream(s):
+            H = inst.H.clone().requires_grad_(True)
+            V = inst.V.clone().requires_grad_(True)
+            G, mu, Siw, shf = qa.run(inst.plan, H, V, inst.w["n_target"], n_iter=1, checkpointed=False)[-1]
+            m0 = int(np.nonzero(inst.d.nodes()["n_f"] == 0)[0][0])
+            shp = tuple(Siw[m0].shape)
+            C = torch.from_numpy(rng.standard_normal(shp) + 1j * rng.standard_normal(shp)).to("cuda:0")
+            losses.append((C.conj() * Siw[m0]).real.sum())
+        leaves.append((H, V))
+    torch.cuda.synchronize()
+    for s, losses in groups:
+        with torch.cuda.stream(s):
+            torch.autograd.backward(losses, retain_graph=True)
+    torch.cuda.synchronize()
+    ref = [(H.grad.cpu().numpy().copy(), V.grad.cpu().numpy().copy()) for H, V in leaves]
+    for rh, rv in ref:
+        assert np.all(np.isfinite(rh)) and np.all(np.isfinite(rv))
+        assert np.max(np.abs(rh)) > 0 and np.max(np.abs(rv)) > 0
+    for H, V in leaves:
+        H.grad, V.grad = None, None
+    print("[batch] capturing the backward of %d instances on %d streams" % (len(insts), len(groups)), flush=True)
+    g = qa.backward_graph(groups)
+    for rep in range(3):
+        for H, V in leaves:
+            H.grad.fill_(float(rep + 1))
+            V.grad.fill_(-float(rep + 1))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, ((H, V), (rh, rv)) in enumerate(zip(leaves, ref)):
+            assert rel_err(H.grad.cpu().numpy(), rh) < 1e-13, (rep, k)
+            assert rel_err(V.grad.cpu().numpy(), rv) < 1e-13, (rep, k)
+    del g
