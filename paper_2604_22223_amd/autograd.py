@@ -325,8 +325,9 @@ def backward_graph(groups):
         for s, _ in groups[1:]:
             s.wait_event(fork)
         for s, losses in groups:
-            with torch.cuda.stream(s):
-                torch.autograd.backward(losses, retain_graph=True)
+            if losses:
+                with torch.cuda.stream(s):
+                    torch.autograd.backward(losses, retain_graph=True)
         for s, _ in groups[1:]:
             s0.wait_stream(s)
     return g
