@@ -54,6 +54,32 @@ __device__ __forceinline__ cpx<T> shfl_cpx(cpx<T> v, int src, int width) {
   return mk(__shfl(v.re, src, width), __shfl(v.im, src, width));
 }
 
+// row shift by DPP; a lane whose source lies outside its row gets INT_MIN, the identity of the max it feeds, so the
+// shift folds into the max instruction (no copy of the value first)
+template <int CTRL>
+__device__ __forceinline__ int dpp_shl_i(int v) {
+  return __builtin_amdgcn_update_dpp(int(0x80000000u), v, CTRL, 0xF, 0xF, false);
+}
+
+// 1 / d by the hardware estimate and Newton-Raphson steps r <- r (2 - d r)
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_nr(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return __builtin_fmaf(r, __builtin_fmaf(-d, r, 1.0f), r);
+}
+
+// |Re| + |Im| rounded to FP32, as bits; a larger value compares larger
+template <typename T>
+__device__ __forceinline__ int mag_bits(cpx<T> a) {
+  return __float_as_int(float(fabs(a.re) + fabs(a.im)));
+}
+
 // ADJ: solve (I - V P)^H X = B instead, with B (pair matrix layout, dense) in place of V, and write X
 template <int NB, typename T, bool ADJ = false>
 __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
@@ -61,6 +87,7 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
                                                 cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld,
                                                 int* __restrict__ cond, const cpx<T>* __restrict__ rhs = nullptr) {
   using S = DysonWShape<NB>;
+  static_assert(S::SEG <= 32, "a row index must fit the five low bits of a pivot key");
   __shared__ cpx<T> sp[S::MPW * S::NN];
   __shared__ cpx<T> piv[2][S::MPW][2 * NB];
   const int lane = threadIdx.x;
@@ -126,17 +153,19 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
   const int partner = lane - half * S::SEG;  // the half-0 lane of this row
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
-    T val = (valid && half == 0 && !used) ? norm2(x[s]) : T(-1);
-    int idx = row;
-#pragma unroll
-    for (int off = S::SEG; off >= 1; off >>= 1) {
-      const T ov = __shfl_xor(val, off, S::LPM);
-      const int oi = __shfl_xor(idx, off, S::LPM);
-      if (ov > val || (ov == val && oi < idx)) {
-        val = ov;
-        idx = oi;
-      }
-    }
+    // the candidates' keys (|Re| + |Im| in FP32 bits, low bits 31 - row: ties go to the lower row) reduced by DPP
+    // row shifts over the SEG lanes of half 0 into its first lane (of each 16-lane DPP row), then sent to the
+    // matrix's lanes
+    int key = (valid && half == 0 && !used) ? ((mag_bits(x[s]) & ~31) | (31 - row)) : int(0x80000000u);
+    if constexpr (S::SEG >= 16) key = max(key, dpp_shl_i<0x108>(key));
+    if constexpr (S::SEG >= 8) key = max(key, dpp_shl_i<0x104>(key));
+    if constexpr (S::SEG >= 4) key = max(key, dpp_shl_i<0x102>(key));
+    if constexpr (S::SEG >= 2) key = max(key, dpp_shl_i<0x101>(key));
+    if constexpr (S::SEG == 32)  // half 0 spans two DPP rows (one matrix per wave)
+      key = max(__builtin_amdgcn_readlane(key, 0), __builtin_amdgcn_readlane(key, 16));
+    else
+      key = __shfl(key, mw * S::LPM, 64);
+    const int idx = 31 - (key & 31);
     const bool is_p = valid && (row == idx);
     if (is_p) {
       if (half == 0) used = true;
@@ -146,9 +175,11 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
     }
     __syncthreads();
     const cpx<T>* pr = piv[s & 1][mw] + half * NB;
-    const T pn = norm2(piv[s & 1][mw][s]);
+    const cpx<T> pv = piv[s & 1][mw][s];
+    const T pn = norm2(pv);
     singular |= !(pn > T(0)) || !isfinite(pn);  // exact zero, NaN or overflow
-    const cpx<T> pinv = inv(piv[s & 1][mw][s]);
+    const T d = rcp_nr(pn);
+    const cpx<T> pinv = mk(pv.re * d, -pv.im * d);
     cpx<T> f = is_p ? mk(T(1), T(0)) - pinv : x[s] * pinv;  // meaningful on half 0
     f = shfl_cpx(f, partner, 64);
     if (valid) {
@@ -201,32 +232,6 @@ __global__ __launch_bounds__(64) void k_dyson_w(const cpx<T>* __restrict__ vq,
 // chunks and the pivot exchange (two buffers, alternating by step): twelve
 // blocks fit a CU.
 // ---------------------------------------------------------------------------
-// row shift by DPP; a lane whose source lies outside its row gets INT_MIN, the identity of the max it feeds, so the
-// shift folds into the max instruction (no copy of the value first)
-template <int CTRL>
-__device__ __forceinline__ int dpp_shl_i(int v) {
-  return __builtin_amdgcn_update_dpp(int(0x80000000u), v, CTRL, 0xF, 0xF, false);
-}
-
-// 1 / d by the hardware estimate and Newton-Raphson steps r <- r (2 - d r)
-__device__ __forceinline__ double rcp_nr(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = __builtin_fma(-d, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-d, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-__device__ __forceinline__ float rcp_nr(float d) {
-  const float r = __builtin_amdgcn_rcpf(d);
-  return __builtin_fmaf(r, __builtin_fmaf(-d, r, 1.0f), r);
-}
-
-// |Re| + |Im| rounded to FP32, as bits; a larger value compares larger
-template <typename T>
-__device__ __forceinline__ int mag_bits(cpx<T> a) {
-  return __float_as_int(float(fabs(a.re) + fabs(a.im)));
-}
-
 struct W25 {
   static constexpr int NB = 25, NS = 3, NT = 7;
   static constexpr int CH = 7;                   // rows of P per staged chunk
