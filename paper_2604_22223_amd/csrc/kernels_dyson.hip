@@ -537,6 +537,159 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 }
 
 // ---------------------------------------------------------------------------
+// Register-blocked form for 8 < N_b <= 16 (three orbitals, four orbitals): one wavefront per (node, q) matrix,
+// the layout and elimination of the N_b = 25 kernel without its spread last row.  Lane = rg + 8 cg holds rows
+// rg + 8 s (s < 2) in columns cg + 8 t (t < NT) of [I - V P | V] (columns 0..N_b-1, then N_b..2 N_b-1; rows and
+// columns past them are zero).  V(q) and P are staged in LDS; V P is formed in that layout; step K searches column
+// K by packed keys in the 8-lane group holding it, the owners of the pivot row and of column K publish them through
+// LDS, and every lane subtracts f_r * (pivot row).  Slots whose columns are all in I - V P and left of K drop out of
+// the update at compile time.  Forward solve only (the adjoint keeps the two-lanes-per-row kernel).
+// ---------------------------------------------------------------------------
+template <int NB>
+struct WR {
+  static_assert(NB > 8 && NB <= 16, "two row slots of eight");
+  static constexpr int NS = 2, NT = (2 * NB + 7) / 8, NN = NB * NB;
+  static constexpr int ROW = 8 * NT;      // pivot row (all column slots)
+  static constexpr int EX = ROW + 16;     // pivot row and the multipliers of one step
+  static constexpr int TA = (NB + 7) / 8;  // slots holding columns of I - V P
+  static_assert(2 * EX <= NN, "the exchange area reuses the P area");
+};
+
+template <typename T, int NB, int K, int S>
+__device__ __forceinline__ void wr_publish(const cpx<T> (&x)[2][WR<NB>::NT], cpx<T>* ex, int cg, int p, int (&cs)[2],
+                                           int (&kof)[2]) {
+  constexpr int tk = K / 8;
+#pragma unroll
+  for (int t = tk; t < WR<NB>::NT; ++t) ex[cg + 8 * t] = x[S][t];
+  if (cg == K % 8) ex[WR<NB>::ROW + p] = mk(x[S][tk].re - T(1), x[S][tk].im);
+  cs[S] |= int(0x80000000u);
+  kof[S] = K;
+}
+
+template <typename T, int NB, int K>
+__device__ __forceinline__ void wr_step(cpx<T> (&x)[2][WR<NB>::NT], int (&cs)[2], int (&kof)[2], int rg, int cg,
+                                        cpx<T>* xs, bool& singular) {
+  constexpr int NT = WR<NB>::NT, ROW = WR<NB>::ROW, MIN = int(0x80000000u);
+  constexpr int cgk = K % 8, tk = K / 8;
+  constexpr int t0 = (K + 1) / 8 < NB / 8 ? (K + 1) / 8 : NB / 8;  // slots left of t0 hold dead columns only
+  int key = MIN;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) key = max(key, (mag_bits(x[s][tk]) & ~31) | cs[s]);
+  key = cg == cgk ? key : MIN;
+  key = max(key, dpp_shl_i<0x104>(key));
+  key = max(key, dpp_shl_i<0x102>(key));
+  key = max(key, dpp_shl_i<0x101>(key));
+  const int p = 31 - (__builtin_amdgcn_readlane(key, cgk * 8) & 31);
+  cpx<T>* ex = xs + (K & 1) * WR<NB>::EX;  // exchange buffers alternate by step parity
+  cpx<T>* mu = ex + ROW;
+  if (cg == cgk) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) mu[rg + 8 * s] = x[s][tk];
+  }
+  if (rg == (p & 7)) {
+    if ((p >> 3) == 0)
+      wr_publish<T, NB, K, 0>(x, ex, cg, p, cs, kof);
+    else
+      wr_publish<T, NB, K, 1>(x, ex, cg, p, cs, kof);
+  }
+  __syncthreads();
+  const cpx<T> pv = ex[K];
+  const T pn = norm2(pv);
+  singular |= !(pn > T(0)) || !isfinite(pn);  // exact zero, NaN or overflow (the same value in every lane)
+  const T d = rcp_nr(pn);
+  const cpx<T> pinv = mk(pv.re * d, -pv.im * d);
+  cpx<T> f[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) f[s] = mu[rg + 8 * s] * pinv;
+#pragma unroll
+  for (int t = t0; t < NT; ++t) {
+    const cpx<T> pc = ex[cg + 8 * t];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) x[s][t] = fms(x[s][t], f[s], pc);
+  }
+}
+
+template <typename T, int NB, int... K>
+__device__ __forceinline__ void wr_all(cpx<T> (&x)[2][WR<NB>::NT], int (&cs)[2], int (&kof)[2], int rg, int cg,
+                                       cpx<T>* xs, bool& singular, std::integer_sequence<int, K...>) {
+  (wr_step<T, NB, K>(x, cs, kof, rg, cg, xs, singular), ...);
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_dyson_wr(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
+                                                 cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld,
+                                                 int* __restrict__ cond) {
+  using S = WR<NB>;
+  constexpr int NT = S::NT, NN = S::NN, TA = S::TA;
+  __shared__ cpx<T> sv[NN];  // V(q)
+  __shared__ cpx<T> sp[NN];  // P; then the pivot exchange
+  const int lane = threadIdx.x;
+  const int rg = lane & 7, cg = lane >> 3;
+  const int64_t mat = blockIdx.x;
+  const int q = int(mat % nk);
+  const cpx<T>* vm = vq + int64_t(q) * NN;
+  const cpx<T>* pm = pnu + mat * NN;
+  for (int e = lane; e < NN; e += 64) {
+    sv[e] = vm[e];
+    sp[e] = pm[e];
+  }
+  __syncthreads();
+  // I - V P in the columns of slots t < TA, V in the right-hand-side columns
+  cpx<T> acc[2][TA];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int t = 0; t < TA; ++t) acc[s][t] = mk(T(0), T(0));
+  const int r1 = min(rg + 8, NB - 1);  // row of slot 1 (clamped: rows past N_b are not kept)
+#pragma unroll 4
+  for (int j = 0; j < NB; ++j) {
+    const cpx<T> v0 = sv[rg * NB + j], v1 = sv[r1 * NB + j];
+#pragma unroll
+    for (int t = 0; t < TA; ++t) {
+      const cpx<T> pj = sp[j * NB + min(cg + 8 * t, NB - 1)];
+      acc[0][t] = fma(acc[0][t], v0, pj);
+      acc[1][t] = fma(acc[1][t], v1, pj);
+    }
+  }
+  cpx<T> x[2][NT];
+  int cs[2], kof[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int row = rg + 8 * s;
+    const bool rv = row < NB;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c = cg + 8 * t;
+      cpx<T> val = mk(T(0), T(0));
+      if (rv && c < NB)
+        val = mk(T(row == c ? 1 : 0) - acc[s][t < TA ? t : 0].re, -acc[s][t < TA ? t : 0].im);
+      else if (rv && c < 2 * NB)
+        val = sv[row * NB + c - NB];
+      x[s][t] = val;
+    }
+    cs[s] = rv ? 31 - row : int(0x80000000u);  // rows past N_b never pivot
+    kof[s] = 0;
+  }
+  __syncthreads();  // every lane has read P: its area takes the pivot exchange
+  bool singular = false;
+  wr_all<T, NB>(x, cs, kof, rg, cg, sp, singular, std::make_integer_sequence<int, NB>{});
+  if (singular && lane == 0) atomicOr(cond, kCondSingular);
+  // row r of the V part is row kof of W; W^C = W - V
+  cpx<T>* wm = wc + mat * ld;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int k = kof[s];
+    if (rg + 8 * s < NB) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int col = cg + 8 * t - NB;
+        if (col >= 0 && col < NB) wm[k * NB + col] = x[s][t] - sv[k * NB + col];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // n_o x n_o inverse in registers, Gauss-Jordan with partial pivoting
 // ---------------------------------------------------------------------------
 template <int NO>
@@ -1091,6 +1244,11 @@ hipError_t dyson_w_nb(const Plan& p, const void* v_q, const void* p_nu, void* wc
     else
       hipLaunchKernelGGL((k_dyson_w25<T, false, false>), dim3(unsigned(nmat)), dim3(64), 0, s, (const cpx<T>*)v_q,
                          (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld, p.d_status + kCondWord, nullptr);
+    return hipGetLastError();
+  }
+  if constexpr (NB > 8 && NB <= 16) {
+    hipLaunchKernelGGL((k_dyson_wr<T, NB>), dim3(unsigned(nmat)), dim3(64), 0, s, (const cpx<T>*)v_q,
+                       (const cpx<T>*)p_nu, (cpx<T>*)wc_nu, nmat, p.nk, ld, p.d_status + kCondWord);
     return hipGetLastError();
   }
   const unsigned blocks = unsigned((nmat + MPW - 1) / MPW);

@@ -96,7 +96,7 @@ def _dyson_ref(vq, pnu, mask):
     return np.linalg.solve(a, v) - v
 
 
-@pytest.mark.parametrize("site_norb", [[1], [5]])
+@pytest.mark.parametrize("site_norb", [[1], [3], [4], [5]])
 @pytest.mark.parametrize("precision", [qgw.F64, qgw.F32])
 def test_singular_dyson_w_sets_status(site_norb, precision):
     """One (node, q) matrix has V(q) = I and P = I, so I - V P = 0 exactly (every pivot is zero): the call sets

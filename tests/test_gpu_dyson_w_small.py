@@ -1,0 +1,86 @@
+"""The register-blocked Dyson-W kernel for 8 < N_b <= 16 (three and four orbitals: N_b = 9 and 16) against the
+oracle's solve W^C = (I - V P)^{-1} V - V (Eq. eq-screened-coulomb): FP64 at the 1e-10 bar, FP32 within the
+rounding bar of a partially pivoted solve (a few N_b cond(I - V P) units of single precision).  The singular-pivot
+condition of the same kernel is tested with the boundary tests.
+
+Inputs are seeded: a Hermitian V(q) per q and a random P(q, i nu) per node, scaled so that I - V P is well
+conditioned, on a 4 x 4 mesh with the DLR nodes of beta = 10 / eV, omega_max = 20 eV; the number of (node, q)
+matrices is not a multiple of anything the kernel tiles by.
+"""
+import numpy as np
+import pytest
+
+from conftest import rel_err
+from oracle import gw
+from oracle.dlr import DLR
+from paper_2604_22223_amd import qgw
+
+pytestmark = pytest.mark.gpu
+
+N = 4
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def dev(x, dt=np.complex128):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def crand(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def make(norb):
+    nb = norb * norb
+    d = DLR(10.0, 20.0, 1e-10)
+    rng = np.random.default_rng(100 + nb)
+    nk = N * N
+    v = crand(rng, (nk, nb, nb))
+    vq = 0.15 * (v + np.conj(np.swapaxes(v, 1, 2)))
+    pnu = 0.15 * crand(rng, (d.r, nk, nb, nb))
+    V_o = np.moveaxis(vq.reshape(N, N, nb, nb), (2, 3), (0, 1))
+    P_o = np.moveaxis(pnu.reshape(d.r, N, N, nb, nb), (3, 4), (1, 2))
+    wc_o = gw.dyson_W(V_o, P_o)
+    wc_ref = np.moveaxis(wc_o, (1, 2), (3, 4)).reshape(d.r, nk, nb, nb)
+    a = np.eye(nb) - np.broadcast_to(vq[None], pnu.shape) @ pnu
+    cond = float(np.linalg.cond(a.reshape(-1, nb, nb)).max())
+    return dict(d=d, nb=nb, norb=norb, vq=vq, pnu=pnu, wc_ref=wc_ref, cond=cond)
+
+
+@pytest.mark.parametrize("norb", [3, 4])
+def test_forward_fp64_matches_oracle(norb):
+    torch = _torch()
+    c = make(norb)
+    p = qgw.Plan.from_nodes(N, [norb], 10.0, c["d"].nodes())
+    print("\n[dyson w] forward FP64, N_b = %d, cond %.1f" % (c["nb"], c["cond"]), flush=True)
+    out = torch.empty((p.r, p.n_k, c["nb"], c["nb"]), dtype=torch.complex128, device="cuda:0")
+    p.dyson_W(dev(c["vq"]), dev(c["pnu"]), out)
+    p.sync_status()  # raises if a pivot was singular
+    assert rel_err(host(out), c["wc_ref"]) < 1e-10
+    p.close()
+
+
+@pytest.mark.parametrize("norb", [3, 4])
+def test_forward_fp32_within_rounding(norb):
+    torch = _torch()
+    c = make(norb)
+    p = qgw.Plan.from_nodes(N, [norb], 10.0, c["d"].nodes(), precision=qgw.F32)
+    print("\n[dyson w] forward FP32, N_b = %d" % c["nb"], flush=True)
+    out = torch.empty((p.r, p.n_k, c["nb"], c["nb"]), dtype=torch.complex64, device="cuda:0")
+    p.dyson_W(dev(c["vq"], np.complex64), dev(c["pnu"], np.complex64), out)
+    p.sync_status()  # raises if a pivot was singular
+    tol = 4.0 * c["nb"] * c["cond"] * 2.0 ** -24
+    ref = c["wc_ref"]
+    err = float(np.abs(host(out) - ref).max()) / max(float(np.abs(ref).max()), float(np.abs(c["vq"]).max()))
+    assert err < tol, (err, tol)
+    p.close()
+
