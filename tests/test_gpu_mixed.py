@@ -99,6 +99,28 @@ def test_mixed_solve_reaches_oracle_fixed_point(five8):
     plan.close()
 
 
+@pytest.mark.parametrize("norb", [3, 4])
+def test_mixed_solve_with_three_and_four_orbitals(norb):
+    """The mixed schedule on one site with three and with four orbitals (N_b = 9 and 16: the register-blocked
+    Dyson-W kernel in both precisions, the Dyson-G search for n_o = 3 and 4) lands on the oracle's fixed point."""
+    w = wl.random_model((6, 6), [norb], seed=4, beta=10.0, omega_max=20.0, eps=1e-10, U=1.0, J=0.1, Vnn=0.2)
+    d = DLR(w["beta"], w["omega_max"], w["eps"])
+    m = gw.Model(w["mesh"], w["site_norb"], w["H_R"], w["V_R"], w["beta"], w["n_target"])
+    conv, h = gw.scf(m, d, tol=1e-11, max_iter=80, state=gw.initial_state(m, d))
+    assert h[-1][0] <= 1e-11
+    plan = qgw.Plan.from_nodes(6, [norb], d.beta, d.nodes())
+    st, hist, mu = _run(plan, m, 1, 1e-9, max_iter=80)
+    print("[mixed] n_o = %d history" % norb, ["%.1e/%d" % x for x in hist], flush=True)
+    last_prec, n32, n64 = st.info()
+    assert last_prec == 0 and n32 >= 2 and n64 >= 1
+    assert hist[-1][0] <= 1e-9
+    assert np.max(np.abs(st.array(1).cpu().numpy() - flat(conv["sig_iw"]))) <= 1e-6
+    assert np.max(np.abs(st.array(0).cpu().numpy() - flat(conv["G_iw"]))) <= 1e-6
+    assert abs(mu - conv["mu"]) <= 1e-7
+    st.close()
+    plan.close()
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_converged_end_point_at_the_fp64_bar(five8, mode):
     """Both sides converged to max |Delta Sigma| <= 1e-12 (FP64 iterations finish the mixed schedule too): the
