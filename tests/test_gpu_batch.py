@@ -1,8 +1,8 @@
 """Batched instances in one graph launch against the same instances run one by one (forward), and the
 backward of every instance captured in one graph against the eager backward.
 
-Five instances of uneven size (orbitals 1-5, product bases 1-25, meshes
-4-8, different beta and DLR rank) are started twice: one copy is iterated by
+Six instances of uneven size (orbitals 1-5, product bases 1-25, 2-D meshes
+5-8 and one 4 x 4 x 4 mesh, different beta and DLR rank) are started twice: one copy is iterated by
 qgw_gw_iteration, the other by replaying a captured batch graph.  Every
 replay is followed by eager work and a synchronisation, and every replay's
 Sigma, G and mu must equal the eager ones (the graph runs the same kernels
