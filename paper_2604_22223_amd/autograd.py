@@ -315,7 +315,8 @@ def backward_graph(groups):
     joined back at the end, so the groups' adjoint chains run side by side, each group's in the order given. The
     forward's saved tensors are kept (``retain_graph``). The leaves' ``.grad`` must be None before the call; the
     gradients are then allocated from the graph's memory pool, and every ``replay()`` recomputes them into the same
-    tensors from that forward.
+    tensors from that forward. The replays read the forward's tensors at their addresses: keep the losses (and with
+    them the forward's saved tensors) alive for as long as the graph is replayed.
     """
     s0 = groups[0][0]
     g = torch.cuda.CUDAGraph()
