@@ -543,7 +543,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 // columns past them are zero).  V(q) and P are staged in LDS; V P is formed in that layout; step K searches column
 // K by packed keys in the 8-lane group holding it, the owners of the pivot row and of column K publish them through
 // LDS, and every lane subtracts f_r * (pivot row).  Slots whose columns are all in I - V P and left of K drop out of
-// the update at compile time.  Forward solve only (the adjoint keeps the two-lanes-per-row kernel).
+// the update at compile time.  With ADJ it solves the conjugate-transposed system of the adjoint.
 // ---------------------------------------------------------------------------
 template <int NB>
 struct WR {
@@ -615,10 +615,12 @@ __device__ __forceinline__ void wr_all(cpx<T> (&x)[2][WR<NB>::NT], int (&cs)[2],
   (wr_step<T, NB, K>(x, cs, kof, rg, cg, xs, singular), ...);
 }
 
-template <typename T, int NB>
+// ADJ: solve (I - V P)^H X = B instead, with B (pair matrix layout, dense) in place of V, and write X; A = I - V P
+// passes through the P area of LDS and is read back conjugate-transposed
+template <typename T, int NB, bool ADJ = false>
 __global__ __launch_bounds__(64) void k_dyson_wr(const cpx<T>* __restrict__ vq, const cpx<T>* __restrict__ pnu,
                                                  cpx<T>* __restrict__ wc, int64_t nmat, int nk, int64_t ld,
-                                                 int* __restrict__ cond) {
+                                                 int* __restrict__ cond, const cpx<T>* __restrict__ rhs = nullptr) {
   using S = WR<NB>;
   constexpr int NT = S::NT, NN = S::NN, TA = S::TA;
   __shared__ cpx<T> sv[NN];  // V(q)
@@ -651,6 +653,18 @@ __global__ __launch_bounds__(64) void k_dyson_wr(const cpx<T>* __restrict__ vq, 
       acc[1][t] = fma(acc[1][t], v1, pj);
     }
   }
+  if constexpr (ADJ) {
+    __syncthreads();  // every lane has read P: its area takes A = I - V P
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < TA; ++t) {
+        const int row = rg + 8 * s, c = cg + 8 * t;
+        if (row < NB && c < NB) sp[row * NB + c] = mk(T(row == c ? 1 : 0) - acc[s][t].re, -acc[s][t].im);
+      }
+    __syncthreads();
+  }
+  const cpx<T>* bm = ADJ ? rhs + mat * NN : nullptr;
   cpx<T> x[2][NT];
   int cs[2], kof[2];
 #pragma unroll
@@ -662,19 +676,20 @@ __global__ __launch_bounds__(64) void k_dyson_wr(const cpx<T>* __restrict__ vq, 
       const int c = cg + 8 * t;
       cpx<T> val = mk(T(0), T(0));
       if (rv && c < NB)
-        val = mk(T(row == c ? 1 : 0) - acc[s][t < TA ? t : 0].re, -acc[s][t < TA ? t : 0].im);
+        val = ADJ ? conj(sp[c * NB + row])
+                  : mk(T(row == c ? 1 : 0) - acc[s][t < TA ? t : 0].re, -acc[s][t < TA ? t : 0].im);
       else if (rv && c < 2 * NB)
-        val = sv[row * NB + c - NB];
+        val = ADJ ? bm[row * NB + c - NB] : sv[row * NB + c - NB];
       x[s][t] = val;
     }
     cs[s] = rv ? 31 - row : int(0x80000000u);  // rows past N_b never pivot
     kof[s] = 0;
   }
-  __syncthreads();  // every lane has read P: its area takes the pivot exchange
+  __syncthreads();  // every lane has read P (ADJ: A): its area takes the pivot exchange
   bool singular = false;
   wr_all<T, NB>(x, cs, kof, rg, cg, sp, singular, std::make_integer_sequence<int, NB>{});
   if (singular && lane == 0) atomicOr(cond, kCondSingular);
-  // row r of the V part is row kof of W; W^C = W - V
+  // row r of the right-hand side is row kof of the solution; W^C = W - V (ADJ: X)
   cpx<T>* wm = wc + mat * ld;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -683,7 +698,7 @@ __global__ __launch_bounds__(64) void k_dyson_wr(const cpx<T>* __restrict__ vq, 
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int col = cg + 8 * t - NB;
-        if (col >= 0 && col < NB) wm[k * NB + col] = x[s][t] - sv[k * NB + col];
+        if (col >= 0 && col < NB) wm[k * NB + col] = ADJ ? x[s][t] : x[s][t] - sv[k * NB + col];
       }
     }
   }
@@ -1358,6 +1373,11 @@ hipError_t dyson_w_bwd_nb(const Plan& p, const void* v_q, const void* p_nu, cons
     hipLaunchKernelGGL((k_dyson_w25<double, false, false>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
                        (const zd*)p_nu, wcm, nmat, p.nk, NN, cond, nullptr);
     hipLaunchKernelGGL((k_dyson_w25<double, true, false>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
+                       (const zd*)p_nu, xm, nmat, p.nk, NN, cond, (const zd*)wbar);
+  } else if constexpr (NB > 8 && NB <= 16) {
+    hipLaunchKernelGGL((k_dyson_wr<double, NB, false>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
+                       (const zd*)p_nu, wcm, nmat, p.nk, NN, cond, nullptr);
+    hipLaunchKernelGGL((k_dyson_wr<double, NB, true>), dim3(unsigned(nmat)), dim3(64), 0, s, (const zd*)v_q,
                        (const zd*)p_nu, xm, nmat, p.nk, NN, cond, (const zd*)wbar);
   } else {
     constexpr int MPW = DysonWShape<NB>::MPW;

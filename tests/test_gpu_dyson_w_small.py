@@ -1,6 +1,8 @@
 """The register-blocked Dyson-W kernel for 8 < N_b <= 16 (three and four orbitals: N_b = 9 and 16) against the
 oracle's solve W^C = (I - V P)^{-1} V - V (Eq. eq-screened-coulomb): FP64 at the 1e-10 bar, FP32 within the
-rounding bar of a partially pivoted solve (a few N_b cond(I - V P) units of single precision).  The singular-pivot
+rounding bar of a partially pivoted solve (a few N_b cond(I - V P) units of single precision), and the adjoint call
+(the same kernel on the system and on its conjugate transpose, then the products) against the oracle's reverse mode
+at 1e-10.  The singular-pivot
 condition of the same kernel is tested with the boundary tests.
 
 Inputs are seeded: a Hermitian V(q) per q and a random P(q, i nu) per node, scaled so that I - V P is well
@@ -11,6 +13,7 @@ import numpy as np
 import pytest
 
 from conftest import rel_err
+from oracle import adjoint as ad
 from oracle import gw
 from oracle.dlr import DLR
 from paper_2604_22223_amd import qgw
@@ -53,7 +56,13 @@ def make(norb):
     wc_ref = np.moveaxis(wc_o, (1, 2), (3, 4)).reshape(d.r, nk, nb, nb)
     a = np.eye(nb) - np.broadcast_to(vq[None], pnu.shape) @ pnu
     cond = float(np.linalg.cond(a.reshape(-1, nb, nb)).max())
-    return dict(d=d, nb=nb, norb=norb, vq=vq, pnu=pnu, wc_ref=wc_ref, cond=cond)
+    wbar = crand(rng, (d.r, nk, nb, nb))
+    Wb_o = np.moveaxis(wbar.reshape(d.r, N, N, nb, nb), (3, 4), (1, 2))
+    vb_o, pb_o = ad.dyson_W_adj(Wb_o, V_o, P_o)
+    vb_ref = np.moveaxis(vb_o, (2, 3), (0, 1)).reshape(nk, nb, nb)
+    pb_ref = np.moveaxis(pb_o, (1, 2), (3, 4)).reshape(d.r, nk, nb, nb)
+    return dict(d=d, nb=nb, norb=norb, vq=vq, pnu=pnu, wc_ref=wc_ref, cond=cond, wbar=wbar, vb_ref=vb_ref,
+                pb_ref=pb_ref)
 
 
 @pytest.mark.parametrize("norb", [3, 4])
@@ -84,3 +93,17 @@ def test_forward_fp32_within_rounding(norb):
     assert err < tol, (err, tol)
     p.close()
 
+
+@pytest.mark.parametrize("norb", [3, 4])
+def test_adjoint_fp64_matches_oracle(norb):
+    torch = _torch()
+    c = make(norb)
+    p = qgw.Plan.from_nodes(N, [norb], 10.0, c["d"].nodes())
+    print("\n[dyson w] adjoint FP64, N_b = %d" % c["nb"], flush=True)
+    vq, pnu = dev(c["vq"]), dev(c["pnu"])
+    pbar, vbar = torch.empty_like(pnu), torch.empty_like(vq)
+    p.dyson_W_bwd(vq, pnu, dev(c["wbar"]), pbar, vbar)
+    p.sync_status()  # raises if a pivot was singular
+    assert rel_err(host(pbar), c["pb_ref"]) < 1e-10
+    assert rel_err(host(vbar), c["vb_ref"]) < 1e-10
+    p.close()
