@@ -1701,6 +1701,15 @@ static void free_batch(qgw_batch b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
 }
 
+// Estimated time of one iteration of a plan (ns), from the sizes that set each step's work: Dyson W grows with
+// N_k r N_b^3 (plus a per-matrix cost of the serial pivot steps), the pair maps with N_k N_b^2 r^2, bubble and
+// self-energy with N_k N_b^2 r, and about 0.1 ms goes to latency-bound steps.  The coefficients are the FP64 rates
+// measured at the five-orbital 24 x 24 workload and on the 64-instance sweep; only the ratios matter.
+static double iteration_cost_ns(const Plan& p) {
+  const double nk = p.nk, r = p.r, nb = p.nb;
+  return nk * r * (0.8e-3 * nb * nb * nb + 1.5 + 4.5e-4 * nb * nb * r + 0.0105 * nb * nb) + 1e5;
+}
+
 qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precision, int32_t n_iter,
                             int32_t mu_steps, qgw_batch* out) {
   QGW_REQUIRE(out && states && n > 0, QGW_ERR_INVALID_ARG, "qgw_batch_create: need states");
@@ -1740,7 +1749,23 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
     e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) b->events.push_back(ev);
   }
-  // capture: fork the workers from the capture stream, instance i on worker i mod nw, join
+  // instances to workers, longest estimated time first, each to the worker with the least estimated work so far (a
+  // round-robin deal left one worker with twice the work of another on the uneven sweep)
+  std::vector<int> worker(n, 0);
+  {
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::vector<double> cost(n);
+    for (int i = 0; i < n; ++i) cost[i] = iteration_cost_ns(states[i]->plan->p);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    std::vector<double> load(nw, 0.0);
+    for (int i : order) {
+      const int w = int(std::min_element(load.begin(), load.end()) - load.begin());
+      worker[i] = w;
+      load[w] += cost[i];
+    }
+  }
+  // capture: fork the workers from the capture stream, each instance on its worker, join
   if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     hipError_t ce = hipEventRecord(b->events[nw], b->cap);
@@ -1749,7 +1774,7 @@ qgw_status qgw_batch_create(int32_t n, const qgw_state* states, int32_t precisio
       for (int i = 0; i < n && ce == hipSuccess; ++i) {
         qgw_state st = states[i];
         const Plan& p = st->plan->p;
-        hipStream_t ws = b->workers[i % nw];
+        hipStream_t ws = b->workers[worker[i]];
         ce = enqueue_steps(st, precision == 1, false, ws, false);
         if (ce == hipSuccess)
           ce = launch_dyson_g_chain(p, st->Hs_k, st->Sig_iw, std::isnan(st->n_target) ? 0 : 1, st->G_iw, st->d_scal,
