@@ -625,16 +625,25 @@ def batch_leg(torch, qgw, count, launches, warmup, mu_steps, solve_replays=100):
 def batch_backward(torch, qgw, plans, ws, n_f, launches, nstreams=4):
     """The sweep's backward: per instance one GW iteration from G0 through the autograd layer (no checkpointing), loss
     Re sum conj(C) Sigma^C(k, i w_0) with a seeded C, gradients in H0(R) and V(R).  The instances are dealt to four
-    streams, as in the forward graph.  The backward of all instances is timed as eager autograd (one call per
+    streams by estimated work, as in the forward graph.  The backward of all instances is timed as eager autograd (one call per
     stream) and as one captured graph; the graph's gradients must equal the eager ones."""
     from paper_2604_22223_amd import autograd as qa
     rng = np.random.default_rng(64)
     flat = lambda x: torch.from_numpy(np.ascontiguousarray(x.reshape(x.shape[:-2] + (-1,)))).to("cuda:0")
     groups = [(torch.cuda.Stream(), []) for _ in range(nstreams)]
+    # instances to streams by longest estimated work first, with the per-iteration estimate the batch graph uses
+    # (Dyson W ~ N_k r N_b^3, pair maps ~ N_k N_b^2 r^2, bubble and self-energy ~ N_k N_b^2 r; ns)
+    cost = [pl.n_k * pl.r * (0.8e-3 * pl.n_b ** 3 + 1.5 + 4.5e-4 * pl.n_b ** 2 * pl.r + 0.0105 * pl.n_b ** 2) + 1e5
+            for pl in plans]
+    load, stream_of = [0.0] * nstreams, [0] * len(plans)
+    for i in sorted(range(len(plans)), key=lambda k: -cost[k]):
+        k = load.index(min(load))
+        stream_of[i] = k
+        load[k] += cost[i]
     leaves = []
     t0 = time.perf_counter()
     for i, (pl, w, nf) in enumerate(zip(plans, ws, n_f)):
-        s, losses = groups[i % nstreams]
+        s, losses = groups[stream_of[i]]
         with torch.cuda.stream(s):
             H = flat(w["H_R"]).requires_grad_(True)
             V = flat(w["V_R"]).requires_grad_(True)
